@@ -1,0 +1,415 @@
+"""Plain float64 CPU oracle of the GP-FVM hot path (test infrastructure only).
+
+Every function names the passage of the paper it follows.  Notation:
+``L`` stacks the observation functionals in the order [IC/BC points; volumes]
+(Sec. 2.2, L_IBVP), ``G = L k L' + Sigma`` (Sec. 2.1, Definition and
+eq. affine-posterior), volumes are flattened row-major with dimension 0 (time)
+slowest.
+
+Parity pins (tests under ``tests/test_oracle_*.py``):
+  cell/point factors ......... pinned: closed-form antiderivative forms,
+                               mpmath high-precision quadrature, special cases
+  Fubini/Kronecker Gram ...... pinned: brute-force tensor Gauss quadrature of
+                               the full-dimensional operator (autograd
+                               derivatives), symmetry, PSD
+  dense posterior ............ pinned: LAPACK Cholesky; noise-free limit
+                               interpolates; analytic heat solution convergence
+  two-stage Schur solve ...... pinned: equals the one-stage dense solve
+  IterGP ..................... pinned: unit-vector actions reproduce Cholesky;
+                               run to n iterations reproduces the exact
+                               posterior; combined variance >= exact and
+                               non-increasing.  The early-terminated posterior
+                               after k << n iterations has no closed form:
+                               only those invariants pin it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import scipy.linalg as sla
+
+__all__ = [
+    "load_quad", "cell_cell", "point_cell", "point_point", "Oracle",
+    "dense_posterior", "itergp", "cg_solve",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "_quad.so")
+_lib = None
+
+
+def build_quad(force: bool = False) -> str:
+    """Compile quad.c with gcc (plain C, no GPU)."""
+    src = os.path.join(_HERE, "quad.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        tmp = _SO + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def load_quad():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build_quad())
+        d, i, p = ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+        for name, args, res in [
+            ("ora_kder", [i, d, d], d),
+            ("ora_point_point", [i, i, d, d, d], d),
+            ("ora_point_cell", [i, i, d, d, d, d], d),
+            ("ora_cell_cell", [i, i, d, d, d, d, d], d),
+            ("ora_integrate_kder", [i, d, d, d], d),
+            ("ora_qk15_monomial", [i, d, d, p, p], None),
+            ("ora_cell_cell_matrix", [i, i, i, p, i, p, d, p], None),
+            ("ora_point_cell_matrix", [i, i, i, p, i, p, d, p], None),
+            ("ora_point_point_matrix", [i, i, i, p, i, p, d, p], None),
+        ]:
+            f = getattr(lib, name)
+            f.argtypes, f.restype = args, res
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---------------------------------------------------------------------------
+# 1-D factors (Sec. 3.1 eq. linop-def-univariate; Sec. 3.2 eq. LkL)
+# ---------------------------------------------------------------------------
+
+def cell_cell(p: int, q: int, e1: np.ndarray, e2: np.ndarray, ell: float) -> np.ndarray:
+    """F^{pq}[i, j] = int_{I_i} int_{I'_j} d^p_s d^q_{s'} k(s, s') ds' ds."""
+    e1 = np.ascontiguousarray(e1, float); e2 = np.ascontiguousarray(e2, float)
+    out = np.empty((len(e1) - 1, len(e2) - 1))
+    load_quad().ora_cell_cell_matrix(p, q, len(e1) - 1, _ptr(e1), len(e2) - 1, _ptr(e2), ell, _ptr(out))
+    return out
+
+
+def point_cell(p: int, q: int, x: np.ndarray, e2: np.ndarray, ell: float) -> np.ndarray:
+    """Q^{pq}[i, j] = int_{I'_j} d^p_x d^q_{s'} k(x_i, s') ds'."""
+    x = np.ascontiguousarray(x, float); e2 = np.ascontiguousarray(e2, float)
+    out = np.empty((len(x), len(e2) - 1))
+    load_quad().ora_point_cell_matrix(p, q, len(x), _ptr(x), len(e2) - 1, _ptr(e2), ell, _ptr(out))
+    return out
+
+
+def point_point(p: int, q: int, x: np.ndarray, x2: np.ndarray, ell: float) -> np.ndarray:
+    """P^{pq}[i, j] = d^p_x d^q_{x'} k(x_i, x'_j)."""
+    x = np.ascontiguousarray(x, float); x2 = np.ascontiguousarray(x2, float)
+    out = np.empty((len(x), len(x2)))
+    load_quad().ora_point_point_matrix(p, q, len(x), _ptr(x), len(x2), _ptr(x2), ell, _ptr(out))
+    return out
+
+
+def _kron_all(mats: Sequence[np.ndarray]) -> np.ndarray:
+    out = mats[0]
+    for m in mats[1:]:
+        out = np.kron(out, m)
+    return out
+
+
+def _mode_apply(mats: Sequence[np.ndarray], v: np.ndarray, shape_in: Sequence[int]) -> np.ndarray:
+    """(M_0 kron M_1 kron ...) v for a row-major tensor v of shape shape_in."""
+    x = v.reshape(shape_in)
+    for d, m in enumerate(mats):
+        x = np.moveaxis(np.tensordot(m, x, axes=(1, d)), 0, d)
+    return x.reshape(-1)
+
+
+class Oracle:
+    """All oracle quantities of one IBVP (``workloads.IBVP``)."""
+
+    def __init__(self, ibvp):
+        self.p = ibvp
+        self.d = ibvp.d
+        self.ell = tuple(float(l) for l in ibvp.lengthscale)
+        self.sf2 = float(ibvp.outputscale)
+        self._cache: Dict[tuple, np.ndarray] = {}
+        self.N = ibvp.n_pde
+        self.ncell = ibvp.ncell
+        self.cc = None if ibvp.cell_coef is None else np.asarray(ibvp.cell_coef, float).ravel()
+
+    # -- factor caches -----------------------------------------------------
+    def F(self, dim: int, p: int, q: int) -> np.ndarray:
+        key = ("F", dim, p, q)
+        if key not in self._cache:
+            e = self.p.edges[dim]
+            self._cache[key] = cell_cell(p, q, e, e, self.ell[dim])
+        return self._cache[key]
+
+    def term_coef(self, term) -> np.ndarray:
+        """c_alpha(V) for every volume V (Sec. 3.2; per-cell coefficients as
+        in the appendix on variable bathymetry)."""
+        if term.cellwise:
+            return term.coef * self.cc
+        return np.full(self.N, term.coef)
+
+    # -- volume block (Sec. 3.2 eq. LkL, Sec. 4.1 eq. kronecker-structure) --
+    def volume_gram(self) -> np.ndarray:
+        """Dense L_V k L_V' (N x N), summed over every (alpha, alpha') pair."""
+        G = np.zeros((self.N, self.N))
+        for t1 in self.p.terms:
+            c1 = self.term_coef(t1)
+            for t2 in self.p.terms:
+                c2 = self.term_coef(t2)
+                K = _kron_all([self.F(i, t1.alpha[i], t2.alpha[i]) for i in range(self.d)])
+                G += c1[:, None] * K * c2[None, :]
+        return self.sf2 * G
+
+    def volume_diag(self) -> np.ndarray:
+        diag = np.zeros(self.N)
+        for t1 in self.p.terms:
+            c1 = self.term_coef(t1)
+            for t2 in self.p.terms:
+                c2 = self.term_coef(t2)
+                dg = [np.diag(self.F(i, t1.alpha[i], t2.alpha[i])) for i in range(self.d)]
+                diag += c1 * c2 * _kron_all(dg)
+        return self.sf2 * diag
+
+    def noise_pde(self) -> float:
+        """PDE-observation noise variance; relative mode scales by the mean of
+        the volume Gram's diagonal (reading of Sec. 2.1's Sigma)."""
+        if self.p.noise_pde_relative:
+            return float(self.p.noise_pde * self.volume_diag().mean())
+        return float(self.p.noise_pde)
+
+    def volume_matvec(self, v: np.ndarray) -> np.ndarray:
+        """Matrix-free (L_V k L_V') v as a sum of Kronecker products."""
+        y = np.zeros(self.N)
+        for t1 in self.p.terms:
+            c1 = self.term_coef(t1)
+            for t2 in self.p.terms:
+                c2 = self.term_coef(t2)
+                mats = [self.F(i, t1.alpha[i], t2.alpha[i]) for i in range(self.d)]
+                y += c1 * _mode_apply(mats, c2 * v, self.ncell)
+        return self.sf2 * y
+
+    # -- point observations (Sec. 2.2, IC/BC operator) -----------------------
+    def point_gram(self) -> np.ndarray:
+        """L_b k L_b' + Sigma_b (dense)."""
+        gs = self.p.groups
+        blocks = []
+        for g1 in gs:
+            row = []
+            for g2 in gs:
+                mats = [point_point(g1.deriv[i], g2.deriv[i], g1.axes[i], g2.axes[i], self.ell[i])
+                        for i in range(self.d)]
+                row.append(self.sf2 * _kron_all(mats))
+            blocks.append(row)
+        G = np.block(blocks)
+        G[np.diag_indices_from(G)] += np.concatenate([np.full(g.size, g.noise_var) for g in gs])
+        return G
+
+    def _group_cell_mats(self, g, alpha) -> List[np.ndarray]:
+        return [self.pc_cached(g, i, g.deriv[i], alpha[i]) for i in range(self.d)]
+
+    def pc_cached(self, g, dim, p, q):
+        key = ("Q", id(g), dim, p, q)
+        if key not in self._cache:
+            self._cache[key] = point_cell(p, q, g.axes[dim], self.p.edges[dim], self.ell[dim])
+        return self._cache[key]
+
+    def cross_gram(self) -> np.ndarray:
+        """L_b k L_V' (n_b x N), dense."""
+        rows = []
+        for g in self.p.groups:
+            B = np.zeros((g.size, self.N))
+            for t in self.p.terms:
+                B += _kron_all(self._group_cell_mats(g, t.alpha)) * self.term_coef(t)[None, :]
+            rows.append(self.sf2 * B)
+        return np.vstack(rows)
+
+    def cross_matvec(self, v: np.ndarray) -> np.ndarray:
+        """(L_b k L_V') v, matrix-free per tensor-grid group."""
+        out = []
+        for g in self.p.groups:
+            acc = np.zeros(g.size)
+            for t in self.p.terms:
+                acc += _mode_apply(self._group_cell_mats(g, t.alpha), self.term_coef(t) * v, self.ncell)
+            out.append(self.sf2 * acc)
+        return np.concatenate(out)
+
+    def cross_rmatvec(self, w: np.ndarray) -> np.ndarray:
+        """(L_V k L_b') w = (L_b k L_V')^T w."""
+        y = np.zeros(self.N)
+        off = 0
+        for g in self.p.groups:
+            wg = w[off:off + g.size]; off += g.size
+            for t in self.p.terms:
+                mats = [m.T for m in self._group_cell_mats(g, t.alpha)]
+                y += self.term_coef(t) * _mode_apply(mats, wg, g.shape)
+        return self.sf2 * y
+
+    def gram(self) -> np.ndarray:
+        """Full IBVP Gram G = L k L' + Sigma (Sec. 2.2)."""
+        Gbb = self.point_gram()
+        Gbp = self.cross_gram()
+        Gpp = self.volume_gram()
+        Gpp[np.diag_indices_from(Gpp)] += self.noise_pde()
+        return np.block([[Gbb, Gbp], [Gbp.T, Gpp]])
+
+    # -- cross-covariances with evaluation points (Sec. 2.1 eq. Lk-def) ------
+    def grid_points(self, grid: Sequence[np.ndarray]) -> np.ndarray:
+        mesh = np.meshgrid(*grid, indexing="ij")
+        return np.stack([m.ravel() for m in mesh], axis=1)
+
+    def Lk_points(self, X: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+        """(L_b k(x), L_V k(x)) for rows x of X: shapes (n_b, M) and (N, M)."""
+        M = X.shape[0]
+        kb = []
+        for g in self.p.groups:
+            mats = [point_point(g.deriv[i], 0, g.axes[i], X[:, i], self.ell[i]) for i in range(self.d)]
+            # group tensor grid x each evaluation point: product over dims
+            blk = np.ones((g.size, M))
+            idx = np.indices(g.shape).reshape(self.d, -1)
+            for i in range(self.d):
+                blk *= mats[i][idx[i], :]
+            kb.append(self.sf2 * blk)
+        kp = np.zeros((self.N, M))
+        idx = np.indices(self.ncell).reshape(self.d, -1)
+        for t in self.p.terms:
+            blk = np.ones((self.N, M))
+            for i in range(self.d):
+                # L_[a,b];alpha applied to the first argument of k(., x)
+                q = point_cell(0, t.alpha[i], X[:, i], self.p.edges[i], self.ell[i])  # M x N_i
+                blk *= q.T[idx[i], :]
+            kp += self.term_coef(t)[:, None] * blk
+        return np.vstack(kb), self.sf2 * kp
+
+
+def dense_posterior(orc: Oracle, X: np.ndarray, y: Optional[np.ndarray] = None):
+    """Exact posterior mean/variance at rows of X (Sec. 2.1 eq. lin-cond-mean,
+    eq. lin-cond-cov; Sec. 4 representer weights via Cholesky)."""
+    G = orc.gram()
+    y = orc.p.y_obs() if y is None else y
+    cf = sla.cho_factor(G, lower=True)
+    alpha = sla.cho_solve(cf, y)
+    kb, kp = orc.Lk_points(X)
+    Lk = np.vstack([kb, kp])
+    mean = Lk.T @ alpha
+    W = sla.solve_triangular(cf[0], Lk, lower=True)
+    var = orc.sf2 - np.einsum("ij,ij->j", W, W)
+    return mean, var, alpha
+
+
+# ---------------------------------------------------------------------------
+# Two-stage solve: exact IC/BC conditioning, then IterGP on the volumes
+# (Sec. 4.2 Cholesky preconditioner; Sec. 4.1 IterGP)
+# ---------------------------------------------------------------------------
+
+class SchurSystem:
+    """Gram of the volume observations under the IC/BC-conditioned prior:
+    S = L_V k L_V' + Sigma_V - G_pb G_bb^{-1} G_bp, and its data residual."""
+
+    def __init__(self, orc: Oracle):
+        self.o = orc
+        self.Gbb = orc.point_gram()
+        self.cf = sla.cho_factor(self.Gbb, lower=True)
+        self.sig = orc.noise_pde()
+        yobs = orc.p.y_obs()
+        self.yb = yobs[:orc.p.n_b]
+        self.yp = yobs[orc.p.n_b:]
+        self.ab0 = sla.cho_solve(self.cf, self.yb)          # G_bb^{-1} y_b
+        self.b = self.yp - orc.cross_rmatvec(self.ab0)        # y_p - G_pb G_bb^{-1} y_b
+        self.nmv = 0
+
+    def matvec(self, v: np.ndarray) -> np.ndarray:
+        self.nmv += 1
+        o = self.o
+        w = sla.cho_solve(self.cf, o.cross_matvec(v))
+        return o.volume_matvec(v) + self.sig * v - o.cross_rmatvec(w)
+
+    def full_weights(self, vp: np.ndarray) -> np.ndarray:
+        """Representer weights of the full system from the volume weights."""
+        ab = sla.cho_solve(self.cf, self.yb - self.o.cross_matvec(vp))
+        return np.concatenate([ab, vp])
+
+
+def itergp(S, maxiter: int, tol: float = 0.0, actions: str = "cg", store: bool = True):
+    """IterGP (Wenger et al. 2022, as used in Sec. 4.1/4.2) on system S with
+    right-hand side S.b:
+
+        r   = b - S v          (residual of the current representer weights)
+        s   = action           (CG policy: s = r; 'unit': e_i)
+        z   = S s
+        d   = s - C z          (C = sum_j d_j d_j^T / eta_j)
+        eta = z^T d
+        C  += d d^T / eta
+        v  += (s^T r / eta) d
+
+    Returns (v, D, eta, residual norms).  Stops after maxiter iterations or
+    once ||r|| <= tol ||b||."""
+    b = S.b
+    n = len(b)
+    v = np.zeros(n)
+    D = np.zeros((n, maxiter)) if store else None
+    eta = np.zeros(maxiter)
+    res = []
+    nb = np.linalg.norm(b)
+    k = 0
+    for i in range(maxiter):
+        r = b - S.matvec(v) if i > 0 else b.copy()
+        res.append(np.linalg.norm(r))
+        if tol > 0 and res[-1] <= tol * nb:
+            break
+        if actions == "cg":
+            s = r
+        elif actions == "unit":
+            s = np.zeros(n); s[i] = 1.0
+        else:
+            raise ValueError(actions)
+        z = S.matvec(s)
+        d = s - D[:, :i] @ ((D[:, :i].T @ z) / eta[:i]) if i > 0 else s.copy()
+        et = z @ d
+        if not et > 0:
+            break
+        D[:, i] = d
+        eta[i] = et
+        v = v + (s @ r) / et * d
+        k = i + 1
+    else:
+        r = b - S.matvec(v)
+        res.append(np.linalg.norm(r))
+    return v, D[:, :k], eta[:k], np.array(res)
+
+
+def cg_solve(S, tol: float, maxiter: int):
+    """Plain conjugate gradients (Sec. 4.1) on S x = S.b."""
+    b = S.b
+    x = np.zeros_like(b); r = b.copy(); p = r.copy(); rr = r @ r
+    nb = np.sqrt(rr)
+    for it in range(maxiter):
+        if np.sqrt(rr) <= tol * nb:
+            return x, it
+        Ap = S.matvec(p)
+        a = rr / (p @ Ap)
+        x += a * p; r -= a * Ap
+        rr2 = r @ r
+        p = r + (rr2 / rr) * p
+        rr = rr2
+    return x, maxiter
+
+
+def two_stage_posterior(S: SchurSystem, vp: np.ndarray, X: np.ndarray,
+                        D: Optional[np.ndarray] = None, eta: Optional[np.ndarray] = None):
+    """Posterior mean, and (if D, eta given) IterGP combined variance, at the
+    rows of X from volume weights vp (Sec. 4.2; Wenger et al. 2022 combined
+    covariance k - k_x^T C k_x under the IC/BC-conditioned prior)."""
+    o = S.o
+    kb, kp = o.Lk_points(X)
+    alpha = S.full_weights(vp)
+    mean = kb.T @ alpha[:o.p.n_b] + kp.T @ alpha[o.p.n_b:]
+    if D is None:
+        return mean, None
+    Wb = sla.solve_triangular(S.cf[0], kb, lower=True)
+    var_b = o.sf2 - np.einsum("ij,ij->j", Wb, Wb)
+    # cross-covariance of the conditioned prior between volumes and x
+    w = kp - np.stack([o.cross_rmatvec(c) for c in sla.cho_solve(S.cf, kb).T], axis=1)
+    proj = D.T @ w                                   # k x M
+    var = var_b - np.einsum("ij,ij->j", proj, proj / eta[:, None])
+    return mean, var
