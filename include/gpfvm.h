@@ -1,0 +1,209 @@
+/*
+ * gpfvm -- GP finite-volume PDE solver hot path for AMD Instinct MI355X (gfx950).
+ *
+ * A Gaussian-process prior with a separable squared-exponential kernel is
+ * conditioned on
+ *   - volume observations  L_V[u] = int_V D[u] dx = int_V f dx  over the cells
+ *     of a factorised box grid (paper Sec. 3, eq. linop-def; Sec. 4.1,
+ *     Definition of a factorised box FVM scheme), and
+ *   - initial/boundary point observations d^beta u(x) = y (Sec. 2.2, L_IC,BC),
+ * with Gram matrix G = L k L' + Sigma in observation order [points; volumes]
+ * (Sec. 2.2; Sec. 2.1 eq. affine-posterior).  The volume block is applied
+ * matrix-free as a sum of Kronecker products of closed-form 1-D cell-integral
+ * factors (Sec. 3.2 eq. LkL; Sec. 4.1 eq. kronecker-structure); the point block
+ * is conditioned exactly by Cholesky and the volume observations by IterGP
+ * with CG actions (Sec. 4.1, Sec. 4.2).
+ *
+ * Conventions common to every call
+ *   - Dimension 0 is time.  Volumes are flattened row-major (dimension 0
+ *     slowest); a point group is a tensor grid flattened the same way.
+ *   - "host" pointers are read during the call only and may be freed on return.
+ *     "device" pointers are caller-owned HBM buffers (e.g. PyTorch tensors) that
+ *     must stay valid until the work queued on `stream` has completed; the
+ *     library never frees them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is queued on it; a call returns once its work is queued,
+ *     except where a call states that it synchronises.
+ *   - Every call returns GPFVM_OK (0) or a negative GPFVM_E_* code.  No C++
+ *     exception crosses this boundary.  Arguments are validated before any HIP
+ *     call, so invalid input never reaches the GPU.  gpfvm_last_error() gives
+ *     a message.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef GPFVM_H
+#define GPFVM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPFVM_OK             0
+#define GPFVM_E_INVALID     -1   /* malformed argument or IBVP                      */
+#define GPFVM_E_NOMEM       -2   /* device allocation failed / admission refused    */
+#define GPFVM_E_HIP         -3   /* a HIP runtime call failed                       */
+#define GPFVM_E_NOTPD       -4   /* Cholesky of the point block failed (not PD), or  */
+                                 /* IterGP breakdown (eta <= 0)                      */
+#define GPFVM_E_NOCONV      -5   /* iteration budget exhausted above the tolerance;  */
+                                 /* the early-terminated state stays valid           */
+#define GPFVM_E_STATE       -6   /* call out of order (e.g. posterior before solve)  */
+
+#define GPFVM_MAX_DIM        3
+#define GPFVM_MAX_TERMS      8
+#define GPFVM_MAX_GROUPS    16
+#define GPFVM_MAX_DERIV      4   /* highest derivative order per dim in any term    */
+
+#define GPFVM_PREC_FP64      0   /* every step in float64                            */
+#define GPFVM_PREC_MIXED     1   /* Gram matvec in low precision inside FP64
+                                    iterative refinement; FP64 recurrences           */
+
+#define GPFVM_TILE_FP32      0   /* mixed-path tile formats (see gpfvm_solve_opts)   */
+#define GPFVM_TILE_BF16X3    1
+#define GPFVM_TILE_FP16X2    2
+#define GPFVM_TILE_BF16      3
+#define GPFVM_TILE_FP16      4
+
+typedef struct gpfvm_handle gpfvm_handle;
+
+/* One tensor grid of point observations  d^deriv u(x) = y + eps,
+ * eps ~ N(0, noise_var)  (Sec. 2.2: initial and boundary observations). */
+typedef struct {
+  int n[GPFVM_MAX_DIM];              /* points per dim (1 pins a dim, e.g. t = 0)    */
+  const double* axis[GPFVM_MAX_DIM]; /* host: n[i] coordinates per dim               */
+  int deriv[GPFVM_MAX_DIM];          /* derivative multi-index beta                  */
+  const double* y;                   /* host: prod(n) values, row-major              */
+  double noise_var;                  /* > 0                                          */
+} gpfvm_pointgroup;
+
+/* An initial-boundary value problem (Sec. 1 eq. def-lin-pde with the IBVP
+ * stacking of Sec. 2.2).  The operator is D = sum_t coef[t] * (cell_coef if
+ * cellwise[t]) * d^alpha_t; per-cell coefficients are constant inside a cell
+ * (appendix on variable bathymetry). */
+typedef struct {
+  int dim;                            /* 2 or 3 (time + 1 or 2 space dims)           */
+  int ncell[GPFVM_MAX_DIM];           /* cells per dim, >= 1                          */
+  const double* edges[GPFVM_MAX_DIM]; /* host: ncell[i]+1 strictly increasing edges  */
+  double lengthscale[GPFVM_MAX_DIM];  /* SE lengthscale per dim, > 0                  */
+  double outputscale;                 /* sigma_f^2 > 0                                */
+  int nterm;                          /* 1..GPFVM_MAX_TERMS                           */
+  const int* alpha;                   /* host: nterm*dim derivative multi-indices     */
+  const double* coef;                 /* host: nterm coefficients                     */
+  const int* cellwise;                /* host: nterm flags, or NULL (all 0)           */
+  const double* cell_coef;            /* host: N per-volume values, needed if any     */
+                                      /* cellwise flag is set, else ignored           */
+  const double* f_int;                /* host: N values of int_V f, or NULL (= 0)     */
+  double noise_pde;                   /* PDE observation noise (see next field)       */
+  int noise_pde_relative;             /* 1: variance = noise_pde * mean diagonal of   */
+                                      /* L_V k L_V';  0: variance = noise_pde         */
+  int ngroup;                         /* 0..GPFVM_MAX_GROUPS                          */
+  const gpfvm_pointgroup* groups;     /* host                                         */
+} gpfvm_ibvp;
+
+typedef struct {
+  int max_iter;        /* capacity for stored IterGP directions (>= 1)              */
+  int tile;            /* GPFVM_TILE_* format prepared for the mixed path           */
+} gpfvm_assemble_opts;
+
+typedef struct {
+  int prec;            /* GPFVM_PREC_FP64 or GPFVM_PREC_MIXED                       */
+  double tol;          /* stop once ||r|| <= tol ||b|| on the volume system (0: none)*/
+  int max_iter;        /* IterGP iterations (<= assemble max_iter)                  */
+  int resume;          /* 1: continue from the stored state of a previous solve     */
+  int tile;            /* mixed path: GPFVM_TILE_* format of the inner matvec        */
+  double inner_tol;    /* mixed path: inner relative reduction per refinement step  */
+  int max_outer;       /* mixed path: refinement steps                              */
+  int check_every;     /* host convergence poll interval in iterations (>= 1)       */
+} gpfvm_solve_opts;
+
+typedef struct {
+  int iters;           /* IterGP directions stored (posterior rank)                 */
+  int outer;           /* refinement steps taken (mixed path)                       */
+  double rel_res;      /* ||b - S v|| / ||b|| on the volume (Schur) system          */
+  double rel_res_full; /* ||y - G alpha|| / ||y|| on the whole IBVP system           */
+  int status;          /* GPFVM_OK, GPFVM_E_NOCONV or GPFVM_E_NOTPD                 */
+} gpfvm_solve_info;
+
+typedef struct {
+  int dim; long long n_pde; int n_b; long long n;
+  double noise_pde_var;          /* absolute PDE noise variance actually used       */
+  long long device_bytes;        /* HBM held by the handle                          */
+} gpfvm_handle_info;
+
+/* Default option values. */
+void gpfvm_default_assemble_opts(gpfvm_assemble_opts* o);
+void gpfvm_default_solve_opts(gpfvm_solve_opts* o);
+
+/* Validate an IBVP without touching the GPU.  Returns GPFVM_OK or
+ * GPFVM_E_INVALID (message via gpfvm_last_error(NULL)). */
+int gpfvm_validate(const gpfvm_ibvp* p);
+
+/* Build a handle: copy the IBVP to HBM, compute the closed-form 1-D factors
+ * (Sec. 3.1 eq. linop-simplified reduces every cell integral of a derivative
+ * to differences of antiderivatives/derivatives, evaluated with erf and exp),
+ * form the point block G_bb (dense), factor it G_bb = L L^T (Sec. 4.2) and its
+ * triangular inverse, and prepare the matrix-free plan of G_pp.  Synchronises
+ * on `stream` before returning (so that a non-PD point block is reported).
+ * Errors: INVALID, NOMEM, HIP, NOTPD.  On error *out is NULL. */
+int gpfvm_assemble(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts,
+                   void* stream, gpfvm_handle** out);
+
+/* y = G x for the whole IBVP Gram (observation order [points; volumes],
+ * including Sigma), for nrhs right-hand sides.  x, y: device, n*nrhs doubles,
+ * right-hand side r at offset r*n; x and y must not overlap.  prec selects the
+ * float64 plan or the mixed plan (GPFVM_PREC_MIXED, tile format given at
+ * assemble).  Errors: INVALID, HIP. */
+int gpfvm_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec,
+                 void* stream);
+
+/* Representer weights alpha = G^{-1} y (Sec. 4, representer weights): exact
+ * conditioning on the points, then IterGP with CG actions on the volume
+ * observations (Sec. 4.1-4.2).  The state (weights, directions, eta) stays in
+ * the handle for gpfvm_posterior and for resume.  Synchronises to fill info.
+ * Returns GPFVM_OK, or NOCONV / NOTPD (info->status too), or INVALID / HIP. */
+int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* opts, gpfvm_solve_info* info,
+                void* stream);
+
+/* Posterior mean and variance on the tensor grid axis[0] x ... x axis[dim-1]
+ * (Sec. 2.1 eq. lin-cond-mean and eq. lin-cond-cov).  The variance is the
+ * IterGP combined variance: prior minus the exact point-block reduction minus
+ * the reduction captured by the stored directions (it equals the mathematical
+ * posterior variance once the directions span the volume system).
+ * n: host, dim sizes; axis: host coordinate arrays; mean, var: device,
+ * prod(n) doubles row-major (var may be NULL).  Errors: INVALID, STATE
+ * (no solve yet), NOMEM, HIP. */
+int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const double* const* axis,
+                    double* mean, double* var, void* stream);
+
+/* Copy the current representer weights (n doubles, [points; volumes]) to the
+ * device buffer `alpha`.  Errors: STATE, HIP. */
+int gpfvm_weights(gpfvm_handle* h, double* alpha, void* stream);
+
+/* Dense block of G (including Sigma): rows [r0, r0+nr), cols [c0, c0+nc) into
+ * the device buffer out (row-major, leading dimension ld >= nc), built from the
+ * factor tiles (Sec. 4.1 eq. kronecker-structure).  Errors: INVALID, HIP. */
+int gpfvm_gram_block(gpfvm_handle* h, long long r0, long long nr, long long c0,
+                     long long nc, double* out, long long ld, void* stream);
+
+/* 1-D closed-form factor matrix (Sec. 3.1 eq. linop-simplified, Sec. 3.2
+ * eq. LkL) for one lengthscale, evaluated by the factor kernel:
+ *   kind 0  cell-cell   out[i*n2+j] = int_{I_i} int_{J_j} d^p_s d^q_s' k(s,s')
+ *   kind 1  point-cell  out[i*n2+j] = int_{J_j} d^p_x d^q_s' k(x_i,s')
+ *   kind 2  point-point out[i*n2+j] = d^p_x d^q_x' k(x_i,x'_j)
+ * For cell arguments the host array holds n+1 edges, for points n coordinates.
+ * 0 <= p, q and p+q <= 2*GPFVM_MAX_DERIV.  out: device, n1*n2 doubles. */
+int gpfvm_factor(int kind, int p, int q, int n1, const double* a1, int n2,
+                 const double* a2, double lengthscale, double* out, void* stream);
+
+int gpfvm_get_info(const gpfvm_handle* h, gpfvm_handle_info* info);
+
+/* Free every device buffer of the handle (after synchronising its stream).
+ * NULL is accepted. */
+void gpfvm_destroy(gpfvm_handle* h);
+
+/* Message of the last error on h, or (h == NULL) of this thread's last
+ * validation / assemble error.  Never NULL. */
+const char* gpfvm_last_error(const gpfvm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPFVM_H */

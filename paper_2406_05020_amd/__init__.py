@@ -1,0 +1,267 @@
+"""Python binding of the gpfvm C-ABI (libgpfvm.so): argument marshalling only.
+
+Every computation runs in the HIP library; PyTorch supplies device memory and
+streams.  The names follow the C entry points declared in include/gpfvm.h
+(gpfvm_assemble -> assemble, ...).  Importing this module does not touch the
+GPU; loading the library fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgpfvm.so")
+
+OK, E_INVALID, E_NOMEM, E_HIP, E_NOTPD, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6
+PREC_FP64, PREC_MIXED = 0, 1
+TILE_FP32, TILE_BF16X3, TILE_FP16X2, TILE_BF16, TILE_FP16 = 0, 1, 2, 3, 4
+MAX_DIM, MAX_TERMS, MAX_GROUPS = 3, 8, 16
+ERR_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOTPD", -5: "NOCONV", -6: "STATE"}
+
+_dp = C.POINTER(C.c_double)
+
+
+class PointGroup(C.Structure):
+    _fields_ = [("n", C.c_int * MAX_DIM), ("axis", _dp * MAX_DIM), ("deriv", C.c_int * MAX_DIM),
+                ("y", _dp), ("noise_var", C.c_double)]
+
+
+class IBVPStruct(C.Structure):
+    _fields_ = [("dim", C.c_int), ("ncell", C.c_int * MAX_DIM), ("edges", _dp * MAX_DIM),
+                ("lengthscale", C.c_double * MAX_DIM), ("outputscale", C.c_double), ("nterm", C.c_int),
+                ("alpha", C.POINTER(C.c_int)), ("coef", _dp), ("cellwise", C.POINTER(C.c_int)),
+                ("cell_coef", _dp), ("f_int", _dp), ("noise_pde", C.c_double), ("noise_pde_relative", C.c_int),
+                ("ngroup", C.c_int), ("groups", C.POINTER(PointGroup))]
+
+
+class AssembleOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("tile", C.c_int)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("prec", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int), ("resume", C.c_int),
+                ("tile", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("outer", C.c_int), ("rel_res", C.c_double), ("rel_res_full", C.c_double),
+                ("status", C.c_int)]
+
+
+class HandleInfo(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_pde", C.c_longlong), ("n_b", C.c_int), ("n", C.c_longlong),
+                ("noise_pde_var", C.c_double), ("device_bytes", C.c_longlong)]
+
+
+_lib = None
+
+SYMBOLS = {
+    "gpfvm_default_assemble_opts": ([C.POINTER(AssembleOpts)], None),
+    "gpfvm_default_solve_opts": ([C.POINTER(SolveOpts)], None),
+    "gpfvm_validate": ([C.POINTER(IBVPStruct)], C.c_int),
+    "gpfvm_assemble": ([C.POINTER(IBVPStruct), C.POINTER(AssembleOpts), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "gpfvm_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "gpfvm_solve": ([C.c_void_p, C.POINTER(SolveOpts), C.POINTER(SolveInfo), C.c_void_p], C.c_int),
+    "gpfvm_posterior": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(_dp), C.c_void_p, C.c_void_p,
+                         C.c_void_p], C.c_int),
+    "gpfvm_weights": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "gpfvm_gram_block": ([C.c_void_p, C.c_longlong, C.c_longlong, C.c_longlong, C.c_longlong, C.c_void_p,
+                          C.c_longlong, C.c_void_p], C.c_int),
+    "gpfvm_factor": ([C.c_int, C.c_int, C.c_int, C.c_int, _dp, C.c_int, _dp, C.c_double, C.c_void_p, C.c_void_p],
+                     C.c_int),
+    "gpfvm_get_info": ([C.c_void_p, C.POINTER(HandleInfo)], C.c_int),
+    "gpfvm_destroy": ([C.c_void_p], None),
+    "gpfvm_last_error": ([C.c_void_p], C.c_char_p),
+}
+
+
+class GpfvmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gpfvm error {ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def lib():
+    """The loaded HIP library; raises if it was not built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"gpfvm HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build() or python paper_2406_05020_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in SYMBOLS.items():
+            f = getattr(L, name)
+            f.argtypes, f.restype = args, res
+        _lib = L
+    return _lib
+
+
+def last_error(h=None) -> str:
+    return lib().gpfvm_last_error(h).decode()
+
+
+def _check(rc: int, h=None):
+    if rc != OK:
+        raise GpfvmError(rc, last_error(h))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _arr(a, dtype=np.float64):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+class _Marshal:
+    """Keeps the numpy buffers referenced by an IBVPStruct alive."""
+
+    def __init__(self, p):
+        self.keep = []
+        s = IBVPStruct()
+        s.dim = int(p.d)
+        d = min(int(p.d), MAX_DIM, len(p.edges))     # the library validates dim itself
+        for i in range(d):
+            e = self._keep(_arr(p.edges[i]))
+            s.ncell[i] = len(e) - 1
+            s.edges[i] = e.ctypes.data_as(_dp)
+            s.lengthscale[i] = float(p.lengthscale[i])
+        s.outputscale = float(p.outputscale)
+        terms = list(p.terms)
+        s.nterm = len(terms)
+        al = self._keep(np.array([t.alpha for t in terms], dtype=np.int32).reshape(-1))
+        cf = self._keep(_arr([t.coef for t in terms]))
+        cw = self._keep(np.array([1 if t.cellwise else 0 for t in terms], dtype=np.int32))
+        s.alpha = al.ctypes.data_as(C.POINTER(C.c_int))
+        s.coef = cf.ctypes.data_as(_dp)
+        s.cellwise = cw.ctypes.data_as(C.POINTER(C.c_int))
+        if getattr(p, "cell_coef", None) is not None:
+            s.cell_coef = self._keep(_arr(p.cell_coef).ravel()).ctypes.data_as(_dp)
+        if getattr(p, "f_int", None) is not None:
+            s.f_int = self._keep(_arr(p.f_int).ravel()).ctypes.data_as(_dp)
+        s.noise_pde = float(p.noise_pde)
+        s.noise_pde_relative = 1 if p.noise_pde_relative else 0
+        groups = list(p.groups)
+        s.ngroup = len(groups)
+        ga = (PointGroup * max(1, len(groups)))()
+        for k, g in enumerate(groups):
+            for i in range(min(d, len(g.axes))):
+                ax = self._keep(_arr(g.axes[i]))
+                ga[k].n[i] = len(ax)
+                ga[k].axis[i] = ax.ctypes.data_as(_dp)
+                ga[k].deriv[i] = int(g.deriv[i])
+            ga[k].y = self._keep(_arr(g.y).ravel()).ctypes.data_as(_dp)
+            ga[k].noise_var = float(g.noise_var)
+        self.keep.append(ga)
+        s.groups = C.cast(ga, C.POINTER(PointGroup))
+        self.s = s
+
+    def _keep(self, a):
+        self.keep.append(a)
+        return a
+
+
+def validate(p) -> None:
+    m = _Marshal(p)
+    _check(lib().gpfvm_validate(C.byref(m.s)))
+
+
+def assemble(p, max_iter: int = 512, tile: int = TILE_FP32, stream=None) -> C.c_void_p:
+    m = _Marshal(p)
+    o = AssembleOpts(max_iter, tile)
+    h = C.c_void_p()
+    _check(lib().gpfvm_assemble(C.byref(m.s), C.byref(o), _stream(stream), C.byref(h)))
+    return h
+
+
+def get_info(h) -> dict:
+    info = HandleInfo()
+    _check(lib().gpfvm_get_info(h, C.byref(info)), h)
+    return {k: getattr(info, k) for k, _ in HandleInfo._fields_}
+
+
+def matvec(h, x, y, nrhs: int = 1, prec: int = PREC_FP64, stream=None) -> None:
+    """y = G x for device float64 tensors x, y of n * nrhs elements."""
+    _check(lib().gpfvm_matvec(h, nrhs, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), prec, _stream(stream)), h)
+
+
+def default_solve_opts() -> SolveOpts:
+    o = SolveOpts()
+    lib().gpfvm_default_solve_opts(C.byref(o))
+    return o
+
+
+def solve(h, prec: int = PREC_FP64, tol: float = 1e-8, max_iter: int = 512, resume: bool = False,
+          tile: int = TILE_FP32, inner_tol: float = 1e-2, max_outer: int = 20, check_every: int = 8,
+          stream=None, raise_on_noconv: bool = False) -> dict:
+    o = SolveOpts(prec, tol, max_iter, 1 if resume else 0, tile, inner_tol, max_outer, check_every)
+    info = SolveInfo()
+    rc = lib().gpfvm_solve(h, C.byref(o), C.byref(info), _stream(stream))
+    if rc not in (OK, E_NOCONV, E_NOTPD) or (raise_on_noconv and rc != OK):
+        _check(rc, h)
+    out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+    out["rc"] = rc
+    return out
+
+
+def posterior(h, axes: Sequence[np.ndarray], mean, var=None, stream=None) -> None:
+    d = len(axes)
+    ax = [_arr(a) for a in axes]
+    n = (C.c_int * d)(*[len(a) for a in ax])
+    ptrs = (_dp * d)(*[a.ctypes.data_as(_dp) for a in ax])
+    _check(lib().gpfvm_posterior(h, d, n, ptrs, C.c_void_p(mean.data_ptr()),
+                                 C.c_void_p(var.data_ptr()) if var is not None else None, _stream(stream)), h)
+
+
+def weights(h, out, stream=None) -> None:
+    _check(lib().gpfvm_weights(h, C.c_void_p(out.data_ptr()), _stream(stream)), h)
+
+
+def gram_block(h, r0: int, nr: int, c0: int, nc: int, out, ld: Optional[int] = None, stream=None) -> None:
+    _check(lib().gpfvm_gram_block(h, r0, nr, c0, nc, C.c_void_p(out.data_ptr()), ld or nc, _stream(stream)), h)
+
+
+def factor(kind: int, p: int, q: int, a1, a2, lengthscale: float, out, stream=None) -> None:
+    a1 = _arr(a1); a2 = _arr(a2)
+    n1 = len(a1) - 1 if kind == 0 else len(a1)
+    n2 = len(a2) if kind == 2 else len(a2) - 1
+    _check(lib().gpfvm_factor(kind, p, q, n1, a1.ctypes.data_as(_dp), n2, a2.ctypes.data_as(_dp),
+                              float(lengthscale), C.c_void_p(out.data_ptr()), _stream(stream)))
+
+
+def destroy(h) -> None:
+    if h:
+        lib().gpfvm_destroy(h)
+
+
+@dataclass
+class Solved:
+    """Convenience: one IBVP assembled, solved and evaluated on its grid."""
+    mean: "object"
+    var: "object"
+    info: dict
+
+
+def solve_ibvp(p, prec: int = PREC_FP64, tol: float = 1e-8, max_iter: int = 512, grid=None, with_var=True,
+               device: str = "cuda:0", **kw) -> Solved:
+    import torch
+    h = assemble(p, max_iter=max_iter)
+    try:
+        info = solve(h, prec=prec, tol=tol, max_iter=max_iter, **kw)
+        axes = grid if grid is not None else p.grid
+        M = int(np.prod([len(a) for a in axes]))
+        mean = torch.empty(M, dtype=torch.float64, device=device)
+        var = torch.empty(M, dtype=torch.float64, device=device) if with_var else None
+        posterior(h, axes, mean, var)
+        torch.cuda.synchronize()
+        return Solved(mean, var, info)
+    finally:
+        destroy(h)

@@ -1,0 +1,646 @@
+// C-ABI entry points: validation, assembly of an IBVP handle, the full-Gram
+// matvec, dense Gram blocks and the stand-alone factor call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "common.h"
+#include "internal.h"
+
+using namespace gpfvm;
+
+static thread_local std::string g_last_error = "";
+
+#define HIPCHK(h, expr)                                                   \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess) {                                               \
+      (h)->err = std::string("HIP error: ") + hipGetErrorString(e_) +     \
+                 " at " #expr;                                            \
+      return GPFVM_E_HIP;                                                 \
+    }                                                                     \
+  } while (0)
+
+static int fail_static(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+extern "C" void gpfvm_default_assemble_opts(gpfvm_assemble_opts* o) {
+  if (!o) return;
+  o->max_iter = 512;
+  o->tile = GPFVM_TILE_FP32;
+}
+
+extern "C" void gpfvm_default_solve_opts(gpfvm_solve_opts* o) {
+  if (!o) return;
+  o->prec = GPFVM_PREC_FP64;
+  o->tol = 1e-8;
+  o->max_iter = 512;
+  o->resume = 0;
+  o->tile = GPFVM_TILE_FP32;
+  o->inner_tol = 1e-2;
+  o->max_outer = 20;
+  o->check_every = 8;
+}
+
+// ---------------------------------------------------------------------------
+// validation (no HIP calls)
+// ---------------------------------------------------------------------------
+static bool finite_arr(const double* a, long long n) {
+  for (long long i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+extern "C" int gpfvm_validate(const gpfvm_ibvp* p) {
+  if (!p) return fail_static(GPFVM_E_INVALID, "ibvp is NULL");
+  if (p->dim < 2 || p->dim > GPFVM_MAX_DIM) return fail_static(GPFVM_E_INVALID, "dim must be 2 or 3");
+  long long N = 1;
+  for (int i = 0; i < p->dim; ++i) {
+    if (p->ncell[i] < 1 || p->ncell[i] > (1 << 20))
+      return fail_static(GPFVM_E_INVALID, "ncell[" + std::to_string(i) + "] out of range");
+    if (!p->edges[i]) return fail_static(GPFVM_E_INVALID, "edges[" + std::to_string(i) + "] is NULL");
+    if (!finite_arr(p->edges[i], p->ncell[i] + 1))
+      return fail_static(GPFVM_E_INVALID, "edges[" + std::to_string(i) + "] not finite");
+    for (int j = 0; j < p->ncell[i]; ++j)
+      if (!(p->edges[i][j + 1] > p->edges[i][j]))
+        return fail_static(GPFVM_E_INVALID, "edges[" + std::to_string(i) + "] not strictly increasing");
+    if (!(p->lengthscale[i] > 0) || !std::isfinite(p->lengthscale[i]))
+      return fail_static(GPFVM_E_INVALID, "lengthscale must be positive");
+    N *= p->ncell[i];
+  }
+  if (N > (1LL << 31) - 1) return fail_static(GPFVM_E_INVALID, "too many volumes");
+  if (!(p->outputscale > 0) || !std::isfinite(p->outputscale))
+    return fail_static(GPFVM_E_INVALID, "outputscale must be positive");
+  if (p->nterm < 1 || p->nterm > GPFVM_MAX_TERMS) return fail_static(GPFVM_E_INVALID, "nterm out of range");
+  if (!p->alpha || !p->coef) return fail_static(GPFVM_E_INVALID, "alpha/coef is NULL");
+  bool any_cw = false;
+  for (int t = 0; t < p->nterm; ++t) {
+    for (int i = 0; i < p->dim; ++i) {
+      const int a = p->alpha[t * p->dim + i];
+      if (a < 0 || a > GPFVM_MAX_DERIV)
+        return fail_static(GPFVM_E_INVALID, "derivative order out of range [0, 4]");
+    }
+    if (!std::isfinite(p->coef[t])) return fail_static(GPFVM_E_INVALID, "coef not finite");
+    if (p->cellwise && p->cellwise[t]) any_cw = true;
+  }
+  if (any_cw) {
+    if (!p->cell_coef) return fail_static(GPFVM_E_INVALID, "cellwise term without cell_coef");
+    if (!finite_arr(p->cell_coef, N)) return fail_static(GPFVM_E_INVALID, "cell_coef not finite");
+  }
+  if (p->f_int && !finite_arr(p->f_int, N)) return fail_static(GPFVM_E_INVALID, "f_int not finite");
+  if (!(p->noise_pde > 0) || !std::isfinite(p->noise_pde))
+    return fail_static(GPFVM_E_INVALID, "noise_pde must be positive");
+  if (p->ngroup < 0 || p->ngroup > GPFVM_MAX_GROUPS) return fail_static(GPFVM_E_INVALID, "ngroup out of range");
+  if (p->ngroup > 0 && !p->groups) return fail_static(GPFVM_E_INVALID, "groups is NULL");
+  long long nb = 0;
+  for (int g = 0; g < p->ngroup; ++g) {
+    const gpfvm_pointgroup& G = p->groups[g];
+    long long sz = 1;
+    for (int i = 0; i < p->dim; ++i) {
+      if (G.n[i] < 1) return fail_static(GPFVM_E_INVALID, "group " + std::to_string(g) + ": n < 1");
+      if (!G.axis[i]) return fail_static(GPFVM_E_INVALID, "group " + std::to_string(g) + ": axis NULL");
+      if (!finite_arr(G.axis[i], G.n[i])) return fail_static(GPFVM_E_INVALID, "group axis not finite");
+      if (G.deriv[i] < 0 || G.deriv[i] > GPFVM_MAX_DERIV)
+        return fail_static(GPFVM_E_INVALID, "group derivative order out of range [0, 4]");
+      sz *= G.n[i];
+    }
+    if (!G.y) return fail_static(GPFVM_E_INVALID, "group " + std::to_string(g) + ": y is NULL");
+    if (!finite_arr(G.y, sz)) return fail_static(GPFVM_E_INVALID, "group y not finite");
+    if (!(G.noise_var > 0) || !std::isfinite(G.noise_var))
+      return fail_static(GPFVM_E_INVALID, "group noise_var must be positive");
+    nb += sz;
+  }
+  if (nb > 65536) return fail_static(GPFVM_E_INVALID, "more than 65536 point observations");
+  return GPFVM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// assembly
+// ---------------------------------------------------------------------------
+static int upload(gpfvm_handle* h, const double* src, size_t n, double** dst) {
+  *dst = (double*)h->arena.alloc(std::max<size_t>(n, 1) * sizeof(double));
+  if (!*dst) { h->err = "out of device memory"; return GPFVM_E_NOMEM; }
+  if (n) HIPCHK(h, hipMemcpyAsync(*dst, src, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  return GPFVM_OK;
+}
+
+static int make_factor(gpfvm_handle* h, int kind, int p, int q, int n1, const double* a1, int n2,
+                       const double* a2, double ell, Factor& f) {
+  f.n1 = n1;
+  f.n2 = n2;
+  f.d = (double*)h->arena.alloc((size_t)n1 * n2 * sizeof(double));
+  if (!f.d) { h->err = "out of device memory (factor)"; return GPFVM_E_NOMEM; }
+  HIPCHK(h, launch_factor(kind, p, q, n1, a1, n2, a2, ell, 1.0, f.d, n2, h->stream));
+  return GPFVM_OK;
+}
+
+static int add_f32_copy(gpfvm_handle* h, Factor& f) {
+  if (f.f) return GPFVM_OK;
+  f.f = (float*)h->arena.alloc((size_t)f.n1 * f.n2 * sizeof(float));
+  if (!f.f) { h->err = "out of device memory (factor f32)"; return GPFVM_E_NOMEM; }
+  HIPCHK(h, launch_copy_f64_to_f32(f.d, f.f, (i64)f.n1 * f.n2, h->stream));
+  return GPFVM_OK;
+}
+
+static void merge_terms(gpfvm_handle* h) {
+  // (L_V k L_V')  =  sum_{a, a'} c_a c_a' prod_i F^{a_i a'_i}, F^{pq} = (-1)^q D(p+q)
+  // (Sec. 3.2 eq. LkL): merge pairs with the same orders and scaling flags.
+  h->gterms.clear();
+  for (auto& t1 : h->pterms)
+    for (auto& t2 : h->pterms) {
+      GramTerm g;
+      int asum = 0;
+      for (int i = 0; i < h->d; ++i) {
+        g.m[i] = t1.alpha[i] + t2.alpha[i];
+        asum += t2.alpha[i];
+      }
+      g.coef = t1.coef * t2.coef * ((asum & 1) ? -1.0 : 1.0);
+      g.lflag = t1.cellwise;
+      g.rflag = t2.cellwise;
+      bool merged = false;
+      for (auto& e : h->gterms)
+        if (e.lflag == g.lflag && e.rflag == g.rflag && e.m[0] == g.m[0] && e.m[1] == g.m[1] &&
+            e.m[2] == g.m[2]) {
+          e.coef += g.coef;
+          merged = true;
+          break;
+        }
+      if (!merged) h->gterms.push_back(g);
+    }
+  h->gterms.erase(std::remove_if(h->gterms.begin(), h->gterms.end(), [](const GramTerm& g) { return g.coef == 0.0; }),
+                  h->gterms.end());
+}
+
+static int build_ops(gpfvm_handle* h) {
+  const int d = h->d;
+  // ---- volume block ----
+  KronOp& op = h->op_pp;
+  op = KronOp();
+  op.d = d;
+  for (int i = 0; i < d; ++i) op.in_shape[i] = op.out_shape[i] = h->nc[i];
+  op.in_len = h->N;
+  if (d == 2) {
+    // pre-sum the last-dimension matrices of terms sharing (m_0, L, R)
+    struct Key { int m0, l, r; };
+    std::vector<Key> keys;
+    std::vector<std::vector<const GramTerm*>> members;
+    for (auto& g : h->gterms) {
+      size_t k = 0;
+      for (; k < keys.size(); ++k)
+        if (keys[k].m0 == g.m[0] && keys[k].l == g.lflag && keys[k].r == g.rflag) break;
+      if (k == keys.size()) { keys.push_back({g.m[0], g.lflag, g.rflag}); members.emplace_back(); }
+      members[k].push_back(&g);
+    }
+    h->combos.clear();
+    h->combos.reserve(keys.size());
+    for (size_t k = 0; k < keys.size(); ++k) {
+      Factor c;
+      c.n1 = c.n2 = h->nc[1];
+      c.d = (double*)h->arena.alloc((size_t)c.n1 * c.n2 * sizeof(double));
+      if (!c.d) { h->err = "out of device memory"; return GPFVM_E_NOMEM; }
+      std::vector<const double*> mats;
+      std::vector<double> cf;
+      for (auto* g : members[k]) { mats.push_back(h->Dfac[{1, g->m[1]}].d); cf.push_back(g->coef); }
+      for (size_t s0 = 0; s0 < mats.size(); s0 += 8) {
+        // (at most 8 per pass; accumulate by chaining with the partial result)
+        std::vector<const double*> mm(mats.begin() + s0, mats.begin() + std::min(mats.size(), s0 + 8));
+        std::vector<double> cc(cf.begin() + s0, cf.begin() + std::min(cf.size(), s0 + 8));
+        if (s0 > 0) { mm.push_back(c.d); cc.push_back(1.0); }
+        HIPCHK(h, launch_lincomb((int)mm.size(), mm.data(), cc.data(), (i64)c.n1 * c.n2, c.d, h->stream));
+      }
+      h->combos.push_back(c);
+      KronTerm t{};
+      t.M[0] = h->Dfac[{0, keys[k].m0}].d; t.ld[0] = h->nc[0];
+      t.M[1] = h->combos.back().d; t.ld[1] = h->nc[1];
+      t.alpha = h->sf2;
+      t.lscale = keys[k].l; t.rscale = keys[k].r;
+      op.terms.push_back(t);
+    }
+  } else {
+    for (auto& g : h->gterms) {
+      KronTerm t{};
+      for (int i = 0; i < d; ++i) { t.M[i] = h->Dfac[{i, g.m[i]}].d; t.ld[i] = h->nc[i]; }
+      t.alpha = h->sf2 * g.coef;
+      t.lscale = g.lflag; t.rscale = g.rflag;
+      op.terms.push_back(t);
+    }
+  }
+  // ---- cross blocks, one operator per point group ----
+  h->op_bp.clear();
+  h->op_pb.clear();
+  for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+    const Group& G = h->groups[gi];
+    KronOp bp, pb;
+    bp.d = pb.d = d;
+    for (int i = 0; i < d; ++i) {
+      bp.in_shape[i] = h->nc[i]; bp.out_shape[i] = G.n[i];
+      pb.in_shape[i] = G.n[i]; pb.out_shape[i] = h->nc[i];
+    }
+    bp.in_len = h->N; bp.out_off = G.offset;
+    pb.in_len = h->nb;
+    for (size_t ti = 0; ti < h->pterms.size(); ++ti) {
+      const PdeTerm& P = h->pterms[ti];
+      KronTerm a{}, b{};
+      for (int i = 0; i < d; ++i) {
+        a.M[i] = b.M[i] = h->Qfac[gi][ti][i].d;
+        a.ld[i] = b.ld[i] = h->nc[i];
+        b.trans[i] = 1;
+      }
+      a.alpha = b.alpha = h->sf2 * P.coef;
+      a.rscale = P.cellwise;
+      b.lscale = P.cellwise;
+      b.in_off = G.offset;
+      bp.terms.push_back(a);
+      pb.terms.push_back(b);
+    }
+    h->op_bp.push_back(bp);
+    h->op_pb.push_back(pb);
+  }
+  return GPFVM_OK;
+}
+
+// float32 operators: same structure on float32 copies of the factors
+int gpfvm::build_ops32(gpfvm_handle* h) {
+  for (auto& kv : h->Dfac) { int rc = add_f32_copy(h, kv.second); if (rc) return rc; }
+  for (auto& c : h->combos) { int rc = add_f32_copy(h, c); if (rc) return rc; }
+  for (auto& g : h->Qfac)
+    for (auto& t : g)
+      for (int i = 0; i < h->d; ++i) { int rc = add_f32_copy(h, t[i]); if (rc) return rc; }
+  auto to32 = [&](const void* p) -> const void* {
+    for (auto& kv : h->Dfac) if (kv.second.d == p) return kv.second.f;
+    for (auto& c : h->combos) if (c.d == p) return c.f;
+    for (auto& g : h->Qfac) for (auto& t : g) for (int i = 0; i < h->d; ++i) if (t[i].d == p) return t[i].f;
+    return nullptr;
+  };
+  auto conv = [&](const KronOp& a) {
+    KronOp b = a;
+    for (auto& t : b.terms)
+      for (int i = 0; i < h->d; ++i) t.M[i] = to32(t.M[i]);
+    return b;
+  };
+  h->op_pp32 = conv(h->op_pp);
+  h->op_bp32.clear(); h->op_pb32.clear();
+  for (auto& o : h->op_bp) h->op_bp32.push_back(conv(o));
+  for (auto& o : h->op_pb) h->op_pb32.push_back(conv(o));
+  if (h->cellc && !h->cellc_f) {
+    h->cellc_f = (float*)h->arena.alloc((size_t)h->N * sizeof(float));
+    if (!h->cellc_f) { h->err = "out of device memory"; return GPFVM_E_NOMEM; }
+    HIPCHK(h, launch_copy_f64_to_f32(h->cellc, h->cellc_f, h->N, h->stream));
+  }
+  if (h->nb > 0 && !h->Linv_f) {
+    h->Linv_f = (float*)h->arena.alloc((size_t)h->nb * h->nb * sizeof(float));
+    if (!h->Linv_f) { h->err = "out of device memory"; return GPFVM_E_NOMEM; }
+    HIPCHK(h, launch_copy_f64_to_f32(h->Linv, h->Linv_f, (i64)h->nb * h->nb, h->stream));
+  }
+  return GPFVM_OK;
+}
+
+
+static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, hipStream_t s, gpfvm_handle* h) {
+  const int d = p->dim;
+  h->d = d;
+  h->stream = s;
+  h->N = 1;
+  for (int i = 0; i < d; ++i) {
+    h->nc[i] = p->ncell[i];
+    h->N *= p->ncell[i];
+    h->ell[i] = p->lengthscale[i];
+    h->edges_h[i].assign(p->edges[i], p->edges[i] + p->ncell[i] + 1);
+  }
+  h->sf2 = p->outputscale;
+  h->max_iter = opts ? std::max(1, opts->max_iter) : 512;
+  h->tile = opts ? opts->tile : GPFVM_TILE_FP32;
+  for (int t = 0; t < p->nterm; ++t) {
+    PdeTerm P;
+    for (int i = 0; i < d; ++i) P.alpha[i] = p->alpha[t * d + i];
+    P.coef = p->coef[t];
+    P.cellwise = (p->cellwise && p->cellwise[t]) ? 1 : 0;
+    h->pterms.push_back(P);
+  }
+  h->has_cc = 0;
+  for (auto& P : h->pterms) h->has_cc |= P.cellwise;
+  i64 off = 0;
+  for (int g = 0; g < p->ngroup; ++g) {
+    Group G;
+    const gpfvm_pointgroup& S = p->groups[g];
+    G.size = 1;
+    for (int i = 0; i < d; ++i) {
+      G.n[i] = S.n[i];
+      G.deriv[i] = S.deriv[i];
+      G.axis[i].assign(S.axis[i], S.axis[i] + S.n[i]);
+      G.size *= S.n[i];
+    }
+    G.noise = S.noise_var;
+    G.offset = off;
+    off += G.size;
+    h->groups.push_back(G);
+  }
+  h->nb = (int)off;
+  h->n = h->nb + h->N;
+  merge_terms(h);
+  if (h->gterms.empty()) { h->err = "the operator's volume Gram is identically zero"; return GPFVM_E_INVALID; }
+
+  // ---- inputs to HBM ----
+  int rc;
+  for (int i = 0; i < d; ++i)
+    if ((rc = upload(h, h->edges_h[i].data(), h->edges_h[i].size(), &h->edges[i]))) return rc;
+  if (h->has_cc)
+    if ((rc = upload(h, p->cell_coef, (size_t)h->N, &h->cellc))) return rc;
+  {
+    std::vector<double> y((size_t)h->n, 0.0);
+    for (int g = 0; g < p->ngroup; ++g)
+      std::memcpy(&y[h->groups[g].offset], p->groups[g].y, h->groups[g].size * sizeof(double));
+    if (p->f_int) std::memcpy(&y[h->nb], p->f_int, (size_t)h->N * sizeof(double));
+    if ((rc = upload(h, y.data(), y.size(), &h->yobs))) return rc;
+  }
+
+  // ---- 1-D factors (closed form) ----
+  for (auto& g : h->gterms)
+    for (int i = 0; i < d; ++i) {
+      auto key = std::make_pair(i, g.m[i]);
+      if (h->Dfac.count(key)) continue;
+      Factor f;
+      if ((rc = make_factor(h, 0, g.m[i], 0, h->nc[i], h->edges[i], h->nc[i], h->edges[i], h->ell[i], f))) return rc;
+      h->Dfac[key] = f;
+    }
+  std::vector<std::array<double*, 3>> gaxis(h->groups.size());
+  for (size_t g = 0; g < h->groups.size(); ++g)
+    for (int i = 0; i < d; ++i)
+      if ((rc = upload(h, h->groups[g].axis[i].data(), h->groups[g].axis[i].size(), &gaxis[g][i]))) return rc;
+  h->Qfac.assign(h->groups.size(), std::vector<std::array<Factor, 3>>(h->pterms.size()));
+  for (size_t g = 0; g < h->groups.size(); ++g)
+    for (size_t t = 0; t < h->pterms.size(); ++t)
+      for (int i = 0; i < d; ++i)
+        if ((rc = make_factor(h, 1, h->groups[g].deriv[i], h->pterms[t].alpha[i], h->groups[g].n[i], gaxis[g][i],
+                              h->nc[i], h->edges[i], h->ell[i], h->Qfac[g][t][i])))
+          return rc;
+  std::vector<Factor> ppf;
+  GramMeta M;
+  std::memset(&M, 0, sizeof(M));
+  for (size_t g1 = 0; g1 < h->groups.size(); ++g1)
+    for (size_t g2 = 0; g2 < h->groups.size(); ++g2)
+      for (int i = 0; i < d; ++i) {
+        Factor f;
+        if ((rc = make_factor(h, 2, h->groups[g1].deriv[i], h->groups[g2].deriv[i], h->groups[g1].n[i], gaxis[g1][i],
+                              h->groups[g2].n[i], gaxis[g2][i], h->ell[i], f)))
+          return rc;
+        M.Pp[g1][g2][i] = f.d;
+      }
+
+  // ---- PDE noise ----
+  if (p->noise_pde_relative) {
+    // mean over volumes of diag(L_V k L_V') = sf2 * sum_terms coef L R prod_i D_i(m_i)[j_i, j_i]
+    std::map<std::pair<int, int>, std::vector<double>> diag;
+    for (auto& kv : h->Dfac) {
+      const int n1 = kv.second.n1;
+      std::vector<double> full((size_t)n1 * n1);
+      HIPCHK(h, hipMemcpyAsync(full.data(), kv.second.d, full.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(h, hipStreamSynchronize(s));
+      std::vector<double> dg(n1);
+      for (int j = 0; j < n1; ++j) dg[j] = full[(size_t)j * n1 + j];
+      diag[kv.first] = dg;
+    }
+    std::vector<std::array<const double*, 3>> dp(h->gterms.size());
+    for (size_t t = 0; t < h->gterms.size(); ++t)
+      for (int i = 0; i < d; ++i) dp[t][i] = diag[{i, h->gterms[t].m[i]}].data();
+    double acc = 0;
+    int idx[3];
+    for (i64 v = 0; v < h->N; ++v) {
+      i64 r = v;
+      for (int i = d - 1; i >= 0; --i) { idx[i] = (int)(r % h->nc[i]); r /= h->nc[i]; }
+      double sv = 0;
+      for (size_t t = 0; t < h->gterms.size(); ++t) {
+        const GramTerm& g = h->gterms[t];
+        double w = g.coef;
+        if (g.lflag) w *= p->cell_coef[v];
+        if (g.rflag) w *= p->cell_coef[v];
+        for (int i = 0; i < d; ++i) w *= dp[t][i][idx[i]];
+        sv += w;
+      }
+      acc += sv;
+    }
+    h->sig_pde = p->noise_pde * h->sf2 * acc / (double)h->N;
+  } else {
+    h->sig_pde = p->noise_pde;
+  }
+
+  // ---- dense-entry metadata (point block, dense Gram tiles) ----
+  M.d = d; M.nb = h->nb; M.ngroup = (int)h->groups.size(); M.nterm = (int)h->pterms.size();
+  M.ngterm = (int)h->gterms.size();
+  if (M.ngterm > MAXGT) { h->err = "too many merged operator terms"; return GPFVM_E_INVALID; }
+  for (int i = 0; i < d; ++i) M.nc[i] = h->nc[i];
+  for (int i = d; i < 3; ++i) M.nc[i] = 1;
+  for (size_t g = 0; g < h->groups.size(); ++g) {
+    for (int i = 0; i < 3; ++i) M.gn[g][i] = (i < d) ? h->groups[g].n[i] : 1;
+    M.goff[g] = h->groups[g].offset;
+    M.gnoise[g] = h->groups[g].noise;
+    for (size_t t = 0; t < h->pterms.size(); ++t)
+      for (int i = 0; i < d; ++i) M.Qp[g][t][i] = h->Qfac[g][t][i].d;
+  }
+  M.goff[h->groups.size()] = h->nb;
+  for (size_t t = 0; t < h->pterms.size(); ++t) { M.tcoef[t] = h->pterms[t].coef; M.tcw[t] = h->pterms[t].cellwise; }
+  for (size_t t = 0; t < h->gterms.size(); ++t) {
+    for (int i = 0; i < 3; ++i) M.gm[t][i] = h->gterms[t].m[i];
+    M.gcoef[t] = h->gterms[t].coef; M.gl[t] = h->gterms[t].lflag; M.gr[t] = h->gterms[t].rflag;
+  }
+  for (auto& kv : h->Dfac) M.Dp[kv.first.first][kv.first.second] = kv.second.d;
+  M.cellc = h->cellc;
+  M.sig_pde = h->sig_pde;
+  M.sf2 = h->sf2;
+  h->meta = (GramMeta*)h->arena.alloc(sizeof(GramMeta));
+  if (!h->meta) { h->err = "out of device memory"; return GPFVM_E_NOMEM; }
+  HIPCHK(h, hipMemcpyAsync(h->meta, &M, sizeof(M), hipMemcpyHostToDevice, s));
+
+  // ---- point block: G_bb, Cholesky, inverse factor ----
+  if (h->nb > 0) {
+    h->L = (double*)h->arena.alloc((size_t)h->nb * h->nb * sizeof(double));
+    h->Linv = (double*)h->arena.alloc((size_t)h->nb * h->nb * sizeof(double));
+    if (!h->L || !h->Linv) { h->err = "out of device memory (point block)"; return GPFVM_E_NOMEM; }
+    HIPCHK(h, launch_gram_block(h->meta, 0, h->nb, 0, h->nb, h->L, h->nb, s));
+    rc = cholesky_and_inverse(h->L, h->Linv, h->nb, h->arena, s, h->err);
+    if (rc) return rc;
+  }
+  if ((rc = build_ops(h))) return rc;
+  HIPCHK(h, hipStreamSynchronize(s));
+  return GPFVM_OK;
+}
+
+extern "C" int gpfvm_assemble(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream,
+                              gpfvm_handle** out) {
+  if (!out) return fail_static(GPFVM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int rc = gpfvm_validate(p);
+  if (rc) return rc;
+  if (opts && (opts->max_iter < 1 || opts->max_iter > (1 << 20)))
+    return fail_static(GPFVM_E_INVALID, "max_iter out of range");
+  gpfvm_handle* h = new (std::nothrow) gpfvm_handle();
+  if (!h) return fail_static(GPFVM_E_NOMEM, "host allocation failed");
+  try {
+    rc = assemble_impl(p, opts, (hipStream_t)stream, h);
+  } catch (const std::exception& e) {
+    h->err = std::string("internal error: ") + e.what();
+    rc = GPFVM_E_NOMEM;
+  }
+  if (rc) {
+    g_last_error = h->err;
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    h->arena.release();
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return GPFVM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// full-Gram matvec
+// ---------------------------------------------------------------------------
+static GemmDesc desc1(void* C, i64 c_rs, const void* A, i64 a_rs, i64 a_cs, const void* B, i64 b_rs, i64 b_cs,
+                      int M, int N, int K, double alpha, double beta, int tri) {
+  GemmDesc D;
+  std::memset(&D, 0, sizeof(D));
+  D.C = C; D.c_rs = c_rs; D.c_cs = 1; D.M = M; D.N = N; D.batch = 1; D.nseg = 1; D.beta = beta;
+  Seg& S = D.seg[0];
+  S.A = A; S.a_rs = a_rs; S.a_cs = a_cs; S.B = B; S.b_rs = b_rs; S.b_cs = b_cs; S.K = K; S.alpha = alpha; S.tri = tri;
+  return D;
+}
+
+int gpfvm::get_full_ops(gpfvm_handle* h, int nrhs, gpfvm_opset** out) {
+  auto it = h->full_ops.find(nrhs);
+  if (it != h->full_ops.end()) { *out = it->second.get(); return GPFVM_OK; }
+  auto os = std::make_unique<gpfvm_opset>();
+  os->nrhs = nrhs;
+  const i64 n = h->n, nb = h->nb;
+  os->XF = (double*)h->arena.alloc((size_t)n * nrhs * sizeof(double));
+  os->YF = (double*)h->arena.alloc((size_t)n * nrhs * sizeof(double));
+  os->TB = (double*)h->arena.alloc((size_t)std::max<i64>(nb, 1) * nrhs * sizeof(double));
+  if (!os->XF || !os->YF || !os->TB) { h->err = "out of device memory"; return GPFVM_E_NOMEM; }
+  // bind with explicit strides (vectors are [points; volumes] of length n)
+  std::vector<KronOp> pp{h->op_pp};
+  int rc = compile_kron_list(pp, F64, nrhs, os->XF + nb, n, os->YF + nb, n, h->cellc, h->cellc, 0.0, os->XF + nb,
+                         h->sig_pde, 1, h->arena, h->stream, os->pp, h->err);
+  if (rc) return rc;
+  if (nb > 0) {
+    rc = compile_kron_list(h->op_bp, F64, nrhs, os->XF + nb, n, os->YF, n, h->cellc, h->cellc, 0.0, nullptr, 0, 0,
+                           h->arena, h->stream, os->bp, h->err);
+    if (rc) return rc;
+    rc = compile_kron_list(h->op_pb, F64, nrhs, os->XF, n, os->YF + nb, n, h->cellc, h->cellc, 1.0, nullptr, 0, 1,
+                           h->arena, h->stream, os->pb, h->err);
+    if (rc) return rc;
+    // TB[r] = L^T x_b[r] ; YF_b[r] += L TB[r]
+    os->gbb_t.descs.push_back(desc1(os->TB, nb, os->XF, n, 1, h->L, nb, 1, nrhs, (int)nb, (int)nb, 1.0, 0.0, 4));
+    os->gbb_l.descs.push_back(desc1(os->YF, n, os->TB, nb, 1, h->L, 1, nb, nrhs, (int)nb, (int)nb, 1.0, 1.0, 3));
+    std::vector<Stage> st{os->gbb_t, os->gbb_l};
+    if (upload_stages(st, h->arena, h->stream) != hipSuccess) { h->err = "upload failed"; return GPFVM_E_HIP; }
+    os->gbb_t = st[0];
+    os->gbb_l = st[1];
+  }
+  *out = os.get();
+  h->full_ops[nrhs] = std::move(os);
+  return GPFVM_OK;
+}
+
+extern "C" int gpfvm_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec, void* stream) {
+  if (!h) return fail_static(GPFVM_E_INVALID, "handle is NULL");
+  if (nrhs < 1 || nrhs > 4096 || !x || !y) { h->err = "matvec: bad nrhs or NULL buffer"; return GPFVM_E_INVALID; }
+  if (prec != GPFVM_PREC_FP64 && prec != GPFVM_PREC_MIXED) { h->err = "matvec: bad prec"; return GPFVM_E_INVALID; }
+  const size_t bytes = (size_t)h->n * nrhs * sizeof(double);
+  if ((const char*)x < (const char*)y + bytes && (const char*)y < (const char*)x + bytes) {
+    h->err = "matvec: x and y overlap";
+    return GPFVM_E_INVALID;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  h->stream = s;
+  gpfvm_opset* os = nullptr;
+  int rc = get_full_ops(h, nrhs, &os);
+  if (rc) return rc;
+  HIPCHK(h, hipMemcpyAsync(os->XF, x, bytes, hipMemcpyDeviceToDevice, s));
+  if (h->nb > 0) {
+    HIPCHK(h, run_plan(os->bp, s));
+    HIPCHK(h, launch_gemm_stage(F64, os->gbb_t, s));
+    HIPCHK(h, launch_gemm_stage(F64, os->gbb_l, s));
+  }
+  if (prec == GPFVM_PREC_FP64) {
+    HIPCHK(h, run_plan(os->pp, s));
+  } else {
+    // volume block through the float32 (mixed) plan, everything else float64
+    gpfvm_sop* so = nullptr;
+    rc = get_sop(h, nrhs, F32, &so);
+    if (rc) return rc;
+    const i64 n = h->n, N = h->N, nb = h->nb;
+    for (int r = 0; r < nrhs; ++r)
+      HIPCHK(h, launch_copy_f64_to_f32(os->XF + r * n + nb, (float*)so->X + r * N, N, s));
+    HIPCHK(h, run_plan(so->pp, s));
+    for (int r = 0; r < nrhs; ++r)
+      HIPCHK(h, launch_copy_f32_to_f64((const float*)so->Y + r * N, os->YF + r * n + nb, N, s));
+  }
+  if (h->nb > 0) HIPCHK(h, run_plan(os->pb, s));
+  HIPCHK(h, hipMemcpyAsync(y, os->YF, bytes, hipMemcpyDeviceToDevice, s));
+  return GPFVM_OK;
+}
+
+extern "C" int gpfvm_gram_block(gpfvm_handle* h, long long r0, long long nr, long long c0, long long nc, double* out,
+                                long long ld, void* stream) {
+  if (!h) return fail_static(GPFVM_E_INVALID, "handle is NULL");
+  if (r0 < 0 || c0 < 0 || nr < 0 || nc < 0 || r0 + nr > h->n || c0 + nc > h->n || ld < nc || !out) {
+    h->err = "gram_block: range out of bounds";
+    return GPFVM_E_INVALID;
+  }
+  HIPCHK(h, launch_gram_block(h->meta, r0, nr, c0, nc, out, ld, (hipStream_t)stream));
+  return GPFVM_OK;
+}
+
+extern "C" int gpfvm_factor(int kind, int p, int q, int n1, const double* a1, int n2, const double* a2,
+                            double lengthscale, double* out, void* stream) {
+  if (kind < 0 || kind > 2) return fail_static(GPFVM_E_INVALID, "factor: kind must be 0, 1 or 2");
+  if (p < 0 || q < 0 || p + q > 2 * GPFVM_MAX_DERIV) return fail_static(GPFVM_E_INVALID, "factor: bad orders");
+  if (n1 < 1 || n2 < 1 || !a1 || !a2 || !out) return fail_static(GPFVM_E_INVALID, "factor: bad sizes/pointers");
+  if (!(lengthscale > 0)) return fail_static(GPFVM_E_INVALID, "factor: lengthscale must be positive");
+  const int l1 = (kind == 0) ? n1 + 1 : n1;
+  const int l2 = (kind == 2) ? n2 : n2 + 1;
+  if (!finite_arr(a1, l1) || !finite_arr(a2, l2)) return fail_static(GPFVM_E_INVALID, "factor: non-finite input");
+  hipStream_t s = (hipStream_t)stream;
+  double *d1 = nullptr, *d2 = nullptr;
+  if (hipMalloc(&d1, l1 * sizeof(double)) != hipSuccess || hipMalloc(&d2, l2 * sizeof(double)) != hipSuccess) {
+    if (d1) (void)hipFree(d1);
+    return fail_static(GPFVM_E_NOMEM, "factor: device allocation failed");
+  }
+  hipError_t e = hipMemcpyAsync(d1, a1, l1 * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d2, a2, l2 * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_factor(kind, p, q, n1, d1, n2, d2, lengthscale, 1.0, out, n2, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d1);
+  (void)hipFree(d2);
+  if (e != hipSuccess) return fail_static(GPFVM_E_HIP, std::string("factor: ") + hipGetErrorString(e));
+  return GPFVM_OK;
+}
+
+extern "C" int gpfvm_get_info(const gpfvm_handle* h, gpfvm_handle_info* info) {
+  if (!h || !info) return fail_static(GPFVM_E_INVALID, "NULL argument");
+  info->dim = h->d;
+  info->n_pde = h->N;
+  info->n_b = h->nb;
+  info->n = h->n;
+  info->noise_pde_var = h->sig_pde;
+  info->device_bytes = h->arena.bytes;
+  return GPFVM_OK;
+}
+
+extern "C" void gpfvm_destroy(gpfvm_handle* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipDeviceSynchronize();
+  h->arena.release();
+  delete h;
+}
+
+extern "C" const char* gpfvm_last_error(const gpfvm_handle* h) {
+  if (h) return h->err.c_str();
+  return g_last_error.c_str();
+}

@@ -1,0 +1,227 @@
+// Internal declarations of the gpfvm library (not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/gpfvm.h"
+
+namespace gpfvm {
+
+typedef long long i64;
+
+// ---------------------------------------------------------------------------
+// Grouped, batched, multi-segment GEMM descriptor.  One launch processes the
+// 32x32 output tiles of every descriptor in an array.  For descriptor D and
+// batch b:
+//   acc_s = sum over segments g with slot s of  alpha_g * A_g[b] (M x K_g) * B_g[b] (K_g x N)
+//   C[b]  = acc_0 + escale[b] o acc_1 + gamma * X[b] + beta * C[b]
+// Every operand is addressed through (row, col, batch) element strides, so
+// transposes and Kronecker mode products of row-major tensors need no copies.
+// ---------------------------------------------------------------------------
+constexpr int MAXSEG = 12;
+constexpr int TILE = 32;
+
+struct Seg {
+  const void* A;
+  const void* B;
+  i64 a_rs, a_cs, a_bs;
+  i64 b_rs, b_cs, b_bs;
+  int K;
+  int slot;     // 0 or 1 (slot 1 is multiplied elementwise by escale)
+  int tri;      // 0 dense; 1/2: A lower/upper-triangular; 3/4: B upper/lower-triangular
+                // (the K loop skips the blocks that are zero for this output tile)
+  int pad;
+  double alpha;
+};
+
+struct GemmDesc {
+  void* C;
+  i64 c_rs, c_cs, c_bs;
+  const double* escale;    // float64 scale (also for float32 plans)
+  i64 e_rs, e_cs, e_bs;
+  const void* X;           // elementwise addend (element type of C), or null
+  i64 x_rs, x_cs, x_bs;
+  double gamma;
+  double beta;
+  int M, N, batch, nseg;
+  int tiles_m, tiles_n, lower_only, pad;
+  i64 tile_begin;
+  Seg seg[MAXSEG];
+};
+
+enum Elt { F64 = 0, F32 = 1 };
+
+// One kernel launch: a set of descriptors whose outputs do not overlap.
+struct Stage {
+  std::vector<GemmDesc> descs;
+  GemmDesc* d_descs = nullptr;
+  i64 tiles = 0;
+};
+
+// Device memory arena owned by a handle (freed at destroy).
+struct Arena {
+  std::vector<void*> ptrs;
+  i64 bytes = 0;
+  void* alloc(size_t nbytes);      // returns nullptr on failure
+  void release();
+};
+
+// ---- a Kronecker-sum operator ------------------------------------------------
+// y = sum_s alpha_s * (Lscale_s o) (M_{s,0} x M_{s,1} x ... ) (Rscale_s o x_s)
+// with x_s = x + in_off_s (per right-hand side), M_{s,i} row-major (rows_i x cols_i).
+struct KronTerm {
+  const void* M[3];      // device matrices (element type of the plan)
+  i64 ld[3];             // leading dimension (row stride) of M
+  int trans[3];          // 1: use M^T
+  double alpha;
+  int lscale, rscale;    // 1: scale by the per-volume coefficient
+  i64 in_off;            // offset of this term's input inside x (per rhs)
+};
+
+struct KronOp {
+  int d = 0;
+  int in_shape[3] = {1, 1, 1};
+  int out_shape[3] = {1, 1, 1};
+  std::vector<KronTerm> terms;
+  i64 in_len = 0;        // elements of x per rhs (>= max in_off + prod(in_shape))
+  i64 out_off = 0;       // offset of the output inside y (per rhs)
+};
+
+// Compiled plan: stages of grouped GEMMs bound to fixed input/output buffers.
+struct Plan {
+  Elt elt = F64;
+  int nrhs = 0;
+  const void* x = nullptr;         // bound input (in_len * nrhs)
+  void* y = nullptr;               // bound output (prod(out_shape) * nrhs)
+  void* xs = nullptr;              // scaled input (cell_coef o x), if needed
+  i64 in_len = 0, out_len = 0;
+  const void* scale_src = nullptr; // per-volume coefficient (double or float)
+  std::vector<Stage> stages;       // the final stages accumulate into y
+  double flops = 0;                // executed flops per application (all rhs)
+};
+
+struct Factor {            // (n1 x n2) matrix on the device, row-major
+  double* d = nullptr;
+  float* f = nullptr;      // float32 copy for the mixed plan (or null)
+  int n1 = 0, n2 = 0;
+};
+
+struct Group {
+  int n[3] = {1, 1, 1};
+  int deriv[3] = {0, 0, 0};
+  double noise = 0;
+  i64 size = 0, offset = 0;
+  std::vector<double> axis[3];
+};
+
+struct PdeTerm {           // coef * (cell_coef if cellwise) * d^alpha
+  int alpha[3] = {0, 0, 0};
+  double coef = 0;
+  int cellwise = 0;
+};
+
+struct GramTerm {          // merged volume-Gram term
+  int m[3] = {0, 0, 0};
+  double coef = 0;
+  int lflag = 0, rflag = 0;
+};
+
+// ---- kernels / launchers (kernels.hip) --------------------------------------
+hipError_t launch_factor(int kind, int p, int q, int n1, const double* a1, int n2, const double* a2,
+                         double ell, double scale, double* out, i64 ld, hipStream_t s);
+hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s);
+hipError_t launch_scale(Elt elt, const void* src, const void* coef, void* dst, i64 n, int nrhs,
+                        hipStream_t s);
+hipError_t launch_axpby(i64 n, double a, const double* x, double b, double* y, hipStream_t s);
+hipError_t launch_copy_f64_to_f32(const double* x, float* y, i64 n, hipStream_t s);
+hipError_t launch_copy_f32_to_f64(const float* x, double* y, i64 n, hipStream_t s);
+hipError_t launch_lincomb(int nmat, const double* const* mats, const double* coefs, i64 len,
+                          double* out, hipStream_t s);
+hipError_t launch_fill(double* p, double v, i64 n, hipStream_t s);
+hipError_t launch_add_diag(double* A, i64 ld, i64 n0, i64 n, const double* vals, hipStream_t s);
+
+// deterministic reductions: out[0] = sum x*y (two passes, fixed order)
+hipError_t launch_dot(i64 n, const double* x, const double* y, double* partial, double* out,
+                      hipStream_t s);
+
+}  // namespace gpfvm
+
+namespace gpfvm { struct GramMeta; }
+
+// Bound operator plans of one handle for one right-hand-side count.
+struct gpfvm_opset {
+  int nrhs = 0;
+  // full-Gram matvec on [points; volumes] vectors (internal buffers XF, YF)
+  double *XF = nullptr, *YF = nullptr, *TB = nullptr;
+  gpfvm::Plan pp, bp, pb;
+  gpfvm::Stage gbb_t, gbb_l;        // y_b += L (L^T x_b)
+};
+
+// Operators of the volume (Schur) system S = G_pp + s2 I - G_pb G_bb^{-1} G_bp.
+struct gpfvm_sop {
+  int nrhs = 0;
+  gpfvm::Elt elt = gpfvm::F64;
+  void *X = nullptr, *Y = nullptr;  // N * nrhs
+  void *U = nullptr, *T = nullptr, *W = nullptr;   // n_b * nrhs
+  gpfvm::Plan pp, bp, pb;
+  gpfvm::Stage linv, linvt;         // T = L^{-1} U ; W = L^{-T} T
+  double flops_pp = 0;
+};
+
+struct gpfvm_handle {
+  int d = 0;
+  int nc[3] = {1, 1, 1};
+  gpfvm::i64 N = 0, n = 0;
+  int nb = 0;
+  double ell[3] = {1, 1, 1};
+  double sf2 = 1;
+  double sig_pde = 0;
+  int has_cc = 0;
+  int tile = GPFVM_TILE_FP32;
+  int max_iter = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  std::vector<gpfvm::PdeTerm> pterms;
+  std::vector<gpfvm::GramTerm> gterms;
+  std::vector<gpfvm::Group> groups;
+  std::vector<double> edges_h[3];
+
+  gpfvm::Arena arena;
+  double* edges[3] = {nullptr, nullptr, nullptr};
+  double* cellc = nullptr;         // N per-volume coefficient (or null)
+  float* cellc_f = nullptr;
+  double* yobs = nullptr;          // n: [y_b ; int_V f]
+  std::map<std::pair<int, int>, gpfvm::Factor> Dfac;   // (dim, order) -> D_i(order)
+  std::vector<gpfvm::Factor> combos;                  // pre-summed factor matrices
+  std::vector<std::vector<std::array<gpfvm::Factor, 3>>> Qfac;   // [group][term][dim]
+  double* L = nullptr;             // n_b x n_b Cholesky factor of G_bb (lower)
+  double* Linv = nullptr;          // n_b x n_b L^{-1} (lower)
+  float* Linv_f = nullptr;
+  gpfvm::GramMeta* meta = nullptr;   // device
+  gpfvm::KronOp op_pp, op_pp32;
+  std::vector<gpfvm::KronOp> op_bp, op_pb, op_bp32, op_pb32;
+  std::map<int, std::unique_ptr<gpfvm_opset>> full_ops;  // by nrhs
+  std::map<int, std::unique_ptr<gpfvm_sop>> sops;        // by nrhs (F64)
+  std::map<int, std::unique_ptr<gpfvm_sop>> sops32;      // by nrhs (F32)
+
+  // solver state
+  bool solved = false;
+  int iters = 0;
+  double* bS = nullptr;            // volume-system right-hand side (N)
+  double* ab0 = nullptr;           // G_bb^{-1} y_b
+  double* v = nullptr;             // volume weights (N)
+  double* Dd = nullptr;            // directions: column j at Dd + j * N
+  double* eta = nullptr;           // max_iter
+  double* vec = nullptr;           // solver vectors (r, s, z, d, ...), 8 * N
+  double* red = nullptr;           // reorthogonalisation partials (RCHUNK x max_iter)
+  double* aux = nullptr;           // dot partials and coefficients
+  double* scal = nullptr;          // device scalars
+  int* flag = nullptr;             // device flags
+};

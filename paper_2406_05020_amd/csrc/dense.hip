@@ -1,0 +1,314 @@
+// Dense pieces of the hot path: Gram tiles generated entry-by-entry from the
+// 1-D factor tiles (Sec. 4.1 eq. kronecker-structure; Sec. 2.2 IBVP block
+// layout), the float64 blocked Cholesky of the point block and its triangular
+// inverse (Sec. 4.2, Cholesky preconditioner).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "common.h"
+#include "internal.h"
+
+namespace gpfvm {
+
+// ---------------------------------------------------------------------------
+// Dense Gram block: entry (r, c) of G = L k L' + Sigma in observation order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void unflatten(i64 idx, int d, const int* shape, int* out) {
+  for (int i = d - 1; i >= 0; --i) {
+    out[i] = (int)(idx % shape[i]);
+    idx /= shape[i];
+  }
+}
+
+__device__ __forceinline__ int find_group(const GramMeta& G, i64 r) {
+  int g = 0;
+  while (g + 1 < G.ngroup && G.goff[g + 1] <= r) ++g;
+  return g;
+}
+
+__global__ void k_gram_block(const GramMeta* __restrict__ meta, i64 r0, i64 nr, i64 c0, i64 nc,
+                             double* __restrict__ out, i64 ld) {
+  const GramMeta& G = *meta;
+  const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nr * nc) return;
+  const i64 r = r0 + idx / nc, c = c0 + idx % nc;
+  const int d = G.d;
+  double v = 0;
+  int ir[3] = {0, 0, 0}, ic[3] = {0, 0, 0};
+  const bool rp = r < G.nb, cp = c < G.nb;
+  if (rp && cp) {                      // point - point
+    const int g1 = find_group(G, r), g2 = find_group(G, c);
+    unflatten(r - G.goff[g1], d, G.gn[g1], ir);
+    unflatten(c - G.goff[g2], d, G.gn[g2], ic);
+    double p = 1;
+    for (int i = 0; i < d; ++i) p *= G.Pp[g1][g2][i][(i64)ir[i] * G.gn[g2][i] + ic[i]];
+    v = G.sf2 * p;
+    if (r == c) v += G.gnoise[g1];
+  } else if (rp != cp) {               // point - volume (symmetric)
+    const i64 pr = rp ? r : c, vc = rp ? c : r;
+    const int g = find_group(G, pr);
+    unflatten(pr - G.goff[g], d, G.gn[g], ir);
+    unflatten(vc - G.nb, d, G.nc, ic);
+    for (int t = 0; t < G.nterm; ++t) {
+      double p = G.tcoef[t];
+      if (G.tcw[t]) p *= G.cellc[vc - G.nb];
+      for (int i = 0; i < d; ++i) p *= G.Qp[g][t][i][(i64)ir[i] * G.nc[i] + ic[i]];
+      v += p;
+    }
+    v *= G.sf2;
+  } else {                             // volume - volume
+    const i64 vr = r - G.nb, vc = c - G.nb;
+    unflatten(vr, d, G.nc, ir);
+    unflatten(vc, d, G.nc, ic);
+    for (int t = 0; t < G.ngterm; ++t) {
+      double p = G.gcoef[t];
+      if (G.gl[t]) p *= G.cellc[vr];
+      if (G.gr[t]) p *= G.cellc[vc];
+      for (int i = 0; i < d; ++i) p *= G.Dp[i][G.gm[t][i]][(i64)ir[i] * G.nc[i] + ic[i]];
+      v += p;
+    }
+    v *= G.sf2;
+    if (r == c) v += G.sig_pde;
+  }
+  out[(idx / nc) * ld + (idx % nc)] = v;
+}
+
+hipError_t launch_gram_block(const GramMeta* meta, i64 r0, i64 nr, i64 c0, i64 nc, double* out, i64 ld,
+                             hipStream_t s) {
+  const i64 tot = nr * nc;
+  if (tot == 0) return hipSuccess;
+  k_gram_block<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(meta, r0, nr, c0, nc, out, ld);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal block of the blocked Cholesky: factor the nb x nb block at (k0,k0)
+// in LDS, write L_kk back and the inverse of L_kk into dinv (NB x NB, row-major).
+// Sets *flag = 1 + k0 + j on the first non-positive pivot j.
+// ---------------------------------------------------------------------------
+constexpr int NB = 64;
+
+__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ A, i64 ld, int k0, int nb,
+                                                    double* __restrict__ dinv, int* __restrict__ flag) {
+  __shared__ double L[NB][NB + 1];
+  __shared__ double Inv[NB][NB + 1];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  for (int e = t; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    L[i][j] = (i < nb && j < nb) ? A[(i64)(k0 + i) * ld + k0 + j] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (*flag != 0) return;            // an earlier block already failed
+  for (int j = 0; j < nb; ++j) {
+    if (t == 0) {
+      const double p = L[j][j];
+      if (!(p > 0.0)) { bad = 1; L[j][j] = 1.0; }
+      else L[j][j] = sqrt(p);
+    }
+    __syncthreads();
+    if (bad) break;
+    const double piv = L[j][j];
+    for (int i = j + 1 + t; i < nb; i += blockDim.x) L[i][j] /= piv;
+    __syncthreads();
+    // rank-1 update of the trailing lower triangle
+    for (int e = t; e < (nb - j - 1) * (nb - j - 1); e += blockDim.x) {
+      const int i = j + 1 + e / (nb - j - 1), c = j + 1 + e % (nb - j - 1);
+      if (c <= i) L[i][c] -= L[i][j] * L[c][j];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (t == 0) atomicCAS(flag, 0, 1 + k0);
+    return;
+  }
+  // inverse of the lower-triangular L (column c solved by thread c)
+  for (int e = t; e < NB * NB; e += blockDim.x) Inv[e / NB][e % NB] = 0.0;
+  __syncthreads();
+  if (t < nb) {
+    const int c = t;
+    for (int i = c; i < nb; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= L[i][k] * Inv[k][c];
+      Inv[i][c] = s / L[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    if (i < nb && j < nb) A[(i64)(k0 + i) * ld + k0 + j] = (j <= i) ? L[i][j] : 0.0;
+    dinv[e] = (i < nb && j < nb) ? Inv[i][j] : 0.0;
+  }
+}
+
+__global__ void k_copy2d(const double* __restrict__ src, i64 sld, double* __restrict__ dst, i64 dld,
+                         i64 rows, i64 cols) {
+  const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const i64 r = idx / cols, c = idx % cols;
+  dst[r * dld + c] = src[r * sld + c];
+}
+
+__global__ void k_zero_upper(double* A, i64 ld, i64 n) {
+  const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const i64 r = idx / n, c = idx % n;
+  if (c > r) A[r * ld + c] = 0.0;
+}
+
+static void gemm_desc_init(GemmDesc& D) { std::memset(&D, 0, sizeof(D)); }
+
+// Append a plain descriptor C = alpha * A * B + beta * C (single batch).
+static GemmDesc mk_desc(double* C, i64 ldc, const double* A, i64 a_rs, i64 a_cs, const double* B, i64 b_rs,
+                        i64 b_cs, int M, int N, int K, double alpha, double beta, int lower_only,
+                        int tri) {
+  GemmDesc D;
+  gemm_desc_init(D);
+  D.C = C; D.c_rs = ldc; D.c_cs = 1;
+  D.M = M; D.N = N; D.batch = 1; D.nseg = 1;
+  D.beta = beta; D.lower_only = lower_only;
+  Seg& S = D.seg[0];
+  S.A = A; S.a_rs = a_rs; S.a_cs = a_cs;
+  S.B = B; S.b_rs = b_rs; S.b_cs = b_cs;
+  S.K = K; S.alpha = alpha; S.tri = tri;
+  return D;
+}
+
+// Extent in bytes of an operand addressed as base + r*rs + c*cs + b*bs.
+static bool extent_ok(const void* base, i64 rows, i64 cols, i64 batch, i64 rs, i64 cs, i64 bs, size_t es) {
+  if (!base) return false;
+  if (rows <= 0 || cols <= 0 || batch <= 0) return true;
+  if (rs < 0 || cs < 0 || bs < 0) return false;
+  const i64 last = (rows - 1) * rs + (cols - 1) * cs + (batch - 1) * bs;
+  return range_ok(base, (size_t)(last + 1) * es);
+}
+
+// Host-side bounds check of every operand of a descriptor.
+bool desc_in_bounds(const GemmDesc& D, size_t es) {
+  if (D.nseg < 1 || D.nseg > MAXSEG || D.M < 0 || D.N < 0 || D.batch < 1) return false;
+  if (!extent_ok(D.C, D.M, D.N, D.batch, D.c_rs, D.c_cs, D.c_bs, es)) return false;
+  if (D.escale && !extent_ok(D.escale, D.M, D.N, D.batch, D.e_rs, D.e_cs, D.e_bs, sizeof(double))) return false;
+  if (D.X && !extent_ok(D.X, D.M, D.N, D.batch, D.x_rs, D.x_cs, D.x_bs, es)) return false;
+  for (int g = 0; g < D.nseg; ++g) {
+    const Seg& S = D.seg[g];
+    if (S.K < 0 || S.slot < 0 || S.slot > 1 || S.tri < 0 || S.tri > 4) return false;
+    if (!extent_ok(S.A, D.M, S.K, D.batch, S.a_rs, S.a_cs, S.a_bs, es)) return false;
+    if (!extent_ok(S.B, S.K, D.N, D.batch, S.b_rs, S.b_cs, S.b_bs, es)) return false;
+  }
+  return true;
+}
+
+// Upload a list of stages whose descriptors are consecutive in one buffer.
+hipError_t upload_stages(std::vector<Stage>& stages, Arena& arena, hipStream_t s, Elt elt) {
+  const size_t es = (elt == F64) ? sizeof(double) : sizeof(float);
+  for (auto& st : stages)
+    for (auto& D : st.descs)
+      if (!desc_in_bounds(D, es)) return hipErrorInvalidValue;
+  size_t total = 0;
+  for (auto& st : stages) total += st.descs.size();
+  if (total == 0) return hipSuccess;
+  GemmDesc* dev = (GemmDesc*)arena.alloc(total * sizeof(GemmDesc));
+  if (!dev) return hipErrorOutOfMemory;
+  std::vector<GemmDesc> host;
+  host.reserve(total);
+  for (auto& st : stages) {
+    st.tiles = 0;
+    for (auto& D : st.descs) {
+      D.tiles_m = (D.M + TILE - 1) / TILE;
+      D.tiles_n = (D.N + TILE - 1) / TILE;
+      D.tile_begin = st.tiles;
+      st.tiles += (i64)D.tiles_m * D.tiles_n * D.batch;
+    }
+    st.d_descs = dev + host.size();
+    host.insert(host.end(), st.descs.begin(), st.descs.end());
+  }
+  hipError_t e = hipMemcpyAsync(dev, host.data(), total * sizeof(GemmDesc), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+// Blocked right-looking Cholesky of the n x n matrix A (row-major, lower),
+// then L^{-1} into Linv.  Returns GPFVM_OK / GPFVM_E_NOTPD / GPFVM_E_HIP.
+int cholesky_and_inverse(double* A, double* Linv, int n, Arena& arena, hipStream_t s, std::string& err) {
+  if (n == 0) return GPFVM_OK;
+  const int nblk = (n + NB - 1) / NB;
+  double* dinv = (double*)arena.alloc((size_t)nblk * NB * NB * sizeof(double));
+  double* panel = (double*)arena.alloc((size_t)n * NB * sizeof(double));
+  double* tmp = (double*)arena.alloc((size_t)n * NB * sizeof(double));
+  int* flag = (int*)arena.alloc(sizeof(int));
+  if (!dinv || !panel || !tmp || !flag) { err = "out of device memory (Cholesky workspace)"; return GPFVM_E_NOMEM; }
+  if (hipMemsetAsync(flag, 0, sizeof(int), s) != hipSuccess) return GPFVM_E_HIP;
+
+  // descriptors: per block k, a panel GEMM and a trailing update
+  std::vector<Stage> st(2 * nblk);
+  for (int k = 0; k < nblk; ++k) {
+    const int k0 = k * NB, nbk = std::min(NB, n - k0), r0 = k0 + nbk, mr = n - r0;
+    if (mr > 0) {
+      // L_panel = panel_copy * Dinv_k^T
+      st[2 * k].descs.push_back(mk_desc(A + (i64)r0 * n + k0, n, panel, NB, 1, dinv + (i64)k * NB * NB, 1, NB,
+                                        mr, nbk, nbk, 1.0, 0.0, 0, 0));
+      // A22 -= L_panel L_panel^T (lower tiles)
+      st[2 * k + 1].descs.push_back(mk_desc(A + (i64)r0 * n + r0, n, A + (i64)r0 * n + k0, n, 1,
+                                            A + (i64)r0 * n + k0, 1, n, mr, mr, nbk, -1.0, 1.0, 1, 0));
+    }
+  }
+  if (upload_stages(st, arena, s) != hipSuccess) { err = "descriptor upload failed"; return GPFVM_E_HIP; }
+  for (int k = 0; k < nblk; ++k) {
+    const int k0 = k * NB, nbk = std::min(NB, n - k0), r0 = k0 + nbk, mr = n - r0;
+    k_potrf_diag<<<1, 256, 0, s>>>(A, n, k0, nbk, dinv + (i64)k * NB * NB, flag);
+    if (mr > 0) {
+      const i64 tot = (i64)mr * nbk;
+      k_copy2d<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(A + (i64)r0 * n + k0, n, panel, NB, mr, nbk);
+      if (launch_gemm_stage(F64, st[2 * k], s) != hipSuccess) return GPFVM_E_HIP;
+      if (launch_gemm_stage(F64, st[2 * k + 1], s) != hipSuccess) return GPFVM_E_HIP;
+    }
+  }
+  int hflag = 0;
+  if (hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return GPFVM_E_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return GPFVM_E_HIP;
+  if (hflag != 0) {
+    err = "point-observation Gram block is not positive definite (Cholesky pivot <= 0 in block at row " +
+          std::to_string(hflag - 1) + ")";
+    return GPFVM_E_NOTPD;
+  }
+  {
+    const i64 tot = (i64)n * n;
+    k_zero_upper<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(A, n, n);
+  }
+  if (!Linv) return GPFVM_OK;
+
+  // Triangular inverse X = L^{-1} by block diagonals:
+  //   X_ii = Dinv_i ;  X_ij = -Dinv_i * sum_{k=j}^{i-1} L_ik X_kj   (i > j)
+  if (hipMemsetAsync(Linv, 0, (size_t)n * n * sizeof(double), s) != hipSuccess) return GPFVM_E_HIP;
+  for (int i = 0; i < nblk; ++i) {
+    const int i0 = i * NB, nbi = std::min(NB, n - i0);
+    k_copy2d<<<(unsigned)(((i64)nbi * nbi + 255) / 256), 256, 0, s>>>(dinv + (i64)i * NB * NB, NB,
+                                                                         Linv + (i64)i0 * n + i0, n, nbi, nbi);
+  }
+  double* T = (double*)arena.alloc((size_t)nblk * NB * NB * sizeof(double));
+  if (!T) { err = "out of device memory (inverse workspace)"; return GPFVM_E_NOMEM; }
+  std::vector<Stage> inv(2 * (nblk > 1 ? nblk - 1 : 0));
+  for (int dl = 1; dl < nblk; ++dl) {
+    for (int j = 0; j + dl < nblk; ++j) {
+      const int i = j + dl, i0 = i * NB, j0 = j * NB;
+      const int nbi = std::min(NB, n - i0), nbj = std::min(NB, n - j0);
+      // T_i = L[i0:i0+nbi, j0:i0] * X[j0:i0, j0:j0+nbj]
+      inv[2 * (dl - 1)].descs.push_back(mk_desc(T + (i64)i * NB * NB, NB, A + (i64)i0 * n + j0, n, 1,
+                                                 Linv + (i64)j0 * n + j0, n, 1, nbi, nbj, i0 - j0, 1.0, 0.0,
+                                                 0, 0));
+      // X_ij = -Dinv_i * T_i
+      inv[2 * (dl - 1) + 1].descs.push_back(mk_desc(Linv + (i64)i0 * n + j0, n, dinv + (i64)i * NB * NB, NB,
+                                                     1, T + (i64)i * NB * NB, NB, 1, nbi, nbj, nbi, -1.0, 0.0,
+                                                     0, 0));
+    }
+  }
+  if (upload_stages(inv, arena, s) != hipSuccess) { err = "descriptor upload failed"; return GPFVM_E_HIP; }
+  for (auto& stg : inv)
+    if (launch_gemm_stage(F64, stg, s) != hipSuccess) return GPFVM_E_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return GPFVM_E_HIP;
+  return GPFVM_OK;
+}
+
+}  // namespace gpfvm

@@ -1,0 +1,60 @@
+// Cross-file internal interfaces of the gpfvm library.
+#pragma once
+#include "common.h"
+
+namespace gpfvm {
+
+constexpr int MAXG = GPFVM_MAX_GROUPS;
+constexpr int MAXT = GPFVM_MAX_TERMS;
+constexpr int MAXGT = 64;                  // merged volume-Gram terms
+constexpr int MAXM = 2 * GPFVM_MAX_DERIV + 1;
+
+// Everything the dense Gram-entry kernel needs, in one device struct.
+struct GramMeta {
+  int d, nb, ngroup, nterm, ngterm, pad;
+  int nc[3];
+  int gn[MAXG][3];
+  i64 goff[MAXG + 1];
+  double gnoise[MAXG];
+  double tcoef[MAXT];
+  int tcw[MAXT];
+  int gm[MAXGT][3];
+  double gcoef[MAXGT];
+  int gl[MAXGT], gr[MAXGT];
+  const double* Dp[3][MAXM];               // cell-cell factors D_i(m), ld = nc[i]
+  const double* Qp[MAXG][MAXT][3];         // point-cell, ld = nc[i]
+  const double* Pp[MAXG][MAXG][3];         // point-point, ld = gn[g2][i]
+  const double* cellc;
+  double sig_pde, sf2;
+};
+
+hipError_t launch_gram_block(const GramMeta* meta, i64 r0, i64 nr, i64 c0, i64 nc, double* out, i64 ld,
+                             hipStream_t s);
+// Checks every descriptor against the live-range registry, then uploads.
+// Returns hipErrorInvalidValue (nothing uploaded) if an operand is out of bounds.
+hipError_t upload_stages(std::vector<Stage>& stages, Arena& arena, hipStream_t s, Elt elt = F64);
+void register_range(const void* p, size_t nbytes);
+void unregister_range(const void* p);
+bool range_ok(const void* p, size_t nbytes);
+int cholesky_and_inverse(double* A, double* Linv, int n, Arena& arena, hipStream_t s, std::string& err);
+
+// Kronecker plans (plan.hip)
+// scale_src: per-volume coefficients in the plan's element type (input scaling);
+// escale64: the same in float64 (output scaling in the GEMM epilogue).
+int compile_kron(const KronOp& op, Elt elt, int nrhs, const void* x, void* y, const void* scale_src,
+                 const double* escale64, double beta, const void* addx, double gamma, Arena& arena,
+                 hipStream_t s, Plan& out, std::string& err);
+// A list of operators into one y: accumulate = 1 sums them (same output
+// region), accumulate = 0 writes disjoint regions (KronOp::out_off).
+int compile_kron_list(const std::vector<KronOp>& ops, Elt elt, int nrhs, const void* x, i64 x_rhs_stride,
+                      void* y, i64 y_rhs_stride, const void* scale_src, const double* escale64, double beta,
+                      const void* addx, double gamma, int accumulate, Arena& arena, hipStream_t s, Plan& out,
+                      std::string& err);
+hipError_t run_plan(const Plan& p, hipStream_t s);
+
+// handle-level operators (api.hip / solver.hip)
+int get_full_ops(gpfvm_handle* h, int nrhs, gpfvm_opset** out);
+int get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out);
+int build_ops32(gpfvm_handle* h);
+
+}  // namespace gpfvm

@@ -1,0 +1,375 @@
+// Device kernels of the gpfvm library: closed-form 1-D factors, the grouped
+// MFMA GEMM that carries every Kronecker mode product, and small BLAS-1 /
+// elementwise kernels.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace gpfvm {
+
+// ============================================================================
+// 1-D squared-exponential calculus (Sec. 3.1 eq. linop-simplified)
+//
+// With k(r) = exp(-r^2 / (2 l^2)), u = r / l:
+//   k^(m)(r)  = (-1/l)^m He_m(u) k(r)                      m >= 0
+//   k^(-1)(r) = l sqrt(pi/2) erf(u / sqrt 2)               (antiderivative)
+//   k^(-2)(r) = l sqrt(pi/2) r erf(u / sqrt 2) + l^2 (k(r) - 1)
+// (He_m: probabilists' Hermite polynomials, He_{n+1} = u He_n - n He_{n-1};
+// the constant -l^2 in k^(-2) is immaterial below and keeps the values small.)
+// By the fundamental theorem of calculus applied to both cell integrals,
+//   int_I int_I' d^p_s d^q_s' k(s - s')  = (-1)^q  D2[k^(p+q-2)](I, I')
+//   D2[g](I, I') = g(b - a') - g(a - a') - g(b - b') + g(a - b')
+//   int_I' d^p_x d^q_s' k(x - s')        = (-1)^q (k^(p+q-1)(x - a') - k^(p+q-1)(x - b'))
+//   d^p_x d^q_x' k(x - x')               = (-1)^q k^(p+q)(x - x')
+// ============================================================================
+__device__ __forceinline__ double se_deriv(int m, double r, double ell) {
+  const double u = r / ell;
+  const double e = exp(-0.5 * u * u);
+  if (m == -2) {
+    const double c = ell * 1.2533141373155002512;   // l sqrt(pi/2)
+    return c * r * erf(u * 0.70710678118654752440) + ell * ell * expm1(-0.5 * u * u);
+  }
+  if (m == -1) return ell * 1.2533141373155002512 * erf(u * 0.70710678118654752440);
+  double h0 = 1.0, h1 = u;
+  double hm = (m == 0) ? h0 : h1;
+  for (int k = 1; k < m; ++k) {
+    const double h2 = u * h1 - k * h0;
+    h0 = h1;
+    h1 = h2;
+    hm = h2;
+  }
+  double s = 1.0;
+  const double il = -1.0 / ell;
+  for (int k = 0; k < m; ++k) s *= il;
+  return s * hm * e;
+}
+
+// kind 0: cell-cell; a1, a2 are edge arrays (n1+1, n2+1).
+// kind 1: point-cell; a1 points (n1), a2 edges (n2+1).
+// kind 2: point-point; a1 (n1), a2 (n2) points.
+__global__ void k_factor(int kind, int p, int q, int n1, const double* __restrict__ a1, int n2,
+                         const double* __restrict__ a2, double ell, double scale,
+                         double* __restrict__ out, i64 ld) {
+  const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (i64)n1 * n2) return;
+  const int i = (int)(idx / n2), j = (int)(idx % n2);
+  const double sgn = (q & 1) ? -scale : scale;
+  double v;
+  if (kind == 0) {
+    const double a = a1[i], b = a1[i + 1], c = a2[j], d = a2[j + 1];
+    const int m = p + q - 2;
+    v = (se_deriv(m, b - c, ell) - se_deriv(m, a - c, ell)) -
+        (se_deriv(m, b - d, ell) - se_deriv(m, a - d, ell));
+  } else if (kind == 1) {
+    const double x = a1[i];
+    const int m = p + q - 1;
+    v = se_deriv(m, x - a2[j], ell) - se_deriv(m, x - a2[j + 1], ell);
+  } else {
+    v = se_deriv(p + q, a1[i] - a2[j], ell);
+  }
+  out[(i64)i * ld + j] = sgn * v;
+}
+
+hipError_t launch_factor(int kind, int p, int q, int n1, const double* a1, int n2, const double* a2,
+                         double ell, double scale, double* out, i64 ld, hipStream_t s) {
+  const i64 tot = (i64)n1 * n2;
+  if (tot == 0) return hipSuccess;
+  const int bs = 256;
+  k_factor<<<dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s>>>(kind, p, q, n1, a1, n2, a2, ell,
+                                                                      scale, out, ld);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Grouped GEMM on MFMA.  One wavefront per 32x32 output tile (2x2 blocks of
+// the 16x16x4 MFMA), K staged through LDS 16 at a time.
+// Lane layout of the 16x16x4 MFMA (f64 and f32): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16].  Accumulator register i of lane l
+// holds D[row][l % 16] with row = 4 * (l / 16) + i for f32 but
+// row = l / 16 + 4 * i for f64 (both checked on gfx950 by a lane probe).
+// ============================================================================
+template <typename T> struct MfmaOp;
+template <> struct MfmaOp<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct MfmaOp<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+
+constexpr int KB = 16;
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_gemm(const GemmDesc* __restrict__ descs, int ndesc) {
+  typedef typename MfmaOp<T>::v4 v4;
+  __shared__ T As[TILE][KB + 1];
+  __shared__ T Bs[KB][TILE + 1];
+
+  const i64 tile = blockIdx.x;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {                      // last descriptor with tile_begin <= tile
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc& D = descs[lo];
+  const i64 local = tile - D.tile_begin;
+  const int tn = (int)(local % D.tiles_n);
+  const i64 rest = local / D.tiles_n;
+  const int tm = (int)(rest % D.tiles_m);
+  const i64 b = rest / D.tiles_m;
+  if (b >= D.batch) return;
+  if (D.lower_only && tn > tm) return;
+  const int m0 = tm * TILE, n0 = tn * TILE;
+  const int M = D.M, N = D.N;
+  const int lane = threadIdx.x;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  v4 acc0[2][2], acc1[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 4; ++r) { acc0[i][j][r] = 0; acc1[i][j][r] = 0; }
+  bool used1 = false;
+
+  for (int g = 0; g < D.nseg; ++g) {
+    const Seg& S = D.seg[g];
+    const T* __restrict__ A = reinterpret_cast<const T*>(S.A) + b * S.a_bs;
+    const T* __restrict__ B = reinterpret_cast<const T*>(S.B) + b * S.b_bs;
+    const T alpha = (T)S.alpha;
+    int kbeg = 0, kend = S.K;
+    if (S.tri == 1) kend = min(S.K, m0 + TILE);          // A lower-triangular
+    else if (S.tri == 2) kbeg = m0;                      // A upper-triangular
+    else if (S.tri == 3) kend = min(S.K, n0 + TILE);     // B upper-triangular (B[k][n] = 0 for k > n)
+    else if (S.tri == 4) kbeg = n0;                      // B lower-triangular (B[k][n] = 0 for k < n)
+    const bool a_rowfast = (S.a_cs == 1) || (S.a_rs != 1);
+    const bool b_colfast = (S.b_cs == 1) || (S.b_rs != 1);
+    for (int k0 = kbeg; k0 < kend; k0 += KB) {
+      // A tile: TILE x KB
+#pragma unroll
+      for (int j = 0; j < (TILE * KB) / 64; ++j) {
+        const int e = lane + 64 * j;
+        int r, c;
+        if (a_rowfast) { r = e / KB; c = e % KB; } else { r = e % TILE; c = e / TILE; }
+        const int gr = m0 + r, gc = k0 + c;
+        T val = 0;
+        if (gr < M && gc < kend) val = alpha * A[(i64)gr * S.a_rs + (i64)gc * S.a_cs];
+        As[r][c] = val;
+      }
+      // B tile: KB x TILE
+#pragma unroll
+      for (int j = 0; j < (TILE * KB) / 64; ++j) {
+        const int e = lane + 64 * j;
+        int r, c;
+        if (b_colfast) { r = e / TILE; c = e % TILE; } else { r = e % KB; c = e / KB; }
+        const int gr = k0 + r, gc = n0 + c;
+        T val = 0;
+        if (gr < kend && gc < N) val = B[(i64)gr * S.b_rs + (i64)gc * S.b_cs];
+        Bs[r][c] = val;
+      }
+      __syncthreads();
+      if (S.slot == 0) {
+#pragma unroll
+        for (int kk = 0; kk < KB / 4; ++kk) {
+          const T a0 = As[lr][kk * 4 + lk], a1 = As[16 + lr][kk * 4 + lk];
+          const T b0 = Bs[kk * 4 + lk][lr], b1 = Bs[kk * 4 + lk][16 + lr];
+          acc0[0][0] = MfmaOp<T>::mac(a0, b0, acc0[0][0]);
+          acc0[0][1] = MfmaOp<T>::mac(a0, b1, acc0[0][1]);
+          acc0[1][0] = MfmaOp<T>::mac(a1, b0, acc0[1][0]);
+          acc0[1][1] = MfmaOp<T>::mac(a1, b1, acc0[1][1]);
+        }
+      } else {
+        used1 = true;
+#pragma unroll
+        for (int kk = 0; kk < KB / 4; ++kk) {
+          const T a0 = As[lr][kk * 4 + lk], a1 = As[16 + lr][kk * 4 + lk];
+          const T b0 = Bs[kk * 4 + lk][lr], b1 = Bs[kk * 4 + lk][16 + lr];
+          acc1[0][0] = MfmaOp<T>::mac(a0, b0, acc1[0][0]);
+          acc1[0][1] = MfmaOp<T>::mac(a0, b1, acc1[0][1]);
+          acc1[1][0] = MfmaOp<T>::mac(a1, b0, acc1[1][0]);
+          acc1[1][1] = MfmaOp<T>::mac(a1, b1, acc1[1][1]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  T* __restrict__ C = reinterpret_cast<T*>(D.C) + b * D.c_bs;
+  const T* __restrict__ X = D.X ? reinterpret_cast<const T*>(D.X) + b * D.x_bs : nullptr;
+  const double* __restrict__ E = D.escale ? D.escale + b * D.e_bs : nullptr;
+  const T beta = (T)D.beta, gamma = (T)D.gamma;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + bm * 16 + MfmaOp<T>::row(lk, r);
+        const int col = n0 + bn * 16 + lr;
+        if (row < M && col < N && !(D.lower_only && col > row)) {
+          T v = acc0[bm][bn][r];
+          if (used1 && E) v += (T)E[(i64)row * D.e_rs + (i64)col * D.e_cs] * acc1[bm][bn][r];
+          if (X) v += gamma * X[(i64)row * D.x_rs + (i64)col * D.x_cs];
+          T* cp = C + (i64)row * D.c_rs + (i64)col * D.c_cs;
+          if (beta != (T)0) v += beta * *cp;
+          *cp = v;
+        }
+      }
+}
+
+hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
+  if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
+  const int nd = (int)st.descs.size();
+  if (elt == F64)
+    k_gemm<double><<<dim3((unsigned)st.tiles), dim3(64), 0, s>>>(st.d_descs, nd);
+  else
+    k_gemm<float><<<dim3((unsigned)st.tiles), dim3(64), 0, s>>>(st.d_descs, nd);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// elementwise kernels
+// ============================================================================
+template <typename T>
+__global__ void k_scale(const T* __restrict__ src, const T* __restrict__ coef, T* __restrict__ dst,
+                        i64 n, int nrhs) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  dst[i] = coef[i % n] * src[i];
+}
+
+hipError_t launch_scale(Elt elt, const void* src, const void* coef, void* dst, i64 n, int nrhs,
+                        hipStream_t s) {
+  const i64 tot = n * nrhs;
+  if (tot == 0) return hipSuccess;
+  const unsigned g = (unsigned)((tot + 255) / 256);
+  if (elt == F64)
+    k_scale<double><<<g, 256, 0, s>>>((const double*)src, (const double*)coef, (double*)dst, n, nrhs);
+  else
+    k_scale<float><<<g, 256, 0, s>>>((const float*)src, (const float*)coef, (float*)dst, n, nrhs);
+  return hipGetLastError();
+}
+
+__global__ void k_axpby(i64 n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+hipError_t launch_axpby(i64 n, double a, const double* x, double b, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_axpby<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, a, x, b, y);
+  return hipGetLastError();
+}
+
+__global__ void k_d2f(const double* __restrict__ x, float* __restrict__ y, i64 n) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+__global__ void k_f2d(const float* __restrict__ x, double* __restrict__ y, i64 n) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
+hipError_t launch_copy_f64_to_f32(const double* x, float* y, i64 n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_d2f<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, n);
+  return hipGetLastError();
+}
+hipError_t launch_copy_f32_to_f64(const float* x, double* y, i64 n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_f2d<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, n);
+  return hipGetLastError();
+}
+
+struct LinComb { const double* m[8]; double c[8]; int n; };
+__global__ void k_lincomb(LinComb lc, i64 len, double* __restrict__ out) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  double v = 0;
+  for (int k = 0; k < lc.n; ++k) v += lc.c[k] * lc.m[k][i];
+  out[i] = v;
+}
+hipError_t launch_lincomb(int nmat, const double* const* mats, const double* coefs, i64 len,
+                          double* out, hipStream_t s) {
+  if (nmat > 8) return hipErrorInvalidValue;
+  LinComb lc{};
+  lc.n = nmat;
+  for (int k = 0; k < nmat; ++k) { lc.m[k] = mats[k]; lc.c[k] = coefs[k]; }
+  k_lincomb<<<(unsigned)((len + 255) / 256), 256, 0, s>>>(lc, len, out);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double* p, double v, i64 n) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill(double* p, double v, i64 n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
+__global__ void k_add_diag(double* A, i64 ld, i64 n0, i64 n, const double* vals) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) A[(n0 + i) * ld + n0 + i] += vals[i];
+}
+hipError_t launch_add_diag(double* A, i64 ld, i64 n0, i64 n, const double* vals, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_add_diag<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(A, ld, n0, n, vals);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Deterministic dot product: fixed per-block partition, fixed tree order.
+// ============================================================================
+constexpr int DOT_BLOCKS = 512;
+constexpr int DOT_THREADS = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(DOT_THREADS) void k_dot_partial(i64 n, const double* __restrict__ x,
+                                                             const double* __restrict__ y,
+                                                             double* __restrict__ partial) {
+  __shared__ double red[DOT_THREADS / 64];
+  double acc = 0;
+  for (i64 i = (i64)blockIdx.x * DOT_THREADS + threadIdx.x; i < n; i += (i64)DOT_BLOCKS * DOT_THREADS)
+    acc += x[i] * y[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < DOT_THREADS / 64; ++w) t += red[w];
+    partial[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(DOT_THREADS) void k_dot_final(const double* __restrict__ partial,
+                                                           double* __restrict__ out) {
+  __shared__ double red[DOT_THREADS / 64];
+  double acc = 0;
+  for (int i = threadIdx.x; i < DOT_BLOCKS; i += DOT_THREADS) acc += partial[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < DOT_THREADS / 64; ++w) t += red[w];
+    out[0] = t;
+  }
+}
+
+hipError_t launch_dot(i64 n, const double* x, const double* y, double* partial, double* out,
+                      hipStream_t s) {
+  k_dot_partial<<<DOT_BLOCKS, DOT_THREADS, 0, s>>>(n, x, y, partial);
+  k_dot_final<<<1, DOT_THREADS, 0, s>>>(partial, out);
+  return hipGetLastError();
+}
+
+}  // namespace gpfvm

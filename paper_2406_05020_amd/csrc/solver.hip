@@ -1,0 +1,714 @@
+// Solve and posterior: exact conditioning on the point observations, then
+// IterGP with CG actions on the volume observations under the conditioned
+// prior (Sec. 4.1 IterGP, Sec. 4.2 Cholesky preconditioner), optional mixed-
+// precision iterative refinement, and the posterior mean / combined variance
+// on a tensor grid (Sec. 2.1 eq. lin-cond-mean, eq. lin-cond-cov).
+//
+// Volume system (block elimination of G = [[G_bb, G_bp], [G_pb, G_pp + s2 I]]):
+//   S = G_pp + s2 I - G_pb G_bb^{-1} G_bp,   b = y_p - G_pb G_bb^{-1} y_b.
+// IterGP with CG actions, every step in float64:
+//   r = b - S v ; s = r ; z = S s ; d = s - D (eta^{-1} o D^T z) ;
+//   eta_i = z^T d ; v += (s^T r / eta_i) d ; store d, eta_i.
+// The combined posterior uses C_i = sum_j d_j d_j^T / eta_j as S^{-1}.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "internal.h"
+
+using namespace gpfvm;
+
+#define HIPCHK(h, expr)                                                   \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess) {                                               \
+      (h)->err = std::string("HIP error: ") + hipGetErrorString(e_) +     \
+                 " at " #expr;                                            \
+      return GPFVM_E_HIP;                                                 \
+    }                                                                     \
+  } while (0)
+
+namespace {
+
+constexpr int RCHUNK = 256;        // chunks of N in the reorthogonalisation dots
+constexpr int RJ = 8;              // directions per block in the dots
+
+// partial[j * RCHUNK + c] = sum_{k in chunk c} D[j][k] z[k],  j < nd
+__global__ __launch_bounds__(256) void k_reorth_dots(const double* __restrict__ D, i64 N, int nd,
+                                                     const double* __restrict__ z, double* __restrict__ partial) {
+  const int c = blockIdx.x, j0 = blockIdx.y * RJ;
+  const i64 len = (N + RCHUNK - 1) / RCHUNK;
+  const i64 k0 = c * len, k1 = min(N, k0 + len);
+  double acc[RJ];
+#pragma unroll
+  for (int j = 0; j < RJ; ++j) acc[j] = 0;
+  for (i64 k = k0 + threadIdx.x; k < k1; k += 256) {
+    const double zk = z[k];
+#pragma unroll
+    for (int j = 0; j < RJ; ++j)
+      if (j0 + j < nd) acc[j] += D[(i64)(j0 + j) * N + k] * zk;
+  }
+  __shared__ double red[RJ][4];
+#pragma unroll
+  for (int j = 0; j < RJ; ++j) {
+    double v = acc[j];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[j][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < RJ && j0 + (int)threadIdx.x < nd) {
+    const int j = threadIdx.x;
+    partial[(i64)(j0 + j) * RCHUNK + c] = red[j][0] + red[j][1] + red[j][2] + red[j][3];
+  }
+}
+
+// coef[j] = (sum_c partial[j][c]) / eta[j]
+__global__ void k_reorth_coef(const double* __restrict__ partial, const double* __restrict__ eta, int nd,
+                              double* __restrict__ coef) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nd) return;
+  double s = 0;
+  for (int c = 0; c < RCHUNK; ++c) s += partial[(i64)j * RCHUNK + c];
+  coef[j] = s / eta[j];
+}
+
+// d[k] = s[k] - sum_{j<nd} coef[j] D[j][k]
+__global__ void k_reorth_apply(const double* __restrict__ D, i64 N, int nd, const double* __restrict__ coef,
+                               const double* __restrict__ s, double* __restrict__ d) {
+  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  double v = s[k];
+  for (int j = 0; j < nd; ++j) v -= coef[j] * D[(i64)j * N + k];
+  d[k] = v;
+}
+
+// scal layout: [0] r.r  [1] z.d (eta_i)  [2] s.r  [3] b.b  [4] tol^2
+// flag layout: [0] state (0 running, 1 converged, 2 breakdown)  [1] iterations
+__global__ void k_check(double* scal, int* flag, int max_iter) {
+  if (flag[0] != 0) return;
+  if (scal[0] <= scal[4] * scal[3]) flag[0] = 1;
+  else if (flag[1] >= max_iter) flag[0] = 3;
+}
+
+// guarded IterGP update of iteration slot `slot`
+__global__ void k_update(i64 N, const double* __restrict__ d, double* __restrict__ v, double* __restrict__ Dcol,
+                         double* __restrict__ eta_slot, const double* __restrict__ scal, int* __restrict__ flag) {
+  const int state = flag[0];
+  if (state != 0) return;
+  const double et = scal[1], sr = scal[2];
+  if (!(et > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 2;   // breakdown: directions no longer S-definite
+    return;
+  }
+  const double a = sr / et;
+  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) {
+    const double dk = d[k];
+    v[k] += a * dk;
+    Dcol[k] = dk;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *eta_slot = et;
+}
+
+__global__ void k_count(int* flag, const double* scal) {
+  if (flag[0] == 0 && scal[1] > 0.0) flag[1] += 1;
+}
+
+// r = b - y (guarded)
+__global__ void k_resid(i64 N, const double* __restrict__ b, const double* __restrict__ y, double* __restrict__ r,
+                        const int* __restrict__ flag) {
+  if (flag[0] != 0) return;
+  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) r[k] = b[k] - y[k];
+}
+
+__global__ void k_sub_sq_acc(i64 M, int nr, const double* __restrict__ P, const double* __restrict__ Q,
+                             const double* __restrict__ eta, double* __restrict__ acc) {
+  const i64 x = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= M) return;
+  double s = 0;
+  for (int j = 0; j < nr; ++j) {
+    const double w = P[(i64)j * M + x] - (Q ? Q[(i64)j * M + x] : 0.0);
+    s += w * w / eta[j];
+  }
+  acc[x] += s;
+}
+
+__global__ void k_colsq(i64 rows, i64 cols, const double* __restrict__ T, double* __restrict__ acc) {
+  const i64 c = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0;
+  for (i64 r = 0; r < rows; ++r) {
+    const double t = T[r * cols + c];
+    s += t * t;
+  }
+  acc[c] += s;
+}
+
+__global__ void k_var_final(i64 M, double sf2, const double* __restrict__ red, double* __restrict__ var) {
+  const i64 x = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < M) var[x] = sf2 - red[x];
+}
+
+// dense point-grid cross-covariance block: out[b][x - x0] = sf2 prod_i P_i[b_i][x_i]
+struct PGMeta {
+  int d, ngroup;
+  int gn[GPFVM_MAX_GROUPS][3];
+  i64 goff[GPFVM_MAX_GROUPS + 1];
+  int gdim[3];
+  const double* P[GPFVM_MAX_GROUPS][3];    // n_{g,i} x G_i
+};
+
+__global__ void k_point_grid(const PGMeta* __restrict__ meta, int nb, i64 x0, i64 nx, double sf2,
+                             double* __restrict__ out) {
+  const PGMeta& G = *meta;
+  const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (i64)nb * nx) return;
+  const i64 b = idx / nx, xl = idx % nx, x = x0 + xl;
+  int g = 0;
+  while (g + 1 < G.ngroup && G.goff[g + 1] <= b) ++g;
+  int ib[3] = {0, 0, 0}, ix[3] = {0, 0, 0};
+  i64 r = b - G.goff[g];
+  for (int i = G.d - 1; i >= 0; --i) { ib[i] = (int)(r % G.gn[g][i]); r /= G.gn[g][i]; }
+  r = x;
+  for (int i = G.d - 1; i >= 0; --i) { ix[i] = (int)(r % G.gdim[i]); r /= G.gdim[i]; }
+  double p = sf2;
+  for (int i = 0; i < G.d; ++i) p *= G.P[g][i][(i64)ib[i] * G.gdim[i] + ix[i]];
+  out[b * nx + xl] = p;
+}
+
+GemmDesc desc1(void* C, i64 c_rs, const void* A, i64 a_rs, i64 a_cs, const void* B, i64 b_rs, i64 b_cs, int M,
+               int N, int K, double alpha, double beta, int tri) {
+  GemmDesc D;
+  std::memset(&D, 0, sizeof(D));
+  D.C = C; D.c_rs = c_rs; D.c_cs = 1; D.M = M; D.N = N; D.batch = 1; D.nseg = 1; D.beta = beta;
+  Seg& S = D.seg[0];
+  S.A = A; S.a_rs = a_rs; S.a_cs = a_cs; S.B = B; S.b_rs = b_rs; S.b_cs = b_cs; S.K = K; S.alpha = alpha;
+  S.tri = tri;
+  return D;
+}
+
+unsigned nblk(i64 n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// volume-system operator S for nrhs right-hand sides (float64 or float32)
+// ---------------------------------------------------------------------------
+int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
+  auto& tab = (elt == F64) ? h->sops : h->sops32;
+  auto it = tab.find(nrhs);
+  if (it != tab.end()) { *out = it->second.get(); return GPFVM_OK; }
+  if (elt == F32 && h->op_pp32.terms.empty()) {
+    int rc = build_ops32(h);
+    if (rc) return rc;
+  }
+  auto so = std::make_unique<gpfvm_sop>();
+  so->nrhs = nrhs;
+  so->elt = elt;
+  const size_t es = (elt == F64) ? 8 : 4;
+  const i64 N = h->N, nb = std::max(h->nb, 1);
+  so->X = h->arena.alloc((size_t)N * nrhs * es);
+  so->Y = h->arena.alloc((size_t)N * nrhs * es);
+  so->U = h->arena.alloc((size_t)nb * nrhs * es);
+  so->T = h->arena.alloc((size_t)nb * nrhs * es);
+  so->W = h->arena.alloc((size_t)nb * nrhs * es);
+  if (!so->X || !so->Y || !so->U || !so->T || !so->W) { h->err = "out of device memory (S operator)"; return GPFVM_E_NOMEM; }
+  const void* cc = (elt == F64) ? (const void*)h->cellc : (const void*)h->cellc_f;
+  const KronOp& opp = (elt == F64) ? h->op_pp : h->op_pp32;
+  std::vector<KronOp> pp{opp};
+  int rc = compile_kron_list(pp, elt, nrhs, so->X, N, so->Y, N, cc, h->cellc, 0.0, so->X, h->sig_pde, 1, h->arena,
+                             h->stream, so->pp, h->err);
+  if (rc) return rc;
+  so->flops_pp = so->pp.flops;
+  if (h->nb > 0) {
+    rc = compile_kron_list((elt == F64) ? h->op_bp : h->op_bp32, elt, nrhs, so->X, N, so->U, h->nb, cc, h->cellc, 0.0,
+                           nullptr, 0, 0, h->arena, h->stream, so->bp, h->err);
+    if (rc) return rc;
+    std::vector<KronOp> pb = (elt == F64) ? h->op_pb : h->op_pb32;
+    for (auto& o : pb)
+      for (auto& t : o.terms) t.alpha = -t.alpha;
+    rc = compile_kron_list(pb, elt, nrhs, so->W, h->nb, so->Y, N, cc, h->cellc, 1.0, nullptr, 0, 1, h->arena,
+                           h->stream, so->pb, h->err);
+    if (rc) return rc;
+    const void* Li = (elt == F64) ? (const void*)h->Linv : (const void*)h->Linv_f;
+    // T[r][i] = sum_j U[r][j] Linv[i][j] ; W[r][i] = sum_j T[r][j] Linv[j][i]
+    so->linv.descs.push_back(desc1(so->T, h->nb, so->U, h->nb, 1, Li, 1, h->nb, nrhs, h->nb, h->nb, 1.0, 0.0, 3));
+    so->linvt.descs.push_back(desc1(so->W, h->nb, so->T, h->nb, 1, Li, h->nb, 1, nrhs, h->nb, h->nb, 1.0, 0.0, 4));
+    std::vector<Stage> st{so->linv, so->linvt};
+    if (upload_stages(st, h->arena, h->stream, elt) != hipSuccess) { h->err = "descriptor check/upload failed"; return GPFVM_E_HIP; }
+    so->linv = st[0];
+    so->linvt = st[1];
+  }
+  *out = so.get();
+  tab[nrhs] = std::move(so);
+  return GPFVM_OK;
+}
+
+static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
+  hipError_t e;
+  if (h->nb > 0) {
+    if ((e = run_plan(so->bp, s)) != hipSuccess) return e;
+    if ((e = launch_gemm_stage(so->elt, so->linv, s)) != hipSuccess) return e;
+    if ((e = launch_gemm_stage(so->elt, so->linvt, s)) != hipSuccess) return e;
+  }
+  if ((e = run_plan(so->pp, s)) != hipSuccess) return e;
+  if (h->nb > 0)
+    if ((e = run_plan(so->pb, s)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+// y = S x for one float64 vector (through the float64 or float32 operator)
+static int apply_S(gpfvm_handle* h, Elt elt, const double* x, double* y, hipStream_t s) {
+  gpfvm_sop* so = nullptr;
+  int rc = get_sop(h, 1, elt, &so);
+  if (rc) return rc;
+  const i64 N = h->N;
+  if (elt == F64) {
+    HIPCHK(h, hipMemcpyAsync(so->X, x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, apply_sop(h, so, s));
+    HIPCHK(h, hipMemcpyAsync(y, so->Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    HIPCHK(h, launch_copy_f64_to_f32(x, (float*)so->X, N, s));
+    HIPCHK(h, apply_sop(h, so, s));
+    HIPCHK(h, launch_copy_f32_to_f64((const float*)so->Y, y, N, s));
+  }
+  return GPFVM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solver state
+// ---------------------------------------------------------------------------
+static int ensure_state(gpfvm_handle* h, hipStream_t s) {
+  if (h->v) return GPFVM_OK;
+  const i64 N = h->N;
+  h->bS = (double*)h->arena.alloc(N * sizeof(double));
+  h->ab0 = (double*)h->arena.alloc(std::max(h->nb, 1) * sizeof(double));
+  h->v = (double*)h->arena.alloc(N * sizeof(double));
+  h->Dd = (double*)h->arena.alloc((size_t)N * h->max_iter * sizeof(double));
+  h->eta = (double*)h->arena.alloc(h->max_iter * sizeof(double));
+  h->vec = (double*)h->arena.alloc((size_t)8 * N * sizeof(double));
+  h->red = (double*)h->arena.alloc((size_t)RCHUNK * h->max_iter * sizeof(double));
+  h->aux = (double*)h->arena.alloc((size_t)(1024 + h->max_iter) * sizeof(double));
+  h->scal = (double*)h->arena.alloc(64 * sizeof(double));
+  h->flag = (int*)h->arena.alloc(16 * sizeof(int));
+  if (!h->bS || !h->ab0 || !h->v || !h->Dd || !h->eta || !h->vec || !h->red || !h->aux || !h->scal || !h->flag) {
+    h->err = "out of device memory (solver state; lower max_iter)";
+    return GPFVM_E_NOMEM;
+  }
+  // b = y_p - G_pb G_bb^{-1} y_b ; ab0 = G_bb^{-1} y_b
+  HIPCHK(h, hipMemcpyAsync(h->bS, h->yobs + h->nb, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (h->nb > 0) {
+    gpfvm_sop* so = nullptr;
+    int rc = get_sop(h, 1, F64, &so);
+    if (rc) return rc;
+    HIPCHK(h, hipMemcpyAsync(so->U, h->yobs, h->nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, launch_gemm_stage(F64, so->linv, s));
+    HIPCHK(h, launch_gemm_stage(F64, so->linvt, s));
+    HIPCHK(h, hipMemcpyAsync(h->ab0, so->W, h->nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // the volume plan of S accumulates -G_pb W into Y (beta = 1): start from zero
+    HIPCHK(h, launch_fill((double*)so->Y, 0.0, N, s));
+    HIPCHK(h, run_plan(so->pb, s));
+    HIPCHK(h, launch_axpby(N, 1.0, (const double*)so->Y, 1.0, h->bS, s));
+  }
+  return GPFVM_OK;
+}
+
+// One IterGP run on the volume system with right-hand side `b`, float64
+// recurrences, operator precision `elt`.  Directions are appended from slot
+// `start`; v accumulates.  Returns the number of stored directions.
+static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int start, int max_new, double tol,
+                      int check_every, hipStream_t s, int* n_out, int* state_out) {
+  const i64 N = h->N;
+  double* r = h->vec;
+  double* z = h->vec + N;
+  double* d = h->vec + 2 * N;
+  double* y = h->vec + 3 * N;
+  double* sv = h->vec + 4 * N;
+  double* partial = h->red;           // RCHUNK x max_iter
+  double* dotp = h->aux;              // 512 dot partials
+  double* coef = h->aux + 1024;       // max_iter reorthogonalisation coefficients
+  int rc;
+  // r = b - S v
+  rc = apply_S(h, elt, v, y, s);
+  if (rc) return rc;
+  HIPCHK(h, hipMemsetAsync(h->flag, 0, 16 * sizeof(int), s));
+  HIPCHK(h, launch_dot(N, b, b, dotp, h->scal + 3, s));
+  {
+    const double t2 = tol * tol;
+    HIPCHK(h, hipMemcpyAsync(h->scal + 4, &t2, sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  hipLaunchKernelGGL(k_resid, dim3(nblk(N)), dim3(256), 0, s, N, b, (const double*)y, r, (const int*)h->flag);
+  int i = start;
+  const int end = std::min(h->max_iter, start + max_new);
+  int hflag[2] = {0, 0};
+  while (i < end) {
+    const int batch_end = std::min(end, i + std::max(1, check_every));
+    for (; i < batch_end; ++i) {
+      HIPCHK(h, launch_dot(N, r, r, dotp, h->scal + 0, s));
+      hipLaunchKernelGGL(k_check, dim3(1), dim3(1), 0, s, h->scal, h->flag, end - start);
+      // s = r ; z = S s
+      HIPCHK(h, hipMemcpyAsync(sv, r, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      rc = apply_S(h, elt, sv, z, s);
+      if (rc) return rc;
+      // d = s - D (eta^{-1} o D^T z)
+      if (i > 0) {
+        hipLaunchKernelGGL(k_reorth_dots, dim3(RCHUNK, (i + RJ - 1) / RJ), dim3(256), 0, s, (const double*)h->Dd, N, i,
+                           (const double*)z, partial);
+        hipLaunchKernelGGL(k_reorth_coef, dim3(nblk(i)), dim3(256), 0, s, (const double*)partial,
+                           (const double*)h->eta, i, coef);
+        hipLaunchKernelGGL(k_reorth_apply, dim3(nblk(N)), dim3(256), 0, s, (const double*)h->Dd, N, i,
+                           (const double*)coef, (const double*)sv, d);
+      } else {
+        HIPCHK(h, hipMemcpyAsync(d, sv, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      }
+      HIPCHK(h, launch_dot(N, z, d, dotp, h->scal + 1, s));
+      HIPCHK(h, launch_dot(N, sv, r, dotp, h->scal + 2, s));
+      hipLaunchKernelGGL(k_update, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, v, h->Dd + (i64)i * N,
+                         h->eta + i, (const double*)h->scal, h->flag);
+      hipLaunchKernelGGL(k_count, dim3(1), dim3(1), 0, s, h->flag, (const double*)h->scal);
+      // r = b - S v
+      rc = apply_S(h, elt, v, y, s);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_resid, dim3(nblk(N)), dim3(256), 0, s, N, b, (const double*)y, r, (const int*)h->flag);
+    }
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(hflag, h->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (hflag[0] != 0) break;
+  }
+  *n_out = start + hflag[1];
+  *state_out = hflag[0];
+  return GPFVM_OK;
+}
+
+static int rel_res(gpfvm_handle* h, const double* v, double* out, hipStream_t s) {
+  const i64 N = h->N;
+  double* y = h->vec + 3 * N;
+  double* dotp = h->aux;
+  int rc = apply_S(h, F64, v, y, s);
+  if (rc) return rc;
+  HIPCHK(h, launch_axpby(N, 1.0, h->bS, -1.0, y, s));      // y = b - S v
+  HIPCHK(h, launch_dot(N, y, y, dotp, h->scal + 8, s));
+  HIPCHK(h, launch_dot(N, h->bS, h->bS, dotp, h->scal + 9, s));
+  double hv[2];
+  HIPCHK(h, hipMemcpyAsync(hv, h->scal + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  *out = hv[1] > 0 ? std::sqrt(hv[0] / hv[1]) : 0.0;
+  return GPFVM_OK;
+}
+
+extern "C" int gpfvm_weights(gpfvm_handle* h, double* alpha, void* stream);
+
+static int full_residual(gpfvm_handle* h, double* out, hipStream_t s) {
+  // ||y - G alpha|| / ||y|| on the whole system
+  const i64 n = h->n;
+  double *a = nullptr, *g = nullptr;
+  if (hipMalloc(&a, n * sizeof(double)) != hipSuccess) { h->err = "out of device memory"; return GPFVM_E_NOMEM; }
+  if (hipMalloc(&g, n * sizeof(double)) != hipSuccess) { (void)hipFree(a); h->err = "out of device memory"; return GPFVM_E_NOMEM; }
+  int rc = gpfvm_weights(h, a, s);
+  if (!rc) rc = gpfvm_matvec(h, 1, a, g, GPFVM_PREC_FP64, s);
+  if (!rc) {
+    double* dotp = h->aux;
+    hipError_t e = launch_axpby(n, 1.0, h->yobs, -1.0, g, s);
+    if (e == hipSuccess) e = launch_dot(n, g, g, dotp, h->scal + 10, s);
+    if (e == hipSuccess) e = launch_dot(n, h->yobs, h->yobs, dotp, h->scal + 11, s);
+    double hv[2] = {0, 1};
+    if (e == hipSuccess) e = hipMemcpyAsync(hv, h->scal + 10, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { h->err = hipGetErrorString(e); rc = GPFVM_E_HIP; }
+    *out = hv[1] > 0 ? std::sqrt(hv[0] / hv[1]) : 0.0;
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(a);
+  (void)hipFree(g);
+  return rc;
+}
+
+extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_solve_info* info, void* stream) {
+  if (!h) return GPFVM_E_INVALID;
+  gpfvm_solve_opts def;
+  gpfvm_default_solve_opts(&def);
+  if (!o) o = &def;
+  if (o->prec != GPFVM_PREC_FP64 && o->prec != GPFVM_PREC_MIXED) { h->err = "solve: bad prec"; return GPFVM_E_INVALID; }
+  if (o->max_iter < 0 || !(o->tol >= 0) || o->check_every < 1 || o->max_outer < 1 || !(o->inner_tol > 0)) {
+    h->err = "solve: bad options";
+    return GPFVM_E_INVALID;
+  }
+  if (o->resume && !h->solved) { h->err = "solve: nothing to resume"; return GPFVM_E_STATE; }
+  hipStream_t s = (hipStream_t)stream;
+  h->stream = s;
+  int rc = ensure_state(h, s);
+  if (rc) return rc;
+  const i64 N = h->N;
+  if (!o->resume) {
+    HIPCHK(h, launch_fill(h->v, 0.0, N, s));
+    h->iters = 0;
+  }
+  int state = 0, outer = 0;
+  if (o->prec == GPFVM_PREC_FP64) {
+    int nd = h->iters;
+    rc = itergp_run(h, F64, h->bS, h->v, h->iters, o->max_iter, o->tol, o->check_every, s, &nd, &state);
+    if (rc) return rc;
+    h->iters = nd;
+  } else {
+    // mixed-precision iterative refinement: float64 residual of the volume
+    // system, float32-operator IterGP for the correction; all directions stay
+    // in one conjugate set so the combined posterior remains defined.
+    double* x = h->v;
+    double* rr = h->vec + 6 * N;      // outer residual
+    double* dx = h->vec + 7 * N;      // correction
+    double res = 0;
+    for (outer = 0; outer < o->max_outer; ++outer) {
+      rc = apply_S(h, F64, x, rr, s);
+      if (rc) return rc;
+      HIPCHK(h, launch_axpby(N, 1.0, h->bS, -1.0, rr, s));
+      rc = rel_res(h, x, &res, s);
+      if (rc) return rc;
+      if (res <= o->tol || h->iters >= std::min(h->max_iter, o->max_iter)) break;
+      HIPCHK(h, launch_fill(dx, 0.0, N, s));
+      int nd = h->iters;
+      rc = itergp_run(h, F32, rr, dx, h->iters, std::min(h->max_iter, o->max_iter) - h->iters, o->inner_tol,
+                      o->check_every, s, &nd, &state);
+      if (rc) return rc;
+      h->iters = nd;
+      HIPCHK(h, launch_axpby(N, 1.0, dx, 1.0, x, s));
+      if (state == 2) break;
+    }
+    state = (res <= o->tol) ? 1 : (state == 2 ? 2 : 3);
+  }
+  h->solved = true;
+  double rs = 0, rf = 0;
+  rc = rel_res(h, h->v, &rs, s);
+  if (rc) return rc;
+  rc = full_residual(h, &rf, s);
+  if (rc) return rc;
+  if (info) {
+    info->iters = h->iters;
+    info->outer = outer;
+    info->rel_res = rs;
+    info->rel_res_full = rf;
+    info->status = GPFVM_OK;
+  }
+  int status = GPFVM_OK;
+  if (state == 2) status = GPFVM_E_NOTPD;
+  else if (o->tol > 0 && rs > o->tol) status = GPFVM_E_NOCONV;
+  if (info) info->status = status;
+  if (status == GPFVM_E_NOTPD) h->err = "IterGP breakdown: eta <= 0 (state kept up to the last good direction)";
+  if (status == GPFVM_E_NOCONV) h->err = "iteration budget exhausted above the tolerance";
+  return status;
+}
+
+extern "C" int gpfvm_weights(gpfvm_handle* h, double* alpha, void* stream) {
+  if (!h || !alpha) return GPFVM_E_INVALID;
+  if (!h->solved) { h->err = "weights: no solve yet"; return GPFVM_E_STATE; }
+  hipStream_t s = (hipStream_t)stream;
+  const i64 N = h->N;
+  HIPCHK(h, hipMemcpyAsync(alpha + h->nb, h->v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (h->nb > 0) {
+    // alpha_b = G_bb^{-1} (y_b - G_bp v)
+    gpfvm_sop* so = nullptr;
+    int rc = get_sop(h, 1, F64, &so);
+    if (rc) return rc;
+    HIPCHK(h, hipMemcpyAsync(so->X, h->v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, run_plan(so->bp, s));
+    HIPCHK(h, launch_axpby(h->nb, 1.0, h->yobs, -1.0, (double*)so->U, s));
+    HIPCHK(h, launch_gemm_stage(F64, so->linv, s));
+    HIPCHK(h, launch_gemm_stage(F64, so->linvt, s));
+    HIPCHK(h, hipMemcpyAsync(alpha, so->W, h->nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  return GPFVM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// posterior on a tensor grid
+// ---------------------------------------------------------------------------
+extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const double* const* axis, double* mean,
+                               double* var, void* stream) {
+  if (!h) return GPFVM_E_INVALID;
+  if (dim != h->d || !n || !axis || !mean) { h->err = "posterior: bad grid arguments"; return GPFVM_E_INVALID; }
+  i64 M = 1;
+  for (int i = 0; i < dim; ++i) {
+    if (n[i] < 1 || !axis[i]) { h->err = "posterior: bad grid axis"; return GPFVM_E_INVALID; }
+    for (int j = 0; j < n[i]; ++j)
+      if (!std::isfinite(axis[i][j])) { h->err = "posterior: non-finite grid"; return GPFVM_E_INVALID; }
+    M *= n[i];
+  }
+  if (!h->solved) { h->err = "posterior: no solve yet"; return GPFVM_E_STATE; }
+  hipStream_t s = (hipStream_t)stream;
+  h->stream = s;
+  const int d = h->d;
+  const i64 N = h->N;
+  Arena tmp;    // per-call allocations
+  auto fail = [&](int code, const std::string& m) { h->err = m; (void)hipStreamSynchronize(s); tmp.release(); return code; };
+  // grid axes on the device
+  double* gax[3] = {nullptr, nullptr, nullptr};
+  for (int i = 0; i < d; ++i) {
+    gax[i] = (double*)tmp.alloc(n[i] * sizeof(double));
+    if (!gax[i]) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+    if (hipMemcpyAsync(gax[i], axis[i], n[i] * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(GPFVM_E_HIP, "posterior: copy failed");
+  }
+  // grid-cell factors per term and dim, grid-point factors per group and dim
+  std::vector<std::array<double*, 3>> Qg(h->pterms.size());
+  for (size_t t = 0; t < h->pterms.size(); ++t)
+    for (int i = 0; i < d; ++i) {
+      Qg[t][i] = (double*)tmp.alloc((size_t)n[i] * h->nc[i] * sizeof(double));
+      if (!Qg[t][i]) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+      if (launch_factor(1, 0, h->pterms[t].alpha[i], n[i], gax[i], h->nc[i], h->edges[i], h->ell[i], 1.0, Qg[t][i],
+                        h->nc[i], s) != hipSuccess)
+        return fail(GPFVM_E_HIP, "posterior: factor launch failed");
+    }
+  PGMeta pg;
+  std::memset(&pg, 0, sizeof(pg));
+  pg.d = d;
+  pg.ngroup = (int)h->groups.size();
+  for (int i = 0; i < d; ++i) pg.gdim[i] = n[i];
+  std::vector<std::array<double*, 3>> gaxis(h->groups.size());
+  for (size_t g = 0; g < h->groups.size(); ++g) {
+    pg.goff[g] = h->groups[g].offset;
+    for (int i = 0; i < d; ++i) {
+      const Group& G = h->groups[g];
+      pg.gn[g][i] = G.n[i];
+      gaxis[g][i] = (double*)tmp.alloc(G.n[i] * sizeof(double));
+      double* P = (double*)tmp.alloc((size_t)G.n[i] * n[i] * sizeof(double));
+      if (!gaxis[g][i] || !P) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+      if (hipMemcpyAsync(gaxis[g][i], G.axis[i].data(), G.n[i] * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(GPFVM_E_HIP, "posterior: copy failed");
+      // P[b][x] = d^beta_1 k(x_b, x)
+      if (launch_factor(2, G.deriv[i], 0, G.n[i], gaxis[g][i], n[i], gax[i], h->ell[i], 1.0, P, n[i], s) != hipSuccess)
+        return fail(GPFVM_E_HIP, "posterior: factor launch failed");
+      pg.P[g][i] = P;
+    }
+  }
+  pg.goff[h->groups.size()] = h->nb;
+  // operators: K_*p (cells -> grid), K_*b (points -> grid)
+  KronOp gp;
+  gp.d = d;
+  for (int i = 0; i < d; ++i) { gp.in_shape[i] = h->nc[i]; gp.out_shape[i] = n[i]; }
+  gp.in_len = N;
+  for (size_t t = 0; t < h->pterms.size(); ++t) {
+    KronTerm k{};
+    for (int i = 0; i < d; ++i) { k.M[i] = Qg[t][i]; k.ld[i] = h->nc[i]; }
+    k.alpha = h->sf2 * h->pterms[t].coef;
+    k.rscale = h->pterms[t].cellwise;
+    gp.terms.push_back(k);
+  }
+  std::vector<KronOp> gb;
+  for (size_t g = 0; g < h->groups.size(); ++g) {
+    KronOp o;
+    o.d = d;
+    for (int i = 0; i < d; ++i) { o.in_shape[i] = h->groups[g].n[i]; o.out_shape[i] = n[i]; }
+    o.in_len = h->nb;
+    KronTerm k{};
+    for (int i = 0; i < d; ++i) { k.M[i] = pg.P[g][i]; k.ld[i] = n[i]; k.trans[i] = 1; }
+    k.alpha = h->sf2;
+    k.in_off = h->groups[g].offset;
+    o.terms.push_back(k);
+    gb.push_back(o);
+  }
+  // ---- mean = K_*b alpha_b + K_*p alpha_p ----
+  struct UserRange {
+    const void* p;
+    UserRange(const void* q, size_t n) : p(q) { register_range(q, n); }
+    ~UserRange() { unregister_range(p); }
+  } user_mean(mean, (size_t)M * sizeof(double));
+  double* alpha = (double*)tmp.alloc((size_t)h->n * sizeof(double));
+  if (!alpha) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+  int rc = gpfvm_weights(h, alpha, s);
+  if (rc) { tmp.release(); return rc; }
+  {
+    Plan pm, pmb;
+    std::vector<KronOp> ops{gp};
+    rc = compile_kron_list(ops, F64, 1, alpha + h->nb, N, mean, M, h->cellc, h->cellc, 0.0, nullptr, 0, 1, tmp, s, pm,
+                           h->err);
+    if (rc) { tmp.release(); return rc; }
+    if (h->nb > 0) {
+      rc = compile_kron_list(gb, F64, 1, alpha, h->nb, mean, M, nullptr, nullptr, 1.0, nullptr, 0, 1, tmp, s, pmb,
+                             h->err);
+      if (rc) { tmp.release(); return rc; }
+    }
+    if (run_plan(pm, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: mean plan failed");
+    if (h->nb > 0 && run_plan(pmb, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: mean plan failed");
+  }
+  if (!var) {
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: sync failed");
+    tmp.release();
+    return GPFVM_OK;
+  }
+  // ---- variance = sf2 - ||L^{-1} k_b(x)||^2 - sum_j (w_j(x))^2 / eta_j ----
+  double* red = (double*)tmp.alloc((size_t)M * sizeof(double));
+  if (!red) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+  if (launch_fill(red, 0.0, M, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: fill failed");
+  if (h->nb > 0) {
+    PGMeta* dpg = (PGMeta*)tmp.alloc(sizeof(PGMeta));
+    if (!dpg) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+    if (hipMemcpyAsync(dpg, &pg, sizeof(pg), hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(GPFVM_E_HIP, "posterior: copy failed");
+    // chunk grid points so that n_b x chunk stays below ~256 MB per buffer
+    const i64 chunk = std::max<i64>(32, std::min<i64>(M, (i64)(32LL << 20) / h->nb));
+    double* KB = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
+    double* TT = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
+    if (!KB || !TT) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+    for (i64 x0 = 0; x0 < M; x0 += chunk) {
+      const i64 nx = std::min(chunk, M - x0);
+      hipLaunchKernelGGL(k_point_grid, dim3(nblk((i64)h->nb * nx)), dim3(256), 0, s, (const PGMeta*)dpg, h->nb, x0, nx,
+                         h->sf2, KB);
+      std::vector<Stage> st(1);
+      st[0].descs.push_back(desc1(TT, nx, h->Linv, h->nb, 1, KB, nx, 1, h->nb, (int)nx, h->nb, 1.0, 0.0, 1));
+      if (upload_stages(st, tmp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: upload failed");
+      if (launch_gemm_stage(F64, st[0], s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: gemm failed");
+      hipLaunchKernelGGL(k_colsq, dim3(nblk(nx)), dim3(256), 0, s, (i64)h->nb, nx, (const double*)TT, red + x0);
+    }
+  }
+  const int K = h->iters;
+  if (K > 0) {
+    const int B = std::min(K, 64);
+    double* P1 = (double*)tmp.alloc((size_t)M * B * sizeof(double));
+    double* P2 = h->nb > 0 ? (double*)tmp.alloc((size_t)M * B * sizeof(double)) : nullptr;
+    double* Ub = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
+    double* Tb = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
+    double* Wb = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
+    double* Dbuf = (double*)tmp.alloc((size_t)N * B * sizeof(double));
+    if (!P1 || !Dbuf || (h->nb > 0 && (!P2 || !Ub || !Tb || !Wb))) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+    Plan pgp, pbp, pgb;
+    std::vector<KronOp> ops{gp};
+    rc = compile_kron_list(ops, F64, B, Dbuf, N, P1, M, h->cellc, h->cellc, 0.0, nullptr, 0, 1, tmp, s, pgp, h->err);
+    if (rc) { tmp.release(); return rc; }
+    std::vector<Stage> st(2);
+    if (h->nb > 0) {
+      rc = compile_kron_list(h->op_bp, F64, B, Dbuf, N, Ub, h->nb, h->cellc, h->cellc, 0.0, nullptr, 0, 0, tmp, s, pbp,
+                             h->err);
+      if (rc) { tmp.release(); return rc; }
+      rc = compile_kron_list(gb, F64, B, Wb, h->nb, P2, M, nullptr, nullptr, 0.0, nullptr, 0, 1, tmp, s, pgb, h->err);
+      if (rc) { tmp.release(); return rc; }
+      st[0].descs.push_back(desc1(Tb, h->nb, Ub, h->nb, 1, h->Linv, 1, h->nb, B, h->nb, h->nb, 1.0, 0.0, 3));
+      st[1].descs.push_back(desc1(Wb, h->nb, Tb, h->nb, 1, h->Linv, h->nb, 1, B, h->nb, h->nb, 1.0, 0.0, 4));
+      if (upload_stages(st, tmp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: upload failed");
+    }
+    for (int j0 = 0; j0 < K; j0 += B) {
+      const int nr = std::min(B, K - j0);
+      if (hipMemcpyAsync(Dbuf, h->Dd + (i64)j0 * N, (size_t)nr * N * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(GPFVM_E_HIP, "posterior: copy failed");
+      if (nr < B && launch_fill(Dbuf + (i64)nr * N, 0.0, (i64)(B - nr) * N, s) != hipSuccess)
+        return fail(GPFVM_E_HIP, "posterior: fill failed");
+      if (run_plan(pgp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
+      if (h->nb > 0) {
+        if (run_plan(pbp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
+        if (launch_gemm_stage(F64, st[0], s) != hipSuccess || launch_gemm_stage(F64, st[1], s) != hipSuccess)
+          return fail(GPFVM_E_HIP, "posterior: gemm failed");
+        if (run_plan(pgb, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
+      }
+      hipLaunchKernelGGL(k_sub_sq_acc, dim3(nblk(M)), dim3(256), 0, s, M, nr, (const double*)P1,
+                         (const double*)(h->nb > 0 ? P2 : nullptr), (const double*)(h->eta + j0), red);
+    }
+  }
+  hipLaunchKernelGGL(k_var_final, dim3(nblk(M)), dim3(256), 0, s, M, h->sf2, (const double*)red, var);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: kernel failed");
+  tmp.release();
+  return GPFVM_OK;
+}
+

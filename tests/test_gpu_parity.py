@@ -1,0 +1,200 @@
+"""GPU parity: the HIP path (through the C-ABI) against the float64 CPU oracle.
+
+Tolerances (float64 path): factors and Gram entries are closed forms whose
+only error is rounding, amplified by the second-difference cancellation of
+the antiderivative form by about (lengthscale / cell width)^2 (< 300 here), so
+1e-11 of the matrix scale; matvecs sum <= 10^3 terms of those, 1e-11 relative.
+Posterior mean and variance: 1e-6 relative (the float64 target)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gpfvm_oracle as O
+from oracle.gpfvm_oracle import SchurSystem, two_stage_posterior
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_05020_amd as G
+    G.lib()
+    return G
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# 1-D factors
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pq", [(0, 0), (1, 0), (0, 1), (1, 1), (2, 0), (0, 2), (2, 2), (4, 0), (1, 3), (0, 4)])
+@pytest.mark.parametrize("ell", [0.1, 0.3])
+def test_factor_kernel_matches_quadrature(G, pq, ell):
+    p, q = pq
+    rng = np.random.default_rng(7)
+    e1 = np.sort(np.concatenate([[0.0, 1.0], rng.uniform(0, 1, 11)]))    # 12 ragged cells
+    e2 = np.linspace(0.0, 1.0, 38)                                        # 37 uniform cells
+    x = rng.uniform(-0.1, 1.1, 9)
+    for kind, a1, a2, ref in [
+        (0, e1, e2, O.cell_cell(p, q, e1, e2, ell)),
+        (1, x, e2, O.point_cell(p, q, x, e2, ell)),
+        (2, x, e1, O.point_point(p, q, x, e1, ell)),
+    ]:
+        out = torch.empty(ref.size, dtype=torch.float64, device="cuda:0")
+        G.factor(kind, p, q, a1, a2, ell, out)
+        got = host(out).reshape(ref.shape)
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-11 * scale, (kind, np.abs(got - ref).max() / scale)
+
+
+# ---------------------------------------------------------------------------
+# dense Gram and matvec
+# ---------------------------------------------------------------------------
+SMALL = {
+    "heat1d_c1": lambda: W.heat1d_c1(),
+    "advdiff_6x7": lambda: W.advdiff_c2(nt=6, nx=7, n_ic=10),
+    "heat2d_3x4x3": lambda: W.heat2d_c3(nt=3, nx=4, ny=3, n_ic=4, n_bt=3, n_bs=2),
+    "wave_3x4x5": lambda: W.wave2d_c4(nt=3, nx=4, ny=5, n_ic=4, n_bt=3, n_bs=2),
+}
+
+RAGGED = {
+    "advdiff_37x45": lambda: W.advdiff_c2(nt=37, nx=45, n_ic=50),
+    "heat2d_9x33x20": lambda: W.heat2d_c3(nt=9, nx=33, ny=20, n_ic=12, n_bt=5, n_bs=7),
+    "wave_5x40x33": lambda: W.wave2d_c4(nt=5, nx=40, ny=33, n_ic=10, n_bt=4, n_bs=6),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_dense_gram_block_matches_oracle(G, name):
+    p = SMALL[name]()
+    ref = O.Oracle(p).gram()
+    h = G.assemble(p, max_iter=8)
+    try:
+        n = ref.shape[0]
+        out = torch.empty(n * n, dtype=torch.float64, device="cuda:0")
+        G.gram_block(h, 0, n, 0, n, out)
+        got = host(out).reshape(n, n)
+        assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+        # an off-origin rectangular block
+        out2 = torch.empty(7 * 5, dtype=torch.float64, device="cuda:0")
+        G.gram_block(h, n - 7, 7, 3, 5, out2)
+        assert np.abs(host(out2).reshape(7, 5) - ref[n - 7:, 3:8]).max() <= 1e-11 * np.abs(ref).max()
+    finally:
+        G.destroy(h)
+
+
+@pytest.mark.parametrize("name", list(SMALL) + list(RAGGED))
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_fp64_matvec_matches_dense_oracle(G, name, nrhs):
+    p = {**SMALL, **RAGGED}[name]()
+    Gd = O.Oracle(p).gram()
+    n = Gd.shape[0]
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((nrhs, n))
+    h = G.assemble(p, max_iter=8)
+    try:
+        y = torch.empty(nrhs * n, dtype=torch.float64, device="cuda:0")
+        G.matvec(h, dev(X.ravel()), y, nrhs=nrhs)
+        Y = host(y).reshape(nrhs, n)
+        for r in range(nrhs):
+            ref = Gd @ X[r]
+            assert relerr(Y[r], ref) <= 1e-11, (r, relerr(Y[r], ref))
+    finally:
+        G.destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# solve + posterior
+# ---------------------------------------------------------------------------
+def _gpu_posterior(G, p, iters, tol, prec=0, grid=None):
+    h = G.assemble(p, max_iter=max(iters, 1))
+    try:
+        info = G.solve(h, prec=prec, tol=tol, max_iter=iters, check_every=4)
+        axes = grid if grid is not None else p.grid
+        M = int(np.prod([len(a) for a in axes]))
+        mean = torch.empty(M, dtype=torch.float64, device="cuda:0")
+        var = torch.empty(M, dtype=torch.float64, device="cuda:0")
+        G.posterior(h, axes, mean, var)
+        return host(mean), host(var), info
+    finally:
+        G.destroy(h)
+
+
+def test_c1_mean_matches_cholesky_oracle(G):
+    p = W.heat1d_c1()
+    o = O.Oracle(p)
+    X = o.grid_points(p.grid)
+    m_ref, v_ref, _ = O.dense_posterior(o, X)
+    m, v, info = _gpu_posterior(G, p, 256, 1e-10)
+    assert info["rel_res"] <= 1e-8, info
+    assert relerr(m, m_ref) <= 1e-6, relerr(m, m_ref)
+    assert np.all(v >= v_ref - 1e-9)            # combined >= mathematical variance
+
+
+@pytest.mark.parametrize("k", [1, 7, 40])
+def test_itergp_fixed_iterations_match_oracle(G, k):
+    """Same IterGP recurrences for k iterations: mean and combined variance."""
+    p = W.heat1d_c1()
+    o = O.Oracle(p)
+    X = o.grid_points(p.grid)
+    S = SchurSystem(o)
+    vp, D, eta, _ = O.itergp(S, k)
+    m_ref, v_ref = two_stage_posterior(S, vp, X, D, eta)
+    m, v, info = _gpu_posterior(G, p, k, 0.0)
+    assert info["iters"] == k
+    assert relerr(m, m_ref) <= 1e-6, relerr(m, m_ref)
+    assert relerr(v, v_ref) <= 1e-6, relerr(v, v_ref)
+
+
+def test_advdiff_small_matches_cholesky(G):
+    p = W.advdiff_c2(nt=24, nx=20, n_ic=40)
+    o = O.Oracle(p)
+    X = o.grid_points(p.grid)
+    m_ref, _, _ = O.dense_posterior(o, X)
+    m, v, info = _gpu_posterior(G, p, 480, 1e-9)
+    assert relerr(m, m_ref) <= 1e-6, (relerr(m, m_ref), info)
+
+
+def test_wave_small_itergp_matches_oracle(G):
+    p = W.wave2d_c4(nt=4, nx=6, ny=5, n_ic=6, n_bt=3, n_bs=3, grid_t=3)
+    o = O.Oracle(p)
+    X = o.grid_points(p.grid)
+    S = SchurSystem(o)
+    vp, D, eta, _ = O.itergp(S, 25)
+    m_ref, v_ref = two_stage_posterior(S, vp, X, D, eta)
+    m, v, info = _gpu_posterior(G, p, 25, 0.0)
+    assert info["iters"] == 25
+    assert relerr(m, m_ref) <= 1e-6, relerr(m, m_ref)
+    assert relerr(v, v_ref) <= 1e-6, relerr(v, v_ref)
+
+
+def test_mixed_matvec_error_is_float32_sized(G):
+    p = RAGGED["heat2d_9x33x20"]()
+    n = p.n
+    rng = np.random.default_rng(3)
+    x = dev(rng.standard_normal(n))
+    h = G.assemble(p, max_iter=8)
+    try:
+        y64 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        y32 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        G.matvec(h, x, y64, prec=G.PREC_FP64)
+        G.matvec(h, x, y32, prec=G.PREC_MIXED)
+        e = relerr(host(y32), host(y64))
+        assert e <= 1e-5, e
+    finally:
+        G.destroy(h)
