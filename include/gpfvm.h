@@ -112,6 +112,9 @@ typedef struct {
   double inner_tol;    /* mixed path: inner relative reduction per refinement step  */
   int max_outer;       /* mixed path: refinement steps                              */
   int check_every;     /* host convergence poll interval in iterations (>= 1)       */
+  int reorth_passes;   /* 1: the published recurrence d = s - C z (one projection);  */
+                       /* 2: the projection repeated on d (stored S D; default)      */
+  int replace_every;   /* passes = 2: residual recomputed as b - S v every k iters   */
 } gpfvm_solve_opts;
 
 typedef struct {
@@ -153,6 +156,15 @@ int gpfvm_assemble(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts,
  * assemble).  Errors: INVALID, HIP. */
 int gpfvm_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec,
                  void* stream);
+
+/* y = S x with S = L_V k L_V' + Sigma_V - G_pb G_bb^{-1} G_bp, the Gram of the
+ * volume observations under the prior already conditioned on the point
+ * observations (Sec. 4.2): the operator the iterative solver applies.
+ * x, y: device, N*nrhs doubles (N = number of volumes), no overlap.  prec
+ * GPFVM_PREC_MIXED evaluates the volume Kronecker block in float32 (float32
+ * factors and accumulation) and the point-block correction in float64.
+ * Errors: INVALID, NOMEM, HIP. */
+int gpfvm_schur_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec, void* stream);
 
 /* Representer weights alpha = G^{-1} y (Sec. 4, representer weights): exact
  * conditioning on the points, then IterGP with CG actions on the volume

@@ -330,7 +330,7 @@ class SchurSystem:
         return np.concatenate([ab, vp])
 
 
-def itergp(S, maxiter: int, tol: float = 0.0, actions: str = "cg", store: bool = True):
+def itergp(S, maxiter: int, tol: float = 0.0, actions: str = "cg", store: bool = True, passes: int = 1):
     """IterGP (Wenger et al. 2022, as used in Sec. 4.1/4.2) on system S with
     right-hand side S.b:
 
@@ -341,6 +341,11 @@ def itergp(S, maxiter: int, tol: float = 0.0, actions: str = "cg", store: bool =
         eta = z^T d
         C  += d d^T / eta
         v  += (s^T r / eta) d
+
+    passes = 2 repeats the projection onto the S-complement of the stored
+    directions once more on d (d <- d - C S d, "full reorthogonalisation"
+    done twice, Limitations section) and then takes eta = d^T S d, which equals
+    z^T d in exact arithmetic.
 
     Returns (v, D, eta, residual norms).  Stops after maxiter iterations or
     once ||r|| <= tol ||b||."""
@@ -365,7 +370,12 @@ def itergp(S, maxiter: int, tol: float = 0.0, actions: str = "cg", store: bool =
             raise ValueError(actions)
         z = S.matvec(s)
         d = s - D[:, :i] @ ((D[:, :i].T @ z) / eta[:i]) if i > 0 else s.copy()
-        et = z @ d
+        if passes == 2:
+            if i > 0:
+                d = d - D[:, :i] @ ((D[:, :i].T @ S.matvec(d)) / eta[:i])
+            et = d @ S.matvec(d)
+        else:
+            et = z @ d
         if not et > 0:
             break
         D[:, i] = d

@@ -45,7 +45,8 @@ class AssembleOpts(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("prec", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int), ("resume", C.c_int),
-                ("tile", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int)]
+                ("tile", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int),
+                ("reorth_passes", C.c_int), ("replace_every", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -66,6 +67,7 @@ SYMBOLS = {
     "gpfvm_validate": ([C.POINTER(IBVPStruct)], C.c_int),
     "gpfvm_assemble": ([C.POINTER(IBVPStruct), C.POINTER(AssembleOpts), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "gpfvm_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "gpfvm_schur_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
     "gpfvm_solve": ([C.c_void_p, C.POINTER(SolveOpts), C.POINTER(SolveInfo), C.c_void_p], C.c_int),
     "gpfvm_posterior": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(_dp), C.c_void_p, C.c_void_p,
                          C.c_void_p], C.c_int),
@@ -193,6 +195,12 @@ def matvec(h, x, y, nrhs: int = 1, prec: int = PREC_FP64, stream=None) -> None:
     _check(lib().gpfvm_matvec(h, nrhs, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), prec, _stream(stream)), h)
 
 
+def schur_matvec(h, x, y, nrhs: int = 1, prec: int = PREC_FP64, stream=None) -> None:
+    """y = S x (volume system after exact conditioning on the points)."""
+    _check(lib().gpfvm_schur_matvec(h, nrhs, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), prec,
+                                    _stream(stream)), h)
+
+
 def default_solve_opts() -> SolveOpts:
     o = SolveOpts()
     lib().gpfvm_default_solve_opts(C.byref(o))
@@ -201,8 +209,9 @@ def default_solve_opts() -> SolveOpts:
 
 def solve(h, prec: int = PREC_FP64, tol: float = 1e-8, max_iter: int = 512, resume: bool = False,
           tile: int = TILE_FP32, inner_tol: float = 1e-2, max_outer: int = 20, check_every: int = 8,
-          stream=None, raise_on_noconv: bool = False) -> dict:
-    o = SolveOpts(prec, tol, max_iter, 1 if resume else 0, tile, inner_tol, max_outer, check_every)
+          reorth_passes: int = 2, replace_every: int = 25, stream=None, raise_on_noconv: bool = False) -> dict:
+    o = SolveOpts(prec, tol, max_iter, 1 if resume else 0, tile, inner_tol, max_outer, check_every,
+                  reorth_passes, replace_every)
     info = SolveInfo()
     rc = lib().gpfvm_solve(h, C.byref(o), C.byref(info), _stream(stream))
     if rc not in (OK, E_NOCONV, E_NOTPD) or (raise_on_noconv and rc != OK):

@@ -46,6 +46,8 @@ extern "C" void gpfvm_default_solve_opts(gpfvm_solve_opts* o) {
   o->inner_tol = 1e-2;
   o->max_outer = 20;
   o->check_every = 8;
+  o->reorth_passes = 2;
+  o->replace_every = 25;
 }
 
 // ---------------------------------------------------------------------------
@@ -501,15 +503,6 @@ extern "C" int gpfvm_assemble(const gpfvm_ibvp* p, const gpfvm_assemble_opts* op
 // ---------------------------------------------------------------------------
 // full-Gram matvec
 // ---------------------------------------------------------------------------
-static GemmDesc desc1(void* C, i64 c_rs, const void* A, i64 a_rs, i64 a_cs, const void* B, i64 b_rs, i64 b_cs,
-                      int M, int N, int K, double alpha, double beta, int tri) {
-  GemmDesc D;
-  std::memset(&D, 0, sizeof(D));
-  D.C = C; D.c_rs = c_rs; D.c_cs = 1; D.M = M; D.N = N; D.batch = 1; D.nseg = 1; D.beta = beta;
-  Seg& S = D.seg[0];
-  S.A = A; S.a_rs = a_rs; S.a_cs = a_cs; S.B = B; S.b_rs = b_rs; S.b_cs = b_cs; S.K = K; S.alpha = alpha; S.tri = tri;
-  return D;
-}
 
 int gpfvm::get_full_ops(gpfvm_handle* h, int nrhs, gpfvm_opset** out) {
   auto it = h->full_ops.find(nrhs);
@@ -575,10 +568,10 @@ extern "C" int gpfvm_matvec(gpfvm_handle* h, int nrhs, const double* x, double* 
     if (rc) return rc;
     const i64 n = h->n, N = h->N, nb = h->nb;
     for (int r = 0; r < nrhs; ++r)
-      HIPCHK(h, launch_copy_f64_to_f32(os->XF + r * n + nb, (float*)so->X + r * N, N, s));
+      HIPCHK(h, launch_copy_f64_to_f32(os->XF + r * n + nb, (float*)so->X32 + r * N, N, s));
     HIPCHK(h, run_plan(so->pp, s));
     for (int r = 0; r < nrhs; ++r)
-      HIPCHK(h, launch_copy_f32_to_f64((const float*)so->Y + r * N, os->YF + r * n + nb, N, s));
+      HIPCHK(h, launch_copy_f32_to_f64((const float*)so->Y32 + r * N, os->YF + r * n + nb, N, s));
   }
   if (h->nb > 0) HIPCHK(h, run_plan(os->pb, s));
   HIPCHK(h, hipMemcpyAsync(y, os->YF, bytes, hipMemcpyDeviceToDevice, s));

@@ -164,13 +164,16 @@ struct gpfvm_opset {
 };
 
 // Operators of the volume (Schur) system S = G_pp + s2 I - G_pb G_bb^{-1} G_bp.
+// G_bb^{-1} is applied as two triangular solves with L, each computed with the
+// explicit L^{-1} and corrected once by the residual with L (backward stable).
 struct gpfvm_sop {
   int nrhs = 0;
-  gpfvm::Elt elt = gpfvm::F64;
-  void *X = nullptr, *Y = nullptr;  // N * nrhs
-  void *U = nullptr, *T = nullptr, *W = nullptr;   // n_b * nrhs
-  gpfvm::Plan pp, bp, pb;
-  gpfvm::Stage linv, linvt;         // T = L^{-1} U ; W = L^{-T} T
+  gpfvm::Elt elt = gpfvm::F64;      // element type of the volume block pp
+  void *X = nullptr, *Y = nullptr;  // N * nrhs (float64)
+  void *X32 = nullptr, *Y32 = nullptr;  // N * nrhs (float32, mixed operator)
+  void *U = nullptr, *T = nullptr, *W = nullptr, *R = nullptr;   // n_b * nrhs
+  gpfvm::Plan pp, bp, pb;           // pp: float64 or float32; bp, pb: float64
+  std::vector<gpfvm::Stage> ginv;   // W = G_bb^{-1} U (six stages)
   double flops_pp = 0;
 };
 
@@ -218,6 +221,7 @@ struct gpfvm_handle {
   double* ab0 = nullptr;           // G_bb^{-1} y_b
   double* v = nullptr;             // volume weights (N)
   double* Dd = nullptr;            // directions: column j at Dd + j * N
+  double* Qd = nullptr;            // S applied to the directions (two-pass projection)
   double* eta = nullptr;           // max_iter
   double* vec = nullptr;           // solver vectors (r, s, z, d, ...), 8 * N
   double* red = nullptr;           // reorthogonalisation partials (RCHUNK x max_iter)

@@ -56,5 +56,9 @@ hipError_t run_plan(const Plan& p, hipStream_t s);
 int get_full_ops(gpfvm_handle* h, int nrhs, gpfvm_opset** out);
 int get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out);
 int build_ops32(gpfvm_handle* h);
+std::vector<Stage> ginv_stages(const gpfvm_handle* h, int nrhs, const double* U, double* T, double* W, double* R);
+hipError_t run_stages(const std::vector<Stage>& st, hipStream_t s);
+GemmDesc desc1(void* C, i64 c_rs, const void* A, i64 a_rs, i64 a_cs, const void* B, i64 b_rs, i64 b_cs, int M,
+               int N, int K, double alpha, double beta, int tri);
 
 }  // namespace gpfvm

@@ -85,6 +85,43 @@ __global__ void k_reorth_apply(const double* __restrict__ D, i64 N, int nd, cons
   d[k] = v;
 }
 
+// d[k] -= sum_j coef[j] D[j][k] ;  w[k] -= sum_j coef[j] Q[j][k]
+__global__ void k_reorth_apply2(const double* __restrict__ D, const double* __restrict__ Q, i64 N, int nd,
+                                const double* __restrict__ coef, double* __restrict__ d, double* __restrict__ w) {
+  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  double dv = d[k], wv = w[k];
+  for (int j = 0; j < nd; ++j) {
+    const double c = coef[j];
+    dv -= c * D[(i64)j * N + k];
+    wv -= c * Q[(i64)j * N + k];
+  }
+  d[k] = dv;
+  w[k] = wv;
+}
+
+// guarded update with recursive residual: v += a d ; r -= a w ; store d, w
+__global__ void k_update2(i64 N, const double* __restrict__ d, const double* __restrict__ w, double* __restrict__ v,
+                          double* __restrict__ r, double* __restrict__ Dcol, double* __restrict__ Qcol,
+                          double* __restrict__ eta_slot, const double* __restrict__ scal, int* __restrict__ flag) {
+  if (flag[0] != 0) return;
+  const double et = scal[1], sr = scal[2];
+  if (!(et > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 2;
+    return;
+  }
+  const double a = sr / et;
+  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) {
+    const double dk = d[k], wk = w[k];
+    v[k] += a * dk;
+    r[k] -= a * wk;
+    Dcol[k] = dk;
+    Qcol[k] = wk;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *eta_slot = et;
+}
+
 // scal layout: [0] r.r  [1] z.d (eta_i)  [2] s.r  [3] b.b  [4] tol^2
 // flag layout: [0] state (0 running, 1 converged, 2 breakdown)  [1] iterations
 __global__ void k_check(double* scal, int* flag, int max_iter) {
@@ -180,7 +217,12 @@ __global__ void k_point_grid(const PGMeta* __restrict__ meta, int nb, i64 x0, i6
   out[b * nx + xl] = p;
 }
 
-GemmDesc desc1(void* C, i64 c_rs, const void* A, i64 a_rs, i64 a_cs, const void* B, i64 b_rs, i64 b_cs, int M,
+
+unsigned nblk(i64 n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+GemmDesc gpfvm::desc1(void* C, i64 c_rs, const void* A, i64 a_rs, i64 a_cs, const void* B, i64 b_rs, i64 b_cs, int M,
                int N, int K, double alpha, double beta, int tri) {
   GemmDesc D;
   std::memset(&D, 0, sizeof(D));
@@ -191,12 +233,50 @@ GemmDesc desc1(void* C, i64 c_rs, const void* A, i64 a_rs, i64 a_cs, const void*
   return D;
 }
 
-unsigned nblk(i64 n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
-
-}  // namespace
 
 // ---------------------------------------------------------------------------
-// volume-system operator S for nrhs right-hand sides (float64 or float32)
+// G_bb^{-1} = L^{-T} L^{-1}, each triangular solve done as t = L^{-1} u
+// followed by one correction t += L^{-1} (u - L t) (and likewise with L^T).
+// Multiplying by an explicit inverse alone is not backward stable for this
+// ill-conditioned block; the single residual correction restores it.
+// Vectors are stored right-hand-side major (each a contiguous n_b vector).
+// ---------------------------------------------------------------------------
+std::vector<Stage> gpfvm::ginv_stages(const gpfvm_handle* h, int nrhs, const double* U, double* T, double* W,
+                                      double* R) {
+  const int nb = h->nb;
+  std::vector<Stage> st(6);
+  auto add = [&](int k, GemmDesc D) { st[k].descs.push_back(D); };
+  // forward: T = Linv U ; R = U - L T ; T += Linv R     (B[j][i] = M[i][j], upper in (j, i))
+  add(0, desc1(T, nb, U, nb, 1, h->Linv, 1, nb, nrhs, nb, nb, 1.0, 0.0, 3));
+  {
+    GemmDesc D = desc1(R, nb, T, nb, 1, h->L, 1, nb, nrhs, nb, nb, -1.0, 0.0, 3);
+    D.X = U; D.x_rs = nb; D.x_cs = 1; D.gamma = 1.0;
+    add(1, D);
+  }
+  add(2, desc1(T, nb, R, nb, 1, h->Linv, 1, nb, nrhs, nb, nb, 1.0, 1.0, 3));
+  // backward: W = Linv^T T ; R = T - L^T W ; W += Linv^T R   (B[j][i] = M[j][i], lower)
+  add(3, desc1(W, nb, T, nb, 1, h->Linv, nb, 1, nrhs, nb, nb, 1.0, 0.0, 4));
+  {
+    GemmDesc D = desc1(R, nb, W, nb, 1, h->L, nb, 1, nrhs, nb, nb, -1.0, 0.0, 4);
+    D.X = T; D.x_rs = nb; D.x_cs = 1; D.gamma = 1.0;
+    add(4, D);
+  }
+  add(5, desc1(W, nb, R, nb, 1, h->Linv, nb, 1, nrhs, nb, nb, 1.0, 1.0, 4));
+  return st;
+}
+
+hipError_t gpfvm::run_stages(const std::vector<Stage>& st, hipStream_t s) {
+  for (const Stage& x : st) {
+    const hipError_t e = launch_gemm_stage(F64, x, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// volume-system operator S for nrhs right-hand sides.  elt = F32 gives the
+// mixed operator: the volume Kronecker block in float32 (float32 factors,
+// float32 accumulation), the point-block correction in float64.
 // ---------------------------------------------------------------------------
 int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
   auto& tab = (elt == F64) ? h->sops : h->sops32;
@@ -209,73 +289,101 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
   auto so = std::make_unique<gpfvm_sop>();
   so->nrhs = nrhs;
   so->elt = elt;
-  const size_t es = (elt == F64) ? 8 : 4;
   const i64 N = h->N, nb = std::max(h->nb, 1);
-  so->X = h->arena.alloc((size_t)N * nrhs * es);
-  so->Y = h->arena.alloc((size_t)N * nrhs * es);
-  so->U = h->arena.alloc((size_t)nb * nrhs * es);
-  so->T = h->arena.alloc((size_t)nb * nrhs * es);
-  so->W = h->arena.alloc((size_t)nb * nrhs * es);
-  if (!so->X || !so->Y || !so->U || !so->T || !so->W) { h->err = "out of device memory (S operator)"; return GPFVM_E_NOMEM; }
-  const void* cc = (elt == F64) ? (const void*)h->cellc : (const void*)h->cellc_f;
-  const KronOp& opp = (elt == F64) ? h->op_pp : h->op_pp32;
-  std::vector<KronOp> pp{opp};
-  int rc = compile_kron_list(pp, elt, nrhs, so->X, N, so->Y, N, cc, h->cellc, 0.0, so->X, h->sig_pde, 1, h->arena,
-                             h->stream, so->pp, h->err);
+  so->X = h->arena.alloc((size_t)N * nrhs * 8);
+  so->Y = h->arena.alloc((size_t)N * nrhs * 8);
+  so->U = h->arena.alloc((size_t)nb * nrhs * 8);
+  so->T = h->arena.alloc((size_t)nb * nrhs * 8);
+  so->W = h->arena.alloc((size_t)nb * nrhs * 8);
+  so->R = h->arena.alloc((size_t)nb * nrhs * 8);
+  if (!so->X || !so->Y || !so->U || !so->T || !so->W || !so->R) {
+    h->err = "out of device memory (S operator)";
+    return GPFVM_E_NOMEM;
+  }
+  int rc;
+  if (elt == F64) {
+    std::vector<KronOp> pp{h->op_pp};
+    rc = compile_kron_list(pp, F64, nrhs, so->X, N, so->Y, N, h->cellc, h->cellc, 0.0, so->X, h->sig_pde, 1,
+                           h->arena, h->stream, so->pp, h->err);
+  } else {
+    so->X32 = h->arena.alloc((size_t)N * nrhs * 4);
+    so->Y32 = h->arena.alloc((size_t)N * nrhs * 4);
+    if (!so->X32 || !so->Y32) { h->err = "out of device memory (S operator)"; return GPFVM_E_NOMEM; }
+    std::vector<KronOp> pp{h->op_pp32};
+    rc = compile_kron_list(pp, F32, nrhs, so->X32, N, so->Y32, N, h->cellc_f, h->cellc, 0.0, so->X32, h->sig_pde,
+                           1, h->arena, h->stream, so->pp, h->err);
+  }
   if (rc) return rc;
   so->flops_pp = so->pp.flops;
   if (h->nb > 0) {
-    rc = compile_kron_list((elt == F64) ? h->op_bp : h->op_bp32, elt, nrhs, so->X, N, so->U, h->nb, cc, h->cellc, 0.0,
-                           nullptr, 0, 0, h->arena, h->stream, so->bp, h->err);
+    rc = compile_kron_list(h->op_bp, F64, nrhs, so->X, N, so->U, h->nb, h->cellc, h->cellc, 0.0, nullptr, 0, 0,
+                           h->arena, h->stream, so->bp, h->err);
     if (rc) return rc;
-    std::vector<KronOp> pb = (elt == F64) ? h->op_pb : h->op_pb32;
+    std::vector<KronOp> pb = h->op_pb;
     for (auto& o : pb)
       for (auto& t : o.terms) t.alpha = -t.alpha;
-    rc = compile_kron_list(pb, elt, nrhs, so->W, h->nb, so->Y, N, cc, h->cellc, 1.0, nullptr, 0, 1, h->arena,
+    rc = compile_kron_list(pb, F64, nrhs, so->W, h->nb, so->Y, N, h->cellc, h->cellc, 1.0, nullptr, 0, 1, h->arena,
                            h->stream, so->pb, h->err);
     if (rc) return rc;
-    const void* Li = (elt == F64) ? (const void*)h->Linv : (const void*)h->Linv_f;
-    // T[r][i] = sum_j U[r][j] Linv[i][j] ; W[r][i] = sum_j T[r][j] Linv[j][i]
-    so->linv.descs.push_back(desc1(so->T, h->nb, so->U, h->nb, 1, Li, 1, h->nb, nrhs, h->nb, h->nb, 1.0, 0.0, 3));
-    so->linvt.descs.push_back(desc1(so->W, h->nb, so->T, h->nb, 1, Li, h->nb, 1, nrhs, h->nb, h->nb, 1.0, 0.0, 4));
-    std::vector<Stage> st{so->linv, so->linvt};
-    if (upload_stages(st, h->arena, h->stream, elt) != hipSuccess) { h->err = "descriptor check/upload failed"; return GPFVM_E_HIP; }
-    so->linv = st[0];
-    so->linvt = st[1];
+    so->ginv = ginv_stages(h, nrhs, (const double*)so->U, (double*)so->T, (double*)so->W, (double*)so->R);
+    if (upload_stages(so->ginv, h->arena, h->stream, F64) != hipSuccess) {
+      h->err = "descriptor check/upload failed";
+      return GPFVM_E_HIP;
+    }
   }
   *out = so.get();
   tab[nrhs] = std::move(so);
   return GPFVM_OK;
 }
 
+// Y = S X on the operator's bound buffers (X, Y float64; X32 filled by the caller for F32)
 static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
   hipError_t e;
+  const i64 NN = h->N * so->nrhs;
+  if (so->elt == F64) {
+    if ((e = run_plan(so->pp, s)) != hipSuccess) return e;
+  } else {
+    if ((e = launch_copy_f64_to_f32((const double*)so->X, (float*)so->X32, NN, s)) != hipSuccess) return e;
+    if ((e = run_plan(so->pp, s)) != hipSuccess) return e;
+    if ((e = launch_copy_f32_to_f64((const float*)so->Y32, (double*)so->Y, NN, s)) != hipSuccess) return e;
+  }
   if (h->nb > 0) {
     if ((e = run_plan(so->bp, s)) != hipSuccess) return e;
-    if ((e = launch_gemm_stage(so->elt, so->linv, s)) != hipSuccess) return e;
-    if ((e = launch_gemm_stage(so->elt, so->linvt, s)) != hipSuccess) return e;
-  }
-  if ((e = run_plan(so->pp, s)) != hipSuccess) return e;
-  if (h->nb > 0)
+    if ((e = run_stages(so->ginv, s)) != hipSuccess) return e;
     if ((e = run_plan(so->pb, s)) != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
-// y = S x for one float64 vector (through the float64 or float32 operator)
+// y = S x for one float64 vector (through the float64 or the mixed operator)
 static int apply_S(gpfvm_handle* h, Elt elt, const double* x, double* y, hipStream_t s) {
   gpfvm_sop* so = nullptr;
   int rc = get_sop(h, 1, elt, &so);
   if (rc) return rc;
   const i64 N = h->N;
-  if (elt == F64) {
-    HIPCHK(h, hipMemcpyAsync(so->X, x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIPCHK(h, apply_sop(h, so, s));
-    HIPCHK(h, hipMemcpyAsync(y, so->Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-  } else {
-    HIPCHK(h, launch_copy_f64_to_f32(x, (float*)so->X, N, s));
-    HIPCHK(h, apply_sop(h, so, s));
-    HIPCHK(h, launch_copy_f32_to_f64((const float*)so->Y, y, N, s));
+  HIPCHK(h, hipMemcpyAsync(so->X, x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, apply_sop(h, so, s));
+  HIPCHK(h, hipMemcpyAsync(y, so->Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return GPFVM_OK;
+}
+
+extern "C" int gpfvm_schur_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec, void* stream) {
+  if (!h) return GPFVM_E_INVALID;
+  if (nrhs < 1 || nrhs > 4096 || !x || !y) { h->err = "schur_matvec: bad nrhs or NULL buffer"; return GPFVM_E_INVALID; }
+  if (prec != GPFVM_PREC_FP64 && prec != GPFVM_PREC_MIXED) { h->err = "schur_matvec: bad prec"; return GPFVM_E_INVALID; }
+  const size_t bytes = (size_t)h->N * nrhs * sizeof(double);
+  if ((const char*)x < (const char*)y + bytes && (const char*)y < (const char*)x + bytes) {
+    h->err = "schur_matvec: x and y overlap";
+    return GPFVM_E_INVALID;
   }
+  hipStream_t s = (hipStream_t)stream;
+  h->stream = s;
+  gpfvm_sop* so = nullptr;
+  int rc = get_sop(h, nrhs, prec == GPFVM_PREC_FP64 ? F64 : F32, &so);
+  if (rc) return rc;
+  HIPCHK(h, hipMemcpyAsync(so->X, x, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, apply_sop(h, so, s));
+  HIPCHK(h, hipMemcpyAsync(y, so->Y, bytes, hipMemcpyDeviceToDevice, s));
   return GPFVM_OK;
 }
 
@@ -306,8 +414,7 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
     int rc = get_sop(h, 1, F64, &so);
     if (rc) return rc;
     HIPCHK(h, hipMemcpyAsync(so->U, h->yobs, h->nb * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIPCHK(h, launch_gemm_stage(F64, so->linv, s));
-    HIPCHK(h, launch_gemm_stage(F64, so->linvt, s));
+    HIPCHK(h, run_stages(so->ginv, s));
     HIPCHK(h, hipMemcpyAsync(h->ab0, so->W, h->nb * sizeof(double), hipMemcpyDeviceToDevice, s));
     // the volume plan of S accumulates -G_pb W into Y (beta = 1): start from zero
     HIPCHK(h, launch_fill((double*)so->Y, 0.0, N, s));
@@ -319,19 +426,29 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
 
 // One IterGP run on the volume system with right-hand side `b`, float64
 // recurrences, operator precision `elt`.  Directions are appended from slot
-// `start`; v accumulates.  Returns the number of stored directions.
+// `start`; v accumulates.  passes = 1 is the published recurrence
+// d = s - C z with eta = z^T d and an explicit residual every iteration;
+// passes = 2 repeats the S-orthogonal projection on d (classical Gram-Schmidt
+// twice, using w = S d and the stored Q = S D), takes eta = d^T S d, updates
+// the residual recursively with w and replaces it by b - S v every
+// `replace_every` iterations.
 static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int start, int max_new, double tol,
-                      int check_every, hipStream_t s, int* n_out, int* state_out) {
+                      int check_every, int passes, int replace_every, hipStream_t s, int* n_out, int* state_out) {
   const i64 N = h->N;
   double* r = h->vec;
   double* z = h->vec + N;
   double* d = h->vec + 2 * N;
   double* y = h->vec + 3 * N;
   double* sv = h->vec + 4 * N;
+  double* w = h->vec + 5 * N;
   double* partial = h->red;           // RCHUNK x max_iter
   double* dotp = h->aux;              // 512 dot partials
   double* coef = h->aux + 1024;       // max_iter reorthogonalisation coefficients
   int rc;
+  if (passes == 2 && !h->Qd) {
+    h->Qd = (double*)h->arena.alloc((size_t)N * h->max_iter * sizeof(double));
+    if (!h->Qd) { h->err = "out of device memory (S D store; lower max_iter)"; return GPFVM_E_NOMEM; }
+  }
   // r = b - S v
   rc = apply_S(h, elt, v, y, s);
   if (rc) return rc;
@@ -345,6 +462,13 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
   int i = start;
   const int end = std::min(h->max_iter, start + max_new);
   int hflag[2] = {0, 0};
+  auto project = [&](const double* rhs_vec, int nd) {
+    // coef = eta^{-1} o (D^T rhs_vec)
+    hipLaunchKernelGGL(k_reorth_dots, dim3(RCHUNK, (nd + RJ - 1) / RJ), dim3(256), 0, s, (const double*)h->Dd, N, nd,
+                       rhs_vec, partial);
+    hipLaunchKernelGGL(k_reorth_coef, dim3(nblk(nd)), dim3(256), 0, s, (const double*)partial, (const double*)h->eta,
+                       nd, coef);
+  };
   while (i < end) {
     const int batch_end = std::min(end, i + std::max(1, check_every));
     for (; i < batch_end; ++i) {
@@ -356,24 +480,42 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
       if (rc) return rc;
       // d = s - D (eta^{-1} o D^T z)
       if (i > 0) {
-        hipLaunchKernelGGL(k_reorth_dots, dim3(RCHUNK, (i + RJ - 1) / RJ), dim3(256), 0, s, (const double*)h->Dd, N, i,
-                           (const double*)z, partial);
-        hipLaunchKernelGGL(k_reorth_coef, dim3(nblk(i)), dim3(256), 0, s, (const double*)partial,
-                           (const double*)h->eta, i, coef);
+        project(z, i);
         hipLaunchKernelGGL(k_reorth_apply, dim3(nblk(N)), dim3(256), 0, s, (const double*)h->Dd, N, i,
                            (const double*)coef, (const double*)sv, d);
       } else {
         HIPCHK(h, hipMemcpyAsync(d, sv, N * sizeof(double), hipMemcpyDeviceToDevice, s));
       }
-      HIPCHK(h, launch_dot(N, z, d, dotp, h->scal + 1, s));
+      if (passes == 2) {
+        rc = apply_S(h, elt, d, w, s);            // w = S d
+        if (rc) return rc;
+        if (i > 0) {
+          project(w, i);                          // second projection
+          hipLaunchKernelGGL(k_reorth_apply2, dim3(nblk(N)), dim3(256), 0, s, (const double*)h->Dd,
+                             (const double*)h->Qd, N, i, (const double*)coef, d, w);
+        }
+        HIPCHK(h, launch_dot(N, w, d, dotp, h->scal + 1, s));
+      } else {
+        HIPCHK(h, launch_dot(N, z, d, dotp, h->scal + 1, s));
+      }
       HIPCHK(h, launch_dot(N, sv, r, dotp, h->scal + 2, s));
-      hipLaunchKernelGGL(k_update, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, v, h->Dd + (i64)i * N,
-                         h->eta + i, (const double*)h->scal, h->flag);
-      hipLaunchKernelGGL(k_count, dim3(1), dim3(1), 0, s, h->flag, (const double*)h->scal);
-      // r = b - S v
-      rc = apply_S(h, elt, v, y, s);
-      if (rc) return rc;
-      hipLaunchKernelGGL(k_resid, dim3(nblk(N)), dim3(256), 0, s, N, b, (const double*)y, r, (const int*)h->flag);
+      if (passes == 2) {
+        hipLaunchKernelGGL(k_update2, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, (const double*)w, v, r,
+                           h->Dd + (i64)i * N, h->Qd + (i64)i * N, h->eta + i, (const double*)h->scal, h->flag);
+        hipLaunchKernelGGL(k_count, dim3(1), dim3(1), 0, s, h->flag, (const double*)h->scal);
+        if ((i + 1 - start) % std::max(1, replace_every) == 0) {
+          rc = apply_S(h, elt, v, y, s);
+          if (rc) return rc;
+          hipLaunchKernelGGL(k_resid, dim3(nblk(N)), dim3(256), 0, s, N, b, (const double*)y, r, (const int*)h->flag);
+        }
+      } else {
+        hipLaunchKernelGGL(k_update, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, v, h->Dd + (i64)i * N,
+                           h->eta + i, (const double*)h->scal, h->flag);
+        hipLaunchKernelGGL(k_count, dim3(1), dim3(1), 0, s, h->flag, (const double*)h->scal);
+        rc = apply_S(h, elt, v, y, s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_resid, dim3(nblk(N)), dim3(256), 0, s, N, b, (const double*)y, r, (const int*)h->flag);
+      }
     }
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipMemcpyAsync(hflag, h->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -434,7 +576,8 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
   gpfvm_default_solve_opts(&def);
   if (!o) o = &def;
   if (o->prec != GPFVM_PREC_FP64 && o->prec != GPFVM_PREC_MIXED) { h->err = "solve: bad prec"; return GPFVM_E_INVALID; }
-  if (o->max_iter < 0 || !(o->tol >= 0) || o->check_every < 1 || o->max_outer < 1 || !(o->inner_tol > 0)) {
+  if (o->max_iter < 0 || !(o->tol >= 0) || o->check_every < 1 || o->max_outer < 1 || !(o->inner_tol > 0) ||
+      o->reorth_passes < 1 || o->reorth_passes > 2 || o->replace_every < 1) {
     h->err = "solve: bad options";
     return GPFVM_E_INVALID;
   }
@@ -451,7 +594,8 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
   int state = 0, outer = 0;
   if (o->prec == GPFVM_PREC_FP64) {
     int nd = h->iters;
-    rc = itergp_run(h, F64, h->bS, h->v, h->iters, o->max_iter, o->tol, o->check_every, s, &nd, &state);
+    rc = itergp_run(h, F64, h->bS, h->v, h->iters, o->max_iter, o->tol, o->check_every, o->reorth_passes,
+                    o->replace_every, s, &nd, &state);
     if (rc) return rc;
     h->iters = nd;
   } else {
@@ -472,7 +616,7 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
       HIPCHK(h, launch_fill(dx, 0.0, N, s));
       int nd = h->iters;
       rc = itergp_run(h, F32, rr, dx, h->iters, std::min(h->max_iter, o->max_iter) - h->iters, o->inner_tol,
-                      o->check_every, s, &nd, &state);
+                      o->check_every, o->reorth_passes, o->replace_every, s, &nd, &state);
       if (rc) return rc;
       h->iters = nd;
       HIPCHK(h, launch_axpby(N, 1.0, dx, 1.0, x, s));
@@ -516,8 +660,7 @@ extern "C" int gpfvm_weights(gpfvm_handle* h, double* alpha, void* stream) {
     HIPCHK(h, hipMemcpyAsync(so->X, h->v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(h, run_plan(so->bp, s));
     HIPCHK(h, launch_axpby(h->nb, 1.0, h->yobs, -1.0, (double*)so->U, s));
-    HIPCHK(h, launch_gemm_stage(F64, so->linv, s));
-    HIPCHK(h, launch_gemm_stage(F64, so->linvt, s));
+    HIPCHK(h, run_stages(so->ginv, s));
     HIPCHK(h, hipMemcpyAsync(alpha, so->W, h->nb * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   return GPFVM_OK;
@@ -652,15 +795,23 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
     const i64 chunk = std::max<i64>(32, std::min<i64>(M, (i64)(32LL << 20) / h->nb));
     double* KB = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
     double* TT = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
-    if (!KB || !TT) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+    double* RR = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
+    if (!KB || !TT || !RR) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
     for (i64 x0 = 0; x0 < M; x0 += chunk) {
       const i64 nx = std::min(chunk, M - x0);
       hipLaunchKernelGGL(k_point_grid, dim3(nblk((i64)h->nb * nx)), dim3(256), 0, s, (const PGMeta*)dpg, h->nb, x0, nx,
                          h->sf2, KB);
-      std::vector<Stage> st(1);
+      // T = L^{-1} KB, corrected once: T += L^{-1} (KB - L T)
+      std::vector<Stage> st(3);
       st[0].descs.push_back(desc1(TT, nx, h->Linv, h->nb, 1, KB, nx, 1, h->nb, (int)nx, h->nb, 1.0, 0.0, 1));
+      {
+        GemmDesc D = desc1(RR, nx, h->L, h->nb, 1, TT, nx, 1, h->nb, (int)nx, h->nb, -1.0, 0.0, 1);
+        D.X = KB; D.x_rs = nx; D.x_cs = 1; D.gamma = 1.0;
+        st[1].descs.push_back(D);
+      }
+      st[2].descs.push_back(desc1(TT, nx, h->Linv, h->nb, 1, RR, nx, 1, h->nb, (int)nx, h->nb, 1.0, 1.0, 1));
       if (upload_stages(st, tmp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: upload failed");
-      if (launch_gemm_stage(F64, st[0], s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: gemm failed");
+      if (run_stages(st, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: gemm failed");
       hipLaunchKernelGGL(k_colsq, dim3(nblk(nx)), dim3(256), 0, s, (i64)h->nb, nx, (const double*)TT, red + x0);
     }
   }
@@ -672,21 +823,22 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
     double* Ub = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
     double* Tb = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
     double* Wb = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
+    double* Rb = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
     double* Dbuf = (double*)tmp.alloc((size_t)N * B * sizeof(double));
-    if (!P1 || !Dbuf || (h->nb > 0 && (!P2 || !Ub || !Tb || !Wb))) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+    if (!P1 || !Dbuf || (h->nb > 0 && (!P2 || !Ub || !Tb || !Wb || !Rb)))
+      return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
     Plan pgp, pbp, pgb;
     std::vector<KronOp> ops{gp};
     rc = compile_kron_list(ops, F64, B, Dbuf, N, P1, M, h->cellc, h->cellc, 0.0, nullptr, 0, 1, tmp, s, pgp, h->err);
     if (rc) { tmp.release(); return rc; }
-    std::vector<Stage> st(2);
+    std::vector<Stage> st;
     if (h->nb > 0) {
       rc = compile_kron_list(h->op_bp, F64, B, Dbuf, N, Ub, h->nb, h->cellc, h->cellc, 0.0, nullptr, 0, 0, tmp, s, pbp,
                              h->err);
       if (rc) { tmp.release(); return rc; }
       rc = compile_kron_list(gb, F64, B, Wb, h->nb, P2, M, nullptr, nullptr, 0.0, nullptr, 0, 1, tmp, s, pgb, h->err);
       if (rc) { tmp.release(); return rc; }
-      st[0].descs.push_back(desc1(Tb, h->nb, Ub, h->nb, 1, h->Linv, 1, h->nb, B, h->nb, h->nb, 1.0, 0.0, 3));
-      st[1].descs.push_back(desc1(Wb, h->nb, Tb, h->nb, 1, h->Linv, h->nb, 1, B, h->nb, h->nb, 1.0, 0.0, 4));
+      st = ginv_stages(h, B, Ub, Tb, Wb, Rb);
       if (upload_stages(st, tmp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: upload failed");
     }
     for (int j0 = 0; j0 < K; j0 += B) {
@@ -698,8 +850,7 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
       if (run_plan(pgp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
       if (h->nb > 0) {
         if (run_plan(pbp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
-        if (launch_gemm_stage(F64, st[0], s) != hipSuccess || launch_gemm_stage(F64, st[1], s) != hipSuccess)
-          return fail(GPFVM_E_HIP, "posterior: gemm failed");
+        if (run_stages(st, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: gemm failed");
         if (run_plan(pgb, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
       }
       hipLaunchKernelGGL(k_sub_sq_acc, dim3(nblk(M)), dim3(256), 0, s, M, nr, (const double*)P1,

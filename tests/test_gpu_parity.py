@@ -121,10 +121,10 @@ def test_fp64_matvec_matches_dense_oracle(G, name, nrhs):
 # ---------------------------------------------------------------------------
 # solve + posterior
 # ---------------------------------------------------------------------------
-def _gpu_posterior(G, p, iters, tol, prec=0, grid=None):
+def _gpu_posterior(G, p, iters, tol, prec=0, grid=None, passes=2):
     h = G.assemble(p, max_iter=max(iters, 1))
     try:
-        info = G.solve(h, prec=prec, tol=tol, max_iter=iters, check_every=4)
+        info = G.solve(h, prec=prec, tol=tol, max_iter=iters, check_every=4, reorth_passes=passes)
         axes = grid if grid is not None else p.grid
         M = int(np.prod([len(a) for a in axes]))
         mean = torch.empty(M, dtype=torch.float64, device="cuda:0")
@@ -147,15 +147,16 @@ def test_c1_mean_matches_cholesky_oracle(G):
 
 
 @pytest.mark.parametrize("k", [1, 7, 40])
-def test_itergp_fixed_iterations_match_oracle(G, k):
+@pytest.mark.parametrize("passes", [1, 2])
+def test_itergp_fixed_iterations_match_oracle(G, k, passes):
     """Same IterGP recurrences for k iterations: mean and combined variance."""
     p = W.heat1d_c1()
     o = O.Oracle(p)
     X = o.grid_points(p.grid)
     S = SchurSystem(o)
-    vp, D, eta, _ = O.itergp(S, k)
+    vp, D, eta, _ = O.itergp(S, k, passes=passes)
     m_ref, v_ref = two_stage_posterior(S, vp, X, D, eta)
-    m, v, info = _gpu_posterior(G, p, k, 0.0)
+    m, v, info = _gpu_posterior(G, p, k, 0.0, passes=passes)
     assert info["iters"] == k
     assert relerr(m, m_ref) <= 1e-6, relerr(m, m_ref)
     assert relerr(v, v_ref) <= 1e-6, relerr(v, v_ref)
@@ -175,7 +176,7 @@ def test_wave_small_itergp_matches_oracle(G):
     o = O.Oracle(p)
     X = o.grid_points(p.grid)
     S = SchurSystem(o)
-    vp, D, eta, _ = O.itergp(S, 25)
+    vp, D, eta, _ = O.itergp(S, 25, passes=2)
     m_ref, v_ref = two_stage_posterior(S, vp, X, D, eta)
     m, v, info = _gpu_posterior(G, p, 25, 0.0)
     assert info["iters"] == 25
