@@ -93,6 +93,17 @@ struct KronOp {
   i64 out_off = 0;       // offset of the output inside y (per rhs)
 };
 
+// Elementwise pre-step of a plan: xs[r*len + i] = coef[i] * x[r*x_stride + i],
+// i < len (the number of volumes), r < nrhs.
+struct Prescale {
+  const void* x = nullptr;
+  const void* coef = nullptr;
+  void* xs = nullptr;
+  i64 len = 0;
+  i64 x_stride = 0;
+  int nrhs = 0;
+};
+
 // Compiled plan: stages of grouped GEMMs bound to fixed input/output buffers.
 struct Plan {
   Elt elt = F64;
@@ -102,6 +113,7 @@ struct Plan {
   void* xs = nullptr;              // scaled input (cell_coef o x), if needed
   i64 in_len = 0, out_len = 0;
   const void* scale_src = nullptr; // per-volume coefficient (double or float)
+  std::vector<Prescale> pre;       // elementwise pre-steps
   std::vector<Stage> stages;       // the final stages accumulate into y
   double flops = 0;                // executed flops per application (all rhs)
 };
@@ -135,9 +147,10 @@ struct GramTerm {          // merged volume-Gram term
 // ---- kernels / launchers (kernels.hip) --------------------------------------
 hipError_t launch_factor(int kind, int p, int q, int n1, const double* a1, int n2, const double* a2,
                          double ell, double scale, double* out, i64 ld, hipStream_t s);
-hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s);
-hipError_t launch_scale(Elt elt, const void* src, const void* coef, void* dst, i64 n, int nrhs,
-                        hipStream_t s);
+hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s);       // split-K, 4 waves / tile
+hipError_t launch_gemm_stage_lds(Elt elt, const Stage& st, hipStream_t s);   // LDS-staged, 1 wave / tile
+hipError_t launch_scale(Elt elt, const void* src, i64 src_stride, const void* coef, void* dst, i64 dst_stride, i64 n,
+                        int nrhs, hipStream_t s);
 hipError_t launch_axpby(i64 n, double a, const double* x, double b, double* y, hipStream_t s);
 hipError_t launch_copy_f64_to_f32(const double* x, float* y, i64 n, hipStream_t s);
 hipError_t launch_copy_f32_to_f64(const float* x, double* y, i64 n, hipStream_t s);
@@ -149,6 +162,15 @@ hipError_t launch_add_diag(double* A, i64 ld, i64 n0, i64 n, const double* vals,
 // deterministic reductions: out[0] = sum x*y (two passes, fixed order)
 hipError_t launch_dot(i64 n, const double* x, const double* y, double* partial, double* out,
                       hipStream_t s);
+// same, then the IterGP stopping test on out[0] (see solver.hip for the layout)
+hipError_t launch_dot_check(i64 n, const double* x, double* partial, double* scal, int* flag, int max_iter,
+                            hipStream_t s);
+// W = G_bb^{-1} U for n_b <= SMALL_GINV_MAX, one right-hand side, one workgroup
+// (needs the transposes Lt = L^T and Linvt = L^{-T} as row-major copies)
+constexpr int SMALL_GINV_MAX = 512;
+hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const double* Lt, const double* Linvt,
+                             const double* U, double* W, hipStream_t s);
+hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s);
 
 }  // namespace gpfvm
 
@@ -174,6 +196,8 @@ struct gpfvm_sop {
   void *U = nullptr, *T = nullptr, *W = nullptr, *R = nullptr;   // n_b * nrhs
   gpfvm::Plan pp, bp, pb;           // pp: float64 or float32; bp, pb: float64
   std::vector<gpfvm::Stage> ginv;   // W = G_bb^{-1} U (six stages)
+  bool ginv_small = false;          // one-workgroup kernel instead of the stages
+  gpfvm::Plan front;                // pp and bp merged into shared launches
   double flops_pp = 0;
 };
 
@@ -206,6 +230,8 @@ struct gpfvm_handle {
   std::vector<std::vector<std::array<gpfvm::Factor, 3>>> Qfac;   // [group][term][dim]
   double* L = nullptr;             // n_b x n_b Cholesky factor of G_bb (lower)
   double* Linv = nullptr;          // n_b x n_b L^{-1} (lower)
+  double* Lt = nullptr;            // L^T and L^{-T} (small point blocks only)
+  double* Linvt = nullptr;
   float* Linv_f = nullptr;
   gpfvm::GramMeta* meta = nullptr;   // device
   gpfvm::KronOp op_pp, op_pp32;

@@ -51,6 +51,8 @@ int compile_kron_list(const std::vector<KronOp>& ops, Elt elt, int nrhs, const v
                       const void* addx, double gamma, int accumulate, Arena& arena, hipStream_t s, Plan& out,
                       std::string& err);
 hipError_t run_plan(const Plan& p, hipStream_t s);
+// Merge plans whose outputs do not overlap: stage i of every part runs in one launch.
+int merge_plans(const std::vector<const Plan*>& parts, Arena& arena, hipStream_t s, Plan& out, std::string& err);
 
 // handle-level operators (api.hip / solver.hip)
 int get_full_ops(gpfvm_handle* h, int nrhs, gpfvm_opset** out);

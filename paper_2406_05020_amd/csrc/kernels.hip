@@ -222,7 +222,177 @@ __global__ __launch_bounds__(64) void k_gemm(const GemmDesc* __restrict__ descs,
       }
 }
 
+// ----------------------------------------------------------------------------
+// Split-K variant: four wavefronts share one 32x32 output tile and split its K
+// range in chunks of 16 (wave w takes chunks w, w+4, ...).  Operands go from
+// global memory (L2-resident for these sizes) straight into MFMA registers in
+// the lane layout above, with the next chunk's loads issued before the current
+// chunk's MFMAs; no LDS staging and no barriers in the K loop.  The four
+// partial accumulators are summed through LDS at the end.  Built for the
+// latency-bound shapes of the hot path: few output tiles, long K.
+// ----------------------------------------------------------------------------
+constexpr int SK_WAVES = 4;
+constexpr int SK_CHUNK = 16;
+
+template <typename T>
+struct Chunk {
+  T a[4][2], b[4][2];   // [k-step][block]
+};
+
+template <typename T>
+__device__ __forceinline__ void sk_load(Chunk<T>& c, const T* __restrict__ A, const T* __restrict__ B, const Seg& S,
+                                        int m0, int n0, int M, int N, int k0, int kbeg, int kend, int lr, int lk,
+                                        T alpha) {
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = k0 + 4 * kk + lk;
+    const bool kin = (k >= kbeg) && (k < kend);
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      const int row = m0 + blk * 16 + lr;
+      const int col = n0 + blk * 16 + lr;
+      c.a[kk][blk] = (kin && row < M) ? alpha * A[(i64)row * S.a_rs + (i64)k * S.a_cs] : (T)0;
+      c.b[kk][blk] = (kin && col < N) ? B[(i64)k * S.b_rs + (i64)col * S.b_cs] : (T)0;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * SK_WAVES) void k_gemm_sk(const GemmDesc* __restrict__ descs, int ndesc) {
+  typedef typename MfmaOp<T>::v4 v4;
+  __shared__ T red[SK_WAVES - 1][16][64];
+
+  const i64 tile = blockIdx.x;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc& D = descs[lo];
+  const i64 local = tile - D.tile_begin;
+  const int tn = (int)(local % D.tiles_n);
+  const i64 rest = local / D.tiles_n;
+  const int tm = (int)(rest % D.tiles_m);
+  const i64 b = rest / D.tiles_m;
+  if (b >= D.batch) return;
+  if (D.lower_only && tn > tm) return;
+  const int m0 = tm * TILE, n0 = tn * TILE;
+  const int M = D.M, N = D.N;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  v4 acc[2][2][2];   // [slot][bm][bn]
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[s][i][j][r] = 0;
+  bool used1 = false;
+
+  for (int g = 0; g < D.nseg; ++g) {
+    const Seg& S = D.seg[g];
+    const T* __restrict__ A = reinterpret_cast<const T*>(S.A) + b * S.a_bs;
+    const T* __restrict__ B = reinterpret_cast<const T*>(S.B) + b * S.b_bs;
+    const T alpha = (T)S.alpha;
+    int kbeg = 0, kend = S.K;
+    if (S.tri == 1) kend = min(S.K, m0 + TILE);
+    else if (S.tri == 2) kbeg = m0;
+    else if (S.tri == 3) kend = min(S.K, n0 + TILE);
+    else if (S.tri == 4) kbeg = n0;
+    if (S.slot) used1 = true;
+    const int first = kbeg + SK_CHUNK * wave;
+    if (first >= kend) continue;
+    Chunk<T> cur, nxt;
+    sk_load(cur, A, B, S, m0, n0, M, N, first, kbeg, kend, lr, lk, alpha);
+    for (int k0 = first; k0 < kend; k0 += SK_CHUNK * SK_WAVES) {
+      const int kn = k0 + SK_CHUNK * SK_WAVES;
+      if (kn < kend) sk_load(nxt, A, B, S, m0, n0, M, N, kn, kbeg, kend, lr, lk, alpha);
+      if (S.slot == 0) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          acc[0][0][0] = MfmaOp<T>::mac(cur.a[kk][0], cur.b[kk][0], acc[0][0][0]);
+          acc[0][0][1] = MfmaOp<T>::mac(cur.a[kk][0], cur.b[kk][1], acc[0][0][1]);
+          acc[0][1][0] = MfmaOp<T>::mac(cur.a[kk][1], cur.b[kk][0], acc[0][1][0]);
+          acc[0][1][1] = MfmaOp<T>::mac(cur.a[kk][1], cur.b[kk][1], acc[0][1][1]);
+        }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          acc[1][0][0] = MfmaOp<T>::mac(cur.a[kk][0], cur.b[kk][0], acc[1][0][0]);
+          acc[1][0][1] = MfmaOp<T>::mac(cur.a[kk][0], cur.b[kk][1], acc[1][0][1]);
+          acc[1][1][0] = MfmaOp<T>::mac(cur.a[kk][1], cur.b[kk][0], acc[1][1][0]);
+          acc[1][1][1] = MfmaOp<T>::mac(cur.a[kk][1], cur.b[kk][1], acc[1][1][1]);
+        }
+      }
+      cur = nxt;
+    }
+  }
+
+  // cross-wave reduction, one slot at a time
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (s == 1 && !used1) break;
+    if (wave > 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[wave - 1][(i * 2 + j) * 4 + r][lane] = acc[s][i][j][r];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int w = 0; w < SK_WAVES - 1; ++w)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[s][i][j][r] += red[w][(i * 2 + j) * 4 + r][lane];
+    }
+    __syncthreads();
+  }
+  if (wave != 0) return;
+
+  T* __restrict__ C = reinterpret_cast<T*>(D.C) + b * D.c_bs;
+  const T* __restrict__ X = D.X ? reinterpret_cast<const T*>(D.X) + b * D.x_bs : nullptr;
+  const double* __restrict__ E = D.escale ? D.escale + b * D.e_bs : nullptr;
+  const T beta = (T)D.beta, gamma = (T)D.gamma;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + bm * 16 + MfmaOp<T>::row(lk, r);
+        const int col = n0 + bn * 16 + lr;
+        if (row < M && col < N && !(D.lower_only && col > row)) {
+          T v = acc[0][bm][bn][r];
+          if (used1 && E) v += (T)E[(i64)row * D.e_rs + (i64)col * D.e_cs] * acc[1][bm][bn][r];
+          if (X) v += gamma * X[(i64)row * D.x_rs + (i64)col * D.x_cs];
+          T* cp = C + (i64)row * D.c_rs + (i64)col * D.c_cs;
+          if (beta != (T)0) v += beta * *cp;
+          *cp = v;
+        }
+      }
+}
+
 hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
+  if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
+  const int nd = (int)st.descs.size();
+  if (elt == F64)
+    k_gemm_sk<double><<<dim3((unsigned)st.tiles), dim3(64 * SK_WAVES), 0, s>>>(st.d_descs, nd);
+  else
+    k_gemm_sk<float><<<dim3((unsigned)st.tiles), dim3(64 * SK_WAVES), 0, s>>>(st.d_descs, nd);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_stage_lds(Elt elt, const Stage& st, hipStream_t s) {
   if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
   const int nd = (int)st.descs.size();
   if (elt == F64)
@@ -236,22 +406,26 @@ hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
 // elementwise kernels
 // ============================================================================
 template <typename T>
-__global__ void k_scale(const T* __restrict__ src, const T* __restrict__ coef, T* __restrict__ dst,
-                        i64 n, int nrhs) {
+__global__ void k_scale(const T* __restrict__ src, i64 src_stride, const T* __restrict__ coef, T* __restrict__ dst,
+                        i64 dst_stride, i64 n, int nrhs) {
   const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * nrhs) return;
-  dst[i] = coef[i % n] * src[i];
+  const i64 r = i / n, k = i % n;
+  dst[r * dst_stride + k] = coef[k] * src[r * src_stride + k];
 }
 
-hipError_t launch_scale(Elt elt, const void* src, const void* coef, void* dst, i64 n, int nrhs,
-                        hipStream_t s) {
+// dst[r*dst_stride + k] = coef[k] * src[r*src_stride + k], k < n, r < nrhs
+hipError_t launch_scale(Elt elt, const void* src, i64 src_stride, const void* coef, void* dst, i64 dst_stride, i64 n,
+                        int nrhs, hipStream_t s) {
   const i64 tot = n * nrhs;
   if (tot == 0) return hipSuccess;
   const unsigned g = (unsigned)((tot + 255) / 256);
   if (elt == F64)
-    k_scale<double><<<g, 256, 0, s>>>((const double*)src, (const double*)coef, (double*)dst, n, nrhs);
+    k_scale<double><<<g, 256, 0, s>>>((const double*)src, src_stride, (const double*)coef, (double*)dst, dst_stride,
+                                      n, nrhs);
   else
-    k_scale<float><<<g, 256, 0, s>>>((const float*)src, (const float*)coef, (float*)dst, n, nrhs);
+    k_scale<float><<<g, 256, 0, s>>>((const float*)src, src_stride, (const float*)coef, (float*)dst, dst_stride, n,
+                                     nrhs);
   return hipGetLastError();
 }
 
@@ -363,6 +537,108 @@ __global__ __launch_bounds__(DOT_THREADS) void k_dot_final(const double* __restr
     for (int w = 0; w < DOT_THREADS / 64; ++w) t += red[w];
     out[0] = t;
   }
+}
+
+// final reduction + stopping test: scal[0] = r.r ; converged if r.r <= tol^2 b.b
+// (scal[4] = tol^2, scal[3] = b.b); flag[0] = 3 once flag[1] reaches max_iter.
+__global__ __launch_bounds__(DOT_THREADS) void k_dot_final_check(const double* __restrict__ partial,
+                                                                 double* __restrict__ scal, int* __restrict__ flag,
+                                                                 int max_iter) {
+  __shared__ double red[DOT_THREADS / 64];
+  double acc = 0;
+  for (int i = threadIdx.x; i < DOT_BLOCKS; i += DOT_THREADS) acc += partial[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < DOT_THREADS / 64; ++w) t += red[w];
+    if (flag[0] == 0) {
+      scal[0] = t;
+      if (t <= scal[4] * scal[3]) flag[0] = 1;
+      else if (flag[1] >= max_iter) flag[0] = 3;
+    }
+  }
+}
+
+hipError_t launch_dot_check(i64 n, const double* x, double* partial, double* scal, int* flag, int max_iter,
+                            hipStream_t s) {
+  k_dot_partial<<<DOT_BLOCKS, DOT_THREADS, 0, s>>>(n, x, x, partial);
+  k_dot_final_check<<<1, DOT_THREADS, 0, s>>>(partial, scal, flag, max_iter);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// W = G_bb^{-1} U for a small point block in one workgroup (vectors in LDS):
+// t = L^{-1} u ; t += L^{-1} (u - L t) ; w = L^{-T} t ; w += L^{-T} (t - L^T w).
+// Every product is evaluated as y[i] = add[i] + alpha sum_k A[k][i] x[k] over a
+// row-major matrix A (L^T / L^{-T} for the row products, L / L^{-1} for the
+// transposed ones), so consecutive lanes read consecutive addresses; the k
+// range is split across the wavefronts and the partial sums meet in LDS.
+// ----------------------------------------------------------------------------
+constexpr int GS_WAVES = 8;
+constexpr int GS_THREADS = 64 * GS_WAVES;
+
+// kmode 0: k <= i contributes (A upper-triangular);  kmode 1: k >= i (A lower)
+__device__ void gs_prod(int n, const double* __restrict__ A, const double* x, double* y, double alpha,
+                        const double* add, int kmode, double (*part)[SMALL_GINV_MAX]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int per = (n + GS_WAVES - 1) / GS_WAVES;
+  const int k0 = wave * per, k1 = min(n, k0 + per);
+  for (int i = lane; i < n; i += 64) {
+    double acc = 0;
+    const int lo = kmode ? max(k0, i) : k0;
+    const int hi = kmode ? k1 : min(k1, i + 1);
+#pragma unroll 4
+    for (int k = lo; k < hi; ++k) acc += A[(i64)k * n + i] * x[k];
+    part[wave][i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += GS_THREADS) {
+    double acc = 0;
+#pragma unroll
+    for (int w = 0; w < GS_WAVES; ++w) acc += part[w][i];
+    y[i] = (add ? add[i] : 0.0) + alpha * acc;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(GS_THREADS) void k_ginv_small(int n, const double* __restrict__ L,
+                                                           const double* __restrict__ Li,
+                                                           const double* __restrict__ Lt,
+                                                           const double* __restrict__ Lit,
+                                                           const double* __restrict__ U, double* __restrict__ W) {
+  __shared__ double u[SMALL_GINV_MAX], t[SMALL_GINV_MAX], r[SMALL_GINV_MAX], w[SMALL_GINV_MAX];
+  __shared__ double part[GS_WAVES][SMALL_GINV_MAX];
+  for (int i = threadIdx.x; i < n; i += GS_THREADS) u[i] = U[i];
+  __syncthreads();
+  gs_prod(n, Lit, u, t, 1.0, nullptr, 0, part);    // t = Li u        (Li lower: A = Li^T upper)
+  gs_prod(n, Lt, t, r, -1.0, u, 0, part);          // r = u - L t
+  gs_prod(n, Lit, r, t, 1.0, t, 0, part);          // t += Li r
+  gs_prod(n, Li, t, w, 1.0, nullptr, 1, part);     // w = Li^T t      (A = Li lower)
+  gs_prod(n, L, w, r, -1.0, t, 1, part);           // r = t - L^T w
+  gs_prod(n, Li, r, u, 1.0, w, 1, part);           // u = w + Li^T r
+  for (int i = threadIdx.x; i < n; i += GS_THREADS) W[i] = u[i];
+}
+
+hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const double* Lt, const double* Linvt,
+                             const double* U, double* W, hipStream_t s) {
+  if (nb < 1 || nb > SMALL_GINV_MAX) return hipErrorInvalidValue;
+  k_ginv_small<<<1, GS_THREADS, 0, s>>>(nb, L, Linv, Lt, Linvt, U, W);
+  return hipGetLastError();
+}
+
+__global__ void k_transpose(const double* __restrict__ A, double* __restrict__ B, int n) {
+  const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (i64)n * n) return;
+  const int r = (int)(idx / n), c = (int)(idx % n);
+  B[(i64)c * n + r] = A[idx];
+}
+
+hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s) {
+  const i64 tot = (i64)n * n;
+  k_transpose<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(A, B, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_dot(i64 n, const double* x, const double* y, double* partial, double* out,

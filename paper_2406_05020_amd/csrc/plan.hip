@@ -139,11 +139,31 @@ int compile_kron_list(const std::vector<KronOp>& ops, Elt elt, int nrhs, const v
   bool need_xs = false;
   for (auto& op : ops)
     for (auto& t : op.terms) need_xs |= (t.rscale != 0);
+  // Per-volume input scaling applies to volume-shaped inputs only: every op
+  // with a scaled term reads prod(in_shape) values at offset 0 of each rhs.
+  i64 xs_len = 0;
+  for (auto& op : ops)
+    for (auto& t : op.terms)
+      if (t.rscale) {
+        const i64 len = prod(op.in_shape, 0, op.d);
+        if (t.in_off != 0 || (xs_len && xs_len != len) || len > x_rhs_stride) {
+          err = "internal error: per-volume scaling of a non-volume input";
+          return GPFVM_E_INVALID;
+        }
+        xs_len = len;
+      }
   if (need_xs) {
     if (!scale_src) { err = "operator needs per-volume coefficients"; return GPFVM_E_INVALID; }
-    out.in_len = x_rhs_stride;
-    out.xs = arena.alloc((size_t)x_rhs_stride * nrhs * es);
+    out.in_len = xs_len;
+    out.xs = arena.alloc((size_t)xs_len * nrhs * es);
     if (!out.xs) { err = "out of device memory (plan)"; return GPFVM_E_NOMEM; }
+    Prescale ps;
+    ps.x = x; ps.coef = scale_src; ps.xs = out.xs; ps.len = xs_len; ps.x_stride = x_rhs_stride; ps.nrhs = nrhs;
+    if (!range_ok(ps.x, (size_t)((nrhs - 1) * x_rhs_stride + xs_len) * es) || !range_ok(ps.coef, (size_t)xs_len * es)) {
+      err = "internal error: per-volume scaling reads outside its buffers";
+      return GPFVM_E_INVALID;
+    }
+    out.pre.push_back(ps);
   }
 
   std::vector<Stage> mid(d > 1 ? d - 1 : 0);
@@ -168,7 +188,7 @@ int compile_kron_list(const std::vector<KronOp>& ops, Elt elt, int nrhs, const v
     for (const KronTerm& t : op.terms) {
       Tensor cur;
       cur.p = (t.rscale ? (const char*)out.xs : (const char*)x) + (size_t)t.in_off * es;
-      cur.rhs_stride = x_rhs_stride;
+      cur.rhs_stride = t.rscale ? xs_len : x_rhs_stride;
       for (int i = 0; i < 3; ++i) cur.shape[i] = op.in_shape[i];
       std::vector<i64> key = {t.rscale, t.in_off};
       for (int k = 0; k + 1 < d; ++k) {
@@ -301,10 +321,31 @@ int compile_kron(const KronOp& op, Elt elt, int nrhs, const void* x, void* y, co
                            beta, addx, gamma, 1, arena, s, out, err);
 }
 
+int merge_plans(const std::vector<const Plan*>& parts, Arena& arena, hipStream_t s, Plan& out, std::string& err) {
+  out = Plan();
+  if (parts.empty()) return GPFVM_OK;
+  out.elt = parts[0]->elt;
+  size_t nst = 0;
+  for (const Plan* q : parts) {
+    if (q->elt != out.elt) { err = "merge of plans with different element types"; return GPFVM_E_INVALID; }
+    out.pre.insert(out.pre.end(), q->pre.begin(), q->pre.end());
+    nst = std::max(nst, q->stages.size());
+    out.flops += q->flops;
+  }
+  out.stages.resize(nst);
+  for (const Plan* q : parts)
+    for (size_t i = 0; i < q->stages.size(); ++i)
+      out.stages[i].descs.insert(out.stages[i].descs.end(), q->stages[i].descs.begin(), q->stages[i].descs.end());
+  const hipError_t e = upload_stages(out.stages, arena, s, out.elt);
+  if (e == hipErrorInvalidValue) { err = "internal error: merged plan failed its bounds check"; return GPFVM_E_INVALID; }
+  if (e != hipSuccess) { err = "plan upload failed"; return GPFVM_E_HIP; }
+  return GPFVM_OK;
+}
+
 hipError_t run_plan(const Plan& p, hipStream_t s) {
   hipError_t e;
-  if (p.xs) {
-    e = launch_scale(p.elt, p.x, p.scale_src, p.xs, p.in_len, p.nrhs, s);
+  for (const Prescale& ps : p.pre) {
+    e = launch_scale(p.elt, ps.x, ps.x_stride, ps.coef, ps.xs, ps.len, ps.len, ps.nrhs, s);
     if (e != hipSuccess) return e;
   }
   for (const Stage& st : p.stages) {

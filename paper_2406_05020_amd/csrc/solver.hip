@@ -33,14 +33,18 @@ using namespace gpfvm;
 
 namespace {
 
-constexpr int RCHUNK = 256;        // chunks of N in the reorthogonalisation dots
+constexpr int RCHUNK = 256;        // max chunks of N in the reorthogonalisation dots
 constexpr int RJ = 8;              // directions per block in the dots
+constexpr int JSPLIT = 16;         // max direction ranges in the direction sums
 
-// partial[j * RCHUNK + c] = sum_{k in chunk c} D[j][k] z[k],  j < nd
-__global__ __launch_bounds__(256) void k_reorth_dots(const double* __restrict__ D, i64 N, int nd,
+int dot_chunks(i64 N) { return (int)std::max<i64>(1, std::min<i64>(RCHUNK, (N + 1023) / 1024)); }
+int jsplit_of(int nd) { return std::max(1, std::min(JSPLIT, (nd + 15) / 16)); }
+
+// partial[j * nch + c] = sum_{k in chunk c} D[j][k] z[k],  j < nd
+__global__ __launch_bounds__(256) void k_reorth_dots(const double* __restrict__ D, i64 N, int nd, int nch,
                                                      const double* __restrict__ z, double* __restrict__ partial) {
   const int c = blockIdx.x, j0 = blockIdx.y * RJ;
-  const i64 len = (N + RCHUNK - 1) / RCHUNK;
+  const i64 len = (N + nch - 1) / nch;
   const i64 k0 = c * len, k1 = min(N, k0 + len);
   double acc[RJ];
 #pragma unroll
@@ -61,73 +65,109 @@ __global__ __launch_bounds__(256) void k_reorth_dots(const double* __restrict__ 
   __syncthreads();
   if (threadIdx.x < RJ && j0 + (int)threadIdx.x < nd) {
     const int j = threadIdx.x;
-    partial[(i64)(j0 + j) * RCHUNK + c] = red[j][0] + red[j][1] + red[j][2] + red[j][3];
+    partial[(i64)(j0 + j) * nch + c] = red[j][0] + red[j][1] + red[j][2] + red[j][3];
   }
 }
 
-// coef[j] = (sum_c partial[j][c]) / eta[j]
-__global__ void k_reorth_coef(const double* __restrict__ partial, const double* __restrict__ eta, int nd,
-                              double* __restrict__ coef) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// coef[j] = (sum_c partial[j][c]) / eta[j]   (one wavefront per direction)
+__global__ __launch_bounds__(256) void k_reorth_coef(const double* __restrict__ partial,
+                                                     const double* __restrict__ eta, int nd, int nch,
+                                                     double* __restrict__ coef) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (j >= nd) return;
   double s = 0;
-  for (int c = 0; c < RCHUNK; ++c) s += partial[(i64)j * RCHUNK + c];
-  coef[j] = s / eta[j];
+  for (int c = lane; c < nch; c += 64) s += partial[(i64)j * nch + c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) coef[j] = s / eta[j];
 }
 
-// d[k] = s[k] - sum_{j<nd} coef[j] D[j][k]
-__global__ void k_reorth_apply(const double* __restrict__ D, i64 N, int nd, const double* __restrict__ coef,
-                               const double* __restrict__ s, double* __restrict__ d) {
+// part[js][k] = sum_{j in range js} coef[j] D[j][k]  (and the same with Q)
+__global__ __launch_bounds__(256) void k_dir_partial(const double* __restrict__ D, const double* __restrict__ Q,
+                                                     i64 N, int nd, int js_n, const double* __restrict__ coef,
+                                                     double* __restrict__ pd, double* __restrict__ pw) {
+  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  const int js = blockIdx.y;
+  if (k >= N) return;
+  const int per = (nd + js_n - 1) / js_n;
+  const int j0 = js * per, j1 = min(nd, j0 + per);
+  double a = 0, b = 0;
+  if (Q) {
+    for (int j = j0; j < j1; ++j) {
+      const double c = coef[j];
+      a += c * D[(i64)j * N + k];
+      b += c * Q[(i64)j * N + k];
+    }
+    pw[(i64)js * N + k] = b;
+  } else {
+    for (int j = j0; j < j1; ++j) a += coef[j] * D[(i64)j * N + k];
+  }
+  pd[(i64)js * N + k] = a;
+}
+
+// d = X - sum_js pd ; X = d
+__global__ void k_reorth_finish_x(i64 N, int js_n, const double* __restrict__ pd, double* __restrict__ X,
+                                  double* __restrict__ d) {
   const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
-  double v = s[k];
-  for (int j = 0; j < nd; ++j) v -= coef[j] * D[(i64)j * N + k];
+  double v = X[k];
+  for (int js = 0; js < js_n; ++js) v -= pd[(i64)js * N + k];
   d[k] = v;
+  X[k] = v;
 }
 
-// d[k] -= sum_j coef[j] D[j][k] ;  w[k] -= sum_j coef[j] Q[j][k]
-__global__ void k_reorth_apply2(const double* __restrict__ D, const double* __restrict__ Q, i64 N, int nd,
-                                const double* __restrict__ coef, double* __restrict__ d, double* __restrict__ w) {
+// d -= sum_js pd ; w = Y - sum_js pw
+__global__ void k_reorth_finish2y(i64 N, int js_n, const double* __restrict__ pd, const double* __restrict__ pw,
+                                  double* __restrict__ d, const double* __restrict__ Y, double* __restrict__ w) {
   const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
-  double dv = d[k], wv = w[k];
-  for (int j = 0; j < nd; ++j) {
-    const double c = coef[j];
-    dv -= c * D[(i64)j * N + k];
-    wv -= c * Q[(i64)j * N + k];
+  double dv = d[k], wv = Y[k];
+  for (int js = 0; js < js_n; ++js) {
+    dv -= pd[(i64)js * N + k];
+    wv -= pw[(i64)js * N + k];
   }
   d[k] = dv;
   w[k] = wv;
 }
 
-// guarded update with recursive residual: v += a d ; r -= a w ; store d, w
-__global__ void k_update2(i64 N, const double* __restrict__ d, const double* __restrict__ w, double* __restrict__ v,
-                          double* __restrict__ r, double* __restrict__ Dcol, double* __restrict__ Qcol,
-                          double* __restrict__ eta_slot, const double* __restrict__ scal, int* __restrict__ flag) {
+// guarded update (two-pass form): a = (s.r)/eta with s = r so s.r = scal[0];
+// v += a d ; r -= a w ; X = r ; store d, w, eta ; count the iteration
+__global__ void k_update2x(i64 N, const double* __restrict__ d, const double* __restrict__ w, double* __restrict__ v,
+                           double* __restrict__ r, double* __restrict__ X, double* __restrict__ Dcol,
+                           double* __restrict__ Qcol, double* __restrict__ eta_slot, const double* __restrict__ scal,
+                           int* __restrict__ flag) {
   if (flag[0] != 0) return;
-  const double et = scal[1], sr = scal[2];
+  const double et = scal[1], sr = scal[0];
+  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (!(et > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 2;
+    if (k == 0) flag[0] = 2;
     return;
   }
   const double a = sr / et;
-  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < N) {
     const double dk = d[k], wk = w[k];
     v[k] += a * dk;
-    r[k] -= a * wk;
+    const double rk = r[k] - a * wk;
+    r[k] = rk;
+    X[k] = rk;
     Dcol[k] = dk;
     Qcol[k] = wk;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *eta_slot = et;
+  if (k == 0) {
+    *eta_slot = et;
+    flag[1] += 1;
+  }
 }
 
-// scal layout: [0] r.r  [1] z.d (eta_i)  [2] s.r  [3] b.b  [4] tol^2
-// flag layout: [0] state (0 running, 1 converged, 2 breakdown)  [1] iterations
-__global__ void k_check(double* scal, int* flag, int max_iter) {
+// r = b - y and X = r (guarded)
+__global__ void k_resid2(i64 N, const double* __restrict__ b, const double* __restrict__ y, double* __restrict__ r,
+                         double* __restrict__ X, const int* __restrict__ flag) {
   if (flag[0] != 0) return;
-  if (scal[0] <= scal[4] * scal[3]) flag[0] = 1;
-  else if (flag[1] >= max_iter) flag[0] = 3;
+  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) {
+    const double v = b[k] - y[k];
+    r[k] = v;
+    X[k] = v;
+  }
 }
 
 // guarded IterGP update of iteration slot `slot`
@@ -135,7 +175,7 @@ __global__ void k_update(i64 N, const double* __restrict__ d, double* __restrict
                          double* __restrict__ eta_slot, const double* __restrict__ scal, int* __restrict__ flag) {
   const int state = flag[0];
   if (state != 0) return;
-  const double et = scal[1], sr = scal[2];
+  const double et = scal[1], sr = scal[0];   // CG actions: s = r, so s.r = r.r
   if (!(et > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 2;   // breakdown: directions no longer S-definite
     return;
@@ -152,14 +192,6 @@ __global__ void k_update(i64 N, const double* __restrict__ d, double* __restrict
 
 __global__ void k_count(int* flag, const double* scal) {
   if (flag[0] == 0 && scal[1] > 0.0) flag[1] += 1;
-}
-
-// r = b - y (guarded)
-__global__ void k_resid(i64 N, const double* __restrict__ b, const double* __restrict__ y, double* __restrict__ r,
-                        const int* __restrict__ flag) {
-  if (flag[0] != 0) return;
-  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < N) r[k] = b[k] - y[k];
 }
 
 __global__ void k_sub_sq_acc(i64 M, int nr, const double* __restrict__ P, const double* __restrict__ Q,
@@ -330,6 +362,13 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
       h->err = "descriptor check/upload failed";
       return GPFVM_E_HIP;
     }
+    so->ginv_small = (nrhs == 1 && h->nb <= SMALL_GINV_MAX && h->Lt && h->Linvt);
+  }
+  if (elt == F64) {
+    std::vector<const Plan*> parts{&so->pp};
+    if (h->nb > 0) parts.push_back(&so->bp);
+    rc = merge_plans(parts, h->arena, h->stream, so->front, h->err);
+    if (rc) return rc;
   }
   *out = so.get();
   tab[nrhs] = std::move(so);
@@ -341,15 +380,19 @@ static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
   hipError_t e;
   const i64 NN = h->N * so->nrhs;
   if (so->elt == F64) {
-    if ((e = run_plan(so->pp, s)) != hipSuccess) return e;
+    if ((e = run_plan(so->front, s)) != hipSuccess) return e;      // G_pp X + s2 X  and  G_bp X
   } else {
     if ((e = launch_copy_f64_to_f32((const double*)so->X, (float*)so->X32, NN, s)) != hipSuccess) return e;
     if ((e = run_plan(so->pp, s)) != hipSuccess) return e;
     if ((e = launch_copy_f32_to_f64((const float*)so->Y32, (double*)so->Y, NN, s)) != hipSuccess) return e;
+    if (h->nb > 0 && (e = run_plan(so->bp, s)) != hipSuccess) return e;
   }
   if (h->nb > 0) {
-    if ((e = run_plan(so->bp, s)) != hipSuccess) return e;
-    if ((e = run_stages(so->ginv, s)) != hipSuccess) return e;
+    if (so->ginv_small)
+      e = launch_ginv_small(h->nb, h->L, h->Linv, h->Lt, h->Linvt, (const double*)so->U, (double*)so->W, s);
+    else
+      e = run_stages(so->ginv, s);
+    if (e != hipSuccess) return e;
     if ((e = run_plan(so->pb, s)) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -398,7 +441,7 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
   h->v = (double*)h->arena.alloc(N * sizeof(double));
   h->Dd = (double*)h->arena.alloc((size_t)N * h->max_iter * sizeof(double));
   h->eta = (double*)h->arena.alloc(h->max_iter * sizeof(double));
-  h->vec = (double*)h->arena.alloc((size_t)8 * N * sizeof(double));
+  h->vec = (double*)h->arena.alloc((size_t)(8 + 2 * JSPLIT) * N * sizeof(double));
   h->red = (double*)h->arena.alloc((size_t)RCHUNK * h->max_iter * sizeof(double));
   h->aux = (double*)h->arena.alloc((size_t)(1024 + h->max_iter) * sizeof(double));
   h->scal = (double*)h->arena.alloc(64 * sizeof(double));
@@ -431,90 +474,97 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
 // passes = 2 repeats the S-orthogonal projection on d (classical Gram-Schmidt
 // twice, using w = S d and the stored Q = S D), takes eta = d^T S d, updates
 // the residual recursively with w and replaces it by b - S v every
-// `replace_every` iterations.
+// `replace_every` iterations.  The operator's input buffer X doubles as the
+// action / direction vector, so no vector is copied inside the loop.
 static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int start, int max_new, double tol,
                       int check_every, int passes, int replace_every, hipStream_t s, int* n_out, int* state_out) {
   const i64 N = h->N;
+  gpfvm_sop* so = nullptr;
+  int rc = get_sop(h, 1, elt, &so);
+  if (rc) return rc;
+  double* X = (double*)so->X;
+  const double* Y = (const double*)so->Y;
   double* r = h->vec;
-  double* z = h->vec + N;
   double* d = h->vec + 2 * N;
-  double* y = h->vec + 3 * N;
-  double* sv = h->vec + 4 * N;
   double* w = h->vec + 5 * N;
   double* partial = h->red;           // RCHUNK x max_iter
   double* dotp = h->aux;              // 512 dot partials
   double* coef = h->aux + 1024;       // max_iter reorthogonalisation coefficients
-  int rc;
   if (passes == 2 && !h->Qd) {
     h->Qd = (double*)h->arena.alloc((size_t)N * h->max_iter * sizeof(double));
     if (!h->Qd) { h->err = "out of device memory (S D store; lower max_iter)"; return GPFVM_E_NOMEM; }
   }
-  // r = b - S v
-  rc = apply_S(h, elt, v, y, s);
-  if (rc) return rc;
+  const int end = std::min(h->max_iter, start + max_new);
+  // r = b - S v ; X = r
   HIPCHK(h, hipMemsetAsync(h->flag, 0, 16 * sizeof(int), s));
+  HIPCHK(h, hipMemcpyAsync(X, v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, apply_sop(h, so, s));
   HIPCHK(h, launch_dot(N, b, b, dotp, h->scal + 3, s));
   {
     const double t2 = tol * tol;
     HIPCHK(h, hipMemcpyAsync(h->scal + 4, &t2, sizeof(double), hipMemcpyHostToDevice, s));
   }
-  hipLaunchKernelGGL(k_resid, dim3(nblk(N)), dim3(256), 0, s, N, b, (const double*)y, r, (const int*)h->flag);
+  hipLaunchKernelGGL(k_resid2, dim3(nblk(N)), dim3(256), 0, s, N, b, Y, r, X, (const int*)h->flag);
   int i = start;
-  const int end = std::min(h->max_iter, start + max_new);
   int hflag[2] = {0, 0};
+  const int nch = dot_chunks(N);
+  double* pd = h->vec + 8 * N;                       // JSPLIT * N
+  double* pw = h->vec + (8 + JSPLIT) * N;            // JSPLIT * N
   auto project = [&](const double* rhs_vec, int nd) {
-    // coef = eta^{-1} o (D^T rhs_vec)
-    hipLaunchKernelGGL(k_reorth_dots, dim3(RCHUNK, (nd + RJ - 1) / RJ), dim3(256), 0, s, (const double*)h->Dd, N, nd,
-                       rhs_vec, partial);
-    hipLaunchKernelGGL(k_reorth_coef, dim3(nblk(nd)), dim3(256), 0, s, (const double*)partial, (const double*)h->eta,
-                       nd, coef);
+    hipLaunchKernelGGL(k_reorth_dots, dim3(nch, (nd + RJ - 1) / RJ), dim3(256), 0, s, (const double*)h->Dd, N, nd,
+                       nch, rhs_vec, partial);
+    hipLaunchKernelGGL(k_reorth_coef, dim3((nd + 3) / 4), dim3(256), 0, s, (const double*)partial,
+                       (const double*)h->eta, nd, nch, coef);
   };
   while (i < end) {
     const int batch_end = std::min(end, i + std::max(1, check_every));
     for (; i < batch_end; ++i) {
-      HIPCHK(h, launch_dot(N, r, r, dotp, h->scal + 0, s));
-      hipLaunchKernelGGL(k_check, dim3(1), dim3(1), 0, s, h->scal, h->flag, end - start);
-      // s = r ; z = S s
-      HIPCHK(h, hipMemcpyAsync(sv, r, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-      rc = apply_S(h, elt, sv, z, s);
-      if (rc) return rc;
-      // d = s - D (eta^{-1} o D^T z)
-      if (i > 0) {
-        project(z, i);
-        hipLaunchKernelGGL(k_reorth_apply, dim3(nblk(N)), dim3(256), 0, s, (const double*)h->Dd, N, i,
-                           (const double*)coef, (const double*)sv, d);
+      // scal[0] = r.r and the stopping test; s = r is already in X
+      HIPCHK(h, launch_dot_check(N, r, dotp, h->scal, h->flag, end - start, s));
+      HIPCHK(h, apply_sop(h, so, s));                         // z = S s  (in Y)
+      if (passes == 1) HIPCHK(h, hipMemcpyAsync(h->vec + N, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (i > 0) {                                            // d = s - D (eta^-1 o D^T z), also into X
+        project(Y, i);
+        const int jn = jsplit_of(i);
+        hipLaunchKernelGGL(k_dir_partial, dim3(nblk(N), jn), dim3(256), 0, s, (const double*)h->Dd,
+                           (const double*)nullptr, N, i, jn, (const double*)coef, pd, (double*)nullptr);
+        hipLaunchKernelGGL(k_reorth_finish_x, dim3(nblk(N)), dim3(256), 0, s, N, jn, (const double*)pd, X, d);
       } else {
-        HIPCHK(h, hipMemcpyAsync(d, sv, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(h, hipMemcpyAsync(d, X, N * sizeof(double), hipMemcpyDeviceToDevice, s));
       }
       if (passes == 2) {
-        rc = apply_S(h, elt, d, w, s);            // w = S d
-        if (rc) return rc;
+        HIPCHK(h, apply_sop(h, so, s));                       // w = S d  (in Y)
         if (i > 0) {
-          project(w, i);                          // second projection
-          hipLaunchKernelGGL(k_reorth_apply2, dim3(nblk(N)), dim3(256), 0, s, (const double*)h->Dd,
-                             (const double*)h->Qd, N, i, (const double*)coef, d, w);
+          project(Y, i);
+          const int jn = jsplit_of(i);
+          hipLaunchKernelGGL(k_dir_partial, dim3(nblk(N), jn), dim3(256), 0, s, (const double*)h->Dd,
+                             (const double*)h->Qd, N, i, jn, (const double*)coef, pd, pw);
+          hipLaunchKernelGGL(k_reorth_finish2y, dim3(nblk(N)), dim3(256), 0, s, N, jn, (const double*)pd,
+                             (const double*)pw, d, Y, w);
+        } else {
+          HIPCHK(h, hipMemcpyAsync(w, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         }
-        HIPCHK(h, launch_dot(N, w, d, dotp, h->scal + 1, s));
-      } else {
-        HIPCHK(h, launch_dot(N, z, d, dotp, h->scal + 1, s));
-      }
-      HIPCHK(h, launch_dot(N, sv, r, dotp, h->scal + 2, s));
-      if (passes == 2) {
-        hipLaunchKernelGGL(k_update2, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, (const double*)w, v, r,
-                           h->Dd + (i64)i * N, h->Qd + (i64)i * N, h->eta + i, (const double*)h->scal, h->flag);
-        hipLaunchKernelGGL(k_count, dim3(1), dim3(1), 0, s, h->flag, (const double*)h->scal);
+        HIPCHK(h, launch_dot(N, w, d, dotp, h->scal + 1, s));     // eta = d^T S d
+        hipLaunchKernelGGL(k_update2x, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, (const double*)w, v, r,
+                           X, h->Dd + (i64)i * N, h->Qd + (i64)i * N, h->eta + i, (const double*)h->scal, h->flag);
         if ((i + 1 - start) % std::max(1, replace_every) == 0) {
-          rc = apply_S(h, elt, v, y, s);
-          if (rc) return rc;
-          hipLaunchKernelGGL(k_resid, dim3(nblk(N)), dim3(256), 0, s, N, b, (const double*)y, r, (const int*)h->flag);
+          HIPCHK(h, hipMemcpyAsync(X, v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+          HIPCHK(h, apply_sop(h, so, s));
+          hipLaunchKernelGGL(k_resid2, dim3(nblk(N)), dim3(256), 0, s, N, b, Y, r, X, (const int*)h->flag);
+          // X must hold r again even when the run has already stopped
+          HIPCHK(h, hipMemcpyAsync(X, r, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         }
       } else {
+        // eta = z^T d with z = S s: recompute z is not needed -- z was in Y before the
+        // projection; the one-pass recurrence keeps a copy of it
+        HIPCHK(h, launch_dot(N, h->vec + N, d, dotp, h->scal + 1, s));
         hipLaunchKernelGGL(k_update, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, v, h->Dd + (i64)i * N,
                            h->eta + i, (const double*)h->scal, h->flag);
         hipLaunchKernelGGL(k_count, dim3(1), dim3(1), 0, s, h->flag, (const double*)h->scal);
-        rc = apply_S(h, elt, v, y, s);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_resid, dim3(nblk(N)), dim3(256), 0, s, N, b, (const double*)y, r, (const int*)h->flag);
+        HIPCHK(h, hipMemcpyAsync(X, v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(h, apply_sop(h, so, s));
+        hipLaunchKernelGGL(k_resid2, dim3(nblk(N)), dim3(256), 0, s, N, b, Y, r, X, (const int*)h->flag);
+        HIPCHK(h, hipMemcpyAsync(X, r, N * sizeof(double), hipMemcpyDeviceToDevice, s));
       }
     }
     HIPCHK(h, hipGetLastError());
