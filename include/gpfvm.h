@@ -207,6 +207,56 @@ int gpfvm_factor(int kind, int p, int q, int n1, const double* a1, int n2,
 
 int gpfvm_get_info(const gpfvm_handle* h, gpfvm_handle_info* info);
 
+/* ---- continuous-batching server --------------------------------------------
+ * Whole GP-PDE solves (assemble + solve + posterior) of different sizes and
+ * data, submitted as they arrive.  Worker threads, one HIP stream each, admit
+ * queued requests in arrival order whenever a worker is free and the
+ * request's estimated HBM footprint fits in the budget left by the requests
+ * in flight; the requests in flight run concurrently on the device.  Device
+ * memory comes from a caching allocator owned by the server.  Results do not
+ * depend on the other requests in flight (deterministic kernels). */
+typedef struct gpfvm_server gpfvm_server;
+
+typedef struct {
+  int workers;              /* concurrent requests (1..16)                       */
+  long long hbm_budget;     /* bytes of HBM the requests in flight may reserve    */
+  int prec;                 /* GPFVM_PREC_* of every solve                        */
+  double tol;               /* relative residual target of every solve            */
+  int max_iter;             /* IterGP iteration cap (also sizes the directions)   */
+  int check_every;          /* convergence poll interval                          */
+} gpfvm_server_opts;
+
+typedef struct {
+  int rc;                   /* GPFVM_OK / NOCONV / error code of the request      */
+  gpfvm_solve_info info;
+  double t_submit, t_start, t_done;   /* host steady-clock seconds                */
+  long long est_bytes;      /* HBM reserved for it at admission                   */
+  long long n_grid;         /* posterior grid points                              */
+} gpfvm_request_result;
+
+typedef struct {
+  long long queued, completed;
+  int in_flight, peak_in_flight;
+  long long reserved_bytes, peak_reserved_bytes, cached_bytes, device_bytes;
+} gpfvm_server_info;
+
+void gpfvm_default_server_opts(gpfvm_server_opts* o);
+/* Start the workers on the current device.  Errors: INVALID, HIP. */
+int gpfvm_server_create(const gpfvm_server_opts* opts, gpfvm_server** out);
+/* Queue one request: the IBVP (validated and deep-copied; the caller may free
+ * its arrays on return) and its posterior grid (host axes).  *ticket
+ * identifies it.  Errors: INVALID, STATE (server stopping). */
+int gpfvm_server_submit(gpfvm_server* s, const gpfvm_ibvp* p, int dim, const int* n, const double* const* axis,
+                        long long* ticket);
+/* *done = 1 once the request has finished (wait = 1 blocks until then); then
+ * fills res (if not NULL) and copies prod(n) posterior means / variances into
+ * the host arrays mean / var (each may be NULL).  Errors: INVALID. */
+int gpfvm_server_poll(gpfvm_server* s, long long ticket, int wait, int* done, gpfvm_request_result* res,
+                      double* mean, double* var);
+int gpfvm_server_stats(gpfvm_server* s, gpfvm_server_info* st);
+/* Finish the queued requests, stop the workers and free all device memory. */
+void gpfvm_server_destroy(gpfvm_server* s);
+
 /* Free every device buffer of the handle (after synchronising its stream).
  * NULL is accepted. */
 void gpfvm_destroy(gpfvm_handle* h);

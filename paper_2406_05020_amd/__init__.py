@@ -59,6 +59,22 @@ class HandleInfo(C.Structure):
                 ("noise_pde_var", C.c_double), ("device_bytes", C.c_longlong)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("workers", C.c_int), ("hbm_budget", C.c_longlong), ("prec", C.c_int), ("tol", C.c_double),
+                ("max_iter", C.c_int), ("check_every", C.c_int)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("rc", C.c_int), ("info", SolveInfo), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double), ("est_bytes", C.c_longlong), ("n_grid", C.c_longlong)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("queued", C.c_longlong), ("completed", C.c_longlong), ("in_flight", C.c_int),
+                ("peak_in_flight", C.c_int), ("reserved_bytes", C.c_longlong), ("peak_reserved_bytes", C.c_longlong),
+                ("cached_bytes", C.c_longlong), ("device_bytes", C.c_longlong)]
+
+
 _lib = None
 
 SYMBOLS = {
@@ -77,6 +93,14 @@ SYMBOLS = {
     "gpfvm_factor": ([C.c_int, C.c_int, C.c_int, C.c_int, _dp, C.c_int, _dp, C.c_double, C.c_void_p, C.c_void_p],
                      C.c_int),
     "gpfvm_get_info": ([C.c_void_p, C.POINTER(HandleInfo)], C.c_int),
+    "gpfvm_default_server_opts": ([C.POINTER(ServerOpts)], None),
+    "gpfvm_server_create": ([C.POINTER(ServerOpts), C.POINTER(C.c_void_p)], C.c_int),
+    "gpfvm_server_submit": ([C.c_void_p, C.POINTER(IBVPStruct), C.c_int, C.POINTER(C.c_int), C.POINTER(_dp),
+                             C.POINTER(C.c_longlong)], C.c_int),
+    "gpfvm_server_poll": ([C.c_void_p, C.c_longlong, C.c_int, C.POINTER(C.c_int), C.POINTER(RequestResult), _dp, _dp],
+                          C.c_int),
+    "gpfvm_server_stats": ([C.c_void_p, C.POINTER(ServerInfo)], C.c_int),
+    "gpfvm_server_destroy": ([C.c_void_p], None),
     "gpfvm_destroy": ([C.c_void_p], None),
     "gpfvm_last_error": ([C.c_void_p], C.c_char_p),
 }
@@ -274,3 +298,60 @@ def solve_ibvp(p, prec: int = PREC_FP64, tol: float = 1e-8, max_iter: int = 512,
         return Solved(mean, var, info)
     finally:
         destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# continuous-batching server
+# ---------------------------------------------------------------------------
+class Server:
+    """Thin wrapper over gpfvm_server_*: submit whole IBVP solves, poll results."""
+
+    def __init__(self, workers: int = 8, hbm_budget: int = 64 << 30, prec: int = PREC_MIXED, tol: float = 1e-6,
+                 max_iter: int = 1024, check_every: int = 16):
+        o = ServerOpts(workers, hbm_budget, prec, tol, max_iter, check_every)
+        self.h = C.c_void_p()
+        _check(lib().gpfvm_server_create(C.byref(o), C.byref(self.h)))
+        self.grids = {}
+
+    def submit(self, p, grid=None) -> int:
+        m = _Marshal(p)
+        axes = [_arr(a) for a in (grid if grid is not None else p.grid)]
+        d = len(axes)
+        n = (C.c_int * d)(*[len(a) for a in axes])
+        ptrs = (_dp * d)(*[a.ctypes.data_as(_dp) for a in axes])
+        t = C.c_longlong()
+        _check(lib().gpfvm_server_submit(self.h, C.byref(m.s), d, n, ptrs, C.byref(t)))
+        self.grids[t.value] = int(np.prod([len(a) for a in axes]))
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = False):
+        """(done, result-dict or None, mean, var) with host numpy arrays."""
+        M = self.grids[ticket]
+        done = C.c_int()
+        res = RequestResult()
+        mean = np.empty(M)
+        var = np.empty(M)
+        _check(lib().gpfvm_server_poll(self.h, ticket, 1 if wait else 0, C.byref(done), C.byref(res),
+                                       mean.ctypes.data_as(_dp), var.ctypes.data_as(_dp)))
+        if not done.value:
+            return False, None, None, None
+        r = {"rc": res.rc, "t_submit": res.t_submit, "t_start": res.t_start, "t_done": res.t_done,
+             "est_bytes": res.est_bytes, "n_grid": res.n_grid}
+        r.update({k: getattr(res.info, k) for k, _ in SolveInfo._fields_})
+        return True, r, mean, var
+
+    def stats(self) -> dict:
+        st = ServerInfo()
+        _check(lib().gpfvm_server_stats(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerInfo._fields_}
+
+    def close(self):
+        if self.h:
+            lib().gpfvm_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

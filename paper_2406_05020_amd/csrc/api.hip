@@ -480,8 +480,16 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
   return GPFVM_OK;
 }
 
+int gpfvm_assemble_cached(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream, DeviceCache* cache,
+                          gpfvm_handle** out);
+
 extern "C" int gpfvm_assemble(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream,
                               gpfvm_handle** out) {
+  return gpfvm_assemble_cached(p, opts, stream, nullptr, out);
+}
+
+int gpfvm_assemble_cached(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream, DeviceCache* cache,
+                          gpfvm_handle** out) {
   if (!out) return fail_static(GPFVM_E_INVALID, "out is NULL");
   *out = nullptr;
   int rc = gpfvm_validate(p);
@@ -490,6 +498,7 @@ extern "C" int gpfvm_assemble(const gpfvm_ibvp* p, const gpfvm_assemble_opts* op
     return fail_static(GPFVM_E_INVALID, "max_iter out of range");
   gpfvm_handle* h = new (std::nothrow) gpfvm_handle();
   if (!h) return fail_static(GPFVM_E_NOMEM, "host allocation failed");
+  h->arena.cache = cache;
   try {
     rc = assemble_impl(p, opts, (hipStream_t)stream, h);
   } catch (const std::exception& e) {
@@ -635,7 +644,6 @@ extern "C" int gpfvm_get_info(const gpfvm_handle* h, gpfvm_handle_info* info) {
 extern "C" void gpfvm_destroy(gpfvm_handle* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
-  (void)hipDeviceSynchronize();
   h->arena.release();
   delete h;
 }

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -64,10 +65,24 @@ struct Stage {
   i64 tiles = 0;
 };
 
+// Caching device allocator shared by the handles of one server: released
+// blocks are kept and reused (best fit within 2x), so a serving loop in steady
+// state calls neither hipMalloc nor hipFree (both can stall other streams).
+struct DeviceCache {
+  std::mutex mu;
+  std::multimap<size_t, void*> free_blocks;    // size -> block
+  std::map<void*, size_t> sizes;               // every block ever allocated
+  i64 cached_bytes = 0, total_bytes = 0;
+  void* get(size_t nbytes);
+  void put(void* p);
+  void release_all();
+};
+
 // Device memory arena owned by a handle (freed at destroy).
 struct Arena {
   std::vector<void*> ptrs;
   i64 bytes = 0;
+  DeviceCache* cache = nullptr;    // when set, blocks come from / go back to it
   void* alloc(size_t nbytes);      // returns nullptr on failure
   void release();
 };

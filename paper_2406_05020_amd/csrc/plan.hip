@@ -53,10 +53,62 @@ bool range_ok(const void* p, size_t nbytes) {
   return a >= it->first && a + nbytes <= it->first + it->second;
 }
 
+void* DeviceCache::get(size_t nbytes) {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = free_blocks.lower_bound(nbytes);
+    if (it != free_blocks.end() && it->first <= 2 * nbytes + 4096) {
+      void* p = it->second;
+      cached_bytes -= (i64)it->first;
+      free_blocks.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, nbytes) != hipSuccess) {
+    // give the cached blocks back to the runtime and try once more
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& kv : free_blocks) {
+      (void)hipFree(kv.second);
+      sizes.erase(kv.second);
+      total_bytes -= (i64)kv.first;
+    }
+    free_blocks.clear();
+    cached_bytes = 0;
+    if (hipMalloc(&p, nbytes) != hipSuccess) return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  sizes[p] = nbytes;
+  total_bytes += (i64)nbytes;
+  return p;
+}
+
+void DeviceCache::put(void* p) {
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = sizes.find(p);
+  if (it == sizes.end()) return;
+  free_blocks.emplace(it->second, p);
+  cached_bytes += (i64)it->second;
+}
+
+void DeviceCache::release_all() {
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto& kv : free_blocks) (void)hipFree(kv.second);
+  free_blocks.clear();
+  sizes.clear();
+  cached_bytes = total_bytes = 0;
+}
+
 void* Arena::alloc(size_t nbytes) {
   void* p = nullptr;
   if (nbytes == 0) nbytes = 256;
-  if (hipMalloc(&p, nbytes) != hipSuccess) return nullptr;
+  nbytes = (nbytes + 255) & ~(size_t)255;
+  if (cache) {
+    p = cache->get(nbytes);
+    if (!p) return nullptr;
+  } else if (hipMalloc(&p, nbytes) != hipSuccess) {
+    return nullptr;
+  }
   ptrs.push_back(p);
   bytes += (i64)nbytes;
   register_range(p, nbytes);
@@ -66,7 +118,8 @@ void* Arena::alloc(size_t nbytes) {
 void Arena::release() {
   for (void* p : ptrs) {
     unregister_range(p);
-    (void)hipFree(p);
+    if (cache) cache->put(p);
+    else (void)hipFree(p);
   }
   ptrs.clear();
   bytes = 0;

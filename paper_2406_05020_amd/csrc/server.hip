@@ -1,0 +1,359 @@
+// Continuous-batching request server.
+//
+// Requests (whole IBVPs plus an evaluation grid) queue on the host.  A pool of
+// worker threads, each owning one HIP stream, takes requests in arrival order
+// as soon as a slot is free and the request's estimated HBM footprint fits
+// within the budget left by the requests in flight; the worker assembles,
+// solves and evaluates the posterior on its stream, so the kernels of the
+// requests in flight overlap on the device, then returns the memory to a
+// shared caching allocator (no hipMalloc / hipFree in steady state) and admits
+// the next request.  Every kernel of the path is deterministic (fixed
+// reduction order, no atomics in arithmetic), so a request's result does not
+// depend on what else is in flight.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+
+#include "common.h"
+#include "internal.h"
+
+using namespace gpfvm;
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Deep copy of an IBVP so that the caller may free its arrays after submit.
+struct IBVPCopy {
+  gpfvm_ibvp p{};
+  std::vector<double> edges[3], cell_coef, f_int, coef;
+  std::vector<int> alpha, cellwise;
+  std::vector<gpfvm_pointgroup> groups;
+  std::vector<std::array<std::vector<double>, 3>> gaxis;
+  std::vector<std::vector<double>> gy;
+
+  explicit IBVPCopy(const gpfvm_ibvp& s) {
+    p = s;
+    long long N = 1;
+    for (int i = 0; i < s.dim; ++i) {
+      edges[i].assign(s.edges[i], s.edges[i] + s.ncell[i] + 1);
+      p.edges[i] = edges[i].data();
+      N *= s.ncell[i];
+    }
+    alpha.assign(s.alpha, s.alpha + s.nterm * s.dim);
+    coef.assign(s.coef, s.coef + s.nterm);
+    p.alpha = alpha.data();
+    p.coef = coef.data();
+    if (s.cellwise) { cellwise.assign(s.cellwise, s.cellwise + s.nterm); p.cellwise = cellwise.data(); }
+    bool any_cw = false;
+    for (int t = 0; t < s.nterm; ++t) any_cw |= (s.cellwise && s.cellwise[t]);
+    if (any_cw && s.cell_coef) { cell_coef.assign(s.cell_coef, s.cell_coef + N); p.cell_coef = cell_coef.data(); }
+    else p.cell_coef = nullptr;
+    if (s.f_int) { f_int.assign(s.f_int, s.f_int + N); p.f_int = f_int.data(); }
+    groups.assign(s.groups, s.groups + s.ngroup);
+    gaxis.resize(s.ngroup);
+    gy.resize(s.ngroup);
+    for (int g = 0; g < s.ngroup; ++g) {
+      long long sz = 1;
+      for (int i = 0; i < s.dim; ++i) {
+        gaxis[g][i].assign(s.groups[g].axis[i], s.groups[g].axis[i] + s.groups[g].n[i]);
+        groups[g].axis[i] = gaxis[g][i].data();
+        sz *= s.groups[g].n[i];
+      }
+      gy[g].assign(s.groups[g].y, s.groups[g].y + sz);
+      groups[g].y = gy[g].data();
+    }
+    p.groups = groups.data();
+  }
+};
+
+}  // namespace
+
+struct gpfvm_request {
+  long long ticket = 0;
+  std::unique_ptr<IBVPCopy> ibvp;
+  int gdim = 0;
+  int gn[3] = {1, 1, 1};
+  std::vector<double> gaxis[3];
+  long long M = 0;
+  size_t est_bytes = 0;
+  double t_submit = 0, t_start = 0, t_done = 0;
+  int rc = GPFVM_OK;
+  bool done = false;
+  std::string err;
+  gpfvm_solve_info info{};
+  std::vector<double> mean, var;
+};
+
+struct gpfvm_server {
+  gpfvm_server_opts opts{};
+  DeviceCache cache;
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<gpfvm_request*> queue;
+  std::map<long long, std::unique_ptr<gpfvm_request>> all;
+  size_t reserved = 0;
+  size_t peak_reserved = 0;
+  int in_flight = 0, peak_in_flight = 0;
+  long long next_ticket = 1;
+  long long completed = 0;
+  bool stop = false;
+  int device = 0;
+};
+
+// Conservative device-memory estimate of one request (bytes).
+static size_t estimate_bytes(const gpfvm_ibvp& p, int max_iter, long long M, int prec) {
+  long long N = 1;
+  for (int i = 0; i < p.dim; ++i) N *= p.ncell[i];
+  long long nb = 0;
+  for (int g = 0; g < p.ngroup; ++g) {
+    long long s = 1;
+    for (int i = 0; i < p.dim; ++i) s *= p.groups[g].n[i];
+    nb += s;
+  }
+  const double d8 = 8.0;
+  double b = 0;
+  b += 2.0 * N * max_iter * d8;                            // directions and S D
+  b += (48.0 + 6.0 * GPFVM_MAX_TERMS) * N * d8;           // solver vectors, plan intermediates, full-Gram buffers
+  b += (nb <= 512 ? 4.0 : 2.0) * nb * nb * d8;             // L, L^{-1} (and transposes)
+  b += 2.0 * nb * 64 * d8 + 4.0 * (nb + 64) * 64 * d8;     // Cholesky workspace
+  const double chunk = std::max(32.0, std::min((double)M, (double)(32LL << 20) / std::max(1LL, nb)));
+  b += 3.0 * nb * chunk * d8;                              // posterior point-block chunks
+  b += 2.0 * M * 64 * d8 + 64.0 * N * d8 + 8.0 * M * d8;  // posterior direction chunks
+  if (prec == GPFVM_PREC_MIXED) b += 12.0 * N * 4.0;       // float32 operator buffers
+  return (size_t)(1.25 * b) + (size_t)(32 << 20);
+}
+
+int gpfvm_assemble_cached(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream, DeviceCache* cache,
+                          gpfvm_handle** out);
+
+static void run_request(gpfvm_server* S, gpfvm_request* r, hipStream_t st) {
+  gpfvm_handle* h = nullptr;
+  gpfvm_assemble_opts ao;
+  gpfvm_default_assemble_opts(&ao);
+  ao.max_iter = S->opts.max_iter;
+  int rc = gpfvm_assemble_cached(&r->ibvp->p, &ao, st, &S->cache, &h);
+  if (rc) {
+    r->rc = rc;
+    r->err = gpfvm_last_error(nullptr);
+    return;
+  }
+  gpfvm_solve_opts so;
+  gpfvm_default_solve_opts(&so);
+  so.prec = S->opts.prec;
+  so.tol = S->opts.tol;
+  so.max_iter = S->opts.max_iter;
+  so.check_every = S->opts.check_every;
+  rc = gpfvm_solve(h, &so, &r->info, st);
+  if (rc && rc != GPFVM_E_NOCONV) {
+    r->rc = rc;
+    r->err = gpfvm_last_error(h);
+    gpfvm_destroy(h);
+    return;
+  }
+  Arena out;
+  out.cache = &S->cache;
+  double* dmean = (double*)out.alloc((size_t)r->M * sizeof(double));
+  double* dvar = (double*)out.alloc((size_t)r->M * sizeof(double));
+  if (!dmean || !dvar) {
+    r->rc = GPFVM_E_NOMEM;
+    r->err = "out of device memory (posterior output)";
+  } else {
+    const double* ax[3] = {r->gaxis[0].data(), r->gaxis[1].data(), r->gaxis[2].data()};
+    rc = gpfvm_posterior(h, r->gdim, r->gn, ax, dmean, dvar, st);
+    if (rc) {
+      r->rc = rc;
+      r->err = gpfvm_last_error(h);
+    } else {
+      r->mean.resize(r->M);
+      r->var.resize(r->M);
+      hipError_t e = hipMemcpyAsync(r->mean.data(), dmean, r->M * sizeof(double), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(r->var.data(), dvar, r->M * sizeof(double), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) { r->rc = GPFVM_E_HIP; r->err = hipGetErrorString(e); }
+      else r->rc = r->info.status;
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  out.release();
+  gpfvm_destroy(h);
+}
+
+static void worker_main(gpfvm_server* S, int w) {
+  (void)hipSetDevice(S->device);
+  hipStream_t st = S->streams[w];
+  for (;;) {
+    gpfvm_request* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait(lk, [&] {
+        if (S->stop) return true;
+        if (S->queue.empty()) return false;
+        return S->queue.front()->est_bytes + S->reserved <= (size_t)S->opts.hbm_budget || S->in_flight == 0;
+      });
+      if (S->stop && S->queue.empty()) return;
+      if (S->queue.empty()) continue;
+      r = S->queue.front();
+      S->queue.pop_front();
+      S->reserved += r->est_bytes;
+      S->peak_reserved = std::max(S->peak_reserved, S->reserved);
+      S->in_flight += 1;
+      S->peak_in_flight = std::max(S->peak_in_flight, S->in_flight);
+    }
+    r->t_start = now_s();
+    if (r->est_bytes > (size_t)S->opts.hbm_budget) {
+      r->rc = GPFVM_E_NOMEM;
+      r->err = "request exceeds the server's HBM budget";
+    } else {
+      try {
+        run_request(S, r, st);
+      } catch (const std::exception& e) {
+        r->rc = GPFVM_E_NOMEM;
+        r->err = std::string("internal error: ") + e.what();
+      }
+    }
+    r->t_done = now_s();
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->reserved -= r->est_bytes;
+      S->in_flight -= 1;
+      S->completed += 1;
+      r->done = true;
+    }
+    S->cv.notify_all();
+  }
+}
+
+extern "C" void gpfvm_default_server_opts(gpfvm_server_opts* o) {
+  if (!o) return;
+  o->workers = 8;
+  o->hbm_budget = 64LL << 30;
+  o->prec = GPFVM_PREC_MIXED;
+  o->tol = 1e-6;
+  o->max_iter = 1024;
+  o->check_every = 16;
+}
+
+extern "C" int gpfvm_server_create(const gpfvm_server_opts* o, gpfvm_server** out) {
+  if (!out) return GPFVM_E_INVALID;
+  *out = nullptr;
+  gpfvm_server_opts def;
+  gpfvm_default_server_opts(&def);
+  if (!o) o = &def;
+  if (o->workers < 1 || o->workers > 16 || o->hbm_budget < (1LL << 26) || o->max_iter < 1 || !(o->tol >= 0) ||
+      o->check_every < 1 || (o->prec != GPFVM_PREC_FP64 && o->prec != GPFVM_PREC_MIXED))
+    return GPFVM_E_INVALID;
+  auto S = std::make_unique<gpfvm_server>();
+  S->opts = *o;
+  if (hipGetDevice(&S->device) != hipSuccess) return GPFVM_E_HIP;
+  for (int w = 0; w < o->workers; ++w) {
+    hipStream_t st;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (auto x : S->streams) (void)hipStreamDestroy(x);
+      return GPFVM_E_HIP;
+    }
+    S->streams.push_back(st);
+  }
+  gpfvm_server* raw = S.release();
+  for (int w = 0; w < o->workers; ++w) raw->workers.emplace_back(worker_main, raw, w);
+  *out = raw;
+  return GPFVM_OK;
+}
+
+extern "C" int gpfvm_server_submit(gpfvm_server* S, const gpfvm_ibvp* p, int dim, const int* n,
+                                   const double* const* axis, long long* ticket) {
+  if (!S || !ticket) return GPFVM_E_INVALID;
+  int rc = gpfvm_validate(p);
+  if (rc) return rc;
+  if (dim != p->dim || !n || !axis) return GPFVM_E_INVALID;
+  auto r = std::make_unique<gpfvm_request>();
+  r->gdim = dim;
+  r->M = 1;
+  for (int i = 0; i < dim; ++i) {
+    if (n[i] < 1 || !axis[i]) return GPFVM_E_INVALID;
+    r->gn[i] = n[i];
+    r->gaxis[i].assign(axis[i], axis[i] + n[i]);
+    r->M *= n[i];
+  }
+  r->ibvp = std::make_unique<IBVPCopy>(*p);
+  r->est_bytes = estimate_bytes(*p, S->opts.max_iter, r->M, S->opts.prec);
+  r->t_submit = now_s();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return GPFVM_E_STATE;
+    r->ticket = S->next_ticket++;
+    *ticket = r->ticket;
+    S->queue.push_back(r.get());
+    S->all[r->ticket] = std::move(r);
+  }
+  S->cv.notify_all();
+  return GPFVM_OK;
+}
+
+extern "C" int gpfvm_server_poll(gpfvm_server* S, long long ticket, int wait, int* done, gpfvm_request_result* res,
+                                 double* mean, double* var) {
+  if (!S || !done) return GPFVM_E_INVALID;
+  gpfvm_request* r = nullptr;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return GPFVM_E_INVALID;
+    r = it->second.get();
+    if (wait) S->cv.wait(lk, [&] { return r->done; });
+    *done = r->done ? 1 : 0;
+  }
+  if (!*done) return GPFVM_OK;
+  if (res) {
+    res->rc = r->rc;
+    res->info = r->info;
+    res->t_submit = r->t_submit;
+    res->t_start = r->t_start;
+    res->t_done = r->t_done;
+    res->est_bytes = (long long)r->est_bytes;
+    res->n_grid = r->M;
+  }
+  if (r->rc == GPFVM_OK || r->rc == GPFVM_E_NOCONV) {
+    if (mean) std::memcpy(mean, r->mean.data(), r->M * sizeof(double));
+    if (var) std::memcpy(var, r->var.data(), r->M * sizeof(double));
+  }
+  return GPFVM_OK;
+}
+
+extern "C" int gpfvm_server_stats(gpfvm_server* S, gpfvm_server_info* st) {
+  if (!S || !st) return GPFVM_E_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  st->queued = (long long)S->queue.size();
+  st->in_flight = S->in_flight;
+  st->completed = S->completed;
+  st->peak_in_flight = S->peak_in_flight;
+  st->reserved_bytes = (long long)S->reserved;
+  st->peak_reserved_bytes = (long long)S->peak_reserved;
+  st->cached_bytes = S->cache.cached_bytes;
+  st->device_bytes = S->cache.total_bytes;
+  return GPFVM_OK;
+}
+
+extern "C" void gpfvm_server_destroy(gpfvm_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  for (auto& t : S->workers) t.join();
+  for (auto st : S->streams) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  S->cache.release_all();
+  delete S;
+}

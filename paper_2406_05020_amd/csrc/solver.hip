@@ -598,9 +598,11 @@ extern "C" int gpfvm_weights(gpfvm_handle* h, double* alpha, void* stream);
 static int full_residual(gpfvm_handle* h, double* out, hipStream_t s) {
   // ||y - G alpha|| / ||y|| on the whole system
   const i64 n = h->n;
-  double *a = nullptr, *g = nullptr;
-  if (hipMalloc(&a, n * sizeof(double)) != hipSuccess) { h->err = "out of device memory"; return GPFVM_E_NOMEM; }
-  if (hipMalloc(&g, n * sizeof(double)) != hipSuccess) { (void)hipFree(a); h->err = "out of device memory"; return GPFVM_E_NOMEM; }
+  Arena tmp;
+  tmp.cache = h->arena.cache;
+  double* a = (double*)tmp.alloc(n * sizeof(double));
+  double* g = (double*)tmp.alloc(n * sizeof(double));
+  if (!a || !g) { tmp.release(); h->err = "out of device memory"; return GPFVM_E_NOMEM; }
   int rc = gpfvm_weights(h, a, s);
   if (!rc) rc = gpfvm_matvec(h, 1, a, g, GPFVM_PREC_FP64, s);
   if (!rc) {
@@ -615,8 +617,7 @@ static int full_residual(gpfvm_handle* h, double* out, hipStream_t s) {
     *out = hv[1] > 0 ? std::sqrt(hv[0] / hv[1]) : 0.0;
   }
   (void)hipStreamSynchronize(s);
-  (void)hipFree(a);
-  (void)hipFree(g);
+  tmp.release();
   return rc;
 }
 
@@ -650,26 +651,37 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
     h->iters = nd;
   } else {
     // mixed-precision iterative refinement: float64 residual of the volume
-    // system, float32-operator IterGP for the correction; all directions stay
-    // in one conjugate set so the combined posterior remains defined.
+    // system, IterGP with the mixed operator for the correction; all
+    // directions stay in one conjugate set so the combined posterior remains
+    // defined.  A correction that does not lower the float64 residual is
+    // undone and the refinement stops (the iterate never gets worse).
     double* x = h->v;
     double* rr = h->vec + 6 * N;      // outer residual
     double* dx = h->vec + 7 * N;      // correction
     double res = 0;
+    rc = rel_res(h, x, &res, s);
+    if (rc) return rc;
     for (outer = 0; outer < o->max_outer; ++outer) {
+      if (res <= o->tol || h->iters >= std::min(h->max_iter, o->max_iter)) break;
       rc = apply_S(h, F64, x, rr, s);
       if (rc) return rc;
       HIPCHK(h, launch_axpby(N, 1.0, h->bS, -1.0, rr, s));
-      rc = rel_res(h, x, &res, s);
-      if (rc) return rc;
-      if (res <= o->tol || h->iters >= std::min(h->max_iter, o->max_iter)) break;
       HIPCHK(h, launch_fill(dx, 0.0, N, s));
       int nd = h->iters;
       rc = itergp_run(h, F32, rr, dx, h->iters, std::min(h->max_iter, o->max_iter) - h->iters, o->inner_tol,
                       o->check_every, o->reorth_passes, o->replace_every, s, &nd, &state);
       if (rc) return rc;
-      h->iters = nd;
       HIPCHK(h, launch_axpby(N, 1.0, dx, 1.0, x, s));
+      double res_new = 0;
+      rc = rel_res(h, x, &res_new, s);
+      if (rc) return rc;
+      if (!(res_new < res)) {                // no progress: undo it and drop its directions
+        HIPCHK(h, launch_axpby(N, -1.0, dx, 1.0, x, s));
+        state = (state == 2) ? 2 : 3;
+        break;
+      }
+      res = res_new;
+      h->iters = nd;
       if (state == 2) break;
     }
     state = (res <= o->tol) ? 1 : (state == 2 ? 2 : 3);
@@ -736,6 +748,7 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
   const int d = h->d;
   const i64 N = h->N;
   Arena tmp;    // per-call allocations
+  tmp.cache = h->arena.cache;
   auto fail = [&](int code, const std::string& m) { h->err = m; (void)hipStreamSynchronize(s); tmp.release(); return code; };
   // grid axes on the device
   double* gax[3] = {nullptr, nullptr, nullptr};

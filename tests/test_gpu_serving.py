@@ -1,0 +1,85 @@
+"""Continuous-batching server: each request's result is the same alone and in
+the mix; admission respects the HBM budget; oversize requests are refused; a
+served request equals the same solve through the single-handle entry points."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_05020_amd as G
+    G.lib()
+    return G
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _requests():
+    shapes = [(16, 16), (32, 16), (16, 24), (32, 24), (48, 16), (16, 32), (32, 32), (24, 16)]
+    return [W.heat2d_request(ns, nt, seed=7000 + k) for k, (ns, nt) in enumerate(shapes)]
+
+
+MAX_ITER = 256
+
+
+def _run(G, reqs, workers, budget=32 << 30, prec=None, tol=1e-6):
+    prec = G.PREC_FP64 if prec is None else prec
+    out = []
+    with G.Server(workers=workers, hbm_budget=budget, prec=prec, tol=tol, max_iter=MAX_ITER) as S:
+        tickets = [S.submit(p) for p in reqs]
+        for t in tickets:
+            done, res, m, v = S.poll(t, wait=True)
+            assert done
+            out.append((res, m, v))
+        st = S.stats()
+    return out, st
+
+
+def test_alone_equals_in_the_mix(G):
+    reqs = _requests()
+    mix, st = _run(G, reqs, workers=4)
+    assert st["completed"] == len(reqs)
+    assert st["peak_in_flight"] >= 2          # work from several requests overlapped
+    for k, p in enumerate(reqs):
+        alone, _ = _run(G, [p], workers=1)
+        (r1, m1, v1), (r2, m2, v2) = mix[k], alone[0]
+        assert r1["rc"] in (G.OK, G.E_NOCONV) and r2["rc"] == r1["rc"]
+        assert r1["iters"] == r2["iters"]
+        # deterministic kernels: identical bits, alone or in the mix
+        assert np.array_equal(m1, m2) and np.array_equal(v1, v2), (k, relerr(m1, m2))
+
+
+def test_admission_respects_budget_and_refuses_oversize(G):
+    reqs = _requests()[:4]
+    out, st = _run(G, reqs, workers=4, budget=1 << 30)
+    est = [r["est_bytes"] for r, _, _ in out]
+    assert st["peak_reserved_bytes"] <= max(1 << 30, max(est))
+    big = W.heat2d_request(64, 32, seed=1)
+    out2, _ = _run(G, [big], workers=2, budget=1 << 27)
+    assert out2[0][0]["rc"] == G.E_NOMEM
+
+
+def test_served_request_equals_direct_solve(G):
+    p = W.heat2d_request(32, 24, seed=4242)
+    (rs, ms, vs), = _run(G, [p], workers=2)[0]
+    h = G.assemble(p, max_iter=MAX_ITER)
+    try:
+        info = G.solve(h, tol=1e-6, max_iter=MAX_ITER, check_every=16)
+        M = len(ms)
+        mean = torch.empty(M, dtype=torch.float64, device="cuda:0")
+        var = torch.empty(M, dtype=torch.float64, device="cuda:0")
+        G.posterior(h, p.grid, mean, var)
+        torch.cuda.synchronize()
+        assert info["iters"] == rs["iters"]
+        assert np.array_equal(mean.cpu().numpy(), ms) and np.array_equal(var.cpu().numpy(), vs)
+    finally:
+        G.destroy(h)
