@@ -129,6 +129,8 @@ typedef struct {
   int dim; long long n_pde; int n_b; long long n;
   double noise_pde_var;          /* absolute PDE noise variance actually used       */
   long long device_bytes;        /* HBM held by the handle                          */
+  int volume_launches;           /* kernel launches of one gpfvm_volume_matvec       */
+  double volume_flops;           /* flops those launches execute (all rhs)          */
 } gpfvm_handle_info;
 
 /* Default option values. */
@@ -165,6 +167,15 @@ int gpfvm_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec
  * factors and accumulation) and the point-block correction in float64.
  * Errors: INVALID, NOMEM, HIP. */
 int gpfvm_schur_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec, void* stream);
+
+/* y = (L_V k L_V' + Sigma_V) x: the volume block of the Gram alone (Sec. 4.1
+ * eq. kronecker-structure, with per-cell coefficients as diagonal scalings),
+ * the Kronecker sum evaluated as MFMA mode products.  x, y: device,
+ * N*nrhs doubles, no overlap.  For GPFVM_PREC_FP64 the plan is bound to x and
+ * y on the first call with that (x, y, nrhs) and reused (the buffers must stay
+ * allocated while the handle lives); GPFVM_PREC_MIXED runs the float32 plan
+ * through internal buffers.  Errors: INVALID, NOMEM, HIP. */
+int gpfvm_volume_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec, void* stream);
 
 /* Representer weights alpha = G^{-1} y (Sec. 4, representer weights): exact
  * conditioning on the points, then IterGP with CG actions on the volume

@@ -56,7 +56,8 @@ class SolveInfo(C.Structure):
 
 class HandleInfo(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_pde", C.c_longlong), ("n_b", C.c_int), ("n", C.c_longlong),
-                ("noise_pde_var", C.c_double), ("device_bytes", C.c_longlong)]
+                ("noise_pde_var", C.c_double), ("device_bytes", C.c_longlong), ("volume_launches", C.c_int),
+                ("volume_flops", C.c_double)]
 
 
 class ServerOpts(C.Structure):
@@ -83,6 +84,7 @@ SYMBOLS = {
     "gpfvm_validate": ([C.POINTER(IBVPStruct)], C.c_int),
     "gpfvm_assemble": ([C.POINTER(IBVPStruct), C.POINTER(AssembleOpts), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "gpfvm_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "gpfvm_volume_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
     "gpfvm_schur_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
     "gpfvm_solve": ([C.c_void_p, C.POINTER(SolveOpts), C.POINTER(SolveInfo), C.c_void_p], C.c_int),
     "gpfvm_posterior": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(_dp), C.c_void_p, C.c_void_p,
@@ -217,6 +219,12 @@ def get_info(h) -> dict:
 def matvec(h, x, y, nrhs: int = 1, prec: int = PREC_FP64, stream=None) -> None:
     """y = G x for device float64 tensors x, y of n * nrhs elements."""
     _check(lib().gpfvm_matvec(h, nrhs, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), prec, _stream(stream)), h)
+
+
+def volume_matvec(h, x, y, nrhs: int = 1, prec: int = PREC_FP64, stream=None) -> None:
+    """y = (L_V k L_V' + Sigma_V) x (volume block only)."""
+    _check(lib().gpfvm_volume_matvec(h, nrhs, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), prec,
+                                     _stream(stream)), h)
 
 
 def schur_matvec(h, x, y, nrhs: int = 1, prec: int = PREC_FP64, stream=None) -> None:

@@ -594,6 +594,45 @@ extern "C" int gpfvm_matvec(gpfvm_handle* h, int nrhs, const double* x, double* 
   return GPFVM_OK;
 }
 
+extern "C" int gpfvm_volume_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec, void* stream) {
+  if (!h) return fail_static(GPFVM_E_INVALID, "handle is NULL");
+  if (nrhs < 1 || nrhs > 4096 || !x || !y) { h->err = "volume_matvec: bad nrhs or NULL buffer"; return GPFVM_E_INVALID; }
+  if (prec != GPFVM_PREC_FP64 && prec != GPFVM_PREC_MIXED) { h->err = "volume_matvec: bad prec"; return GPFVM_E_INVALID; }
+  const size_t bytes = (size_t)h->N * nrhs * sizeof(double);
+  if ((const char*)x < (const char*)y + bytes && (const char*)y < (const char*)x + bytes) {
+    h->err = "volume_matvec: x and y overlap";
+    return GPFVM_E_INVALID;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  h->stream = s;
+  if (prec == GPFVM_PREC_MIXED) {
+    gpfvm_sop* so = nullptr;
+    int rc = get_sop(h, nrhs, F32, &so);
+    if (rc) return rc;
+    HIPCHK(h, launch_copy_f64_to_f32(x, (float*)so->X32, (i64)h->N * nrhs, s));
+    HIPCHK(h, run_plan(so->pp, s));
+    HIPCHK(h, launch_copy_f32_to_f64((const float*)so->Y32, y, (i64)h->N * nrhs, s));
+    return GPFVM_OK;
+  }
+  auto key = std::make_tuple((const void*)x, (void*)y, nrhs);
+  auto it = h->vplans.find(key);
+  if (it == h->vplans.end()) {
+    // bind the plan to the caller's buffers (registered for the plan's bounds check)
+    register_range(x, bytes);
+    register_range(y, bytes);
+    h->user_ranges.push_back(x);
+    h->user_ranges.push_back(y);
+    auto pl = std::make_unique<Plan>();
+    std::vector<KronOp> pp{h->op_pp};
+    int rc = compile_kron_list(pp, F64, nrhs, x, h->N, y, h->N, h->cellc, h->cellc, 0.0, x, h->sig_pde, 1, h->arena,
+                               s, *pl, h->err);
+    if (rc) return rc;
+    it = h->vplans.emplace(key, std::move(pl)).first;
+  }
+  HIPCHK(h, run_plan(*it->second, s));
+  return GPFVM_OK;
+}
+
 extern "C" int gpfvm_gram_block(gpfvm_handle* h, long long r0, long long nr, long long c0, long long nc, double* out,
                                 long long ld, void* stream) {
   if (!h) return fail_static(GPFVM_E_INVALID, "handle is NULL");
@@ -638,12 +677,16 @@ extern "C" int gpfvm_get_info(const gpfvm_handle* h, gpfvm_handle_info* info) {
   info->n = h->n;
   info->noise_pde_var = h->sig_pde;
   info->device_bytes = h->arena.bytes;
+  info->volume_launches = 0;
+  for (auto& kv : h->vplans) { info->volume_launches = (int)kv.second->stages.size(); break; }
+  info->volume_flops = h->vplans.empty() ? 0.0 : h->vplans.begin()->second->flops;
   return GPFVM_OK;
 }
 
 extern "C" void gpfvm_destroy(gpfvm_handle* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  for (const void* p : h->user_ranges) unregister_range(p);
   h->arena.release();
   delete h;
 }

@@ -8,6 +8,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/gpfvm.h"
@@ -254,6 +255,9 @@ struct gpfvm_handle {
   std::map<int, std::unique_ptr<gpfvm_opset>> full_ops;  // by nrhs
   std::map<int, std::unique_ptr<gpfvm_sop>> sops;        // by nrhs (F64)
   std::map<int, std::unique_ptr<gpfvm_sop>> sops32;      // by nrhs (F32)
+  // volume-block plans bound to caller buffers: (x, y, nrhs) -> plan
+  std::map<std::tuple<const void*, void*, int>, std::unique_ptr<gpfvm::Plan>> vplans;
+  std::vector<const void*> user_ranges;                  // registered caller buffers
 
   // solver state
   bool solved = false;
