@@ -467,7 +467,7 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
     HIPCHK(h, launch_gram_block(h->meta, 0, h->nb, 0, h->nb, h->L, h->nb, s));
     rc = cholesky_and_inverse(h->L, h->Linv, h->nb, h->arena, s, h->err);
     if (rc) return rc;
-    if (h->nb <= SMALL_GINV_MAX) {
+    {   // transposed copies: every triangular product then streams rows
       h->Lt = (double*)h->arena.alloc((size_t)h->nb * h->nb * sizeof(double));
       h->Linvt = (double*)h->arena.alloc((size_t)h->nb * h->nb * sizeof(double));
       if (!h->Lt || !h->Linvt) { h->err = "out of device memory (point block)"; return GPFVM_E_NOMEM; }

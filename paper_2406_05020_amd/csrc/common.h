@@ -52,7 +52,7 @@ struct GemmDesc {
   double gamma;
   double beta;
   int M, N, batch, nseg;
-  int tiles_m, tiles_n, lower_only, pad;
+  int tiles_m, tiles_n, lower_only, rsub;   // rsub: row sub-tiles per workgroup (LDS-staged kernel)
   i64 tile_begin;
   Seg seg[MAXSEG];
 };
@@ -64,7 +64,11 @@ struct Stage {
   std::vector<GemmDesc> descs;
   GemmDesc* d_descs = nullptr;
   i64 tiles = 0;
+  int kind = 0;    // 0: split-K kernel (32x32 tiles); 1: LDS-staged B kernel (64-column tiles, K <= 128)
 };
+constexpr int BS_K = 128;          // max K per segment of the LDS-staged kernel
+constexpr int BS_COLS = 64;        // output columns per workgroup tile
+constexpr int BS_ROWS = 64;        // output rows per sub-tile (4 waves x 16)
 
 // Caching device allocator shared by the handles of one server: released
 // blocks are kept and reused (best fit within 2x), so a serving loop in steady
@@ -187,6 +191,9 @@ constexpr int SMALL_GINV_MAX = 512;
 hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const double* Lt, const double* Linvt,
                              const double* U, double* W, hipStream_t s);
 hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s);
+// y[i] = add[i] + alpha * sum_k M[i][k] x[k] over k <= i (upper = 0) or k >= i (upper = 1)
+hipError_t launch_trmv_rows(int n, const double* M, const double* x, double* y, double alpha, const double* add,
+                            int upper, hipStream_t s);
 
 }  // namespace gpfvm
 

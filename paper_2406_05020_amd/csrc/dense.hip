@@ -200,6 +200,45 @@ bool desc_in_bounds(const GemmDesc& D, size_t es) {
   return true;
 }
 
+// C^T = B^T A^T: the same product with operands swapped and every view transposed.
+static GemmDesc transposed(const GemmDesc& D) {
+  GemmDesc T = D;
+  T.M = D.N; T.N = D.M;
+  T.c_rs = D.c_cs; T.c_cs = D.c_rs;
+  T.e_rs = D.e_cs; T.e_cs = D.e_rs;
+  T.x_rs = D.x_cs; T.x_cs = D.x_rs;
+  for (int g = 0; g < D.nseg; ++g) {
+    const Seg& S = D.seg[g];
+    Seg& U = T.seg[g];
+    U.A = S.B; U.a_rs = S.b_cs; U.a_cs = S.b_rs; U.a_bs = S.b_bs;
+    U.B = S.A; U.b_rs = S.a_cs; U.b_cs = S.a_rs; U.b_bs = S.a_bs;
+  }
+  return T;
+}
+
+// Pick the kernel of a stage.  The LDS-staged kernel keeps a K x 64 slab of B
+// in LDS and streams A from memory; it serves mode products whose contracted
+// dimension is a 1-D factor size (K <= 128).  A descriptor is transposed when
+// that puts the larger operand in A (more rows per workgroup, B slab reused).
+void choose_kernel(Stage& st) {
+  st.kind = 0;
+  if (st.descs.empty()) return;
+  i64 tiles32 = 0;
+  for (auto& D : st.descs) {
+    if (D.lower_only) return;
+    for (int g = 0; g < D.nseg; ++g)
+      if (D.seg[g].tri != 0 || D.seg[g].K > BS_K || D.seg[g].K < 1) return;
+    tiles32 += (i64)((D.M + TILE - 1) / TILE) * ((D.N + TILE - 1) / TILE) * D.batch;
+  }
+  if (tiles32 < 256) return;          // small stages stay on the split-K kernel
+  for (auto& D : st.descs) {
+    if (D.N > D.M) D = transposed(D);
+    D.rsub = (D.nseg == 1) ? 4 : 1;
+    if ((i64)BS_ROWS * D.rsub > D.M) D.rsub = 1;
+  }
+  st.kind = 1;
+}
+
 // Upload a list of stages whose descriptors are consecutive in one buffer.
 hipError_t upload_stages(std::vector<Stage>& stages, Arena& arena, hipStream_t s, Elt elt) {
   const size_t es = (elt == F64) ? sizeof(double) : sizeof(float);
@@ -214,10 +253,17 @@ hipError_t upload_stages(std::vector<Stage>& stages, Arena& arena, hipStream_t s
   std::vector<GemmDesc> host;
   host.reserve(total);
   for (auto& st : stages) {
+    choose_kernel(st);
     st.tiles = 0;
     for (auto& D : st.descs) {
-      D.tiles_m = (D.M + TILE - 1) / TILE;
-      D.tiles_n = (D.N + TILE - 1) / TILE;
+      if (st.kind == 1) {
+        const int rows = BS_ROWS * D.rsub;
+        D.tiles_m = (D.M + rows - 1) / rows;
+        D.tiles_n = (D.N + BS_COLS - 1) / BS_COLS;
+      } else {
+        D.tiles_m = (D.M + TILE - 1) / TILE;
+        D.tiles_n = (D.N + TILE - 1) / TILE;
+      }
       D.tile_begin = st.tiles;
       st.tiles += (i64)D.tiles_m * D.tiles_n * D.batch;
     }

@@ -33,6 +33,7 @@ hipError_t launch_gram_block(const GramMeta* meta, i64 r0, i64 nr, i64 c0, i64 n
 // Checks every descriptor against the live-range registry, then uploads.
 // Returns hipErrorInvalidValue (nothing uploaded) if an operand is out of bounds.
 hipError_t upload_stages(std::vector<Stage>& stages, Arena& arena, hipStream_t s, Elt elt = F64);
+void choose_kernel(Stage& st);
 void register_range(const void* p, size_t nbytes);
 void unregister_range(const void* p);
 bool range_ok(const void* p, size_t nbytes);
@@ -60,6 +61,7 @@ int get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out);
 int build_ops32(gpfvm_handle* h);
 std::vector<Stage> ginv_stages(const gpfvm_handle* h, int nrhs, const double* U, double* T, double* W, double* R);
 hipError_t run_stages(const std::vector<Stage>& st, hipStream_t s);
+hipError_t ginv_rows(const gpfvm_handle* h, const double* U, double* T, double* W, double* R, hipStream_t s);
 GemmDesc desc1(void* C, i64 c_rs, const void* A, i64 a_rs, i64 a_cs, const void* B, i64 b_rs, i64 b_cs, int M,
                int N, int K, double alpha, double beta, int tri);
 

@@ -382,9 +382,125 @@ __global__ __launch_bounds__(64 * SK_WAVES) void k_gemm_sk(const GemmDesc* __res
       }
 }
 
+// ----------------------------------------------------------------------------
+// LDS-staged variant for mode products (K <= 128 per segment).  A workgroup
+// owns 64 output columns and rsub sub-tiles of 64 rows; for each segment the
+// K x 64 slab of B is staged in LDS once and reused by every row sub-tile,
+// while each wavefront streams its 16 rows of A straight into MFMA registers.
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_bs(const GemmDesc* __restrict__ descs, int ndesc) {
+  typedef typename MfmaOp<T>::v4 v4;
+  __shared__ T Bs[BS_K][BS_COLS + 1];
+  const i64 tile = blockIdx.x;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc& D = descs[lo];
+  const i64 local = tile - D.tile_begin;
+  const int tn = (int)(local % D.tiles_n);
+  const i64 rest = local / D.tiles_n;
+  const int tm = (int)(rest % D.tiles_m);
+  const i64 b = rest / D.tiles_m;
+  if (b >= D.batch) return;
+  const int M = D.M, N = D.N;
+  const int n0 = tn * BS_COLS;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int rsub = D.rsub > 0 ? D.rsub : 1;
+  T* __restrict__ C = reinterpret_cast<T*>(D.C) + b * D.c_bs;
+  const T* __restrict__ X = D.X ? reinterpret_cast<const T*>(D.X) + b * D.x_bs : nullptr;
+  const double* __restrict__ E = D.escale ? D.escale + b * D.e_bs : nullptr;
+  const T beta = (T)D.beta, gamma = (T)D.gamma;
+
+  // single-segment descriptors: stage the slab once for all row sub-tiles
+  const bool one = (D.nseg == 1);
+  auto stage_slab = [&](const Seg& S) {
+    const T* __restrict__ B = reinterpret_cast<const T*>(S.B) + b * S.b_bs;
+    const int K = S.K, K4 = (K + 3) & ~3;
+    const bool kfast = (S.b_rs == 1 && S.b_cs != 1);
+    for (int e = threadIdx.x; e < K4 * BS_COLS; e += 256) {
+      int k, c;
+      if (kfast) { k = e % K4; c = e / K4; } else { k = e / BS_COLS; c = e % BS_COLS; }
+      const int col = n0 + c;
+      T v = 0;
+      if (k < K && col < N) v = B[(i64)k * S.b_rs + (i64)col * S.b_cs];
+      Bs[k][c] = v;
+    }
+  };
+  if (one) {
+    stage_slab(D.seg[0]);
+    __syncthreads();
+  }
+  for (int sub = 0; sub < rsub; ++sub) {
+    const int m0 = (tm * rsub + sub) * BS_ROWS;
+    if (m0 >= M) break;
+    const int row = m0 + wave * 16 + lr;
+    v4 acc[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[s][j][r] = 0;
+    bool used1 = false;
+    for (int g = 0; g < D.nseg; ++g) {
+      const Seg& S = D.seg[g];
+      if (!one) {
+        __syncthreads();
+        stage_slab(S);
+        __syncthreads();
+      }
+      const T* __restrict__ A = reinterpret_cast<const T*>(S.A) + b * S.a_bs;
+      const T alpha = (T)S.alpha;
+      const int K = S.K, steps = (K + 3) >> 2;
+      const bool rin = row < M;
+      if (S.slot) used1 = true;
+      T a_cur = (rin && lk < K) ? alpha * A[(i64)row * S.a_rs + (i64)lk * S.a_cs] : (T)0;
+      for (int st = 0; st < steps; ++st) {
+        const int kn = 4 * (st + 1) + lk;
+        const T a_nxt = (st + 1 < steps && rin && kn < K) ? alpha * A[(i64)row * S.a_rs + (i64)kn * S.a_cs] : (T)0;
+        const int kr = 4 * st + lk;
+        if (S.slot == 0) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[0][j] = MfmaOp<T>::mac(a_cur, Bs[kr][j * 16 + lr], acc[0][j]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[1][j] = MfmaOp<T>::mac(a_cur, Bs[kr][j * 16 + lr], acc[1][j]);
+        }
+        a_cur = a_nxt;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int orow = m0 + wave * 16 + MfmaOp<T>::row(lk, r);
+        const int col = n0 + j * 16 + lr;
+        if (orow < M && col < N) {
+          T v = acc[0][j][r];
+          if (used1 && E) v += (T)E[(i64)orow * D.e_rs + (i64)col * D.e_cs] * acc[1][j][r];
+          if (X) v += gamma * X[(i64)orow * D.x_rs + (i64)col * D.x_cs];
+          T* cp = C + (i64)orow * D.c_rs + (i64)col * D.c_cs;
+          if (beta != (T)0) v += beta * *cp;
+          *cp = v;
+        }
+      }
+  }
+}
+
 hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
   if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
   const int nd = (int)st.descs.size();
+  if (st.kind == 1) {
+    if (elt == F64)
+      k_gemm_bs<double><<<dim3((unsigned)st.tiles), dim3(256), 0, s>>>(st.d_descs, nd);
+    else
+      k_gemm_bs<float><<<dim3((unsigned)st.tiles), dim3(256), 0, s>>>(st.d_descs, nd);
+    return hipGetLastError();
+  }
   if (elt == F64)
     k_gemm_sk<double><<<dim3((unsigned)st.tiles), dim3(64 * SK_WAVES), 0, s>>>(st.d_descs, nd);
   else
@@ -625,6 +741,40 @@ hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const 
                              const double* U, double* W, hipStream_t s) {
   if (nb < 1 || nb > SMALL_GINV_MAX) return hipErrorInvalidValue;
   k_ginv_small<<<1, GS_THREADS, 0, s>>>(nb, L, Linv, Lt, Linvt, U, W);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Triangular matrix-vector product for large point blocks, one wavefront per
+// row of a row-major matrix (coalesced streaming of the triangle):
+//   y[i] = add[i] + alpha * sum_{k in K_i} M[i][k] x[k],
+//   K_i = [0, i] (upper = 0, lower-triangular M) or [i, n) (upper = 1).
+// Transposed products use the stored transpose, so every product streams rows.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_trmv_rows(int n, const double* __restrict__ M, const double* __restrict__ x,
+                                                   double* __restrict__ y, double alpha, const double* __restrict__ add,
+                                                   int upper) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int lo = upper ? i : 0, hi = upper ? n : i + 1;
+  const double* __restrict__ row = M + (i64)i * n;
+  double acc = 0;
+  int k = lo + lane;
+  for (; k + 192 < hi; k += 256) {
+    acc += row[k] * x[k];
+    acc += row[k + 64] * x[k + 64];
+    acc += row[k + 128] * x[k + 128];
+    acc += row[k + 192] * x[k + 192];
+  }
+  for (; k < hi; k += 64) acc += row[k] * x[k];
+  acc = wave_sum(acc);
+  if (lane == 0) y[i] = (add ? add[i] : 0.0) + alpha * acc;
+}
+
+hipError_t launch_trmv_rows(int n, const double* M, const double* x, double* y, double alpha, const double* add,
+                            int upper, hipStream_t s) {
+  k_trmv_rows<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, M, x, y, alpha, add, upper);
   return hipGetLastError();
 }
 

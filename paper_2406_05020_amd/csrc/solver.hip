@@ -297,6 +297,19 @@ std::vector<Stage> gpfvm::ginv_stages(const gpfvm_handle* h, int nrhs, const dou
   return st;
 }
 
+// Same six products for one right-hand side as row-streaming triangular
+// matrix-vector products (large point blocks).
+hipError_t gpfvm::ginv_rows(const gpfvm_handle* h, const double* U, double* T, double* W, double* R, hipStream_t s) {
+  const int nb = h->nb;
+  hipError_t e;
+  if ((e = launch_trmv_rows(nb, h->Linv, U, T, 1.0, nullptr, 0, s)) != hipSuccess) return e;   // t = Li u
+  if ((e = launch_trmv_rows(nb, h->L, T, R, -1.0, U, 0, s)) != hipSuccess) return e;           // r = u - L t
+  if ((e = launch_trmv_rows(nb, h->Linv, R, T, 1.0, T, 0, s)) != hipSuccess) return e;         // t += Li r
+  if ((e = launch_trmv_rows(nb, h->Linvt, T, W, 1.0, nullptr, 1, s)) != hipSuccess) return e;  // w = Li^T t
+  if ((e = launch_trmv_rows(nb, h->Lt, W, R, -1.0, T, 1, s)) != hipSuccess) return e;          // r = t - L^T w
+  return launch_trmv_rows(nb, h->Linvt, R, W, 1.0, W, 1, s);                                   // w += Li^T r
+}
+
 hipError_t gpfvm::run_stages(const std::vector<Stage>& st, hipStream_t s) {
   for (const Stage& x : st) {
     const hipError_t e = launch_gemm_stage(F64, x, s);
@@ -390,6 +403,8 @@ static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
   if (h->nb > 0) {
     if (so->ginv_small)
       e = launch_ginv_small(h->nb, h->L, h->Linv, h->Lt, h->Linvt, (const double*)so->U, (double*)so->W, s);
+    else if (so->nrhs == 1)
+      e = ginv_rows(h, (const double*)so->U, (double*)so->T, (double*)so->W, (double*)so->R, s);
     else
       e = run_stages(so->ginv, s);
     if (e != hipSuccess) return e;
