@@ -52,7 +52,7 @@ struct GemmDesc {
   double gamma;
   double beta;
   int M, N, batch, nseg;
-  int tiles_m, tiles_n, lower_only, rsub;   // rsub: row sub-tiles per workgroup (LDS-staged kernel)
+  int tiles_m, tiles_n, lower_only, pad;
   i64 tile_begin;
   Seg seg[MAXSEG];
 };
@@ -64,11 +64,17 @@ struct Stage {
   std::vector<GemmDesc> descs;
   GemmDesc* d_descs = nullptr;
   i64 tiles = 0;
-  int kind = 0;    // 0: split-K kernel (32x32 tiles); 1: LDS-staged B kernel (64-column tiles, K <= 128)
+  int kind = 0;    // GEMM_SPLITK / GEMM_LDS32 / GEMM_LDS64 (set when the stage is uploaded)
+  int slot1 = 0;   // some segment accumulates into slot 1
 };
-constexpr int BS_K = 128;          // max K per segment of the LDS-staged kernel
-constexpr int BS_COLS = 64;        // output columns per workgroup tile
-constexpr int BS_ROWS = 64;        // output rows per sub-tile (4 waves x 16)
+enum GemmKind { GEMM_SPLITK = 0, GEMM_LDS32 = 1, GEMM_LDS64 = 2 };
+
+// Point-block correction of the volume system as Q^T Q with Q = L^{-1} G_bp
+// (n_b x N, row-major), used for one right-hand side when Q is small enough
+// to stay resident (it replaces the cross-block Kronecker products and the
+// point-block triangular solves of every operator application).
+constexpr i64 QFORM_MAX_BYTES = 256LL << 20;
+inline bool qform_ok(i64 N, i64 nb) { return nb > 0 && 8 * N * nb <= QFORM_MAX_BYTES; }
 
 // Caching device allocator shared by the handles of one server: released
 // blocks are kept and reused (best fit within 2x), so a serving loop in steady
@@ -167,8 +173,7 @@ struct GramTerm {          // merged volume-Gram term
 // ---- kernels / launchers (kernels.hip) --------------------------------------
 hipError_t launch_factor(int kind, int p, int q, int n1, const double* a1, int n2, const double* a2,
                          double ell, double scale, double* out, i64 ld, hipStream_t s);
-hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s);       // split-K, 4 waves / tile
-hipError_t launch_gemm_stage_lds(Elt elt, const Stage& st, hipStream_t s);   // LDS-staged, 1 wave / tile
+hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s);   // kernel chosen by st.kind
 hipError_t launch_scale(Elt elt, const void* src, i64 src_stride, const void* coef, void* dst, i64 dst_stride, i64 n,
                         int nrhs, hipStream_t s);
 hipError_t launch_axpby(i64 n, double a, const double* x, double b, double* y, hipStream_t s);
@@ -191,6 +196,14 @@ constexpr int SMALL_GINV_MAX = 512;
 hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const double* Lt, const double* Linvt,
                              const double* U, double* W, hipStream_t s);
 hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s);
+// Streaming products with a row-major nr x N matrix M:
+//   rows_dot:    out[j] = (sum_k M[j][k] x[k]) / (eta ? eta[j] : 1)
+//   cols_update: out[c] = base[c] - sum_j M[j][c] u[j] (and out2[c] = out[c] if out2);
+//                with M2: out3[c] = base2[c] - sum_j M2[j][c] u[j].   base may alias out.
+hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, const double* eta, double* out,
+                           hipStream_t s);
+hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, const double* base, double* out,
+                              double* out2, const double* M2, const double* base2, double* out3, hipStream_t s);
 // y[i] = add[i] + alpha * sum_k M[i][k] x[k] over k <= i (upper = 0) or k >= i (upper = 1)
 hipError_t launch_trmv_rows(int n, const double* M, const double* x, double* y, double alpha, const double* add,
                             int upper, hipStream_t s);
@@ -220,6 +233,7 @@ struct gpfvm_sop {
   gpfvm::Plan pp, bp, pb;           // pp: float64 or float32; bp, pb: float64
   std::vector<gpfvm::Stage> ginv;   // W = G_bb^{-1} U (six stages)
   bool ginv_small = false;          // one-workgroup kernel instead of the stages
+  bool qform = false;               // correction as Q^T (Q x) with the handle's Q
   gpfvm::Plan front;                // pp and bp merged into shared launches
   double flops_pp = 0;
 };
@@ -253,8 +267,9 @@ struct gpfvm_handle {
   std::vector<std::vector<std::array<gpfvm::Factor, 3>>> Qfac;   // [group][term][dim]
   double* L = nullptr;             // n_b x n_b Cholesky factor of G_bb (lower)
   double* Linv = nullptr;          // n_b x n_b L^{-1} (lower)
-  double* Lt = nullptr;            // L^T and L^{-T} (small point blocks only)
+  double* Lt = nullptr;            // row-major copies of L^T and L^{-T}
   double* Linvt = nullptr;
+  double* Qc = nullptr;            // n_b x N: L^{-1} G_bp (built on first use when qform_ok)
   float* Linv_f = nullptr;
   gpfvm::GramMeta* meta = nullptr;   // device
   gpfvm::KronOp op_pp, op_pp32;
@@ -276,7 +291,6 @@ struct gpfvm_handle {
   double* Qd = nullptr;            // S applied to the directions (two-pass projection)
   double* eta = nullptr;           // max_iter
   double* vec = nullptr;           // solver vectors (r, s, z, d, ...), 8 * N
-  double* red = nullptr;           // reorthogonalisation partials (RCHUNK x max_iter)
   double* aux = nullptr;           // dot partials and coefficients
   double* scal = nullptr;          // device scalars
   int* flag = nullptr;             // device flags

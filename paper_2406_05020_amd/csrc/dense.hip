@@ -200,43 +200,28 @@ bool desc_in_bounds(const GemmDesc& D, size_t es) {
   return true;
 }
 
-// C^T = B^T A^T: the same product with operands swapped and every view transposed.
-static GemmDesc transposed(const GemmDesc& D) {
-  GemmDesc T = D;
-  T.M = D.N; T.N = D.M;
-  T.c_rs = D.c_cs; T.c_cs = D.c_rs;
-  T.e_rs = D.e_cs; T.e_cs = D.e_rs;
-  T.x_rs = D.x_cs; T.x_cs = D.x_rs;
-  for (int g = 0; g < D.nseg; ++g) {
-    const Seg& S = D.seg[g];
-    Seg& U = T.seg[g];
-    U.A = S.B; U.a_rs = S.b_cs; U.a_cs = S.b_rs; U.a_bs = S.b_bs;
-    U.B = S.A; U.b_rs = S.a_cs; U.b_cs = S.a_rs; U.b_bs = S.a_bs;
-  }
-  return T;
-}
-
-// Pick the kernel of a stage.  The LDS-staged kernel keeps a K x 64 slab of B
-// in LDS and streams A from memory; it serves mode products whose contracted
-// dimension is a 1-D factor size (K <= 128).  A descriptor is transposed when
-// that puts the larger operand in A (more rows per workgroup, B slab reused).
+// Pick the kernel of a stage (sizes measured on the advection-diffusion and
+// wave volume operators).  Long reductions over few tiles (K beyond 2048:
+// GEMV-shaped projections, point-block products) stay on the split-K kernel,
+// whose four wavefronts share the K range of a 32x32 tile.  Everything else
+// runs LDS-tiled: 64x64 tiles once there are at least 256 of them, else
+// 32x32 tiles.
 void choose_kernel(Stage& st) {
-  st.kind = 0;
+  st.kind = GEMM_SPLITK;
+  st.slot1 = 0;
   if (st.descs.empty()) return;
-  i64 tiles32 = 0;
+  i64 tiles64 = 0, kmax = 0;
   for (auto& D : st.descs) {
-    if (D.lower_only) return;
-    for (int g = 0; g < D.nseg; ++g)
-      if (D.seg[g].tri != 0 || D.seg[g].K > BS_K || D.seg[g].K < 1) return;
-    tiles32 += (i64)((D.M + TILE - 1) / TILE) * ((D.N + TILE - 1) / TILE) * D.batch;
+    i64 ksum = 0;
+    for (int g = 0; g < D.nseg; ++g) {
+      ksum += D.seg[g].K;
+      if (D.seg[g].slot) st.slot1 = 1;
+    }
+    kmax = std::max(kmax, ksum);
+    tiles64 += (i64)((D.M + 63) / 64) * ((D.N + 63) / 64) * D.batch;
   }
-  if (tiles32 < 256) return;          // small stages stay on the split-K kernel
-  for (auto& D : st.descs) {
-    if (D.N > D.M) D = transposed(D);
-    D.rsub = (D.nseg == 1) ? 4 : 1;
-    if ((i64)BS_ROWS * D.rsub > D.M) D.rsub = 1;
-  }
-  st.kind = 1;
+  if (kmax > 2048) return;
+  st.kind = tiles64 >= 256 ? GEMM_LDS64 : GEMM_LDS32;
 }
 
 // Upload a list of stages whose descriptors are consecutive in one buffer.
@@ -256,14 +241,9 @@ hipError_t upload_stages(std::vector<Stage>& stages, Arena& arena, hipStream_t s
     choose_kernel(st);
     st.tiles = 0;
     for (auto& D : st.descs) {
-      if (st.kind == 1) {
-        const int rows = BS_ROWS * D.rsub;
-        D.tiles_m = (D.M + rows - 1) / rows;
-        D.tiles_n = (D.N + BS_COLS - 1) / BS_COLS;
-      } else {
-        D.tiles_m = (D.M + TILE - 1) / TILE;
-        D.tiles_n = (D.N + TILE - 1) / TILE;
-      }
+      const int t = st.kind == GEMM_LDS64 ? 64 : 32;
+      D.tiles_m = (D.M + t - 1) / t;
+      D.tiles_n = (D.N + t - 1) / t;
       D.tile_begin = st.tiles;
       st.tiles += (i64)D.tiles_m * D.tiles_n * D.batch;
     }

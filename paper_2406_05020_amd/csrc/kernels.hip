@@ -81,8 +81,9 @@ hipError_t launch_factor(int kind, int p, int q, int n1, const double* a1, int n
 }
 
 // ============================================================================
-// Grouped GEMM on MFMA.  One wavefront per 32x32 output tile (2x2 blocks of
-// the 16x16x4 MFMA), K staged through LDS 16 at a time.
+// Grouped GEMM on MFMA (descriptor semantics in common.h).  Two kernels share
+// the descriptor format: an LDS-tiled one for stages with many output tiles
+// and short K, and a split-K one for long reductions over few tiles.
 // Lane layout of the 16x16x4 MFMA (f64 and f32): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16].  Accumulator register i of lane l
 // holds D[row][l % 16] with row = 4 * (l / 16) + i for f32 but
@@ -103,124 +104,6 @@ template <> struct MfmaOp<float> {
   }
   static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
 };
-
-constexpr int KB = 16;
-
-template <typename T>
-__global__ __launch_bounds__(64) void k_gemm(const GemmDesc* __restrict__ descs, int ndesc) {
-  typedef typename MfmaOp<T>::v4 v4;
-  __shared__ T As[TILE][KB + 1];
-  __shared__ T Bs[KB][TILE + 1];
-
-  const i64 tile = blockIdx.x;
-  int lo = 0, hi = ndesc - 1;
-  while (lo < hi) {                      // last descriptor with tile_begin <= tile
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
-  }
-  const GemmDesc& D = descs[lo];
-  const i64 local = tile - D.tile_begin;
-  const int tn = (int)(local % D.tiles_n);
-  const i64 rest = local / D.tiles_n;
-  const int tm = (int)(rest % D.tiles_m);
-  const i64 b = rest / D.tiles_m;
-  if (b >= D.batch) return;
-  if (D.lower_only && tn > tm) return;
-  const int m0 = tm * TILE, n0 = tn * TILE;
-  const int M = D.M, N = D.N;
-  const int lane = threadIdx.x;
-  const int lr = lane & 15, lk = lane >> 4;
-
-  v4 acc0[2][2], acc1[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      for (int r = 0; r < 4; ++r) { acc0[i][j][r] = 0; acc1[i][j][r] = 0; }
-  bool used1 = false;
-
-  for (int g = 0; g < D.nseg; ++g) {
-    const Seg& S = D.seg[g];
-    const T* __restrict__ A = reinterpret_cast<const T*>(S.A) + b * S.a_bs;
-    const T* __restrict__ B = reinterpret_cast<const T*>(S.B) + b * S.b_bs;
-    const T alpha = (T)S.alpha;
-    int kbeg = 0, kend = S.K;
-    if (S.tri == 1) kend = min(S.K, m0 + TILE);          // A lower-triangular
-    else if (S.tri == 2) kbeg = m0;                      // A upper-triangular
-    else if (S.tri == 3) kend = min(S.K, n0 + TILE);     // B upper-triangular (B[k][n] = 0 for k > n)
-    else if (S.tri == 4) kbeg = n0;                      // B lower-triangular (B[k][n] = 0 for k < n)
-    const bool a_rowfast = (S.a_cs == 1) || (S.a_rs != 1);
-    const bool b_colfast = (S.b_cs == 1) || (S.b_rs != 1);
-    for (int k0 = kbeg; k0 < kend; k0 += KB) {
-      // A tile: TILE x KB
-#pragma unroll
-      for (int j = 0; j < (TILE * KB) / 64; ++j) {
-        const int e = lane + 64 * j;
-        int r, c;
-        if (a_rowfast) { r = e / KB; c = e % KB; } else { r = e % TILE; c = e / TILE; }
-        const int gr = m0 + r, gc = k0 + c;
-        T val = 0;
-        if (gr < M && gc < kend) val = alpha * A[(i64)gr * S.a_rs + (i64)gc * S.a_cs];
-        As[r][c] = val;
-      }
-      // B tile: KB x TILE
-#pragma unroll
-      for (int j = 0; j < (TILE * KB) / 64; ++j) {
-        const int e = lane + 64 * j;
-        int r, c;
-        if (b_colfast) { r = e / TILE; c = e % TILE; } else { r = e % KB; c = e / KB; }
-        const int gr = k0 + r, gc = n0 + c;
-        T val = 0;
-        if (gr < kend && gc < N) val = B[(i64)gr * S.b_rs + (i64)gc * S.b_cs];
-        Bs[r][c] = val;
-      }
-      __syncthreads();
-      if (S.slot == 0) {
-#pragma unroll
-        for (int kk = 0; kk < KB / 4; ++kk) {
-          const T a0 = As[lr][kk * 4 + lk], a1 = As[16 + lr][kk * 4 + lk];
-          const T b0 = Bs[kk * 4 + lk][lr], b1 = Bs[kk * 4 + lk][16 + lr];
-          acc0[0][0] = MfmaOp<T>::mac(a0, b0, acc0[0][0]);
-          acc0[0][1] = MfmaOp<T>::mac(a0, b1, acc0[0][1]);
-          acc0[1][0] = MfmaOp<T>::mac(a1, b0, acc0[1][0]);
-          acc0[1][1] = MfmaOp<T>::mac(a1, b1, acc0[1][1]);
-        }
-      } else {
-        used1 = true;
-#pragma unroll
-        for (int kk = 0; kk < KB / 4; ++kk) {
-          const T a0 = As[lr][kk * 4 + lk], a1 = As[16 + lr][kk * 4 + lk];
-          const T b0 = Bs[kk * 4 + lk][lr], b1 = Bs[kk * 4 + lk][16 + lr];
-          acc1[0][0] = MfmaOp<T>::mac(a0, b0, acc1[0][0]);
-          acc1[0][1] = MfmaOp<T>::mac(a0, b1, acc1[0][1]);
-          acc1[1][0] = MfmaOp<T>::mac(a1, b0, acc1[1][0]);
-          acc1[1][1] = MfmaOp<T>::mac(a1, b1, acc1[1][1]);
-        }
-      }
-      __syncthreads();
-    }
-  }
-
-  T* __restrict__ C = reinterpret_cast<T*>(D.C) + b * D.c_bs;
-  const T* __restrict__ X = D.X ? reinterpret_cast<const T*>(D.X) + b * D.x_bs : nullptr;
-  const double* __restrict__ E = D.escale ? D.escale + b * D.e_bs : nullptr;
-  const T beta = (T)D.beta, gamma = (T)D.gamma;
-#pragma unroll
-  for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-    for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + bm * 16 + MfmaOp<T>::row(lk, r);
-        const int col = n0 + bn * 16 + lr;
-        if (row < M && col < N && !(D.lower_only && col > row)) {
-          T v = acc0[bm][bn][r];
-          if (used1 && E) v += (T)E[(i64)row * D.e_rs + (i64)col * D.e_cs] * acc1[bm][bn][r];
-          if (X) v += gamma * X[(i64)row * D.x_rs + (i64)col * D.x_cs];
-          T* cp = C + (i64)row * D.c_rs + (i64)col * D.c_cs;
-          if (beta != (T)0) v += beta * *cp;
-          *cp = v;
-        }
-      }
-}
 
 // ----------------------------------------------------------------------------
 // Split-K variant: four wavefronts share one 32x32 output tile and split its K
@@ -383,15 +266,27 @@ __global__ __launch_bounds__(64 * SK_WAVES) void k_gemm_sk(const GemmDesc* __res
 }
 
 // ----------------------------------------------------------------------------
-// LDS-staged variant for mode products (K <= 128 per segment).  A workgroup
-// owns 64 output columns and rsub sub-tiles of 64 rows; for each segment the
-// K x 64 slab of B is staged in LDS once and reused by every row sub-tile,
-// while each wavefront streams its 16 rows of A straight into MFMA registers.
+// LDS-tiled variant.  A workgroup owns a BM x BN output tile and has one
+// wavefront per 16x16 block of it.  K advances in chunks of 16: the threads
+// load the next chunk of both operands into registers (coalesced along
+// whichever index is contiguous) while the MFMAs consume the current chunk
+// from the other half of a double-buffered LDS tile; one barrier per chunk.
+// Triangular segments restrict the chunk range to the blocks that can be
+// nonzero for this tile (the zero triangle must hold zeros), and lower_only
+// skips tiles above the diagonal (BM == BN).
 // ----------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_bs(const GemmDesc* __restrict__ descs, int ndesc) {
+constexpr int LK = 16;
+
+template <typename T, int BM, int BN, bool SLOT1>
+__global__ __launch_bounds__(4 * BM * BN / 16) void k_gemm_lds(const GemmDesc* __restrict__ descs, int ndesc) {
   typedef typename MfmaOp<T>::v4 v4;
-  __shared__ T Bs[BS_K][BS_COLS + 1];
+  constexpr int WNN = BN / 16, NT = 4 * BM * BN / 16;
+  constexpr int EA = BM * LK / NT, EB = LK * BN / NT;
+  static_assert(EA * NT == BM * LK && EB * NT == LK * BN, "tile shape");
+  constexpr int NS = SLOT1 ? 2 : 1;
+  __shared__ T As[2][LK][BM + 1];
+  __shared__ T Bs[2][LK][BN + 1];
+
   const i64 tile = blockIdx.x;
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
@@ -405,116 +300,125 @@ __global__ __launch_bounds__(256) void k_gemm_bs(const GemmDesc* __restrict__ de
   const int tm = (int)(rest % D.tiles_m);
   const i64 b = rest / D.tiles_m;
   if (b >= D.batch) return;
+  if (D.lower_only && tn > tm) return;
   const int M = D.M, N = D.N;
-  const int n0 = tn * BS_COLS;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int lr = lane & 15, lk = lane >> 4;
-  const int rsub = D.rsub > 0 ? D.rsub : 1;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  const int rb = (wave / WNN) * 16, cb = (wave % WNN) * 16;
+
+  v4 acc[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[q][r] = 0;
+
+  for (int g = 0; g < D.nseg; ++g) {
+    const Seg& S = D.seg[g];
+    const T* __restrict__ A = reinterpret_cast<const T*>(S.A) + b * S.a_bs;
+    const T* __restrict__ B = reinterpret_cast<const T*>(S.B) + b * S.b_bs;
+    const T alpha = (T)S.alpha;
+    int kbeg = 0, kend = S.K;
+    if (S.tri == 1) kend = min(S.K, m0 + BM);
+    else if (S.tri == 2) kbeg = m0;
+    else if (S.tri == 3) kend = min(S.K, n0 + BN);
+    else if (S.tri == 4) kbeg = n0;
+    if (kbeg >= kend) continue;                    // uniform over the workgroup
+    const bool akf = (S.a_cs == 1), bnf = (S.b_cs == 1);
+    const int q = SLOT1 ? S.slot : 0;
+    T ra[EA], rbv[EB];
+    auto gload = [&](int kc) {
+#pragma unroll
+      for (int u = 0; u < EA; ++u) {
+        const int e = tid + NT * u;
+        int k, m;
+        if (akf) { k = e % LK; m = e / LK; } else { m = e % BM; k = e / BM; }
+        ra[u] = (m0 + m < M && kc + k < kend) ? A[(i64)(m0 + m) * S.a_rs + (i64)(kc + k) * S.a_cs] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < EB; ++u) {
+        const int e = tid + NT * u;
+        int k, n;
+        if (bnf) { n = e % BN; k = e / BN; } else { k = e % LK; n = e / LK; }
+        rbv[u] = (n0 + n < N && kc + k < kend) ? B[(i64)(kc + k) * S.b_rs + (i64)(n0 + n) * S.b_cs] : (T)0;
+      }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+      for (int u = 0; u < EA; ++u) {
+        const int e = tid + NT * u;
+        int k, m;
+        if (akf) { k = e % LK; m = e / LK; } else { m = e % BM; k = e / BM; }
+        As[buf][k][m] = alpha * ra[u];
+      }
+#pragma unroll
+      for (int u = 0; u < EB; ++u) {
+        const int e = tid + NT * u;
+        int k, n;
+        if (bnf) { n = e % BN; k = e / BN; } else { k = e % LK; n = e / LK; }
+        Bs[buf][k][n] = rbv[u];
+      }
+    };
+    __syncthreads();                               // previous segment's reads of buffer 0 are done
+    gload(kbeg);
+    sstore(0);
+    __syncthreads();
+    int buf = 0;
+    for (int kc = kbeg; kc < kend; kc += LK) {
+      const bool more = kc + LK < kend;
+      if (more) gload(kc + LK);
+#pragma unroll
+      for (int kk = 0; kk < LK; kk += 4) {
+        const T av = As[buf][kk + lk][rb + lr];
+        const T bv = Bs[buf][kk + lk][cb + lr];
+        if (q == 0) acc[0] = MfmaOp<T>::mac(av, bv, acc[0]);
+        else acc[NS - 1] = MfmaOp<T>::mac(av, bv, acc[NS - 1]);
+      }
+      if (more) sstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
   T* __restrict__ C = reinterpret_cast<T*>(D.C) + b * D.c_bs;
   const T* __restrict__ X = D.X ? reinterpret_cast<const T*>(D.X) + b * D.x_bs : nullptr;
   const double* __restrict__ E = D.escale ? D.escale + b * D.e_bs : nullptr;
   const T beta = (T)D.beta, gamma = (T)D.gamma;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = m0 + rb + MfmaOp<T>::row(lk, r);
+    const int col = n0 + cb + lr;
+    if (row < M && col < N && !(D.lower_only && col > row)) {
+      T v = acc[0][r];
+      if (SLOT1 && E) v += (T)E[(i64)row * D.e_rs + (i64)col * D.e_cs] * acc[NS - 1][r];
+      if (X) v += gamma * X[(i64)row * D.x_rs + (i64)col * D.x_cs];
+      T* cp = C + (i64)row * D.c_rs + (i64)col * D.c_cs;
+      if (beta != (T)0) v += beta * *cp;
+      *cp = v;
+    }
+  }
+}
 
-  // single-segment descriptors: stage the slab once for all row sub-tiles
-  const bool one = (D.nseg == 1);
-  auto stage_slab = [&](const Seg& S) {
-    const T* __restrict__ B = reinterpret_cast<const T*>(S.B) + b * S.b_bs;
-    const int K = S.K, K4 = (K + 3) & ~3;
-    const bool kfast = (S.b_rs == 1 && S.b_cs != 1);
-    for (int e = threadIdx.x; e < K4 * BS_COLS; e += 256) {
-      int k, c;
-      if (kfast) { k = e % K4; c = e / K4; } else { k = e / BS_COLS; c = e % BS_COLS; }
-      const int col = n0 + c;
-      T v = 0;
-      if (k < K && col < N) v = B[(i64)k * S.b_rs + (i64)col * S.b_cs];
-      Bs[k][c] = v;
-    }
-  };
-  if (one) {
-    stage_slab(D.seg[0]);
-    __syncthreads();
-  }
-  for (int sub = 0; sub < rsub; ++sub) {
-    const int m0 = (tm * rsub + sub) * BS_ROWS;
-    if (m0 >= M) break;
-    const int row = m0 + wave * 16 + lr;
-    v4 acc[2][4];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[s][j][r] = 0;
-    bool used1 = false;
-    for (int g = 0; g < D.nseg; ++g) {
-      const Seg& S = D.seg[g];
-      if (!one) {
-        __syncthreads();
-        stage_slab(S);
-        __syncthreads();
-      }
-      const T* __restrict__ A = reinterpret_cast<const T*>(S.A) + b * S.a_bs;
-      const T alpha = (T)S.alpha;
-      const int K = S.K, steps = (K + 3) >> 2;
-      const bool rin = row < M;
-      if (S.slot) used1 = true;
-      T a_cur = (rin && lk < K) ? alpha * A[(i64)row * S.a_rs + (i64)lk * S.a_cs] : (T)0;
-      for (int st = 0; st < steps; ++st) {
-        const int kn = 4 * (st + 1) + lk;
-        const T a_nxt = (st + 1 < steps && rin && kn < K) ? alpha * A[(i64)row * S.a_rs + (i64)kn * S.a_cs] : (T)0;
-        const int kr = 4 * st + lk;
-        if (S.slot == 0) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[0][j] = MfmaOp<T>::mac(a_cur, Bs[kr][j * 16 + lr], acc[0][j]);
-        } else {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[1][j] = MfmaOp<T>::mac(a_cur, Bs[kr][j * 16 + lr], acc[1][j]);
-        }
-        a_cur = a_nxt;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int orow = m0 + wave * 16 + MfmaOp<T>::row(lk, r);
-        const int col = n0 + j * 16 + lr;
-        if (orow < M && col < N) {
-          T v = acc[0][j][r];
-          if (used1 && E) v += (T)E[(i64)orow * D.e_rs + (i64)col * D.e_cs] * acc[1][j][r];
-          if (X) v += gamma * X[(i64)orow * D.x_rs + (i64)col * D.x_cs];
-          T* cp = C + (i64)orow * D.c_rs + (i64)col * D.c_cs;
-          if (beta != (T)0) v += beta * *cp;
-          *cp = v;
-        }
-      }
-  }
+template <typename T, int BM>
+static void launch_lds(const Stage& st, int nd, hipStream_t s) {
+  const dim3 grid((unsigned)st.tiles), block(4 * BM * BM / 16);
+  if (st.slot1)
+    k_gemm_lds<T, BM, BM, true><<<grid, block, 0, s>>>(st.d_descs, nd);
+  else
+    k_gemm_lds<T, BM, BM, false><<<grid, block, 0, s>>>(st.d_descs, nd);
 }
 
 hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
   if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
   const int nd = (int)st.descs.size();
-  if (st.kind == 1) {
-    if (elt == F64)
-      k_gemm_bs<double><<<dim3((unsigned)st.tiles), dim3(256), 0, s>>>(st.d_descs, nd);
-    else
-      k_gemm_bs<float><<<dim3((unsigned)st.tiles), dim3(256), 0, s>>>(st.d_descs, nd);
-    return hipGetLastError();
-  }
-  if (elt == F64)
+  if (st.kind == GEMM_LDS64) {
+    if (elt == F64) launch_lds<double, 64>(st, nd, s); else launch_lds<float, 64>(st, nd, s);
+  } else if (st.kind == GEMM_LDS32) {
+    if (elt == F64) launch_lds<double, 32>(st, nd, s); else launch_lds<float, 32>(st, nd, s);
+  } else if (elt == F64) {
     k_gemm_sk<double><<<dim3((unsigned)st.tiles), dim3(64 * SK_WAVES), 0, s>>>(st.d_descs, nd);
-  else
+  } else {
     k_gemm_sk<float><<<dim3((unsigned)st.tiles), dim3(64 * SK_WAVES), 0, s>>>(st.d_descs, nd);
-  return hipGetLastError();
-}
-
-hipError_t launch_gemm_stage_lds(Elt elt, const Stage& st, hipStream_t s) {
-  if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
-  const int nd = (int)st.descs.size();
-  if (elt == F64)
-    k_gemm<double><<<dim3((unsigned)st.tiles), dim3(64), 0, s>>>(st.d_descs, nd);
-  else
-    k_gemm<float><<<dim3((unsigned)st.tiles), dim3(64), 0, s>>>(st.d_descs, nd);
+  }
   return hipGetLastError();
 }
 
@@ -741,6 +645,105 @@ hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const 
                              const double* U, double* W, hipStream_t s) {
   if (nb < 1 || nb > SMALL_GINV_MAX) return hipErrorInvalidValue;
   k_ginv_small<<<1, GS_THREADS, 0, s>>>(nb, L, Linv, Lt, Linvt, U, W);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Streaming products with a row-major r x N matrix M (the resident point
+// correction Q, the stored IterGP directions D and their images S D).
+//
+// rows_dot:    out[j] = sum_k M[j][k] x[k]  (divided by eta[j] when given).
+//   One 1024-thread workgroup per row streams it contiguously with two
+//   independent accumulators; fixed-order wavefront and workgroup reductions.
+// cols_update: out[c] = base[c] - sum_j M[j][c] u[j]  (also into out2), and
+//   optionally out3[c] = base2[c] - sum_j M2[j][c] u[j] with the same u.
+//   A 1024-thread workgroup owns 64 columns; its 16 wavefronts take every
+//   16th row (64 contiguous doubles per load), u is staged through LDS in
+//   blocks, and the 16 partial sums are added in a fixed order.
+// Both are deterministic; base may alias out.
+// ----------------------------------------------------------------------------
+constexpr int CU_WAVES = 16;
+constexpr int CU_BLK = 2048;
+
+__global__ __launch_bounds__(1024) void k_rows_dot(i64 N, const double* __restrict__ M, const double* __restrict__ x,
+                                                   const double* __restrict__ eta, double* __restrict__ out) {
+  __shared__ double red[16];
+  const double* __restrict__ q = M + (i64)blockIdx.x * N;
+  double a0 = 0.0, a1 = 0.0;
+  i64 c = threadIdx.x;
+  for (; c + 1024 < N; c += 2048) {
+    a0 = fma(q[c], x[c], a0);
+    a1 = fma(q[c + 1024], x[c + 1024], a1);
+  }
+  if (c < N) a0 = fma(q[c], x[c], a0);
+  double v = a0 + a1;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < 16; ++w) s += red[w];
+    out[blockIdx.x] = eta ? s / eta[blockIdx.x] : s;
+  }
+}
+
+template <bool TWO>
+__global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, const double* __restrict__ M,
+                                                               const double* __restrict__ u, const double* base,
+                                                               double* out, double* out2, const double* __restrict__ M2,
+                                                               const double* base2, double* out3) {
+  __shared__ double us[CU_BLK];
+  __shared__ double part[CU_WAVES][64];
+  __shared__ double part2[TWO ? CU_WAVES : 1][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const i64 c = (i64)blockIdx.x * 64 + lane;
+  double acc = 0.0, acc2 = 0.0;
+  for (int j0 = 0; j0 < nr; j0 += CU_BLK) {
+    const int jn = min(CU_BLK, nr - j0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < jn; i += 64 * CU_WAVES) us[i] = u[j0 + i];
+    __syncthreads();
+    if (c < N) {
+#pragma unroll 4
+      for (int i = wave; i < jn; i += CU_WAVES) {
+        const i64 off = (i64)(j0 + i) * N + c;
+        acc = fma(M[off], us[i], acc);
+        if (TWO) acc2 = fma(M2[off], us[i], acc2);
+      }
+    }
+  }
+  part[wave][lane] = acc;
+  if (TWO) part2[wave][lane] = acc2;
+  __syncthreads();
+  if (wave == 0 && c < N) {
+    double s = 0.0;
+    for (int w = 0; w < CU_WAVES; ++w) s += part[w][lane];
+    const double v = base[c] - s;
+    out[c] = v;
+    if (out2) out2[c] = v;
+    if (TWO) {
+      double s2 = 0.0;
+      for (int w = 0; w < CU_WAVES; ++w) s2 += part2[w][lane];
+      out3[c] = base2[c] - s2;
+    }
+  }
+}
+
+hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, const double* eta, double* out,
+                           hipStream_t s) {
+  if (nr <= 0 || N <= 0) return hipSuccess;
+  k_rows_dot<<<dim3((unsigned)nr), dim3(1024), 0, s>>>(N, M, x, eta, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, const double* base, double* out,
+                              double* out2, const double* M2, const double* base2, double* out3, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((N + 63) / 64)), block(64 * CU_WAVES);
+  if (M2)
+    k_cols_update<true><<<grid, block, 0, s>>>(nr, N, M, u, base, out, out2, M2, base2, out3);
+  else
+    k_cols_update<false><<<grid, block, 0, s>>>(nr, N, M, u, base, out, out2, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 

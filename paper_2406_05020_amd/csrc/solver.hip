@@ -33,102 +33,6 @@ using namespace gpfvm;
 
 namespace {
 
-constexpr int RCHUNK = 256;        // max chunks of N in the reorthogonalisation dots
-constexpr int RJ = 8;              // directions per block in the dots
-constexpr int JSPLIT = 16;         // max direction ranges in the direction sums
-
-int dot_chunks(i64 N) { return (int)std::max<i64>(1, std::min<i64>(RCHUNK, (N + 1023) / 1024)); }
-int jsplit_of(int nd) { return std::max(1, std::min(JSPLIT, (nd + 15) / 16)); }
-
-// partial[j * nch + c] = sum_{k in chunk c} D[j][k] z[k],  j < nd
-__global__ __launch_bounds__(256) void k_reorth_dots(const double* __restrict__ D, i64 N, int nd, int nch,
-                                                     const double* __restrict__ z, double* __restrict__ partial) {
-  const int c = blockIdx.x, j0 = blockIdx.y * RJ;
-  const i64 len = (N + nch - 1) / nch;
-  const i64 k0 = c * len, k1 = min(N, k0 + len);
-  double acc[RJ];
-#pragma unroll
-  for (int j = 0; j < RJ; ++j) acc[j] = 0;
-  for (i64 k = k0 + threadIdx.x; k < k1; k += 256) {
-    const double zk = z[k];
-#pragma unroll
-    for (int j = 0; j < RJ; ++j)
-      if (j0 + j < nd) acc[j] += D[(i64)(j0 + j) * N + k] * zk;
-  }
-  __shared__ double red[RJ][4];
-#pragma unroll
-  for (int j = 0; j < RJ; ++j) {
-    double v = acc[j];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((threadIdx.x & 63) == 0) red[j][threadIdx.x >> 6] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < RJ && j0 + (int)threadIdx.x < nd) {
-    const int j = threadIdx.x;
-    partial[(i64)(j0 + j) * nch + c] = red[j][0] + red[j][1] + red[j][2] + red[j][3];
-  }
-}
-
-// coef[j] = (sum_c partial[j][c]) / eta[j]   (one wavefront per direction)
-__global__ __launch_bounds__(256) void k_reorth_coef(const double* __restrict__ partial,
-                                                     const double* __restrict__ eta, int nd, int nch,
-                                                     double* __restrict__ coef) {
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (j >= nd) return;
-  double s = 0;
-  for (int c = lane; c < nch; c += 64) s += partial[(i64)j * nch + c];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) coef[j] = s / eta[j];
-}
-
-// part[js][k] = sum_{j in range js} coef[j] D[j][k]  (and the same with Q)
-__global__ __launch_bounds__(256) void k_dir_partial(const double* __restrict__ D, const double* __restrict__ Q,
-                                                     i64 N, int nd, int js_n, const double* __restrict__ coef,
-                                                     double* __restrict__ pd, double* __restrict__ pw) {
-  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  const int js = blockIdx.y;
-  if (k >= N) return;
-  const int per = (nd + js_n - 1) / js_n;
-  const int j0 = js * per, j1 = min(nd, j0 + per);
-  double a = 0, b = 0;
-  if (Q) {
-    for (int j = j0; j < j1; ++j) {
-      const double c = coef[j];
-      a += c * D[(i64)j * N + k];
-      b += c * Q[(i64)j * N + k];
-    }
-    pw[(i64)js * N + k] = b;
-  } else {
-    for (int j = j0; j < j1; ++j) a += coef[j] * D[(i64)j * N + k];
-  }
-  pd[(i64)js * N + k] = a;
-}
-
-// d = X - sum_js pd ; X = d
-__global__ void k_reorth_finish_x(i64 N, int js_n, const double* __restrict__ pd, double* __restrict__ X,
-                                  double* __restrict__ d) {
-  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N) return;
-  double v = X[k];
-  for (int js = 0; js < js_n; ++js) v -= pd[(i64)js * N + k];
-  d[k] = v;
-  X[k] = v;
-}
-
-// d -= sum_js pd ; w = Y - sum_js pw
-__global__ void k_reorth_finish2y(i64 N, int js_n, const double* __restrict__ pd, const double* __restrict__ pw,
-                                  double* __restrict__ d, const double* __restrict__ Y, double* __restrict__ w) {
-  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N) return;
-  double dv = d[k], wv = Y[k];
-  for (int js = 0; js < js_n; ++js) {
-    dv -= pd[(i64)js * N + k];
-    wv -= pw[(i64)js * N + k];
-  }
-  d[k] = dv;
-  w[k] = wv;
-}
-
 // guarded update (two-pass form): a = (s.r)/eta with s = r so s.r = scal[0];
 // v += a d ; r -= a w ; X = r ; store d, w, eta ; count the iteration
 __global__ void k_update2x(i64 N, const double* __restrict__ d, const double* __restrict__ w, double* __restrict__ v,
@@ -319,6 +223,49 @@ hipError_t gpfvm::run_stages(const std::vector<Stage>& st, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Q = L^{-1} G_bp (n_b x N, row-major), so that the point-block correction of
+// the volume system is G_pb G_bb^{-1} G_bp = Q^T Q, symmetric by construction.
+// G_bp comes from the closed-form Gram-entry kernel; the triangular solve is
+// the explicit inverse with one residual correction, Q += L^{-1} (G_bp - L Q),
+// which is backward stable where the inverse alone is not.
+// ---------------------------------------------------------------------------
+static int build_qc(gpfvm_handle* h, hipStream_t s) {
+  if (h->Qc) return GPFVM_OK;
+  const i64 N = h->N;
+  const int nb = h->nb;
+  const size_t bytes = (size_t)nb * N * sizeof(double);
+  double* Q = (double*)h->arena.alloc(bytes);
+  Arena tmp;
+  tmp.cache = h->arena.cache;
+  double* G = (double*)tmp.alloc(bytes);
+  double* R = (double*)tmp.alloc(bytes);
+  if (!Q || !G || !R) {
+    tmp.release();
+    h->err = "out of device memory (point correction Q)";
+    return GPFVM_E_NOMEM;
+  }
+  hipError_t e = launch_gram_block(h->meta, 0, nb, nb, N, G, N, s);
+  std::vector<Stage> st(3);
+  st[0].descs.push_back(desc1(Q, N, h->Linv, nb, 1, G, N, 1, nb, (int)N, nb, 1.0, 0.0, 1));
+  {
+    GemmDesc D = desc1(R, N, h->L, nb, 1, Q, N, 1, nb, (int)N, nb, -1.0, 0.0, 1);
+    D.X = G; D.x_rs = N; D.x_cs = 1; D.gamma = 1.0;
+    st[1].descs.push_back(D);
+  }
+  st[2].descs.push_back(desc1(Q, N, h->Linv, nb, 1, R, N, 1, nb, (int)N, nb, 1.0, 1.0, 1));
+  if (e == hipSuccess) e = upload_stages(st, tmp, s);
+  if (e == hipSuccess) e = run_stages(st, s);
+  const hipError_t e2 = hipStreamSynchronize(s);
+  tmp.release();
+  if (e != hipSuccess || e2 != hipSuccess) {
+    h->err = std::string("building the point correction Q failed: ") + hipGetErrorString(e != hipSuccess ? e : e2);
+    return GPFVM_E_HIP;
+  }
+  h->Qc = Q;
+  return GPFVM_OK;
+}
+
+// ---------------------------------------------------------------------------
 // volume-system operator S for nrhs right-hand sides.  elt = F32 gives the
 // mixed operator: the volume Kronecker block in float32 (float32 factors,
 // float32 accumulation), the point-block correction in float64.
@@ -376,6 +323,11 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
       return GPFVM_E_HIP;
     }
     so->ginv_small = (nrhs == 1 && h->nb <= SMALL_GINV_MAX && h->Lt && h->Linvt);
+    if (elt == F64 && nrhs == 1 && qform_ok(N, h->nb)) {
+      rc = build_qc(h, h->stream);
+      if (rc) return rc;
+      so->qform = true;
+    }
   }
   if (elt == F64) {
     std::vector<const Plan*> parts{&so->pp};
@@ -392,6 +344,13 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
 static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
   hipError_t e;
   const i64 NN = h->N * so->nrhs;
+  if (so->qform) {                                                  // G_pp X + s2 X - Q^T Q X
+    if ((e = launch_rows_dot(h->nb, h->N, h->Qc, (const double*)so->X, nullptr, (double*)so->U, s)) != hipSuccess)
+      return e;
+    if ((e = run_plan(so->pp, s)) != hipSuccess) return e;
+    return launch_cols_update(h->nb, h->N, h->Qc, (const double*)so->U, (const double*)so->Y, (double*)so->Y, nullptr,
+                              nullptr, nullptr, nullptr, s);
+  }
   if (so->elt == F64) {
     if ((e = run_plan(so->front, s)) != hipSuccess) return e;      // G_pp X + s2 X  and  G_bp X
   } else {
@@ -456,12 +415,11 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
   h->v = (double*)h->arena.alloc(N * sizeof(double));
   h->Dd = (double*)h->arena.alloc((size_t)N * h->max_iter * sizeof(double));
   h->eta = (double*)h->arena.alloc(h->max_iter * sizeof(double));
-  h->vec = (double*)h->arena.alloc((size_t)(8 + 2 * JSPLIT) * N * sizeof(double));
-  h->red = (double*)h->arena.alloc((size_t)RCHUNK * h->max_iter * sizeof(double));
+  h->vec = (double*)h->arena.alloc((size_t)8 * N * sizeof(double));
   h->aux = (double*)h->arena.alloc((size_t)(1024 + h->max_iter) * sizeof(double));
   h->scal = (double*)h->arena.alloc(64 * sizeof(double));
   h->flag = (int*)h->arena.alloc(16 * sizeof(int));
-  if (!h->bS || !h->ab0 || !h->v || !h->Dd || !h->eta || !h->vec || !h->red || !h->aux || !h->scal || !h->flag) {
+  if (!h->bS || !h->ab0 || !h->v || !h->Dd || !h->eta || !h->vec || !h->aux || !h->scal || !h->flag) {
     h->err = "out of device memory (solver state; lower max_iter)";
     return GPFVM_E_NOMEM;
   }
@@ -502,7 +460,6 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
   double* r = h->vec;
   double* d = h->vec + 2 * N;
   double* w = h->vec + 5 * N;
-  double* partial = h->red;           // RCHUNK x max_iter
   double* dotp = h->aux;              // 512 dot partials
   double* coef = h->aux + 1024;       // max_iter reorthogonalisation coefficients
   if (passes == 2 && !h->Qd) {
@@ -522,14 +479,9 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
   hipLaunchKernelGGL(k_resid2, dim3(nblk(N)), dim3(256), 0, s, N, b, Y, r, X, (const int*)h->flag);
   int i = start;
   int hflag[2] = {0, 0};
-  const int nch = dot_chunks(N);
-  double* pd = h->vec + 8 * N;                       // JSPLIT * N
-  double* pw = h->vec + (8 + JSPLIT) * N;            // JSPLIT * N
+  // coef = eta^-1 o (D^T rhs) over the first nd stored directions
   auto project = [&](const double* rhs_vec, int nd) {
-    hipLaunchKernelGGL(k_reorth_dots, dim3(nch, (nd + RJ - 1) / RJ), dim3(256), 0, s, (const double*)h->Dd, N, nd,
-                       nch, rhs_vec, partial);
-    hipLaunchKernelGGL(k_reorth_coef, dim3((nd + 3) / 4), dim3(256), 0, s, (const double*)partial,
-                       (const double*)h->eta, nd, nch, coef);
+    return launch_rows_dot(nd, N, h->Dd, rhs_vec, h->eta, coef, s);
   };
   while (i < end) {
     const int batch_end = std::min(end, i + std::max(1, check_every));
@@ -539,23 +491,16 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
       HIPCHK(h, apply_sop(h, so, s));                         // z = S s  (in Y)
       if (passes == 1) HIPCHK(h, hipMemcpyAsync(h->vec + N, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
       if (i > 0) {                                            // d = s - D (eta^-1 o D^T z), also into X
-        project(Y, i);
-        const int jn = jsplit_of(i);
-        hipLaunchKernelGGL(k_dir_partial, dim3(nblk(N), jn), dim3(256), 0, s, (const double*)h->Dd,
-                           (const double*)nullptr, N, i, jn, (const double*)coef, pd, (double*)nullptr);
-        hipLaunchKernelGGL(k_reorth_finish_x, dim3(nblk(N)), dim3(256), 0, s, N, jn, (const double*)pd, X, d);
+        HIPCHK(h, project(Y, i));
+        HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, X, d, X, nullptr, nullptr, nullptr, s));
       } else {
         HIPCHK(h, hipMemcpyAsync(d, X, N * sizeof(double), hipMemcpyDeviceToDevice, s));
       }
       if (passes == 2) {
         HIPCHK(h, apply_sop(h, so, s));                       // w = S d  (in Y)
         if (i > 0) {
-          project(Y, i);
-          const int jn = jsplit_of(i);
-          hipLaunchKernelGGL(k_dir_partial, dim3(nblk(N), jn), dim3(256), 0, s, (const double*)h->Dd,
-                             (const double*)h->Qd, N, i, jn, (const double*)coef, pd, pw);
-          hipLaunchKernelGGL(k_reorth_finish2y, dim3(nblk(N)), dim3(256), 0, s, N, jn, (const double*)pd,
-                             (const double*)pw, d, Y, w);
+          HIPCHK(h, project(Y, i));                         // d -= D coef ; w = S d - (S D) coef
+          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, d, d, nullptr, h->Qd, Y, w, s));
         } else {
           HIPCHK(h, hipMemcpyAsync(w, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         }

@@ -39,11 +39,18 @@ def relerr(a, b):
 
 
 def test_schur_operator_matches_oracle(G, c2):
+    """nrhs = 1 applies the point correction as Q^T Q with the resident
+    Q = L^{-1} G_bp; nrhs = 2 through the cross-block Kronecker products and
+    the point-block triangular solves.  Both against the oracle's Cholesky."""
     p, o, S = c2
     rng = np.random.default_rng(5)
     X = rng.standard_normal((2, p.n_pde))
     h = G.assemble(p, max_iter=8)
     try:
+        x1 = torch.as_tensor(X[0], device="cuda:0")
+        y1 = torch.empty_like(x1)
+        G.schur_matvec(h, x1, y1, nrhs=1)
+        assert relerr(host(y1), S.matvec(X[0])) <= 1e-11
         x = torch.as_tensor(X.ravel(), device="cuda:0")
         y = torch.empty_like(x)
         G.schur_matvec(h, x, y, nrhs=2)

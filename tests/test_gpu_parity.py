@@ -221,3 +221,25 @@ def test_volume_matvec_matches_oracle(G, name, nrhs):
             assert relerr(Y[r], Gv @ X[r]) <= 1e-11
     finally:
         G.destroy(h)
+
+
+@pytest.mark.parametrize("name", list(RAGGED))
+def test_schur_matvec_matches_oracle(G, name):
+    """Volume-system operator S = G_pp + s2 I - G_pb G_bb^{-1} G_bp: one
+    right-hand side (resident Q = L^{-1} G_bp) and three (Kronecker cross
+    blocks and triangular solves), against the oracle's Cholesky solve."""
+    p = RAGGED[name]()
+    S = SchurSystem(O.Oracle(p))
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal((3, p.n_pde))
+    h = G.assemble(p, max_iter=8)
+    try:
+        for nrhs in (1, 3):
+            y = torch.empty(nrhs * p.n_pde, dtype=torch.float64, device="cuda:0")
+            G.schur_matvec(h, dev(X[:nrhs].ravel()), y, nrhs=nrhs)
+            Y = host(y).reshape(nrhs, -1)
+            for r in range(nrhs):
+                ref = S.matvec(X[r])
+                assert relerr(Y[r], ref) <= 1e-11, (nrhs, r, relerr(Y[r], ref))
+    finally:
+        G.destroy(h)
