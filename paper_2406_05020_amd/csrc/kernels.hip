@@ -266,26 +266,30 @@ __global__ __launch_bounds__(64 * SK_WAVES) void k_gemm_sk(const GemmDesc* __res
 }
 
 // ----------------------------------------------------------------------------
-// LDS-tiled variant.  A workgroup owns a BM x BN output tile and has one
-// wavefront per 16x16 block of it.  K advances in chunks of 16: the threads
-// load the next chunk of both operands into registers (coalesced along
-// whichever index is contiguous) while the MFMAs consume the current chunk
-// from the other half of a double-buffered LDS tile; one barrier per chunk.
-// Triangular segments restrict the chunk range to the blocks that can be
-// nonzero for this tile (the zero triangle must hold zeros), and lower_only
-// skips tiles above the diagonal (BM == BN).
+// LDS-tiled variant.  A workgroup owns a BM x BN output tile; its wavefronts
+// form KS groups, each with one wavefront per 16x16 block of the tile.  K
+// advances in chunks of 16 KS: the threads load the next chunk of both
+// operands into registers (coalesced along whichever index is contiguous)
+// while group g runs the MFMAs of k-rows [16 g, 16 g + 16) of the current
+// chunk from the other half of a double-buffered LDS tile; one barrier per
+// chunk.  With KS > 1 the groups' partial accumulators are summed through LDS
+// in a fixed order at the end (fewer sequential chunks for short, latency-
+// bound stages).  Triangular segments restrict the chunk range to the blocks
+// that can be nonzero for this tile (the zero triangle must hold zeros), and
+// lower_only skips tiles above the diagonal (BM == BN).
 // ----------------------------------------------------------------------------
-constexpr int LK = 16;
-
-template <typename T, int BM, int BN, bool SLOT1>
-__global__ __launch_bounds__(4 * BM * BN / 16) void k_gemm_lds(const GemmDesc* __restrict__ descs, int ndesc) {
+template <typename T, int BM, int BN, int KS, bool SLOT1>
+__global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDesc* __restrict__ descs, int ndesc) {
   typedef typename MfmaOp<T>::v4 v4;
-  constexpr int WNN = BN / 16, NT = 4 * BM * BN / 16;
-  constexpr int EA = BM * LK / NT, EB = LK * BN / NT;
-  static_assert(EA * NT == BM * LK && EB * NT == LK * BN, "tile shape");
+  constexpr int WNN = BN / 16, NBLK = (BM / 16) * (BN / 16), NT = 64 * NBLK * KS, LKC = 16 * KS;
+  constexpr int EA = BM * LKC / NT, EB = LKC * BN / NT;
+  static_assert(EA * NT == BM * LKC && EB * NT == LKC * BN, "tile shape");
   constexpr int NS = SLOT1 ? 2 : 1;
-  __shared__ T As[2][LK][BM + 1];
-  __shared__ T Bs[2][LK][BN + 1];
+  constexpr int SZA = 2 * LKC * (BM + 1), SZB = 2 * LKC * (BN + 1);
+  static_assert(NS * (KS - 1) * NBLK * 256 <= SZA + SZB, "reduction space");
+  __shared__ T sm[SZA + SZB];
+  auto As = [&](int buf, int k, int m) -> T& { return sm[(buf * LKC + k) * (BM + 1) + m]; };
+  auto Bs = [&](int buf, int k, int n) -> T& { return sm[SZA + (buf * LKC + k) * (BN + 1) + n]; };
 
   const i64 tile = blockIdx.x;
   int lo = 0, hi = ndesc - 1;
@@ -304,7 +308,8 @@ __global__ __launch_bounds__(4 * BM * BN / 16) void k_gemm_lds(const GemmDesc* _
   const int M = D.M, N = D.N;
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-  const int rb = (wave / WNN) * 16, cb = (wave % WNN) * 16;
+  const int bidx = wave % NBLK, kg = wave / NBLK;
+  const int rb = (bidx / WNN) * 16, cb = (bidx % WNN) * 16;
 
   v4 acc[NS];
 #pragma unroll
@@ -331,14 +336,14 @@ __global__ __launch_bounds__(4 * BM * BN / 16) void k_gemm_lds(const GemmDesc* _
       for (int u = 0; u < EA; ++u) {
         const int e = tid + NT * u;
         int k, m;
-        if (akf) { k = e % LK; m = e / LK; } else { m = e % BM; k = e / BM; }
+        if (akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
         ra[u] = (m0 + m < M && kc + k < kend) ? A[(i64)(m0 + m) * S.a_rs + (i64)(kc + k) * S.a_cs] : (T)0;
       }
 #pragma unroll
       for (int u = 0; u < EB; ++u) {
         const int e = tid + NT * u;
         int k, n;
-        if (bnf) { n = e % BN; k = e / BN; } else { k = e % LK; n = e / LK; }
+        if (bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
         rbv[u] = (n0 + n < N && kc + k < kend) ? B[(i64)(kc + k) * S.b_rs + (i64)(n0 + n) * S.b_cs] : (T)0;
       }
     };
@@ -347,15 +352,15 @@ __global__ __launch_bounds__(4 * BM * BN / 16) void k_gemm_lds(const GemmDesc* _
       for (int u = 0; u < EA; ++u) {
         const int e = tid + NT * u;
         int k, m;
-        if (akf) { k = e % LK; m = e / LK; } else { m = e % BM; k = e / BM; }
-        As[buf][k][m] = alpha * ra[u];
+        if (akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
+        As(buf, k, m) = alpha * ra[u];
       }
 #pragma unroll
       for (int u = 0; u < EB; ++u) {
         const int e = tid + NT * u;
         int k, n;
-        if (bnf) { n = e % BN; k = e / BN; } else { k = e % LK; n = e / LK; }
-        Bs[buf][k][n] = rbv[u];
+        if (bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
+        Bs(buf, k, n) = rbv[u];
       }
     };
     __syncthreads();                               // previous segment's reads of buffer 0 are done
@@ -363,13 +368,14 @@ __global__ __launch_bounds__(4 * BM * BN / 16) void k_gemm_lds(const GemmDesc* _
     sstore(0);
     __syncthreads();
     int buf = 0;
-    for (int kc = kbeg; kc < kend; kc += LK) {
-      const bool more = kc + LK < kend;
-      if (more) gload(kc + LK);
+    for (int kc = kbeg; kc < kend; kc += LKC) {
+      const bool more = kc + LKC < kend;
+      if (more) gload(kc + LKC);
 #pragma unroll
-      for (int kk = 0; kk < LK; kk += 4) {
-        const T av = As[buf][kk + lk][rb + lr];
-        const T bv = Bs[buf][kk + lk][cb + lr];
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int k = kg * 16 + kk + lk;
+        const T av = As(buf, k, rb + lr);
+        const T bv = Bs(buf, k, cb + lr);
         if (q == 0) acc[0] = MfmaOp<T>::mac(av, bv, acc[0]);
         else acc[NS - 1] = MfmaOp<T>::mac(av, bv, acc[NS - 1]);
       }
@@ -377,6 +383,23 @@ __global__ __launch_bounds__(4 * BM * BN / 16) void k_gemm_lds(const GemmDesc* _
       __syncthreads();
       buf ^= 1;
     }
+  }
+
+  if (KS > 1) {                                    // sum the K groups in a fixed order
+    __syncthreads();
+    if (kg > 0) {
+#pragma unroll
+      for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sm[((((q * (KS - 1)) + kg - 1) * NBLK + bidx) * 4 + r) * 64 + lane] = acc[q][r];
+    }
+    __syncthreads();
+    if (kg > 0) return;
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+      for (int g2 = 1; g2 < KS; ++g2)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[q][r] += sm[((((q * (KS - 1)) + g2 - 1) * NBLK + bidx) * 4 + r) * 64 + lane];
   }
 
   T* __restrict__ C = reinterpret_cast<T*>(D.C) + b * D.c_bs;
@@ -398,22 +421,22 @@ __global__ __launch_bounds__(4 * BM * BN / 16) void k_gemm_lds(const GemmDesc* _
   }
 }
 
-template <typename T, int BM>
+template <typename T, int BM, int KS>
 static void launch_lds(const Stage& st, int nd, hipStream_t s) {
-  const dim3 grid((unsigned)st.tiles), block(4 * BM * BM / 16);
+  const dim3 grid((unsigned)st.tiles), block(4 * BM * BM / 16 * KS);
   if (st.slot1)
-    k_gemm_lds<T, BM, BM, true><<<grid, block, 0, s>>>(st.d_descs, nd);
+    k_gemm_lds<T, BM, BM, KS, true><<<grid, block, 0, s>>>(st.d_descs, nd);
   else
-    k_gemm_lds<T, BM, BM, false><<<grid, block, 0, s>>>(st.d_descs, nd);
+    k_gemm_lds<T, BM, BM, KS, false><<<grid, block, 0, s>>>(st.d_descs, nd);
 }
 
 hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
   if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
   const int nd = (int)st.descs.size();
   if (st.kind == GEMM_LDS64) {
-    if (elt == F64) launch_lds<double, 64>(st, nd, s); else launch_lds<float, 64>(st, nd, s);
+    if (elt == F64) launch_lds<double, 64, 1>(st, nd, s); else launch_lds<float, 64, 1>(st, nd, s);
   } else if (st.kind == GEMM_LDS32) {
-    if (elt == F64) launch_lds<double, 32>(st, nd, s); else launch_lds<float, 32>(st, nd, s);
+    if (elt == F64) launch_lds<double, 32, 4>(st, nd, s); else launch_lds<float, 32, 4>(st, nd, s);
   } else if (elt == F64) {
     k_gemm_sk<double><<<dim3((unsigned)st.tiles), dim3(64 * SK_WAVES), 0, s>>>(st.d_descs, nd);
   } else {

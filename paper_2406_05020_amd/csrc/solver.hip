@@ -443,12 +443,14 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
 // One IterGP run on the volume system with right-hand side `b`, float64
 // recurrences, operator precision `elt`.  Directions are appended from slot
 // `start`; v accumulates.  passes = 1 is the published recurrence
-// d = s - C z with eta = z^T d and an explicit residual every iteration;
-// passes = 2 repeats the S-orthogonal projection on d (classical Gram-Schmidt
-// twice, using w = S d and the stored Q = S D), takes eta = d^T S d, updates
-// the residual recursively with w and replaces it by b - S v every
-// `replace_every` iterations.  The operator's input buffer X doubles as the
-// action / direction vector, so no vector is copied inside the loop.
+// d = s - C z with eta = z^T d and an explicit residual every iteration.
+// passes = 2 projects twice (classical Gram-Schmidt twice in the S inner
+// product) with one operator application per iteration: z = S s; first pass
+// c = eta^-1 o D^T z, d = s - D c, w = z - (S D) c (= S d); second pass
+// c = eta^-1 o D^T w, d -= D c, w -= (S D) c; then eta = d^T w, S D gains w,
+// and the residual is updated recursively with w and replaced by b - S v
+// every `replace_every` iterations.  The operator's input buffer X doubles as
+// the action vector, so no vector is copied inside the loop.
 static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int start, int max_new, double tol,
                       int check_every, int passes, int replace_every, hipStream_t s, int* n_out, int* state_out) {
   const i64 N = h->N;
@@ -489,21 +491,28 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
       // scal[0] = r.r and the stopping test; s = r is already in X
       HIPCHK(h, launch_dot_check(N, r, dotp, h->scal, h->flag, end - start, s));
       HIPCHK(h, apply_sop(h, so, s));                         // z = S s  (in Y)
-      if (passes == 1) HIPCHK(h, hipMemcpyAsync(h->vec + N, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-      if (i > 0) {                                            // d = s - D (eta^-1 o D^T z), also into X
-        HIPCHK(h, project(Y, i));
-        HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, X, d, X, nullptr, nullptr, nullptr, s));
-      } else {
-        HIPCHK(h, hipMemcpyAsync(d, X, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-      }
-      if (passes == 2) {
-        HIPCHK(h, apply_sop(h, so, s));                       // w = S d  (in Y)
-        if (i > 0) {
-          HIPCHK(h, project(Y, i));                         // d -= D coef ; w = S d - (S D) coef
-          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, d, d, nullptr, h->Qd, Y, w, s));
+      if (passes == 1) {
+        HIPCHK(h, hipMemcpyAsync(h->vec + N, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (i > 0) {                                          // d = s - D (eta^-1 o D^T z)
+          HIPCHK(h, project(Y, i));
+          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, X, d, X, nullptr, nullptr, nullptr, s));
         } else {
+          HIPCHK(h, hipMemcpyAsync(d, X, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+      } else {
+        if (i > 0) {
+          // first pass: c = eta^-1 o D^T z ; d = s - D c ; w = S d = z - (S D) c
+          HIPCHK(h, project(Y, i));
+          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, X, d, nullptr, h->Qd, Y, w, s));
+          // second pass on (d, w): c = eta^-1 o D^T w ; d -= D c ; w -= (S D) c
+          HIPCHK(h, project(w, i));
+          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, d, d, nullptr, h->Qd, w, w, s));
+        } else {
+          HIPCHK(h, hipMemcpyAsync(d, X, N * sizeof(double), hipMemcpyDeviceToDevice, s));
           HIPCHK(h, hipMemcpyAsync(w, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         }
+      }
+      if (passes == 2) {
         HIPCHK(h, launch_dot(N, w, d, dotp, h->scal + 1, s));     // eta = d^T S d
         hipLaunchKernelGGL(k_update2x, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, (const double*)w, v, r,
                            X, h->Dd + (i64)i * N, h->Qd + (i64)i * N, h->eta + i, (const double*)h->scal, h->flag);
