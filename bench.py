@@ -32,8 +32,14 @@ def parse():
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the volume-Gram matvec measurement (the command profiled under rocprofv3)")
-    ap.add_argument("--wave-roofline", action="store_true",
-                    help="also measure the 64x128x128 wave volume matvec with one right-hand side")
+    ap.add_argument("--extra-rooflines", action="store_true",
+                    help="also measure the 64x128x128 wave volume matvec with one right-hand side and the "
+                         "64^3 heat volume matvec with 64")
+    ap.add_argument("--large-timing", action="store_true",
+                    help="only time the wave 64x128x128 problem: assemble, 200 IterGP iterations, posterior")
+    ap.add_argument("--copy-bytes", type=int, default=256 << 20,
+                    help="size of the plain device copy run after the roofline measurement (the counter "
+                         "calibration for FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -73,8 +79,15 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     p = W.advdiff_c2()
+    if args.large_timing:
+        print(json.dumps(large_timing()), flush=True)
+        return
     if args.roofline_only:
-        print(json.dumps({"roofline": roofline_volume(p, B=64, reps=args.mv_reps)}), flush=True)
+        out = {"roofline": roofline_volume(p, B=64, reps=args.mv_reps)}
+        if args.extra_rooflines:
+            out.update(extra_rooflines())
+        out["copy_calibration"] = copy_calibration(args.copy_bytes)
+        print(json.dumps(out), flush=True)
         return
     prec = G.PREC_FP64 if args.prec == "fp64" else G.PREC_MIXED
     cap = 2048
@@ -132,9 +145,8 @@ def main():
         "gram_matvec_gflops": rl["achieved"] * 1e3,
     }
     out["roofline"] = rl
-    if args.wave_roofline:
-        import workloads as W2
-        out["roofline_wave_1rhs"] = roofline_volume(W2.wave2d_c4(), B=1, reps=20)
+    if args.extra_rooflines:
+        out.update(extra_rooflines())
     if args.serve_requests > 0:
         out["serving"] = serving_bench(args.serve_requests, args.serve_workers)
     if not args.no_cpu_baseline:
@@ -142,10 +154,79 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+# HBM bytes per launch of the volume-Gram GEMM on advection-diffusion 128^2
+# with 64 right-hand sides: FETCH_SIZE + WRITE_SIZE (two counter runs of
+# `bench.py --roofline-only`), each divided by the ratio the same counter
+# reads for the plain copy of known size that follows the measurement.  Set
+# to None whenever the GEMM kernel or the plan changes until re-measured.
+VOLUME_GEMM_TRAFFIC_BYTES = 57.10e6   # measured for k_gemm_lds<double,64,64> (scaled, per launch)
+
+
+def large_timing(iters=200):
+    """Wave 64x128x128 cells + 16384 points: assemble, a fixed number of IterGP
+    iterations, combined posterior on 8 x 128^2 points (wall clock, synchronised)."""
+    import numpy as np
+    import torch
+    import paper_2406_05020_amd as G
+    import workloads as W2
+    p = W2.wave2d_c4()
+    out = {"workload": p.name, "n_pde": int(p.n_pde), "n_b": int(p.n_b), "iters": iters}
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    h = G.assemble(p, max_iter=iters)
+    torch.cuda.synchronize()
+    out["assemble_s"] = time.perf_counter() - t
+    try:
+        t = time.perf_counter()
+        info = G.solve(h, tol=0.0, max_iter=iters, check_every=16)
+        torch.cuda.synchronize()
+        out["solve_s"] = time.perf_counter() - t
+        out["rel_res"] = info["rel_res"]
+        M = int(np.prod([len(a) for a in p.grid]))
+        mean = torch.empty(M, dtype=torch.float64, device="cuda:0")
+        var = torch.empty_like(mean)
+        t = time.perf_counter()
+        G.posterior(h, p.grid, mean, var)
+        torch.cuda.synchronize()
+        out["posterior_s"] = time.perf_counter() - t
+        out["grid_points"] = M
+        v = var.cpu().numpy()
+        out["var_min"], out["var_max"] = float(v.min()), float(v.max())
+    finally:
+        G.destroy(h)
+    return out
+
+
+def extra_rooflines():
+    import workloads as W2
+    return {"roofline_wave_1rhs": roofline_volume(W2.wave2d_c4(), B=1, reps=20),
+            "roofline_heat3d_64rhs": roofline_volume(W2.heat2d_c3(), B=64, reps=5)}
+
+
+def copy_calibration(nbytes):
+    """A plain float64 device copy of `nbytes` (reads nbytes, writes nbytes),
+    timed with HIP events; under the counter runs it calibrates FETCH_SIZE and
+    WRITE_SIZE against known traffic."""
+    import torch
+    n = nbytes // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return {"bytes_read": n * 8, "bytes_written": n * 8, "us": 1e3 * ms, "GB_s": 2 * n * 8 / (ms * 1e-3) / 1e9}
+
+
 def roofline_volume(p, B, reps):
-    """Volume-Gram matvec (the dominant MFMA kernel, k_gemm_sk<double>) on B
-    right-hand sides: HIP events on the stream it is launched on, around
-    `reps` applications; per-launch time = time per application / launches."""
+    """Volume-Gram matvec (its GEMM stages are the dominant MFMA kernel,
+    k_gemm_lds<double, 64, 64> at these sizes) on B right-hand sides: HIP
+    events on the stream it is launched on, around `reps` applications;
+    per-launch time = time per application / launches."""
     import torch
     import paper_2406_05020_amd as G
     stream = torch.cuda.current_stream()
@@ -170,8 +251,9 @@ def roofline_volume(p, B, reps):
     launches = max(1, info["volume_launches"])
     alg = flops1 * B
     achieved = alg / (ms * 1e-3) / 1e12
+    traffic = VOLUME_GEMM_TRAFFIC_BYTES if (p.name == "advdiff_128x128" and B == 64) else None
     return {"bound": "mfma", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6,
-            "traffic": None, "kernel": "k_gemm_sk<double> (volume-Gram mode products)",
+            "traffic": traffic, "kernel": "k_gemm_lds<double,64,64> (volume-Gram mode products)",
             "workload": f"{p.name} volume Gram, {B} rhs", "alg_flops_per_launch": alg / launches,
             "launches_per_matvec": launches, "avg_launch_us": 1e3 * ms / launches,
             "executed_flops_per_matvec": info["volume_flops"], "kronecker_applications": napp}

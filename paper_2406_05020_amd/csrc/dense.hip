@@ -4,6 +4,7 @@
 // inverse (Sec. 4.2, Cholesky preconditioner).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include "common.h"
@@ -201,11 +202,12 @@ bool desc_in_bounds(const GemmDesc& D, size_t es) {
 }
 
 // Pick the kernel of a stage (sizes measured on the advection-diffusion and
-// wave volume operators).  Long reductions over few tiles (K beyond 2048:
-// GEMV-shaped projections, point-block products) stay on the split-K kernel,
-// whose four wavefronts share the K range of a 32x32 tile.  Everything else
-// runs LDS-tiled: 64x64 tiles once there are at least 256 of them, else
-// 32x32 tiles.
+// wave volume operators).  Stages with at least 256 output tiles of 64x64 run
+// on the 64x64 LDS-tiled kernel whatever their K.  Below that, long
+// reductions (K beyond 2048: GEMV-shaped projections, point-block products
+// with few right-hand sides) go to the split-K kernel, whose four wavefronts
+// share the K range of a 32x32 tile, and short ones to the 32x32 LDS-tiled
+// kernel with its K range split over four wavefront groups.
 void choose_kernel(Stage& st) {
   st.kind = GEMM_SPLITK;
   st.slot1 = 0;
@@ -220,8 +222,8 @@ void choose_kernel(Stage& st) {
     kmax = std::max(kmax, ksum);
     tiles64 += (i64)((D.M + 63) / 64) * ((D.N + 63) / 64) * D.batch;
   }
-  if (kmax > 2048) return;
-  st.kind = tiles64 >= 256 ? GEMM_LDS64 : GEMM_LDS32;
+  if (tiles64 >= 256) st.kind = GEMM_LDS64;
+  else if (kmax <= 2048) st.kind = GEMM_LDS32;
 }
 
 // Upload a list of stages whose descriptors are consecutive in one buffer.
