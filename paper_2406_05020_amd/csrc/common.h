@@ -202,8 +202,11 @@ hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s);
 //                with M2: out3[c] = base2[c] - sum_j M2[j][c] u[j].   base may alias out.
 hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, const double* eta, double* out,
                            hipStream_t s);
+//   With M2 and dot_part: also dot_part[g] = workgroup g's share of sum_c out[c] * out3[c]
+//   (ceil(N/64) values; their fixed-order sum is the dot product).
 hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, const double* base, double* out,
-                              double* out2, const double* M2, const double* base2, double* out3, hipStream_t s);
+                              double* out2, const double* M2, const double* base2, double* out3, hipStream_t s,
+                              double* dot_part = nullptr);
 // y[i] = add[i] + alpha * sum_k M[i][k] x[k] over k <= i (upper = 0) or k >= i (upper = 1)
 hipError_t launch_trmv_rows(int n, const double* M, const double* x, double* y, double alpha, const double* add,
                             int upper, hipStream_t s);
@@ -294,4 +297,5 @@ struct gpfvm_handle {
   double* aux = nullptr;           // dot partials and coefficients
   double* scal = nullptr;          // device scalars
   int* flag = nullptr;             // device flags
+  double* part = nullptr;          // per-workgroup partial sums: d.w (ceil(N/64)), then r.r twice (nblk(N))
 };

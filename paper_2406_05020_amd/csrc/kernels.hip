@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.h"
+#include "reduce.h"
 
 namespace gpfvm {
 
@@ -285,11 +286,15 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
   constexpr int EA = BM * LKC / NT, EB = LKC * BN / NT;
   static_assert(EA * NT == BM * LKC && EB * NT == LKC * BN, "tile shape");
   constexpr int NS = SLOT1 ? 2 : 1;
-  constexpr int SZA = 2 * LKC * (BM + 1), SZB = 2 * LKC * (BN + 1);
+  // LDS tiles are stored k-contiguous, A as [m][k] and B as [n][k], with a row stride of LKC + 2
+  // elements: an MFMA operand read (16 rows x 4 consecutive k per wavefront) then touches 16 row
+  // starts 4 banks apart (f64), so each half-wavefront reads 64 distinct banks.
+  constexpr int LS = LKC + 2;
+  constexpr int SZA = 2 * BM * LS, SZB = 2 * BN * LS;
   static_assert(NS * (KS - 1) * NBLK * 256 <= SZA + SZB, "reduction space");
   __shared__ T sm[SZA + SZB];
-  auto As = [&](int buf, int k, int m) -> T& { return sm[(buf * LKC + k) * (BM + 1) + m]; };
-  auto Bs = [&](int buf, int k, int n) -> T& { return sm[SZA + (buf * LKC + k) * (BN + 1) + n]; };
+  auto As = [&](int buf, int k, int m) -> T& { return sm[(buf * BM + m) * LS + k]; };
+  auto Bs = [&](int buf, int k, int n) -> T& { return sm[SZA + (buf * BN + n) * LS + k]; };
 
   const i64 tile = blockIdx.x;
   int lo = 0, hi = ndesc - 1;
@@ -545,10 +550,6 @@ hipError_t launch_add_diag(double* A, i64 ld, i64 n0, i64 n, const double* vals,
 constexpr int DOT_BLOCKS = 512;
 constexpr int DOT_THREADS = 256;
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
 
 __global__ __launch_bounds__(DOT_THREADS) void k_dot_partial(i64 n, const double* __restrict__ x,
                                                              const double* __restrict__ y,
@@ -710,11 +711,11 @@ __global__ __launch_bounds__(1024) void k_rows_dot(i64 N, const double* __restri
   }
 }
 
-template <bool TWO>
+template <bool TWO, bool DOT>
 __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, const double* __restrict__ M,
                                                                const double* __restrict__ u, const double* base,
                                                                double* out, double* out2, const double* __restrict__ M2,
-                                                               const double* base2, double* out3) {
+                                                               const double* base2, double* out3, double* dot_part) {
   __shared__ double us[CU_BLK];
   __shared__ double part[CU_WAVES][64];
   __shared__ double part2[TWO ? CU_WAVES : 1][64];
@@ -738,6 +739,7 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
   part[wave][lane] = acc;
   if (TWO) part2[wave][lane] = acc2;
   __syncthreads();
+  double prod = 0.0;
   if (wave == 0 && c < N) {
     double s = 0.0;
     for (int w = 0; w < CU_WAVES; ++w) s += part[w][lane];
@@ -747,8 +749,14 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
     if (TWO) {
       double s2 = 0.0;
       for (int w = 0; w < CU_WAVES; ++w) s2 += part2[w][lane];
-      out3[c] = base2[c] - s2;
+      const double v3 = base2[c] - s2;
+      out3[c] = v3;
+      prod = v * v3;
     }
+  }
+  if (DOT && wave == 0) {                        // this workgroup's part of sum_c out[c] * out3[c]
+    prod = wave_sum(prod);
+    if (lane == 0) dot_part[blockIdx.x] = prod;
   }
 }
 
@@ -760,13 +768,17 @@ hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, cons
 }
 
 hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, const double* base, double* out,
-                              double* out2, const double* M2, const double* base2, double* out3, hipStream_t s) {
+                              double* out2, const double* M2, const double* base2, double* out3, hipStream_t s,
+                              double* dot_part) {
   if (N <= 0) return hipSuccess;
   const dim3 grid((unsigned)((N + 63) / 64)), block(64 * CU_WAVES);
-  if (M2)
-    k_cols_update<true><<<grid, block, 0, s>>>(nr, N, M, u, base, out, out2, M2, base2, out3);
+  if (M2 && dot_part)
+    k_cols_update<true, true><<<grid, block, 0, s>>>(nr, N, M, u, base, out, out2, M2, base2, out3, dot_part);
+  else if (M2)
+    k_cols_update<true, false><<<grid, block, 0, s>>>(nr, N, M, u, base, out, out2, M2, base2, out3, nullptr);
   else
-    k_cols_update<false><<<grid, block, 0, s>>>(nr, N, M, u, base, out, out2, nullptr, nullptr, nullptr);
+    k_cols_update<false, false><<<grid, block, 0, s>>>(nr, N, M, u, base, out, out2, nullptr, nullptr, nullptr,
+                                                       nullptr);
   return hipGetLastError();
 }
 

@@ -12,7 +12,9 @@
 // depend on what else is in flight.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -129,7 +131,11 @@ static size_t estimate_bytes(const gpfvm_ibvp& p, int max_iter, long long M, int
   b += 2.0 * nb * 64 * d8 + 4.0 * (nb + 64) * 64 * d8;     // Cholesky workspace
   const double chunk = std::max(32.0, std::min((double)M, (double)(32LL << 20) / std::max(1LL, nb)));
   b += 3.0 * nb * chunk * d8;                              // posterior point-block chunks
-  b += 2.0 * M * 64 * d8 + 64.0 * N * d8 + 8.0 * M * d8;  // posterior direction chunks
+  {                                                        // posterior direction batches
+    const double widest = std::max(std::max((double)M, (double)N), std::max(1.0, (double)nb));
+    const double B = std::min((double)max_iter, std::max(64.0, std::floor((double)(512LL << 20) / (8.0 * widest))));
+    b += (2.0 * M * B + N * B + 4.0 * nb * B) * d8 + 8.0 * M * d8;
+  }
   if (prec == GPFVM_PREC_MIXED) b += 12.0 * N * 4.0;       // float32 operator buffers
   return (size_t)(1.25 * b) + (size_t)(32 << 20);
 }

@@ -18,6 +18,7 @@
 
 #include "common.h"
 #include "internal.h"
+#include "reduce.h"
 
 using namespace gpfvm;
 
@@ -33,20 +34,51 @@ using namespace gpfvm;
 
 namespace {
 
-// guarded update (two-pass form): a = (s.r)/eta with s = r so s.r = scal[0];
-// v += a d ; r -= a w ; X = r ; store d, w, eta ; count the iteration
-__global__ void k_update2x(i64 N, const double* __restrict__ d, const double* __restrict__ w, double* __restrict__ v,
-                           double* __restrict__ r, double* __restrict__ X, double* __restrict__ Dcol,
-                           double* __restrict__ Qcol, double* __restrict__ eta_slot, const double* __restrict__ scal,
-                           int* __restrict__ flag) {
-  if (flag[0] != 0) return;
-  const double et = scal[1], sr = scal[0];
+// guarded update (two-pass form): a = (s.r)/eta with s = r;
+// v += a d ; r -= a w ; X = r ; store d, w, eta ; count the iteration.
+// eta comes from the previous kernel's per-workgroup partials (eta_part,
+// n_eta values) or from scal[1].  s.r = r.r comes from the previous update's
+// partials (rr_in, n_rr values) or from scal[0] (already tested by the dot
+// kernel).  Every workgroup sums the partials itself in the same fixed order,
+// so no workgroup waits on another.  With rr_in this kernel also runs the
+// stopping test (converged if r.r <= tol^2 b.b: scal[4] = tol^2,
+// scal[3] = b.b).  rr_out receives this update's partials of the new r.r.
+__global__ __launch_bounds__(256) void k_update2x(i64 N, const double* __restrict__ d, const double* __restrict__ w,
+                                                  double* __restrict__ v, double* __restrict__ r,
+                                                  double* __restrict__ X, double* __restrict__ Dcol,
+                                                  double* __restrict__ Qcol, double* __restrict__ eta_slot,
+                                                  double* __restrict__ scal, int* __restrict__ flag,
+                                                  const double* __restrict__ eta_part, int n_eta,
+                                                  const double* __restrict__ rr_in, int n_rr,
+                                                  double* __restrict__ rr_out) {
+  __shared__ double red[256];
+  __shared__ int fl;
+  if (threadIdx.x == 0) fl = flag[0];
+  __syncthreads();
+  if (fl != 0) return;
+  double sr = scal[0], et = scal[1];
+  if (rr_in) {
+    sr = block_sum_fixed<256>(rr_in, n_rr, red);
+    __syncthreads();
+  }
+  if (eta_part) {
+    et = block_sum_fixed<256>(eta_part, n_eta, red);
+    __syncthreads();
+  }
   const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rr_in && sr <= scal[4] * scal[3]) {
+    if (k == 0) {
+      scal[0] = sr;
+      flag[0] = 1;
+    }
+    return;
+  }
   if (!(et > 0.0)) {
     if (k == 0) flag[0] = 2;
     return;
   }
   const double a = sr / et;
+  double rr = 0.0;
   if (k < N) {
     const double dk = d[k], wk = w[k];
     v[k] += a * dk;
@@ -55,10 +87,19 @@ __global__ void k_update2x(i64 N, const double* __restrict__ d, const double* __
     X[k] = rk;
     Dcol[k] = dk;
     Qcol[k] = wk;
+    rr = rk * rk;
   }
   if (k == 0) {
     *eta_slot = et;
+    scal[0] = sr;
+    scal[1] = et;
     flag[1] += 1;
+  }
+  if (rr_out) {
+    rr = wave_sum(rr);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rr;
+    __syncthreads();
+    if (threadIdx.x == 0) rr_out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
   }
 }
 
@@ -419,7 +460,8 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
   h->aux = (double*)h->arena.alloc((size_t)(1024 + h->max_iter) * sizeof(double));
   h->scal = (double*)h->arena.alloc(64 * sizeof(double));
   h->flag = (int*)h->arena.alloc(16 * sizeof(int));
-  if (!h->bS || !h->ab0 || !h->v || !h->Dd || !h->eta || !h->vec || !h->aux || !h->scal || !h->flag) {
+  h->part = (double*)h->arena.alloc((size_t)((N + 63) / 64 + 2 * nblk(N) + 1) * sizeof(double));
+  if (!h->bS || !h->ab0 || !h->v || !h->Dd || !h->eta || !h->vec || !h->aux || !h->scal || !h->flag || !h->part) {
     h->err = "out of device memory (solver state; lower max_iter)";
     return GPFVM_E_NOMEM;
   }
@@ -485,11 +527,20 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
   auto project = [&](const double* rhs_vec, int nd) {
     return launch_rows_dot(nd, N, h->Dd, rhs_vec, h->eta, coef, s);
   };
+  // two-pass form: r.r and the stopping test of an iteration come from the
+  // previous update's partial sums (tested inside the update kernel), or from
+  // the dot kernel at the start and after an explicit residual replacement
+  const int n_eta = (int)((N + 63) / 64), n_rr = (int)nblk(N);
+  double* eta_p = h->part;
+  double* rr_a = h->part + n_eta;
+  double* rr_b = rr_a + n_rr;
+  double* rr_prev = nullptr;
+  if (passes == 2) HIPCHK(h, launch_dot_check(N, r, dotp, h->scal, h->flag, end - start, s));
   while (i < end) {
     const int batch_end = std::min(end, i + std::max(1, check_every));
     for (; i < batch_end; ++i) {
       // scal[0] = r.r and the stopping test; s = r is already in X
-      HIPCHK(h, launch_dot_check(N, r, dotp, h->scal, h->flag, end - start, s));
+      if (passes == 1) HIPCHK(h, launch_dot_check(N, r, dotp, h->scal, h->flag, end - start, s));
       HIPCHK(h, apply_sop(h, so, s));                         // z = S s  (in Y)
       if (passes == 1) {
         HIPCHK(h, hipMemcpyAsync(h->vec + N, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -504,24 +555,29 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
           // first pass: c = eta^-1 o D^T z ; d = s - D c ; w = S d = z - (S D) c
           HIPCHK(h, project(Y, i));
           HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, X, d, nullptr, h->Qd, Y, w, s));
-          // second pass on (d, w): c = eta^-1 o D^T w ; d -= D c ; w -= (S D) c
+          // second pass on (d, w): c = eta^-1 o D^T w ; d -= D c ; w -= (S D) c ; eta = d^T w
           HIPCHK(h, project(w, i));
-          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, d, d, nullptr, h->Qd, w, w, s));
+          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, d, d, nullptr, h->Qd, w, w, s, eta_p));
         } else {
           HIPCHK(h, hipMemcpyAsync(d, X, N * sizeof(double), hipMemcpyDeviceToDevice, s));
           HIPCHK(h, hipMemcpyAsync(w, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+          HIPCHK(h, launch_dot(N, w, d, dotp, h->scal + 1, s));   // eta = d^T S d
         }
       }
       if (passes == 2) {
-        HIPCHK(h, launch_dot(N, w, d, dotp, h->scal + 1, s));     // eta = d^T S d
+        const bool replace = (i + 1 - start) % std::max(1, replace_every) == 0;
+        double* rr_next = replace ? nullptr : (rr_prev == rr_a ? rr_b : rr_a);
         hipLaunchKernelGGL(k_update2x, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, (const double*)w, v, r,
-                           X, h->Dd + (i64)i * N, h->Qd + (i64)i * N, h->eta + i, (const double*)h->scal, h->flag);
-        if ((i + 1 - start) % std::max(1, replace_every) == 0) {
+                           X, h->Dd + (i64)i * N, h->Qd + (i64)i * N, h->eta + i, h->scal, h->flag,
+                           (const double*)(i > 0 ? eta_p : nullptr), n_eta, (const double*)rr_prev, n_rr, rr_next);
+        rr_prev = rr_next;
+        if (replace) {
           HIPCHK(h, hipMemcpyAsync(X, v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
           HIPCHK(h, apply_sop(h, so, s));
           hipLaunchKernelGGL(k_resid2, dim3(nblk(N)), dim3(256), 0, s, N, b, Y, r, X, (const int*)h->flag);
           // X must hold r again even when the run has already stopped
           HIPCHK(h, hipMemcpyAsync(X, r, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+          HIPCHK(h, launch_dot_check(N, r, dotp, h->scal, h->flag, end - start, s));
         }
       } else {
         // eta = z^T d with z = S s: recompute z is not needed -- z was in Y before the
@@ -849,7 +905,9 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
   }
   const int K = h->iters;
   if (K > 0) {
-    const int B = std::min(K, 64);
+    // direction batch: as many as keep each per-batch buffer within 512 MB (at least 64)
+    const i64 widest = std::max<i64>(std::max<i64>(M, N), std::max(h->nb, 1));
+    const int B = (int)std::min<i64>(K, std::max<i64>(64, (512LL << 20) / (8 * widest)));
     double* P1 = (double*)tmp.alloc((size_t)M * B * sizeof(double));
     double* P2 = h->nb > 0 ? (double*)tmp.alloc((size_t)M * B * sizeof(double)) : nullptr;
     double* Ub = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
