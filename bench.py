@@ -97,14 +97,22 @@ def main():
     stream = torch.cuda.current_stream()
     infos = []
 
+    phases = []
+
     def step():
+        t0 = time.perf_counter()
         h = G.assemble(p, max_iter=cap, stream=stream.cuda_stream)
+        t1 = time.perf_counter()
         try:
             info = G.solve(h, prec=prec, tol=1e-8, max_iter=cap, check_every=16, stream=stream.cuda_stream)
+            t2 = time.perf_counter()
             G.posterior(h, p.grid, mean, var, stream=stream.cuda_stream)
+            t3 = time.perf_counter()
         finally:
             G.destroy(h)
+        t4 = time.perf_counter()
         infos.append(info)
+        phases.append((t1 - t0, t2 - t1, t3 - t2, t4 - t3))
 
     for _ in range(args.warmup):
         step()
@@ -140,6 +148,8 @@ def main():
         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "iters": info["iters"],
+        "phase_ms_p50": {k: 1e3 * float(np.median([ph[j] for ph in phases[args.warmup:]]))
+                         for j, k in enumerate(["assemble", "solve", "posterior", "destroy"])},
         "rel_res": info["rel_res"],
         "rel_res_full": info["rel_res_full"],
         "gram_matvec_gflops": rl["achieved"] * 1e3,

@@ -101,6 +101,11 @@ typedef struct {
 typedef struct {
   int max_iter;        /* capacity for stored IterGP directions (>= 1)              */
   int tile;            /* GPFVM_TILE_* format prepared for the mixed path           */
+  int reuse_memory;    /* 1 (default): device blocks come from and return to a      */
+                       /* per-device cache of this process, so repeated             */
+                       /* assemble/destroy cycles make no hipMalloc/hipFree calls;  */
+                       /* gpfvm_release_cached_memory() hands the cached blocks     */
+                       /* back.  0: the handle allocates and frees its own blocks.  */
 } gpfvm_assemble_opts;
 
 typedef struct {
@@ -268,9 +273,14 @@ int gpfvm_server_stats(gpfvm_server* s, gpfvm_server_info* st);
 /* Finish the queued requests, stop the workers and free all device memory. */
 void gpfvm_server_destroy(gpfvm_server* s);
 
-/* Free every device buffer of the handle (after synchronising its stream).
- * NULL is accepted. */
+/* Free every device buffer of the handle (after synchronising its stream;
+ * with reuse_memory, after synchronising the device, then the blocks go back
+ * to the cache).  NULL is accepted. */
 void gpfvm_destroy(gpfvm_handle* h);
+
+/* Return the unused blocks of every per-device cache (reuse_memory) to the
+ * runtime.  Blocks held by live handles stay.  Returns the bytes freed. */
+long long gpfvm_release_cached_memory(void);
 
 /* Message of the last error on h, or (h == NULL) of this thread's last
  * validation / assemble error.  Never NULL. */

@@ -40,7 +40,7 @@ class IBVPStruct(C.Structure):
 
 
 class AssembleOpts(C.Structure):
-    _fields_ = [("max_iter", C.c_int), ("tile", C.c_int)]
+    _fields_ = [("max_iter", C.c_int), ("tile", C.c_int), ("reuse_memory", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -105,6 +105,7 @@ SYMBOLS = {
     "gpfvm_server_destroy": ([C.c_void_p], None),
     "gpfvm_destroy": ([C.c_void_p], None),
     "gpfvm_last_error": ([C.c_void_p], C.c_char_p),
+    "gpfvm_release_cached_memory": ([], C.c_longlong),
 }
 
 
@@ -127,6 +128,11 @@ def lib():
             f.argtypes, f.restype = args, res
         _lib = L
     return _lib
+
+
+def release_cached_memory() -> int:
+    """Return the unused blocks of the per-device caches to the runtime (bytes freed)."""
+    return int(lib().gpfvm_release_cached_memory())
 
 
 def last_error(h=None) -> str:
@@ -202,9 +208,9 @@ def validate(p) -> None:
     _check(lib().gpfvm_validate(C.byref(m.s)))
 
 
-def assemble(p, max_iter: int = 512, tile: int = TILE_FP32, stream=None) -> C.c_void_p:
+def assemble(p, max_iter: int = 512, tile: int = TILE_FP32, stream=None, reuse_memory: bool = True) -> C.c_void_p:
     m = _Marshal(p)
-    o = AssembleOpts(max_iter, tile)
+    o = AssembleOpts(max_iter, tile, 1 if reuse_memory else 0)
     h = C.c_void_p()
     _check(lib().gpfvm_assemble(C.byref(m.s), C.byref(o), _stream(stream), C.byref(h)))
     return h

@@ -2,6 +2,10 @@
 // matvec, dense Gram blocks and the stand-alone factor call.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <memory>
+#include <mutex>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -34,6 +38,35 @@ extern "C" void gpfvm_default_assemble_opts(gpfvm_assemble_opts* o) {
   if (!o) return;
   o->max_iter = 512;
   o->tile = GPFVM_TILE_FP32;
+  o->reuse_memory = 1;
+}
+
+namespace {
+// Per-device block caches of standalone handles (reuse_memory).
+std::mutex g_cache_mu;
+std::map<int, std::unique_ptr<DeviceCache>> g_caches;
+
+DeviceCache* process_cache() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto& c = g_caches[dev];
+  if (!c) c = std::make_unique<DeviceCache>();
+  return c.get();
+}
+}  // namespace
+
+extern "C" long long gpfvm_release_cached_memory(void) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  long long freed = 0;
+  for (auto& kv : g_caches) {
+    if (hipSetDevice(kv.first) != hipSuccess) continue;
+    freed += (long long)kv.second->trim();
+  }
+  (void)hipSetDevice(cur);
+  return freed;
 }
 
 extern "C" void gpfvm_default_solve_opts(gpfvm_solve_opts* o) {
@@ -485,7 +518,11 @@ int gpfvm_assemble_cached(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, 
 
 extern "C" int gpfvm_assemble(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream,
                               gpfvm_handle** out) {
-  return gpfvm_assemble_cached(p, opts, stream, nullptr, out);
+  const bool reuse = !opts || opts->reuse_memory != 0;
+  DeviceCache* cache = reuse ? process_cache() : nullptr;
+  const int rc = gpfvm_assemble_cached(p, opts, stream, cache, out);
+  if (rc == GPFVM_OK && out && *out) (*out)->process_cache = (cache != nullptr);
+  return rc;
 }
 
 int gpfvm_assemble_cached(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream, DeviceCache* cache,
@@ -686,6 +723,9 @@ extern "C" int gpfvm_get_info(const gpfvm_handle* h, gpfvm_handle_info* info) {
 extern "C" void gpfvm_destroy(gpfvm_handle* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  // cached blocks are handed to the next handle at once: wait for any work the
+  // caller may still have queued on other streams (hipFree would as well)
+  if (h->process_cache) (void)hipDeviceSynchronize();
   for (const void* p : h->user_ranges) unregister_range(p);
   h->arena.release();
   delete h;

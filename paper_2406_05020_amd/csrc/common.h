@@ -87,12 +87,20 @@ struct DeviceCache {
   void* get(size_t nbytes);
   void put(void* p);
   void release_all();
+  i64 trim();                      // free the unused blocks only; returns their bytes
 };
 
-// Device memory arena owned by a handle (freed at destroy).
+// Device memory arena owned by a handle (freed at destroy).  Allocations up
+// to a quarter of a slab are carved from 8 MiB slabs (256-byte aligned), so a
+// handle makes a few dozen runtime allocations instead of hundreds; larger
+// ones get their own block.  Every allocation is registered as its own range.
+constexpr size_t ARENA_SLAB = 8u << 20;
 struct Arena {
-  std::vector<void*> ptrs;
-  i64 bytes = 0;
+  std::vector<void*> ptrs;         // slabs and large blocks (from hipMalloc or the cache)
+  std::vector<void*> regs;         // registered allocations
+  char* slab = nullptr;
+  size_t slab_left = 0;
+  i64 bytes = 0;                   // device bytes held (slabs counted whole)
   DeviceCache* cache = nullptr;    // when set, blocks come from / go back to it
   void* alloc(size_t nbytes);      // returns nullptr on failure
   void release();
@@ -273,6 +281,7 @@ struct gpfvm_handle {
   double* Lt = nullptr;            // row-major copies of L^T and L^{-T}
   double* Linvt = nullptr;
   double* Qc = nullptr;            // n_b x N: L^{-1} G_bp (built on first use when qform_ok)
+  bool process_cache = false;      // arena blocks come from the per-process cache
   float* Linv_f = nullptr;
   gpfvm::GramMeta* meta = nullptr;   // device
   gpfvm::KronOp op_pp, op_pp32;

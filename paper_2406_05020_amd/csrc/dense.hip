@@ -93,54 +93,57 @@ constexpr int NB = 64;
 __global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ A, i64 ld, int k0, int nb,
                                                     double* __restrict__ dinv, int* __restrict__ flag) {
   __shared__ double L[NB][NB + 1];
-  __shared__ double Inv[NB][NB + 1];
-  __shared__ int bad;
-  const int t = threadIdx.x;
-  if (t == 0) bad = 0;
+  __shared__ double V[NB][NB + 1];
+  const int t = threadIdx.x, ty = t >> 4, tx = t & 15;     // 16 x 16 threads, 4 x 4 elements each
   for (int e = t; e < NB * NB; e += blockDim.x) {
     const int i = e / NB, j = e % NB;
     L[i][j] = (i < nb && j < nb) ? A[(i64)(k0 + i) * ld + k0 + j] : (i == j ? 1.0 : 0.0);
+    V[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   if (*flag != 0) return;            // an earlier block already failed
+  // right-looking Cholesky: column j is scaled, then the trailing lower triangle
+  // takes the rank-1 update, each thread on its fixed 4 x 4 set of elements
+  int bad = 0;
   for (int j = 0; j < nb; ++j) {
-    if (t == 0) {
-      const double p = L[j][j];
-      if (!(p > 0.0)) { bad = 1; L[j][j] = 1.0; }
-      else L[j][j] = sqrt(p);
-    }
+    const double p = L[j][j];          // the same value in every thread
+    if (!(p > 0.0)) { bad = 1; break; }
+    const double dj = sqrt(p);
+    __syncthreads();                   // every thread has read the pivot
+    for (int i = j + t; i < nb; i += blockDim.x) L[i][j] = (i == j) ? dj : L[i][j] / dj;
     __syncthreads();
-    if (bad) break;
-    const double piv = L[j][j];
-    for (int i = j + 1 + t; i < nb; i += blockDim.x) L[i][j] /= piv;
-    __syncthreads();
-    // rank-1 update of the trailing lower triangle
-    for (int e = t; e < (nb - j - 1) * (nb - j - 1); e += blockDim.x) {
-      const int i = j + 1 + e / (nb - j - 1), c = j + 1 + e % (nb - j - 1);
-      if (c <= i) L[i][c] -= L[i][j] * L[c][j];
-    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = ty + 16 * a, c = tx + 16 * b;
+        if (i < nb && c > j && c <= i) L[i][c] -= L[i][j] * L[c][j];
+      }
     __syncthreads();
   }
   if (bad) {
     if (t == 0) atomicCAS(flag, 0, 1 + k0);
     return;
   }
-  // inverse of the lower-triangular L (column c solved by thread c)
-  for (int e = t; e < NB * NB; e += blockDim.x) Inv[e / NB][e % NB] = 0.0;
-  __syncthreads();
-  if (t < nb) {
-    const int c = t;
-    for (int i = c; i < nb; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) s -= L[i][k] * Inv[k][c];
-      Inv[i][c] = s / L[i][i];
-    }
+  // inverse by forward elimination on [L | I]: row j of V is divided by L[j][j],
+  // then subtracted from the rows below with multipliers L[i][j]
+  for (int j = 0; j < nb; ++j) {
+    const double dj = L[j][j];
+    if (t <= j) V[j][t] /= dj;
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = ty + 16 * a, c = tx + 16 * b;
+        if (i > j && i < nb && c <= j) V[i][c] -= L[i][j] * V[j][c];
+      }
+    __syncthreads();
   }
-  __syncthreads();
   for (int e = t; e < NB * NB; e += blockDim.x) {
     const int i = e / NB, j = e % NB;
     if (i < nb && j < nb) A[(i64)(k0 + i) * ld + k0 + j] = (j <= i) ? L[i][j] : 0.0;
-    dinv[e] = (i < nb && j < nb) ? Inv[i][j] : 0.0;
+    dinv[e] = (i < nb && j < nb && j <= i) ? V[i][j] : 0.0;
   }
 }
 

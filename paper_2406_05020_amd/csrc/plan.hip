@@ -91,6 +91,20 @@ void DeviceCache::put(void* p) {
   cached_bytes += (i64)it->second;
 }
 
+i64 DeviceCache::trim() {
+  std::lock_guard<std::mutex> lk(mu);
+  i64 freed = 0;
+  for (auto& kv : free_blocks) {
+    (void)hipFree(kv.second);
+    sizes.erase(kv.second);
+    freed += (i64)kv.first;
+  }
+  free_blocks.clear();
+  total_bytes -= freed;
+  cached_bytes = 0;
+  return freed;
+}
+
 void DeviceCache::release_all() {
   std::lock_guard<std::mutex> lk(mu);
   for (auto& kv : free_blocks) (void)hipFree(kv.second);
@@ -100,28 +114,47 @@ void DeviceCache::release_all() {
 }
 
 void* Arena::alloc(size_t nbytes) {
-  void* p = nullptr;
   if (nbytes == 0) nbytes = 256;
   nbytes = (nbytes + 255) & ~(size_t)255;
-  if (cache) {
-    p = cache->get(nbytes);
-    if (!p) return nullptr;
-  } else if (hipMalloc(&p, nbytes) != hipSuccess) {
-    return nullptr;
+  auto block = [&](size_t n) -> void* {
+    void* q = nullptr;
+    if (cache) q = cache->get(n);
+    else if (hipMalloc(&q, n) != hipSuccess) q = nullptr;
+    if (q) {
+      ptrs.push_back(q);
+      bytes += (i64)n;
+    }
+    return q;
+  };
+  void* p = nullptr;
+  if (nbytes > ARENA_SLAB / 4) {
+    p = block(nbytes);
+  } else {
+    if (nbytes > slab_left) {
+      slab = (char*)block(ARENA_SLAB);
+      slab_left = slab ? ARENA_SLAB : 0;
+    }
+    if (slab) {
+      p = slab + (ARENA_SLAB - slab_left);
+      slab_left -= nbytes;
+    }
   }
-  ptrs.push_back(p);
-  bytes += (i64)nbytes;
+  if (!p) return nullptr;
+  regs.push_back(p);
   register_range(p, nbytes);
   return p;
 }
 
 void Arena::release() {
+  for (void* p : regs) unregister_range(p);
+  regs.clear();
   for (void* p : ptrs) {
-    unregister_range(p);
     if (cache) cache->put(p);
     else (void)hipFree(p);
   }
   ptrs.clear();
+  slab = nullptr;
+  slab_left = 0;
   bytes = 0;
 }
 

@@ -536,8 +536,15 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
   double* rr_b = rr_a + n_rr;
   double* rr_prev = nullptr;
   if (passes == 2) HIPCHK(h, launch_dot_check(N, r, dotp, h->scal, h->flag, end - start, s));
+  // Iterations run in batches between host checks of the flags.  The batch
+  // length is check_every, shortened near convergence to the number of
+  // iterations the residual's geometric rate over the last batch predicts
+  // (plus one), so few iterations run after the stopping test has fired.
+  int batch = std::max(1, check_every);
+  double rr_last = -1.0;
+  int i_last = i;
   while (i < end) {
-    const int batch_end = std::min(end, i + std::max(1, check_every));
+    const int batch_end = std::min(end, i + batch);
     for (; i < batch_end; ++i) {
       // scal[0] = r.r and the stopping test; s = r is already in X
       if (passes == 1) HIPCHK(h, launch_dot_check(N, r, dotp, h->scal, h->flag, end - start, s));
@@ -593,9 +600,20 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
       }
     }
     HIPCHK(h, hipGetLastError());
+    double hs[5] = {0, 0, 0, 0, 0};
     HIPCHK(h, hipMemcpyAsync(hflag, h->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(hs, h->scal, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     if (hflag[0] != 0) break;
+    batch = std::max(1, check_every);
+    const double rr = hs[0], target = hs[4] * hs[3];
+    if (tol > 0 && rr_last > 0 && rr > 0 && rr < rr_last && target > 0 && i > i_last) {
+      const double rate = std::log(rr / rr_last) / (i - i_last);        // per iteration, < 0
+      const double left = std::log(target / rr) / rate;
+      if (left >= 0 && left < batch) batch = std::max(1, (int)std::ceil(left) + 1);
+    }
+    rr_last = rr;
+    i_last = i;
   }
   *n_out = start + hflag[1];
   *state_out = hflag[0];

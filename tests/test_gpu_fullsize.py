@@ -113,3 +113,28 @@ def test_fixed_iteration_posterior_matches_oracle(G, c2):
         assert relerr(host(var)[idx], v_ref) <= 1e-6
     finally:
         G.destroy(h)
+
+
+@pytest.mark.parametrize("name,B,checked", [("wave2d_64x128x128", 1, [0]), ("heat2d_64x64x64", 64, [0, 31, 63])])
+def test_full_size_volume_matvec_matches_oracle(G, name, B, checked):
+    """The volume Gram (plus noise) at full size, in the launch configuration of
+    bench.py's extra rooflines (wave 64x128x128 with 1 rhs; heat 64^3 with 64
+    rhs), compared on whole right-hand sides with the oracle's Kronecker
+    matvec over the quadrature factors."""
+    p = {"wave2d_64x128x128": W.wave2d_c4, "heat2d_64x64x64": W.heat2d_c3}[name]()
+    assert p.name == name
+    o = O.Oracle(p)
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((B, p.n_pde))
+    h = G.assemble(p, max_iter=8)
+    try:
+        x = torch.as_tensor(X.ravel(), device="cuda:0")
+        y = torch.empty_like(x)
+        G.volume_matvec(h, x, y, nrhs=B)
+        Y = host(y).reshape(B, -1)
+    finally:
+        G.destroy(h)
+    noise = o.noise_pde()
+    for r in checked:
+        ref = o.volume_matvec(X[r]) + noise * X[r]
+        assert relerr(Y[r], ref) <= 1e-11, (r, relerr(Y[r], ref))

@@ -243,3 +243,31 @@ def test_schur_matvec_matches_oracle(G, name):
                 assert relerr(Y[r], ref) <= 1e-11, (nrhs, r, relerr(Y[r], ref))
     finally:
         G.destroy(h)
+
+
+def test_memory_reuse_gives_identical_results_and_releases(G):
+    """Handles drawing on the per-device block cache (the default) give the
+    same bits as handles with their own allocations; releasing the cache
+    frees its unused blocks and later handles still work."""
+    p = W.advdiff_c2(nt=24, nx=20, n_ic=40)
+
+    def run(reuse):
+        h = G.assemble(p, max_iter=64, reuse_memory=reuse)
+        try:
+            info = G.solve(h, tol=1e-6, max_iter=64, check_every=8)
+            M = int(np.prod([len(a) for a in p.grid]))
+            mean = torch.empty(M, dtype=torch.float64, device="cuda:0")
+            var = torch.empty(M, dtype=torch.float64, device="cuda:0")
+            G.posterior(h, p.grid, mean, var)
+            return info["iters"], host(mean), host(var)
+        finally:
+            G.destroy(h)
+
+    ref = run(False)
+    for _ in range(2):                     # the second run takes its blocks from the cache
+        it, m, v = run(True)
+        assert it == ref[0] and np.array_equal(m, ref[1]) and np.array_equal(v, ref[2])
+    assert G.release_cached_memory() > 0
+    assert G.release_cached_memory() == 0
+    it, m, v = run(True)
+    assert np.array_equal(m, ref[1])
