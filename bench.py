@@ -30,6 +30,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests in the serving trace (0 = skip the serving measurement)")
     ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--serve-rates", default="0.8",
+                    help="comma-separated arrival rates as fractions of the saturated throughput")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving measurement")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the volume-Gram matvec measurement (the command profiled under rocprofv3)")
     ap.add_argument("--extra-rooflines", action="store_true",
@@ -79,6 +82,10 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     p = W.advdiff_c2()
+    if args.serving_only:
+        rates = tuple(float(r) for r in args.serve_rates.split(","))
+        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_workers, rates)}), flush=True)
+        return
     if args.large_timing:
         print(json.dumps(large_timing()), flush=True)
         return
@@ -158,7 +165,8 @@ def main():
     if args.extra_rooflines:
         out.update(extra_rooflines())
     if args.serve_requests > 0:
-        out["serving"] = serving_bench(args.serve_requests, args.serve_workers)
+        rates = tuple(float(r) for r in args.serve_rates.split(","))
+        out["serving"] = serving_bench(args.serve_requests, args.serve_workers, rates)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, info["iters"])
     print(json.dumps(out), flush=True)
@@ -277,19 +285,23 @@ def _pctl(x, q):
     return float(np.percentile(np.asarray(x), q)) * 1e3
 
 
-def serving_bench(n_req, workers):
+def serving_bench(n_req, workers, rates=(0.8,)):
     """Continuous batching vs the plain per-request float64 solve (FIFO, one at
     a time) on the same Poisson arrival trace of 2-D heat requests with grids
     drawn from {16,32,48,64}^2 x {16,24,32} cells and GP-drawn initial data.
     Every solve: IterGP-CG to 1e-6 or 256 iterations, posterior on 8 time
-    slices of the cell-centre grid.  Latency = completion - arrival."""
+    slices of the cell-centre grid.  Latency = completion - arrival.  The
+    saturated throughput (all requests queued at t = 0) is measured first; each
+    entry of `rates` is an arrival rate as a fraction of it.  The top-level
+    figures are those of the first rate."""
     import numpy as np
     import torch
     import paper_2406_05020_amd as G
     import workloads as W
 
-    # saturated throughput first (all requests queued at t = 0), then a Poisson
-    # trace at 0.8x that rate
+    def note(msg):
+        print(f"[serving] {msg}", file=sys.stderr, flush=True)
+
     probe = [W.heat2d_request(ns, nt, seed) for (_, ns, nt, seed) in W.serving_trace(n_req, 1.0, seed=5)]
     with G.Server(workers=workers, hbm_budget=96 << 30, prec=G.PREC_FP64, tol=SERVE_TOL,
                   max_iter=SERVE_ITERS) as S:
@@ -298,57 +310,67 @@ def serving_bench(n_req, workers):
         for t in tk:
             S.poll(t, wait=True)
         sat = n_req / (time.perf_counter() - t0)
-    rate = 0.8 * sat
-    trace = W.serving_trace(n_req, rate, seed=5)
-    reqs = [(arr, W.heat2d_request(ns, nt, seed)) for (arr, ns, nt, seed) in trace]
+    note(f"saturated {sat:.2f} solves/s")
+    dev = torch.device("cuda:0")
+    runs = []
+    for frac in rates:
+        rate = frac * sat
+        trace = W.serving_trace(n_req, rate, seed=5)
+        reqs = [(arr, W.heat2d_request(ns, nt, seed)) for (arr, ns, nt, seed) in trace]
 
-    # continuous batching
-    lat = []
-    with G.Server(workers=workers, hbm_budget=96 << 30, prec=G.PREC_FP64, tol=SERVE_TOL,
-                  max_iter=SERVE_ITERS) as S:
+        # continuous batching
+        lat = []
+        with G.Server(workers=workers, hbm_budget=96 << 30, prec=G.PREC_FP64, tol=SERVE_TOL,
+                      max_iter=SERVE_ITERS) as S:
+            start = time.perf_counter()
+            tickets = []
+            for arr, q in reqs:
+                now = time.perf_counter() - start
+                if arr > now:
+                    time.sleep(arr - now)
+                tickets.append((arr, S.submit(q)))
+            for arr, t in tickets:
+                _, res, _, _ = S.poll(t, wait=True)
+                # t_done comes from the library's std::chrono::steady_clock, the
+                # same CLOCK_MONOTONIC that time.perf_counter reads on Linux
+                lat.append(res["t_done"] - (start + arr))
+            makespan = time.perf_counter() - start
+            stats = S.stats()
+        note(f"rate {frac:g}x: served {n_req / makespan:.2f} solves/s")
+
+        # plain float64 per-request solve, FIFO, one at a time, same arrivals
+        lat_fifo = []
         start = time.perf_counter()
-        tickets = []
-        for arr, q in reqs:
+        for k, (arr, q) in enumerate(reqs):
             now = time.perf_counter() - start
             if arr > now:
                 time.sleep(arr - now)
-            tickets.append((arr, S.submit(q)))
-        for arr, t in tickets:
-            _, res, _, _ = S.poll(t, wait=True)
-            # t_done comes from the library's std::chrono::steady_clock, the
-            # same CLOCK_MONOTONIC that time.perf_counter reads on Linux
-            lat.append(res["t_done"] - (start + arr))
-        makespan = time.perf_counter() - start
-        stats = S.stats()
-
-    # plain float64 per-request solve, FIFO, one at a time, same arrivals
-    dev = torch.device("cuda:0")
-    lat_fifo = []
-    start = time.perf_counter()
-    for arr, q in reqs:
-        now = time.perf_counter() - start
-        if arr > now:
-            time.sleep(arr - now)
-        h = G.assemble(q, max_iter=SERVE_ITERS)
-        try:
-            G.solve(h, tol=SERVE_TOL, max_iter=SERVE_ITERS, check_every=16)
-            M = int(np.prod([len(a) for a in q.grid]))
-            mean = torch.empty(M, dtype=torch.float64, device=dev)
-            var = torch.empty(M, dtype=torch.float64, device=dev)
-            G.posterior(h, q.grid, mean, var)
-            torch.cuda.synchronize()
-        finally:
-            G.destroy(h)
-        lat_fifo.append(time.perf_counter() - start - arr)
-    makespan_fifo = time.perf_counter() - start
-    return {
-        "requests": n_req, "workers": workers, "arrival_rate_per_s": rate, "saturated_solves_per_s": sat,
-        "solves_per_s": n_req / makespan, "p50_ms": _pctl(lat, 50), "p99_ms": _pctl(lat, 99),
-        "fifo_fp64_solves_per_s": n_req / makespan_fifo, "fifo_fp64_p50_ms": _pctl(lat_fifo, 50),
-        "fifo_fp64_p99_ms": _pctl(lat_fifo, 99), "peak_in_flight": stats["peak_in_flight"],
-        "peak_reserved_gb": stats["peak_reserved_bytes"] / 2 ** 30,
-        "solve": f"fp64 IterGP-CG, tol {SERVE_TOL:g} or {SERVE_ITERS} iterations",
-    }
+            h = G.assemble(q, max_iter=SERVE_ITERS)
+            try:
+                G.solve(h, tol=SERVE_TOL, max_iter=SERVE_ITERS, check_every=16)
+                M = int(np.prod([len(a) for a in q.grid]))
+                mean = torch.empty(M, dtype=torch.float64, device=dev)
+                var = torch.empty(M, dtype=torch.float64, device=dev)
+                G.posterior(h, q.grid, mean, var)
+                torch.cuda.synchronize()
+            finally:
+                G.destroy(h)
+            lat_fifo.append(time.perf_counter() - start - arr)
+            if (k + 1) % 64 == 0:
+                note(f"rate {frac:g}x: fifo {k + 1}/{n_req}")
+        makespan_fifo = time.perf_counter() - start
+        runs.append({
+            "rate_fraction": frac, "arrival_rate_per_s": rate,
+            "solves_per_s": n_req / makespan, "p50_ms": _pctl(lat, 50), "p99_ms": _pctl(lat, 99),
+            "fifo_fp64_solves_per_s": n_req / makespan_fifo, "fifo_fp64_p50_ms": _pctl(lat_fifo, 50),
+            "fifo_fp64_p99_ms": _pctl(lat_fifo, 99), "peak_in_flight": stats["peak_in_flight"],
+            "peak_reserved_gb": stats["peak_reserved_bytes"] / 2 ** 30,
+        })
+    out = {"requests": n_req, "workers": workers, "saturated_solves_per_s": sat, **runs[0],
+           "solve": f"fp64 IterGP-CG, tol {SERVE_TOL:g} or {SERVE_ITERS} iterations"}
+    if len(runs) > 1:
+        out["by_rate"] = runs
+    return out
 
 
 def cpu_baseline(p, iters):

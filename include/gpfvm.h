@@ -56,11 +56,12 @@ extern "C" {
 #define GPFVM_PREC_MIXED     1   /* Gram matvec in low precision inside FP64
                                     iterative refinement; FP64 recurrences           */
 
-#define GPFVM_TILE_FP32      0   /* mixed-path tile formats (see gpfvm_solve_opts)   */
-#define GPFVM_TILE_BF16X3    1
-#define GPFVM_TILE_FP16X2    2
-#define GPFVM_TILE_BF16      3
-#define GPFVM_TILE_FP16      4
+#define GPFVM_TILE_FP32      0   /* the one mixed-path tile format: float32 factor
+                                    tiles, float32 accumulation.  Narrower formats
+                                    are not provided: the volume Gram is a sum of
+                                    Kronecker terms that cancel to far below their
+                                    size, so even float32 loses the small
+                                    eigenvalues (any other value: GPFVM_E_INVALID) */
 
 typedef struct gpfvm_handle gpfvm_handle;
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgpfvm.so")
 
 OK, E_INVALID, E_NOMEM, E_HIP, E_NOTPD, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_MIXED = 0, 1
-TILE_FP32, TILE_BF16X3, TILE_FP16X2, TILE_BF16, TILE_FP16 = 0, 1, 2, 3, 4
+TILE_FP32 = 0        # the only mixed-path tile format
 MAX_DIM, MAX_TERMS, MAX_GROUPS = 3, 8, 16
 ERR_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOTPD", -5: "NOCONV", -6: "STATE"}
 

@@ -513,26 +513,37 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
   return GPFVM_OK;
 }
 
-int gpfvm_assemble_cached(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream, DeviceCache* cache,
-                          gpfvm_handle** out);
-
-extern "C" int gpfvm_assemble(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream,
-                              gpfvm_handle** out) {
-  const bool reuse = !opts || opts->reuse_memory != 0;
-  DeviceCache* cache = reuse ? process_cache() : nullptr;
-  const int rc = gpfvm_assemble_cached(p, opts, stream, cache, out);
-  if (rc == GPFVM_OK && out && *out) (*out)->process_cache = (cache != nullptr);
-  return rc;
-}
-
-int gpfvm_assemble_cached(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream, DeviceCache* cache,
-                          gpfvm_handle** out) {
+// Host-side checks of the assemble arguments (no HIP call).
+static int check_assemble_args(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, gpfvm_handle** out) {
   if (!out) return fail_static(GPFVM_E_INVALID, "out is NULL");
   *out = nullptr;
   int rc = gpfvm_validate(p);
   if (rc) return rc;
   if (opts && (opts->max_iter < 1 || opts->max_iter > (1 << 20)))
     return fail_static(GPFVM_E_INVALID, "max_iter out of range");
+  if (opts && opts->tile != GPFVM_TILE_FP32)
+    return fail_static(GPFVM_E_INVALID, "tile: only GPFVM_TILE_FP32 is provided");
+  return GPFVM_OK;
+}
+
+int gpfvm_assemble_cached(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream, DeviceCache* cache,
+                          gpfvm_handle** out);
+
+extern "C" int gpfvm_assemble(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream,
+                              gpfvm_handle** out) {
+  int rc = check_assemble_args(p, opts, out);
+  if (rc) return rc;
+  const bool reuse = !opts || opts->reuse_memory != 0;
+  DeviceCache* cache = reuse ? process_cache() : nullptr;
+  rc = gpfvm_assemble_cached(p, opts, stream, cache, out);
+  if (rc == GPFVM_OK && out && *out) (*out)->process_cache = (cache != nullptr);
+  return rc;
+}
+
+int gpfvm_assemble_cached(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream, DeviceCache* cache,
+                          gpfvm_handle** out) {
+  int rc = check_assemble_args(p, opts, out);
+  if (rc) return rc;
   gpfvm_handle* h = new (std::nothrow) gpfvm_handle();
   if (!h) return fail_static(GPFVM_E_NOMEM, "host allocation failed");
   h->arena.cache = cache;

@@ -670,6 +670,7 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
   gpfvm_default_solve_opts(&def);
   if (!o) o = &def;
   if (o->prec != GPFVM_PREC_FP64 && o->prec != GPFVM_PREC_MIXED) { h->err = "solve: bad prec"; return GPFVM_E_INVALID; }
+  if (o->tile != GPFVM_TILE_FP32) { h->err = "solve: only GPFVM_TILE_FP32 is provided"; return GPFVM_E_INVALID; }
   if (o->max_iter < 0 || !(o->tol >= 0) || o->check_every < 1 || o->max_outer < 1 || !(o->inner_tol > 0) ||
       o->reorth_passes < 1 || o->reorth_passes > 2 || o->replace_every < 1) {
     h->err = "solve: bad options";

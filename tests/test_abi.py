@@ -84,3 +84,15 @@ def test_null_handle_calls_are_rejected(G):
     assert L.gpfvm_posterior(None, 2, None, None, None, None, None) == G.E_INVALID
     L.gpfvm_destroy(None)   # accepted
     assert isinstance(G.last_error(None), str)
+
+
+def test_assemble_option_checks_happen_on_the_host(G):
+    """Only the float32 tile format exists; max_iter is bounded.  Both are
+    rejected before any device call."""
+    p = W.heat1d_c1()
+    with pytest.raises(G.GpfvmError) as e:
+        G.assemble(p, tile=3, stream=0)
+    assert e.value.code == G.E_INVALID and "tile" in str(e.value)
+    with pytest.raises(G.GpfvmError) as e:
+        G.assemble(p, max_iter=0, stream=0)
+    assert e.value.code == G.E_INVALID and "max_iter" in str(e.value)
