@@ -19,7 +19,8 @@ typedef long long i64;
 
 // ---------------------------------------------------------------------------
 // Grouped, batched, multi-segment GEMM descriptor.  One launch processes the
-// 32x32 output tiles of every descriptor in an array.  For descriptor D and
+// output tiles (32x32 or 64x64, by the stage's kernel) of every descriptor in
+// an array.  For descriptor D and
 // batch b:
 //   acc_s = sum over segments g with slot s of  alpha_g * A_g[b] (M x K_g) * B_g[b] (K_g x N)
 //   C[b]  = acc_0 + escale[b] o acc_1 + gamma * X[b] + beta * C[b]

@@ -271,3 +271,34 @@ def test_memory_reuse_gives_identical_results_and_releases(G):
     assert G.release_cached_memory() == 0
     it, m, v = run(True)
     assert np.array_equal(m, ref[1])
+
+
+POINT_SOLVE_CASES = {
+    # n_b = 512 <= the one-workgroup limit, and 8 n_b N above the resident-Q budget:
+    # one right-hand side goes through the one-workgroup refined triangular solves
+    "one_workgroup_solve": (lambda: W.advdiff_c2(nt=256, nx=260, n_ic=512), 1),
+    # n_b = 2112 with two right-hand sides: the point-block products are GEMV-shaped
+    # (few output tiles, K = n_b > 2048) and run on the split-K GEMM
+    "split_k_products": (lambda: W.heat2d_c3(nt=8, nx=16, ny=16, n_ic=24, n_bt=24, n_bs=16), 2),
+}
+
+
+@pytest.mark.parametrize("name", list(POINT_SOLVE_CASES))
+def test_point_correction_paths_match_oracle(G, name):
+    """The volume-system operator on the point-solve paths that the standard
+    workloads do not reach, against the oracle's Cholesky solve."""
+    make, nrhs = POINT_SOLVE_CASES[name]
+    p = make()
+    S = SchurSystem(O.Oracle(p))
+    rng = np.random.default_rng(23)
+    X = rng.standard_normal((nrhs, p.n_pde))
+    h = G.assemble(p, max_iter=8)
+    try:
+        y = torch.empty(nrhs * p.n_pde, dtype=torch.float64, device="cuda:0")
+        G.schur_matvec(h, dev(X.ravel()), y, nrhs=nrhs)
+        Y = host(y).reshape(nrhs, -1)
+        for r in range(nrhs):
+            ref = S.matvec(X[r])
+            assert relerr(Y[r], ref) <= 1e-10, (r, relerr(Y[r], ref))
+    finally:
+        G.destroy(h)
