@@ -33,7 +33,7 @@ import numpy as np
 import scipy.linalg as sla
 
 __all__ = [
-    "load_quad", "cell_cell", "point_cell", "point_point", "Oracle",
+    "load_quad", "kernel_q", "cell_cell", "point_cell", "point_point", "Oracle",
     "dense_posterior", "itergp", "cg_solve",
 ]
 
@@ -59,14 +59,15 @@ def load_quad():
         d, i, p = ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
         for name, args, res in [
             ("ora_kder", [i, d, d], d),
-            ("ora_point_point", [i, i, d, d, d], d),
-            ("ora_point_cell", [i, i, d, d, d, d], d),
-            ("ora_cell_cell", [i, i, d, d, d, d, d], d),
-            ("ora_integrate_kder", [i, d, d, d], d),
+            ("ora_kder_k", [i, i, d, d], d),
+            ("ora_point_point", [i, i, i, d, d, d], d),
+            ("ora_point_cell", [i, i, i, d, d, d, d], d),
+            ("ora_cell_cell", [i, i, i, d, d, d, d, d], d),
+            ("ora_integrate_kder", [i, i, d, d, d], d),
             ("ora_qk15_monomial", [i, d, d, p, p], None),
-            ("ora_cell_cell_matrix", [i, i, i, p, i, p, d, p], None),
-            ("ora_point_cell_matrix", [i, i, i, p, i, p, d, p], None),
-            ("ora_point_point_matrix", [i, i, i, p, i, p, d, p], None),
+            ("ora_cell_cell_matrix", [i, i, i, i, p, i, p, d, p], None),
+            ("ora_point_cell_matrix", [i, i, i, i, p, i, p, d, p], None),
+            ("ora_point_point_matrix", [i, i, i, i, p, i, p, d, p], None),
         ]:
             f = getattr(lib, name)
             f.argtypes, f.restype = args, res
@@ -82,27 +83,45 @@ def _ptr(a: np.ndarray):
 # 1-D factors (Sec. 3.1 eq. linop-def-univariate; Sec. 3.2 eq. LkL)
 # ---------------------------------------------------------------------------
 
-def cell_cell(p: int, q: int, e1: np.ndarray, e2: np.ndarray, ell: float) -> np.ndarray:
+def kernel_q(code: int) -> int:
+    """Per-dimension kernel code -> oracle selector: 0 (squared exponential)
+    -> -1; 1..4 (Matern nu = 1/2, 3/2, 5/2, 7/2) -> q with nu = q + 1/2."""
+    return -1 if code == 0 else code - 1
+
+
+def _check_order(kq: int, m: int):
+    # Matern-(q+1/2) has 2q continuous derivatives; the integrated blocks also
+    # accept one order more (a finite jump at r = 0).  Beyond that the
+    # pointwise derivative misses a singular part.
+    if kq >= 0 and m > 2 * kq + 1:
+        raise ValueError(f"derivative order {m} exceeds the smoothness of Matern-{kq}+1/2")
+
+
+def cell_cell(p: int, q: int, e1: np.ndarray, e2: np.ndarray, ell: float, kq: int = -1) -> np.ndarray:
     """F^{pq}[i, j] = int_{I_i} int_{I'_j} d^p_s d^q_{s'} k(s, s') ds' ds."""
+    _check_order(kq, p + q)
     e1 = np.ascontiguousarray(e1, float); e2 = np.ascontiguousarray(e2, float)
     out = np.empty((len(e1) - 1, len(e2) - 1))
-    load_quad().ora_cell_cell_matrix(p, q, len(e1) - 1, _ptr(e1), len(e2) - 1, _ptr(e2), ell, _ptr(out))
+    load_quad().ora_cell_cell_matrix(kq, p, q, len(e1) - 1, _ptr(e1), len(e2) - 1, _ptr(e2), ell, _ptr(out))
     return out
 
 
-def point_cell(p: int, q: int, x: np.ndarray, e2: np.ndarray, ell: float) -> np.ndarray:
+def point_cell(p: int, q: int, x: np.ndarray, e2: np.ndarray, ell: float, kq: int = -1) -> np.ndarray:
     """Q^{pq}[i, j] = int_{I'_j} d^p_x d^q_{s'} k(x_i, s') ds'."""
+    _check_order(kq, p + q)
     x = np.ascontiguousarray(x, float); e2 = np.ascontiguousarray(e2, float)
     out = np.empty((len(x), len(e2) - 1))
-    load_quad().ora_point_cell_matrix(p, q, len(x), _ptr(x), len(e2) - 1, _ptr(e2), ell, _ptr(out))
+    load_quad().ora_point_cell_matrix(kq, p, q, len(x), _ptr(x), len(e2) - 1, _ptr(e2), ell, _ptr(out))
     return out
 
 
-def point_point(p: int, q: int, x: np.ndarray, x2: np.ndarray, ell: float) -> np.ndarray:
+def point_point(p: int, q: int, x: np.ndarray, x2: np.ndarray, ell: float, kq: int = -1) -> np.ndarray:
     """P^{pq}[i, j] = d^p_x d^q_{x'} k(x_i, x'_j)."""
+    if kq >= 0 and p + q > 2 * kq:
+        raise ValueError(f"derivative order {p + q} exceeds the smoothness of Matern-{kq}+1/2")
     x = np.ascontiguousarray(x, float); x2 = np.ascontiguousarray(x2, float)
     out = np.empty((len(x), len(x2)))
-    load_quad().ora_point_point_matrix(p, q, len(x), _ptr(x), len(x2), _ptr(x2), ell, _ptr(out))
+    load_quad().ora_point_point_matrix(kq, p, q, len(x), _ptr(x), len(x2), _ptr(x2), ell, _ptr(out))
     return out
 
 
@@ -128,6 +147,7 @@ class Oracle:
         self.p = ibvp
         self.d = ibvp.d
         self.ell = tuple(float(l) for l in ibvp.lengthscale)
+        self.kq = tuple(kernel_q(c) for c in ibvp.kernel_codes())
         self.sf2 = float(ibvp.outputscale)
         self._cache: Dict[tuple, np.ndarray] = {}
         self.N = ibvp.n_pde
@@ -139,7 +159,7 @@ class Oracle:
         key = ("F", dim, p, q)
         if key not in self._cache:
             e = self.p.edges[dim]
-            self._cache[key] = cell_cell(p, q, e, e, self.ell[dim])
+            self._cache[key] = cell_cell(p, q, e, e, self.ell[dim], self.kq[dim])
         return self._cache[key]
 
     def term_coef(self, term) -> np.ndarray:
@@ -197,7 +217,7 @@ class Oracle:
         for g1 in gs:
             row = []
             for g2 in gs:
-                mats = [point_point(g1.deriv[i], g2.deriv[i], g1.axes[i], g2.axes[i], self.ell[i])
+                mats = [point_point(g1.deriv[i], g2.deriv[i], g1.axes[i], g2.axes[i], self.ell[i], self.kq[i])
                         for i in range(self.d)]
                 row.append(self.sf2 * _kron_all(mats))
             blocks.append(row)
@@ -211,7 +231,7 @@ class Oracle:
     def pc_cached(self, g, dim, p, q):
         key = ("Q", id(g), dim, p, q)
         if key not in self._cache:
-            self._cache[key] = point_cell(p, q, g.axes[dim], self.p.edges[dim], self.ell[dim])
+            self._cache[key] = point_cell(p, q, g.axes[dim], self.p.edges[dim], self.ell[dim], self.kq[dim])
         return self._cache[key]
 
     def cross_gram(self) -> np.ndarray:
@@ -263,7 +283,7 @@ class Oracle:
         M = X.shape[0]
         kb = []
         for g in self.p.groups:
-            mats = [point_point(g.deriv[i], 0, g.axes[i], X[:, i], self.ell[i]) for i in range(self.d)]
+            mats = [point_point(g.deriv[i], 0, g.axes[i], X[:, i], self.ell[i], self.kq[i]) for i in range(self.d)]
             # group tensor grid x each evaluation point: product over dims
             blk = np.ones((g.size, M))
             idx = np.indices(g.shape).reshape(self.d, -1)
@@ -276,7 +296,7 @@ class Oracle:
             blk = np.ones((self.N, M))
             for i in range(self.d):
                 # L_[a,b];alpha applied to the first argument of k(., x)
-                q = point_cell(0, t.alpha[i], X[:, i], self.p.edges[i], self.ell[i])  # M x N_i
+                q = point_cell(0, t.alpha[i], X[:, i], self.p.edges[i], self.ell[i], self.kq[i])  # M x N_i
                 blk *= q.T[idx[i], :]
             kp += self.term_coef(t)[:, None] * blk
         return np.vstack(kb), self.sf2 * kp

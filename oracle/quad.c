@@ -13,16 +13,22 @@
  *     Q^{pq}(x,I') = int_I' d^p/dx^p d^q/ds'^q k(x,s') ds'
  *     P^{pq}(x,x') = d^p/dx^p d^q/dx'^q k(x,x')
  *
- * with k(s,s') = exp(-(s-s')^2 / (2 l^2)).  No antiderivative, no erf and no
- * fundamental-theorem-of-calculus reduction is used here: the derivative is
- * evaluated pointwise from the Hermite representation
+ * for the squared-exponential kernel k(s,s') = exp(-(s-s')^2 / (2 l^2))
+ * (kq = -1) and for the half-integer Matern kernels (Sec. 3.1: nu = kq + 1/2,
+ * k(r) = exp(-c |r| / l) p_kq(c |r| / l) with c = sqrt(2 kq + 1)).  No
+ * antiderivative, no erf and no fundamental-theorem-of-calculus reduction is
+ * used here: the derivative is evaluated pointwise -- for SE from the Hermite
+ * representation
  *
  *     d^m/dr^m exp(-z^2) |_{z = r/(sqrt2 l)} = (-1/(sqrt2 l))^m H_m(z) e^{-z^2}
  *
- * (physicists' Hermite polynomials, three-term recurrence) and the chain rule
- * d/ds' = -d/dr for r = s - s'.  The integrals are computed by recursive
- * bisection with the 7-point Gauss / 15-point Kronrod pair (QUADPACK's QK15
- * rule), nested for the double integral.
+ * (physicists' Hermite polynomials, three-term recurrence), for Matern by the
+ * Leibniz rule on exp(-s) p(s) -- and the chain rule d/ds' = -d/dr for
+ * r = s - s'.  The integrals are computed by recursive bisection with the
+ * 7-point Gauss / 15-point Kronrod pair (QUADPACK's QK15 rule), nested for the
+ * double integral; for Matern the panels are split where the integrand is not
+ * smooth (r = 0, hence s' = s inside a cell and s at the ends of the inner
+ * cell).
  */
 #include <math.h>
 #include <stddef.h>
@@ -63,10 +69,59 @@ double ora_kder(int m, double r, double ell)
     return s * hm * exp(-z * z);
 }
 
-/* d^p/dx^p d^q/dx'^q k(x, x'); r = x - x', each d/dx' contributes -d/dr. */
-double ora_point_point(int p, int q, double x, double x2, double ell)
+/* Coefficients of p_kq (Rasmussen & Williams eq. 4.16 written in s = c r / l):
+ * p_kq(s) = kq!/(2kq)! sum_{i=0}^{kq} (kq+i)!/(i! (kq-i)!) (2s)^(kq-i). */
+static void matern_poly(int kq, double* coef)
 {
-    double v = ora_kder(p + q, x - x2, ell);
+    double f[16];
+    f[0] = 1.0;
+    for (int i = 1; i < 16; ++i) f[i] = f[i - 1] * i;
+    for (int k = 0; k <= kq; ++k) coef[k] = 0.0;
+    for (int i = 0; i <= kq; ++i) {
+        const int deg = kq - i;
+        coef[deg] += f[kq] / f[2 * kq] * f[kq + i] / (f[i] * f[kq - i]) * pow(2.0, deg);
+    }
+}
+
+/* m-th derivative in r of the Matern-(kq+1/2) kernel, m >= 0, by the Leibniz
+ * rule on exp(-s) p(s), s = c |r| / l; even in r, so odd derivatives flip sign
+ * for r < 0 and vanish at r = 0. */
+double ora_kder_matern(int kq, int m, double r, double ell)
+{
+    double p[8], binom = 1.0, acc = 0.0;
+    matern_poly(kq, p);
+    const double c = sqrt(2.0 * kq + 1.0);
+    const double s = c * fabs(r) / ell;
+    for (int j = 0; j <= m; ++j) {
+        /* j-th derivative of p at s */
+        double dj = 0.0;
+        for (int k = j; k <= kq; ++k) {
+            double fall = 1.0;
+            for (int t = 0; t < j; ++t) fall *= (double)(k - t);
+            dj += p[k] * fall * pow(s, k - j);
+        }
+        const double sign = ((m - j) & 1) ? -1.0 : 1.0;
+        acc += binom * sign * dj;
+        binom = binom * (m - j) / (j + 1);
+    }
+    double v = acc * exp(-s) * pow(c / ell, m);
+    if (m & 1) {
+        if (r < 0) v = -v;
+        else if (r == 0) v = 0.0;
+    }
+    return v;
+}
+
+/* kq < 0: squared exponential; kq >= 0: Matern nu = kq + 1/2. */
+double ora_kder_k(int kq, int m, double r, double ell)
+{
+    return kq < 0 ? ora_kder(m, r, ell) : ora_kder_matern(kq, m, r, ell);
+}
+
+/* d^p/dx^p d^q/dx'^q k(x, x'); r = x - x', each d/dx' contributes -d/dr. */
+double ora_point_point(int kq, int p, int q, double x, double x2, double ell)
+{
+    double v = ora_kder_k(kq, p + q, x - x2, ell);
     return (q & 1) ? -v : v;
 }
 
@@ -89,21 +144,24 @@ static void qk15(integrand_t f, const void* ctx, double a, double b,
 }
 
 static double adapt(integrand_t f, const void* ctx, double a, double b,
-                    double tol, int depth)
+                    double tol, int depth, long* budget)
 {
     double k, g, ab;
     qk15(f, ctx, a, b, &k, &g, &ab);
+    --*budget;
     /* accept on the requested tolerance, or once the Kronrod-Gauss gap is at
-       the rounding level of this panel (further bisection cannot help). */
+       the rounding level of this panel (further bisection cannot help), or
+       when the depth or the panel budget of this integral is spent. */
     if (fabs(k - g) <= tol || fabs(k - g) <= 50.0 * 2.220446049250313e-16 * ab ||
-        depth >= 30)
+        depth >= 30 || *budget <= 0)
         return k;
     const double m = 0.5 * (a + b);
-    return adapt(f, ctx, a, m, 0.5 * tol, depth + 1) +
-           adapt(f, ctx, m, b, 0.5 * tol, depth + 1);
+    return adapt(f, ctx, a, m, 0.5 * tol, depth + 1, budget) +
+           adapt(f, ctx, m, b, 0.5 * tol, depth + 1, budget);
 }
 
-/* Integral of f over [a,b], to absolute error ~ rel * int |f| (plus a floor). */
+/* Integral of f over [a,b], to absolute error ~ rel * int |f| (plus a floor);
+   at most 4096 QK15 panels. */
 static double integrate(integrand_t f, const void* ctx, double a, double b, double rel)
 {
     if (a == b) return 0.0;
@@ -111,52 +169,72 @@ static double integrate(integrand_t f, const void* ctx, double a, double b, doub
     qk15(f, ctx, a, b, &k, &g, &ab);
     double tol = rel * ab;
     if (tol < 1e-300) tol = 1e-300;
-    return adapt(f, ctx, a, b, tol, 0);
+    long budget = 4096;
+    return adapt(f, ctx, a, b, tol, 0, &budget);
 }
 
-typedef struct { int m; double x; double ell; double sign; } pc_ctx;
+typedef struct { int kq; int m; double x; double ell; double sign; } pc_ctx;
 
 /* integrand s' -> d^p/dx^p d^q/ds'^q k(x, s') with m = p + q folded in. */
 static double pc_f(double s2, const void* vc)
 {
     const pc_ctx* c = (const pc_ctx*)vc;
-    return c->sign * ora_kder(c->m, c->x - s2, c->ell);
+    return c->sign * ora_kder_k(c->kq, c->m, c->x - s2, c->ell);
 }
 
 static const double REL_INNER = 1e-14;
 static const double REL_OUTER = 1e-14;
+static const double REL_OUTER_MATERN = 1e-12;
 
-double ora_point_cell(int p, int q, double x, double a2, double b2, double ell)
+/* Integral over [a,b] split at the points of cuts[] that fall inside. */
+static double integrate_split(integrand_t f, const void* ctx, double a, double b, double rel,
+                              const double* cuts, int ncut)
 {
-    pc_ctx c = {p + q, x, ell, (q & 1) ? -1.0 : 1.0};
-    return integrate(pc_f, &c, a2, b2, REL_INNER);
+    double pts[4];
+    int n = 0;
+    pts[n++] = a;
+    for (int k = 0; k < ncut; ++k)
+        if (cuts[k] > pts[n - 1] && cuts[k] < b) pts[n++] = cuts[k];
+    double v = 0.0;
+    for (int k = 0; k < n; ++k) v += integrate(f, ctx, pts[k], k + 1 < n ? pts[k + 1] : b, rel);
+    return v;
 }
 
-typedef struct { int p, q; double a2, b2, ell; } cc_ctx;
+double ora_point_cell(int kq, int p, int q, double x, double a2, double b2, double ell)
+{
+    pc_ctx c = {kq, p + q, x, ell, (q & 1) ? -1.0 : 1.0};
+    return integrate_split(pc_f, &c, a2, b2, REL_INNER, &x, kq >= 0 ? 1 : 0);
+}
+
+typedef struct { int kq, p, q; double a2, b2, ell; } cc_ctx;
 
 static double cc_f(double s, const void* vc)
 {
     const cc_ctx* c = (const cc_ctx*)vc;
-    return ora_point_cell(c->p, c->q, s, c->a2, c->b2, c->ell);
+    return ora_point_cell(c->kq, c->p, c->q, s, c->a2, c->b2, c->ell);
 }
 
-double ora_cell_cell(int p, int q, double a, double b, double a2, double b2, double ell)
+double ora_cell_cell(int kq, int p, int q, double a, double b, double a2, double b2, double ell)
 {
-    cc_ctx c = {p, q, a2, b2, ell};
-    return integrate(cc_f, &c, a, b, REL_OUTER);
+    cc_ctx c = {kq, p, q, a2, b2, ell};
+    const double cuts[2] = {a2 < b2 ? a2 : b2, a2 < b2 ? b2 : a2};
+    /* for Matern the inner integral is split at the moving kink, so its value
+       carries rounding noise near 1e-14: the outer rule asks for less */
+    return integrate_split(cc_f, &c, a, b, kq >= 0 ? REL_OUTER_MATERN : REL_OUTER, cuts, kq >= 0 ? 2 : 0);
 }
 
 /* Generic integral of d^m k(r) over [a,b] in r (used to pin the rule). */
-typedef struct { int m; double ell; } r_ctx;
+typedef struct { int kq; int m; double ell; } r_ctx;
 static double r_f(double r, const void* vc)
 {
     const r_ctx* c = (const r_ctx*)vc;
-    return ora_kder(c->m, r, c->ell);
+    return ora_kder_k(c->kq, c->m, r, c->ell);
 }
-double ora_integrate_kder(int m, double a, double b, double ell)
+double ora_integrate_kder(int kq, int m, double a, double b, double ell)
 {
-    r_ctx c = {m, ell};
-    return integrate(r_f, &c, a, b, 1e-14);
+    r_ctx c = {kq, m, ell};
+    const double zero = 0.0;
+    return integrate_split(r_f, &c, a, b, 1e-14, &zero, kq >= 0 ? 1 : 0);
 }
 
 /* Polynomial x^k over [a,b] with a single QK15 panel (Kronrod and Gauss). */
@@ -175,28 +253,28 @@ void ora_qk15_monomial(int k, double a, double b, double* kron, double* gauss)
 /* ---- matrix builders (row-major outputs) --------------------------------- */
 
 /* out[i*n2 + j] = F^{pq}([e1[i],e1[i+1]], [e2[j],e2[j+1]]) */
-void ora_cell_cell_matrix(int p, int q, int n1, const double* e1, int n2,
+void ora_cell_cell_matrix(int kq, int p, int q, int n1, const double* e1, int n2,
                           const double* e2, double ell, double* out)
 {
     for (int i = 0; i < n1; ++i)
         for (int j = 0; j < n2; ++j)
-            out[(size_t)i * n2 + j] = ora_cell_cell(p, q, e1[i], e1[i + 1], e2[j], e2[j + 1], ell);
+            out[(size_t)i * n2 + j] = ora_cell_cell(kq, p, q, e1[i], e1[i + 1], e2[j], e2[j + 1], ell);
 }
 
 /* out[i*n2 + j] = Q^{pq}(x[i], [e2[j],e2[j+1]]) */
-void ora_point_cell_matrix(int p, int q, int n1, const double* x, int n2,
+void ora_point_cell_matrix(int kq, int p, int q, int n1, const double* x, int n2,
                            const double* e2, double ell, double* out)
 {
     for (int i = 0; i < n1; ++i)
         for (int j = 0; j < n2; ++j)
-            out[(size_t)i * n2 + j] = ora_point_cell(p, q, x[i], e2[j], e2[j + 1], ell);
+            out[(size_t)i * n2 + j] = ora_point_cell(kq, p, q, x[i], e2[j], e2[j + 1], ell);
 }
 
 /* out[i*n2 + j] = P^{pq}(x[i], x2[j]) */
-void ora_point_point_matrix(int p, int q, int n1, const double* x, int n2,
+void ora_point_point_matrix(int kq, int p, int q, int n1, const double* x, int n2,
                             const double* x2, double ell, double* out)
 {
     for (int i = 0; i < n1; ++i)
         for (int j = 0; j < n2; ++j)
-            out[(size_t)i * n2 + j] = ora_point_point(p, q, x[i], x2[j], ell);
+            out[(size_t)i * n2 + j] = ora_point_point(kq, p, q, x[i], x2[j], ell);
 }

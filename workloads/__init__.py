@@ -73,6 +73,11 @@ class IBVP:
     noise_pde_relative: bool = True          # True: variance = noise_pde * mean diag of the volume Gram
     grid: List[np.ndarray] = field(default_factory=list)   # posterior grid axes
     meta: dict = field(default_factory=dict)
+    # per-dimension kernel: 0 = squared exponential, 1..4 = Matern nu = 1/2, 3/2, 5/2, 7/2
+    kernel: Tuple[int, ...] = ()
+
+    def kernel_codes(self) -> Tuple[int, ...]:
+        return tuple(self.kernel[i] if i < len(self.kernel) else 0 for i in range(self.d))
 
     @property
     def ncell(self) -> Tuple[int, ...]:
