@@ -63,6 +63,17 @@ extern "C" {
                                     size, so even float32 loses the small
                                     eigenvalues (any other value: GPFVM_E_INVALID) */
 
+/* One-dimensional kernels of the tensor-product prior (Sec. 3.1-3.2).  The
+ * half-integer Matern kernels k(r) = exp(-c r/l) p_q(c r/l), c = sqrt(2q+1),
+ * nu = q + 1/2, admit derivative orders up to q in that dimension (PDE terms
+ * and point observations alike); the squared exponential admits any order up
+ * to GPFVM_MAX_DERIV. */
+#define GPFVM_KERNEL_SE        0
+#define GPFVM_KERNEL_MATERN12  1   /* q = 0 */
+#define GPFVM_KERNEL_MATERN32  2   /* q = 1 */
+#define GPFVM_KERNEL_MATERN52  3   /* q = 2 */
+#define GPFVM_KERNEL_MATERN72  4   /* q = 3 */
+
 typedef struct gpfvm_handle gpfvm_handle;
 
 /* One tensor grid of point observations  d^deriv u(x) = y + eps,
@@ -83,7 +94,8 @@ typedef struct {
   int dim;                            /* 2 or 3 (time + 1 or 2 space dims)           */
   int ncell[GPFVM_MAX_DIM];           /* cells per dim, >= 1                          */
   const double* edges[GPFVM_MAX_DIM]; /* host: ncell[i]+1 strictly increasing edges  */
-  double lengthscale[GPFVM_MAX_DIM];  /* SE lengthscale per dim, > 0                  */
+  double lengthscale[GPFVM_MAX_DIM];  /* lengthscale per dim, > 0                      */
+  int kernel[GPFVM_MAX_DIM];          /* GPFVM_KERNEL_* per dim (0: squared exponential)*/
   double outputscale;                 /* sigma_f^2 > 0                                */
   int nterm;                          /* 1..GPFVM_MAX_TERMS                           */
   const int* alpha;                   /* host: nterm*dim derivative multi-indices     */
@@ -218,8 +230,9 @@ int gpfvm_gram_block(gpfvm_handle* h, long long r0, long long nr, long long c0,
  *   kind 1  point-cell  out[i*n2+j] = int_{J_j} d^p_x d^q_s' k(x_i,s')
  *   kind 2  point-point out[i*n2+j] = d^p_x d^q_x' k(x_i,x'_j)
  * For cell arguments the host array holds n+1 edges, for points n coordinates.
- * 0 <= p, q and p+q <= 2*GPFVM_MAX_DERIV.  out: device, n1*n2 doubles. */
-int gpfvm_factor(int kind, int p, int q, int n1, const double* a1, int n2,
+ * kernel: GPFVM_KERNEL_*.  0 <= p, q and p+q <= 2*GPFVM_MAX_DERIV; for a Matern
+ * kernel also p, q <= its q.  out: device, n1*n2 doubles. */
+int gpfvm_factor(int kind, int kernel, int p, int q, int n1, const double* a1, int n2,
                  const double* a2, double lengthscale, double* out, void* stream);
 
 int gpfvm_get_info(const gpfvm_handle* h, gpfvm_handle_info* info);

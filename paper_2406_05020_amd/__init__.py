@@ -33,7 +33,8 @@ class PointGroup(C.Structure):
 
 class IBVPStruct(C.Structure):
     _fields_ = [("dim", C.c_int), ("ncell", C.c_int * MAX_DIM), ("edges", _dp * MAX_DIM),
-                ("lengthscale", C.c_double * MAX_DIM), ("outputscale", C.c_double), ("nterm", C.c_int),
+                ("lengthscale", C.c_double * MAX_DIM), ("kernel", C.c_int * MAX_DIM), ("outputscale", C.c_double),
+                ("nterm", C.c_int),
                 ("alpha", C.POINTER(C.c_int)), ("coef", _dp), ("cellwise", C.POINTER(C.c_int)),
                 ("cell_coef", _dp), ("f_int", _dp), ("noise_pde", C.c_double), ("noise_pde_relative", C.c_int),
                 ("ngroup", C.c_int), ("groups", C.POINTER(PointGroup))]
@@ -92,7 +93,8 @@ SYMBOLS = {
     "gpfvm_weights": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "gpfvm_gram_block": ([C.c_void_p, C.c_longlong, C.c_longlong, C.c_longlong, C.c_longlong, C.c_void_p,
                           C.c_longlong, C.c_void_p], C.c_int),
-    "gpfvm_factor": ([C.c_int, C.c_int, C.c_int, C.c_int, _dp, C.c_int, _dp, C.c_double, C.c_void_p, C.c_void_p],
+    "gpfvm_factor": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, C.c_int, _dp, C.c_double, C.c_void_p,
+                      C.c_void_p],
                      C.c_int),
     "gpfvm_get_info": ([C.c_void_p, C.POINTER(HandleInfo)], C.c_int),
     "gpfvm_default_server_opts": ([C.POINTER(ServerOpts)], None),
@@ -168,6 +170,7 @@ class _Marshal:
             s.ncell[i] = len(e) - 1
             s.edges[i] = e.ctypes.data_as(_dp)
             s.lengthscale[i] = float(p.lengthscale[i])
+            s.kernel[i] = int(p.kernel_codes()[i]) if i < p.d else 0
         s.outputscale = float(p.outputscale)
         terms = list(p.terms)
         s.nterm = len(terms)
@@ -276,11 +279,14 @@ def gram_block(h, r0: int, nr: int, c0: int, nc: int, out, ld: Optional[int] = N
     _check(lib().gpfvm_gram_block(h, r0, nr, c0, nc, C.c_void_p(out.data_ptr()), ld or nc, _stream(stream)), h)
 
 
-def factor(kind: int, p: int, q: int, a1, a2, lengthscale: float, out, stream=None) -> None:
+KERNEL_SE, KERNEL_MATERN12, KERNEL_MATERN32, KERNEL_MATERN52, KERNEL_MATERN72 = 0, 1, 2, 3, 4
+
+
+def factor(kind: int, p: int, q: int, a1, a2, lengthscale: float, out, stream=None, kernel: int = KERNEL_SE) -> None:
     a1 = _arr(a1); a2 = _arr(a2)
     n1 = len(a1) - 1 if kind == 0 else len(a1)
     n2 = len(a2) if kind == 2 else len(a2) - 1
-    _check(lib().gpfvm_factor(kind, p, q, n1, a1.ctypes.data_as(_dp), n2, a2.ctypes.data_as(_dp),
+    _check(lib().gpfvm_factor(kind, kernel, p, q, n1, a1.ctypes.data_as(_dp), n2, a2.ctypes.data_as(_dp),
                               float(lengthscale), C.c_void_p(out.data_ptr()), _stream(stream)))
 
 

@@ -107,8 +107,12 @@ extern "C" int gpfvm_validate(const gpfvm_ibvp* p) {
         return fail_static(GPFVM_E_INVALID, "edges[" + std::to_string(i) + "] not strictly increasing");
     if (!(p->lengthscale[i] > 0) || !std::isfinite(p->lengthscale[i]))
       return fail_static(GPFVM_E_INVALID, "lengthscale must be positive");
+    if (p->kernel[i] < GPFVM_KERNEL_SE || p->kernel[i] > GPFVM_KERNEL_MATERN72)
+      return fail_static(GPFVM_E_INVALID, "kernel[" + std::to_string(i) + "] unknown");
     N *= p->ncell[i];
   }
+  // a Matern-(q + 1/2) dimension admits derivative orders up to q
+  auto order_cap = [&](int i) { return p->kernel[i] == GPFVM_KERNEL_SE ? GPFVM_MAX_DERIV : p->kernel[i] - 1; };
   if (N > (1LL << 31) - 1) return fail_static(GPFVM_E_INVALID, "too many volumes");
   if (!(p->outputscale > 0) || !std::isfinite(p->outputscale))
     return fail_static(GPFVM_E_INVALID, "outputscale must be positive");
@@ -120,6 +124,9 @@ extern "C" int gpfvm_validate(const gpfvm_ibvp* p) {
       const int a = p->alpha[t * p->dim + i];
       if (a < 0 || a > GPFVM_MAX_DERIV)
         return fail_static(GPFVM_E_INVALID, "derivative order out of range [0, 4]");
+      if (a > order_cap(i))
+        return fail_static(GPFVM_E_INVALID, "derivative order above the smoothness of the Matern kernel in dim " +
+                                                std::to_string(i));
     }
     if (!std::isfinite(p->coef[t])) return fail_static(GPFVM_E_INVALID, "coef not finite");
     if (p->cellwise && p->cellwise[t]) any_cw = true;
@@ -143,6 +150,9 @@ extern "C" int gpfvm_validate(const gpfvm_ibvp* p) {
       if (!finite_arr(G.axis[i], G.n[i])) return fail_static(GPFVM_E_INVALID, "group axis not finite");
       if (G.deriv[i] < 0 || G.deriv[i] > GPFVM_MAX_DERIV)
         return fail_static(GPFVM_E_INVALID, "group derivative order out of range [0, 4]");
+      if (G.deriv[i] > order_cap(i))
+        return fail_static(GPFVM_E_INVALID, "group derivative order above the smoothness of the Matern kernel in dim " +
+                                                std::to_string(i));
       sz *= G.n[i];
     }
     if (!G.y) return fail_static(GPFVM_E_INVALID, "group " + std::to_string(g) + ": y is NULL");
@@ -165,13 +175,14 @@ static int upload(gpfvm_handle* h, const double* src, size_t n, double** dst) {
   return GPFVM_OK;
 }
 
+// Factor matrix of dimension `dim` (its lengthscale and kernel).
 static int make_factor(gpfvm_handle* h, int kind, int p, int q, int n1, const double* a1, int n2,
-                       const double* a2, double ell, Factor& f) {
+                       const double* a2, int dim, Factor& f) {
   f.n1 = n1;
   f.n2 = n2;
   f.d = (double*)h->arena.alloc((size_t)n1 * n2 * sizeof(double));
   if (!f.d) { h->err = "out of device memory (factor)"; return GPFVM_E_NOMEM; }
-  HIPCHK(h, launch_factor(kind, p, q, n1, a1, n2, a2, ell, 1.0, f.d, n2, h->stream));
+  HIPCHK(h, launch_factor(kind, h->kq[dim], p, q, n1, a1, n2, a2, h->ell[dim], 1.0, f.d, n2, h->stream));
   return GPFVM_OK;
 }
 
@@ -346,6 +357,7 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
     h->nc[i] = p->ncell[i];
     h->N *= p->ncell[i];
     h->ell[i] = p->lengthscale[i];
+    h->kq[i] = p->kernel[i] == GPFVM_KERNEL_SE ? -1 : p->kernel[i] - 1;
     h->edges_h[i].assign(p->edges[i], p->edges[i] + p->ncell[i] + 1);
   }
   h->sf2 = p->outputscale;
@@ -401,7 +413,7 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
       auto key = std::make_pair(i, g.m[i]);
       if (h->Dfac.count(key)) continue;
       Factor f;
-      if ((rc = make_factor(h, 0, g.m[i], 0, h->nc[i], h->edges[i], h->nc[i], h->edges[i], h->ell[i], f))) return rc;
+      if ((rc = make_factor(h, 0, g.m[i], 0, h->nc[i], h->edges[i], h->nc[i], h->edges[i], i, f))) return rc;
       h->Dfac[key] = f;
     }
   std::vector<std::array<double*, 3>> gaxis(h->groups.size());
@@ -413,7 +425,7 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
     for (size_t t = 0; t < h->pterms.size(); ++t)
       for (int i = 0; i < d; ++i)
         if ((rc = make_factor(h, 1, h->groups[g].deriv[i], h->pterms[t].alpha[i], h->groups[g].n[i], gaxis[g][i],
-                              h->nc[i], h->edges[i], h->ell[i], h->Qfac[g][t][i])))
+                              h->nc[i], h->edges[i], i, h->Qfac[g][t][i])))
           return rc;
   std::vector<Factor> ppf;
   GramMeta M;
@@ -423,7 +435,7 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
       for (int i = 0; i < d; ++i) {
         Factor f;
         if ((rc = make_factor(h, 2, h->groups[g1].deriv[i], h->groups[g2].deriv[i], h->groups[g1].n[i], gaxis[g1][i],
-                              h->groups[g2].n[i], gaxis[g2][i], h->ell[i], f)))
+                              h->groups[g2].n[i], gaxis[g2][i], i, f)))
           return rc;
         M.Pp[g1][g2][i] = f.d;
       }
@@ -692,10 +704,14 @@ extern "C" int gpfvm_gram_block(gpfvm_handle* h, long long r0, long long nr, lon
   return GPFVM_OK;
 }
 
-extern "C" int gpfvm_factor(int kind, int p, int q, int n1, const double* a1, int n2, const double* a2,
+extern "C" int gpfvm_factor(int kind, int kernel, int p, int q, int n1, const double* a1, int n2, const double* a2,
                             double lengthscale, double* out, void* stream) {
   if (kind < 0 || kind > 2) return fail_static(GPFVM_E_INVALID, "factor: kind must be 0, 1 or 2");
+  if (kernel < GPFVM_KERNEL_SE || kernel > GPFVM_KERNEL_MATERN72) return fail_static(GPFVM_E_INVALID, "factor: unknown kernel");
   if (p < 0 || q < 0 || p + q > 2 * GPFVM_MAX_DERIV) return fail_static(GPFVM_E_INVALID, "factor: bad orders");
+  const int kq = kernel == GPFVM_KERNEL_SE ? -1 : kernel - 1;
+  if (kq >= 0 && (p > kq || q > kq))
+    return fail_static(GPFVM_E_INVALID, "factor: order above the smoothness of the Matern kernel");
   if (n1 < 1 || n2 < 1 || !a1 || !a2 || !out) return fail_static(GPFVM_E_INVALID, "factor: bad sizes/pointers");
   if (!(lengthscale > 0)) return fail_static(GPFVM_E_INVALID, "factor: lengthscale must be positive");
   const int l1 = (kind == 0) ? n1 + 1 : n1;
@@ -709,7 +725,7 @@ extern "C" int gpfvm_factor(int kind, int p, int q, int n1, const double* a1, in
   }
   hipError_t e = hipMemcpyAsync(d1, a1, l1 * sizeof(double), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d2, a2, l2 * sizeof(double), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_factor(kind, p, q, n1, d1, n2, d2, lengthscale, 1.0, out, n2, s);
+  if (e == hipSuccess) e = launch_factor(kind, kq, p, q, n1, d1, n2, d2, lengthscale, 1.0, out, n2, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(d1);
   (void)hipFree(d2);

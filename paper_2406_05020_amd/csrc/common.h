@@ -180,7 +180,7 @@ struct GramTerm {          // merged volume-Gram term
 };
 
 // ---- kernels / launchers (kernels.hip) --------------------------------------
-hipError_t launch_factor(int kind, int p, int q, int n1, const double* a1, int n2, const double* a2,
+hipError_t launch_factor(int kind, int kq, int p, int q, int n1, const double* a1, int n2, const double* a2,
                          double ell, double scale, double* out, i64 ld, hipStream_t s);
 hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s);   // kernel chosen by st.kind
 hipError_t launch_scale(Elt elt, const void* src, i64 src_stride, const void* coef, void* dst, i64 dst_stride, i64 n,
@@ -256,6 +256,7 @@ struct gpfvm_handle {
   gpfvm::i64 N = 0, n = 0;
   int nb = 0;
   double ell[3] = {1, 1, 1};
+  int kq[3] = {-1, -1, -1};        // per dim: -1 squared exponential, q >= 0 Matern nu = q + 1/2
   double sf2 = 1;
   double sig_pde = 0;
   int has_cc = 0;

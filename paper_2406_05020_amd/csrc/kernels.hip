@@ -45,10 +45,70 @@ __device__ __forceinline__ double se_deriv(int m, double r, double ell) {
   return s * hm * e;
 }
 
+// ============================================================================
+// Half-integer Matern kernels (Sec. 3.1): nu = q + 1/2, q = 0..3,
+//   k(r) = e^{-s} p_q(s),  s = c |r| / l,  c = sqrt(2q + 1),
+//   p_0 = 1, p_1 = 1 + s, p_2 = 1 + s + s^2/3, p_3 = 1 + s + 2s^2/5 + s^3/15.
+// Derivatives and antiderivatives stay exponential times polynomial:
+//   k^(m)(r)  = sgn(r)^m (c/l)^m e^{-s} P_m(s),   P_0 = p_q, P_{j+1} = d/ds P_j - P_j,
+//   k^(-1)(r) = sgn(r) (l/c) (A1 - e^{-s} Q1(s)), Q1 = sum_j d^j/ds^j p_q, A1 = Q1(0),
+//   k^(-2)(r) = (l/c)^2 (A1 s - A2 + e^{-s} Q2(s)), Q2 = sum_j d^j/ds^j Q1, A2 = Q2(0),
+// because d/ds [-e^{-s} sum_j d^j/ds^j Q] = e^{-s} Q.  k^(-2) is evaluated as
+// A1 s + A2 expm1(-s) + e^{-s} (Q2(s) - A2) to keep its O(s^2) size near 0.
+// ============================================================================
+__device__ __forceinline__ double poly3(const double* a, double s) {
+  return ((a[3] * s + a[2]) * s + a[1]) * s + a[0];
+}
+
+// b = sum_j d^j/ds^j a for a cubic a (coefficients, lowest first)
+__device__ __forceinline__ void sum_of_derivatives(const double* a, double* b) {
+  b[3] = a[3];
+  b[2] = a[2] + 3.0 * a[3];
+  b[1] = a[1] + 2.0 * a[2] + 6.0 * a[3];
+  b[0] = a[0] + a[1] + 2.0 * a[2] + 6.0 * a[3];
+}
+
+__device__ double matern_deriv(int q, int m, double r, double ell) {
+  double P[4] = {1.0, 0.0, 0.0, 0.0};
+  if (q >= 1) P[1] = 1.0;
+  if (q == 2) P[2] = 1.0 / 3.0;
+  if (q == 3) { P[2] = 0.4; P[3] = 1.0 / 15.0; }
+  const double c = sqrt(2.0 * q + 1.0);
+  const double s = c * fabs(r) / ell;
+  const double e = exp(-s);
+  const double sg = (r > 0.0) ? 1.0 : (r < 0.0 ? -1.0 : 0.0);
+  if (m >= 0) {
+    double f = 1.0;
+    for (int j = 0; j < m; ++j) {       // P <- d/ds P - P
+      P[0] = P[1] - P[0];
+      P[1] = 2.0 * P[2] - P[1];
+      P[2] = 3.0 * P[3] - P[2];
+      P[3] = -P[3];
+      f *= c / ell;
+    }
+    const double v = f * e * poly3(P, s);
+    return (m & 1) ? sg * v : v;
+  }
+  double Q1[4], Q2[4];
+  sum_of_derivatives(P, Q1);
+  const double A1 = Q1[0];
+  if (m == -1) return sg * (ell / c) * (A1 - e * poly3(Q1, s));
+  sum_of_derivatives(Q1, Q2);
+  const double A2 = Q2[0];
+  const double tail = s * ((Q2[3] * s + Q2[2]) * s + Q2[1]);
+  const double lc = ell / c;
+  return lc * lc * (A1 * s + A2 * expm1(-s) + e * tail);
+}
+
+// kq < 0: squared exponential; kq = 0..3: Matern nu = kq + 1/2.
+__device__ __forceinline__ double kernel_deriv(int kq, int m, double r, double ell) {
+  return kq < 0 ? se_deriv(m, r, ell) : matern_deriv(kq, m, r, ell);
+}
+
 // kind 0: cell-cell; a1, a2 are edge arrays (n1+1, n2+1).
 // kind 1: point-cell; a1 points (n1), a2 edges (n2+1).
 // kind 2: point-point; a1 (n1), a2 (n2) points.
-__global__ void k_factor(int kind, int p, int q, int n1, const double* __restrict__ a1, int n2,
+__global__ void k_factor(int kind, int kq, int p, int q, int n1, const double* __restrict__ a1, int n2,
                          const double* __restrict__ a2, double ell, double scale,
                          double* __restrict__ out, i64 ld) {
   const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -59,24 +119,24 @@ __global__ void k_factor(int kind, int p, int q, int n1, const double* __restric
   if (kind == 0) {
     const double a = a1[i], b = a1[i + 1], c = a2[j], d = a2[j + 1];
     const int m = p + q - 2;
-    v = (se_deriv(m, b - c, ell) - se_deriv(m, a - c, ell)) -
-        (se_deriv(m, b - d, ell) - se_deriv(m, a - d, ell));
+    v = (kernel_deriv(kq, m, b - c, ell) - kernel_deriv(kq, m, a - c, ell)) -
+        (kernel_deriv(kq, m, b - d, ell) - kernel_deriv(kq, m, a - d, ell));
   } else if (kind == 1) {
     const double x = a1[i];
     const int m = p + q - 1;
-    v = se_deriv(m, x - a2[j], ell) - se_deriv(m, x - a2[j + 1], ell);
+    v = kernel_deriv(kq, m, x - a2[j], ell) - kernel_deriv(kq, m, x - a2[j + 1], ell);
   } else {
-    v = se_deriv(p + q, a1[i] - a2[j], ell);
+    v = kernel_deriv(kq, p + q, a1[i] - a2[j], ell);
   }
   out[(i64)i * ld + j] = sgn * v;
 }
 
-hipError_t launch_factor(int kind, int p, int q, int n1, const double* a1, int n2, const double* a2,
+hipError_t launch_factor(int kind, int kq, int p, int q, int n1, const double* a1, int n2, const double* a2,
                          double ell, double scale, double* out, i64 ld, hipStream_t s) {
   const i64 tot = (i64)n1 * n2;
   if (tot == 0) return hipSuccess;
   const int bs = 256;
-  k_factor<<<dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s>>>(kind, p, q, n1, a1, n2, a2, ell,
+  k_factor<<<dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s>>>(kind, kq, p, q, n1, a1, n2, a2, ell,
                                                                       scale, out, ld);
   return hipGetLastError();
 }

@@ -808,7 +808,7 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
     for (int i = 0; i < d; ++i) {
       Qg[t][i] = (double*)tmp.alloc((size_t)n[i] * h->nc[i] * sizeof(double));
       if (!Qg[t][i]) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
-      if (launch_factor(1, 0, h->pterms[t].alpha[i], n[i], gax[i], h->nc[i], h->edges[i], h->ell[i], 1.0, Qg[t][i],
+      if (launch_factor(1, h->kq[i], 0, h->pterms[t].alpha[i], n[i], gax[i], h->nc[i], h->edges[i], h->ell[i], 1.0, Qg[t][i],
                         h->nc[i], s) != hipSuccess)
         return fail(GPFVM_E_HIP, "posterior: factor launch failed");
     }
@@ -829,7 +829,8 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
       if (hipMemcpyAsync(gaxis[g][i], G.axis[i].data(), G.n[i] * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(GPFVM_E_HIP, "posterior: copy failed");
       // P[b][x] = d^beta_1 k(x_b, x)
-      if (launch_factor(2, G.deriv[i], 0, G.n[i], gaxis[g][i], n[i], gax[i], h->ell[i], 1.0, P, n[i], s) != hipSuccess)
+      if (launch_factor(2, h->kq[i], G.deriv[i], 0, G.n[i], gaxis[g][i], n[i], gax[i], h->ell[i], 1.0, P, n[i], s) !=
+          hipSuccess)
         return fail(GPFVM_E_HIP, "posterior: factor launch failed");
       pg.P[g][i] = P;
     }

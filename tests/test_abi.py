@@ -70,10 +70,15 @@ def test_factor_argument_checks(G):
     L = G.lib()
     a = np.array([0.0, 0.5, 1.0])
     p = a.ctypes.data_as(C.POINTER(C.c_double))
-    assert L.gpfvm_factor(3, 0, 0, 2, p, 2, p, 0.1, None, None) == G.E_INVALID
-    assert L.gpfvm_factor(0, 5, 5, 2, p, 2, p, 0.1, None, None) == G.E_INVALID
-    assert L.gpfvm_factor(0, 0, 0, 2, p, 2, p, -0.1, C.c_void_p(8), None) == G.E_INVALID
+    assert L.gpfvm_factor(3, 0, 0, 0, 2, p, 2, p, 0.1, None, None) == G.E_INVALID
+    assert L.gpfvm_factor(0, 0, 5, 5, 2, p, 2, p, 0.1, None, None) == G.E_INVALID
+    assert L.gpfvm_factor(0, 0, 0, 0, 2, p, 2, p, -0.1, C.c_void_p(8), None) == G.E_INVALID
     assert "lengthscale" in G.last_error()
+    assert L.gpfvm_factor(0, 7, 0, 0, 2, p, 2, p, 0.1, C.c_void_p(8), None) == G.E_INVALID
+    assert "kernel" in G.last_error()
+    # Matern-3/2 (q = 1) admits orders up to 1
+    assert L.gpfvm_factor(0, G.KERNEL_MATERN32, 2, 0, 2, p, 2, p, 0.1, C.c_void_p(8), None) == G.E_INVALID
+    assert "Matern" in G.last_error()
 
 
 def test_null_handle_calls_are_rejected(G):
@@ -96,3 +101,15 @@ def test_assemble_option_checks_happen_on_the_host(G):
     with pytest.raises(G.GpfvmError) as e:
         G.assemble(p, max_iter=0, stream=0)
     assert e.value.code == G.E_INVALID and "max_iter" in str(e.value)
+
+
+def test_matern_orders_are_validated_on_the_host(G):
+    """A Matern-(q+1/2) dimension admits PDE and point derivative orders up to q."""
+    import dataclasses
+    p = W.heat1d_c1()                                  # u_t - 0.1 u_xx: orders (1, 0) and (0, 2)
+    ok = dataclasses.replace(p, kernel=(G.KERNEL_MATERN32, G.KERNEL_MATERN52))
+    G.validate(ok)
+    for bad in [(G.KERNEL_MATERN32, G.KERNEL_MATERN32), (G.KERNEL_MATERN12, G.KERNEL_MATERN52), (9, 0)]:
+        with pytest.raises(G.GpfvmError) as e:
+            G.validate(dataclasses.replace(p, kernel=bad))
+        assert e.value.code == G.E_INVALID
