@@ -15,6 +15,10 @@ Parity pins (tests under ``tests/test_oracle_*.py``):
   dense posterior ............ pinned: LAPACK Cholesky; noise-free limit
                                interpolates; analytic heat solution convergence
   two-stage Schur solve ...... pinned: equals the one-stage dense solve
+  targeted IterGP ............ pinned: with one fixed right-hand side its action
+                               residuals are the residuals of textbook CG on
+                               that right-hand side; N iterations reproduce the
+                               exact posterior; variance non-increasing
   IterGP ..................... pinned: unit-vector actions reproduce Cholesky;
                                run to n iterations reproduces the exact
                                posterior; combined variance >= exact and
@@ -34,7 +38,7 @@ import scipy.linalg as sla
 
 __all__ = [
     "load_quad", "kernel_q", "cell_cell", "point_cell", "point_point", "Oracle",
-    "dense_posterior", "itergp", "cg_solve",
+    "dense_posterior", "itergp", "itergp_targeted", "schur_cross", "cg_solve",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -423,6 +427,57 @@ def cg_solve(S, tol: float, maxiter: int):
         p = r + (rr2 / rr) * p
         rr = rr2
     return x, maxiter
+
+
+def schur_cross(S: "SchurSystem", X: np.ndarray) -> np.ndarray:
+    """Cross-covariance between the volume observations and the points X under
+    the IC/BC-conditioned prior (Sec. 4.2): K_S(X) = L_V k(X) - G_pb G_bb^{-1}
+    L_b k(X), shape (N, M)."""
+    o = S.o
+    kb, kp = o.Lk_points(X)
+    if kb.size == 0:
+        return kp
+    return kp - np.stack([o.cross_rmatvec(c) for c in sla.cho_solve(S.cf, kb).T], axis=1)
+
+
+def itergp_targeted(S, vp: np.ndarray, D: np.ndarray, eta: np.ndarray, KS: np.ndarray, betas: np.ndarray,
+                    passes: int = 2):
+    """Targeted uncertainty reduction (appendix "Targeted uncertainty
+    reduction"): IterGP continued from (vp, D, eta), where iteration i takes as
+    its action the residual of the right-hand side b_i = KS @ betas[i] with
+    respect to the current inverse approximation C = D diag(1/eta) D^T,
+
+        s = b_i - S C b_i,
+
+    and otherwise the IterGP step of ``itergp`` (projection against the stored
+    directions, once or twice; eta; representer weights updated with the data
+    residual).  The weights betas (one row per iteration, e.g. Dirichlet draws)
+    are inputs.  Returns (v, D, eta, norms of the action residuals)."""
+    v = vp.copy()
+    Ds = [D[:, j] for j in range(D.shape[1])]
+    es = list(eta)
+    res = []
+    for beta in betas:
+        bt = KS @ beta
+        Dm = np.stack(Ds, axis=1) if Ds else np.zeros((len(v), 0))
+        e = np.asarray(es)
+        s = bt - S.matvec(Dm @ ((Dm.T @ bt) / e)) if Ds else bt.copy()
+        res.append(np.linalg.norm(s))
+        z = S.matvec(s)
+        d = s - Dm @ ((Dm.T @ z) / e) if Ds else s.copy()
+        if passes == 2:
+            if Ds:
+                d = d - Dm @ ((Dm.T @ S.matvec(d)) / e)
+            et = d @ S.matvec(d)
+        else:
+            et = z @ d
+        if not et > 0:
+            break
+        r = S.b - S.matvec(v)
+        v = v + (d @ r) / et * d
+        Ds.append(d)
+        es.append(et)
+    return v, np.stack(Ds, axis=1), np.asarray(es), np.asarray(res)
 
 
 def two_stage_posterior(S: SchurSystem, vp: np.ndarray, X: np.ndarray,
