@@ -214,6 +214,27 @@ int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* opts, gpfvm_solve_info*
 int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const double* const* axis,
                     double* mean, double* var, void* stream);
 
+/* Targeted uncertainty reduction (appendix "Targeted uncertainty reduction"):
+ * `iters` further IterGP iterations on the volume system after gpfvm_solve,
+ * each taking as its action the residual b_i - S C b_i of the right-hand side
+ * b_i = K_S(X~) beta_i, where K_S(X~) is the cross-covariance between the
+ * volume observations and the target grid axis[0] x ... x axis[dim-1] under
+ * the IC/BC-conditioned prior (Sec. 4.2) and C the inverse approximation of
+ * the directions stored so far.  The new directions are appended, so the
+ * combined variance of gpfvm_posterior drops first where the weights put
+ * mass; the representer weights take the usual step with the data residual.
+ * weights: host, iters x prod(n) doubles row-major (row i = beta_i, e.g. a
+ * Dirichlet draw the caller makes).  n, axis: host, as for gpfvm_posterior.
+ * Needs a preceding float64 solve with reorth_passes = 2 (its stored S D
+ * images form the action without extra operator applications) and room for
+ * the directions (iterations so far + iters <= assemble max_iter).
+ * Synchronises to fill info (iters = directions now stored).  Errors: INVALID
+ * (bad grid, weights or capacity), STATE (no suitable solve), NOMEM, HIP;
+ * NOTPD when eta <= 0 (directions kept up to the last good one). */
+int gpfvm_refine_variance(gpfvm_handle* h, int dim, const int* n, const double* const* axis,
+                          int iters, const double* weights, gpfvm_solve_info* info,
+                          void* stream);
+
 /* Copy the current representer weights (n doubles, [points; volumes]) to the
  * device buffer `alpha`.  Errors: STATE, HIP. */
 int gpfvm_weights(gpfvm_handle* h, double* alpha, void* stream);

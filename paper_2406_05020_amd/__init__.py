@@ -91,6 +91,8 @@ SYMBOLS = {
     "gpfvm_posterior": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(_dp), C.c_void_p, C.c_void_p,
                          C.c_void_p], C.c_int),
     "gpfvm_weights": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "gpfvm_refine_variance": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(_dp), C.c_int, _dp,
+                               C.POINTER(SolveInfo), C.c_void_p], C.c_int),
     "gpfvm_gram_block": ([C.c_void_p, C.c_longlong, C.c_longlong, C.c_longlong, C.c_longlong, C.c_void_p,
                           C.c_longlong, C.c_void_p], C.c_int),
     "gpfvm_factor": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, C.c_int, _dp, C.c_double, C.c_void_p,
@@ -269,6 +271,27 @@ def posterior(h, axes: Sequence[np.ndarray], mean, var=None, stream=None) -> Non
     ptrs = (_dp * d)(*[a.ctypes.data_as(_dp) for a in ax])
     _check(lib().gpfvm_posterior(h, d, n, ptrs, C.c_void_p(mean.data_ptr()),
                                  C.c_void_p(var.data_ptr()) if var is not None else None, _stream(stream)), h)
+
+
+def refine_variance(h, axes: Sequence[np.ndarray], weights, stream=None) -> dict:
+    """Targeted uncertainty reduction: one extra IterGP iteration per row of
+    `weights` (iters x prod(len(a) for a in axes)), the action of row i being
+    the residual of K_S(grid) weights[i]."""
+    d = len(axes)
+    ax = [_arr(a) for a in axes]
+    n = (C.c_int * d)(*[len(a) for a in ax])
+    ptrs = (_dp * d)(*[a.ctypes.data_as(_dp) for a in ax])
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    if w.ndim != 2 or w.shape[1] != int(np.prod([len(a) for a in ax])):
+        raise ValueError("weights must be a 2-D array (iterations x grid points)")
+    info = SolveInfo()
+    rc = lib().gpfvm_refine_variance(h, d, n, ptrs, int(w.shape[0]), w.ctypes.data_as(_dp), C.byref(info),
+                                     _stream(stream))
+    if rc not in (OK, E_NOTPD):
+        _check(rc, h)
+    out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+    out["rc"] = rc
+    return out
 
 
 def weights(h, out, stream=None) -> None:

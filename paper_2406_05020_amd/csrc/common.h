@@ -303,6 +303,7 @@ struct gpfvm_handle {
   double* v = nullptr;             // volume weights (N)
   double* Dd = nullptr;            // directions: column j at Dd + j * N
   double* Qd = nullptr;            // S applied to the directions (two-pass projection)
+  bool sd_exact = false;           // Qd holds the float64 S D of every stored direction
   double* eta = nullptr;           // max_iter
   double* vec = nullptr;           // solver vectors (r, s, z, d, ...), 8 * N
   double* aux = nullptr;           // dot partials and coefficients

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 
 #include "common.h"
 #include "internal.h"
@@ -381,6 +382,14 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
   return GPFVM_OK;
 }
 
+// W = G_bb^{-1} U on the operator's bound buffers
+static hipError_t apply_ginv(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
+  if (so->ginv_small)
+    return launch_ginv_small(h->nb, h->L, h->Linv, h->Lt, h->Linvt, (const double*)so->U, (double*)so->W, s);
+  if (so->nrhs == 1) return ginv_rows(h, (const double*)so->U, (double*)so->T, (double*)so->W, (double*)so->R, s);
+  return run_stages(so->ginv, s);
+}
+
 // Y = S X on the operator's bound buffers (X, Y float64; X32 filled by the caller for F32)
 static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
   hipError_t e;
@@ -401,13 +410,7 @@ static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
     if (h->nb > 0 && (e = run_plan(so->bp, s)) != hipSuccess) return e;
   }
   if (h->nb > 0) {
-    if (so->ginv_small)
-      e = launch_ginv_small(h->nb, h->L, h->Linv, h->Lt, h->Linvt, (const double*)so->U, (double*)so->W, s);
-    else if (so->nrhs == 1)
-      e = ginv_rows(h, (const double*)so->U, (double*)so->T, (double*)so->W, (double*)so->R, s);
-    else
-      e = run_stages(so->ginv, s);
-    if (e != hipSuccess) return e;
+    if ((e = apply_ginv(h, so, s)) != hipSuccess) return e;
     if ((e = run_plan(so->pb, s)) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -494,7 +497,8 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
 // every `replace_every` iterations.  The operator's input buffer X doubles as
 // the action vector, so no vector is copied inside the loop.
 static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int start, int max_new, double tol,
-                      int check_every, int passes, int replace_every, hipStream_t s, int* n_out, int* state_out) {
+                      int check_every, int passes, int replace_every, hipStream_t s, int* n_out, int* state_out,
+                      const std::function<int(int)>* action = nullptr) {
   const i64 N = h->N;
   gpfvm_sop* so = nullptr;
   int rc = get_sop(h, 1, elt, &so);
@@ -517,7 +521,7 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
   HIPCHK(h, apply_sop(h, so, s));
   HIPCHK(h, launch_dot(N, b, b, dotp, h->scal + 3, s));
   {
-    const double t2 = tol * tol;
+    const double t2 = action ? -1.0 : tol * tol;     // caller's actions: no stopping test
     HIPCHK(h, hipMemcpyAsync(h->scal + 4, &t2, sizeof(double), hipMemcpyHostToDevice, s));
   }
   hipLaunchKernelGGL(k_resid2, dim3(nblk(N)), dim3(256), 0, s, N, b, Y, r, X, (const int*)h->flag);
@@ -548,6 +552,10 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
     for (; i < batch_end; ++i) {
       // scal[0] = r.r and the stopping test; s = r is already in X
       if (passes == 1) HIPCHK(h, launch_dot_check(N, r, dotp, h->scal, h->flag, end - start, s));
+      if (action) {                                           // s = the caller's action (in X)
+        const int rc = (*action)(i);
+        if (rc) return rc;
+      }
       HIPCHK(h, apply_sop(h, so, s));                         // z = S s  (in Y)
       if (passes == 1) {
         HIPCHK(h, hipMemcpyAsync(h->vec + N, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -573,7 +581,9 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
       }
       if (passes == 2) {
         const bool replace = (i + 1 - start) % std::max(1, replace_every) == 0;
-        double* rr_next = replace ? nullptr : (rr_prev == rr_a ? rr_b : rr_a);
+        double* rr_next = (replace || action) ? nullptr : (rr_prev == rr_a ? rr_b : rr_a);
+        // with CG actions s = r, so the step numerator s^T r is r^T r; otherwise d^T r
+        if (action) HIPCHK(h, launch_dot(N, d, r, dotp, h->scal, s));
         hipLaunchKernelGGL(k_update2x, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, (const double*)w, v, r,
                            X, h->Dd + (i64)i * N, h->Qd + (i64)i * N, h->eta + i, h->scal, h->flag,
                            (const double*)(i > 0 ? eta_p : nullptr), n_eta, (const double*)rr_prev, n_rr, rr_next);
@@ -685,7 +695,9 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
   if (!o->resume) {
     HIPCHK(h, launch_fill(h->v, 0.0, N, s));
     h->iters = 0;
+    h->sd_exact = true;
   }
+  if (o->prec != GPFVM_PREC_FP64 || o->reorth_passes != 2) h->sd_exact = false;
   int state = 0, outer = 0;
   if (o->prec == GPFVM_PREC_FP64) {
     int nd = h->iters;
@@ -749,6 +761,167 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
   if (info) info->status = status;
   if (status == GPFVM_E_NOTPD) h->err = "IterGP breakdown: eta <= 0 (state kept up to the last good direction)";
   if (status == GPFVM_E_NOCONV) h->err = "iteration budget exhausted above the tolerance";
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// Targeted uncertainty reduction (appendix "Targeted uncertainty reduction"):
+// `iters` further IterGP iterations after a solve whose actions are the
+// residuals of b_i = K_S(X~) beta_i with respect to the current inverse
+// approximation C = D diag(1/eta) D^T,  s_i = b_i - S C b_i = b_i - (S D)(eta^-1 o D^T b_i),
+// using the stored images S D (no extra operator application).  K_S(X~) is the
+// volume-target cross-covariance under the IC/BC-conditioned prior,
+// L_V k(X~) - G_pb G_bb^{-1} L_b k(X~); X~ is a tensor grid and beta_i the i-th
+// row of `weights` (host, iters x prod(n)).  The representer weights take the
+// usual IterGP step with the data residual; the directions are appended.
+// ---------------------------------------------------------------------------
+extern "C" int gpfvm_refine_variance(gpfvm_handle* h, int dim, const int* n, const double* const* axis, int iters,
+                                     const double* weights, gpfvm_solve_info* info, void* stream) {
+  if (!h) return GPFVM_E_INVALID;
+  if (dim != h->d || !n || !axis) { h->err = "refine_variance: bad target grid"; return GPFVM_E_INVALID; }
+  i64 M = 1;
+  for (int i = 0; i < dim; ++i) {
+    if (n[i] < 1 || !axis[i]) { h->err = "refine_variance: bad target axis"; return GPFVM_E_INVALID; }
+    for (int j = 0; j < n[i]; ++j)
+      if (!std::isfinite(axis[i][j])) { h->err = "refine_variance: non-finite target"; return GPFVM_E_INVALID; }
+    M *= n[i];
+  }
+  if (iters < 1 || !weights) { h->err = "refine_variance: bad iteration count or weights"; return GPFVM_E_INVALID; }
+  for (i64 k = 0; k < (i64)iters * M; ++k)
+    if (!std::isfinite(weights[k])) { h->err = "refine_variance: non-finite weights"; return GPFVM_E_INVALID; }
+  if (!h->solved) { h->err = "refine_variance: no solve yet"; return GPFVM_E_STATE; }
+  if (!h->sd_exact) {
+    h->err = "refine_variance: needs a float64 solve with two projection passes (the stored S D images)";
+    return GPFVM_E_STATE;
+  }
+  if (h->iters + iters > h->max_iter) {
+    h->err = "refine_variance: direction capacity (assemble max_iter) exceeded";
+    return GPFVM_E_INVALID;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  h->stream = s;
+  int rc = ensure_state(h, s);
+  if (rc) return rc;
+  gpfvm_sop* so = nullptr;
+  rc = get_sop(h, 1, F64, &so);
+  if (rc) return rc;
+  const int d = h->d;
+  const i64 N = h->N;
+  Arena tmp;
+  tmp.cache = h->arena.cache;
+  auto fail = [&](int code, const std::string& m) { h->err = m; (void)hipStreamSynchronize(s); tmp.release(); return code; };
+  double* gax[3] = {nullptr, nullptr, nullptr};
+  for (int i = 0; i < d; ++i) {
+    gax[i] = (double*)tmp.alloc(n[i] * sizeof(double));
+    if (!gax[i]) return fail(GPFVM_E_NOMEM, "refine_variance: out of device memory");
+    if (hipMemcpyAsync(gax[i], axis[i], n[i] * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(GPFVM_E_HIP, "refine_variance: copy failed");
+  }
+  double* wts = (double*)tmp.alloc((size_t)iters * M * sizeof(double));
+  double* beta = (double*)tmp.alloc((size_t)M * sizeof(double));
+  if (!wts || !beta) return fail(GPFVM_E_NOMEM, "refine_variance: out of device memory");
+  if (hipMemcpyAsync(wts, weights, (size_t)iters * M * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(GPFVM_E_HIP, "refine_variance: copy failed");
+  // L_V k(X~): cells <- targets, the adjoint of the posterior's grid operator
+  KronOp pt;
+  pt.d = d;
+  for (int i = 0; i < d; ++i) { pt.in_shape[i] = n[i]; pt.out_shape[i] = h->nc[i]; }
+  pt.in_len = M;
+  for (size_t t = 0; t < h->pterms.size(); ++t) {
+    KronTerm k{};
+    for (int i = 0; i < d; ++i) {
+      double* Q = (double*)tmp.alloc((size_t)n[i] * h->nc[i] * sizeof(double));
+      if (!Q) return fail(GPFVM_E_NOMEM, "refine_variance: out of device memory");
+      if (launch_factor(1, h->kq[i], 0, h->pterms[t].alpha[i], n[i], gax[i], h->nc[i], h->edges[i], h->ell[i], 1.0, Q,
+                        h->nc[i], s) != hipSuccess)
+        return fail(GPFVM_E_HIP, "refine_variance: factor launch failed");
+      k.M[i] = Q;
+      k.ld[i] = h->nc[i];
+      k.trans[i] = 1;
+    }
+    k.alpha = h->sf2 * h->pterms[t].coef;
+    k.lscale = h->pterms[t].cellwise;
+    pt.terms.push_back(k);
+  }
+  // L_b k(X~): points of each group <- targets
+  std::vector<KronOp> bt;
+  for (size_t g = 0; g < h->groups.size(); ++g) {
+    const Group& Gr = h->groups[g];
+    KronOp o;
+    o.d = d;
+    for (int i = 0; i < d; ++i) { o.in_shape[i] = n[i]; o.out_shape[i] = Gr.n[i]; }
+    o.in_len = M;
+    o.out_off = Gr.offset;
+    KronTerm k{};
+    for (int i = 0; i < d; ++i) {
+      double* ga = (double*)tmp.alloc(Gr.n[i] * sizeof(double));
+      double* P = (double*)tmp.alloc((size_t)Gr.n[i] * n[i] * sizeof(double));
+      if (!ga || !P) return fail(GPFVM_E_NOMEM, "refine_variance: out of device memory");
+      if (hipMemcpyAsync(ga, Gr.axis[i].data(), Gr.n[i] * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(GPFVM_E_HIP, "refine_variance: copy failed");
+      // P[b][x] = d^beta_b k(x_b, x)
+      if (launch_factor(2, h->kq[i], Gr.deriv[i], 0, Gr.n[i], ga, n[i], gax[i], h->ell[i], 1.0, P, n[i], s) !=
+          hipSuccess)
+        return fail(GPFVM_E_HIP, "refine_variance: factor launch failed");
+      k.M[i] = P;
+      k.ld[i] = n[i];
+    }
+    k.alpha = h->sf2;
+    o.terms.push_back(k);
+    bt.push_back(o);
+  }
+  Plan ppt, pbt;
+  {
+    std::vector<KronOp> ops{pt};
+    rc = compile_kron_list(ops, F64, 1, beta, M, so->Y, N, h->cellc, h->cellc, 0.0, nullptr, 0, 1, tmp, s, ppt, h->err);
+    if (rc) { tmp.release(); return rc; }
+    if (h->nb > 0) {
+      rc = compile_kron_list(bt, F64, 1, beta, M, so->U, h->nb, nullptr, nullptr, 0.0, nullptr, 0, 0, tmp, s, pbt,
+                             h->err);
+      if (rc) { tmp.release(); return rc; }
+    }
+  }
+  double* X = (double*)so->X;
+  double* Y = (double*)so->Y;
+  double* coef = h->aux + 1024;
+  const int start = h->iters;
+  // X = b_i - (S D) (eta^-1 o D^T b_i),  b_i = K_S(X~) beta_i (built in Y)
+  std::function<int(int)> action = [&](int i) -> int {
+    HIPCHK(h, hipMemcpyAsync(beta, wts + (i64)(i - start) * M, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, run_plan(ppt, s));
+    if (h->nb > 0) {
+      HIPCHK(h, run_plan(pbt, s));
+      HIPCHK(h, apply_ginv(h, so, s));
+      HIPCHK(h, run_plan(so->pb, s));                       // Y -= G_pb G_bb^{-1} L_b k(X~) beta
+    }
+    if (i > 0) {
+      HIPCHK(h, launch_rows_dot(i, N, h->Dd, Y, h->eta, coef, s));
+      HIPCHK(h, launch_cols_update(i, N, h->Qd, coef, Y, X, nullptr, nullptr, nullptr, nullptr, s));
+    } else {
+      HIPCHK(h, hipMemcpyAsync(X, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    return GPFVM_OK;
+  };
+  int nd = start, state = 0;
+  rc = itergp_run(h, F64, h->bS, h->v, start, iters, 0.0, 16, 2, 25, s, &nd, &state, &action);
+  if (rc) { (void)hipStreamSynchronize(s); tmp.release(); return rc; }
+  h->iters = nd;
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(GPFVM_E_HIP, "refine_variance: kernel failed");
+  tmp.release();
+  double rs = 0, rf = 0;
+  rc = rel_res(h, h->v, &rs, s);
+  if (rc) return rc;
+  rc = full_residual(h, &rf, s);
+  if (rc) return rc;
+  const int status = (state == 2) ? GPFVM_E_NOTPD : GPFVM_OK;
+  if (info) {
+    info->iters = h->iters;
+    info->outer = 0;
+    info->rel_res = rs;
+    info->rel_res_full = rf;
+    info->status = status;
+  }
+  if (status == GPFVM_E_NOTPD) h->err = "IterGP breakdown: eta <= 0 (state kept up to the last good direction)";
   return status;
 }
 
