@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "PointGroup", "PDETerm", "IBVP", "uniform_edges", "centres",
     "heat1d_c1", "advdiff_c2", "heat2d_c3", "wave2d_c4", "serving_trace",
-    "heat2d_request", "scaled", "CONFIGS",
+    "heat2d_request", "scaled", "CONFIGS", "wave2d_benchmark", "wave2d_benchmark_solution",
 ]
 
 
@@ -233,6 +233,58 @@ def wave2d_c4(nt: int = 64, nx: int = 128, ny: int = 128, seed: int = 4, n_ic: i
         grid=[centres(grid_t), xc.copy(), yc.copy()],
         meta={"H_range_m": [10.0, 200.0], "c2_scale": "9.81*H/(9.81*200)"},
     )
+
+
+def wave2d_benchmark(n: int = 8, seed: int = 0, lengthscale=(0.575, 0.325, 0.325), kernel: int = 3,
+                     grid=(8, 16, 16)) -> IBVP:
+    """The paper's 2-D wave benchmark (appendix "2D Wave Equation Benchmark"):
+    u_tt = c^2 (u_xx + u_yy), c = 1, on [0,2] x [0,1]^2 with n cells per
+    dimension; IC sum_{i,j<=2} C_ij sin(i pi x) sin(j pi y) observed on 8 x 8
+    uniform points together with u_t(0) = 0 there; Dirichlet 0 on the four
+    spatial edges at 20 uniform times x 10 uniform positions each.  C is one
+    seeded draw of N((1, .5, .5, 0), diag(.1, .2, .2, .3)^2).  Tensor-product
+    Matern kernel (code 3: nu = 5/2) in every dimension.  The exact solution is
+    wave2d_benchmark_solution."""
+    C = _wave_benchmark_coefs(seed)
+    xi = centres(8)
+    X, Y = np.meshgrid(xi, xi, indexing="ij")
+    u0 = sum(C[i, j] * np.sin((i + 1) * np.pi * X) * np.sin((j + 1) * np.pi * Y) for i in range(2) for j in range(2))
+    zero = np.array([0.0])
+    groups = [
+        PointGroup([zero, xi, xi.copy()], (0, 0, 0), u0.ravel(), NOISE_EXACT),
+        PointGroup([zero, xi.copy(), xi.copy()], (1, 0, 0), np.zeros(64), NOISE_EXACT),
+    ]
+    groups += _edge_groups_2d(centres(20, 0.0, 2.0), centres(10))
+    return IBVP(
+        name=f"wave2d_benchmark_{n}^3", d=3,
+        edges=[uniform_edges(0, 2, n), uniform_edges(0, 1, n), uniform_edges(0, 1, n)],
+        lengthscale=tuple(lengthscale), outputscale=1.0,
+        terms=[PDETerm((2, 0, 0), 1.0), PDETerm((0, 2, 0), -1.0), PDETerm((0, 0, 2), -1.0)],
+        groups=groups, noise_pde=TAU_PDE,
+        grid=[centres(grid[0], 0.0, 2.0), centres(grid[1]), centres(grid[2])],
+        kernel=(kernel, kernel, kernel),
+        meta={"C": C.tolist(), "c": 1.0},
+    )
+
+
+def _wave_benchmark_coefs(seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    mean = np.array([1.0, 0.5, 0.5, 0.0])
+    std = np.array([0.1, 0.2, 0.2, 0.3])
+    return (mean + std * rng.standard_normal(4)).reshape(2, 2)
+
+
+def wave2d_benchmark_solution(seed: int, axes: Sequence[np.ndarray]) -> np.ndarray:
+    """Separation of variables for wave2d_benchmark: each mode sin(i pi x)
+    sin(j pi y) oscillates as cos(pi sqrt(i^2 + j^2) t) (c = 1, u_t(0) = 0).
+    Values on the tensor grid `axes` (t, x, y), flattened row-major."""
+    C = _wave_benchmark_coefs(seed)
+    T, X, Y = np.meshgrid(*axes, indexing="ij")
+    u = np.zeros(T.shape)
+    for i in range(1, 3):
+        for j in range(1, 3):
+            u += C[i - 1, j - 1] * np.sin(i * np.pi * X) * np.sin(j * np.pi * Y) * np.cos(np.pi * np.hypot(i, j) * T)
+    return u.ravel()
 
 
 def heat2d_request(ns: int, nt: int, seed: int, kappa: float = 0.01, grid_t: int = 8) -> IBVP:
