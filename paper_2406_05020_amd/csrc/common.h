@@ -61,14 +61,27 @@ struct GemmDesc {
 enum Elt { F64 = 0, F32 = 1 };
 
 // One kernel launch: a set of descriptors whose outputs do not overlap.
+// Row dots carried by a GEMM stage's launch as extra workgroups after its
+// tiles: out[j] = M[j,:] . x (divided by eta[j] when eta is set), j < nr,
+// float64.  They must not touch the stage's own inputs or outputs.
+struct RowsRider {
+  int nr = 0;
+  i64 N = 0;
+  const double* M = nullptr;   // nr x N, row-major
+  const double* x = nullptr;
+  const double* eta = nullptr;
+  double* out = nullptr;
+};
+
 struct Stage {
   std::vector<GemmDesc> descs;
   GemmDesc* d_descs = nullptr;
   i64 tiles = 0;
-  int kind = 0;    // GEMM_SPLITK / GEMM_LDS32 / GEMM_LDS64 (set when the stage is uploaded)
+  int kind = 0;    // GEMM_SPLITK / GEMM_LDS16 / GEMM_LDS32 / GEMM_LDS64 (set when the stage is uploaded)
   int slot1 = 0;   // some segment accumulates into slot 1
+  RowsRider rider; // launched with the stage (nr = 0: none)
 };
-enum GemmKind { GEMM_SPLITK = 0, GEMM_LDS32 = 1, GEMM_LDS64 = 2 };
+enum GemmKind { GEMM_SPLITK = 0, GEMM_LDS32 = 1, GEMM_LDS64 = 2, GEMM_LDS16 = 3 };
 
 // Point-block correction of the volume system as Q^T Q with Q = L^{-1} G_bp
 // (n_b x N, row-major), used for one right-hand side when Q is small enough
@@ -206,16 +219,20 @@ hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const 
                              const double* U, double* W, hipStream_t s);
 hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s);
 // Streaming products with a row-major nr x N matrix M:
-//   rows_dot:    out[j] = (sum_k M[j][k] x[k]) / (eta ? eta[j] : 1)
-//   cols_update: out[c] = base[c] - sum_j M[j][c] u[j] (and out2[c] = out[c] if out2);
-//                with M2: out3[c] = base2[c] - sum_j M2[j][c] u[j].   base may alias out.
-hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, const double* eta, double* out,
-                           hipStream_t s);
+//   rows_dot:    part[j * nch + ch] = sum_{k in chunk ch} M[j][k] x[k], nch = rows_dot_chunks(nr, N)
+//                (part holds nr * nch <= nr + 527 values)
+//   rows_dot_full: out[j] = sum_k M[j][k] x[k]
+//   cols_update: u_j = (sum_ch u[j * u_nch + ch]) / (eta ? eta[j] : 1);
+//                out[c] = base[c] - sum_j M[j][c] u_j (and out2[c] = out[c] if out2);
+//                with M2: out3[c] = base2[c] - sum_j M2[j][c] u_j.   base may alias out.
+int rows_dot_chunks(int nr, i64 N);
+hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, double* part, hipStream_t s);
+hipError_t launch_rows_dot_full(int nr, i64 N, const double* M, const double* x, double* out, hipStream_t s);
 //   With M2 and dot_part: also dot_part[g] = workgroup g's share of sum_c out[c] * out3[c]
 //   (ceil(N/64) values; their fixed-order sum is the dot product).
-hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, const double* base, double* out,
-                              double* out2, const double* M2, const double* base2, double* out3, hipStream_t s,
-                              double* dot_part = nullptr);
+hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, int u_nch, const double* eta,
+                              const double* base, double* out, double* out2, const double* M2, const double* base2,
+                              double* out3, hipStream_t s, double* dot_part = nullptr);
 // y[i] = add[i] + alpha * sum_k M[i][k] x[k] over k <= i (upper = 0) or k >= i (upper = 1)
 hipError_t launch_trmv_rows(int n, const double* M, const double* x, double* y, double alpha, const double* add,
                             int upper, hipStream_t s);

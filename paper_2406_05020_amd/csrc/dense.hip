@@ -209,13 +209,16 @@ bool desc_in_bounds(const GemmDesc& D, size_t es) {
 // on the 64x64 LDS-tiled kernel whatever their K.  Below that, long
 // reductions (K beyond 2048: GEMV-shaped projections, point-block products
 // with few right-hand sides) go to the split-K kernel, whose four wavefronts
-// share the K range of a 32x32 tile, and short ones to the 32x32 LDS-tiled
-// kernel with its K range split over four wavefront groups.
+// share the K range of a 32x32 tile, and short ones to the LDS-tiled kernel
+// with its K range split over wavefront groups: 32x32 tiles and four groups,
+// or, when that leaves fewer than 128 workgroups (one-right-hand-side mode
+// products), 16x16 tiles and eight groups, for four times the workgroups and
+// half the chunks in each one's sequential K loop.
 void choose_kernel(Stage& st) {
   st.kind = GEMM_SPLITK;
   st.slot1 = 0;
   if (st.descs.empty()) return;
-  i64 tiles64 = 0, kmax = 0;
+  i64 tiles64 = 0, tiles32 = 0, kmax = 0;
   for (auto& D : st.descs) {
     i64 ksum = 0;
     for (int g = 0; g < D.nseg; ++g) {
@@ -224,9 +227,10 @@ void choose_kernel(Stage& st) {
     }
     kmax = std::max(kmax, ksum);
     tiles64 += (i64)((D.M + 63) / 64) * ((D.N + 63) / 64) * D.batch;
+    tiles32 += (i64)((D.M + 31) / 32) * ((D.N + 31) / 32) * D.batch;
   }
   if (tiles64 >= 256) st.kind = GEMM_LDS64;
-  else if (kmax <= 2048) st.kind = GEMM_LDS32;
+  else if (kmax <= 2048) st.kind = tiles32 < 128 ? GEMM_LDS16 : GEMM_LDS32;
 }
 
 // Upload a list of stages whose descriptors are consecutive in one buffer.
@@ -246,7 +250,7 @@ hipError_t upload_stages(std::vector<Stage>& stages, Arena& arena, hipStream_t s
     choose_kernel(st);
     st.tiles = 0;
     for (auto& D : st.descs) {
-      const int t = st.kind == GEMM_LDS64 ? 64 : 32;
+      const int t = st.kind == GEMM_LDS64 ? 64 : st.kind == GEMM_LDS16 ? 16 : 32;
       D.tiles_m = (D.M + t - 1) / t;
       D.tiles_n = (D.N + t - 1) / t;
       D.tile_begin = st.tiles;

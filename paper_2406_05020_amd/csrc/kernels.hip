@@ -5,6 +5,7 @@
 
 #include "common.h"
 #include "reduce.h"
+#include <type_traits>
 
 namespace gpfvm {
 
@@ -339,8 +340,59 @@ __global__ __launch_bounds__(64 * SK_WAVES) void k_gemm_sk(const GemmDesc* __res
 // that can be nonzero for this tile (the zero triangle must hold zeros), and
 // lower_only skips tiles above the diagonal (BM == BN).
 // ----------------------------------------------------------------------------
-template <typename T, int BM, int BN, int KS, bool SLOT1>
-__global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDesc* __restrict__ descs, int ndesc) {
+// One workgroup of NT threads: out[row] = M[row,:] . x (/ eta[row]), summed in
+// a fixed order (two interleaved accumulators per thread, then a wavefront
+// tree, then the wavefronts in order).  red: NT / 64 doubles of LDS.
+// Dot product of q[c_lo, c_hi) and x[c_lo, c_hi) by one workgroup of NT
+// threads, valid in thread 0.  Each thread issues RD_U loads of both vectors
+// before it multiplies; the sum runs in a fixed order (RD_U accumulators per
+// thread, a pairwise tree over them, a wavefront tree, then the wavefronts in
+// order).  red: NT / 64 doubles of LDS.
+constexpr int RD_U = 16;
+
+template <int NT>
+__device__ __forceinline__ double dot_range(const double* __restrict__ q, const double* __restrict__ x, i64 c_lo,
+                                            i64 c_hi, double* red) {
+  double acc[RD_U];
+#pragma unroll
+  for (int u = 0; u < RD_U; ++u) acc[u] = 0.0;
+  for (i64 c0 = c_lo + threadIdx.x; c0 < c_hi; c0 += (i64)NT * RD_U) {
+    double qv[RD_U], xv[RD_U];
+#pragma unroll
+    for (int u = 0; u < RD_U; ++u) {
+      const i64 c = c0 + (i64)u * NT;
+      qv[u] = c < c_hi ? q[c] : 0.0;
+      xv[u] = c < c_hi ? x[c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RD_U; ++u) acc[u] = fma(qv[u], xv[u], acc[u]);
+  }
+#pragma unroll
+  for (int w = RD_U / 2; w > 0; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) acc[u] += acc[u + w];
+  double v = acc[0];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+  return s;
+}
+
+// One workgroup of NT threads: out[row] = M[row,:] . x (/ eta[row]).
+template <int NT>
+__device__ __forceinline__ void rows_dot_block(i64 N, const double* __restrict__ M, const double* __restrict__ x,
+                                               const double* __restrict__ eta, double* __restrict__ out, int row,
+                                               double* red) {
+  const double s = dot_range<NT>(M + (i64)row * N, x, 0, N, red);
+  if (threadIdx.x == 0) out[row] = eta ? s / eta[row] : s;
+}
+
+template <typename T, int BM, int BN, int KS, bool SLOT1, bool RIDE>
+__global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDesc* __restrict__ descs, int ndesc,
+                                                                    i64 ntiles, RowsRider rider) {
   typedef typename MfmaOp<T>::v4 v4;
   constexpr int WNN = BN / 16, NBLK = (BM / 16) * (BN / 16), NT = 64 * NBLK * KS, LKC = 16 * KS;
   constexpr int EA = BM * LKC / NT, EB = LKC * BN / NT;
@@ -357,6 +409,13 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
   auto Bs = [&](int buf, int k, int n) -> T& { return sm[SZA + (buf * BN + n) * LS + k]; };
 
   const i64 tile = blockIdx.x;
+  if constexpr (RIDE) {
+    if (tile >= ntiles) {                          // a workgroup of the riding row dots
+      __shared__ double rred[NT / 64];
+      rows_dot_block<NT>(rider.N, rider.M, rider.x, rider.eta, rider.out, (int)(tile - ntiles), rred);
+      return;
+    }
+  }
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -382,72 +441,177 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[q][r] = 0;
 
-  for (int g = 0; g < D.nseg; ++g) {
-    const Seg& S = D.seg[g];
-    const T* __restrict__ A = reinterpret_cast<const T*>(S.A) + b * S.a_bs;
-    const T* __restrict__ B = reinterpret_cast<const T*>(S.B) + b * S.b_bs;
-    const T alpha = (T)S.alpha;
-    int kbeg = 0, kend = S.K;
-    if (S.tri == 1) kend = min(S.K, m0 + BM);
-    else if (S.tri == 2) kbeg = m0;
-    else if (S.tri == 3) kend = min(S.K, n0 + BN);
-    else if (S.tri == 4) kbeg = n0;
-    if (kbeg >= kend) continue;                    // uniform over the workgroup
-    const bool akf = (S.a_cs == 1), bnf = (S.b_cs == 1);
-    const int q = SLOT1 ? S.slot : 0;
+  if constexpr (KS == 1) {
+    // one K group: each segment runs its own chunk loop (many short chunks per
+    // segment, so the exposed first load of a segment matters little)
+    for (int g = 0; g < D.nseg; ++g) {
+      const Seg& S = D.seg[g];
+      const T* __restrict__ A = reinterpret_cast<const T*>(S.A) + b * S.a_bs;
+      const T* __restrict__ B = reinterpret_cast<const T*>(S.B) + b * S.b_bs;
+      const T alpha = (T)S.alpha;
+      int kbeg = 0, kend = S.K;
+      if (S.tri == 1) kend = min(S.K, m0 + BM);
+      else if (S.tri == 2) kbeg = m0;
+      else if (S.tri == 3) kend = min(S.K, n0 + BN);
+      else if (S.tri == 4) kbeg = n0;
+      if (kbeg >= kend) continue;                    // uniform over the workgroup
+      const bool akf = (S.a_cs == 1), bnf = (S.b_cs == 1);
+      const int q = SLOT1 ? S.slot : 0;
+      T ra[EA], rbv[EB];
+      auto gload = [&](int kc) {
+  #pragma unroll
+        for (int u = 0; u < EA; ++u) {
+          const int e = tid + NT * u;
+          int k, m;
+          if (akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
+          ra[u] = (m0 + m < M && kc + k < kend) ? A[(i64)(m0 + m) * S.a_rs + (i64)(kc + k) * S.a_cs] : (T)0;
+        }
+  #pragma unroll
+        for (int u = 0; u < EB; ++u) {
+          const int e = tid + NT * u;
+          int k, n;
+          if (bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
+          rbv[u] = (n0 + n < N && kc + k < kend) ? B[(i64)(kc + k) * S.b_rs + (i64)(n0 + n) * S.b_cs] : (T)0;
+        }
+      };
+      auto sstore = [&](int buf) {
+  #pragma unroll
+        for (int u = 0; u < EA; ++u) {
+          const int e = tid + NT * u;
+          int k, m;
+          if (akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
+          As(buf, k, m) = alpha * ra[u];
+        }
+  #pragma unroll
+        for (int u = 0; u < EB; ++u) {
+          const int e = tid + NT * u;
+          int k, n;
+          if (bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
+          Bs(buf, k, n) = rbv[u];
+        }
+      };
+      __syncthreads();                               // previous segment's reads of buffer 0 are done
+      gload(kbeg);
+      sstore(0);
+      __syncthreads();
+      int buf = 0;
+      for (int kc = kbeg; kc < kend; kc += LKC) {
+        const bool more = kc + LKC < kend;
+        if (more) gload(kc + LKC);
+  #pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const int k = kg * 16 + kk + lk;
+          const T av = As(buf, k, rb + lr);
+          const T bv = Bs(buf, k, cb + lr);
+          if (q == 0) acc[0] = MfmaOp<T>::mac(av, bv, acc[0]);
+          else acc[NS - 1] = MfmaOp<T>::mac(av, bv, acc[NS - 1]);
+        }
+        if (more) sstore(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      }
+    }
+
+  } else {
+    // The K ranges of all segments form one sequence of LKC-wide chunks; the
+    // next chunk (possibly the first of the next segment) is prefetched to
+    // registers while the current one is multiplied out of LDS.
+    struct Ctx {
+      const T* A;
+      const T* B;
+      i64 a_rs, a_cs, b_rs, b_cs;
+      T alpha;
+      int kbeg, kend, q;
+      bool akf, bnf;
+    };
+    auto ctx_of = [&](int g, Ctx& c) -> bool {      // false: empty K range
+      const Seg& S = D.seg[g];
+      c.A = reinterpret_cast<const T*>(S.A) + b * S.a_bs;
+      c.B = reinterpret_cast<const T*>(S.B) + b * S.b_bs;
+      c.a_rs = S.a_rs; c.a_cs = S.a_cs; c.b_rs = S.b_rs; c.b_cs = S.b_cs;
+      c.alpha = (T)S.alpha;
+      c.kbeg = 0; c.kend = S.K;
+      if (S.tri == 1) c.kend = min(S.K, m0 + BM);
+      else if (S.tri == 2) c.kbeg = m0;
+      else if (S.tri == 3) c.kend = min(S.K, n0 + BN);
+      else if (S.tri == 4) c.kbeg = n0;
+      c.akf = (S.a_cs == 1);
+      c.bnf = (S.b_cs == 1);
+      c.q = SLOT1 ? S.slot : 0;
+      return c.kbeg < c.kend;
+    };
     T ra[EA], rbv[EB];
-    auto gload = [&](int kc) {
-#pragma unroll
+    auto gload = [&](const Ctx& c, int kc) {
+  #pragma unroll
       for (int u = 0; u < EA; ++u) {
         const int e = tid + NT * u;
         int k, m;
-        if (akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
-        ra[u] = (m0 + m < M && kc + k < kend) ? A[(i64)(m0 + m) * S.a_rs + (i64)(kc + k) * S.a_cs] : (T)0;
+        if (c.akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
+        ra[u] = (m0 + m < M && kc + k < c.kend) ? c.A[(i64)(m0 + m) * c.a_rs + (i64)(kc + k) * c.a_cs] : (T)0;
       }
-#pragma unroll
+  #pragma unroll
       for (int u = 0; u < EB; ++u) {
         const int e = tid + NT * u;
         int k, n;
-        if (bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
-        rbv[u] = (n0 + n < N && kc + k < kend) ? B[(i64)(kc + k) * S.b_rs + (i64)(n0 + n) * S.b_cs] : (T)0;
+        if (c.bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
+        rbv[u] = (n0 + n < N && kc + k < c.kend) ? c.B[(i64)(kc + k) * c.b_rs + (i64)(n0 + n) * c.b_cs] : (T)0;
       }
     };
-    auto sstore = [&](int buf) {
-#pragma unroll
+    auto sstore = [&](const Ctx& c, int buf) {
+  #pragma unroll
       for (int u = 0; u < EA; ++u) {
         const int e = tid + NT * u;
         int k, m;
-        if (akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
-        As(buf, k, m) = alpha * ra[u];
+        if (c.akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
+        As(buf, k, m) = c.alpha * ra[u];
       }
-#pragma unroll
+  #pragma unroll
       for (int u = 0; u < EB; ++u) {
         const int e = tid + NT * u;
         int k, n;
-        if (bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
+        if (c.bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
         Bs(buf, k, n) = rbv[u];
       }
     };
-    __syncthreads();                               // previous segment's reads of buffer 0 are done
-    gload(kbeg);
-    sstore(0);
-    __syncthreads();
-    int buf = 0;
-    for (int kc = kbeg; kc < kend; kc += LKC) {
-      const bool more = kc + LKC < kend;
-      if (more) gload(kc + LKC);
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
-        const int k = kg * 16 + kk + lk;
-        const T av = As(buf, k, rb + lr);
-        const T bv = Bs(buf, k, cb + lr);
-        if (q == 0) acc[0] = MfmaOp<T>::mac(av, bv, acc[0]);
-        else acc[NS - 1] = MfmaOp<T>::mac(av, bv, acc[NS - 1]);
-      }
-      if (more) sstore(buf ^ 1);
+    int g = 0;
+    Ctx cur;
+    while (g < D.nseg && !ctx_of(g, cur)) ++g;       // uniform over the workgroup
+    if (g < D.nseg) {
+      int kc = cur.kbeg;
+      gload(cur, kc);
+      sstore(cur, 0);
       __syncthreads();
-      buf ^= 1;
+      int buf = 0;
+      for (;;) {
+        Ctx nxt = cur;
+        int ng = g, nkc = kc + LKC;
+        bool more = true;
+        if (nkc >= cur.kend) {
+          ng = g + 1;
+          while (ng < D.nseg && !ctx_of(ng, nxt)) ++ng;
+          more = ng < D.nseg;
+          if (more) nkc = nxt.kbeg;
+        }
+        if (more) gload(nxt, nkc);
+        const int q = cur.q;
+  #pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const int k = kg * 16 + kk + lk;
+          const T av = As(buf, k, rb + lr);
+          const T bv = Bs(buf, k, cb + lr);
+          if (q == 0) acc[0] = MfmaOp<T>::mac(av, bv, acc[0]);
+          else acc[NS - 1] = MfmaOp<T>::mac(av, bv, acc[NS - 1]);
+        }
+        if (more) sstore(nxt, buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+        if (!more) break;
+        cur = nxt;
+        g = ng;
+        kc = nkc;
+      }
     }
+
   }
 
   if (KS > 1) {                                    // sum the K groups in a fixed order
@@ -488,20 +652,43 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
 
 template <typename T, int BM, int KS>
 static void launch_lds(const Stage& st, int nd, hipStream_t s) {
-  const dim3 grid((unsigned)st.tiles), block(4 * BM * BM / 16 * KS);
+  const dim3 block(4 * BM * BM / 16 * KS);
+  if constexpr (std::is_same<T, double>::value) {
+    if (st.rider.nr > 0) {                         // the stage carries row dots
+      const dim3 grid((unsigned)(st.tiles + st.rider.nr));
+      if (st.slot1)
+        k_gemm_lds<T, BM, BM, KS, true, true><<<grid, block, 0, s>>>(st.d_descs, nd, st.tiles, st.rider);
+      else
+        k_gemm_lds<T, BM, BM, KS, false, true><<<grid, block, 0, s>>>(st.d_descs, nd, st.tiles, st.rider);
+      return;
+    }
+  }
+  const dim3 grid((unsigned)st.tiles);
   if (st.slot1)
-    k_gemm_lds<T, BM, BM, KS, true><<<grid, block, 0, s>>>(st.d_descs, nd);
+    k_gemm_lds<T, BM, BM, KS, true, false><<<grid, block, 0, s>>>(st.d_descs, nd, st.tiles, st.rider);
   else
-    k_gemm_lds<T, BM, BM, KS, false><<<grid, block, 0, s>>>(st.d_descs, nd);
+    k_gemm_lds<T, BM, BM, KS, false, false><<<grid, block, 0, s>>>(st.d_descs, nd, st.tiles, st.rider);
 }
 
 hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
+  if (st.rider.nr > 0 && (elt != F64 || st.kind == GEMM_SPLITK || st.tiles == 0 || st.descs.empty())) {
+    // the riding row dots run on their own where the stage's kernel cannot carry them
+    if (st.rider.eta) return hipErrorInvalidValue;  // partial sums carry no division
+    const hipError_t e = launch_rows_dot_full(st.rider.nr, st.rider.N, st.rider.M, st.rider.x, st.rider.out, s);
+    if (e != hipSuccess) return e;
+    if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
+    Stage plain = st;
+    plain.rider = RowsRider();
+    return launch_gemm_stage(elt, plain, s);
+  }
   if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
   const int nd = (int)st.descs.size();
   if (st.kind == GEMM_LDS64) {
     if (elt == F64) launch_lds<double, 64, 1>(st, nd, s); else launch_lds<float, 64, 1>(st, nd, s);
   } else if (st.kind == GEMM_LDS32) {
     if (elt == F64) launch_lds<double, 32, 4>(st, nd, s); else launch_lds<float, 32, 4>(st, nd, s);
+  } else if (st.kind == GEMM_LDS16) {
+    if (elt == F64) launch_lds<double, 16, 8>(st, nd, s); else launch_lds<float, 16, 8>(st, nd, s);
   } else if (elt == F64) {
     k_gemm_sk<double><<<dim3((unsigned)st.tiles), dim3(64 * SK_WAVES), 0, s>>>(st.d_descs, nd);
   } else {
@@ -748,32 +935,28 @@ hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const 
 // ----------------------------------------------------------------------------
 constexpr int CU_WAVES = 16;
 constexpr int CU_BLK = 2048;
+constexpr int CU_MAXCH = 16;   // most partial sums per coefficient (rows_dot_chunks <= 16)
 
-__global__ __launch_bounds__(1024) void k_rows_dot(i64 N, const double* __restrict__ M, const double* __restrict__ x,
-                                                   const double* __restrict__ eta, double* __restrict__ out) {
-  __shared__ double red[16];
-  const double* __restrict__ q = M + (i64)blockIdx.x * N;
-  double a0 = 0.0, a1 = 0.0;
-  i64 c = threadIdx.x;
-  for (; c + 1024 < N; c += 2048) {
-    a0 = fma(q[c], x[c], a0);
-    a1 = fma(q[c + 1024], x[c + 1024], a1);
-  }
-  if (c < N) a0 = fma(q[c], x[c], a0);
-  double v = a0 + a1;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < 16; ++w) s += red[w];
-    out[blockIdx.x] = eta ? s / eta[blockIdx.x] : s;
-  }
+// Row dots split over column chunks, so that a few long rows still occupy
+// the whole chip: part[row * nch + ch] = M[row, chunk ch] . x[chunk ch], the
+// chunks being consecutive ranges of ceil(N / nch) columns.  The consumer
+// (k_cols_update) adds the nch partials of a row in order.
+constexpr int RP_THREADS = 256;
+
+__global__ __launch_bounds__(RP_THREADS) void k_rows_dot(i64 N, int nch, const double* __restrict__ M,
+                                                         const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double red[RP_THREADS / 64];
+  const int row = (int)(blockIdx.x / nch), ch = (int)(blockIdx.x % nch);
+  const i64 L = (N + nch - 1) / nch;
+  const i64 lo = (i64)ch * L, hi = min(N, lo + L);
+  const double s = dot_range<RP_THREADS>(M + (i64)row * N, x, lo, hi, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 template <bool TWO, bool DOT>
 __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, const double* __restrict__ M,
-                                                               const double* __restrict__ u, const double* base,
+                                                               const double* __restrict__ u, int u_nch,
+                                                               const double* __restrict__ eta, const double* base,
                                                                double* out, double* out2, const double* __restrict__ M2,
                                                                const double* base2, double* out3, double* dot_part) {
   __shared__ double us[CU_BLK];
@@ -785,7 +968,18 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
   for (int j0 = 0; j0 < nr; j0 += CU_BLK) {
     const int jn = min(CU_BLK, nr - j0);
     __syncthreads();
-    for (int i = threadIdx.x; i < jn; i += 64 * CU_WAVES) us[i] = u[j0 + i];
+    for (int i = threadIdx.x; i < jn; i += 64 * CU_WAVES) {
+      // all partials of row j0 + i are loaded before they are added (in order)
+      const double* pu = u + (i64)(j0 + i) * u_nch;
+      double pv[CU_MAXCH];
+#pragma unroll
+      for (int ch = 0; ch < CU_MAXCH; ++ch) pv[ch] = ch < u_nch ? pu[ch] : 0.0;
+      const double ev = eta ? eta[j0 + i] : 1.0;
+      double v = pv[0];
+#pragma unroll
+      for (int ch = 1; ch < CU_MAXCH; ++ch) v += pv[ch];     // + 0.0 past u_nch: exact
+      us[i] = eta ? v / ev : v;
+    }
     __syncthreads();
     if (c < N) {
 #pragma unroll 4
@@ -820,25 +1014,41 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
   }
 }
 
-hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, const double* eta, double* out,
-                           hipStream_t s) {
+int rows_dot_chunks(int nr, i64 N) {
+  if (nr <= 0) return 1;
+  const i64 by_rows = (512 + nr - 1) / nr;           // aim at >= 512 workgroups
+  const i64 by_len = std::max<i64>(1, (N + 2047) / 2048);   // chunks of >= 2048 columns
+  return (int)std::max<i64>(1, std::min<i64>(16, std::min(by_rows, by_len)));
+}
+
+hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, double* part, hipStream_t s) {
   if (nr <= 0 || N <= 0) return hipSuccess;
-  k_rows_dot<<<dim3((unsigned)nr), dim3(1024), 0, s>>>(N, M, x, eta, out);
+  const int nch = rows_dot_chunks(nr, N);
+  k_rows_dot<<<dim3((unsigned)((i64)nr * nch)), dim3(RP_THREADS), 0, s>>>(N, nch, M, x, part);
   return hipGetLastError();
 }
 
-hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, const double* base, double* out,
-                              double* out2, const double* M2, const double* base2, double* out3, hipStream_t s,
-                              double* dot_part) {
+hipError_t launch_rows_dot_full(int nr, i64 N, const double* M, const double* x, double* out, hipStream_t s) {
+  if (nr <= 0 || N <= 0) return hipSuccess;
+  k_rows_dot<<<dim3((unsigned)nr), dim3(RP_THREADS), 0, s>>>(N, 1, M, x, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, int u_nch, const double* eta,
+                              const double* base, double* out, double* out2, const double* M2, const double* base2,
+                              double* out3, hipStream_t s, double* dot_part) {
   if (N <= 0) return hipSuccess;
+  if (u_nch < 1 || u_nch > CU_MAXCH) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((N + 63) / 64)), block(64 * CU_WAVES);
   if (M2 && dot_part)
-    k_cols_update<true, true><<<grid, block, 0, s>>>(nr, N, M, u, base, out, out2, M2, base2, out3, dot_part);
+    k_cols_update<true, true><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3,
+                                                     dot_part);
   else if (M2)
-    k_cols_update<true, false><<<grid, block, 0, s>>>(nr, N, M, u, base, out, out2, M2, base2, out3, nullptr);
+    k_cols_update<true, false><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3,
+                                                      nullptr);
   else
-    k_cols_update<false, false><<<grid, block, 0, s>>>(nr, N, M, u, base, out, out2, nullptr, nullptr, nullptr,
-                                                       nullptr);
+    k_cols_update<false, false><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, nullptr, nullptr,
+                                                       nullptr, nullptr);
   return hipGetLastError();
 }
 

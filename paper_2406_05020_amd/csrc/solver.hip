@@ -52,22 +52,41 @@ __global__ __launch_bounds__(256) void k_update2x(i64 N, const double* __restric
                                                   const double* __restrict__ eta_part, int n_eta,
                                                   const double* __restrict__ rr_in, int n_rr,
                                                   double* __restrict__ rr_out) {
-  __shared__ double red[256];
-  __shared__ int fl;
-  if (threadIdx.x == 0) fl = flag[0];
-  __syncthreads();
-  if (fl != 0) return;
-  double sr = scal[0], et = scal[1];
-  if (rr_in) {
-    sr = block_sum_fixed<256>(rr_in, n_rr, red);
-    __syncthreads();
-  }
-  if (eta_part) {
-    et = block_sum_fixed<256>(eta_part, n_eta, red);
-    __syncthreads();
-  }
+  __shared__ double red[256], red2[256];
+  // every load of the update is issued up front: the flag, both partial sums and the vectors
   const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (rr_in && sr <= scal[4] * scal[3]) {
+  const int fl = flag[0];
+  double dk = 0.0, wk = 0.0, vk = 0.0, rk0 = 0.0;
+  if (k < N) {
+    dk = d[k];
+    wk = w[k];
+    vk = v[k];
+    rk0 = r[k];
+  }
+  double pa = 0.0, pb = 0.0;                   // thread t adds t, t + 256, ... in order
+  if (rr_in)
+    for (int i = threadIdx.x; i < n_rr; i += 256) pa += rr_in[i];
+  if (eta_part)
+    for (int i = threadIdx.x; i < n_eta; i += 256) pb += eta_part[i];
+  double sr = scal[0], et = scal[1];
+  const double stop2 = scal[4] * scal[3];
+  if (fl != 0) return;                         // uniform: every thread read the same flag
+  if (rr_in || eta_part) {                     // both fixed trees at once
+    red[threadIdx.x] = pa;
+    red2[threadIdx.x] = pb;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+      if ((int)threadIdx.x < s2) {
+        red[threadIdx.x] += red[threadIdx.x + s2];
+        red2[threadIdx.x] += red2[threadIdx.x + s2];
+      }
+      __syncthreads();
+    }
+    if (rr_in) sr = red[0];
+    if (eta_part) et = red2[0];
+    __syncthreads();                           // red is reused for the r.r partials below
+  }
+  if (rr_in && sr <= stop2) {
     if (k == 0) {
       scal[0] = sr;
       flag[0] = 1;
@@ -81,9 +100,8 @@ __global__ __launch_bounds__(256) void k_update2x(i64 N, const double* __restric
   const double a = sr / et;
   double rr = 0.0;
   if (k < N) {
-    const double dk = d[k], wk = w[k];
-    v[k] += a * dk;
-    const double rk = r[k] - a * wk;
+    v[k] = vk + a * dk;
+    const double rk = rk0 - a * wk;
     r[k] = rk;
     X[k] = rk;
     Dcol[k] = dk;
@@ -369,6 +387,16 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
       rc = build_qc(h, h->stream);
       if (rc) return rc;
       so->qform = true;
+      // U = Q X rides in the launch of the volume operator's first stage (both read X only)
+      if (!so->pp.stages.empty()) {
+        RowsRider& rd = so->pp.stages[0].rider;
+        rd.nr = (int)h->nb;
+        rd.N = N;
+        rd.M = h->Qc;
+        rd.x = (const double*)so->X;
+        rd.eta = nullptr;
+        rd.out = (double*)so->U;
+      }
     }
   }
   if (elt == F64) {
@@ -395,10 +423,12 @@ static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
   hipError_t e;
   const i64 NN = h->N * so->nrhs;
   if (so->qform) {                                                  // G_pp X + s2 X - Q^T Q X
-    if ((e = launch_rows_dot(h->nb, h->N, h->Qc, (const double*)so->X, nullptr, (double*)so->U, s)) != hipSuccess)
+    if (so->pp.stages.empty() &&
+        (e = launch_rows_dot_full(h->nb, h->N, h->Qc, (const double*)so->X, (double*)so->U, s)) != hipSuccess)
       return e;
-    if ((e = run_plan(so->pp, s)) != hipSuccess) return e;
-    return launch_cols_update(h->nb, h->N, h->Qc, (const double*)so->U, (const double*)so->Y, (double*)so->Y, nullptr,
+    if ((e = run_plan(so->pp, s)) != hipSuccess) return e;               // (with U = Q X riding along)
+    return launch_cols_update(h->nb, h->N, h->Qc, (const double*)so->U, 1, nullptr, (const double*)so->Y,
+                              (double*)so->Y, nullptr,
                               nullptr, nullptr, nullptr, s);
   }
   if (so->elt == F64) {
@@ -460,7 +490,8 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
   h->Dd = (double*)h->arena.alloc((size_t)N * h->max_iter * sizeof(double));
   h->eta = (double*)h->arena.alloc(h->max_iter * sizeof(double));
   h->vec = (double*)h->arena.alloc((size_t)8 * N * sizeof(double));
-  h->aux = (double*)h->arena.alloc((size_t)(1024 + h->max_iter) * sizeof(double));
+  // 1024 dot partials, then the row-dot partials of the projections (<= max_iter + 527)
+  h->aux = (double*)h->arena.alloc((size_t)(2048 + h->max_iter) * sizeof(double));
   h->scal = (double*)h->arena.alloc(64 * sizeof(double));
   h->flag = (int*)h->arena.alloc(16 * sizeof(int));
   h->part = (double*)h->arena.alloc((size_t)((N + 63) / 64 + 2 * nblk(N) + 1) * sizeof(double));
@@ -509,7 +540,7 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
   double* d = h->vec + 2 * N;
   double* w = h->vec + 5 * N;
   double* dotp = h->aux;              // 512 dot partials
-  double* coef = h->aux + 1024;       // max_iter reorthogonalisation coefficients
+  double* coef = h->aux + 1024;       // row-dot partials of D^T (.) for the projections
   if (passes == 2 && !h->Qd) {
     h->Qd = (double*)h->arena.alloc((size_t)N * h->max_iter * sizeof(double));
     if (!h->Qd) { h->err = "out of device memory (S D store; lower max_iter)"; return GPFVM_E_NOMEM; }
@@ -527,9 +558,10 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
   hipLaunchKernelGGL(k_resid2, dim3(nblk(N)), dim3(256), 0, s, N, b, Y, r, X, (const int*)h->flag);
   int i = start;
   int hflag[2] = {0, 0};
-  // coef = eta^-1 o (D^T rhs) over the first nd stored directions
+  // coef = partial sums of D^T rhs over the first nd stored directions; the column update adds
+  // them up and divides by eta, so it applies eta^-1 o (D^T rhs)
   auto project = [&](const double* rhs_vec, int nd) {
-    return launch_rows_dot(nd, N, h->Dd, rhs_vec, h->eta, coef, s);
+    return launch_rows_dot(nd, N, h->Dd, rhs_vec, coef, s);
   };
   // two-pass form: r.r and the stopping test of an iteration come from the
   // previous update's partial sums (tested inside the update kernel), or from
@@ -561,7 +593,8 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
         HIPCHK(h, hipMemcpyAsync(h->vec + N, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         if (i > 0) {                                          // d = s - D (eta^-1 o D^T z)
           HIPCHK(h, project(Y, i));
-          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, X, d, X, nullptr, nullptr, nullptr, s));
+          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, rows_dot_chunks(i, N), h->eta, X, d, X, nullptr, nullptr,
+                                       nullptr, s));
         } else {
           HIPCHK(h, hipMemcpyAsync(d, X, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         }
@@ -569,10 +602,12 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
         if (i > 0) {
           // first pass: c = eta^-1 o D^T z ; d = s - D c ; w = S d = z - (S D) c
           HIPCHK(h, project(Y, i));
-          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, X, d, nullptr, h->Qd, Y, w, s));
+          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, rows_dot_chunks(i, N), h->eta, X, d, nullptr, h->Qd, Y, w,
+                                       s));
           // second pass on (d, w): c = eta^-1 o D^T w ; d -= D c ; w -= (S D) c ; eta = d^T w
           HIPCHK(h, project(w, i));
-          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, d, d, nullptr, h->Qd, w, w, s, eta_p));
+          HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, rows_dot_chunks(i, N), h->eta, d, d, nullptr, h->Qd, w, w,
+                                       s, eta_p));
         } else {
           HIPCHK(h, hipMemcpyAsync(d, X, N * sizeof(double), hipMemcpyDeviceToDevice, s));
           HIPCHK(h, hipMemcpyAsync(w, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -895,8 +930,9 @@ extern "C" int gpfvm_refine_variance(gpfvm_handle* h, int dim, const int* n, con
       HIPCHK(h, run_plan(so->pb, s));                       // Y -= G_pb G_bb^{-1} L_b k(X~) beta
     }
     if (i > 0) {
-      HIPCHK(h, launch_rows_dot(i, N, h->Dd, Y, h->eta, coef, s));
-      HIPCHK(h, launch_cols_update(i, N, h->Qd, coef, Y, X, nullptr, nullptr, nullptr, nullptr, s));
+      HIPCHK(h, launch_rows_dot(i, N, h->Dd, Y, coef, s));
+      HIPCHK(h, launch_cols_update(i, N, h->Qd, coef, rows_dot_chunks(i, N), h->eta, Y, X, nullptr, nullptr, nullptr,
+                                   nullptr, s));
     } else {
       HIPCHK(h, hipMemcpyAsync(X, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
