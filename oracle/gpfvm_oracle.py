@@ -19,6 +19,11 @@ Parity pins (tests under ``tests/test_oracle_*.py``):
                                residuals are the residuals of textbook CG on
                                that right-hand side; N iterations reproduce the
                                exact posterior; variance non-increasing
+  coarse warm start .......... pinned: the aggregated fine Gram equals the
+                               coarse scheme's own Gram (subdomain additivity);
+                               after the coarse block the posterior equals the
+                               exact posterior conditioned on points + coarse
+                               volumes; N directions reproduce the exact one
   IterGP ..................... pinned: unit-vector actions reproduce Cholesky;
                                run to n iterations reproduces the exact
                                posterior; combined variance >= exact and
@@ -39,6 +44,7 @@ import scipy.linalg as sla
 __all__ = [
     "load_quad", "kernel_q", "cell_cell", "point_cell", "point_point", "Oracle",
     "dense_posterior", "itergp", "itergp_targeted", "schur_cross", "cg_solve",
+    "coarse_aggregation", "itergp_coarse",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -354,7 +360,8 @@ class SchurSystem:
         return np.concatenate([ab, vp])
 
 
-def itergp(S, maxiter: int, tol: float = 0.0, actions: str = "cg", store: bool = True, passes: int = 1):
+def itergp(S, maxiter: int, tol: float = 0.0, actions: str = "cg", store: bool = True, passes: int = 1,
+           init: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None):
     """IterGP (Wenger et al. 2022, as used in Sec. 4.1/4.2) on system S with
     right-hand side S.b:
 
@@ -371,17 +378,25 @@ def itergp(S, maxiter: int, tol: float = 0.0, actions: str = "cg", store: bool =
     done twice, Limitations section) and then takes eta = d^T S d, which equals
     z^T d in exact arithmetic.
 
+    init = (v0, D0, eta0) continues from that state: the stored directions
+    D0 (with their eta0) stay in C and the iterations add to them (maxiter
+    counts the new ones).
+
     Returns (v, D, eta, residual norms).  Stops after maxiter iterations or
     once ||r|| <= tol ||b||."""
     b = S.b
     n = len(b)
-    v = np.zeros(n)
-    D = np.zeros((n, maxiter)) if store else None
-    eta = np.zeros(maxiter)
+    k0 = 0 if init is None else init[1].shape[1]
+    v = np.zeros(n) if init is None else np.array(init[0], dtype=float)
+    D = np.zeros((n, k0 + maxiter)) if store else None
+    eta = np.zeros(k0 + maxiter)
+    if k0:
+        D[:, :k0] = init[1]
+        eta[:k0] = init[2]
     res = []
     nb = np.linalg.norm(b)
-    k = 0
-    for i in range(maxiter):
+    k = k0
+    for i in range(k0, k0 + maxiter):
         r = b - S.matvec(v) if i > 0 else b.copy()
         res.append(np.linalg.norm(r))
         if tol > 0 and res[-1] <= tol * nb:
@@ -410,6 +425,45 @@ def itergp(S, maxiter: int, tol: float = 0.0, actions: str = "cg", store: bool =
         r = b - S.matvec(v)
         res.append(np.linalg.norm(r))
     return v, D[:, :k], eta[:k], np.array(res)
+
+
+def coarse_aggregation(p, factors: Sequence[int]) -> np.ndarray:
+    """The nested coarse scheme of the appendix "Multigrid preconditioners":
+    coarse cell a is the union of the factors[0] x ... x factors[d-1] fine
+    cells that refine it (Fig. multigrid-pyramid), so by eq.
+    subdomain-partition its integral functional is the sum of theirs.
+    Returns C (Nc x N, 0/1) with (C u)_a = sum of the fine values inside a,
+    both flattened row-major."""
+    nc = p.ncell
+    f = tuple(int(x) for x in factors)
+    if len(f) != p.d or any(x < 1 or n % x for x, n in zip(f, nc)):
+        raise ValueError(f"coarsening factors {f} must divide the cell counts {nc}")
+    cc = tuple(n // x for n, x in zip(nc, f))
+    fine = np.indices(nc).reshape(p.d, -1)                 # fine multi-indices, row-major
+    coarse = np.ravel_multi_index(tuple(fine[i] // f[i] for i in range(p.d)), cc)
+    C = np.zeros((int(np.prod(cc)), int(np.prod(nc))))
+    C[coarse, np.arange(C.shape[1])] = 1.0
+    return C
+
+
+def itergp_coarse(S, C: np.ndarray, maxiter: int, tol: float = 0.0, passes: int = 2):
+    """Coarse-scheme warm start (appendix "Multigrid preconditioners"): first
+    condition exactly on the coarse observations C y_V, then run IterGP with
+    CG actions on the fine volume observations as before.
+
+    Under the IC/BC-conditioned prior (Sec. 4.2) the coarse observations have
+    the Gram C S C^T, the aggregated fine noise included.  Conditioning on
+    them exactly is IterGP on S with the block of actions C^T solved by one
+    Cholesky factorisation C S C^T = L L^T: the directions D0 = C^T L^{-T}
+    are S-orthonormal (eta = 1) and the weights start at v0 = D0 D0^T b.
+    The CG iterations then continue with D0 kept in the inverse
+    approximation.  Returns (v, D, eta, residual norms of the CG phase)."""
+    SC = np.stack([S.matvec(c) for c in C], axis=1)          # S C^T, N x Nc
+    L = np.linalg.cholesky(C @ SC)
+    D0 = sla.solve_triangular(L, C, lower=True).T            # C^T L^{-T}
+    eta0 = np.ones(D0.shape[1])
+    v0 = D0 @ (D0.T @ S.b)
+    return itergp(S, maxiter, tol=tol, passes=passes, init=(v0, D0, eta0))
 
 
 def cg_solve(S, tol: float, maxiter: int):
