@@ -40,6 +40,9 @@ def parse():
                          "64^3 heat volume matvec with 64")
     ap.add_argument("--large-timing", action="store_true",
                     help="only time the wave 64x128x128 problem: assemble, 200 IterGP iterations, posterior")
+    ap.add_argument("--coarse-steps", type=int, default=5,
+                    help="steps of the same solve with the coarse-scheme warm start (8 x 8 fine cells per "
+                         "coarse cell), reported beside the headline (0 = skip)")
     ap.add_argument("--copy-bytes", type=int, default=256 << 20,
                     help="size of the plain device copy run after the roofline measurement (the counter "
                          "calibration for FETCH_SIZE / WRITE_SIZE)")
@@ -162,6 +165,8 @@ def main():
         "gram_matvec_gflops": rl["achieved"] * 1e3,
     }
     out["roofline"] = rl
+    if args.coarse_steps > 0 and prec == G.PREC_FP64:
+        out["coarse_warm_start"] = coarse_bench(p, (8, 8), args.coarse_steps, stream, mean, var)
     if args.extra_rooflines:
         out.update(extra_rooflines())
     if args.serve_requests > 0:
@@ -178,6 +183,34 @@ def main():
 # reads for the plain copy of known size that follows the measurement.  Set
 # to None whenever the GEMM kernel or the plan changes until re-measured.
 VOLUME_GEMM_TRAFFIC_BYTES = 57.10e6   # measured for k_gemm_lds<double,64,64> (scaled, per launch)
+
+
+def coarse_bench(p, coarsen, steps, stream, mean, var):
+    """The same step (assemble, solve to 1e-8, posterior, destroy) with the
+    coarse-scheme warm start: exact conditioning on the nested coarse volumes
+    first, then CG.  One untimed step first."""
+    import numpy as np
+    import torch
+    import paper_2406_05020_amd as G
+    cap = 2048
+    infos, lat = [], []
+    for k in range(steps + 1):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        h = G.assemble(p, max_iter=cap, stream=stream.cuda_stream)
+        try:
+            info = G.solve(h, tol=1e-8, max_iter=cap, check_every=16, coarsen=coarsen, stream=stream.cuda_stream)
+            G.posterior(h, p.grid, mean, var, stream=stream.cuda_stream)
+        finally:
+            G.destroy(h)
+        torch.cuda.synchronize()
+        if k > 0:
+            lat.append(time.perf_counter() - s0)
+            infos.append(info)
+    info = infos[-1]
+    return {"coarsen": list(coarsen), "solves_per_s": steps / sum(lat),
+            "ms_per_step": 1e3 * float(np.mean(lat)), "coarse_dirs": info["coarse"],
+            "cg_iters": info["iters"] - info["coarse"], "rel_res": info["rel_res"], "steps": steps}
 
 
 def large_timing(iters=200):

@@ -133,7 +133,16 @@ typedef struct {
   int reorth_passes;   /* 1: the published recurrence d = s - C z (one projection);  */
                        /* 2: the projection repeated on d (stored S D; default)      */
   int replace_every;   /* passes = 2: residual recomputed as b - S v every k iters   */
+  int coarsen[GPFVM_MAX_DIM]; /* coarse warm start (appendix "Multigrid preconditioners"):*/
+                       /* before CG, condition exactly on the nested coarse scheme   */
+                       /* whose cells are coarsen[0] x ... x coarsen[d-1] blocks of  */
+                       /* fine cells (factors divide the cell counts; all 1: off).   */
+                       /* Needs a fresh FP64 solve with reorth_passes = 2; the       */
+                       /* coarse cells (< assemble max_iter, <= GPFVM_MAX_COARSE)    */
+                       /* become the first stored directions.                       */
 } gpfvm_solve_opts;
+
+#define GPFVM_MAX_COARSE 8192
 
 typedef struct {
   int iters;           /* IterGP directions stored (posterior rank)                 */
@@ -141,6 +150,7 @@ typedef struct {
   double rel_res;      /* ||b - S v|| / ||b|| on the volume (Schur) system          */
   double rel_res_full; /* ||y - G alpha|| / ||y|| on the whole IBVP system           */
   int status;          /* GPFVM_OK, GPFVM_E_NOCONV or GPFVM_E_NOTPD                 */
+  int coarse;          /* directions of the coarse warm start (included in iters)   */
 } gpfvm_solve_info;
 
 typedef struct {

@@ -47,12 +47,12 @@ class AssembleOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("prec", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int), ("resume", C.c_int),
                 ("tile", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int),
-                ("reorth_passes", C.c_int), ("replace_every", C.c_int)]
+                ("reorth_passes", C.c_int), ("replace_every", C.c_int), ("coarsen", C.c_int * 3)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("outer", C.c_int), ("rel_res", C.c_double), ("rel_res_full", C.c_double),
-                ("status", C.c_int)]
+                ("status", C.c_int), ("coarse", C.c_int)]
 
 
 class HandleInfo(C.Structure):
@@ -252,9 +252,14 @@ def default_solve_opts() -> SolveOpts:
 
 def solve(h, prec: int = PREC_FP64, tol: float = 1e-8, max_iter: int = 512, resume: bool = False,
           tile: int = TILE_FP32, inner_tol: float = 1e-2, max_outer: int = 20, check_every: int = 8,
-          reorth_passes: int = 2, replace_every: int = 25, stream=None, raise_on_noconv: bool = False) -> dict:
+          reorth_passes: int = 2, replace_every: int = 25, stream=None, raise_on_noconv: bool = False,
+          coarsen: Optional[Sequence[int]] = None) -> dict:
+    """IterGP solve.  coarsen: per-dimension factors of the coarse warm start
+    (the coarse cells become the first directions; None or all 1: off)."""
+    cf = list(coarsen) if coarsen is not None else []
+    cf = (cf + [1, 1, 1])[:3]
     o = SolveOpts(prec, tol, max_iter, 1 if resume else 0, tile, inner_tol, max_outer, check_every,
-                  reorth_passes, replace_every)
+                  reorth_passes, replace_every, (C.c_int * 3)(*cf))
     info = SolveInfo()
     rc = lib().gpfvm_solve(h, C.byref(o), C.byref(info), _stream(stream))
     if rc not in (OK, E_NOCONV, E_NOTPD) or (raise_on_noconv and rc != OK):

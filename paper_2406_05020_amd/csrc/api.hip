@@ -81,6 +81,7 @@ extern "C" void gpfvm_default_solve_opts(gpfvm_solve_opts* o) {
   o->check_every = 8;
   o->reorth_passes = 2;
   o->replace_every = 25;
+  for (int k = 0; k < GPFVM_MAX_DIM; ++k) o->coarsen[k] = 1;
 }
 
 // ---------------------------------------------------------------------------

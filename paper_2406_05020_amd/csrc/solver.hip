@@ -709,6 +709,150 @@ static int full_residual(gpfvm_handle* h, double* out, hipStream_t s) {
   return rc;
 }
 
+// ---------------------------------------------------------------------------
+// Coarse-scheme warm start (appendix "Multigrid preconditioners"): exact
+// conditioning on nested coarse volumes before the CG iterations.  Coarse cell
+// a is the union of f[0] x ... x f[d-1] fine cells; its observation is the sum
+// of theirs (eq. subdomain-partition), i.e. the IterGP action C^T e_a on the
+// fine volume system.  The block of Nc such actions is solved exactly: with
+// C S C^T = L L^T the directions D0 = C^T L^{-T} are S-orthonormal (eta = 1),
+// S D0 = (S C^T) L^{-T}, and the weights start at v0 = D0 D0^T b.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct CoarseGeom {
+  int d;
+  int nc[3];   // fine cells per dimension
+  int f[3];    // coarsening factors
+  int cc[3];   // coarse cells per dimension
+};
+
+__device__ __forceinline__ i64 coarse_of(const CoarseGeom& g, i64 i) {
+  int idx[3] = {0, 0, 0};
+  for (int k = g.d - 1; k >= 0; --k) {
+    idx[k] = (int)(i % g.nc[k]);
+    i /= g.nc[k];
+  }
+  i64 a = 0;
+  for (int k = 0; k < g.d; ++k) a = a * g.cc[k] + idx[k] / g.f[k];
+  return a;
+}
+
+// C[a][i] = 1 if fine cell i lies in coarse cell a (Nc x N, row-major)
+__global__ void k_coarse_indicator(CoarseGeom g, i64 Nc, i64 N, double* __restrict__ C) {
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Nc * N) return;
+  const i64 a = e / N, i = e % N;
+  C[e] = coarse_of(g, i) == a ? 1.0 : 0.0;
+}
+
+// Gc[a][b] = sum over the fine cells i of coarse cell a of SC[b][i] (fine cells in row-major order)
+__global__ void k_coarse_gram(CoarseGeom g, i64 Nc, i64 N, const double* __restrict__ SC, double* __restrict__ Gc) {
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Nc * Nc) return;
+  const i64 a = e / Nc, b = e % Nc;
+  int ac[3] = {0, 0, 0};
+  i64 t = a;
+  for (int k = g.d - 1; k >= 0; --k) {
+    ac[k] = (int)(t % g.cc[k]);
+    t /= g.cc[k];
+  }
+  const int f1 = g.d > 1 ? g.f[1] : 1, f2 = g.d > 2 ? g.f[2] : 1;
+  double s = 0.0;
+  for (int j0 = 0; j0 < g.f[0]; ++j0)
+    for (int j1 = 0; j1 < f1; ++j1)
+      for (int j2 = 0; j2 < f2; ++j2) {
+        const int i0 = ac[0] * g.f[0] + j0;
+        i64 i = i0;
+        if (g.d > 1) i = i * g.nc[1] + (ac[1] * g.f[1] + j1);
+        if (g.d > 2) i = i * g.nc[2] + (ac[2] * g.f[2] + j2);
+        s += SC[b * N + i];
+      }
+  Gc[e] = s;
+}
+
+}  // namespace
+
+// Fills Dd, Qd and eta for the first Nc directions and v with v0; returns Nc through *nc_out.
+static int coarse_init(gpfvm_handle* h, const int* factors, hipStream_t s, int* nc_out) {
+  const int d = h->d;
+  const i64 N = h->N;
+  CoarseGeom g{};
+  g.d = d;
+  i64 Nc = 1;
+  for (int k = 0; k < 3; ++k) { g.nc[k] = 1; g.f[k] = 1; g.cc[k] = 1; }
+  for (int k = 0; k < d; ++k) {
+    g.nc[k] = h->nc[k];
+    g.f[k] = factors[k];
+    g.cc[k] = h->nc[k] / factors[k];
+    Nc *= g.cc[k];
+  }
+  if (!h->Qd) {
+    h->Qd = (double*)h->arena.alloc((size_t)N * h->max_iter * sizeof(double));
+    if (!h->Qd) { h->err = "out of device memory (S D store; lower max_iter)"; return GPFVM_E_NOMEM; }
+  }
+  Arena tmp;
+  tmp.cache = h->arena.cache;
+  auto fail = [&](int code, const std::string& m) { h->err = m; (void)hipStreamSynchronize(s); tmp.release(); return code; };
+  double* C = (double*)tmp.alloc((size_t)Nc * N * sizeof(double));
+  double* SC = (double*)tmp.alloc((size_t)Nc * N * sizeof(double));
+  double* R = (double*)tmp.alloc((size_t)Nc * N * sizeof(double));
+  double* Gc = (double*)tmp.alloc((size_t)Nc * Nc * sizeof(double));
+  double* Lic = (double*)tmp.alloc((size_t)Nc * Nc * sizeof(double));
+  if (!C || !SC || !R || !Gc || !Lic) return fail(GPFVM_E_NOMEM, "coarse warm start: out of device memory");
+  hipLaunchKernelGGL(k_coarse_indicator, dim3((unsigned)((Nc * N + 255) / 256)), dim3(256), 0, s, g, Nc, N, C);
+  // S C^T, a batch of right-hand sides at a time (rows of C are the rhs, N apart)
+  const int B = (int)std::min<i64>(Nc, 64);
+  gpfvm_sop* so = nullptr;
+  int rc = get_sop(h, B, F64, &so);
+  if (rc) { (void)hipStreamSynchronize(s); tmp.release(); return rc; }
+  for (i64 j0 = 0; j0 < Nc; j0 += B) {
+    const i64 nr = std::min<i64>(B, Nc - j0);
+    if (hipMemcpyAsync(so->X, C + j0 * N, (size_t)nr * N * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return fail(GPFVM_E_HIP, "coarse warm start: copy failed");
+    if (nr < B && launch_fill((double*)so->X + nr * N, 0.0, (B - nr) * N, s) != hipSuccess)
+      return fail(GPFVM_E_HIP, "coarse warm start: fill failed");
+    if (apply_sop(h, so, s) != hipSuccess) return fail(GPFVM_E_HIP, "coarse warm start: operator failed");
+    if (hipMemcpyAsync(SC + j0 * N, so->Y, (size_t)nr * N * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return fail(GPFVM_E_HIP, "coarse warm start: copy failed");
+  }
+  hipLaunchKernelGGL(k_coarse_gram, dim3((unsigned)((Nc * Nc + 255) / 256)), dim3(256), 0, s, g, Nc, N,
+                     (const double*)SC, Gc);
+  rc = cholesky_and_inverse(Gc, Lic, (int)Nc, tmp, s, h->err);
+  if (rc) {
+    if (rc == GPFVM_E_NOTPD) h->err = "coarse warm start: C S C^T is not positive definite";
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    return rc;
+  }
+  // Dd[0:Nc] = L^{-1} C and Qd[0:Nc] = L^{-1} (S C^T)^T, each as T = Linv B ; R = B - L T ; T += Linv R
+  const int n = (int)Nc;
+  std::vector<Stage> st(6);
+  double* outs[2] = {h->Dd, h->Qd};
+  const double* ins[2] = {C, SC};
+  for (int q = 0; q < 2; ++q) {
+    st[3 * q].descs.push_back(desc1(outs[q], N, Lic, n, 1, ins[q], N, 1, n, (int)N, n, 1.0, 0.0, 1));
+    GemmDesc D = desc1(R, N, Gc, n, 1, outs[q], N, 1, n, (int)N, n, -1.0, 0.0, 1);
+    D.X = ins[q]; D.x_rs = N; D.x_cs = 1; D.gamma = 1.0;
+    st[3 * q + 1].descs.push_back(D);
+    st[3 * q + 2].descs.push_back(desc1(outs[q], N, Lic, n, 1, R, N, 1, n, (int)N, n, 1.0, 1.0, 1));
+  }
+  if (upload_stages(st, tmp, s) != hipSuccess) return fail(GPFVM_E_HIP, "coarse warm start: upload failed");
+  if (run_stages(st, s) != hipSuccess) return fail(GPFVM_E_HIP, "coarse warm start: gemm failed");
+  // eta = 1 ; v = D0 (D0^T b): the column update gives -D0 c from base 0, negated after
+  double* coef = h->aux + 1024;
+  if (launch_fill(h->eta, 1.0, Nc, s) != hipSuccess || launch_fill(h->v, 0.0, N, s) != hipSuccess ||
+      launch_rows_dot(n, N, h->Dd, h->bS, coef, s) != hipSuccess ||
+      launch_cols_update(n, N, h->Dd, coef, rows_dot_chunks(n, N), h->eta, h->v, h->v, nullptr, nullptr, nullptr,
+                         nullptr, s) != hipSuccess ||
+      launch_axpby(N, 0.0, h->v, -1.0, h->v, s) != hipSuccess)
+    return fail(GPFVM_E_HIP, "coarse warm start: launch failed");
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(GPFVM_E_HIP, "coarse warm start: kernel failed");
+  tmp.release();
+  *nc_out = n;
+  return GPFVM_OK;
+}
+
 extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_solve_info* info, void* stream) {
   if (!h) return GPFVM_E_INVALID;
   gpfvm_solve_opts def;
@@ -722,15 +866,41 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
     return GPFVM_E_INVALID;
   }
   if (o->resume && !h->solved) { h->err = "solve: nothing to resume"; return GPFVM_E_STATE; }
+  // coarse warm start: factors >= 1 dividing the cell counts; all 1 = off
+  i64 n_coarse = 1;
+  bool coarse = false;
+  for (int k = 0; k < h->d; ++k) {
+    const int f = o->coarsen[k];
+    if (f < 1 || h->nc[k] % f != 0) { h->err = "solve: coarsening factors must divide the cell counts"; return GPFVM_E_INVALID; }
+    n_coarse *= h->nc[k] / f;
+    coarse |= (f > 1);
+  }
+  if (coarse) {
+    if (o->resume || o->prec != GPFVM_PREC_FP64 || o->reorth_passes != 2) {
+      h->err = "solve: the coarse warm start needs a fresh float64 solve with reorth_passes = 2";
+      return GPFVM_E_INVALID;
+    }
+    if (n_coarse >= h->max_iter || n_coarse > GPFVM_MAX_COARSE) {
+      h->err = "solve: too many coarse cells for the direction capacity (assemble max_iter) or the limit";
+      return GPFVM_E_INVALID;
+    }
+  }
   hipStream_t s = (hipStream_t)stream;
   h->stream = s;
   int rc = ensure_state(h, s);
   if (rc) return rc;
   const i64 N = h->N;
+  int n_dirs_coarse = 0;
   if (!o->resume) {
     HIPCHK(h, launch_fill(h->v, 0.0, N, s));
     h->iters = 0;
     h->sd_exact = true;
+    h->solved = false;
+    if (coarse) {
+      rc = coarse_init(h, o->coarsen, s, &n_dirs_coarse);
+      if (rc) return rc;
+      h->iters = n_dirs_coarse;
+    }
   }
   if (o->prec != GPFVM_PREC_FP64 || o->reorth_passes != 2) h->sd_exact = false;
   int state = 0, outer = 0;
@@ -789,6 +959,7 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
     info->rel_res = rs;
     info->rel_res_full = rf;
     info->status = GPFVM_OK;
+    info->coarse = n_dirs_coarse;
   }
   int status = GPFVM_OK;
   if (state == 2) status = GPFVM_E_NOTPD;
@@ -956,6 +1127,7 @@ extern "C" int gpfvm_refine_variance(gpfvm_handle* h, int dim, const int* n, con
     info->rel_res = rs;
     info->rel_res_full = rf;
     info->status = status;
+    info->coarse = 0;
   }
   if (status == GPFVM_E_NOTPD) h->err = "IterGP breakdown: eta <= 0 (state kept up to the last good direction)";
   return status;
