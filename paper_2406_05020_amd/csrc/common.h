@@ -61,14 +61,18 @@ struct GemmDesc {
 enum Elt { F64 = 0, F32 = 1 };
 
 // One kernel launch: a set of descriptors whose outputs do not overlap.
-// Row dots carried by a GEMM stage's launch as extra workgroups after its
-// tiles: out[j] = M[j,:] . x (divided by eta[j] when eta is set), j < nr,
-// float64.  They must not touch the stage's own inputs or outputs.
-struct RowsRider {
+// Streaming products carried by a GEMM stage's launch as extra workgroups
+// after its tiles (float64).  They must not touch the stage's own inputs or
+// outputs.
+//   RIDE_ROWS: out[j] = M[j,:] . v (divided by eta[j] when eta is set), j < nr
+//   RIDE_COLS: out[c] = sum_j M[j][c] v[j], c < N (v: nr coefficients)
+enum RiderKind { RIDE_NONE = 0, RIDE_ROWS = 1, RIDE_COLS = 2 };
+struct Rider {
+  int kind = RIDE_NONE;
   int nr = 0;
   i64 N = 0;
   const double* M = nullptr;   // nr x N, row-major
-  const double* x = nullptr;
+  const double* v = nullptr;
   const double* eta = nullptr;
   double* out = nullptr;
 };
@@ -79,7 +83,7 @@ struct Stage {
   i64 tiles = 0;
   int kind = 0;    // GEMM_SPLITK / GEMM_LDS16 / GEMM_LDS32 / GEMM_LDS64 (set when the stage is uploaded)
   int slot1 = 0;   // some segment accumulates into slot 1
-  RowsRider rider; // launched with the stage (nr = 0: none)
+  Rider rider;     // launched with the stage (kind RIDE_NONE: none)
 };
 enum GemmKind { GEMM_SPLITK = 0, GEMM_LDS32 = 1, GEMM_LDS64 = 2, GEMM_LDS16 = 3 };
 
@@ -225,14 +229,18 @@ hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s);
 //   cols_update: u_j = (sum_ch u[j * u_nch + ch]) / (eta ? eta[j] : 1);
 //                out[c] = base[c] - sum_j M[j][c] u_j (and out2[c] = out[c] if out2);
 //                with M2: out3[c] = base2[c] - sum_j M2[j][c] u_j.   base may alias out.
+//   (rows_dot with xm: the dots are taken with x - xm)
 int rows_dot_chunks(int nr, i64 N);
-hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, double* part, hipStream_t s);
+hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, double* part, hipStream_t s,
+                           const double* xm = nullptr);
 hipError_t launch_rows_dot_full(int nr, i64 N, const double* M, const double* x, double* out, hipStream_t s);
 //   With M2 and dot_part: also dot_part[g] = workgroup g's share of sum_c out[c] * out3[c]
 //   (ceil(N/64) values; their fixed-order sum is the dot product).
+//   With base2m: out3[c] = (base2[c] - base2m[c]) - sum_j M2[j][c] u_j.
 hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, int u_nch, const double* eta,
                               const double* base, double* out, double* out2, const double* M2, const double* base2,
-                              double* out3, hipStream_t s, double* dot_part = nullptr);
+                              double* out3, hipStream_t s, double* dot_part = nullptr,
+                              const double* base2m = nullptr);
 // y[i] = add[i] + alpha * sum_k M[i][k] x[k] over k <= i (upper = 0) or k >= i (upper = 1)
 hipError_t launch_trmv_rows(int n, const double* M, const double* x, double* y, double alpha, const double* add,
                             int upper, hipStream_t s);
@@ -265,6 +273,11 @@ struct gpfvm_sop {
   bool qform = false;               // correction as Q^T (Q x) with the handle's Q
   gpfvm::Plan front;                // pp and bp merged into shared launches
   double flops_pp = 0;
+  // Q-form split application (two-pass solver loop): pp_split leaves Y = G_pp X + s2 X and
+  // csub = Q^T (Q X), riding on the first and the last stage; consumers use Y - csub.
+  gpfvm::Plan pp_split;
+  double* csub = nullptr;
+  bool split = false;
 };
 
 struct gpfvm_handle {

@@ -352,7 +352,7 @@ constexpr int RD_U = 16;
 
 template <int NT>
 __device__ __forceinline__ double dot_range(const double* __restrict__ q, const double* __restrict__ x, i64 c_lo,
-                                            i64 c_hi, double* red) {
+                                            i64 c_hi, double* red, const double* __restrict__ xm = nullptr) {
   double acc[RD_U];
 #pragma unroll
   for (int u = 0; u < RD_U; ++u) acc[u] = 0.0;
@@ -363,6 +363,13 @@ __device__ __forceinline__ double dot_range(const double* __restrict__ q, const 
       const i64 c = c0 + (i64)u * NT;
       qv[u] = c < c_hi ? q[c] : 0.0;
       xv[u] = c < c_hi ? x[c] : 0.0;
+    }
+    if (xm) {
+#pragma unroll
+      for (int u = 0; u < RD_U; ++u) {
+        const i64 c = c0 + (i64)u * NT;
+        xv[u] -= c < c_hi ? xm[c] : 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < RD_U; ++u) acc[u] = fma(qv[u], xv[u], acc[u]);
@@ -390,9 +397,51 @@ __device__ __forceinline__ void rows_dot_block(i64 N, const double* __restrict__
   if (threadIdx.x == 0) out[row] = eta ? s / eta[row] : s;
 }
 
+// One workgroup of NT threads: out[c] = sum_j M[j][c] v[j] for the 64
+// columns c of block `blk`.  The sum runs in the order of k_cols_update:
+// 16 partial sums, partial w over the rows j = w, w + 16, ... in turn, then
+// the partials in order (each wavefront keeps 16 / (NT / 64) of them).
+// red: 1024 doubles of LDS.
+constexpr int CS_PARTS = 16;
+
+template <int NT>
+__device__ __forceinline__ void cols_sum_block(int nr, i64 N, const double* __restrict__ M,
+                                               const double* __restrict__ v, double* __restrict__ out, i64 blk,
+                                               double* red) {
+  constexpr int NW = NT / 64, PER = CS_PARTS / NW;
+  static_assert(PER * NW == CS_PARTS, "partial sums per wavefront");
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const i64 c = blk * 64 + lane;
+  double acc[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) acc[k] = 0.0;
+  if (c < N) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int w = wave + k * NW;
+#pragma unroll 4
+      for (int j = w; j < nr; j += CS_PARTS) acc[k] = fma(M[(i64)j * N + c], v[j], acc[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) red[(wave + k * NW) * 64 + lane] = acc[k];
+  __syncthreads();
+  if (wave == 0 && c < N) {
+    double t = 0.0;
+    for (int w = 0; w < CS_PARTS; ++w) t += red[w * 64 + lane];
+    out[c] = t;
+  }
+}
+
+__global__ __launch_bounds__(512) void k_cols_sum(int nr, i64 N, const double* __restrict__ M,
+                                                  const double* __restrict__ v, double* __restrict__ out) {
+  __shared__ double red[64 * CS_PARTS];
+  cols_sum_block<512>(nr, N, M, v, out, blockIdx.x, red);
+}
+
 template <typename T, int BM, int BN, int KS, bool SLOT1, bool RIDE>
 __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDesc* __restrict__ descs, int ndesc,
-                                                                    i64 ntiles, RowsRider rider) {
+                                                                    i64 ntiles, Rider rider) {
   typedef typename MfmaOp<T>::v4 v4;
   constexpr int WNN = BN / 16, NBLK = (BM / 16) * (BN / 16), NT = 64 * NBLK * KS, LKC = 16 * KS;
   constexpr int EA = BM * LKC / NT, EB = LKC * BN / NT;
@@ -410,9 +459,12 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
 
   const i64 tile = blockIdx.x;
   if constexpr (RIDE) {
-    if (tile >= ntiles) {                          // a workgroup of the riding row dots
-      __shared__ double rred[NT / 64];
-      rows_dot_block<NT>(rider.N, rider.M, rider.x, rider.eta, rider.out, (int)(tile - ntiles), rred);
+    if (tile >= ntiles) {                          // a workgroup of the riding streaming product
+      __shared__ double rred[64 * CS_PARTS];
+      if (rider.kind == RIDE_ROWS)
+        rows_dot_block<NT>(rider.N, rider.M, rider.v, rider.eta, rider.out, (int)(tile - ntiles), rred);
+      else
+        cols_sum_block<NT>(rider.nr, rider.N, rider.M, rider.v, rider.out, tile - ntiles, rred);
       return;
     }
   }
@@ -654,8 +706,9 @@ template <typename T, int BM, int KS>
 static void launch_lds(const Stage& st, int nd, hipStream_t s) {
   const dim3 block(4 * BM * BM / 16 * KS);
   if constexpr (std::is_same<T, double>::value) {
-    if (st.rider.nr > 0) {                         // the stage carries row dots
-      const dim3 grid((unsigned)(st.tiles + st.rider.nr));
+    if (st.rider.kind != RIDE_NONE) {              // the stage carries a streaming product
+      const i64 extra = st.rider.kind == RIDE_ROWS ? st.rider.nr : (st.rider.N + 63) / 64;
+      const dim3 grid((unsigned)(st.tiles + extra));
       if (st.slot1)
         k_gemm_lds<T, BM, BM, KS, true, true><<<grid, block, 0, s>>>(st.d_descs, nd, st.tiles, st.rider);
       else
@@ -671,14 +724,21 @@ static void launch_lds(const Stage& st, int nd, hipStream_t s) {
 }
 
 hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
-  if (st.rider.nr > 0 && (elt != F64 || st.kind == GEMM_SPLITK || st.tiles == 0 || st.descs.empty())) {
-    // the riding row dots run on their own where the stage's kernel cannot carry them
-    if (st.rider.eta) return hipErrorInvalidValue;  // partial sums carry no division
-    const hipError_t e = launch_rows_dot_full(st.rider.nr, st.rider.N, st.rider.M, st.rider.x, st.rider.out, s);
+  if (st.rider.kind != RIDE_NONE && (elt != F64 || st.kind == GEMM_SPLITK || st.tiles == 0 || st.descs.empty())) {
+    // the riding product runs on its own where the stage's kernel cannot carry it
+    hipError_t e;
+    if (st.rider.kind == RIDE_ROWS) {
+      if (st.rider.eta) return hipErrorInvalidValue;  // the stand-alone row dots carry no division
+      e = launch_rows_dot_full(st.rider.nr, st.rider.N, st.rider.M, st.rider.v, st.rider.out, s);
+    } else {
+      k_cols_sum<<<dim3((unsigned)((st.rider.N + 63) / 64)), dim3(512), 0, s>>>(st.rider.nr, st.rider.N, st.rider.M,
+                                                                                st.rider.v, st.rider.out);
+      e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
     if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
     Stage plain = st;
-    plain.rider = RowsRider();
+    plain.rider = Rider();
     return launch_gemm_stage(elt, plain, s);
   }
   if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
@@ -934,6 +994,7 @@ hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const 
 // Both are deterministic; base may alias out.
 // ----------------------------------------------------------------------------
 constexpr int CU_WAVES = 16;
+static_assert(CU_WAVES == CS_PARTS, "the riding column sums follow the column update's order");
 constexpr int CU_BLK = 2048;
 constexpr int CU_MAXCH = 16;   // most partial sums per coefficient (rows_dot_chunks <= 16)
 
@@ -944,12 +1005,13 @@ constexpr int CU_MAXCH = 16;   // most partial sums per coefficient (rows_dot_ch
 constexpr int RP_THREADS = 256;
 
 __global__ __launch_bounds__(RP_THREADS) void k_rows_dot(i64 N, int nch, const double* __restrict__ M,
-                                                         const double* __restrict__ x, double* __restrict__ part) {
+                                                         const double* __restrict__ x, const double* __restrict__ xm,
+                                                         double* __restrict__ part) {
   __shared__ double red[RP_THREADS / 64];
   const int row = (int)(blockIdx.x / nch), ch = (int)(blockIdx.x % nch);
   const i64 L = (N + nch - 1) / nch;
   const i64 lo = (i64)ch * L, hi = min(N, lo + L);
-  const double s = dot_range<RP_THREADS>(M + (i64)row * N, x, lo, hi, red);
+  const double s = dot_range<RP_THREADS>(M + (i64)row * N, x, lo, hi, red, xm);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -958,7 +1020,8 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
                                                                const double* __restrict__ u, int u_nch,
                                                                const double* __restrict__ eta, const double* base,
                                                                double* out, double* out2, const double* __restrict__ M2,
-                                                               const double* base2, double* out3, double* dot_part) {
+                                                               const double* base2, double* out3, double* dot_part,
+                                                               const double* __restrict__ base2m) {
   __shared__ double us[CU_BLK];
   __shared__ double part[CU_WAVES][64];
   __shared__ double part2[TWO ? CU_WAVES : 1][64];
@@ -1003,7 +1066,8 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
     if (TWO) {
       double s2 = 0.0;
       for (int w = 0; w < CU_WAVES; ++w) s2 += part2[w][lane];
-      const double v3 = base2[c] - s2;
+      const double b2 = base2m ? base2[c] - base2m[c] : base2[c];
+      const double v3 = b2 - s2;
       out3[c] = v3;
       prod = v * v3;
     }
@@ -1021,34 +1085,35 @@ int rows_dot_chunks(int nr, i64 N) {
   return (int)std::max<i64>(1, std::min<i64>(16, std::min(by_rows, by_len)));
 }
 
-hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, double* part, hipStream_t s) {
+hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, double* part, hipStream_t s,
+                           const double* xm) {
   if (nr <= 0 || N <= 0) return hipSuccess;
   const int nch = rows_dot_chunks(nr, N);
-  k_rows_dot<<<dim3((unsigned)((i64)nr * nch)), dim3(RP_THREADS), 0, s>>>(N, nch, M, x, part);
+  k_rows_dot<<<dim3((unsigned)((i64)nr * nch)), dim3(RP_THREADS), 0, s>>>(N, nch, M, x, xm, part);
   return hipGetLastError();
 }
 
 hipError_t launch_rows_dot_full(int nr, i64 N, const double* M, const double* x, double* out, hipStream_t s) {
   if (nr <= 0 || N <= 0) return hipSuccess;
-  k_rows_dot<<<dim3((unsigned)nr), dim3(RP_THREADS), 0, s>>>(N, 1, M, x, out);
+  k_rows_dot<<<dim3((unsigned)nr), dim3(RP_THREADS), 0, s>>>(N, 1, M, x, nullptr, out);
   return hipGetLastError();
 }
 
 hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, int u_nch, const double* eta,
                               const double* base, double* out, double* out2, const double* M2, const double* base2,
-                              double* out3, hipStream_t s, double* dot_part) {
+                              double* out3, hipStream_t s, double* dot_part, const double* base2m) {
   if (N <= 0) return hipSuccess;
   if (u_nch < 1 || u_nch > CU_MAXCH) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((N + 63) / 64)), block(64 * CU_WAVES);
   if (M2 && dot_part)
     k_cols_update<true, true><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3,
-                                                     dot_part);
+                                                     dot_part, base2m);
   else if (M2)
     k_cols_update<true, false><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3,
-                                                      nullptr);
+                                                      nullptr, base2m);
   else
     k_cols_update<false, false><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, nullptr, nullptr,
-                                                       nullptr, nullptr);
+                                                       nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 

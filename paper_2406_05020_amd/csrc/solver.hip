@@ -389,13 +389,29 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
       so->qform = true;
       // U = Q X rides in the launch of the volume operator's first stage (both read X only)
       if (!so->pp.stages.empty()) {
-        RowsRider& rd = so->pp.stages[0].rider;
+        Rider& rd = so->pp.stages[0].rider;
+        rd.kind = RIDE_ROWS;
         rd.nr = (int)h->nb;
         rd.N = N;
         rd.M = h->Qc;
-        rd.x = (const double*)so->X;
+        rd.v = (const double*)so->X;
         rd.eta = nullptr;
         rd.out = (double*)so->U;
+      }
+      // split form for the two-pass loop: Q^T U also rides, on the last stage (U is complete by then)
+      if (so->pp.stages.size() >= 2) {
+        so->csub = (double*)h->arena.alloc((size_t)N * sizeof(double));
+        if (!so->csub) { h->err = "out of device memory (S operator)"; return GPFVM_E_NOMEM; }
+        so->pp_split = so->pp;
+        Rider& rc2 = so->pp_split.stages.back().rider;
+        rc2.kind = RIDE_COLS;
+        rc2.nr = (int)h->nb;
+        rc2.N = N;
+        rc2.M = h->Qc;
+        rc2.v = (const double*)so->U;
+        rc2.eta = nullptr;
+        rc2.out = so->csub;
+        so->split = true;
       }
     }
   }
@@ -588,7 +604,11 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
         const int rc = (*action)(i);
         if (rc) return rc;
       }
-      HIPCHK(h, apply_sop(h, so, s));                         // z = S s  (in Y)
+      // z = S s: in Y, or as Y - csub with the split Q-form (two-pass loop)
+      const bool split = (passes == 2 && so->split);
+      if (split) HIPCHK(h, run_plan(so->pp_split, s));
+      else HIPCHK(h, apply_sop(h, so, s));
+      const double* zm = split ? so->csub : nullptr;
       if (passes == 1) {
         HIPCHK(h, hipMemcpyAsync(h->vec + N, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         if (i > 0) {                                          // d = s - D (eta^-1 o D^T z)
@@ -601,9 +621,9 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
       } else {
         if (i > 0) {
           // first pass: c = eta^-1 o D^T z ; d = s - D c ; w = S d = z - (S D) c
-          HIPCHK(h, project(Y, i));
+          HIPCHK(h, launch_rows_dot(i, N, h->Dd, Y, coef, s, zm));
           HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, rows_dot_chunks(i, N), h->eta, X, d, nullptr, h->Qd, Y, w,
-                                       s));
+                                       s, nullptr, zm));
           // second pass on (d, w): c = eta^-1 o D^T w ; d -= D c ; w -= (S D) c ; eta = d^T w
           HIPCHK(h, project(w, i));
           HIPCHK(h, launch_cols_update(i, N, h->Dd, coef, rows_dot_chunks(i, N), h->eta, d, d, nullptr, h->Qd, w, w,
@@ -611,6 +631,7 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
         } else {
           HIPCHK(h, hipMemcpyAsync(d, X, N * sizeof(double), hipMemcpyDeviceToDevice, s));
           HIPCHK(h, hipMemcpyAsync(w, Y, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+          if (zm) HIPCHK(h, launch_axpby(N, -1.0, zm, 1.0, w, s));   // w = z = Y - csub
           HIPCHK(h, launch_dot(N, w, d, dotp, h->scal + 1, s));   // eta = d^T S d
         }
       }
