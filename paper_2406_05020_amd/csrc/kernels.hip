@@ -343,6 +343,18 @@ __global__ __launch_bounds__(64 * SK_WAVES) void k_gemm_sk(const GemmDesc* __res
 // One workgroup of NT threads: out[row] = M[row,:] . x (/ eta[row]), summed in
 // a fixed order (two interleaved accumulators per thread, then a wavefront
 // tree, then the wavefronts in order).  red: NT / 64 doubles of LDS.
+// Operand pointers read from a descriptor are generic; as global-address-space
+// pointers (the same address for device allocations) their loads become
+// global loads, whose completion counter is in order, so a load can stay in
+// flight across the LDS stores of an earlier chunk.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(const T* p) {
+  return (gptr<T>)p;
+}
+
 // Dot product of q[c_lo, c_hi) and x[c_lo, c_hi) by one workgroup of NT
 // threads, valid in thread 0.  Each thread issues RD_U loads of both vectors
 // before it multiplies; the sum runs in a fixed order (RD_U accumulators per
@@ -439,11 +451,15 @@ __global__ __launch_bounds__(512) void k_cols_sum(int nr, i64 N, const double* _
   cols_sum_block<512>(nr, N, M, v, out, blockIdx.x, red);
 }
 
+constexpr int GEMM_KDEPTH1 = 1;
+
 template <typename T, int BM, int BN, int KS, bool SLOT1, bool RIDE>
 __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDesc* __restrict__ descs, int ndesc,
                                                                     i64 ntiles, Rider rider) {
   typedef typename MfmaOp<T>::v4 v4;
-  constexpr int WNN = BN / 16, NBLK = (BM / 16) * (BN / 16), NT = 64 * NBLK * KS, LKC = 16 * KS;
+  // K chunk: 16 per K group; a single K group takes GEMM_KDEPTH1 x 16 per chunk
+  constexpr int WNN = BN / 16, NBLK = (BM / 16) * (BN / 16), NT = 64 * NBLK * KS,
+                LKC = KS == 1 ? 16 * GEMM_KDEPTH1 : 16 * KS;
   constexpr int EA = BM * LKC / NT, EB = LKC * BN / NT;
   static_assert(EA * NT == BM * LKC && EB * NT == LKC * BN, "tile shape");
   constexpr int NS = SLOT1 ? 2 : 1;
@@ -487,19 +503,23 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
   const int bidx = wave % NBLK, kg = wave / NBLK;
   const int rb = (bidx / WNN) * 16, cb = (bidx % WNN) * 16;
 
-  v4 acc[NS];
+  // two accumulators per slot, alternating over the MFMAs of a chunk, so that
+  // consecutive MFMAs of a wavefront do not wait on each other's result; they
+  // are added once at the end
+  v4 acc[NS], acc2[NS];
 #pragma unroll
   for (int q = 0; q < NS; ++q)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[q][r] = 0;
+    for (int r = 0; r < 4; ++r) acc[q][r] = acc2[q][r] = 0;
 
   if constexpr (KS == 1) {
     // one K group: each segment runs its own chunk loop (many short chunks per
     // segment, so the exposed first load of a segment matters little)
     for (int g = 0; g < D.nseg; ++g) {
       const Seg& S = D.seg[g];
-      const T* __restrict__ A = reinterpret_cast<const T*>(S.A) + b * S.a_bs;
-      const T* __restrict__ B = reinterpret_cast<const T*>(S.B) + b * S.b_bs;
+      const gptr<T> __restrict__ A = to_global(reinterpret_cast<const T*>(S.A) + b * S.a_bs);
+      const gptr<T> __restrict__ B = to_global(reinterpret_cast<const T*>(S.B) + b * S.b_bs);
+      const i64 a_rs = S.a_rs, a_cs = S.a_cs, b_rs = S.b_rs, b_cs = S.b_cs;
       const T alpha = (T)S.alpha;
       int kbeg = 0, kend = S.K;
       if (S.tri == 1) kend = min(S.K, m0 + BM);
@@ -507,60 +527,83 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
       else if (S.tri == 3) kend = min(S.K, n0 + BN);
       else if (S.tri == 4) kbeg = n0;
       if (kbeg >= kend) continue;                    // uniform over the workgroup
-      const bool akf = (S.a_cs == 1), bnf = (S.b_cs == 1);
+      const bool akf = (a_cs == 1), bnf = (b_cs == 1);
       const int q = SLOT1 ? S.slot : 0;
-      T ra[EA], rbv[EB];
-      auto gload = [&](int kc) {
+      // two register sets: the load of chunk c + 2 is issued while chunk c is
+      // multiplied, so each load has two chunks of work to hide behind.  Every
+      // lane loads (from a clamped, in-range address) and out-of-range elements
+      // are multiplied by zero when stored to LDS, so the loads form
+      // straight-line code and only the older set is waited for.  (For finite
+      // operands this is exactly zero; a non-finite value at a clamped address
+      // reaches only outputs whose own sums already hold it.)
+      T ra0[EA], rb0[EB], ra1[EA], rb1[EB];
+      auto gload = [&](T* ra, T* rbv, int kc) {
   #pragma unroll
         for (int u = 0; u < EA; ++u) {
           const int e = tid + NT * u;
           int k, m;
           if (akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
-          ra[u] = (m0 + m < M && kc + k < kend) ? A[(i64)(m0 + m) * S.a_rs + (i64)(kc + k) * S.a_cs] : (T)0;
+          const int mm = min(m0 + m, M - 1), kk = min(kc + k, kend - 1);
+          ra[u] = A[(i64)mm * a_rs + (i64)kk * a_cs];
         }
   #pragma unroll
         for (int u = 0; u < EB; ++u) {
           const int e = tid + NT * u;
           int k, n;
           if (bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
-          rbv[u] = (n0 + n < N && kc + k < kend) ? B[(i64)(kc + k) * S.b_rs + (i64)(n0 + n) * S.b_cs] : (T)0;
+          const int nn = min(n0 + n, N - 1), kk = min(kc + k, kend - 1);
+          rbv[u] = B[(i64)kk * b_rs + (i64)nn * b_cs];
         }
       };
-      auto sstore = [&](int buf) {
+      // the chunk starting at kc goes to LDS buffer buf; out-of-range elements x 0
+      auto sstore = [&](const T* ra, const T* rbv, int buf, int kc) {
   #pragma unroll
         for (int u = 0; u < EA; ++u) {
           const int e = tid + NT * u;
           int k, m;
           if (akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
-          As(buf, k, m) = alpha * ra[u];
+          const T msk = (m0 + m < M && kc + k < kend) ? alpha : (T)0;
+          As(buf, k, m) = msk * ra[u];
         }
   #pragma unroll
         for (int u = 0; u < EB; ++u) {
           const int e = tid + NT * u;
           int k, n;
           if (bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
-          Bs(buf, k, n) = rbv[u];
+          const T msk = (n0 + n < N && kc + k < kend) ? (T)1 : (T)0;
+          Bs(buf, k, n) = msk * rbv[u];
         }
       };
-      __syncthreads();                               // previous segment's reads of buffer 0 are done
-      gload(kbeg);
-      sstore(0);
-      __syncthreads();
-      int buf = 0;
-      for (int kc = kbeg; kc < kend; kc += LKC) {
-        const bool more = kc + LKC < kend;
-        if (more) gload(kc + LKC);
+      auto mult = [&](int buf) {
   #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const int k = kg * 16 + kk + lk;
+        for (int kk = 0; kk < LKC; kk += 4) {
+          const int k = kk + lk;
           const T av = As(buf, k, rb + lr);
           const T bv = Bs(buf, k, cb + lr);
-          if (q == 0) acc[0] = MfmaOp<T>::mac(av, bv, acc[0]);
-          else acc[NS - 1] = MfmaOp<T>::mac(av, bv, acc[NS - 1]);
+          v4* a = ((kk >> 2) & 1) ? acc2 : acc;
+          if (q == 0) a[0] = MfmaOp<T>::mac(av, bv, a[0]);
+          else a[NS - 1] = MfmaOp<T>::mac(av, bv, a[NS - 1]);
         }
-        if (more) sstore(buf ^ 1);
+      };
+      const int nch = (kend - kbeg + LKC - 1) / LKC;
+      const int klast = kbeg + (nch - 1) * LKC;       // start of the last chunk
+      __syncthreads();                               // previous segment's reads of buffer 0 are done
+      gload(ra0, rb0, kbeg);
+      gload(ra1, rb1, min(kbeg + LKC, klast));
+      sstore(ra0, rb0, 0, kbeg);
+      __syncthreads();
+      // chunk c is in LDS buffer c % 2 and, before that, in register set c % 2;
+      // past the last chunk the prefetch re-reads it and is never stored
+      for (int c = 0; c < nch; c += 2) {
+        gload(ra0, rb0, min(kbeg + (c + 2) * LKC, klast));
+        mult(0);
+        if (c + 1 < nch) sstore(ra1, rb1, 1, kbeg + (c + 1) * LKC);
         __syncthreads();
-        buf ^= 1;
+        if (c + 1 >= nch) break;
+        gload(ra1, rb1, min(kbeg + (c + 3) * LKC, klast));
+        mult(1);
+        if (c + 2 < nch) sstore(ra0, rb0, 0, kbeg + (c + 2) * LKC);
+        __syncthreads();
       }
     }
 
@@ -569,8 +612,8 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
     // next chunk (possibly the first of the next segment) is prefetched to
     // registers while the current one is multiplied out of LDS.
     struct Ctx {
-      const T* A;
-      const T* B;
+      gptr<T> A;
+      gptr<T> B;
       i64 a_rs, a_cs, b_rs, b_cs;
       T alpha;
       int kbeg, kend, q;
@@ -578,8 +621,8 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
     };
     auto ctx_of = [&](int g, Ctx& c) -> bool {      // false: empty K range
       const Seg& S = D.seg[g];
-      c.A = reinterpret_cast<const T*>(S.A) + b * S.a_bs;
-      c.B = reinterpret_cast<const T*>(S.B) + b * S.b_bs;
+      c.A = to_global(reinterpret_cast<const T*>(S.A) + b * S.a_bs);
+      c.B = to_global(reinterpret_cast<const T*>(S.B) + b * S.b_bs);
       c.a_rs = S.a_rs; c.a_cs = S.a_cs; c.b_rs = S.b_rs; c.b_cs = S.b_cs;
       c.alpha = (T)S.alpha;
       c.kbeg = 0; c.kend = S.K;
@@ -651,8 +694,9 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
           const int k = kg * 16 + kk + lk;
           const T av = As(buf, k, rb + lr);
           const T bv = Bs(buf, k, cb + lr);
-          if (q == 0) acc[0] = MfmaOp<T>::mac(av, bv, acc[0]);
-          else acc[NS - 1] = MfmaOp<T>::mac(av, bv, acc[NS - 1]);
+          v4* a = ((kk >> 2) & 1) ? acc2 : acc;
+          if (q == 0) a[0] = MfmaOp<T>::mac(av, bv, a[0]);
+          else a[NS - 1] = MfmaOp<T>::mac(av, bv, a[NS - 1]);
         }
         if (more) sstore(nxt, buf ^ 1);
         __syncthreads();
@@ -665,6 +709,11 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
     }
 
   }
+
+#pragma unroll
+  for (int q = 0; q < NS; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[q][r] += acc2[q][r];
 
   if (KS > 1) {                                    // sum the K groups in a fixed order
     __syncthreads();
