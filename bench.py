@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--serve-rates", default="0.8",
                     help="comma-separated arrival rates as fractions of the saturated throughput")
     ap.add_argument("--serving-only", action="store_true", help="only the serving measurement")
+    ap.add_argument("--serve-coarse", type=int, default=0,
+                    help="also serve with every solve warm-started on a coarse scheme of at most this many "
+                         "cells (0 = skip)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the volume-Gram matvec measurement (the command profiled under rocprofv3)")
     ap.add_argument("--extra-rooflines", action="store_true",
@@ -87,7 +90,7 @@ def main():
     p = W.advdiff_c2()
     if args.serving_only:
         rates = tuple(float(r) for r in args.serve_rates.split(","))
-        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_workers, rates)}), flush=True)
+        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_workers, rates, args.serve_coarse)}), flush=True)
         return
     if args.large_timing:
         print(json.dumps(large_timing()), flush=True)
@@ -171,7 +174,7 @@ def main():
         out.update(extra_rooflines())
     if args.serve_requests > 0:
         rates = tuple(float(r) for r in args.serve_rates.split(","))
-        out["serving"] = serving_bench(args.serve_requests, args.serve_workers, rates)
+        out["serving"] = serving_bench(args.serve_requests, args.serve_workers, rates, args.serve_coarse)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, info["iters"])
     print(json.dumps(out), flush=True)
@@ -318,15 +321,17 @@ def _pctl(x, q):
     return float(np.percentile(np.asarray(x), q)) * 1e3
 
 
-def serving_bench(n_req, workers, rates=(0.8,)):
+def serving_bench(n_req, workers, rates=(0.8,), coarse_cells=0):
     """Continuous batching vs the plain per-request float64 solve (FIFO, one at
     a time) on the same Poisson arrival trace of 2-D heat requests with grids
     drawn from {16,32,48,64}^2 x {16,24,32} cells and GP-drawn initial data.
     Every solve: IterGP-CG to 1e-6 or 256 iterations, posterior on 8 time
     slices of the cell-centre grid.  Latency = completion - arrival.  The
     saturated throughput (all requests queued at t = 0) is measured first; each
-    entry of `rates` is an arrival rate as a fraction of it.  The top-level
-    figures are those of the first rate."""
+    entry of `rates` is an arrival rate as a fraction of it.  With coarse_cells
+    the served run is repeated with every solve warm-started on a coarse
+    scheme of at most that many cells.  The top-level figures are those of the
+    first rate."""
     import numpy as np
     import torch
     import paper_2406_05020_amd as G
@@ -351,25 +356,35 @@ def serving_bench(n_req, workers, rates=(0.8,)):
         trace = W.serving_trace(n_req, rate, seed=5)
         reqs = [(arr, W.heat2d_request(ns, nt, seed)) for (arr, ns, nt, seed) in trace]
 
+        def served(coarse_cells):
+            lat = []
+            with G.Server(workers=workers, hbm_budget=96 << 30, prec=G.PREC_FP64, tol=SERVE_TOL,
+                          max_iter=SERVE_ITERS, coarse_cells=coarse_cells) as S:
+                start = time.perf_counter()
+                tickets = []
+                for arr, q in reqs:
+                    now = time.perf_counter() - start
+                    if arr > now:
+                        time.sleep(arr - now)
+                    tickets.append((arr, S.submit(q)))
+                for arr, t in tickets:
+                    _, res, _, _ = S.poll(t, wait=True)
+                    # t_done comes from the library's std::chrono::steady_clock, the
+                    # same CLOCK_MONOTONIC that time.perf_counter reads on Linux
+                    lat.append(res["t_done"] - (start + arr))
+                makespan = time.perf_counter() - start
+                stats = S.stats()
+            return lat, makespan, stats
+
         # continuous batching
-        lat = []
-        with G.Server(workers=workers, hbm_budget=96 << 30, prec=G.PREC_FP64, tol=SERVE_TOL,
-                      max_iter=SERVE_ITERS) as S:
-            start = time.perf_counter()
-            tickets = []
-            for arr, q in reqs:
-                now = time.perf_counter() - start
-                if arr > now:
-                    time.sleep(arr - now)
-                tickets.append((arr, S.submit(q)))
-            for arr, t in tickets:
-                _, res, _, _ = S.poll(t, wait=True)
-                # t_done comes from the library's std::chrono::steady_clock, the
-                # same CLOCK_MONOTONIC that time.perf_counter reads on Linux
-                lat.append(res["t_done"] - (start + arr))
-            makespan = time.perf_counter() - start
-            stats = S.stats()
+        lat, makespan, stats = served(0)
         note(f"rate {frac:g}x: served {n_req / makespan:.2f} solves/s")
+        coarse = {}
+        if coarse_cells > 0:      # the same, each solve warm-started on a coarse scheme
+            lat_c, makespan_c, _ = served(coarse_cells)
+            note(f"rate {frac:g}x: served with the coarse warm start {n_req / makespan_c:.2f} solves/s")
+            coarse = {"coarse_cells": coarse_cells, "coarse_solves_per_s": n_req / makespan_c,
+                      "coarse_p50_ms": _pctl(lat_c, 50), "coarse_p99_ms": _pctl(lat_c, 99)}
 
         # plain float64 per-request solve, FIFO, one at a time, same arrivals
         lat_fifo = []
@@ -397,7 +412,7 @@ def serving_bench(n_req, workers, rates=(0.8,)):
             "solves_per_s": n_req / makespan, "p50_ms": _pctl(lat, 50), "p99_ms": _pctl(lat, 99),
             "fifo_fp64_solves_per_s": n_req / makespan_fifo, "fifo_fp64_p50_ms": _pctl(lat_fifo, 50),
             "fifo_fp64_p99_ms": _pctl(lat_fifo, 99), "peak_in_flight": stats["peak_in_flight"],
-            "peak_reserved_gb": stats["peak_reserved_bytes"] / 2 ** 30,
+            "peak_reserved_gb": stats["peak_reserved_bytes"] / 2 ** 30, **coarse,
         })
     out = {"requests": n_req, "workers": workers, "saturated_solves_per_s": sat, **runs[0],
            "solve": f"fp64 IterGP-CG, tol {SERVE_TOL:g} or {SERVE_ITERS} iterations"}

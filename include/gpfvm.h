@@ -285,6 +285,11 @@ typedef struct {
   double tol;               /* relative residual target of every solve            */
   int max_iter;             /* IterGP iteration cap (also sizes the directions)   */
   int check_every;          /* convergence poll interval                          */
+  int coarse_cells;         /* coarse-scheme warm start of every solve (appendix  */
+                            /* "Multigrid preconditioners"): the nested coarse    */
+                            /* scheme with the most cells <= coarse_cells whose   */
+                            /* factors divide the request's cell counts (0: off;  */
+                            /* needs prec FP64, <= GPFVM_MAX_COARSE)              */
 } gpfvm_server_opts;
 
 typedef struct {

@@ -63,7 +63,7 @@ class HandleInfo(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("workers", C.c_int), ("hbm_budget", C.c_longlong), ("prec", C.c_int), ("tol", C.c_double),
-                ("max_iter", C.c_int), ("check_every", C.c_int)]
+                ("max_iter", C.c_int), ("check_every", C.c_int), ("coarse_cells", C.c_int)]
 
 
 class RequestResult(C.Structure):
@@ -355,8 +355,8 @@ class Server:
     """Thin wrapper over gpfvm_server_*: submit whole IBVP solves, poll results."""
 
     def __init__(self, workers: int = 8, hbm_budget: int = 64 << 30, prec: int = PREC_MIXED, tol: float = 1e-6,
-                 max_iter: int = 1024, check_every: int = 16):
-        o = ServerOpts(workers, hbm_budget, prec, tol, max_iter, check_every)
+                 max_iter: int = 1024, check_every: int = 16, coarse_cells: int = 0):
+        o = ServerOpts(workers, hbm_budget, prec, tol, max_iter, check_every, coarse_cells)
         self.h = C.c_void_p()
         _check(lib().gpfvm_server_create(C.byref(o), C.byref(self.h)))
         self.grids = {}

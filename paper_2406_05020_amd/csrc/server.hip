@@ -112,8 +112,40 @@ struct gpfvm_server {
   int device = 0;
 };
 
-// Conservative device-memory estimate of one request (bytes).
-static size_t estimate_bytes(const gpfvm_ibvp& p, int max_iter, long long M, int prec) {
+// Coarsening factors of the coarse warm start: among the nested schemes whose
+// per-dimension factors divide the cell counts, the one with the most coarse
+// cells that is at most `target` and coarser than the fine scheme (ties: the
+// smaller largest factor).  Returns the number of coarse cells, 0 for none.
+static long long choose_coarsen(const gpfvm_ibvp& p, long long target, int f[3]) {
+  f[0] = f[1] = f[2] = 1;
+  if (target < 1) return 0;
+  std::vector<int> div[3];
+  for (int i = 0; i < p.dim; ++i)
+    for (int k = 1; k <= p.ncell[i]; ++k)
+      if (p.ncell[i] % k == 0) div[i].push_back(k);
+  for (int i = p.dim; i < 3; ++i) div[i].push_back(1);
+  long long best = 0;
+  int best_max = 1 << 30;
+  for (int a : div[0])
+    for (int b : div[1])
+      for (int c : div[2]) {
+        if (a == 1 && b == 1 && c == 1) continue;
+        long long nc = (long long)(p.ncell[0] / a);
+        if (p.dim > 1) nc *= p.ncell[1] / b;
+        if (p.dim > 2) nc *= p.ncell[2] / c;
+        const int mx = std::max(a, std::max(b, c));
+        if (nc <= target && (nc > best || (nc == best && mx < best_max))) {
+          best = nc;
+          best_max = mx;
+          f[0] = a; f[1] = b; f[2] = c;
+        }
+      }
+  if (best == 0) f[0] = f[1] = f[2] = 1;
+  return best;
+}
+
+// Conservative device-memory estimate of one request (bytes); n_coarse: coarse cells of the warm start.
+static size_t estimate_bytes(const gpfvm_ibvp& p, int max_iter, long long M, int prec, long long n_coarse) {
   long long N = 1;
   for (int i = 0; i < p.dim; ++i) N *= p.ncell[i];
   long long nb = 0;
@@ -137,6 +169,10 @@ static size_t estimate_bytes(const gpfvm_ibvp& p, int max_iter, long long M, int
     b += (2.0 * M * B + N * B + 4.0 * nb * B) * d8 + 8.0 * M * d8;
   }
   if (prec == GPFVM_PREC_MIXED) b += 12.0 * N * 4.0;       // float32 operator buffers
+  if (n_coarse > 0) {                                      // C, S C^T, R, C S C^T, L^{-1} (directions: max_iter)
+    b += 3.0 * n_coarse * N * d8 + 3.0 * n_coarse * n_coarse * d8;
+    b += 6.0 * 64.0 * N * d8;                              // the 64-rhs operator buffers
+  }
   return (size_t)(1.25 * b) + (size_t)(32 << 20);
 }
 
@@ -145,9 +181,11 @@ int gpfvm_assemble_cached(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, 
 
 static void run_request(gpfvm_server* S, gpfvm_request* r, hipStream_t st) {
   gpfvm_handle* h = nullptr;
+  int f[3];
+  const long long n_coarse = choose_coarsen(r->ibvp->p, S->opts.coarse_cells, f);
   gpfvm_assemble_opts ao;
   gpfvm_default_assemble_opts(&ao);
-  ao.max_iter = S->opts.max_iter;
+  ao.max_iter = S->opts.max_iter + (int)n_coarse;
   int rc = gpfvm_assemble_cached(&r->ibvp->p, &ao, st, &S->cache, &h);
   if (rc) {
     r->rc = rc;
@@ -160,6 +198,8 @@ static void run_request(gpfvm_server* S, gpfvm_request* r, hipStream_t st) {
   so.tol = S->opts.tol;
   so.max_iter = S->opts.max_iter;
   so.check_every = S->opts.check_every;
+  if (n_coarse > 0)
+    for (int i = 0; i < 3; ++i) so.coarsen[i] = f[i];
   rc = gpfvm_solve(h, &so, &r->info, st);
   if (rc && rc != GPFVM_E_NOCONV) {
     r->rc = rc;
@@ -248,6 +288,7 @@ extern "C" void gpfvm_default_server_opts(gpfvm_server_opts* o) {
   o->tol = 1e-6;
   o->max_iter = 1024;
   o->check_every = 16;
+  o->coarse_cells = 0;
 }
 
 extern "C" int gpfvm_server_create(const gpfvm_server_opts* o, gpfvm_server** out) {
@@ -257,7 +298,8 @@ extern "C" int gpfvm_server_create(const gpfvm_server_opts* o, gpfvm_server** ou
   gpfvm_default_server_opts(&def);
   if (!o) o = &def;
   if (o->workers < 1 || o->workers > 16 || o->hbm_budget < (1LL << 26) || o->max_iter < 1 || !(o->tol >= 0) ||
-      o->check_every < 1 || (o->prec != GPFVM_PREC_FP64 && o->prec != GPFVM_PREC_MIXED))
+      o->check_every < 1 || (o->prec != GPFVM_PREC_FP64 && o->prec != GPFVM_PREC_MIXED) || o->coarse_cells < 0 ||
+      o->coarse_cells > GPFVM_MAX_COARSE || (o->coarse_cells > 0 && o->prec != GPFVM_PREC_FP64))
     return GPFVM_E_INVALID;
   auto S = std::make_unique<gpfvm_server>();
   S->opts = *o;
@@ -292,7 +334,11 @@ extern "C" int gpfvm_server_submit(gpfvm_server* S, const gpfvm_ibvp* p, int dim
     r->M *= n[i];
   }
   r->ibvp = std::make_unique<IBVPCopy>(*p);
-  r->est_bytes = estimate_bytes(*p, S->opts.max_iter, r->M, S->opts.prec);
+  {
+    int f[3];
+    const long long n_coarse = choose_coarsen(r->ibvp->p, S->opts.coarse_cells, f);
+    r->est_bytes = estimate_bytes(*p, S->opts.max_iter + (int)n_coarse, r->M, S->opts.prec, n_coarse);
+  }
   r->t_submit = now_s();
   {
     std::lock_guard<std::mutex> lk(S->mu);

@@ -83,3 +83,46 @@ def test_served_request_equals_direct_solve(G):
         assert np.array_equal(mean.cpu().numpy(), ms) and np.array_equal(var.cpu().numpy(), vs)
     finally:
         G.destroy(h)
+
+
+def _coarsen_rule(ncell, target):
+    """The server's choice of coarsening factors: the most coarse cells <= target
+    among nested schemes coarser than the fine one (ties: smaller largest
+    factor, then the first in lexicographic order)."""
+    import itertools
+    divs = [[k for k in range(1, n + 1) if n % k == 0] for n in ncell]
+    best, best_f, best_max = 0, (1,) * len(ncell), None
+    for f in itertools.product(*divs):
+        if all(x == 1 for x in f):
+            continue
+        nc = int(np.prod([n // x for n, x in zip(ncell, f)]))
+        mx = max(f)
+        if nc <= target and (nc > best or (nc == best and mx < best_max)):
+            best, best_f, best_max = nc, f, mx
+    return best, best_f
+
+
+def test_served_coarse_warm_start_equals_direct_solve(G):
+    p = W.heat2d_request(32, 24, seed=4343)
+    target = 64
+    nc, f = _coarsen_rule(p.ncell, target)
+    assert 1 <= nc <= target
+    with G.Server(workers=2, hbm_budget=32 << 30, prec=G.PREC_FP64, tol=1e-6, max_iter=MAX_ITER,
+                  coarse_cells=target) as S:
+        done, rs, ms, vs = S.poll(S.submit(p), wait=True)
+    assert done and rs["rc"] in (G.OK, G.E_NOCONV) and rs["coarse"] == nc, rs
+    h = G.assemble(p, max_iter=MAX_ITER + nc)
+    try:
+        info = G.solve(h, tol=1e-6, max_iter=MAX_ITER, check_every=16, coarsen=f)
+        M = len(ms)
+        mean = torch.empty(M, dtype=torch.float64, device="cuda:0")
+        var = torch.empty(M, dtype=torch.float64, device="cuda:0")
+        G.posterior(h, p.grid, mean, var)
+        torch.cuda.synchronize()
+        assert info["iters"] == rs["iters"] and info["coarse"] == nc
+        assert np.array_equal(mean.cpu().numpy(), ms) and np.array_equal(var.cpu().numpy(), vs)
+    finally:
+        G.destroy(h)
+    # the coarse warm start is float64 only
+    with pytest.raises(G.GpfvmError):
+        G.Server(workers=1, prec=G.PREC_MIXED, coarse_cells=target)
