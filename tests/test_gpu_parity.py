@@ -223,6 +223,29 @@ def test_volume_matvec_matches_oracle(G, name, nrhs):
         G.destroy(h)
 
 
+# Many right-hand sides on ragged cell counts: both mode-product stages run on
+# the 64x64 kernel (>= 256 tiles) with partial edge tiles and odd numbers of
+# 16-deep K chunks per segment (K = 70: 5 chunks; K = 100 per term: 7).
+@pytest.mark.parametrize("nt,nx,nrhs", [(100, 70, 64), (100, 70, 65), (36, 50, 96)])
+def test_batched_volume_matvec_on_ragged_tiles(G, nt, nx, nrhs):
+    p = W.advdiff_c2(nt=nt, nx=nx, n_ic=40)
+    o = O.Oracle(p)
+    s2 = o.noise_pde()
+    rng = np.random.default_rng(nt + nx + nrhs)
+    X = rng.standard_normal((nrhs, p.n_pde))
+    h = G.assemble(p, max_iter=8)
+    try:
+        x = dev(X.ravel())
+        y = torch.empty_like(x)
+        G.volume_matvec(h, x, y, nrhs=nrhs)
+        Y = host(y).reshape(nrhs, -1)
+    finally:
+        G.destroy(h)
+    for r in range(nrhs):
+        ref = o.volume_matvec(X[r]) + s2 * X[r]
+        assert relerr(Y[r], ref) <= 1e-11, (r, relerr(Y[r], ref))
+
+
 @pytest.mark.parametrize("name", list(RAGGED))
 def test_schur_matvec_matches_oracle(G, name):
     """Volume-system operator S = G_pp + s2 I - G_pb G_bb^{-1} G_bp: one
