@@ -223,6 +223,8 @@ class Oracle:
     def point_gram(self) -> np.ndarray:
         """L_b k L_b' + Sigma_b (dense)."""
         gs = self.p.groups
+        if not gs:                                   # no IC/BC observations: an empty block
+            return np.zeros((0, 0))
         blocks = []
         for g1 in gs:
             row = []
@@ -246,7 +248,7 @@ class Oracle:
 
     def cross_gram(self) -> np.ndarray:
         """L_b k L_V' (n_b x N), dense."""
-        rows = []
+        rows = [np.zeros((0, self.N))]
         for g in self.p.groups:
             B = np.zeros((g.size, self.N))
             for t in self.p.terms:
@@ -256,7 +258,7 @@ class Oracle:
 
     def cross_matvec(self, v: np.ndarray) -> np.ndarray:
         """(L_b k L_V') v, matrix-free per tensor-grid group."""
-        out = []
+        out = [np.zeros(0)]
         for g in self.p.groups:
             acc = np.zeros(g.size)
             for t in self.p.terms:
@@ -291,7 +293,7 @@ class Oracle:
     def Lk_points(self, X: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
         """(L_b k(x), L_V k(x)) for rows x of X: shapes (n_b, M) and (N, M)."""
         M = X.shape[0]
-        kb = []
+        kb = [np.zeros((0, M))]
         for g in self.p.groups:
             mats = [point_point(g.deriv[i], 0, g.axes[i], X[:, i], self.ell[i], self.kq[i]) for i in range(self.d)]
             # group tensor grid x each evaluation point: product over dims
@@ -339,24 +341,33 @@ class SchurSystem:
     def __init__(self, orc: Oracle):
         self.o = orc
         self.Gbb = orc.point_gram()
-        self.cf = sla.cho_factor(self.Gbb, lower=True)
+        # no IC/BC observations: nothing to condition on first, S is the volume Gram
+        self.cf = sla.cho_factor(self.Gbb, lower=True) if orc.p.n_b > 0 else None
         self.sig = orc.noise_pde()
         yobs = orc.p.y_obs()
         self.yb = yobs[:orc.p.n_b]
         self.yp = yobs[orc.p.n_b:]
-        self.ab0 = sla.cho_solve(self.cf, self.yb)          # G_bb^{-1} y_b
+        self.ab0 = self.bb_solve(self.yb)                     # G_bb^{-1} y_b
         self.b = self.yp - orc.cross_rmatvec(self.ab0)        # y_p - G_pb G_bb^{-1} y_b
         self.nmv = 0
+
+    def bb_solve(self, B: np.ndarray) -> np.ndarray:
+        """G_bb^{-1} B (LAPACK Cholesky); B with n_b rows."""
+        return sla.cho_solve(self.cf, B) if self.cf is not None else np.zeros(B.shape)
+
+    def bb_lsolve(self, B: np.ndarray) -> np.ndarray:
+        """L^{-1} B with G_bb = L L^T."""
+        return sla.solve_triangular(self.cf[0], B, lower=True) if self.cf is not None else np.zeros(B.shape)
 
     def matvec(self, v: np.ndarray) -> np.ndarray:
         self.nmv += 1
         o = self.o
-        w = sla.cho_solve(self.cf, o.cross_matvec(v))
+        w = self.bb_solve(o.cross_matvec(v))
         return o.volume_matvec(v) + self.sig * v - o.cross_rmatvec(w)
 
     def full_weights(self, vp: np.ndarray) -> np.ndarray:
         """Representer weights of the full system from the volume weights."""
-        ab = sla.cho_solve(self.cf, self.yb - self.o.cross_matvec(vp))
+        ab = self.bb_solve(self.yb - self.o.cross_matvec(vp))
         return np.concatenate([ab, vp])
 
 
@@ -491,7 +502,7 @@ def schur_cross(S: "SchurSystem", X: np.ndarray) -> np.ndarray:
     kb, kp = o.Lk_points(X)
     if kb.size == 0:
         return kp
-    return kp - np.stack([o.cross_rmatvec(c) for c in sla.cho_solve(S.cf, kb).T], axis=1)
+    return kp - np.stack([o.cross_rmatvec(c) for c in S.bb_solve(kb).T], axis=1)
 
 
 def itergp_targeted(S, vp: np.ndarray, D: np.ndarray, eta: np.ndarray, KS: np.ndarray, betas: np.ndarray,
@@ -545,10 +556,10 @@ def two_stage_posterior(S: SchurSystem, vp: np.ndarray, X: np.ndarray,
     mean = kb.T @ alpha[:o.p.n_b] + kp.T @ alpha[o.p.n_b:]
     if D is None:
         return mean, None
-    Wb = sla.solve_triangular(S.cf[0], kb, lower=True)
+    Wb = S.bb_lsolve(kb)
     var_b = o.sf2 - np.einsum("ij,ij->j", Wb, Wb)
     # cross-covariance of the conditioned prior between volumes and x
-    w = kp - np.stack([o.cross_rmatvec(c) for c in sla.cho_solve(S.cf, kb).T], axis=1)
+    w = kp - np.stack([o.cross_rmatvec(c) for c in S.bb_solve(kb).T], axis=1)
     proj = D.T @ w                                   # k x M
     var = var_b - np.einsum("ij,ij->j", proj, proj / eta[:, None])
     return mean, var
