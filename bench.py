@@ -77,8 +77,8 @@ def canonical_pp_flops(p):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the single-GPU path is the measured unit).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs a solve "
+              "on a single device; sharding over several is a design note only).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

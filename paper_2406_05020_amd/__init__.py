@@ -125,7 +125,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"gpfvm HIP library not built: {LIB_PATH} is missing "
-                               "(run __graft_entry__.build() or python paper_2406_05020_amd/build.py)")
+                               "(build it with: python paper_2406_05020_amd/build.py)")
         L = C.CDLL(LIB_PATH)
         for name, (args, res) in SYMBOLS.items():
             f = getattr(L, name)
