@@ -170,15 +170,44 @@ __global__ void k_sub_sq_acc(i64 M, int nr, const double* __restrict__ P, const 
   acc[x] += s;
 }
 
-__global__ void k_colsq(i64 rows, i64 cols, const double* __restrict__ T, double* __restrict__ acc) {
+// Column sums of squares of a rows x cols row-major block, added to acc.  The rows are split
+// into gridDim.y chunks; a workgroup's four wavefronts take every fourth row of its chunk for
+// 64 columns and meet in LDS (fixed order); k_colsq_finish adds the chunk partials in order.
+__global__ __launch_bounds__(256) void k_colsq_part(i64 rows, i64 cols, const double* __restrict__ T,
+                                                    double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const i64 c = (i64)blockIdx.x * 64 + lane;
+  const i64 R = gridDim.y, ch = blockIdx.y;
+  const i64 L = (rows + R - 1) / R, r0 = ch * L, r1 = min(rows, r0 + L);
+  double s = 0.0;
+  if (c < cols) {
+#pragma unroll 8
+    for (i64 r = r0 + wave; r < r1; r += 4) {
+      const double t = T[r * cols + c];
+      s = fma(t, t, s);
+    }
+  }
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && c < cols) part[ch * cols + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+__global__ void k_colsq_finish(i64 cols, int R, const double* __restrict__ part, double* __restrict__ acc) {
   const i64 c = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
-  double s = 0;
-  for (i64 r = 0; r < rows; ++r) {
-    const double t = T[r * cols + c];
-    s += t * t;
-  }
+  double s = 0.0;
+  for (int ch = 0; ch < R; ++ch) s += part[(i64)ch * cols + c];
   acc[c] += s;
+}
+
+constexpr int COLSQ_MAX_CHUNKS = 64;
+
+// Row chunks for k_colsq_part: about 1024 workgroups in all
+static int colsq_chunks(i64 rows, i64 cols) {
+  const i64 colblocks = (cols + 63) / 64;
+  const i64 want = (1024 + colblocks - 1) / colblocks;
+  return (int)std::max<i64>(1, std::min<i64>({(i64)COLSQ_MAX_CHUNKS, want, rows}));
 }
 
 __global__ void k_var_final(i64 M, double sf2, const double* __restrict__ red, double* __restrict__ var) {
@@ -1306,7 +1335,8 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
     double* KB = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
     double* TT = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
     double* RR = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
-    if (!KB || !TT || !RR) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+    double* CP = (double*)tmp.alloc((size_t)COLSQ_MAX_CHUNKS * chunk * sizeof(double));
+    if (!KB || !TT || !RR || !CP) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
     for (i64 x0 = 0; x0 < M; x0 += chunk) {
       const i64 nx = std::min(chunk, M - x0);
       hipLaunchKernelGGL(k_point_grid, dim3(nblk((i64)h->nb * nx)), dim3(256), 0, s, (const PGMeta*)dpg, h->nb, x0, nx,
@@ -1322,7 +1352,10 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
       st[2].descs.push_back(desc1(TT, nx, h->Linv, h->nb, 1, RR, nx, 1, h->nb, (int)nx, h->nb, 1.0, 1.0, 1));
       if (upload_stages(st, tmp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: upload failed");
       if (run_stages(st, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: gemm failed");
-      hipLaunchKernelGGL(k_colsq, dim3(nblk(nx)), dim3(256), 0, s, (i64)h->nb, nx, (const double*)TT, red + x0);
+      const int R = colsq_chunks(h->nb, nx);
+      hipLaunchKernelGGL(k_colsq_part, dim3((unsigned)((nx + 63) / 64), (unsigned)R), dim3(256), 0, s, (i64)h->nb, nx,
+                         (const double*)TT, CP);
+      hipLaunchKernelGGL(k_colsq_finish, dim3(nblk(nx)), dim3(256), 0, s, nx, R, (const double*)CP, red + x0);
     }
   }
   const int K = h->iters;
