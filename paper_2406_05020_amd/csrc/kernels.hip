@@ -453,6 +453,17 @@ __global__ __launch_bounds__(512) void k_cols_sum(int nr, i64 N, const double* _
 
 constexpr int GEMM_KDEPTH1 = 1;
 
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup w runs on XCD
+// w % 8), and each XCD has its own L2.  Give XCD x the contiguous tile range
+// [x q + min(x, r), ...) of n = 8 q + r tiles, so that tiles sharing an operand
+// row block or a batch slab are fetched into one L2 (a bijection of [0, n)).
+constexpr int GEMM_NXCD = 8;
+
+__device__ __forceinline__ i64 xcd_tile(i64 w, i64 n) {
+  const i64 q = n / GEMM_NXCD, r = n % GEMM_NXCD, x = w % GEMM_NXCD;
+  return x * q + (x < r ? x : r) + w / GEMM_NXCD;
+}
+
 template <typename T, int BM, int BN, int KS, bool SLOT1, bool RIDE>
 __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDesc* __restrict__ descs, int ndesc,
                                                                     i64 ntiles, Rider rider) {
@@ -464,8 +475,9 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
   static_assert(EA * NT == BM * LKC && EB * NT == LKC * BN, "tile shape");
   constexpr int NS = SLOT1 ? 2 : 1;
   // LDS tiles are stored k-contiguous, A as [m][k] and B as [n][k], with a row stride of LKC + 2
-  // elements: an MFMA operand read (16 rows x 4 consecutive k per wavefront) then touches 16 row
-  // starts 4 banks apart (f64), so each half-wavefront reads 64 distinct banks.
+  // elements.  An operand whose global layout runs along m (or n) is stored one row per lane and
+  // meets bank conflicts at this stride; an odd stride removes them (measured: zero conflict
+  // cycles) but is no faster, as those stores are off the critical path of the chunk loop.
   constexpr int LS = LKC + 2;
   constexpr int SZA = 2 * BM * LS, SZB = 2 * BN * LS;
   static_assert(NS * (KS - 1) * NBLK * 256 <= SZA + SZB, "reduction space");
@@ -473,17 +485,18 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
   auto As = [&](int buf, int k, int m) -> T& { return sm[(buf * BM + m) * LS + k]; };
   auto Bs = [&](int buf, int k, int n) -> T& { return sm[SZA + (buf * BN + n) * LS + k]; };
 
-  const i64 tile = blockIdx.x;
   if constexpr (RIDE) {
-    if (tile >= ntiles) {                          // a workgroup of the riding streaming product
+    const i64 w = blockIdx.x;
+    if (w >= ntiles) {                             // a workgroup of the riding streaming product
       __shared__ double rred[64 * CS_PARTS];
       if (rider.kind == RIDE_ROWS)
-        rows_dot_block<NT>(rider.N, rider.M, rider.v, rider.eta, rider.out, (int)(tile - ntiles), rred);
+        rows_dot_block<NT>(rider.N, rider.M, rider.v, rider.eta, rider.out, (int)(w - ntiles), rred);
       else
-        cols_sum_block<NT>(rider.nr, rider.N, rider.M, rider.v, rider.out, tile - ntiles, rred);
+        cols_sum_block<NT>(rider.nr, rider.N, rider.M, rider.v, rider.out, w - ntiles, rred);
       return;
     }
   }
+  const i64 tile = xcd_tile(blockIdx.x, ntiles);
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
