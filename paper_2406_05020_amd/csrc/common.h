@@ -66,7 +66,33 @@ enum Elt { F64 = 0, F32 = 1 };
 // outputs.
 //   RIDE_ROWS: out[j] = M[j,:] . v (divided by eta[j] when eta is set), j < nr
 //   RIDE_COLS: out[c] = sum_j M[j][c] v[j], c < N (v: nr coefficients)
-enum RiderKind { RIDE_NONE = 0, RIDE_ROWS = 1, RIDE_COLS = 2 };
+//   RIDE_QFV:  the nr work units of the factored point correction (QFactor)
+enum RiderKind { RIDE_NONE = 0, RIDE_ROWS = 1, RIDE_COLS = 2, RIDE_QFV = 3 };
+
+// Factored point correction for a 2-D volume tensor (n0 x n1 cells, dim 1
+// fastest) whose point groups are each pinned in one dimension.  With
+// G_bp = sum_r Gf_r (x)_{p_r} q_r (piece r = one group and one PDE term; q_r
+// the group's factor over the cells of its pinned dimension p_r, Gf_r its
+// n_b x n_{f_r} factor over the free one), Q = L^{-1} G_bp is
+// sum_r M_r (x)_{p_r} q_r with M_r = L^{-1} Gf_r, and
+//   Q^T Q x = sum_r q_r (x)_{p_r} (P w)_r,   w_r = x contracted with q_r over p_r,
+// where P = M_cat^T M_cat (W x W) and M_cat = [M_0 | M_1 | ...] (n_b x W).
+// Pieces pinned in dimension 0 come first.  v = P w is formed as nunit
+// partial sums stored piece-major (vpart[nunit off_r + u nf_r + j]), so that
+// sum_r q_r (x) v_r is two GEMM segments of the volume operator's last stage:
+// [q_r columns, each repeated nunit times] x vpart (pinned dimension 0) and
+// vpart^T x [q_r rows, repeated] (pinned dimension 1).
+constexpr int QF_MAXR = 16, QF_MAXW = 2048;
+constexpr int QF_UW = 16;          // free indices per work unit of v = P w
+struct QFactor {
+  int R = 0, W = 0, n0 = 0, n1 = 0;
+  int nunit = 0;                   // work units of v = P w: QF_UW free indices of one piece each
+  int w0 = 0;                      // free indices of the pieces pinned in dimension 0 (R0 n1)
+  int p[QF_MAXR];                  // pinned dimension of piece r (0 or 1)
+  int off[QF_MAXR];                // first index of piece r in the concatenated free index
+  const double* q[QF_MAXR];        // n_{p_r} values
+  const double* P = nullptr;       // W x W, row-major
+};
 struct Rider {
   int kind = RIDE_NONE;
   int nr = 0;
@@ -75,6 +101,7 @@ struct Rider {
   const double* v = nullptr;
   const double* eta = nullptr;
   double* out = nullptr;
+  const QFactor* qf = nullptr; // RIDE_QFV: the factored correction (device)
 };
 
 struct Stage {
@@ -234,6 +261,8 @@ int rows_dot_chunks(int nr, i64 N);
 hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, double* part, hipStream_t s,
                            const double* xm = nullptr);
 hipError_t launch_rows_dot_full(int nr, i64 N, const double* M, const double* x, double* out, hipStream_t s);
+// the nunit partial sums of v = P w(x) of the factored point correction, on their own
+hipError_t launch_qf_v(const QFactor* F, int nunit, const double* x, double* vpart, hipStream_t s);
 //   With M2 and dot_part: also dot_part[g] = workgroup g's share of sum_c out[c] * out3[c]
 //   (ceil(N/64) values; their fixed-order sum is the dot product).
 //   With base2m: out3[c] = (base2[c] - base2m[c]) - sum_j M2[j][c] u_j.
@@ -278,6 +307,11 @@ struct gpfvm_sop {
   gpfvm::Plan pp_split;
   double* csub = nullptr;
   bool split = false;
+  // factored form of the correction (2-D, every point group pinned in one dimension): the
+  // partial sums of v = P w ride on the first stage of pp_split, and sum_r q_r (x) v_r is
+  // subtracted by two extra segments of its last stage, so pp_split gives Y = S X; no resident Q
+  bool qf = false;
+  double* qf_v = nullptr;          // nunit x W partial sums of v, piece-major
 };
 
 struct gpfvm_handle {
@@ -313,6 +347,11 @@ struct gpfvm_handle {
   double* Lt = nullptr;            // row-major copies of L^T and L^{-T}
   double* Linvt = nullptr;
   double* Qc = nullptr;            // n_b x N: L^{-1} G_bp (built on first use when qform_ok)
+  gpfvm::QFactor* qf = nullptr;    // device: the factored correction (built on first use), or null
+  int qf_nunit = 0;                // work units (workgroups) of v = P w
+  int qf_w0 = 0, qf_k0 = 0, qf_k1 = 0;   // free indices of the dim-0 pieces; segment depths
+  double* qf_aq = nullptr;         // n0 x k0: q_r (pinned dim 0) as columns, each nunit times
+  double* qf_bq = nullptr;         // k1 x n1: q_r (pinned dim 1) as rows, each nunit times
   bool process_cache = false;      // arena blocks come from the per-process cache
   float* Linv_f = nullptr;
   gpfvm::GramMeta* meta = nullptr;   // device

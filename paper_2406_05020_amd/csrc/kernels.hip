@@ -451,6 +451,112 @@ __global__ __launch_bounds__(512) void k_cols_sum(int nr, i64 N, const double* _
   cols_sum_block<512>(nr, N, M, v, out, blockIdx.x, red);
 }
 
+// ---------------------------------------------------------------------------
+// Factored point correction (QFactor), one workgroup of NT threads each.
+//
+// qf_v_block: work unit u = QF_UW consecutive free indices j of one piece r.
+// It forms w_r[j] (x contracted with q_r over the pinned dimension) for those
+// j: pinned dimension 0 with the unit's columns across QF_UW lanes and the
+// rows split into NT / QF_UW interleaved phases (their partial sums then added
+// in order), pinned dimension 1 with a wavefront per row.  Then it writes the
+// unit's share of v = P w for every a < W, sum_k P[b_k][a] w[b_k] (P is
+// symmetric, so rows of P are read contiguously), stored piece-major: output
+// a = off_r + j of piece r goes to vpart[nunit off_r + u nf_r + j].  Narrow
+// units keep every phase to about one round of loads.  wl: NT + QF_UW doubles.
+// ---------------------------------------------------------------------------
+constexpr int QF_U = 4;
+
+template <int NT>
+__device__ void qf_v_block(const QFactor& F, const double* __restrict__ x, double* __restrict__ vpart, int u,
+                           double* wl) {
+  constexpr int NW = NT / 64, NPH = NT / QF_UW;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int n0 = F.n0, n1 = F.n1, W = F.W;
+  int r = 0, j0 = 0;
+  for (int uu = u; r < F.R; ++r) {
+    const int cnt = ((F.p[r] == 0 ? n1 : n0) + QF_UW - 1) / QF_UW;
+    if (uu < cnt) { j0 = uu * QF_UW; break; }
+    uu -= cnt;
+  }
+  const int p = F.p[r], nf = p == 0 ? n1 : n0;
+  const int jn = min(QF_UW, nf - j0);
+  const double* __restrict__ q = F.q[r];
+  const double* __restrict__ P = F.P;
+  const int b0 = F.off[r] + j0;
+  double* part = wl;
+  double* wc = wl + NT;
+  // the first QF_PF of this thread's P entries for output a = tid, loaded before w is
+  // formed (more would raise the kernel's register count above that of its GEMM tiles)
+  constexpr int QF_PF = 8;
+  double pr[QF_PF];
+#pragma unroll
+  for (int k = 0; k < QF_PF; ++k) pr[k] = (tid < W && k < jn) ? P[(i64)(b0 + k) * W + tid] : 0.0;
+  if (p == 0) {
+    const int k = tid % QF_UW, ph = tid / QF_UW;
+    double acc = 0.0;
+    if (k < jn) {
+      const int c = j0 + k;
+      for (int i0 = ph; i0 < n0; i0 += NPH * QF_U) {
+        double xv[QF_U], qv[QF_U];
+#pragma unroll
+        for (int m = 0; m < QF_U; ++m) {
+          const int i = i0 + m * NPH;
+          xv[m] = i < n0 ? x[(i64)i * n1 + c] : 0.0;
+          qv[m] = i < n0 ? q[i] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < QF_U; ++m) acc = fma(qv[m], xv[m], acc);
+      }
+    }
+    part[tid] = acc;
+    __syncthreads();
+    if (tid < QF_UW) {
+      double t = 0.0;
+      for (int h = 0; h < NPH; ++h) t += part[h * QF_UW + tid];
+      wc[tid] = t;
+    }
+  } else {
+    for (int k = wave; k < jn; k += NW) {
+      const int i = j0 + k;
+      double t = 0.0;
+      for (int c = lane; c < n1; c += 64) t = fma(q[c], x[(i64)i * n1 + c], t);
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_down(t, o, 64);
+      if (lane == 0) wc[k] = t;
+    }
+  }
+  __syncthreads();
+  for (int a = tid; a < W; a += NT) {
+    double t = 0.0;
+    if (a == tid) {
+#pragma unroll
+      for (int k = 0; k < QF_PF; ++k)
+        if (k < jn) t = fma(pr[k], wc[k], t);
+      for (int k = QF_PF; k < jn; ++k) t = fma(P[(i64)(b0 + k) * W + a], wc[k], t);
+    } else {
+#pragma unroll 16
+      for (int k = 0; k < jn; ++k) t = fma(P[(i64)(b0 + k) * W + a], wc[k], t);
+    }
+    // pieces pinned in dimension 0 hold [0, w0) in blocks of n1, the others blocks of n0
+    const int nfa = a < F.w0 ? n1 : n0;
+    const int j = a < F.w0 ? a % n1 : (a - F.w0) % n0;
+    vpart[(i64)F.nunit * (a - j) + (i64)u * nfa + j] = t;
+  }
+}
+
+constexpr int QF_THREADS = 512;
+
+__global__ __launch_bounds__(QF_THREADS) void k_qf_v(const QFactor* __restrict__ F, const double* __restrict__ x,
+                                                     double* __restrict__ vpart) {
+  __shared__ double wl[QF_THREADS + QF_UW];
+  qf_v_block<QF_THREADS>(*F, x, vpart, blockIdx.x, wl);
+}
+
+hipError_t launch_qf_v(const QFactor* F, int nunit, const double* x, double* vpart, hipStream_t s) {
+  if (nunit < 1) return hipErrorInvalidValue;
+  k_qf_v<<<dim3((unsigned)nunit), dim3(QF_THREADS), 0, s>>>(F, x, vpart);
+  return hipGetLastError();
+}
+
 constexpr int GEMM_KDEPTH1 = 1;
 
 // Workgroups are dispatched to the 8 XCDs in turn (workgroup w runs on XCD
@@ -487,12 +593,15 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
 
   if constexpr (RIDE) {
     const i64 w = blockIdx.x;
-    if (w >= ntiles) {                             // a workgroup of the riding streaming product
+    if (w >= ntiles) {                             // a workgroup of the riding product
       __shared__ double rred[64 * CS_PARTS];
+      static_assert(SZA + SZB >= NT + QF_UW, "LDS for the factored correction");
       if (rider.kind == RIDE_ROWS)
         rows_dot_block<NT>(rider.N, rider.M, rider.v, rider.eta, rider.out, (int)(w - ntiles), rred);
-      else
+      else if (rider.kind == RIDE_COLS)
         cols_sum_block<NT>(rider.nr, rider.N, rider.M, rider.v, rider.out, w - ntiles, rred);
+      else
+        qf_v_block<NT>(*rider.qf, rider.v, rider.out, (int)(w - ntiles), reinterpret_cast<double*>(sm));
       return;
     }
   }
@@ -769,7 +878,7 @@ static void launch_lds(const Stage& st, int nd, hipStream_t s) {
   const dim3 block(4 * BM * BM / 16 * KS);
   if constexpr (std::is_same<T, double>::value) {
     if (st.rider.kind != RIDE_NONE) {              // the stage carries a streaming product
-      const i64 extra = st.rider.kind == RIDE_ROWS ? st.rider.nr : (st.rider.N + 63) / 64;
+      const i64 extra = st.rider.kind == RIDE_COLS ? (st.rider.N + 63) / 64 : st.rider.nr;
       const dim3 grid((unsigned)(st.tiles + extra));
       if (st.slot1)
         k_gemm_lds<T, BM, BM, KS, true, true><<<grid, block, 0, s>>>(st.d_descs, nd, st.tiles, st.rider);
@@ -792,6 +901,8 @@ hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
     if (st.rider.kind == RIDE_ROWS) {
       if (st.rider.eta) return hipErrorInvalidValue;  // the stand-alone row dots carry no division
       e = launch_rows_dot_full(st.rider.nr, st.rider.N, st.rider.M, st.rider.v, st.rider.out, s);
+    } else if (st.rider.kind == RIDE_QFV) {
+      e = launch_qf_v(st.rider.qf, st.rider.nr, st.rider.v, st.rider.out, s);
     } else {
       k_cols_sum<<<dim3((unsigned)((st.rider.N + 63) / 64)), dim3(512), 0, s>>>(st.rider.nr, st.rider.N, st.rider.M,
                                                                                 st.rider.v, st.rider.out);

@@ -355,6 +355,129 @@ static int build_qc(gpfvm_handle* h, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Factored point correction (2-D, every point group pinned in one dimension,
+// no per-cell coefficients).  Piece r = (group g, PDE term t): the group's
+// cross-covariance with the volumes is sf2 coef_t Gf (x) q over its free and
+// pinned dimensions (the point-cell factors of Sec. 3.2), so G_bp =
+// sum_r Gf_r (x)_{p_r} q_r.  Then M_cat = L^{-1} [Gf_0 | Gf_1 | ...] (the
+// explicit inverse with one residual correction, as for Q) and P = M_cat^T
+// M_cat give Q^T Q x = sum_r q_r (x) (P w)_r with n_b W + W^2 work in place
+// of the n_b N of a resident Q.
+// ---------------------------------------------------------------------------
+static bool qfact_ok(const gpfvm_handle* h, int* W_out, int* R_out) {
+  if (h->d != 2 || h->nb <= 0) return false;
+  for (const auto& t : h->pterms)
+    if (t.cellwise) return false;
+  int W = 0, R = 0;
+  for (const auto& G : h->groups) {
+    if (G.n[0] != 1 && G.n[1] != 1) return false;
+    const int f = G.n[0] == 1 ? 1 : 0;
+    for (size_t t = 0; t < h->pterms.size(); ++t) {
+      W += h->nc[f];
+      ++R;
+    }
+  }
+  if (R < 1 || R > QF_MAXR || W > QF_MAXW) return false;
+  *W_out = W;
+  *R_out = R;
+  return true;
+}
+
+static int build_qf(gpfvm_handle* h, hipStream_t s) {
+  if (h->qf) return GPFVM_OK;
+  int W = 0, R = 0;
+  if (!qfact_ok(h, &W, &R)) { h->err = "factored point correction: not applicable"; return GPFVM_E_INVALID; }
+  const int nb = h->nb, n0 = h->nc[0], n1 = h->nc[1];
+  QFactor F;
+  F.R = R; F.W = W; F.n0 = n0; F.n1 = n1;
+  F.nunit = 0;
+  std::vector<double> gf((size_t)nb * W, 0.0), fac;
+  std::vector<std::vector<double>> qh;                  // host copies of the q_r
+  HIPCHK(h, hipStreamSynchronize(s));                    // the point-cell factors are complete
+  int r = 0, off = 0;
+  for (int pass = 0; pass < 2; ++pass)                   // pieces pinned in dimension 0 first
+    for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+      const Group& G = h->groups[gi];
+      const int p = G.n[0] == 1 ? 0 : 1, f = 1 - p;
+      if (p != pass) continue;
+      const int nf = G.n[f], cf = h->nc[f];
+      for (size_t ti = 0; ti < h->pterms.size(); ++ti, ++r) {
+        F.p[r] = p;
+        F.off[r] = off;
+        F.q[r] = h->Qfac[gi][ti][p].d;                   // 1 x nc[p]
+        F.nunit += (cf + QF_UW - 1) / QF_UW;
+        qh.emplace_back((size_t)h->nc[p]);
+        HIPCHK(h, hipMemcpy(qh.back().data(), F.q[r], qh.back().size() * sizeof(double), hipMemcpyDeviceToHost));
+        fac.resize((size_t)nf * cf);
+        HIPCHK(h, hipMemcpy(fac.data(), h->Qfac[gi][ti][f].d, fac.size() * sizeof(double), hipMemcpyDeviceToHost));
+        const double a = h->sf2 * h->pterms[ti].coef;
+        for (int k = 0; k < nf; ++k)
+          for (int c = 0; c < cf; ++c) gf[(size_t)(G.offset + k) * W + off + c] = a * fac[(size_t)k * cf + c];
+        off += cf;
+      }
+    }
+  // the constant operands of the last-stage segments
+  const int nu = F.nunit;
+  int R0 = 0;
+  while (R0 < R && F.p[R0] == 0) ++R0;
+  const int K0 = R0 * nu, K1 = (R - R0) * nu;
+  F.w0 = R0 * n1;
+  std::vector<double> aq((size_t)n0 * std::max(K0, 1), 0.0), bq((size_t)std::max(K1, 1) * n1, 0.0);
+  for (int rr = 0; rr < R0; ++rr)
+    for (int u = 0; u < nu; ++u)
+      for (int i = 0; i < n0; ++i) aq[(size_t)i * K0 + rr * nu + u] = qh[rr][i];
+  for (int rr = R0; rr < R; ++rr)
+    for (int u = 0; u < nu; ++u)
+      for (int c = 0; c < n1; ++c) bq[(size_t)((rr - R0) * nu + u) * n1 + c] = qh[rr][c];
+  double* P = (double*)h->arena.alloc((size_t)W * W * sizeof(double));
+  QFactor* Fd = (QFactor*)h->arena.alloc(sizeof(QFactor));
+  double* Aq = (double*)h->arena.alloc(aq.size() * sizeof(double));
+  double* Bq = (double*)h->arena.alloc(bq.size() * sizeof(double));
+  Arena tmp;
+  tmp.cache = h->arena.cache;
+  const size_t bytes = (size_t)nb * W * sizeof(double);
+  double* Gd = (double*)tmp.alloc(bytes);
+  double* M = (double*)tmp.alloc(bytes);
+  double* Rr = (double*)tmp.alloc(bytes);
+  if (!P || !Fd || !Aq || !Bq || !Gd || !M || !Rr) {
+    tmp.release();
+    h->err = "out of device memory (factored point correction)";
+    return GPFVM_E_NOMEM;
+  }
+  F.P = P;
+  hipError_t e = hipMemcpyAsync(Gd, gf.data(), bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(Fd, &F, sizeof(QFactor), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(Aq, aq.data(), aq.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(Bq, bq.data(), bq.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  std::vector<Stage> st(4);
+  st[0].descs.push_back(desc1(M, W, h->Linv, nb, 1, Gd, W, 1, nb, W, nb, 1.0, 0.0, 1));
+  {
+    GemmDesc D = desc1(Rr, W, h->L, nb, 1, M, W, 1, nb, W, nb, -1.0, 0.0, 1);
+    D.X = Gd; D.x_rs = W; D.x_cs = 1; D.gamma = 1.0;
+    st[1].descs.push_back(D);
+  }
+  st[2].descs.push_back(desc1(M, W, h->Linv, nb, 1, Rr, W, 1, nb, W, nb, 1.0, 1.0, 1));
+  st[3].descs.push_back(desc1(P, W, M, 1, W, M, W, 1, W, W, nb, 1.0, 0.0, 0));   // P = M^T M
+  if (e == hipSuccess) e = upload_stages(st, tmp, s);
+  if (e == hipSuccess) e = run_stages(st, s);
+  const hipError_t e2 = hipStreamSynchronize(s);          // gf, F, aq and bq are host buffers
+  tmp.release();
+  if (e != hipSuccess || e2 != hipSuccess) {
+    h->err = std::string("building the factored point correction failed: ") +
+             hipGetErrorString(e != hipSuccess ? e : e2);
+    return GPFVM_E_HIP;
+  }
+  h->qf = Fd;
+  h->qf_nunit = nu;
+  h->qf_w0 = R0 * n1;
+  h->qf_k0 = K0;
+  h->qf_k1 = K1;
+  h->qf_aq = Aq;
+  h->qf_bq = Bq;
+  return GPFVM_OK;
+}
+
+// ---------------------------------------------------------------------------
 // volume-system operator S for nrhs right-hand sides.  elt = F32 gives the
 // mixed operator: the volume Kronecker block in float32 (float32 factors,
 // float32 accumulation), the point-block correction in float64.
@@ -412,7 +535,57 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
       return GPFVM_E_HIP;
     }
     so->ginv_small = (nrhs == 1 && h->nb <= SMALL_GINV_MAX && h->Lt && h->Linvt);
-    if (elt == F64 && nrhs == 1 && qform_ok(N, h->nb)) {
+    // the factored form needs the 2-D volume operator's last stage as one descriptor over the
+    // row-major n0 x n1 output, with room for two more segments
+    int qW = 0, qR = 0;
+    bool qf_fit = elt == F64 && nrhs == 1 && qform_ok(N, h->nb) && so->pp.stages.size() >= 2 &&
+                  qfact_ok(h, &qW, &qR);
+    if (qf_fit) {
+      const Stage& L = so->pp.stages.back();
+      const GemmDesc& D = L.descs.empty() ? GemmDesc() : L.descs[0];
+      qf_fit = L.descs.size() == 1 && D.M == h->nc[0] && D.N == h->nc[1] && D.batch == 1 &&
+               D.c_rs == h->nc[1] && D.c_cs == 1 && D.nseg + 2 <= MAXSEG && L.rider.kind == RIDE_NONE &&
+               so->pp.stages.front().rider.kind == RIDE_NONE;
+    }
+    if (qf_fit) {
+      rc = build_qf(h, h->stream);
+      if (rc) return rc;
+      so->qform = so->qf = true;
+      const int nu = h->qf_nunit, n0 = h->nc[0], n1 = h->nc[1];
+      so->qf_v = (double*)h->arena.alloc((size_t)nu * qW * sizeof(double));
+      if (!so->qf_v) { h->err = "out of device memory (S operator)"; return GPFVM_E_NOMEM; }
+      so->pp_split = so->pp;
+      // the partial sums of v = P w(X) ride on the first stage (it reads X only)
+      Rider& r1 = so->pp_split.stages.front().rider;
+      r1.kind = RIDE_QFV;
+      r1.nr = nu;
+      r1.N = N;
+      r1.v = (const double*)so->X;
+      r1.out = so->qf_v;
+      r1.qf = h->qf;
+      // Y -= sum_r q_r (x) v_r as two more segments of the last stage
+      std::vector<Stage> last{so->pp_split.stages.back()};
+      GemmDesc& D = last[0].descs[0];
+      if (h->qf_k0 > 0) {
+        Seg& S = D.seg[D.nseg++];
+        std::memset(&S, 0, sizeof(S));
+        S.A = h->qf_aq; S.a_rs = h->qf_k0; S.a_cs = 1;
+        S.B = so->qf_v; S.b_rs = n1; S.b_cs = 1;
+        S.K = h->qf_k0; S.alpha = -1.0;
+      }
+      if (h->qf_k1 > 0) {
+        Seg& S = D.seg[D.nseg++];
+        std::memset(&S, 0, sizeof(S));
+        S.A = so->qf_v + (size_t)nu * h->qf_w0; S.a_rs = 1; S.a_cs = n0;
+        S.B = h->qf_bq; S.b_rs = n1; S.b_cs = 1;
+        S.K = h->qf_k1; S.alpha = -1.0;
+      }
+      if (upload_stages(last, h->arena, h->stream, F64) != hipSuccess) {
+        h->err = "descriptor check/upload failed";
+        return GPFVM_E_HIP;
+      }
+      so->pp_split.stages.back() = last[0];
+    } else if (elt == F64 && nrhs == 1 && qform_ok(N, h->nb)) {
       rc = build_qc(h, h->stream);
       if (rc) return rc;
       so->qform = true;
@@ -467,6 +640,7 @@ static hipError_t apply_ginv(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
 static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
   hipError_t e;
   const i64 NN = h->N * so->nrhs;
+  if (so->qf) return run_plan(so->pp_split, s);             // G_pp X + s2 X - sum_r q_r (x) (P w)_r
   if (so->qform) {                                                  // G_pp X + s2 X - Q^T Q X
     if (so->pp.stages.empty() &&
         (e = launch_rows_dot_full(h->nb, h->N, h->Qc, (const double*)so->X, (double*)so->U, s)) != hipSuccess)
@@ -956,10 +1130,26 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
   int state = 0, outer = 0;
   if (o->prec == GPFVM_PREC_FP64) {
     int nd = h->iters;
+    const int start0 = h->iters;
     rc = itergp_run(h, F64, h->bS, h->v, h->iters, o->max_iter, o->tol, o->check_every, o->reorth_passes,
                     o->replace_every, s, &nd, &state);
     if (rc) return rc;
     h->iters = nd;
+    // The stopping test reads the recursive residual.  Where the explicit residual is still
+    // above the tolerance and the budget allows, continue from it (the loop starts from
+    // r = b - S v, a residual replacement), at most twice.
+    for (int again = 0; again < 2 && state == 1 && o->tol > 0; ++again) {
+      const int left = o->max_iter - (h->iters - start0);
+      if (left <= 0 || h->iters >= h->max_iter) break;
+      double r0 = 0;
+      rc = rel_res(h, h->v, &r0, s);
+      if (rc) return rc;
+      if (r0 <= o->tol) break;
+      rc = itergp_run(h, F64, h->bS, h->v, h->iters, left, o->tol, o->check_every, o->reorth_passes,
+                      o->replace_every, s, &nd, &state);
+      if (rc) return rc;
+      h->iters = nd;
+    }
   } else {
     // mixed-precision iterative refinement: float64 residual of the volume
     // system, IterGP with the mixed operator for the correction; all
