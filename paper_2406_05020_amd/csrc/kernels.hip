@@ -559,6 +559,23 @@ hipError_t launch_qf_v(const QFactor* F, int nunit, const double* x, double* vpa
 
 constexpr int GEMM_KDEPTH1 = 1;
 
+// Wavefront-uniform copies of values read from LDS (equal in every lane), so
+// that they live in scalar registers and steer scalar control flow.
+__device__ __forceinline__ int ufl(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ i64 ufl(i64 x) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+  return (i64)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double ufl(double x) { return __longlong_as_double(ufl((i64)__double_as_longlong(x))); }
+template <typename P>
+__device__ __forceinline__ P* ufl(P* p) {
+  return reinterpret_cast<P*>((uintptr_t)ufl((i64)(uintptr_t)p));
+}
+
+template <typename T>
+using gptrw = __attribute__((address_space(1))) T*;
+
 // Workgroups are dispatched to the 8 XCDs in turn (workgroup w runs on XCD
 // w % 8), and each XCD has its own L2.  Give XCD x the contiguous tile range
 // [x q + min(x, r), ...) of n = 8 q + r tiles, so that tiles sharing an operand
@@ -606,22 +623,53 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
     }
   }
   const i64 tile = xcd_tile(blockIdx.x, ntiles);
-  int lo = 0, hi = ndesc - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
-  }
-  const GemmDesc& D = descs[lo];
-  const i64 local = tile - D.tile_begin;
-  const int tn = (int)(local % D.tiles_n);
-  const i64 rest = local / D.tiles_n;
-  const int tm = (int)(rest % D.tiles_m);
-  const i64 b = rest / D.tiles_m;
-  if (b >= D.batch) return;
-  if (D.lower_only && tn > tm) return;
-  const int M = D.M, N = D.N;
-  const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  // This tile's descriptor, staged in LDS: one round of vector loads finds it
+  // among the stage's descriptors (each thread tests one range), one more
+  // copies it.  Read through scalar loads, its fields formed a chain of
+  // dependent round trips in every tile, and the output stores forced them to
+  // be loaded again (a store through C might have changed them).
+  __shared__ GemmDesc sD;
+  __shared__ int sLo;
+  static_assert(sizeof(GemmDesc) % 8 == 0, "descriptor words");
+  int lo = 0;
+  if (ndesc > 1) {
+    if (ndesc <= NT) {
+      if (tid < ndesc) {
+        const i64 t0 = descs[tid].tile_begin;
+        const i64 t1 = tid + 1 < ndesc ? descs[tid + 1].tile_begin : (i64)0x7fffffffffffffffLL;
+        if (t0 <= tile && tile < t1) sLo = tid;
+      }
+    } else if (tid == 0) {
+      int l = 0, h = ndesc - 1;
+      while (l < h) {
+        const int mid = (l + h + 1) >> 1;
+        if (descs[mid].tile_begin <= tile) l = mid; else h = mid - 1;
+      }
+      sLo = l;
+    }
+    __syncthreads();
+    lo = ufl(sLo);
+  }
+  {
+    constexpr int NW8 = (int)(sizeof(GemmDesc) / 8);
+    const unsigned long long* __restrict__ src = reinterpret_cast<const unsigned long long*>(descs + lo);
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(&sD);
+    for (int w = tid; w < NW8; w += NT) dst[w] = src[w];
+  }
+  __syncthreads();
+  const GemmDesc& D = sD;
+  const int tiles_n = ufl(D.tiles_n), tiles_m = ufl(D.tiles_m);
+  const i64 local = tile - ufl(D.tile_begin);
+  const int tn = (int)(local % tiles_n);
+  const i64 rest = local / tiles_n;
+  const int tm = (int)(rest % tiles_m);
+  const i64 b = rest / tiles_m;
+  if (b >= ufl(D.batch)) return;
+  const int lower_only = ufl(D.lower_only);
+  if (lower_only && tn > tm) return;
+  const int M = ufl(D.M), N = ufl(D.N), nseg = ufl(D.nseg);
+  const int m0 = tm * BM, n0 = tn * BN;
   const int bidx = wave % NBLK, kg = wave / NBLK;
   const int rb = (bidx / WNN) * 16, cb = (bidx % WNN) * 16;
 
@@ -637,20 +685,21 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
   if constexpr (KS == 1) {
     // one K group: each segment runs its own chunk loop (many short chunks per
     // segment, so the exposed first load of a segment matters little)
-    for (int g = 0; g < D.nseg; ++g) {
+    for (int g = 0; g < nseg; ++g) {
       const Seg& S = D.seg[g];
-      const gptr<T> __restrict__ A = to_global(reinterpret_cast<const T*>(S.A) + b * S.a_bs);
-      const gptr<T> __restrict__ B = to_global(reinterpret_cast<const T*>(S.B) + b * S.b_bs);
-      const i64 a_rs = S.a_rs, a_cs = S.a_cs, b_rs = S.b_rs, b_cs = S.b_cs;
-      const T alpha = (T)S.alpha;
-      int kbeg = 0, kend = S.K;
-      if (S.tri == 1) kend = min(S.K, m0 + BM);
-      else if (S.tri == 2) kbeg = m0;
-      else if (S.tri == 3) kend = min(S.K, n0 + BN);
-      else if (S.tri == 4) kbeg = n0;
+      const gptr<T> __restrict__ A = to_global(reinterpret_cast<const T*>(ufl(S.A)) + b * ufl(S.a_bs));
+      const gptr<T> __restrict__ B = to_global(reinterpret_cast<const T*>(ufl(S.B)) + b * ufl(S.b_bs));
+      const i64 a_rs = ufl(S.a_rs), a_cs = ufl(S.a_cs), b_rs = ufl(S.b_rs), b_cs = ufl(S.b_cs);
+      const T alpha = (T)ufl(S.alpha);
+      const int K = ufl(S.K), tri = ufl(S.tri);
+      int kbeg = 0, kend = K;
+      if (tri == 1) kend = min(K, m0 + BM);
+      else if (tri == 2) kbeg = m0;
+      else if (tri == 3) kend = min(K, n0 + BN);
+      else if (tri == 4) kbeg = n0;
       if (kbeg >= kend) continue;                    // uniform over the workgroup
       const bool akf = (a_cs == 1), bnf = (b_cs == 1);
-      const int q = SLOT1 ? S.slot : 0;
+      const int q = SLOT1 ? ufl(S.slot) : 0;
       // two register sets: the load of chunk c + 2 is issued while chunk c is
       // multiplied, so each load has two chunks of work to hide behind.  Every
       // lane loads (from a clamped, in-range address) and out-of-range elements
@@ -743,57 +792,100 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
     };
     auto ctx_of = [&](int g, Ctx& c) -> bool {      // false: empty K range
       const Seg& S = D.seg[g];
-      c.A = to_global(reinterpret_cast<const T*>(S.A) + b * S.a_bs);
-      c.B = to_global(reinterpret_cast<const T*>(S.B) + b * S.b_bs);
-      c.a_rs = S.a_rs; c.a_cs = S.a_cs; c.b_rs = S.b_rs; c.b_cs = S.b_cs;
-      c.alpha = (T)S.alpha;
-      c.kbeg = 0; c.kend = S.K;
-      if (S.tri == 1) c.kend = min(S.K, m0 + BM);
-      else if (S.tri == 2) c.kbeg = m0;
-      else if (S.tri == 3) c.kend = min(S.K, n0 + BN);
-      else if (S.tri == 4) c.kbeg = n0;
-      c.akf = (S.a_cs == 1);
-      c.bnf = (S.b_cs == 1);
-      c.q = SLOT1 ? S.slot : 0;
+      c.A = to_global(reinterpret_cast<const T*>(ufl(S.A)) + b * ufl(S.a_bs));
+      c.B = to_global(reinterpret_cast<const T*>(ufl(S.B)) + b * ufl(S.b_bs));
+      c.a_rs = ufl(S.a_rs); c.a_cs = ufl(S.a_cs); c.b_rs = ufl(S.b_rs); c.b_cs = ufl(S.b_cs);
+      c.alpha = (T)ufl(S.alpha);
+      const int K = ufl(S.K), tri = ufl(S.tri);
+      c.kbeg = 0; c.kend = K;
+      if (tri == 1) c.kend = min(K, m0 + BM);
+      else if (tri == 2) c.kbeg = m0;
+      else if (tri == 3) c.kend = min(K, n0 + BN);
+      else if (tri == 4) c.kbeg = n0;
+      c.akf = (c.a_cs == 1);
+      c.bnf = (c.b_cs == 1);
+      c.q = SLOT1 ? ufl(S.slot) : 0;
       return c.kbeg < c.kend;
     };
     T ra[EA], rbv[EB];
-    auto gload = [&](const Ctx& c, int kc) {
+    auto gload_to = [&](const Ctx& c, int kc, T* oa, T* ob) {
   #pragma unroll
       for (int u = 0; u < EA; ++u) {
         const int e = tid + NT * u;
         int k, m;
         if (c.akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
-        ra[u] = (m0 + m < M && kc + k < c.kend) ? c.A[(i64)(m0 + m) * c.a_rs + (i64)(kc + k) * c.a_cs] : (T)0;
+        oa[u] = (m0 + m < M && kc + k < c.kend) ? c.A[(i64)(m0 + m) * c.a_rs + (i64)(kc + k) * c.a_cs] : (T)0;
       }
   #pragma unroll
       for (int u = 0; u < EB; ++u) {
         const int e = tid + NT * u;
         int k, n;
         if (c.bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
-        rbv[u] = (n0 + n < N && kc + k < c.kend) ? c.B[(i64)(kc + k) * c.b_rs + (i64)(n0 + n) * c.b_cs] : (T)0;
+        ob[u] = (n0 + n < N && kc + k < c.kend) ? c.B[(i64)(kc + k) * c.b_rs + (i64)(n0 + n) * c.b_cs] : (T)0;
       }
     };
-    auto sstore = [&](const Ctx& c, int buf) {
+    auto sstore_from = [&](const Ctx& c, int buf, const T* ia, const T* ib) {
   #pragma unroll
       for (int u = 0; u < EA; ++u) {
         const int e = tid + NT * u;
         int k, m;
         if (c.akf) { k = e % LKC; m = e / LKC; } else { m = e % BM; k = e / BM; }
-        As(buf, k, m) = c.alpha * ra[u];
+        As(buf, k, m) = c.alpha * ia[u];
       }
   #pragma unroll
       for (int u = 0; u < EB; ++u) {
         const int e = tid + NT * u;
         int k, n;
         if (c.bnf) { n = e % BN; k = e / BN; } else { k = e % LKC; n = e / LKC; }
-        Bs(buf, k, n) = rbv[u];
+        Bs(buf, k, n) = ib[u];
       }
     };
+    auto gload = [&](const Ctx& c, int kc) { gload_to(c, kc, ra, rbv); };
+    auto sstore = [&](const Ctx& c, int buf) { sstore_from(c, buf, ra, rbv); };
+    auto mult = [&](int buf, int q) {
+  #pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int k = kg * 16 + kk + lk;
+        const T av = As(buf, k, rb + lr);
+        const T bv = Bs(buf, k, cb + lr);
+        v4* a = ((kk >> 2) & 1) ? acc2 : acc;
+        if (q == 0) a[0] = MfmaOp<T>::mac(av, bv, a[0]);
+        else a[NS - 1] = MfmaOp<T>::mac(av, bv, a[NS - 1]);
+      }
+    };
+    // At most UPF segments of at most one chunk each (the summing stage of a
+    // one-rhs operator): every operand load is issued before the first
+    // multiply, so the loads' latencies overlap instead of adding up.  The
+    // chunks then alternate between the two LDS buffers; the barrier after
+    // each store also orders the multiply two chunks back before the next
+    // store into its buffer.
+    constexpr int UPF = 4;
+    bool upfront = nseg <= UPF;
+    for (int g = 0; g < nseg; ++g) upfront = upfront && ufl(D.seg[g].K) <= LKC;
+    if (upfront) {
+      T ua[UPF][EA], ub[UPF][EB];
+      Ctx cs[UPF];
+      bool live[UPF];
+  #pragma unroll
+      for (int g = 0; g < UPF; ++g) live[g] = g < nseg && ctx_of(g, cs[g]);   // uniform
+  #pragma unroll
+      for (int g = 0; g < UPF; ++g)
+        if (live[g]) gload_to(cs[g], cs[g].kbeg, ua[g], ub[g]);
+      int buf = 0;
+  #pragma unroll
+      for (int g = 0; g < UPF; ++g) {
+        if (!live[g]) continue;
+        sstore_from(cs[g], buf, ua[g], ub[g]);
+        __syncthreads();
+        mult(buf, cs[g].q);
+        buf ^= 1;
+      }
+    }
     int g = 0;
     Ctx cur;
-    while (g < D.nseg && !ctx_of(g, cur)) ++g;       // uniform over the workgroup
-    if (g < D.nseg) {
+    if (!upfront)
+      while (g < nseg && !ctx_of(g, cur)) ++g;       // uniform over the workgroup
+    if (!upfront && g < nseg) {
       int kc = cur.kbeg;
       gload(cur, kc);
       sstore(cur, 0);
@@ -805,21 +897,12 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
         bool more = true;
         if (nkc >= cur.kend) {
           ng = g + 1;
-          while (ng < D.nseg && !ctx_of(ng, nxt)) ++ng;
-          more = ng < D.nseg;
+          while (ng < nseg && !ctx_of(ng, nxt)) ++ng;
+          more = ng < nseg;
           if (more) nkc = nxt.kbeg;
         }
         if (more) gload(nxt, nkc);
-        const int q = cur.q;
-  #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const int k = kg * 16 + kk + lk;
-          const T av = As(buf, k, rb + lr);
-          const T bv = Bs(buf, k, cb + lr);
-          v4* a = ((kk >> 2) & 1) ? acc2 : acc;
-          if (q == 0) a[0] = MfmaOp<T>::mac(av, bv, a[0]);
-          else a[NS - 1] = MfmaOp<T>::mac(av, bv, a[NS - 1]);
-        }
+        mult(buf, cur.q);
         if (more) sstore(nxt, buf ^ 1);
         __syncthreads();
         buf ^= 1;
@@ -854,21 +937,38 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
         for (int r = 0; r < 4; ++r) acc[q][r] += sm[((((q * (KS - 1)) + g2 - 1) * NBLK + bidx) * 4 + r) * 64 + lane];
   }
 
-  T* __restrict__ C = reinterpret_cast<T*>(D.C) + b * D.c_bs;
-  const T* __restrict__ X = D.X ? reinterpret_cast<const T*>(D.X) + b * D.x_bs : nullptr;
-  const double* __restrict__ E = D.escale ? D.escale + b * D.e_bs : nullptr;
-  const T beta = (T)D.beta, gamma = (T)D.gamma;
+  // the descriptor's output fields as uniform values; every addend of the four
+  // outputs of this lane is loaded before the first store (an output reads only
+  // its own element of X, escale and C)
+  const gptrw<T> C = (gptrw<T>)(reinterpret_cast<T*>(ufl(D.C)) + b * ufl(D.c_bs));
+  const T* Xp = reinterpret_cast<const T*>(ufl(D.X));
+  const double* Ep = ufl(D.escale);
+  const gptr<T> X = Xp ? to_global(Xp + b * ufl(D.x_bs)) : nullptr;
+  const gptr<double> E = Ep ? to_global(Ep + b * ufl(D.e_bs)) : nullptr;
+  const i64 c_rs = ufl(D.c_rs), c_cs = ufl(D.c_cs), x_rs = ufl(D.x_rs), x_cs = ufl(D.x_cs);
+  const i64 e_rs = ufl(D.e_rs), e_cs = ufl(D.e_cs);
+  const T beta = (T)ufl(D.beta), gamma = (T)ufl(D.gamma);
+  bool ok[4];
+  T ev[4], xv[4], cv[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = m0 + rb + MfmaOp<T>::row(lk, r);
     const int col = n0 + cb + lr;
-    if (row < M && col < N && !(D.lower_only && col > row)) {
+    ok[r] = row < M && col < N && !(lower_only && col > row);
+    ev[r] = (SLOT1 && E && ok[r]) ? (T)E[(i64)row * e_rs + (i64)col * e_cs] : (T)0;
+    xv[r] = (X && ok[r]) ? X[(i64)row * x_rs + (i64)col * x_cs] : (T)0;
+    cv[r] = (beta != (T)0 && ok[r]) ? C[(i64)row * c_rs + (i64)col * c_cs] : (T)0;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = m0 + rb + MfmaOp<T>::row(lk, r);
+    const int col = n0 + cb + lr;
+    if (ok[r]) {
       T v = acc[0][r];
-      if (SLOT1 && E) v += (T)E[(i64)row * D.e_rs + (i64)col * D.e_cs] * acc[NS - 1][r];
-      if (X) v += gamma * X[(i64)row * D.x_rs + (i64)col * D.x_cs];
-      T* cp = C + (i64)row * D.c_rs + (i64)col * D.c_cs;
-      if (beta != (T)0) v += beta * *cp;
-      *cp = v;
+      if (SLOT1 && E) v += ev[r] * acc[NS - 1][r];
+      if (X) v += gamma * xv[r];
+      if (beta != (T)0) v += beta * cv[r];
+      C[(i64)row * c_rs + (i64)col * c_cs] = v;
     }
   }
 }
