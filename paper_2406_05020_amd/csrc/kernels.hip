@@ -577,14 +577,19 @@ template <typename T>
 using gptrw = __attribute__((address_space(1))) T*;
 
 // Workgroups are dispatched to the 8 XCDs in turn (workgroup w runs on XCD
-// w % 8), and each XCD has its own L2.  Give XCD x the contiguous tile range
-// [x q + min(x, r), ...) of n = 8 q + r tiles, so that tiles sharing an operand
-// row block or a batch slab are fetched into one L2 (a bijection of [0, n)).
-constexpr int GEMM_NXCD = 8;
+// w % 8), and each XCD has its own L2.  Tiles are dealt to the XCDs in chunks
+// of GEMM_XCHUNK consecutive tiles (a batch slab of 2 x 2 tiles, or tiles
+// sharing an operand row block), so that a chunk is fetched into one L2, and
+// chunk c goes to XCD c % 8, so that every XCD gets an even share of
+// triangular stages whose tiles' K ranges grow with the row block.  A
+// bijection of [0, n); the last n mod (8 GEMM_XCHUNK) tiles keep their order.
+constexpr int GEMM_NXCD = 8, GEMM_XCHUNK = 4;
 
 __device__ __forceinline__ i64 xcd_tile(i64 w, i64 n) {
-  const i64 q = n / GEMM_NXCD, r = n % GEMM_NXCD, x = w % GEMM_NXCD;
-  return x * q + (x < r ? x : r) + w / GEMM_NXCD;
+  const i64 full = n / (GEMM_NXCD * GEMM_XCHUNK) * (GEMM_NXCD * GEMM_XCHUNK);
+  if (w >= full) return w;
+  const i64 x = w % GEMM_NXCD, j = w / GEMM_NXCD;
+  return ((j / GEMM_XCHUNK) * GEMM_NXCD + x) * GEMM_XCHUNK + j % GEMM_XCHUNK;
 }
 
 template <typename T, int BM, int BN, int KS, bool SLOT1, bool RIDE>
@@ -624,41 +629,51 @@ __global__ __launch_bounds__(4 * BM * BN / 16 * KS) void k_gemm_lds(const GemmDe
   }
   const i64 tile = xcd_tile(blockIdx.x, ntiles);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-  // This tile's descriptor, staged in LDS: one round of vector loads finds it
-  // among the stage's descriptors (each thread tests one range), one more
-  // copies it.  Read through scalar loads, its fields formed a chain of
-  // dependent round trips in every tile, and the output stores forced them to
-  // be loaded again (a store through C might have changed them).
-  __shared__ GemmDesc sD;
-  __shared__ int sLo;
-  static_assert(sizeof(GemmDesc) % 8 == 0, "descriptor words");
+  // This tile's descriptor.  In the K-split kernels (short, latency-bound
+  // stages) it is staged in LDS: one round of vector loads finds it among the
+  // stage's descriptors (each thread tests one range), one more copies it.
+  // Read through scalar loads, its fields form a chain of dependent round
+  // trips per segment.  The single-group kernel has long K loops per tile and
+  // reads it directly (the extra round trips of staging measured slower there).
+  const GemmDesc* Dp = nullptr;
   int lo = 0;
-  if (ndesc > 1) {
-    if (ndesc <= NT) {
-      if (tid < ndesc) {
-        const i64 t0 = descs[tid].tile_begin;
-        const i64 t1 = tid + 1 < ndesc ? descs[tid + 1].tile_begin : (i64)0x7fffffffffffffffLL;
-        if (t0 <= tile && tile < t1) sLo = tid;
-      }
-    } else if (tid == 0) {
-      int l = 0, h = ndesc - 1;
-      while (l < h) {
-        const int mid = (l + h + 1) >> 1;
-        if (descs[mid].tile_begin <= tile) l = mid; else h = mid - 1;
-      }
-      sLo = l;
+  if constexpr (KS == 1) {
+    int hi = ndesc - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (descs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
     }
-    __syncthreads();
-    lo = ufl(sLo);
-  }
-  {
+    Dp = descs + lo;
+  } else {
+    __shared__ GemmDesc sD;
+    __shared__ int sLo;
+    static_assert(sizeof(GemmDesc) % 8 == 0, "descriptor words");
+    if (ndesc > 1) {
+      if (ndesc <= NT) {
+        if (tid < ndesc) {
+          const i64 t0 = descs[tid].tile_begin;
+          const i64 t1 = tid + 1 < ndesc ? descs[tid + 1].tile_begin : (i64)0x7fffffffffffffffLL;
+          if (t0 <= tile && tile < t1) sLo = tid;
+        }
+      } else if (tid == 0) {
+        int l = 0, h = ndesc - 1;
+        while (l < h) {
+          const int mid = (l + h + 1) >> 1;
+          if (descs[mid].tile_begin <= tile) l = mid; else h = mid - 1;
+        }
+        sLo = l;
+      }
+      __syncthreads();
+      lo = ufl(sLo);
+    }
     constexpr int NW8 = (int)(sizeof(GemmDesc) / 8);
     const unsigned long long* __restrict__ src = reinterpret_cast<const unsigned long long*>(descs + lo);
     unsigned long long* dst = reinterpret_cast<unsigned long long*>(&sD);
     for (int w = tid; w < NW8; w += NT) dst[w] = src[w];
+    __syncthreads();
+    Dp = &sD;
   }
-  __syncthreads();
-  const GemmDesc& D = sD;
+  const GemmDesc& D = *Dp;
   const int tiles_n = ufl(D.tiles_n), tiles_m = ufl(D.tiles_m);
   const i64 local = tile - ufl(D.tile_begin);
   const int tn = (int)(local % tiles_n);
