@@ -39,9 +39,10 @@ def relerr(a, b):
 
 
 def test_schur_operator_matches_oracle(G, c2):
-    """nrhs = 1 applies the point correction as Q^T Q with the resident
-    Q = L^{-1} G_bp; nrhs = 2 through the cross-block Kronecker products and
-    the point-block triangular solves.  Both against the oracle's Cholesky."""
+    """nrhs = 1 applies the point correction Q^T Q (Q = L^{-1} G_bp) in
+    factored form, the initial points being one group pinned at t = 0;
+    nrhs = 2 through the cross-block Kronecker products and the point-block
+    triangular solves.  Both against the oracle's Cholesky."""
     p, o, S = c2
     rng = np.random.default_rng(5)
     X = rng.standard_normal((2, p.n_pde))

@@ -249,8 +249,9 @@ def test_batched_volume_matvec_on_ragged_tiles(G, nt, nx, nrhs):
 @pytest.mark.parametrize("name", list(RAGGED))
 def test_schur_matvec_matches_oracle(G, name):
     """Volume-system operator S = G_pp + s2 I - G_pb G_bb^{-1} G_bp: one
-    right-hand side (resident Q = L^{-1} G_bp) and three (Kronecker cross
-    blocks and triangular solves), against the oracle's Cholesky solve."""
+    right-hand side (the correction through Q = L^{-1} G_bp: factored for the
+    2-D case, resident for the 3-D ones) and three (Kronecker cross blocks and
+    triangular solves), against the oracle's Cholesky solve."""
     p = RAGGED[name]()
     S = SchurSystem(O.Oracle(p))
     rng = np.random.default_rng(17)
