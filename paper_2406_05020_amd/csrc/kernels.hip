@@ -1284,6 +1284,7 @@ hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const 
 constexpr int CU_WAVES = 16;
 static_assert(CU_WAVES == CS_PARTS, "the riding column sums follow the column update's order");
 constexpr int CU_BLK = 2048;
+constexpr int CU_PF = 8;        // rows per wavefront loaded before the coefficients are staged
 constexpr int CU_MAXCH = 16;   // most partial sums per coefficient (rows_dot_chunks <= 16)
 
 // Row dots split over column chunks, so that a few long rows still occupy
@@ -1315,9 +1316,24 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
   __shared__ double part2[TWO ? CU_WAVES : 1][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const i64 c = (i64)blockIdx.x * 64 + lane;
+  // the addends of the output, loaded before anything they do not depend on
+  const bool cw = wave == 0 && c < N;
+  const double bv = cw ? base[c] : 0.0;
+  const double bv2 = (TWO && cw) ? base2[c] : 0.0;
+  const double bvm = (TWO && cw && base2m) ? base2m[c] : 0.0;
   double acc = 0.0, acc2 = 0.0;
   for (int j0 = 0; j0 < nr; j0 += CU_BLK) {
     const int jn = min(CU_BLK, nr - j0);
+    // this wavefront's first CU_PF rows of the block, loaded before the
+    // coefficients are staged (they do not depend on them)
+    double pm[CU_PF], pm2[CU_PF];
+#pragma unroll
+    for (int k = 0; k < CU_PF; ++k) {
+      const int i = wave + k * CU_WAVES;
+      const bool ok = c < N && i < jn;
+      pm[k] = ok ? M[(i64)(j0 + i) * N + c] : 0.0;
+      pm2[k] = (TWO && ok) ? M2[(i64)(j0 + i) * N + c] : 0.0;
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < jn; i += 64 * CU_WAVES) {
       // all partials of row j0 + i are loaded before they are added (in order)
@@ -1333,8 +1349,16 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
     }
     __syncthreads();
     if (c < N) {
+#pragma unroll
+      for (int k = 0; k < CU_PF; ++k) {
+        const int i = wave + k * CU_WAVES;
+        if (i < jn) {
+          acc = fma(pm[k], us[i], acc);
+          if (TWO) acc2 = fma(pm2[k], us[i], acc2);
+        }
+      }
 #pragma unroll 4
-      for (int i = wave; i < jn; i += CU_WAVES) {
+      for (int i = wave + CU_PF * CU_WAVES; i < jn; i += CU_WAVES) {
         const i64 off = (i64)(j0 + i) * N + c;
         acc = fma(M[off], us[i], acc);
         if (TWO) acc2 = fma(M2[off], us[i], acc2);
@@ -1348,13 +1372,13 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
   if (wave == 0 && c < N) {
     double s = 0.0;
     for (int w = 0; w < CU_WAVES; ++w) s += part[w][lane];
-    const double v = base[c] - s;
+    const double v = bv - s;
     out[c] = v;
     if (out2) out2[c] = v;
     if (TWO) {
       double s2 = 0.0;
       for (int w = 0; w < CU_WAVES; ++w) s2 += part2[w][lane];
-      const double b2 = base2m ? base2[c] - base2m[c] : base2[c];
+      const double b2 = base2m ? bv2 - bvm : bv2;
       const double v3 = b2 - s2;
       out3[c] = v3;
       prod = v * v3;
