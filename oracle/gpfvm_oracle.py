@@ -27,9 +27,14 @@ Parity pins (tests under ``tests/test_oracle_*.py``):
   IterGP ..................... pinned: unit-vector actions reproduce Cholesky;
                                run to n iterations reproduces the exact
                                posterior; combined variance >= exact and
-                               non-increasing.  The early-terminated posterior
-                               after k << n iterations has no closed form:
-                               only those invariants pin it.
+                               non-increasing.  At a fixed k << n (one or two
+                               projection passes) the weights and the inverse
+                               approximation equal the Galerkin projection onto
+                               the Krylov space K_k(S, b), built by Arnoldi on
+                               the dense S
+  schur_cross ................ pinned: block elimination of the joint Gaussian
+                               conditional (full posterior covariance and mean
+                               from the dense Gram)
 """
 from __future__ import annotations
 

@@ -142,3 +142,102 @@ def test_ode_toy_fvm_converges_to_sine():
         m, v, _ = O.dense_posterior(o, X)
         errs.append(np.abs(m - np.sin(X[:, 0])).max())
     assert errs[2] < errs[1] < errs[0] and errs[2] < 1e-3, errs
+
+
+# ---------------------------------------------------------------------------
+# IterGP at a fixed iteration count k << N (Sec. 4.1).  With CG actions the
+# first k directions span the Krylov space K_k(S, b), and IterGP's inverse
+# approximation C_k = D diag(1/eta) D^T is the S-Galerkin projector onto it:
+# C_k = V (V^T S V)^{-1} V^T for any basis V, and v_k = C_k b.  The pin builds
+# V by Arnoldi (twice-orthogonalised) on the dense S formed from the dense
+# Gram blocks, independent of the matrix-free operator and of the recurrence.
+# ---------------------------------------------------------------------------
+def _dense_schur(o, p):
+    G = o.gram()
+    nb = p.n_b
+    Gbb, Gbp, Gpp = G[:nb, :nb], G[:nb, nb:], G[nb:, nb:]
+    return Gpp - Gbp.T @ np.linalg.solve(Gbb, Gbp)
+
+
+def _krylov_basis(A, b, k):
+    V = np.zeros((len(b), k))
+    V[:, 0] = b / np.linalg.norm(b)
+    for j in range(1, k):
+        w = A @ V[:, j - 1]
+        for _ in range(2):
+            w -= V[:, :j] @ (V[:, :j].T @ w)
+        V[:, j] = w / np.linalg.norm(w)
+    return V
+
+
+def _galerkin_gap(itergp_fn, S, Sd, k):
+    """Relative distance of (v_k, C_k) from the Krylov-Galerkin solution."""
+    V = _krylov_basis(Sd, S.b, k)
+    H = V.T @ Sd @ V
+    Cg = V @ np.linalg.solve(H, V.T)
+    xg = Cg @ S.b
+    vp, D, eta = itergp_fn(S, k)[:3]
+    C = D @ np.diag(1.0 / eta) @ D.T
+    return (np.linalg.norm(vp - xg) / np.linalg.norm(xg), np.abs(C - Cg).max() / np.abs(Cg).max())
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+def test_itergp_fixed_k_is_the_krylov_galerkin_projection(passes):
+    p = W.heat1d_c1(nt=8, nx=8, n_ic=16, grid_n=9)
+    o = O.Oracle(p)
+    S = SchurSystem(o)
+    Sd = _dense_schur(o, p)
+    # the projected matrix V^T S V reaches cond 7e4 at k = 40: bound 1e-9 there
+    for k, tol in ((1, 1e-13), (7, 1e-12), (20, 1e-11), (40, 1e-9)):
+        gv, gc = _galerkin_gap(lambda S_, k_: O.itergp(S_, k_, passes=passes), S, Sd, k)
+        assert gv <= tol and gc <= tol, (k, gv, gc)
+
+
+def test_itergp_two_pass_variance_bounds_and_cg_iterate():
+    """Two-pass IterGP at fixed k: combined variance >= the exact one and
+    non-increasing in k; for small k (before plain CG loses orthogonality) the
+    iterate is textbook CG's."""
+    p = W.heat1d_c1(nt=8, nx=8, n_ic=16, grid_n=9)
+    o = O.Oracle(p)
+    X = o.grid_points(p.grid)
+    _, v_ex, _ = O.dense_posterior(o, X)
+    S = SchurSystem(o)
+    prev = None
+    for k in (2, 5, 10, 20, 40):
+        vp, D, eta, _ = O.itergp(S, k, passes=2)
+        _, var = two_stage_posterior(S, vp, X, D, eta)
+        assert np.all(var >= v_ex - 1e-9)
+        if prev is not None:
+            assert np.all(var <= prev + 1e-9)
+        prev = var
+    for k in (1, 3, 7):
+        vp, _, _, _ = O.itergp(S, k, passes=2)
+        x_cg, _ = _cg_fixed(S, k)
+        assert np.linalg.norm(vp - x_cg) <= 1e-12 * np.linalg.norm(x_cg)
+
+
+def _itergp_second_pass_with_z(S, k):
+    """A plausible slip planted in a copy of the two-pass recurrence: the
+    second projection reuses z = S s instead of S d."""
+    b = S.b
+    n = len(b)
+    v = np.zeros(n); D = np.zeros((n, k)); eta = np.zeros(k)
+    for i in range(k):
+        r = b - S.matvec(v) if i > 0 else b.copy()
+        z = S.matvec(r)
+        d = r - D[:, :i] @ ((D[:, :i].T @ z) / eta[:i]) if i > 0 else r.copy()
+        if i > 0:
+            d = d - D[:, :i] @ ((D[:, :i].T @ z) / eta[:i])
+        eta[i] = d @ S.matvec(d)
+        D[:, i] = d
+        v = v + (r @ r) / eta[i] * d
+    return v, D, eta
+
+
+def test_galerkin_pin_detects_a_planted_projection_slip():
+    p = W.heat1d_c1(nt=8, nx=8, n_ic=16, grid_n=9)
+    o = O.Oracle(p)
+    S = SchurSystem(o)
+    Sd = _dense_schur(o, p)
+    gv, gc = _galerkin_gap(_itergp_second_pass_with_z, S, Sd, 7)
+    assert gv > 1e-2 and gc > 1e-2, (gv, gc)
