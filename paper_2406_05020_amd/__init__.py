@@ -354,7 +354,7 @@ def solve_ibvp(p, prec: int = PREC_FP64, tol: float = 1e-8, max_iter: int = 512,
 class Server:
     """Thin wrapper over gpfvm_server_*: submit whole IBVP solves, poll results."""
 
-    def __init__(self, workers: int = 8, hbm_budget: int = 64 << 30, prec: int = PREC_MIXED, tol: float = 1e-6,
+    def __init__(self, workers: int = 8, hbm_budget: int = 64 << 30, prec: int = PREC_FP64, tol: float = 1e-6,
                  max_iter: int = 1024, check_every: int = 16, coarse_cells: int = 0):
         o = ServerOpts(workers, hbm_budget, prec, tol, max_iter, check_every, coarse_cells)
         self.h = C.c_void_p()

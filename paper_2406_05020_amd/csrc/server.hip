@@ -284,7 +284,7 @@ extern "C" void gpfvm_default_server_opts(gpfvm_server_opts* o) {
   if (!o) return;
   o->workers = 8;
   o->hbm_budget = 64LL << 30;
-  o->prec = GPFVM_PREC_MIXED;
+  o->prec = GPFVM_PREC_FP64;
   o->tol = 1e-6;
   o->max_iter = 1024;
   o->check_every = 16;

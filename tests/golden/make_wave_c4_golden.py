@@ -1,0 +1,62 @@
+"""Write the stored oracle values for the full-size wave problem
+(64 x 128 x 128 volumes with per-cell c^2, 16384 initial/boundary points).
+
+Calls only the oracle: the two-stage system (exact Cholesky conditioning on
+the points, Sec. 4.2) and IterGP with CG actions and the projection done twice
+(Sec. 4.1; the Limitations section's full reorthogonalisation), stopped early
+after a fixed number of iterations.  The posterior mean and the combined
+variance (Sec. 2.1 eq. lin-cond-mean / lin-cond-cov with the IterGP inverse
+approximation) are stored at 256 seeded sample points of the 8 x 128 x 128
+evaluation grid of cell centres, after 30 and after 200 iterations (the
+second run continues the first, with the same recurrences).
+
+Run from the repository root:  python tests/golden/make_wave_c4_golden.py
+(about half an hour on 8 cores; writes tests/golden/wave2d_c4_itergp.json).
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import workloads as W                                     # noqa: E402
+from oracle import gpfvm_oracle as O                      # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "wave2d_c4_itergp.json")
+STOPS = (30, 200)
+N_SAMPLE, SAMPLE_SEED = 256, 4
+
+
+def main():
+    t0 = time.perf_counter()
+    p = W.wave2d_c4()
+    o = O.Oracle(p)
+    S = O.SchurSystem(o)
+    X = o.grid_points(p.grid)
+    idx = np.sort(np.random.default_rng(SAMPLE_SEED).choice(len(X), size=N_SAMPLE, replace=False))
+    print(f"setup {time.perf_counter() - t0:.0f}s", flush=True)
+    out = {"workload": p.name, "n_pde": int(p.n_pde), "n_b": int(p.n_b),
+           "grid": [len(a) for a in p.grid], "passes": 2, "sample_seed": SAMPLE_SEED,
+           "idx": idx.tolist(), "stops": {}}
+    state = None
+    done = 0
+    for k in STOPS:
+        vp, D, eta, res = O.itergp(S, k - done, passes=2, init=state)
+        state = (vp, D, eta)
+        done = k
+        assert D.shape[1] == k, (D.shape, k)
+        m, v = O.two_stage_posterior(S, vp, X[idx], D, eta)
+        rr = float(np.linalg.norm(S.b - S.matvec(vp)) / np.linalg.norm(S.b))
+        out["stops"][str(k)] = {"mean": [float(x) for x in m], "var": [float(x) for x in v], "rel_res": rr}
+        print(f"k={k}: rel_res {rr:.3e}, {time.perf_counter() - t0:.0f}s", flush=True)
+        with open(OUT + ".tmp", "w") as f:
+            json.dump(out, f)
+        os.replace(OUT + ".tmp", OUT)
+
+
+if __name__ == "__main__":
+    main()
