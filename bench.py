@@ -270,7 +270,8 @@ def c2_block(args, G, W, stream):
 # sources it was measured with; once those change, traffic reads null until
 # it is measured again.
 VOLUME_GEMM_TRAFFIC = {
-    # (workload, rhs): (bytes per launch, source hash)
+    # (workload, rhs): (bytes per launch, source hash); profiles/k_gemm_lds_wave64x128x128_volume_gram_1rhs.md
+    ("wave2d_64x128x128", 1): (104.4e6, "a3085c56a16492dc"),
 }
 TRAFFIC_SOURCES = ("kernels.hip", "plan.hip", "dense.hip", "common.h")
 
