@@ -53,15 +53,31 @@ extern "C" {
 #define GPFVM_MAX_DERIV      4   /* highest derivative order per dim in any term    */
 
 #define GPFVM_PREC_FP64      0   /* every step in float64                            */
-#define GPFVM_PREC_MIXED     1   /* Gram matvec in low precision inside FP64
-                                    iterative refinement; FP64 recurrences           */
+#define GPFVM_PREC_MIXED     1   /* Gram matvec in low precision (tile format below)
+                                    inside float64 iterative refinement; float64
+                                    recurrences, directions and posterior            */
 
-#define GPFVM_TILE_FP32      0   /* the one mixed-path tile format: float32 factor
-                                    tiles, float32 accumulation.  Narrower formats
-                                    are not provided: the volume Gram is a sum of
-                                    Kronecker terms that cancel to far below their
-                                    size, so even float32 loses the small
-                                    eigenvalues (any other value: GPFVM_E_INVALID) */
+/* Tile formats of the low-precision volume Gram (chosen at assemble).  The
+ * volume Gram is a sum of Kronecker terms that cancel to far below their
+ * size: its small eigenvalues sit at the PDE noise level (about 1e-6 of the
+ * mean diagonal), so the low-precision operator must keep float32 accuracy or
+ * the volume system turns indefinite, as it does with a single bfloat16 or
+ * float16 tile (relative error 2^-9 / 2^-11).  Both formats below keep float32
+ * accuracy. */
+#define GPFVM_TILE_FP32      0   /* float32 factor tiles and tensors on the float32
+                                    matrix cores, float32 accumulation              */
+#define GPFVM_TILE_BF16X3    1   /* float32 factor tiles and tensors, each value
+                                    split into three bfloat16 slices on the way
+                                    into the bfloat16 matrix cores; the six slice
+                                    products of order <= 4 per block, float32
+                                    accumulation (float32 accuracy)                 */
+
+/* Solve methods (Sec. 4.1, "Iterative techniques"). */
+#define GPFVM_METHOD_ITERGP  0   /* IterGP with CG actions: stores every direction;
+                                    posterior mean and combined variance             */
+#define GPFVM_METHOD_CG      1   /* plain conjugate gradients: O(N) state, no stored
+                                    directions; posterior mean only (the variance
+                                    needs the directions: GPFVM_E_STATE)             */
 
 /* One-dimensional kernels of the tensor-product prior (Sec. 3.1-3.2).  The
  * half-integer Matern kernels k(r) = exp(-c r/l) p_q(c r/l), c = sqrt(2q+1),
@@ -113,7 +129,7 @@ typedef struct {
 
 typedef struct {
   int max_iter;        /* capacity for stored IterGP directions (>= 1)              */
-  int tile;            /* GPFVM_TILE_* format prepared for the mixed path           */
+  int tile;            /* GPFVM_TILE_* format of the low-precision volume Gram      */
   int reuse_memory;    /* 1 (default): device blocks come from and return to a      */
                        /* per-device cache of this process, so repeated             */
                        /* assemble/destroy cycles make no hipMalloc/hipFree calls;  */
@@ -124,11 +140,13 @@ typedef struct {
 typedef struct {
   int prec;            /* GPFVM_PREC_FP64 or GPFVM_PREC_MIXED                       */
   double tol;          /* stop once ||r|| <= tol ||b|| on the volume system (0: none)*/
-  int max_iter;        /* IterGP iterations (<= assemble max_iter)                  */
+  int max_iter;        /* iterations (IterGP: <= assemble max_iter)                 */
   int resume;          /* 1: continue from the stored state of a previous solve     */
-  int tile;            /* mixed path: GPFVM_TILE_* format of the inner matvec        */
-  double inner_tol;    /* mixed path: inner relative reduction per refinement step  */
-  int max_outer;       /* mixed path: refinement steps                              */
+  int tile;            /* mixed path: must equal the handle's tile format           */
+  int block;           /* mixed path: low-precision iterations per refinement block */
+                       /* (1 .. GPFVM_MAX_BLOCK); each block is followed by the     */
+                       /* float64 re-stabilisation of its directions               */
+  int max_outer;       /* mixed path: refinement blocks at most                     */
   int check_every;     /* host convergence poll interval in iterations (>= 1)       */
   int reorth_passes;   /* 1: the published recurrence d = s - C z (one projection);  */
                        /* 2: the projection repeated on d (stored S D; default)      */
@@ -140,13 +158,16 @@ typedef struct {
                        /* Needs a fresh FP64 solve with reorth_passes = 2; the       */
                        /* coarse cells (< assemble max_iter, <= GPFVM_MAX_COARSE)    */
                        /* become the first stored directions.                       */
+  int method;          /* GPFVM_METHOD_ITERGP (default) or GPFVM_METHOD_CG; CG is    */
+                       /* float64, fresh (no resume) and without the coarse start   */
 } gpfvm_solve_opts;
 
 #define GPFVM_MAX_COARSE 8192
+#define GPFVM_MAX_BLOCK  64
 
 typedef struct {
-  int iters;           /* IterGP directions stored (posterior rank)                 */
-  int outer;           /* refinement steps taken (mixed path)                       */
+  int iters;           /* IterGP: directions stored (posterior rank); CG: iterations*/
+  int outer;           /* refinement blocks taken (mixed path)                      */
   double rel_res;      /* ||b - S v|| / ||b|| on the volume (Schur) system          */
   double rel_res_full; /* ||y - G alpha|| / ||y|| on the whole IBVP system           */
   int status;          /* GPFVM_OK, GPFVM_E_NOCONV or GPFVM_E_NOTPD                 */
@@ -179,20 +200,24 @@ int gpfvm_validate(const gpfvm_ibvp* p);
 int gpfvm_assemble(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts,
                    void* stream, gpfvm_handle** out);
 
-/* y = G x for the whole IBVP Gram (observation order [points; volumes],
- * including Sigma), for nrhs right-hand sides.  x, y: device, n*nrhs doubles,
- * right-hand side r at offset r*n; x and y must not overlap.  prec selects the
- * float64 plan or the mixed plan (GPFVM_PREC_MIXED, tile format given at
- * assemble).  Errors: INVALID, HIP. */
-int gpfvm_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec,
-                 void* stream);
+/* y = G x for the whole IBVP Gram (Sec. 2.2, G = L k L' + Sigma, observation
+ * order [points; volumes], Sigma included), for nrhs right-hand sides.
+ * x, y: device, n*nrhs values of type dtype (GPFVM_DTYPE_F64: double,
+ * GPFVM_DTYPE_F32: float; float input is widened to float64 and the float64
+ * result rounded to float), right-hand side r at offset r*n; x and y must not
+ * overlap.  prec selects the float64 plan or the low-precision plan of the
+ * volume block (GPFVM_PREC_MIXED, tile format given at assemble); the point
+ * and cross blocks stay float64.  Errors: INVALID, NOMEM, HIP. */
+#define GPFVM_DTYPE_F64 0
+#define GPFVM_DTYPE_F32 1
+int gpfvm_matvec(gpfvm_handle* h, int nrhs, const void* x, void* y, int dtype, int prec, void* stream);
 
 /* y = S x with S = L_V k L_V' + Sigma_V - G_pb G_bb^{-1} G_bp, the Gram of the
  * volume observations under the prior already conditioned on the point
  * observations (Sec. 4.2): the operator the iterative solver applies.
  * x, y: device, N*nrhs doubles (N = number of volumes), no overlap.  prec
- * GPFVM_PREC_MIXED evaluates the volume Kronecker block in float32 (float32
- * factors and accumulation) and the point-block correction in float64.
+ * GPFVM_PREC_MIXED evaluates the volume Kronecker block in the handle's
+ * low-precision tile format and the point-block correction in float64.
  * Errors: INVALID, NOMEM, HIP. */
 int gpfvm_schur_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec, void* stream);
 
@@ -201,8 +226,8 @@ int gpfvm_schur_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, in
  * the Kronecker sum evaluated as MFMA mode products.  x, y: device,
  * N*nrhs doubles, no overlap.  For GPFVM_PREC_FP64 the plan is bound to x and
  * y on the first call with that (x, y, nrhs) and reused (the buffers must stay
- * allocated while the handle lives); GPFVM_PREC_MIXED runs the float32 plan
- * through internal buffers.  Errors: INVALID, NOMEM, HIP. */
+ * allocated while the handle lives); GPFVM_PREC_MIXED runs the low-precision
+ * plan (the handle's tile format) through internal buffers.  Errors: INVALID, NOMEM, HIP. */
 int gpfvm_volume_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec, void* stream);
 
 /* Representer weights alpha = G^{-1} y (Sec. 4, representer weights): exact

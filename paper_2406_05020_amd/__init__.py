@@ -19,7 +19,9 @@ LIB_PATH = os.path.join(HERE, "libgpfvm.so")
 
 OK, E_INVALID, E_NOMEM, E_HIP, E_NOTPD, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_MIXED = 0, 1
-TILE_FP32 = 0        # the only mixed-path tile format
+TILE_FP32, TILE_BF16X3 = 0, 1      # low-precision volume-Gram tile formats
+METHOD_ITERGP, METHOD_CG = 0, 1
+DTYPE_F64, DTYPE_F32 = 0, 1
 MAX_DIM, MAX_TERMS, MAX_GROUPS = 3, 8, 16
 ERR_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOTPD", -5: "NOCONV", -6: "STATE"}
 
@@ -46,8 +48,9 @@ class AssembleOpts(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("prec", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int), ("resume", C.c_int),
-                ("tile", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int),
-                ("reorth_passes", C.c_int), ("replace_every", C.c_int), ("coarsen", C.c_int * 3)]
+                ("tile", C.c_int), ("block", C.c_int), ("max_outer", C.c_int), ("check_every", C.c_int),
+                ("reorth_passes", C.c_int), ("replace_every", C.c_int), ("coarsen", C.c_int * 3),
+                ("method", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -84,7 +87,7 @@ SYMBOLS = {
     "gpfvm_default_solve_opts": ([C.POINTER(SolveOpts)], None),
     "gpfvm_validate": ([C.POINTER(IBVPStruct)], C.c_int),
     "gpfvm_assemble": ([C.POINTER(IBVPStruct), C.POINTER(AssembleOpts), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
-    "gpfvm_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "gpfvm_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p], C.c_int),
     "gpfvm_volume_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
     "gpfvm_schur_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
     "gpfvm_solve": ([C.c_void_p, C.POINTER(SolveOpts), C.POINTER(SolveInfo), C.c_void_p], C.c_int),
@@ -228,8 +231,13 @@ def get_info(h) -> dict:
 
 
 def matvec(h, x, y, nrhs: int = 1, prec: int = PREC_FP64, stream=None) -> None:
-    """y = G x for device float64 tensors x, y of n * nrhs elements."""
-    _check(lib().gpfvm_matvec(h, nrhs, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), prec, _stream(stream)), h)
+    """y = G x for device tensors x, y of n * nrhs elements, both float64 or both float32."""
+    import torch
+    if x.dtype != y.dtype or x.dtype not in (torch.float64, torch.float32):
+        raise ValueError("matvec: x and y must both be float64 or both float32")
+    dt = DTYPE_F64 if x.dtype == torch.float64 else DTYPE_F32
+    _check(lib().gpfvm_matvec(h, nrhs, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), dt, prec,
+                              _stream(stream)), h)
 
 
 def volume_matvec(h, x, y, nrhs: int = 1, prec: int = PREC_FP64, stream=None) -> None:
@@ -251,15 +259,19 @@ def default_solve_opts() -> SolveOpts:
 
 
 def solve(h, prec: int = PREC_FP64, tol: float = 1e-8, max_iter: int = 512, resume: bool = False,
-          tile: int = TILE_FP32, inner_tol: float = 1e-2, max_outer: int = 20, check_every: int = 8,
+          tile: int = TILE_FP32, block: int = 32, max_outer: int = 1000, check_every: int = 8,
           reorth_passes: int = 2, replace_every: int = 25, stream=None, raise_on_noconv: bool = False,
-          coarsen: Optional[Sequence[int]] = None) -> dict:
-    """IterGP solve.  coarsen: per-dimension factors of the coarse warm start
-    (the coarse cells become the first directions; None or all 1: off)."""
+          coarsen: Optional[Sequence[int]] = None, method: int = METHOD_ITERGP) -> dict:
+    """Solve of the volume system.  method: METHOD_ITERGP (directions stored,
+    combined variance) or METHOD_CG (plain CG, mean only).  prec PREC_MIXED:
+    blocks of `block` low-precision iterations, each re-stabilised in float64
+    (tile must be the handle's tile format).  coarsen: per-dimension factors
+    of the coarse warm start (the coarse cells become the first directions;
+    None or all 1: off)."""
     cf = list(coarsen) if coarsen is not None else []
     cf = (cf + [1, 1, 1])[:3]
-    o = SolveOpts(prec, tol, max_iter, 1 if resume else 0, tile, inner_tol, max_outer, check_every,
-                  reorth_passes, replace_every, (C.c_int * 3)(*cf))
+    o = SolveOpts(prec, tol, max_iter, 1 if resume else 0, tile, block, max_outer, check_every,
+                  reorth_passes, replace_every, (C.c_int * 3)(*cf), method)
     info = SolveInfo()
     rc = lib().gpfvm_solve(h, C.byref(o), C.byref(info), _stream(stream))
     if rc not in (OK, E_NOCONV, E_NOTPD) or (raise_on_noconv and rc != OK):

@@ -76,12 +76,13 @@ extern "C" void gpfvm_default_solve_opts(gpfvm_solve_opts* o) {
   o->max_iter = 512;
   o->resume = 0;
   o->tile = GPFVM_TILE_FP32;
-  o->inner_tol = 1e-2;
-  o->max_outer = 20;
+  o->block = 32;
+  o->max_outer = 1000;
   o->check_every = 8;
   o->reorth_passes = 2;
   o->replace_every = 25;
   for (int k = 0; k < GPFVM_MAX_DIM; ++k) o->coarsen[k] = 1;
+  o->method = GPFVM_METHOD_ITERGP;
 }
 
 // ---------------------------------------------------------------------------
@@ -534,8 +535,8 @@ static int check_assemble_args(const gpfvm_ibvp* p, const gpfvm_assemble_opts* o
   if (rc) return rc;
   if (opts && (opts->max_iter < 1 || opts->max_iter > (1 << 20)))
     return fail_static(GPFVM_E_INVALID, "max_iter out of range");
-  if (opts && opts->tile != GPFVM_TILE_FP32)
-    return fail_static(GPFVM_E_INVALID, "tile: only GPFVM_TILE_FP32 is provided");
+  if (opts && opts->tile != GPFVM_TILE_FP32 && opts->tile != GPFVM_TILE_BF16X3)
+    return fail_static(GPFVM_E_INVALID, "tile: GPFVM_TILE_FP32 or GPFVM_TILE_BF16X3");
   return GPFVM_OK;
 }
 
@@ -616,11 +617,13 @@ int gpfvm::get_full_ops(gpfvm_handle* h, int nrhs, gpfvm_opset** out) {
   return GPFVM_OK;
 }
 
-extern "C" int gpfvm_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec, void* stream) {
+extern "C" int gpfvm_matvec(gpfvm_handle* h, int nrhs, const void* x, void* y, int dtype, int prec, void* stream) {
   if (!h) return fail_static(GPFVM_E_INVALID, "handle is NULL");
   if (nrhs < 1 || nrhs > 4096 || !x || !y) { h->err = "matvec: bad nrhs or NULL buffer"; return GPFVM_E_INVALID; }
   if (prec != GPFVM_PREC_FP64 && prec != GPFVM_PREC_MIXED) { h->err = "matvec: bad prec"; return GPFVM_E_INVALID; }
-  const size_t bytes = (size_t)h->n * nrhs * sizeof(double);
+  if (dtype != GPFVM_DTYPE_F64 && dtype != GPFVM_DTYPE_F32) { h->err = "matvec: bad dtype"; return GPFVM_E_INVALID; }
+  const size_t esz = dtype == GPFVM_DTYPE_F64 ? sizeof(double) : sizeof(float);
+  const size_t bytes = (size_t)h->n * nrhs * esz;
   if ((const char*)x < (const char*)y + bytes && (const char*)y < (const char*)x + bytes) {
     h->err = "matvec: x and y overlap";
     return GPFVM_E_INVALID;
@@ -630,7 +633,9 @@ extern "C" int gpfvm_matvec(gpfvm_handle* h, int nrhs, const double* x, double* 
   gpfvm_opset* os = nullptr;
   int rc = get_full_ops(h, nrhs, &os);
   if (rc) return rc;
-  HIPCHK(h, hipMemcpyAsync(os->XF, x, bytes, hipMemcpyDeviceToDevice, s));
+  const i64 nn = h->n * nrhs;
+  if (dtype == GPFVM_DTYPE_F64) HIPCHK(h, hipMemcpyAsync(os->XF, x, bytes, hipMemcpyDeviceToDevice, s));
+  else HIPCHK(h, launch_copy_f32_to_f64((const float*)x, os->XF, nn, s));
   if (h->nb > 0) {
     HIPCHK(h, run_plan(os->bp, s));
     HIPCHK(h, launch_gemm_stage(F64, os->gbb_t, s));
@@ -639,7 +644,7 @@ extern "C" int gpfvm_matvec(gpfvm_handle* h, int nrhs, const double* x, double* 
   if (prec == GPFVM_PREC_FP64) {
     HIPCHK(h, run_plan(os->pp, s));
   } else {
-    // volume block through the float32 (mixed) plan, everything else float64
+    // volume block through the low-precision plan (the handle's tile format), everything else float64
     gpfvm_sop* so = nullptr;
     rc = get_sop(h, nrhs, F32, &so);
     if (rc) return rc;
@@ -651,7 +656,8 @@ extern "C" int gpfvm_matvec(gpfvm_handle* h, int nrhs, const double* x, double* 
       HIPCHK(h, launch_copy_f32_to_f64((const float*)so->Y32 + r * N, os->YF + r * n + nb, N, s));
   }
   if (h->nb > 0) HIPCHK(h, run_plan(os->pb, s));
-  HIPCHK(h, hipMemcpyAsync(y, os->YF, bytes, hipMemcpyDeviceToDevice, s));
+  if (dtype == GPFVM_DTYPE_F64) HIPCHK(h, hipMemcpyAsync(y, os->YF, bytes, hipMemcpyDeviceToDevice, s));
+  else HIPCHK(h, launch_copy_f64_to_f32(os->YF, (float*)y, nn, s));
   return GPFVM_OK;
 }
 

@@ -58,7 +58,10 @@ struct GemmDesc {
   Seg seg[MAXSEG];
 };
 
-enum Elt { F64 = 0, F32 = 1 };
+// Element type of a plan: float64; float32 on the float32 matrix cores; float32
+// in HBM with the products on the bfloat16 matrix cores, each operand split
+// into three bfloat16 slices (float32 accuracy, lowp.hip).
+enum Elt { F64 = 0, F32 = 1, F32B = 2 };
 
 // One kernel launch: a set of descriptors whose outputs do not overlap.
 // Streaming products carried by a GEMM stage's launch as extra workgroups
@@ -112,7 +115,7 @@ struct Stage {
   int slot1 = 0;   // some segment accumulates into slot 1
   Rider rider;     // launched with the stage (kind RIDE_NONE: none)
 };
-enum GemmKind { GEMM_SPLITK = 0, GEMM_LDS32 = 1, GEMM_LDS64 = 2, GEMM_LDS16 = 3 };
+enum GemmKind { GEMM_SPLITK = 0, GEMM_LDS32 = 1, GEMM_LDS64 = 2, GEMM_LDS16 = 3, GEMM_BF16S32 = 4, GEMM_BF16S64 = 5 };
 
 // Point-block correction of the volume system as Q^T Q with Q = L^{-1} G_bp
 // (n_b x N, row-major), used for one right-hand side when Q is small enough
@@ -227,6 +230,7 @@ struct GramTerm {          // merged volume-Gram term
 hipError_t launch_factor(int kind, int kq, int p, int q, int n1, const double* a1, int n2, const double* a2,
                          double ell, double scale, double* out, i64 ld, hipStream_t s);
 hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s);   // kernel chosen by st.kind
+hipError_t launch_gemm_bf16s(const Stage& st, hipStream_t s);           // GEMM_BF16S32 / 64 (lowp.hip)
 hipError_t launch_scale(Elt elt, const void* src, i64 src_stride, const void* coef, void* dst, i64 dst_stride, i64 n,
                         int nrhs, hipStream_t s);
 hipError_t launch_axpby(i64 n, double a, const double* x, double b, double* y, hipStream_t s);
@@ -373,6 +377,7 @@ struct gpfvm_handle {
   double* Dd = nullptr;            // directions: column j at Dd + j * N
   double* Qd = nullptr;            // S applied to the directions (two-pass projection)
   bool sd_exact = false;           // Qd holds the float64 S D of every stored direction
+  bool cg_only = false;            // the last solve was plain CG: weights only, no directions
   double* eta = nullptr;           // max_iter
   double* vec = nullptr;           // solver vectors (r, s, z, d, ...), 8 * N
   double* aux = nullptr;           // dot partials and coefficients

@@ -248,9 +248,14 @@ hipError_t upload_stages(std::vector<Stage>& stages, Arena& arena, hipStream_t s
   host.reserve(total);
   for (auto& st : stages) {
     choose_kernel(st);
+    if (elt == F32B) {               // split-bfloat16 GEMM: 64x64 tiles where there are enough, else 32x32
+      i64 t64 = 0;
+      for (auto& D : st.descs) t64 += (i64)((D.M + 63) / 64) * ((D.N + 63) / 64) * D.batch;
+      st.kind = t64 >= 256 ? GEMM_BF16S64 : GEMM_BF16S32;
+    }
     st.tiles = 0;
     for (auto& D : st.descs) {
-      const int t = st.kind == GEMM_LDS64 ? 64 : st.kind == GEMM_LDS16 ? 16 : 32;
+      const int t = (st.kind == GEMM_LDS64 || st.kind == GEMM_BF16S64) ? 64 : st.kind == GEMM_LDS16 ? 16 : 32;
       D.tiles_m = (D.M + t - 1) / t;
       D.tiles_n = (D.N + t - 1) / t;
       D.tile_begin = st.tiles;

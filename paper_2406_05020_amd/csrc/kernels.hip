@@ -1030,6 +1030,7 @@ hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
     return launch_gemm_stage(elt, plain, s);
   }
   if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
+  if (elt == F32B) return launch_gemm_bf16s(st, s);
   const int nd = (int)st.descs.size();
   if (st.kind == GEMM_LDS64) {
     if (elt == F64) launch_lds<double, 64, 1>(st, nd, s); else launch_lds<float, 64, 1>(st, nd, s);

@@ -245,6 +245,49 @@ __global__ void k_point_grid(const PGMeta* __restrict__ meta, int nb, i64 x0, i6
 
 unsigned nblk(i64 n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
+// C[j][c] /= eta[j] for a rows x cols row-major block
+__global__ void k_rowscale(int rows, int cols, double* __restrict__ C, const double* __restrict__ eta) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (i64)rows * cols) C[i] /= eta[i / cols];
+}
+
+// Plain CG (Sec. 4.1), device-side scalars: scal[CG_RR + (it & 1)] holds r.r of
+// the current iteration, scal[CG_PAP] = p.S p, scal[3] = b.b, scal[4] = tol^2.
+// flag[0]: 0 running, 1 converged, 2 breakdown (p.S p <= 0); flag[1]: updates made.
+constexpr int CG_RR = 5, CG_PAP = 7;
+
+// x += a p ; r -= a S p,  a = r.r / p.S p
+__global__ void k_cg_step(i64 N, const double* __restrict__ p, const double* __restrict__ Sp, double* __restrict__ x,
+                          double* __restrict__ r, const double* __restrict__ scal, int slot, int* __restrict__ flag) {
+  if (flag[0] != 0) return;
+  const double pap = scal[CG_PAP];
+  if (!(pap > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 2;
+    return;
+  }
+  const double a = scal[CG_RR + slot] / pap;
+  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) {
+    x[k] += a * p[k];
+    r[k] -= a * Sp[k];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) flag[1] += 1;
+}
+
+// stopping test on the new r.r, else p = r + (r.r_new / r.r) p
+__global__ void k_cg_dir(i64 N, const double* __restrict__ r, double* __restrict__ p, const double* __restrict__ scal,
+                         int slot, int* __restrict__ flag) {
+  if (flag[0] != 0) return;
+  const double rr = scal[CG_RR + slot], rn = scal[CG_RR + (slot ^ 1)];
+  if (rn <= scal[4] * scal[3]) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 1;
+    return;
+  }
+  const double beta = rn / rr;
+  const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) p[k] = r[k] + beta * p[k];
+}
+
 }  // namespace
 
 GemmDesc gpfvm::desc1(void* C, i64 c_rs, const void* A, i64 a_rs, i64 a_cs, const void* B, i64 b_rs, i64 b_cs, int M,
@@ -486,10 +529,12 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
   auto& tab = (elt == F64) ? h->sops : h->sops32;
   auto it = tab.find(nrhs);
   if (it != tab.end()) { *out = it->second.get(); return GPFVM_OK; }
-  if (elt == F32 && h->op_pp32.terms.empty()) {
+  if (elt != F64 && h->op_pp32.terms.empty()) {
     int rc = build_ops32(h);
     if (rc) return rc;
   }
+  // the low-precision volume plan: float32 MFMA, or split-bfloat16 MFMA (float32 storage)
+  const Elt lowp = h->tile == GPFVM_TILE_BF16X3 ? F32B : F32;
   auto so = std::make_unique<gpfvm_sop>();
   so->nrhs = nrhs;
   so->elt = elt;
@@ -514,7 +559,7 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
     so->Y32 = h->arena.alloc((size_t)N * nrhs * 4);
     if (!so->X32 || !so->Y32) { h->err = "out of device memory (S operator)"; return GPFVM_E_NOMEM; }
     std::vector<KronOp> pp{h->op_pp32};
-    rc = compile_kron_list(pp, F32, nrhs, so->X32, N, so->Y32, N, h->cellc_f, h->cellc, 0.0, so->X32, h->sig_pde,
+    rc = compile_kron_list(pp, lowp, nrhs, so->X32, N, so->Y32, N, h->cellc_f, h->cellc, 0.0, so->X32, h->sig_pde,
                            1, h->arena, h->stream, so->pp, h->err);
   }
   if (rc) return rc;
@@ -748,7 +793,7 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
 // the action vector, so no vector is copied inside the loop.
 static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int start, int max_new, double tol,
                       int check_every, int passes, int replace_every, hipStream_t s, int* n_out, int* state_out,
-                      const std::function<int(int)>* action = nullptr) {
+                      const std::function<int(int)>* action = nullptr, bool res64 = false) {
   const i64 N = h->N;
   gpfvm_sop* so = nullptr;
   int rc = get_sop(h, 1, elt, &so);
@@ -765,16 +810,25 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
     if (!h->Qd) { h->err = "out of device memory (S D store; lower max_iter)"; return GPFVM_E_NOMEM; }
   }
   const int end = std::min(h->max_iter, start + max_new);
-  // r = b - S v ; X = r
+  // r = b - S v ; X = r   (res64: S in float64 whatever the loop's operator, the
+  // refinement residual of the mixed-precision blocks)
   HIPCHK(h, hipMemsetAsync(h->flag, 0, 16 * sizeof(int), s));
-  HIPCHK(h, hipMemcpyAsync(X, v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIPCHK(h, apply_sop(h, so, s));
+  const double* Y0 = Y;
+  if (res64 && elt != F64) {
+    double* y64 = h->vec + 6 * N;
+    rc = apply_S(h, F64, v, y64, s);
+    if (rc) return rc;
+    Y0 = y64;
+  } else {
+    HIPCHK(h, hipMemcpyAsync(X, v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, apply_sop(h, so, s));
+  }
   HIPCHK(h, launch_dot(N, b, b, dotp, h->scal + 3, s));
   {
     const double t2 = action ? -1.0 : tol * tol;     // caller's actions: no stopping test
     HIPCHK(h, hipMemcpyAsync(h->scal + 4, &t2, sizeof(double), hipMemcpyHostToDevice, s));
   }
-  hipLaunchKernelGGL(k_resid2, dim3(nblk(N)), dim3(256), 0, s, N, b, Y, r, X, (const int*)h->flag);
+  hipLaunchKernelGGL(k_resid2, dim3(nblk(N)), dim3(256), 0, s, N, b, Y0, r, X, (const int*)h->flag);
   int i = start;
   int hflag[2] = {0, 0};
   // coef = partial sums of D^T rhs over the first nd stored directions; the column update adds
@@ -889,6 +943,132 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
   return GPFVM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Float64 re-stabilisation of a block of directions found with the
+// low-precision operator (the mixed path).  Directions [i0, i0 + n) of Dd are
+// S-conjugated in float64 against the stored ones, which are exact in float64:
+//   B = block, SB = S B (float64 operator, the block as nrhs = m right-hand sides);
+//   twice: C = eta^-1 o (D^T SB), B -= D C, SB -= (S D) C;
+//   P = B^T S B = L L^T (the small projected Cholesky), B <- B L^{-T}, SB <- SB L^{-T},
+// so the block's directions are S-orthonormal (eta = 1) in float64 and the
+// combined posterior is exact for the space they span.  The weights become
+// v = v0 + B (B^T b) (v0: the weights before the block).  Returns GPFVM_E_NOTPD
+// if P is not numerically positive definite (nothing stored then).
+// ---------------------------------------------------------------------------
+static int restabilise_block(gpfvm_handle* h, gpfvm_sop* sm, int i0, int n, const double* v0, Arena& tmp,
+                             hipStream_t s) {
+  const i64 N = h->N;
+  const int m = sm->nrhs;
+  double* X = (double*)sm->X;
+  double* Y = (double*)sm->Y;
+  double* Cb = (double*)tmp.alloc((size_t)std::max(i0, 1) * n * sizeof(double));
+  double* P = (double*)tmp.alloc((size_t)n * n * sizeof(double));
+  double* Pi = (double*)tmp.alloc((size_t)n * n * sizeof(double));
+  double* wc = (double*)tmp.alloc((size_t)n * sizeof(double));
+  if (!Cb || !P || !Pi || !wc) { h->err = "out of device memory (re-stabilisation)"; return GPFVM_E_NOMEM; }
+  HIPCHK(h, hipMemcpyAsync(X, h->Dd + (i64)i0 * N, (size_t)n * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (n < m) HIPCHK(h, launch_fill(X + (i64)n * N, 0.0, (i64)(m - n) * N, s));
+  HIPCHK(h, apply_sop(h, sm, s));                                       // Y = S X (float64)
+  std::vector<Stage> st;
+  if (i0 > 0) {
+    // C = D^T SB (i0 x n), then B -= D (C / eta), SB -= (S D) (C / eta)
+    Stage c1, c2;
+    c1.descs.push_back(desc1(Cb, n, h->Dd, N, 1, Y, 1, N, i0, n, (int)N, 1.0, 0.0, 0));
+    c2.descs.push_back(desc1(X, N, Cb, 1, n, h->Dd, N, 1, n, (int)N, i0, -1.0, 1.0, 0));
+    c2.descs.push_back(desc1(Y, N, Cb, 1, n, h->Qd, N, 1, n, (int)N, i0, -1.0, 1.0, 0));
+    st.push_back(c1);
+    st.push_back(c2);
+  }
+  {
+    Stage pg, up;
+    pg.descs.push_back(desc1(P, n, X, N, 1, Y, 1, N, n, n, (int)N, 1.0, 0.0, 0));   // P = B (S B)^T
+    st.push_back(pg);
+    // D_block = L^{-1} B, (S D)_block = L^{-1} SB   (rows of B are the directions)
+    up.descs.push_back(desc1(h->Dd + (i64)i0 * N, N, Pi, n, 1, X, N, 1, n, (int)N, n, 1.0, 0.0, 1));
+    up.descs.push_back(desc1(h->Qd + (i64)i0 * N, N, Pi, n, 1, Y, N, 1, n, (int)N, n, 1.0, 0.0, 1));
+    st.push_back(up);
+    Stage wb, vu;
+    wb.descs.push_back(desc1(wc, 1, h->Dd + (i64)i0 * N, N, 1, h->bS, 1, 1, n, 1, (int)N, 1.0, 0.0, 0));
+    GemmDesc V = desc1(h->v, N, wc, n, 1, h->Dd + (i64)i0 * N, N, 1, 1, (int)N, n, 1.0, 0.0, 0);
+    V.X = v0; V.x_rs = N; V.x_cs = 1; V.gamma = 1.0;                    // v = v0 + B (B^T b)
+    vu.descs.push_back(V);
+    st.push_back(wb);
+    st.push_back(vu);
+  }
+  if (upload_stages(st, tmp, s) != hipSuccess) { h->err = "re-stabilisation: descriptor check/upload failed"; return GPFVM_E_HIP; }
+  size_t k = 0;
+  if (i0 > 0) {
+    for (int pass = 0; pass < 2; ++pass) {
+      HIPCHK(h, launch_gemm_stage(F64, st[0], s));
+      hipLaunchKernelGGL(k_rowscale, dim3(nblk((i64)i0 * n)), dim3(256), 0, s, i0, n, Cb, (const double*)h->eta);
+      HIPCHK(h, launch_gemm_stage(F64, st[1], s));
+    }
+    k = 2;
+  }
+  HIPCHK(h, launch_gemm_stage(F64, st[k], s));                          // P
+  {
+    std::string e;
+    const int rc = cholesky_and_inverse(P, Pi, n, tmp, s, e);
+    if (rc == GPFVM_E_NOTPD) { h->err = "re-stabilisation: projected block Gram is not positive definite"; return rc; }
+    if (rc) { h->err = e; return rc; }
+  }
+  HIPCHK(h, launch_gemm_stage(F64, st[k + 1], s));                      // directions and S D
+  HIPCHK(h, launch_fill(h->eta + i0, 1.0, n, s));
+  HIPCHK(h, launch_gemm_stage(F64, st[k + 2], s));                      // B^T b
+  HIPCHK(h, launch_gemm_stage(F64, st[k + 3], s));                      // v
+  return GPFVM_OK;
+}
+
+// Plain conjugate gradients on the volume system in float64 (Sec. 4.1): x, r
+// and p only (no stored directions).  p lives in the operator's input buffer.
+static int cg_run(gpfvm_handle* h, const double* b, double* x, int max_iter, double tol, int check_every,
+                  hipStream_t s, int* iters_out, int* state_out) {
+  const i64 N = h->N;
+  gpfvm_sop* so = nullptr;
+  int rc = get_sop(h, 1, F64, &so);
+  if (rc) return rc;
+  double* p = (double*)so->X;
+  const double* Sp = (const double*)so->Y;
+  double* r = h->vec;
+  double* dotp = h->aux;
+  HIPCHK(h, hipMemsetAsync(h->flag, 0, 16 * sizeof(int), s));
+  HIPCHK(h, launch_fill(x, 0.0, N, s));
+  HIPCHK(h, hipMemcpyAsync(r, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(p, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, launch_dot(N, b, b, dotp, h->scal + 3, s));
+  HIPCHK(h, launch_dot(N, b, b, dotp, h->scal + CG_RR, s));
+  {
+    const double t2 = tol * tol;
+    HIPCHK(h, hipMemcpyAsync(h->scal + 4, &t2, sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  int hflag[2] = {0, 0};
+  double hs[5];
+  HIPCHK(h, hipMemcpyAsync(hs, h->scal, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (hs[3] == 0.0) { *iters_out = 0; *state_out = 1; return GPFVM_OK; }
+  int it = 0;
+  while (it < max_iter) {
+    const int end = std::min(max_iter, it + std::max(1, check_every));
+    for (; it < end; ++it) {
+      const int slot = it & 1;
+      HIPCHK(h, apply_sop(h, so, s));                                   // S p
+      HIPCHK(h, launch_dot(N, p, Sp, dotp, h->scal + CG_PAP, s));
+      hipLaunchKernelGGL(k_cg_step, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)p, Sp, x, r,
+                         (const double*)h->scal, slot, h->flag);
+      HIPCHK(h, launch_dot(N, r, r, dotp, h->scal + CG_RR + (slot ^ 1), s));
+      hipLaunchKernelGGL(k_cg_dir, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)r, p, (const double*)h->scal,
+                         slot, h->flag);
+    }
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(hflag, h->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (hflag[0] != 0) break;
+  }
+  *iters_out = hflag[1];
+  *state_out = hflag[0];
+  return GPFVM_OK;
+}
+
 static int rel_res(gpfvm_handle* h, const double* v, double* out, hipStream_t s) {
   const i64 N = h->N;
   double* y = h->vec + 3 * N;
@@ -916,7 +1096,7 @@ static int full_residual(gpfvm_handle* h, double* out, hipStream_t s) {
   double* g = (double*)tmp.alloc(n * sizeof(double));
   if (!a || !g) { tmp.release(); h->err = "out of device memory"; return GPFVM_E_NOMEM; }
   int rc = gpfvm_weights(h, a, s);
-  if (!rc) rc = gpfvm_matvec(h, 1, a, g, GPFVM_PREC_FP64, s);
+  if (!rc) rc = gpfvm_matvec(h, 1, a, g, GPFVM_DTYPE_F64, GPFVM_PREC_FP64, s);
   if (!rc) {
     double* dotp = h->aux;
     hipError_t e = launch_axpby(n, 1.0, h->yobs, -1.0, g, s);
@@ -1083,13 +1263,25 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
   gpfvm_default_solve_opts(&def);
   if (!o) o = &def;
   if (o->prec != GPFVM_PREC_FP64 && o->prec != GPFVM_PREC_MIXED) { h->err = "solve: bad prec"; return GPFVM_E_INVALID; }
-  if (o->tile != GPFVM_TILE_FP32) { h->err = "solve: only GPFVM_TILE_FP32 is provided"; return GPFVM_E_INVALID; }
-  if (o->max_iter < 0 || !(o->tol >= 0) || o->check_every < 1 || o->max_outer < 1 || !(o->inner_tol > 0) ||
-      o->reorth_passes < 1 || o->reorth_passes > 2 || o->replace_every < 1) {
+  if (o->method != GPFVM_METHOD_ITERGP && o->method != GPFVM_METHOD_CG) { h->err = "solve: bad method"; return GPFVM_E_INVALID; }
+  if (o->prec == GPFVM_PREC_MIXED && o->tile != h->tile) {
+    h->err = "solve: the mixed path's tile format must be the one given at assemble";
+    return GPFVM_E_INVALID;
+  }
+  if (o->max_iter < 0 || !(o->tol >= 0) || o->check_every < 1 || o->max_outer < 1 || o->block < 1 ||
+      o->block > GPFVM_MAX_BLOCK || o->reorth_passes < 1 || o->reorth_passes > 2 || o->replace_every < 1) {
     h->err = "solve: bad options";
     return GPFVM_E_INVALID;
   }
-  if (o->resume && !h->solved) { h->err = "solve: nothing to resume"; return GPFVM_E_STATE; }
+  if (o->prec == GPFVM_PREC_MIXED && o->reorth_passes != 2) {
+    h->err = "solve: the mixed path needs reorth_passes = 2";
+    return GPFVM_E_INVALID;
+  }
+  if (o->method == GPFVM_METHOD_CG && (o->prec != GPFVM_PREC_FP64 || o->resume)) {
+    h->err = "solve: method CG is float64 and does not resume";
+    return GPFVM_E_INVALID;
+  }
+  if (o->resume && (!h->solved || h->cg_only)) { h->err = "solve: nothing to resume"; return GPFVM_E_STATE; }
   // coarse warm start: factors >= 1 dividing the cell counts; all 1 = off
   i64 n_coarse = 1;
   bool coarse = false;
@@ -1100,7 +1292,7 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
     coarse |= (f > 1);
   }
   if (coarse) {
-    if (o->resume || o->prec != GPFVM_PREC_FP64 || o->reorth_passes != 2) {
+    if (o->resume || o->prec != GPFVM_PREC_FP64 || o->reorth_passes != 2 || o->method != GPFVM_METHOD_ITERGP) {
       h->err = "solve: the coarse warm start needs a fresh float64 solve with reorth_passes = 2";
       return GPFVM_E_INVALID;
     }
@@ -1126,9 +1318,19 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
       h->iters = n_dirs_coarse;
     }
   }
-  if (o->prec != GPFVM_PREC_FP64 || o->reorth_passes != 2) h->sd_exact = false;
+  // S D holds float64 S D after float64 two-pass iterations and after the mixed
+  // path's re-stabilised blocks, not after one-pass iterations
+  if (o->reorth_passes != 2) h->sd_exact = false;
   int state = 0, outer = 0;
-  if (o->prec == GPFVM_PREC_FP64) {
+  h->cg_only = false;
+  int cg_iters = 0;
+  if (o->method == GPFVM_METHOD_CG) {
+    rc = cg_run(h, h->bS, h->v, o->max_iter, o->tol, o->check_every, s, &cg_iters, &state);
+    if (rc) return rc;
+    h->iters = 0;
+    h->cg_only = true;
+    h->sd_exact = false;
+  } else if (o->prec == GPFVM_PREC_FP64) {
     int nd = h->iters;
     const int start0 = h->iters;
     rc = itergp_run(h, F64, h->bS, h->v, h->iters, o->max_iter, o->tol, o->check_every, o->reorth_passes,
@@ -1151,41 +1353,62 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
       h->iters = nd;
     }
   } else {
-    // mixed-precision iterative refinement: float64 residual of the volume
-    // system, IterGP with the mixed operator for the correction; all
-    // directions stay in one conjugate set so the combined posterior remains
-    // defined.  A correction that does not lower the float64 residual is
-    // undone and the refinement stops (the iterate never gets worse).
-    double* x = h->v;
-    double* rr = h->vec + 6 * N;      // outer residual
-    double* dx = h->vec + 7 * N;      // correction
-    double res = 0;
-    rc = rel_res(h, x, &res, s);
+    // Mixed precision: blocks of up to `block` IterGP iterations with the
+    // low-precision operator (its directions projected twice against every
+    // stored direction, in float64), each started from the float64 residual
+    // b - S v and followed by the float64 re-stabilisation of its directions
+    // (restabilise_block: float64 S D, the small projected Cholesky, weights
+    // v = C b).  The float64 residual at the start of the next block is the
+    // refinement step.  If a block cannot add a direction (eta <= 0 at once,
+    // or a block Gram that is not positive definite) the solve continues with
+    // the float64 operator.
+    gpfvm_sop* sm = nullptr;
+    rc = get_sop(h, o->block, F64, &sm);
     if (rc) return rc;
-    for (outer = 0; outer < o->max_outer; ++outer) {
-      if (res <= o->tol || h->iters >= std::min(h->max_iter, o->max_iter)) break;
-      rc = apply_S(h, F64, x, rr, s);
-      if (rc) return rc;
-      HIPCHK(h, launch_axpby(N, 1.0, h->bS, -1.0, rr, s));
-      HIPCHK(h, launch_fill(dx, 0.0, N, s));
+    if (!h->Qd) {
+      h->Qd = (double*)h->arena.alloc((size_t)N * h->max_iter * sizeof(double));
+      if (!h->Qd) { h->err = "out of device memory (S D store; lower max_iter)"; return GPFVM_E_NOMEM; }
+    }
+    Arena tmp;
+    tmp.cache = h->arena.cache;
+    double* vsave = (double*)tmp.alloc((size_t)N * sizeof(double));
+    if (!vsave) { tmp.release(); h->err = "out of device memory (mixed path)"; return GPFVM_E_NOMEM; }
+    const int start0 = h->iters, end = std::min(h->max_iter, start0 + o->max_iter);
+    bool fall_back = false;
+    for (outer = 0; outer < o->max_outer && h->iters < end; ++outer) {
+      HIPCHK(h, hipMemcpyAsync(vsave, h->v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
       int nd = h->iters;
-      rc = itergp_run(h, F32, rr, dx, h->iters, std::min(h->max_iter, o->max_iter) - h->iters, o->inner_tol,
-                      o->check_every, o->reorth_passes, o->replace_every, s, &nd, &state);
-      if (rc) return rc;
-      HIPCHK(h, launch_axpby(N, 1.0, dx, 1.0, x, s));
-      double res_new = 0;
-      rc = rel_res(h, x, &res_new, s);
-      if (rc) return rc;
-      if (!(res_new < res)) {                // no progress: undo it and drop its directions
-        HIPCHK(h, launch_axpby(N, -1.0, dx, 1.0, x, s));
-        state = (state == 2) ? 2 : 3;
+      rc = itergp_run(h, F32, h->bS, h->v, h->iters, std::min(o->block, end - h->iters), o->tol, o->check_every, 2,
+                      1 << 30, s, &nd, &state, nullptr, true);
+      if (rc) { tmp.release(); return rc; }
+      const int nnew = nd - h->iters;
+      if (nnew == 0) {
+        HIPCHK(h, hipMemcpyAsync(h->v, vsave, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        fall_back = (state != 1);               // converged at the block's float64 residual, or stuck
         break;
       }
-      res = res_new;
+      rc = restabilise_block(h, sm, h->iters, nnew, vsave, tmp, s);
+      if (rc == GPFVM_E_NOTPD) {               // drop the block
+        HIPCHK(h, hipMemcpyAsync(h->v, vsave, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        fall_back = true;
+        break;
+      }
+      if (rc) { tmp.release(); return rc; }
       h->iters = nd;
-      if (state == 2) break;
+      state = 0;
     }
-    state = (res <= o->tol) ? 1 : (state == 2 ? 2 : 3);
+    tmp.release();
+    if (fall_back && h->iters < end) {
+      int nd = h->iters;
+      rc = itergp_run(h, F64, h->bS, h->v, h->iters, end - h->iters, o->tol, o->check_every, 2, o->replace_every, s,
+                      &nd, &state);
+      if (rc) return rc;
+      h->iters = nd;
+    }
+    double res = 0;
+    rc = rel_res(h, h->v, &res, s);
+    if (rc) return rc;
+    state = (o->tol > 0 && res <= o->tol) ? 1 : (state == 2 ? 2 : 3);
   }
   h->solved = true;
   double rs = 0, rf = 0;
@@ -1194,7 +1417,7 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
   rc = full_residual(h, &rf, s);
   if (rc) return rc;
   if (info) {
-    info->iters = h->iters;
+    info->iters = h->cg_only ? cg_iters : h->iters;
     info->outer = outer;
     info->rel_res = rs;
     info->rel_res_full = rf;
@@ -1408,6 +1631,10 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
     M *= n[i];
   }
   if (!h->solved) { h->err = "posterior: no solve yet"; return GPFVM_E_STATE; }
+  if (var && h->cg_only) {
+    h->err = "posterior: a CG solve stores no directions; the variance needs method ITERGP";
+    return GPFVM_E_STATE;
+  }
   hipStream_t s = (hipStream_t)stream;
   h->stream = s;
   const int d = h->d;

@@ -84,7 +84,7 @@ def test_factor_argument_checks(G):
 def test_null_handle_calls_are_rejected(G):
     import ctypes as C
     L = G.lib()
-    assert L.gpfvm_matvec(None, 1, None, None, 0, None) == G.E_INVALID
+    assert L.gpfvm_matvec(None, 1, None, None, 0, 0, None) == G.E_INVALID
     assert L.gpfvm_solve(None, None, None, None) == G.E_INVALID
     assert L.gpfvm_posterior(None, 2, None, None, None, None, None) == G.E_INVALID
     L.gpfvm_destroy(None)   # accepted
