@@ -230,6 +230,22 @@ int gpfvm_schur_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, in
  * plan (the handle's tile format) through internal buffers.  Errors: INVALID, NOMEM, HIP. */
 int gpfvm_volume_matvec(gpfvm_handle* h, int nrhs, const double* x, double* y, int prec, void* stream);
 
+/* The float64 volume-Gram matvec of gpfvm_volume_matvec (y = (L_V k L_V' +
+ * Sigma_V) x, nrhs right-hand sides), for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the call makes no hipMalloc, hipFree or other device
+ * allocation.  Its Kronecker-plan intermediates and GEMM descriptors live in
+ * a static device scratch of GPFVM_NOALLOC_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends; the plan is rebuilt in it on
+ * every call (a host-side compile and one descriptor upload, which
+ * synchronises `stream`), and nothing in it needs to start at zero.  Every
+ * call on a GPU shares that GPU's scratch: calls that overlap on one GPU (from
+ * several threads, or on several streams without ordering) race.  x, y:
+ * device, N*nrhs doubles, no overlap.  Errors: INVALID (also when the plan
+ * for this problem and nrhs does not fit the scratch), HIP. */
+#define GPFVM_NOALLOC_SCRATCH_BYTES (32LL << 20)
+int gpfvm_volume_matvec_noalloc(gpfvm_handle* h, int nrhs, const double* x, double* y, void* stream);
+
 /* Representer weights alpha = G^{-1} y (Sec. 4, representer weights): exact
  * conditioning on the points, then IterGP with CG actions on the volume
  * observations (Sec. 4.1-4.2).  The state (weights, directions, eta) stays in

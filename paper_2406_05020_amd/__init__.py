@@ -89,6 +89,7 @@ SYMBOLS = {
     "gpfvm_assemble": ([C.POINTER(IBVPStruct), C.POINTER(AssembleOpts), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "gpfvm_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p], C.c_int),
     "gpfvm_volume_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "gpfvm_volume_matvec_noalloc": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "gpfvm_schur_matvec": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
     "gpfvm_solve": ([C.c_void_p, C.POINTER(SolveOpts), C.POINTER(SolveInfo), C.c_void_p], C.c_int),
     "gpfvm_posterior": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(_dp), C.c_void_p, C.c_void_p,
@@ -244,6 +245,12 @@ def volume_matvec(h, x, y, nrhs: int = 1, prec: int = PREC_FP64, stream=None) ->
     """y = (L_V k L_V' + Sigma_V) x (volume block only)."""
     _check(lib().gpfvm_volume_matvec(h, nrhs, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), prec,
                                      _stream(stream)), h)
+
+
+def volume_matvec_noalloc(h, x, y, nrhs: int = 1, stream=None) -> None:
+    """volume_matvec in float64 with no device allocation (static device scratch)."""
+    _check(lib().gpfvm_volume_matvec_noalloc(h, nrhs, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                             _stream(stream)), h)
 
 
 def schur_matvec(h, x, y, nrhs: int = 1, prec: int = PREC_FP64, stream=None) -> None:

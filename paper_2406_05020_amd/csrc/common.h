@@ -150,6 +150,10 @@ struct Arena {
   size_t slab_left = 0;
   i64 bytes = 0;                   // device bytes held (slabs counted whole)
   DeviceCache* cache = nullptr;    // when set, blocks come from / go back to it
+  // fixed mode (fixed != null): allocations are carved from [fixed, fixed + fixed_cap)
+  // and nothing is ever allocated from or returned to the runtime
+  char* fixed = nullptr;
+  size_t fixed_cap = 0, fixed_used = 0;
   void* alloc(size_t nbytes);      // returns nullptr on failure
   void release();
 };

@@ -116,6 +116,14 @@ void DeviceCache::release_all() {
 void* Arena::alloc(size_t nbytes) {
   if (nbytes == 0) nbytes = 256;
   nbytes = (nbytes + 255) & ~(size_t)255;
+  if (fixed) {
+    if (nbytes > fixed_cap - fixed_used) return nullptr;
+    void* p = fixed + fixed_used;
+    fixed_used += nbytes;
+    regs.push_back(p);
+    register_range(p, nbytes);
+    return p;
+  }
   auto block = [&](size_t n) -> void* {
     void* q = nullptr;
     if (cache) q = cache->get(n);
@@ -148,6 +156,7 @@ void* Arena::alloc(size_t nbytes) {
 void Arena::release() {
   for (void* p : regs) unregister_range(p);
   regs.clear();
+  fixed_used = 0;
   for (void* p : ptrs) {
     if (cache) cache->put(p);
     else (void)hipFree(p);
