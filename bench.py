@@ -50,6 +50,10 @@ def parse():
                          "64^3 heat volume matvec with 64")
     ap.add_argument("--large-timing", action="store_true",
                     help="only time the wave 64x128x128 problem: assemble, 200 IterGP iterations, posterior")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="only the advection-diffusion block with its mixed-precision measurement (profiling)")
+    ap.add_argument("--mixed-steps", type=int, default=5,
+                    help="steps of the advection-diffusion solve on the mixed-precision path (0 = skip)")
     ap.add_argument("--coarse-steps", type=int, default=5,
                     help="steps of the same solve with the coarse-scheme warm start (8 x 8 fine cells per "
                          "coarse cell), reported beside the headline (0 = skip)")
@@ -117,6 +121,10 @@ def main():
             out.update(extra_rooflines())
         out["copy_calibration"] = copy_calibration(args.copy_bytes)
         print(json.dumps(out), flush=True)
+        return
+
+    if args.mixed_only:
+        print(json.dumps({"advdiff_128x128": c2_block(args, G, W, torch.cuda.current_stream())}), flush=True)
         return
 
     # ---- headline: wave 64x128x128 + 16384 points, assemble + 200 IterGP + posterior ----
@@ -260,6 +268,60 @@ def c2_block(args, G, W, stream):
            "roofline_64rhs": roofline_volume(p, B=64, reps=args.mv_reps)}
     if args.coarse_steps > 0:
         out["coarse_warm_start"] = coarse_bench(p, (8, 8), args.coarse_steps, stream, mean, var)
+    if args.mixed_steps > 0:
+        out["mixed"] = mixed_bench(p, args.mixed_steps, stream, mean.cpu().numpy(), var.cpu().numpy(), info["iters"],
+                                   args.mv_reps)
+    return out
+
+
+def mixed_bench(p, steps, stream, mean64, var64, iters64, mv_reps):
+    """The same step on the mixed-precision path: the volume Gram on the
+    bfloat16 matrix cores (three bfloat16 slices per float32 operand) in
+    blocks of 32 IterGP iterations, each re-stabilised in float64, to the same
+    1e-8.  Errors against the float64 plain solve of the same step: the
+    converged means, the combined variances (these differ by the unexplored
+    part of the Krylov space, which the variance carries and the mean does
+    not), and both at a fixed 120 iterations on either path.  Also the
+    64-rhs volume matvec on the split-bfloat16 kernel."""
+    import numpy as np
+    import torch
+    import paper_2406_05020_amd as G
+    cap = 2048
+    M = len(mean64)
+    mean = torch.empty(M, dtype=torch.float64, device="cuda:0")
+    var = torch.empty(M, dtype=torch.float64, device="cuda:0")
+
+    def run(prec, k, tol):
+        h = G.assemble(p, max_iter=k, tile=G.TILE_BF16X3, stream=stream.cuda_stream)
+        try:
+            info = G.solve(h, prec=prec, tile=G.TILE_BF16X3, tol=tol, max_iter=k, check_every=16,
+                           stream=stream.cuda_stream)
+            G.posterior(h, p.grid, mean, var, stream=stream.cuda_stream)
+        finally:
+            G.destroy(h)
+        torch.cuda.synchronize()
+        return info
+
+    lat = []
+    for k in range(steps + 2):
+        s0 = time.perf_counter()
+        info = run(G.PREC_MIXED, cap, 1e-8)
+        if k >= 2:
+            lat.append(time.perf_counter() - s0)
+    m, v = mean.cpu().numpy(), var.cpu().numpy()
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    out = {"tile": "bf16x3", "block": 32, "solves_per_s": len(lat) / sum(lat), "p50_ms": _pctl(lat, 50),
+           "p99_ms": _pctl(lat, 99), "iters": info["iters"], "fp64_iters": iters64, "blocks": info["outer"],
+           "rel_res": info["rel_res"], "mean_rel_err_vs_fp64": rel(m, mean64), "var_rel_err_vs_fp64": rel(v, var64)}
+    run(G.PREC_FP64, 120, 0.0)
+    m64, v64 = mean.cpu().numpy(), var.cpu().numpy()
+    run(G.PREC_MIXED, 120, 0.0)
+    out["fixed120"] = {"mean_rel_err_vs_fp64": rel(mean.cpu().numpy(), m64),
+                       "var_rel_err_vs_fp64": rel(var.cpu().numpy(), v64)}
+    out["roofline_64rhs_bf16x3"] = roofline_volume(p, B=64, reps=mv_reps, prec=G.PREC_MIXED, tile=G.TILE_BF16X3)
     return out
 
 
@@ -373,26 +435,29 @@ def copy_calibration(nbytes):
     return {"bytes_read": n * 8, "bytes_written": n * 8, "us": 1e3 * ms, "GB_s": 2 * n * 8 / (ms * 1e-3) / 1e9}
 
 
-def roofline_volume(p, B, reps):
-    """Volume-Gram matvec (its GEMM stages are the dominant MFMA kernel,
-    k_gemm_lds<double, 64, 64> at these sizes) on B right-hand sides: HIP
-    events on the stream it is launched on, around `reps` applications;
-    per-launch time = time per application / launches."""
+def roofline_volume(p, B, reps, prec=0, tile=0):
+    """Volume-Gram matvec on B right-hand sides (its GEMM stages are the
+    dominant kernel: k_gemm_lds<double, 64, 64> in float64, k_gemm_bf16s on
+    the mixed path with split-bfloat16 tiles): HIP events on the stream it is
+    launched on, around `reps` applications; per-launch time = time per
+    application / launches.  The mixed path's roofline is the bfloat16 MFMA
+    peak against the flops the slice products execute (six per canonical
+    product)."""
     import torch
     import paper_2406_05020_amd as G
     stream = torch.cuda.current_stream()
     flops1, napp = canonical_pp_flops(p)
-    h = G.assemble(p, max_iter=8, stream=stream.cuda_stream)
+    h = G.assemble(p, max_iter=8, tile=tile, stream=stream.cuda_stream)
     try:
         x = torch.randn(p.n_pde * B, dtype=torch.float64, device="cuda:0")
         y = torch.empty_like(x)
         for _ in range(3):
-            G.volume_matvec(h, x, y, nrhs=B, stream=stream.cuda_stream)
+            G.volume_matvec(h, x, y, nrhs=B, prec=prec, stream=stream.cuda_stream)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(reps):
-            G.volume_matvec(h, x, y, nrhs=B, stream=stream.cuda_stream)
+            G.volume_matvec(h, x, y, nrhs=B, prec=prec, stream=stream.cuda_stream)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
@@ -402,14 +467,21 @@ def roofline_volume(p, B, reps):
     launches = max(1, info["volume_launches"])
     alg = flops1 * B
     achieved = alg / (ms * 1e-3) / 1e12
-    ent = VOLUME_GEMM_TRAFFIC.get((p.name, B))
-    traffic = ent[0] if (ent is not None and ent[1] == gemm_source_hash()) else None
-    return {"bound": "mfma", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6,
-            "traffic": traffic, "gemm_source_hash": gemm_source_hash(),
-            "kernel": "k_gemm_lds<double,...> (volume-Gram mode products)",
-            "workload": f"{p.name} volume Gram, {B} rhs", "alg_flops_per_launch": alg / launches,
-            "launches_per_matvec": launches, "avg_launch_us": 1e3 * ms / launches,
-            "executed_flops_per_matvec": info["volume_flops"], "kronecker_applications": napp}
+    if prec == 0:
+        ent = VOLUME_GEMM_TRAFFIC.get((p.name, B))
+        traffic = ent[0] if (ent is not None and ent[1] == gemm_source_hash()) else None
+        return {"bound": "mfma", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6,
+                "traffic": traffic, "gemm_source_hash": gemm_source_hash(),
+                "kernel": "k_gemm_lds<double,...> (volume-Gram mode products)",
+                "workload": f"{p.name} volume Gram, {B} rhs", "alg_flops_per_launch": alg / launches,
+                "launches_per_matvec": launches, "avg_launch_us": 1e3 * ms / launches,
+                "executed_flops_per_matvec": info["volume_flops"], "kronecker_applications": napp}
+    executed = 6.0 * alg / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved_executed": executed, "peak": 2500.0, "unit": "TFLOP/s",
+            "frac": executed / 2500.0, "canonical_float32_equivalent": achieved,
+            "kernel": "k_gemm_bf16s (split-bfloat16 slices, float32 accumulation)",
+            "workload": f"{p.name} volume Gram, {B} rhs, mixed path", "ms_per_matvec": ms,
+            "note": "time includes the float64<->float32 conversions of x and y around the plan"}
 
 
 SERVE_TOL, SERVE_ITERS = 1e-6, 256

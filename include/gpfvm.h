@@ -331,7 +331,12 @@ typedef struct {
                             /* scheme with the most cells <= coarse_cells whose   */
                             /* factors divide the request's cell counts (0: off;  */
                             /* needs prec FP64, <= GPFVM_MAX_COARSE)              */
+  int max_batch;            /* most requests solved together as one batch when    */
+                            /* they share the operator (same grid, kernel, PDE and */
+                            /* point layout; float64 path without the coarse       */
+                            /* start), 1 .. GPFVM_MAX_SERVER_BATCH; 1: none        */
 } gpfvm_server_opts;
+#define GPFVM_MAX_SERVER_BATCH 64
 
 typedef struct {
   int rc;                   /* GPFVM_OK / NOCONV / error code of the request      */
@@ -339,6 +344,8 @@ typedef struct {
   double t_submit, t_start, t_done;   /* host steady-clock seconds                */
   long long est_bytes;      /* HBM reserved for it at admission                   */
   long long n_grid;         /* posterior grid points                              */
+  int batch;                /* requests solved together with it (1: alone);      */
+                            /* for batched requests info.rel_res_full is NaN      */
 } gpfvm_request_result;
 
 typedef struct {

@@ -66,12 +66,12 @@ class HandleInfo(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("workers", C.c_int), ("hbm_budget", C.c_longlong), ("prec", C.c_int), ("tol", C.c_double),
-                ("max_iter", C.c_int), ("check_every", C.c_int), ("coarse_cells", C.c_int)]
+                ("max_iter", C.c_int), ("check_every", C.c_int), ("coarse_cells", C.c_int), ("max_batch", C.c_int)]
 
 
 class RequestResult(C.Structure):
     _fields_ = [("rc", C.c_int), ("info", SolveInfo), ("t_submit", C.c_double), ("t_start", C.c_double),
-                ("t_done", C.c_double), ("est_bytes", C.c_longlong), ("n_grid", C.c_longlong)]
+                ("t_done", C.c_double), ("est_bytes", C.c_longlong), ("n_grid", C.c_longlong), ("batch", C.c_int)]
 
 
 class ServerInfo(C.Structure):
@@ -374,8 +374,8 @@ class Server:
     """Thin wrapper over gpfvm_server_*: submit whole IBVP solves, poll results."""
 
     def __init__(self, workers: int = 8, hbm_budget: int = 64 << 30, prec: int = PREC_FP64, tol: float = 1e-6,
-                 max_iter: int = 1024, check_every: int = 16, coarse_cells: int = 0):
-        o = ServerOpts(workers, hbm_budget, prec, tol, max_iter, check_every, coarse_cells)
+                 max_iter: int = 1024, check_every: int = 16, coarse_cells: int = 0, max_batch: int = 16):
+        o = ServerOpts(workers, hbm_budget, prec, tol, max_iter, check_every, coarse_cells, max_batch)
         self.h = C.c_void_p()
         _check(lib().gpfvm_server_create(C.byref(o), C.byref(self.h)))
         self.grids = {}
@@ -403,7 +403,7 @@ class Server:
         if not done.value:
             return False, None, None, None
         r = {"rc": res.rc, "t_submit": res.t_submit, "t_start": res.t_start, "t_done": res.t_done,
-             "est_bytes": res.est_bytes, "n_grid": res.n_grid}
+             "est_bytes": res.est_bytes, "n_grid": res.n_grid, "batch": res.batch}
         r.update({k: getattr(res.info, k) for k, _ in SolveInfo._fields_})
         return True, r, mean, var
 

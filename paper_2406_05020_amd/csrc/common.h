@@ -230,6 +230,15 @@ struct GramTerm {          // merged volume-Gram term
   int lflag = 0, rflag = 0;
 };
 
+// Element offsets between the problems of a batch: problem z = blockIdx.y of a
+// batched launch reads and writes each operand at base + z * stride (all zero:
+// one problem).  M: stored matrices (directions, S D), v: length-N vectors,
+// u: coefficient partials, eta: eta arrays, part: per-workgroup partial sums,
+// scal / flag: the solver's device scalars and flags.
+struct BatchStrides {
+  i64 M = 0, v = 0, u = 0, eta = 0, part = 0, scal = 0, flag = 0;
+};
+
 // ---- kernels / launchers (kernels.hip) --------------------------------------
 hipError_t launch_factor(int kind, int kq, int p, int q, int n1, const double* a1, int n2, const double* a2,
                          double ell, double scale, double* out, i64 ld, hipStream_t s);
@@ -247,10 +256,12 @@ hipError_t launch_add_diag(double* A, i64 ld, i64 n0, i64 n, const double* vals,
 
 // deterministic reductions: out[0] = sum x*y (two passes, fixed order)
 hipError_t launch_dot(i64 n, const double* x, const double* y, double* partial, double* out,
-                      hipStream_t s);
+                      hipStream_t s, int batch = 1, const BatchStrides& bs = BatchStrides());
 // same, then the IterGP stopping test on out[0] (see solver.hip for the layout)
 hipError_t launch_dot_check(i64 n, const double* x, double* partial, double* scal, int* flag, int max_iter,
-                            hipStream_t s);
+                            hipStream_t s, int batch = 1, const BatchStrides& bs = BatchStrides());
+// partial sums of a (batched) dot product: DOT_PARTIALS per problem
+constexpr int DOT_PARTIALS = 512;
 // W = G_bb^{-1} U for n_b <= SMALL_GINV_MAX, one right-hand side, one workgroup
 // (needs the transposes Lt = L^T and Linvt = L^{-T} as row-major copies)
 constexpr int SMALL_GINV_MAX = 512;
@@ -267,7 +278,7 @@ hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s);
 //   (rows_dot with xm: the dots are taken with x - xm)
 int rows_dot_chunks(int nr, i64 N);
 hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, double* part, hipStream_t s,
-                           const double* xm = nullptr);
+                           const double* xm = nullptr, int batch = 1, const BatchStrides& bs = BatchStrides());
 hipError_t launch_rows_dot_full(int nr, i64 N, const double* M, const double* x, double* out, hipStream_t s);
 // the nunit partial sums of v = P w(x) of the factored point correction, on their own
 hipError_t launch_qf_v(const QFactor* F, int nunit, const double* x, double* vpart, hipStream_t s);
@@ -277,7 +288,8 @@ hipError_t launch_qf_v(const QFactor* F, int nunit, const double* x, double* vpa
 hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, int u_nch, const double* eta,
                               const double* base, double* out, double* out2, const double* M2, const double* base2,
                               double* out3, hipStream_t s, double* dot_part = nullptr,
-                              const double* base2m = nullptr);
+                              const double* base2m = nullptr, int batch = 1,
+                              const BatchStrides& bs = BatchStrides());
 // y[i] = add[i] + alpha * sum_k M[i][k] x[k] over k <= i (upper = 0) or k >= i (upper = 1)
 hipError_t launch_trmv_rows(int n, const double* M, const double* x, double* y, double alpha, const double* add,
                             int upper, hipStream_t s);
@@ -320,6 +332,20 @@ struct gpfvm_sop {
   // subtracted by two extra segments of its last stage, so pp_split gives Y = S X; no resident Q
   bool qf = false;
   double* qf_v = nullptr;          // nunit x W partial sums of v, piece-major
+};
+
+// State of a batched solve (problems sharing the handle's operator; see
+// gpfvm::batch_solve): per-problem slices of the solver state, problem z at
+// offset z * (its length).
+struct GpfvmBatch {
+  int R = 0;
+  double* yobs = nullptr;          // R x n data [y_b; int_V f]
+  double* bS = nullptr;            // R x N volume-system right-hand sides
+  double* v = nullptr;             // R x N weights
+  double* Dd = nullptr;            // R x max_iter x N directions
+  double* Qd = nullptr;            // R x max_iter x N  S D
+  double* eta = nullptr;           // R x max_iter
+  std::vector<int> iters;          // directions stored per problem
 };
 
 struct gpfvm_handle {
@@ -388,4 +414,5 @@ struct gpfvm_handle {
   double* scal = nullptr;          // device scalars
   int* flag = nullptr;             // device flags
   double* part = nullptr;          // per-workgroup partial sums: d.w (ceil(N/64)), then r.r twice (nblk(N))
+  GpfvmBatch batch;                // the last batched solve
 };

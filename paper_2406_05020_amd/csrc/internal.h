@@ -62,6 +62,15 @@ int build_ops32(gpfvm_handle* h);
 std::vector<Stage> ginv_stages(const gpfvm_handle* h, int nrhs, const double* U, double* T, double* W, double* R);
 hipError_t run_stages(const std::vector<Stage>& st, hipStream_t s);
 hipError_t ginv_rows(const gpfvm_handle* h, const double* U, double* T, double* W, double* R, hipStream_t s);
+// batched solve of problems sharing the handle's operator (solver.hip)
+struct BatchResult {
+  int iters = 0, state = 0;        // directions stored; 0 budget, 1 converged, 2 breakdown
+  double rel_res = 0;
+};
+int batch_solve(gpfvm_handle* h, int R, const double* yobs_host, double tol, int max_iter, int check_every,
+                int replace_every, hipStream_t s, std::vector<BatchResult>& out);
+int batch_posterior(gpfvm_handle* h, int z, int dim, const int* n, const double* const* axis, double* mean,
+                    double* var, hipStream_t s);
 GemmDesc desc1(void* C, i64 c_rs, const void* A, i64 a_rs, i64 a_cs, const void* B, i64 b_rs, i64 b_cs, int M,
                int N, int K, double alpha, double beta, int tri);
 

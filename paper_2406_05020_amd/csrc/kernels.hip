@@ -1147,10 +1147,15 @@ constexpr int DOT_BLOCKS = 512;
 constexpr int DOT_THREADS = 256;
 
 
+static_assert(DOT_BLOCKS == DOT_PARTIALS, "dot partial count");
+
 __global__ __launch_bounds__(DOT_THREADS) void k_dot_partial(i64 n, const double* __restrict__ x,
                                                              const double* __restrict__ y,
-                                                             double* __restrict__ partial) {
+                                                             double* __restrict__ partial, i64 bsv) {
   __shared__ double red[DOT_THREADS / 64];
+  x += blockIdx.y * bsv;
+  y += blockIdx.y * bsv;
+  partial += (i64)blockIdx.y * DOT_BLOCKS;
   double acc = 0;
   for (i64 i = (i64)blockIdx.x * DOT_THREADS + threadIdx.x; i < n; i += (i64)DOT_BLOCKS * DOT_THREADS)
     acc += x[i] * y[i];
@@ -1165,8 +1170,10 @@ __global__ __launch_bounds__(DOT_THREADS) void k_dot_partial(i64 n, const double
 }
 
 __global__ __launch_bounds__(DOT_THREADS) void k_dot_final(const double* __restrict__ partial,
-                                                           double* __restrict__ out) {
+                                                           double* __restrict__ out, i64 bso) {
   __shared__ double red[DOT_THREADS / 64];
+  partial += (i64)blockIdx.x * DOT_BLOCKS;
+  out += blockIdx.x * bso;
   double acc = 0;
   for (int i = threadIdx.x; i < DOT_BLOCKS; i += DOT_THREADS) acc += partial[i];
   acc = wave_sum(acc);
@@ -1183,8 +1190,11 @@ __global__ __launch_bounds__(DOT_THREADS) void k_dot_final(const double* __restr
 // (scal[4] = tol^2, scal[3] = b.b); flag[0] = 3 once flag[1] reaches max_iter.
 __global__ __launch_bounds__(DOT_THREADS) void k_dot_final_check(const double* __restrict__ partial,
                                                                  double* __restrict__ scal, int* __restrict__ flag,
-                                                                 int max_iter) {
+                                                                 int max_iter, i64 bss, i64 bsf) {
   __shared__ double red[DOT_THREADS / 64];
+  partial += (i64)blockIdx.x * DOT_BLOCKS;
+  scal += blockIdx.x * bss;
+  flag += blockIdx.x * bsf;
   double acc = 0;
   for (int i = threadIdx.x; i < DOT_BLOCKS; i += DOT_THREADS) acc += partial[i];
   acc = wave_sum(acc);
@@ -1202,9 +1212,9 @@ __global__ __launch_bounds__(DOT_THREADS) void k_dot_final_check(const double* _
 }
 
 hipError_t launch_dot_check(i64 n, const double* x, double* partial, double* scal, int* flag, int max_iter,
-                            hipStream_t s) {
-  k_dot_partial<<<DOT_BLOCKS, DOT_THREADS, 0, s>>>(n, x, x, partial);
-  k_dot_final_check<<<1, DOT_THREADS, 0, s>>>(partial, scal, flag, max_iter);
+                            hipStream_t s, int batch, const BatchStrides& bs) {
+  k_dot_partial<<<dim3(DOT_BLOCKS, batch), DOT_THREADS, 0, s>>>(n, x, x, partial, bs.v);
+  k_dot_final_check<<<batch, DOT_THREADS, 0, s>>>(partial, scal, flag, max_iter, bs.scal, bs.flag);
   return hipGetLastError();
 }
 
@@ -1296,8 +1306,12 @@ constexpr int RP_THREADS = 256;
 
 __global__ __launch_bounds__(RP_THREADS) void k_rows_dot(i64 N, int nch, const double* __restrict__ M,
                                                          const double* __restrict__ x, const double* __restrict__ xm,
-                                                         double* __restrict__ part) {
+                                                         double* __restrict__ part, BatchStrides bs) {
   __shared__ double red[RP_THREADS / 64];
+  M += blockIdx.y * bs.M;
+  x += blockIdx.y * bs.v;
+  if (xm) xm += blockIdx.y * bs.v;
+  part += blockIdx.y * bs.u;
   const int row = (int)(blockIdx.x / nch), ch = (int)(blockIdx.x % nch);
   const i64 L = (N + nch - 1) / nch;
   const i64 lo = (i64)ch * L, hi = min(N, lo + L);
@@ -1311,10 +1325,23 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
                                                                const double* __restrict__ eta, const double* base,
                                                                double* out, double* out2, const double* __restrict__ M2,
                                                                const double* base2, double* out3, double* dot_part,
-                                                               const double* __restrict__ base2m) {
+                                                               const double* __restrict__ base2m, BatchStrides bs) {
   __shared__ double us[CU_BLK];
   __shared__ double part[CU_WAVES][64];
   __shared__ double part2[TWO ? CU_WAVES : 1][64];
+  {
+    const i64 z = blockIdx.y;
+    M += z * bs.M;
+    if (TWO) M2 += z * bs.M;
+    u += z * bs.u;
+    if (eta) eta += z * bs.eta;
+    base += z * bs.v;
+    out += z * bs.v;
+    if (out2) out2 += z * bs.v;
+    if (TWO) { base2 += z * bs.v; out3 += z * bs.v; }
+    if (base2m) base2m += z * bs.v;
+    if (DOT) dot_part += z * bs.part;
+  }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const i64 c = (i64)blockIdx.x * 64 + lane;
   // the addends of the output, loaded before anything they do not depend on
@@ -1399,34 +1426,35 @@ int rows_dot_chunks(int nr, i64 N) {
 }
 
 hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, double* part, hipStream_t s,
-                           const double* xm) {
+                           const double* xm, int batch, const BatchStrides& bs) {
   if (nr <= 0 || N <= 0) return hipSuccess;
   const int nch = rows_dot_chunks(nr, N);
-  k_rows_dot<<<dim3((unsigned)((i64)nr * nch)), dim3(RP_THREADS), 0, s>>>(N, nch, M, x, xm, part);
+  k_rows_dot<<<dim3((unsigned)((i64)nr * nch), batch), dim3(RP_THREADS), 0, s>>>(N, nch, M, x, xm, part, bs);
   return hipGetLastError();
 }
 
 hipError_t launch_rows_dot_full(int nr, i64 N, const double* M, const double* x, double* out, hipStream_t s) {
   if (nr <= 0 || N <= 0) return hipSuccess;
-  k_rows_dot<<<dim3((unsigned)nr), dim3(RP_THREADS), 0, s>>>(N, 1, M, x, nullptr, out);
+  k_rows_dot<<<dim3((unsigned)nr), dim3(RP_THREADS), 0, s>>>(N, 1, M, x, nullptr, out, BatchStrides());
   return hipGetLastError();
 }
 
 hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, int u_nch, const double* eta,
                               const double* base, double* out, double* out2, const double* M2, const double* base2,
-                              double* out3, hipStream_t s, double* dot_part, const double* base2m) {
+                              double* out3, hipStream_t s, double* dot_part, const double* base2m, int batch,
+                              const BatchStrides& bs) {
   if (N <= 0) return hipSuccess;
   if (u_nch < 1 || u_nch > CU_MAXCH) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((N + 63) / 64)), block(64 * CU_WAVES);
+  const dim3 grid((unsigned)((N + 63) / 64), batch), block(64 * CU_WAVES);
   if (M2 && dot_part)
     k_cols_update<true, true><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3,
-                                                     dot_part, base2m);
+                                                     dot_part, base2m, bs);
   else if (M2)
     k_cols_update<true, false><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3,
-                                                      nullptr, base2m);
+                                                      nullptr, base2m, bs);
   else
     k_cols_update<false, false><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, nullptr, nullptr,
-                                                       nullptr, nullptr, nullptr);
+                                                       nullptr, nullptr, nullptr, bs);
   return hipGetLastError();
 }
 
@@ -1478,9 +1506,9 @@ hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s) {
 }
 
 hipError_t launch_dot(i64 n, const double* x, const double* y, double* partial, double* out,
-                      hipStream_t s) {
-  k_dot_partial<<<DOT_BLOCKS, DOT_THREADS, 0, s>>>(n, x, y, partial);
-  k_dot_final<<<1, DOT_THREADS, 0, s>>>(partial, out);
+                      hipStream_t s, int batch, const BatchStrides& bs) {
+  k_dot_partial<<<dim3(DOT_BLOCKS, batch), DOT_THREADS, 0, s>>>(n, x, y, partial, bs.v);
+  k_dot_final<<<batch, DOT_THREADS, 0, s>>>(partial, out, bs.scal);
   return hipGetLastError();
 }
 

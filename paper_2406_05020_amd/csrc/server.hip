@@ -1,15 +1,21 @@
 // Continuous-batching request server.
 //
 // Requests (whole IBVPs plus an evaluation grid) queue on the host.  A pool of
-// worker threads, each owning one HIP stream, takes requests in arrival order
-// as soon as a slot is free and the request's estimated HBM footprint fits
-// within the budget left by the requests in flight; the worker assembles,
-// solves and evaluates the posterior on its stream, so the kernels of the
-// requests in flight overlap on the device, then returns the memory to a
-// shared caching allocator (no hipMalloc / hipFree in steady state) and admits
-// the next request.  Every kernel of the path is deterministic (fixed
-// reduction order, no atomics in arithmetic), so a request's result does not
-// depend on what else is in flight.
+// worker threads, each owning one HIP stream, takes work in arrival order as
+// soon as a slot is free and the estimated HBM footprint fits within the
+// budget left by the work in flight.  Work is a batch: the oldest queued
+// request together with the later queued requests that share its operator
+// (the same grid, kernel, PDE and point layout -- only the point data differ,
+// as for serving requests of one grid size), up to max_batch.  A batch is
+// assembled once and solved as one multi-problem IterGP (gpfvm::batch_solve:
+// every iteration applies the shared operator to all its problems in one set
+// of grouped launches), then each request's posterior is evaluated on its
+// own grid.  A batch of one runs the single-request path.  Batches in flight
+// overlap on the device; memory comes from a shared caching allocator (no
+// hipMalloc / hipFree in steady state).  Every kernel of the path is
+// deterministic (fixed reduction order, no atomics in arithmetic); a request
+// solved in a batch agrees with the same request solved alone to rounding
+// (the batched operator takes the GEMM form of the point-block solves).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -78,9 +84,55 @@ struct IBVPCopy {
 
 }  // namespace
 
+// Everything of an IBVP that defines its operator (all but the point data),
+// as bytes: requests with equal keys share the operator and can be batched.
+static std::string operator_key(const gpfvm_ibvp& p) {
+  std::string k;
+  auto put = [&](const void* a, size_t n) { k.append((const char*)a, n); };
+  long long N = 1;
+  put(&p.dim, sizeof(int));
+  for (int i = 0; i < p.dim; ++i) {
+    put(&p.ncell[i], sizeof(int));
+    put(p.edges[i], (p.ncell[i] + 1) * sizeof(double));
+    put(&p.lengthscale[i], sizeof(double));
+    put(&p.kernel[i], sizeof(int));
+    N *= p.ncell[i];
+  }
+  put(&p.outputscale, sizeof(double));
+  put(&p.nterm, sizeof(int));
+  put(p.alpha, (size_t)p.nterm * p.dim * sizeof(int));
+  put(p.coef, p.nterm * sizeof(double));
+  bool any_cw = false;
+  for (int t = 0; t < p.nterm; ++t) {
+    const int cw = p.cellwise ? p.cellwise[t] : 0;
+    put(&cw, sizeof(int));
+    any_cw |= cw != 0;
+  }
+  if (any_cw) put(p.cell_coef, N * sizeof(double));
+  const int has_f = p.f_int ? 1 : 0;
+  put(&has_f, sizeof(int));
+  if (p.f_int) put(p.f_int, N * sizeof(double));
+  put(&p.noise_pde, sizeof(double));
+  put(&p.noise_pde_relative, sizeof(int));
+  put(&p.ngroup, sizeof(int));
+  for (int g = 0; g < p.ngroup; ++g) {
+    const gpfvm_pointgroup& G = p.groups[g];
+    for (int i = 0; i < p.dim; ++i) {
+      put(&G.n[i], sizeof(int));
+      put(G.axis[i], G.n[i] * sizeof(double));
+      put(&G.deriv[i], sizeof(int));
+    }
+    put(&G.noise_var, sizeof(double));
+  }
+  return k;
+}
+
 struct gpfvm_request {
   long long ticket = 0;
   std::unique_ptr<IBVPCopy> ibvp;
+  std::string opkey;                // operator_key of the IBVP
+  std::vector<double> yobs;         // [y_b; int_V f] in observation order
+  int batch = 1;                    // requests solved together with this one
   int gdim = 0;
   int gn[3] = {1, 1, 1};
   std::vector<double> gaxis[3];
@@ -176,6 +228,20 @@ static size_t estimate_bytes(const gpfvm_ibvp& p, int max_iter, long long M, int
   return (size_t)(1.25 * b) + (size_t)(32 << 20);
 }
 
+// Device bytes one more problem adds to a batch: its directions and S D, its
+// solver vectors and the wider multi-rhs operator buffers.
+static size_t batch_extra_bytes(const gpfvm_ibvp& p, int max_iter) {
+  long long N = 1, nb = 0;
+  for (int i = 0; i < p.dim; ++i) N *= p.ncell[i];
+  for (int g = 0; g < p.ngroup; ++g) {
+    long long s = 1;
+    for (int i = 0; i < p.dim; ++i) s *= p.groups[g].n[i];
+    nb += s;
+  }
+  const double b = (2.0 * max_iter + 24.0 + 2.0 * GPFVM_MAX_TERMS) * N * 8.0 + 8.0 * nb * 8.0 + 8.0 * max_iter;
+  return (size_t)(1.25 * b);
+}
+
 int gpfvm_assemble_cached(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, void* stream, DeviceCache* cache,
                           gpfvm_handle** out);
 
@@ -235,9 +301,65 @@ static void run_request(gpfvm_server* S, gpfvm_request* r, hipStream_t st) {
   gpfvm_destroy(h);
 }
 
+// A batch of requests sharing one operator: one assembly, one batched solve,
+// a posterior per request.
+static void run_batch(gpfvm_server* S, std::vector<gpfvm_request*>& rs, hipStream_t st) {
+  const int R = (int)rs.size();
+  for (auto* r : rs) r->batch = R;
+  gpfvm_handle* h = nullptr;
+  gpfvm_assemble_opts ao;
+  gpfvm_default_assemble_opts(&ao);
+  ao.max_iter = S->opts.max_iter;
+  int rc = gpfvm_assemble_cached(&rs[0]->ibvp->p, &ao, st, &S->cache, &h);
+  auto fail_all = [&](int code, const std::string& m) {
+    for (auto* r : rs) { r->rc = code; r->err = m; }
+  };
+  if (rc) { fail_all(rc, gpfvm_last_error(nullptr)); return; }
+  const long long n = (long long)rs[0]->yobs.size();
+  std::vector<double> yall((size_t)R * n);
+  for (int z = 0; z < R; ++z) std::memcpy(yall.data() + (size_t)z * n, rs[z]->yobs.data(), n * sizeof(double));
+  std::vector<BatchResult> res;
+  rc = batch_solve(h, R, yall.data(), S->opts.tol, S->opts.max_iter, S->opts.check_every, 25, st, res);
+  if (rc) {
+    fail_all(rc, gpfvm_last_error(h));
+    gpfvm_destroy(h);
+    return;
+  }
+  Arena out;
+  out.cache = &S->cache;
+  for (int z = 0; z < R; ++z) {
+    gpfvm_request* r = rs[z];
+    r->info.iters = res[z].iters;
+    r->info.outer = 0;
+    r->info.rel_res = res[z].rel_res;
+    r->info.rel_res_full = std::nan("");          // not evaluated for batched requests
+    r->info.coarse = 0;
+    r->info.status = res[z].state == 2 ? GPFVM_E_NOTPD
+                     : (S->opts.tol > 0 && res[z].rel_res > S->opts.tol) ? GPFVM_E_NOCONV : GPFVM_OK;
+    double* dmean = (double*)out.alloc((size_t)r->M * sizeof(double));
+    double* dvar = (double*)out.alloc((size_t)r->M * sizeof(double));
+    if (!dmean || !dvar) { r->rc = GPFVM_E_NOMEM; r->err = "out of device memory (posterior output)"; continue; }
+    const double* ax[3] = {r->gaxis[0].data(), r->gaxis[1].data(), r->gaxis[2].data()};
+    rc = batch_posterior(h, z, r->gdim, r->gn, ax, dmean, dvar, st);
+    if (rc) { r->rc = rc; r->err = gpfvm_last_error(h); continue; }
+    r->mean.resize(r->M);
+    r->var.resize(r->M);
+    hipError_t e = hipMemcpyAsync(r->mean.data(), dmean, r->M * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->var.data(), dvar, r->M * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { r->rc = GPFVM_E_HIP; r->err = hipGetErrorString(e); }
+    else r->rc = r->info.status == GPFVM_E_NOTPD ? GPFVM_E_NOTPD : r->info.status;
+  }
+  (void)hipStreamSynchronize(st);
+  out.release();
+  gpfvm_destroy(h);
+}
+
 static void worker_main(gpfvm_server* S, int w) {
   (void)hipSetDevice(S->device);
   hipStream_t st = S->streams[w];
+  std::vector<gpfvm_request*> batch;
+  size_t batch_bytes = 0;
   for (;;) {
     gpfvm_request* r = nullptr;
     {
@@ -251,30 +373,54 @@ static void worker_main(gpfvm_server* S, int w) {
       if (S->queue.empty()) continue;
       r = S->queue.front();
       S->queue.pop_front();
-      S->reserved += r->est_bytes;
+      batch.assign(1, r);
+      batch_bytes = r->est_bytes;
+      // later queued requests with the same operator join, in arrival order, while the batch
+      // stays within max_batch and the budget (float64 IterGP without the coarse start only)
+      if (S->opts.max_batch > 1 && S->opts.prec == GPFVM_PREC_FP64 && S->opts.coarse_cells == 0 &&
+          r->est_bytes <= (size_t)S->opts.hbm_budget) {
+        const size_t extra = batch_extra_bytes(r->ibvp->p, S->opts.max_iter);
+        for (auto it = S->queue.begin(); it != S->queue.end() && (int)batch.size() < S->opts.max_batch;) {
+          if ((*it)->opkey == r->opkey && S->reserved + batch_bytes + extra <= (size_t)S->opts.hbm_budget) {
+            batch.push_back(*it);
+            batch_bytes += extra;
+            it = S->queue.erase(it);
+          } else {
+            ++it;
+          }
+        }
+      }
+      S->reserved += batch_bytes;
       S->peak_reserved = std::max(S->peak_reserved, S->reserved);
-      S->in_flight += 1;
+      S->in_flight += (int)batch.size();
       S->peak_in_flight = std::max(S->peak_in_flight, S->in_flight);
     }
-    r->t_start = now_s();
+    const double t0 = now_s();
+    for (auto* q : batch) q->t_start = t0;
     if (r->est_bytes > (size_t)S->opts.hbm_budget) {
       r->rc = GPFVM_E_NOMEM;
       r->err = "request exceeds the server's HBM budget";
     } else {
       try {
-        run_request(S, r, st);
+        if (batch.size() == 1) run_request(S, r, st);
+        else run_batch(S, batch, st);
       } catch (const std::exception& e) {
-        r->rc = GPFVM_E_NOMEM;
-        r->err = std::string("internal error: ") + e.what();
+        for (auto* q : batch) {
+          q->rc = GPFVM_E_NOMEM;
+          q->err = std::string("internal error: ") + e.what();
+        }
       }
     }
-    r->t_done = now_s();
+    const double t1 = now_s();
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      S->reserved -= r->est_bytes;
-      S->in_flight -= 1;
-      S->completed += 1;
-      r->done = true;
+      S->reserved -= batch_bytes;
+      S->in_flight -= (int)batch.size();
+      S->completed += (long long)batch.size();
+      for (auto* q : batch) {
+        q->t_done = t1;
+        q->done = true;
+      }
     }
     S->cv.notify_all();
   }
@@ -289,6 +435,7 @@ extern "C" void gpfvm_default_server_opts(gpfvm_server_opts* o) {
   o->max_iter = 1024;
   o->check_every = 16;
   o->coarse_cells = 0;
+  o->max_batch = 16;
 }
 
 extern "C" int gpfvm_server_create(const gpfvm_server_opts* o, gpfvm_server** out) {
@@ -299,7 +446,8 @@ extern "C" int gpfvm_server_create(const gpfvm_server_opts* o, gpfvm_server** ou
   if (!o) o = &def;
   if (o->workers < 1 || o->workers > 16 || o->hbm_budget < (1LL << 26) || o->max_iter < 1 || !(o->tol >= 0) ||
       o->check_every < 1 || (o->prec != GPFVM_PREC_FP64 && o->prec != GPFVM_PREC_MIXED) || o->coarse_cells < 0 ||
-      o->coarse_cells > GPFVM_MAX_COARSE || (o->coarse_cells > 0 && o->prec != GPFVM_PREC_FP64))
+      o->coarse_cells > GPFVM_MAX_COARSE || (o->coarse_cells > 0 && o->prec != GPFVM_PREC_FP64) ||
+      o->max_batch < 1 || o->max_batch > GPFVM_MAX_SERVER_BATCH)
     return GPFVM_E_INVALID;
   auto S = std::make_unique<gpfvm_server>();
   S->opts = *o;
@@ -334,6 +482,19 @@ extern "C" int gpfvm_server_submit(gpfvm_server* S, const gpfvm_ibvp* p, int dim
     r->M *= n[i];
   }
   r->ibvp = std::make_unique<IBVPCopy>(*p);
+  r->opkey = operator_key(r->ibvp->p);
+  {
+    const gpfvm_ibvp& q = r->ibvp->p;
+    long long N = 1;
+    for (int i = 0; i < q.dim; ++i) N *= q.ncell[i];
+    for (int g = 0; g < q.ngroup; ++g) {
+      long long sz = 1;
+      for (int i = 0; i < q.dim; ++i) sz *= q.groups[g].n[i];
+      r->yobs.insert(r->yobs.end(), q.groups[g].y, q.groups[g].y + sz);
+    }
+    if (q.f_int) r->yobs.insert(r->yobs.end(), q.f_int, q.f_int + N);
+    else r->yobs.insert(r->yobs.end(), (size_t)N, 0.0);
+  }
   {
     int f[3];
     const long long n_coarse = choose_coarsen(r->ibvp->p, S->opts.coarse_cells, f);
@@ -373,6 +534,7 @@ extern "C" int gpfvm_server_poll(gpfvm_server* S, long long ticket, int wait, in
     res->t_done = r->t_done;
     res->est_bytes = (long long)r->est_bytes;
     res->n_grid = r->M;
+    res->batch = r->batch;
   }
   if (r->rc == GPFVM_OK || r->rc == GPFVM_E_NOCONV) {
     if (mean) std::memcpy(mean, r->mean.data(), r->M * sizeof(double));

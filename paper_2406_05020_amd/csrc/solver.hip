@@ -51,8 +51,17 @@ __global__ __launch_bounds__(256) void k_update2x(i64 N, const double* __restric
                                                   double* __restrict__ scal, int* __restrict__ flag,
                                                   const double* __restrict__ eta_part, int n_eta,
                                                   const double* __restrict__ rr_in, int n_rr,
-                                                  double* __restrict__ rr_out) {
+                                                  double* __restrict__ rr_out, BatchStrides bs) {
   __shared__ double red[256], red2[256];
+  {                                              // problem blockIdx.y of a batch
+    const i64 z = blockIdx.y;
+    d += z * bs.v; w += z * bs.v; v += z * bs.v; r += z * bs.v; X += z * bs.v;
+    Dcol += z * bs.M; Qcol += z * bs.M; eta_slot += z * bs.eta;
+    scal += z * bs.scal; flag += z * bs.flag;
+    if (eta_part) eta_part += z * bs.part;
+    if (rr_in) rr_in += z * bs.part;
+    if (rr_out) rr_out += z * bs.part;
+  }
   // every load of the update is issued up front: the flag, both partial sums and the vectors
   const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   const int fl = flag[0];
@@ -122,9 +131,13 @@ __global__ __launch_bounds__(256) void k_update2x(i64 N, const double* __restric
   }
 }
 
-// r = b - y and X = r (guarded)
+// r = b - y and X = r (guarded; problem blockIdx.y of a batch at offset blockIdx.y * vs, flags at * fs)
 __global__ void k_resid2(i64 N, const double* __restrict__ b, const double* __restrict__ y, double* __restrict__ r,
-                         double* __restrict__ X, const int* __restrict__ flag) {
+                         double* __restrict__ X, const int* __restrict__ flag, i64 vs = 0, i64 fs = 0) {
+  {
+    const i64 z = blockIdx.y;
+    b += z * vs; y += z * vs; r += z * vs; X += z * vs; flag += z * fs;
+  }
   if (flag[0] != 0) return;
   const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < N) {
@@ -245,10 +258,15 @@ __global__ void k_point_grid(const PGMeta* __restrict__ meta, int nb, i64 x0, i6
 
 unsigned nblk(i64 n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
-// C[j][c] /= eta[j] for a rows x cols row-major block
-__global__ void k_rowscale(int rows, int cols, double* __restrict__ C, const double* __restrict__ eta) {
+// C[j][c] = (sum over the nch chunk partials in order) / eta[j] (eta null: no division)
+__global__ void k_sum_rowscale(int nch, int rows, int cols, const double* __restrict__ part,
+                               const double* __restrict__ eta, double* __restrict__ C) {
   const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < (i64)rows * cols) C[i] /= eta[i / cols];
+  const i64 n = (i64)rows * cols;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < nch; ++c) s += part[c * n + i];
+  C[i] = eta ? s / eta[i / cols] : s;
 }
 
 // Plain CG (Sec. 4.1), device-side scalars: scal[CG_RR + (it & 1)] holds r.r of
@@ -630,6 +648,11 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
         return GPFVM_E_HIP;
       }
       so->pp_split.stages.back() = last[0];
+    } else if (elt != F64 && nrhs == 1 && qform_ok(N, h->nb)) {
+      // low-precision operator: the resident Q applied on its own around the volume plan
+      rc = build_qc(h, h->stream);
+      if (rc) return rc;
+      so->qform = true;
     } else if (elt == F64 && nrhs == 1 && qform_ok(N, h->nb)) {
       rc = build_qc(h, h->stream);
       if (rc) return rc;
@@ -686,6 +709,14 @@ static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
   hipError_t e;
   const i64 NN = h->N * so->nrhs;
   if (so->qf) return run_plan(so->pp_split, s);             // G_pp X + s2 X - sum_r q_r (x) (P w)_r
+  if (so->qform && so->elt != F64) {                                // low-precision G_pp, float64 Q^T Q X
+    if ((e = launch_rows_dot_full(h->nb, h->N, h->Qc, (const double*)so->X, (double*)so->U, s)) != hipSuccess) return e;
+    if ((e = launch_copy_f64_to_f32((const double*)so->X, (float*)so->X32, NN, s)) != hipSuccess) return e;
+    if ((e = run_plan(so->pp, s)) != hipSuccess) return e;
+    if ((e = launch_copy_f32_to_f64((const float*)so->Y32, (double*)so->Y, NN, s)) != hipSuccess) return e;
+    return launch_cols_update(h->nb, h->N, h->Qc, (const double*)so->U, 1, nullptr, (const double*)so->Y,
+                              (double*)so->Y, nullptr, nullptr, nullptr, nullptr, s);
+  }
   if (so->qform) {                                                  // G_pp X + s2 X - Q^T Q X
     if (so->pp.stages.empty() &&
         (e = launch_rows_dot_full(h->nb, h->N, h->Qc, (const double*)so->X, (double*)so->U, s)) != hipSuccess)
@@ -899,7 +930,8 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
         if (action) HIPCHK(h, launch_dot(N, d, r, dotp, h->scal, s));
         hipLaunchKernelGGL(k_update2x, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, (const double*)w, v, r,
                            X, h->Dd + (i64)i * N, h->Qd + (i64)i * N, h->eta + i, h->scal, h->flag,
-                           (const double*)(i > 0 ? eta_p : nullptr), n_eta, (const double*)rr_prev, n_rr, rr_next);
+                           (const double*)(i > 0 ? eta_p : nullptr), n_eta, (const double*)rr_prev, n_rr, rr_next,
+                           BatchStrides());
         rr_prev = rr_next;
         if (replace) {
           HIPCHK(h, hipMemcpyAsync(X, v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -944,6 +976,32 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
 }
 
 // ---------------------------------------------------------------------------
+// C (M x Nc, row-major) = A (M x K, rows contiguous, ld lda) * B^T with B
+// (Nc x K, rows contiguous, ld ldb), for short M, Nc and long K: the K range
+// is cut into chunks that run as batches of one GEMM stage into partial
+// products, summed in chunk order afterwards (deterministic).  Stages are
+// appended to `st`; part must hold nch * M * Nc doubles.
+// ---------------------------------------------------------------------------
+static int long_k_chunks(i64 K) { return (int)std::max<i64>(1, std::min<i64>(64, K / 2048)); }
+
+static void add_long_k(std::vector<Stage>& st, double* C, const double* A, i64 lda, const double* B, i64 ldb, int M,
+                       int Nc, i64 K, double* part) {
+  const int nch = long_k_chunks(K);
+  const i64 kc = K / nch, tail = K - (i64)(nch - 1) * kc;
+  Stage g;
+  GemmDesc D = desc1(part, Nc, A, lda, 1, B, 1, ldb, M, Nc, (int)kc, 1.0, 0.0, 0);
+  D.batch = nch - 1;
+  D.c_bs = (i64)M * Nc;
+  D.seg[0].a_bs = kc;
+  D.seg[0].b_bs = kc;
+  if (nch > 1) g.descs.push_back(D);
+  g.descs.push_back(desc1(part + (i64)(nch - 1) * M * Nc, Nc, A + (i64)(nch - 1) * kc, lda, 1,
+                          B + (i64)(nch - 1) * kc, 1, ldb, M, Nc, (int)tail, 1.0, 0.0, 0));
+  st.push_back(g);
+  (void)C;
+}
+
+// ---------------------------------------------------------------------------
 // Float64 re-stabilisation of a block of directions found with the
 // low-precision operator (the mixed path).  Directions [i0, i0 + n) of Dd are
 // S-conjugated in float64 against the stored ones, which are exact in float64:
@@ -961,28 +1019,28 @@ static int restabilise_block(gpfvm_handle* h, gpfvm_sop* sm, int i0, int n, cons
   const int m = sm->nrhs;
   double* X = (double*)sm->X;
   double* Y = (double*)sm->Y;
+  const int nch = long_k_chunks(N);
   double* Cb = (double*)tmp.alloc((size_t)std::max(i0, 1) * n * sizeof(double));
   double* P = (double*)tmp.alloc((size_t)n * n * sizeof(double));
   double* Pi = (double*)tmp.alloc((size_t)n * n * sizeof(double));
   double* wc = (double*)tmp.alloc((size_t)n * sizeof(double));
-  if (!Cb || !P || !Pi || !wc) { h->err = "out of device memory (re-stabilisation)"; return GPFVM_E_NOMEM; }
+  double* part = (double*)tmp.alloc((size_t)nch * std::max(i0, n) * n * sizeof(double));
+  if (!Cb || !P || !Pi || !wc || !part) { h->err = "out of device memory (re-stabilisation)"; return GPFVM_E_NOMEM; }
   HIPCHK(h, hipMemcpyAsync(X, h->Dd + (i64)i0 * N, (size_t)n * N * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (n < m) HIPCHK(h, launch_fill(X + (i64)n * N, 0.0, (i64)(m - n) * N, s));
   HIPCHK(h, apply_sop(h, sm, s));                                       // Y = S X (float64)
   std::vector<Stage> st;
   if (i0 > 0) {
     // C = D^T SB (i0 x n), then B -= D (C / eta), SB -= (S D) (C / eta)
-    Stage c1, c2;
-    c1.descs.push_back(desc1(Cb, n, h->Dd, N, 1, Y, 1, N, i0, n, (int)N, 1.0, 0.0, 0));
+    Stage c2;
+    add_long_k(st, Cb, h->Dd, N, Y, N, i0, n, N, part);                  // partials of D^T SB
     c2.descs.push_back(desc1(X, N, Cb, 1, n, h->Dd, N, 1, n, (int)N, i0, -1.0, 1.0, 0));
     c2.descs.push_back(desc1(Y, N, Cb, 1, n, h->Qd, N, 1, n, (int)N, i0, -1.0, 1.0, 0));
-    st.push_back(c1);
     st.push_back(c2);
   }
   {
-    Stage pg, up;
-    pg.descs.push_back(desc1(P, n, X, N, 1, Y, 1, N, n, n, (int)N, 1.0, 0.0, 0));   // P = B (S B)^T
-    st.push_back(pg);
+    Stage up;
+    add_long_k(st, P, X, N, Y, N, n, n, N, part);                         // partials of P = B (S B)^T
     // D_block = L^{-1} B, (S D)_block = L^{-1} SB   (rows of B are the directions)
     up.descs.push_back(desc1(h->Dd + (i64)i0 * N, N, Pi, n, 1, X, N, 1, n, (int)N, n, 1.0, 0.0, 1));
     up.descs.push_back(desc1(h->Qd + (i64)i0 * N, N, Pi, n, 1, Y, N, 1, n, (int)N, n, 1.0, 0.0, 1));
@@ -1000,12 +1058,15 @@ static int restabilise_block(gpfvm_handle* h, gpfvm_sop* sm, int i0, int n, cons
   if (i0 > 0) {
     for (int pass = 0; pass < 2; ++pass) {
       HIPCHK(h, launch_gemm_stage(F64, st[0], s));
-      hipLaunchKernelGGL(k_rowscale, dim3(nblk((i64)i0 * n)), dim3(256), 0, s, i0, n, Cb, (const double*)h->eta);
+      hipLaunchKernelGGL(k_sum_rowscale, dim3(nblk((i64)i0 * n)), dim3(256), 0, s, nch, i0, n, (const double*)part,
+                         (const double*)h->eta, Cb);
       HIPCHK(h, launch_gemm_stage(F64, st[1], s));
     }
     k = 2;
   }
   HIPCHK(h, launch_gemm_stage(F64, st[k], s));                          // P
+  hipLaunchKernelGGL(k_sum_rowscale, dim3(nblk((i64)n * n)), dim3(256), 0, s, nch, n, n, (const double*)part,
+                     (const double*)nullptr, P);
   {
     std::string e;
     const int rc = cholesky_and_inverse(P, Pi, n, tmp, s, e);
@@ -1825,3 +1886,176 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
   return GPFVM_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched solve of R problems that share the handle's operator: the same
+// grid, kernel, PDE and point layout, different point data (serving requests
+// of one grid size).  Each problem runs its own IterGP recurrence (its own
+// directions, eta and weights, float64, two projection passes, residual
+// replacement every `replace_every`), in lockstep: one batched iteration
+// applies the shared volume-system operator to all R actions at once (the
+// nrhs = R plan: grouped GEMM launches, the point block as GEMM-form
+// triangular products), and every projection, update and dot product of all
+// problems runs as one launch with a batch dimension.  A problem that has
+// converged keeps its state; its share of the later launches does nothing.
+// ---------------------------------------------------------------------------
+int gpfvm::batch_solve(gpfvm_handle* h, int R, const double* yobs_host, double tol, int max_iter, int check_every,
+                       int replace_every, hipStream_t s, std::vector<BatchResult>& out) {
+  if (R < 1 || max_iter < 1 || max_iter > h->max_iter) { h->err = "batch: bad size"; return GPFVM_E_INVALID; }
+  h->stream = s;
+  const i64 N = h->N, n = h->n, nb = h->nb, cap = h->max_iter;
+  gpfvm_sop* so = nullptr;
+  int rc = get_sop(h, R, F64, &so);
+  if (rc) return rc;
+  GpfvmBatch& B = h->batch;
+  B = GpfvmBatch();
+  B.R = R;
+  const int n_eta = (int)((N + 63) / 64), n_rr = (int)nblk(N);
+  const i64 ucap = cap + 528, pstride = n_eta + 2 * (i64)n_rr;
+  auto A = [&](size_t bytes) { return h->arena.alloc(bytes); };
+  B.yobs = (double*)A((size_t)R * n * 8);
+  B.bS = (double*)A((size_t)R * N * 8);
+  B.v = (double*)A((size_t)R * N * 8);
+  B.Dd = (double*)A((size_t)R * cap * N * 8);
+  B.Qd = (double*)A((size_t)R * cap * N * 8);
+  B.eta = (double*)A((size_t)R * cap * 8);
+  double* r = (double*)A((size_t)R * N * 8);
+  double* d = (double*)A((size_t)R * N * 8);
+  double* w = (double*)A((size_t)R * N * 8);
+  double* coef = (double*)A((size_t)R * ucap * 8);
+  double* dotp = (double*)A((size_t)R * DOT_PARTIALS * 8);
+  double* scal = (double*)A((size_t)R * 64 * 8);
+  int* flag = (int*)A((size_t)R * 16 * sizeof(int));
+  double* part = (double*)A((size_t)R * pstride * 8);
+  if (!B.yobs || !B.bS || !B.v || !B.Dd || !B.Qd || !B.eta || !r || !d || !w || !coef || !dotp || !scal || !flag ||
+      !part) {
+    h->err = "out of device memory (batched solve)";
+    return GPFVM_E_NOMEM;
+  }
+  double* X = (double*)so->X;
+  const double* Y = (const double*)so->Y;
+  BatchStrides bs;
+  bs.M = cap * N; bs.v = N; bs.u = ucap; bs.eta = cap; bs.part = pstride; bs.scal = 64; bs.flag = 16;
+  BatchStrides bsd;                               // dots: vectors and scalars only
+  bsd.v = N; bsd.scal = 64;
+  // data, and b_r = y_p - G_pb G_bb^{-1} y_b,r for all problems with the nrhs = R plans
+  HIPCHK(h, hipMemcpyAsync(B.yobs, yobs_host, (size_t)R * n * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(h, launch_fill(B.v, 0.0, (i64)R * N, s));
+  HIPCHK(h, launch_fill(B.eta, 1.0, (i64)R * cap, s));
+  for (int z = 0; z < R; ++z)
+    HIPCHK(h, hipMemcpyAsync(B.bS + (i64)z * N, B.yobs + (i64)z * n + nb, N * 8, hipMemcpyDeviceToDevice, s));
+  if (nb > 0) {
+    for (int z = 0; z < R; ++z)
+      HIPCHK(h, hipMemcpyAsync((double*)so->U + (i64)z * nb, B.yobs + (i64)z * n, nb * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, run_stages(so->ginv, s));
+    HIPCHK(h, launch_fill((double*)so->Y, 0.0, (i64)R * N, s));
+    HIPCHK(h, run_plan(so->pb, s));
+    HIPCHK(h, launch_axpby((i64)R * N, 1.0, Y, 1.0, B.bS, s));
+  }
+  // r = b - S v (v = 0), X = r; b.b; the stopping test of every problem
+  HIPCHK(h, hipMemsetAsync(flag, 0, (size_t)R * 16 * sizeof(int), s));
+  HIPCHK(h, hipMemcpyAsync(X, B.v, (size_t)R * N * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, apply_sop(h, so, s));
+  HIPCHK(h, launch_dot(N, B.bS, B.bS, dotp, scal + 3, s, R, bsd));
+  {
+    std::vector<double> t2(R * 64, 0.0);
+    HIPCHK(h, hipMemcpyAsync(t2.data(), scal, (size_t)R * 64 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    for (int z = 0; z < R; ++z) t2[z * 64 + 4] = tol * tol;
+    HIPCHK(h, hipMemcpyAsync(scal, t2.data(), (size_t)R * 64 * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+  }
+  hipLaunchKernelGGL(k_resid2, dim3(nblk(N), R), dim3(256), 0, s, N, (const double*)B.bS, Y, r, X,
+                     (const int*)flag, N, (i64)16);
+  HIPCHK(h, launch_dot_check(N, r, dotp, scal, flag, max_iter, s, R, bs));
+  double* eta_p = part;
+  double* rr_a = part + n_eta;
+  double* rr_b = rr_a + n_rr;
+  double* rr_prev = nullptr;
+  std::vector<int> hflag((size_t)R * 16, 0);
+  int i = 0;
+  while (i < max_iter) {
+    const int end = std::min(max_iter, i + std::max(1, check_every));
+    for (; i < end; ++i) {
+      HIPCHK(h, apply_sop(h, so, s));                                 // Y = S X, all problems
+      if (i > 0) {
+        const int nch = rows_dot_chunks(i, N);
+        HIPCHK(h, launch_rows_dot(i, N, B.Dd, Y, coef, s, nullptr, R, bs));
+        HIPCHK(h, launch_cols_update(i, N, B.Dd, coef, nch, B.eta, X, d, nullptr, B.Qd, Y, w, s, nullptr, nullptr,
+                                     R, bs));
+        HIPCHK(h, launch_rows_dot(i, N, B.Dd, w, coef, s, nullptr, R, bs));
+        HIPCHK(h, launch_cols_update(i, N, B.Dd, coef, nch, B.eta, d, d, nullptr, B.Qd, w, w, s, eta_p, nullptr,
+                                     R, bs));
+      } else {
+        HIPCHK(h, hipMemcpyAsync(d, X, (size_t)R * N * 8, hipMemcpyDeviceToDevice, s));
+        HIPCHK(h, hipMemcpyAsync(w, Y, (size_t)R * N * 8, hipMemcpyDeviceToDevice, s));
+        HIPCHK(h, launch_dot(N, w, d, dotp, scal + 1, s, R, bsd));    // eta = d^T S d
+      }
+      const bool replace = (i + 1) % std::max(1, replace_every) == 0;
+      double* rr_next = replace ? nullptr : (rr_prev == rr_a ? rr_b : rr_a);
+      hipLaunchKernelGGL(k_update2x, dim3(nblk(N), R), dim3(256), 0, s, N, (const double*)d, (const double*)w, B.v,
+                         r, X, B.Dd + (i64)i * N, B.Qd + (i64)i * N, B.eta + i, scal, flag,
+                         (const double*)(i > 0 ? eta_p : nullptr), n_eta, (const double*)rr_prev, n_rr, rr_next, bs);
+      rr_prev = rr_next;
+      if (replace) {
+        HIPCHK(h, hipMemcpyAsync(X, B.v, (size_t)R * N * 8, hipMemcpyDeviceToDevice, s));
+        HIPCHK(h, apply_sop(h, so, s));
+        hipLaunchKernelGGL(k_resid2, dim3(nblk(N), R), dim3(256), 0, s, N, (const double*)B.bS, Y, r, X,
+                           (const int*)flag, N, (i64)16);
+        HIPCHK(h, hipMemcpyAsync(X, r, (size_t)R * N * 8, hipMemcpyDeviceToDevice, s));
+        HIPCHK(h, launch_dot_check(N, r, dotp, scal, flag, max_iter, s, R, bs));
+      }
+    }
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(hflag.data(), flag, (size_t)R * 16 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    bool all = true;
+    for (int z = 0; z < R; ++z) all = all && hflag[(size_t)z * 16] != 0;
+    if (all) break;
+  }
+  // explicit residual of every problem
+  HIPCHK(h, hipMemcpyAsync(X, B.v, (size_t)R * N * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, apply_sop(h, so, s));
+  HIPCHK(h, hipMemcpyAsync(r, B.bS, (size_t)R * N * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, launch_axpby((i64)R * N, -1.0, Y, 1.0, r, s));
+  HIPCHK(h, launch_dot(N, r, r, dotp, scal + 8, s, R, bsd));
+  std::vector<double> hs((size_t)R * 64);
+  HIPCHK(h, hipMemcpyAsync(hs.data(), scal, (size_t)R * 64 * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  out.assign(R, BatchResult());
+  B.iters.assign(R, 0);
+  for (int z = 0; z < R; ++z) {
+    B.iters[z] = hflag[(size_t)z * 16 + 1];
+    out[z].iters = B.iters[z];
+    out[z].state = hflag[(size_t)z * 16];
+    const double bb = hs[(size_t)z * 64 + 3], rr = hs[(size_t)z * 64 + 8];
+    out[z].rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+  }
+  return GPFVM_OK;
+}
+
+// Posterior of problem z of the last batched solve: the handle's solver state
+// is pointed at that problem's slices for the call.
+int gpfvm::batch_posterior(gpfvm_handle* h, int z, int dim, const int* n, const double* const* axis, double* mean,
+                           double* var, hipStream_t s) {
+  GpfvmBatch& B = h->batch;
+  if (z < 0 || z >= B.R) { h->err = "batch: no such problem"; return GPFVM_E_INVALID; }
+  const i64 N = h->N, cap = h->max_iter;
+  double *v0 = h->v, *D0 = h->Dd, *Q0 = h->Qd, *e0 = h->eta, *y0 = h->yobs, *b0 = h->bS;
+  const int it0 = h->iters;
+  const bool s0 = h->solved, x0 = h->sd_exact, c0 = h->cg_only;
+  h->v = B.v + (i64)z * N;
+  h->Dd = B.Dd + (i64)z * cap * N;
+  h->Qd = B.Qd + (i64)z * cap * N;
+  h->eta = B.eta + (i64)z * cap;
+  h->yobs = B.yobs + (i64)z * h->n;
+  h->bS = B.bS + (i64)z * N;
+  h->iters = B.iters[z];
+  h->solved = true;
+  h->sd_exact = true;
+  h->cg_only = false;
+  const int rc = gpfvm_posterior(h, dim, n, axis, mean, var, s);
+  h->v = v0; h->Dd = D0; h->Qd = Q0; h->eta = e0; h->yobs = y0; h->bS = b0; h->iters = it0;
+  h->solved = s0; h->sd_exact = x0; h->cg_only = c0;
+  return rc;
+}

@@ -1,6 +1,8 @@
 """Continuous-batching server: each request's result is the same alone and in
-the mix; admission respects the HBM budget; oversize requests are refused; a
-served request equals the same solve through the single-handle entry points."""
+the mix (bit for bit among requests of different operators, to rounding for
+requests batched on a shared operator); admission respects the HBM budget;
+oversize requests are refused; a served request equals the same solve through
+the single-handle entry points."""
 import numpy as np
 import pytest
 
@@ -126,3 +128,41 @@ def test_served_coarse_warm_start_equals_direct_solve(G):
     # the coarse warm start is float64 only
     with pytest.raises(G.GpfvmError):
         G.Server(workers=1, prec=G.PREC_MIXED, coarse_cells=target)
+
+
+def test_batched_requests_agree_with_alone_and_oracle(G):
+    """Requests that share the operator (one grid size, different initial
+    data) are solved together as one batch: each result equals the same
+    request served alone to rounding (the batched operator uses the GEMM form
+    of the point-block solves) and the oracle's IterGP at the same iteration
+    count (12 iterations, no stopping test)."""
+    from oracle import gpfvm_oracle as O
+    from oracle.gpfvm_oracle import SchurSystem, two_stage_posterior
+    from parity import assert_close
+    k = 12
+    blocker = W.heat2d_request(48, 24, seed=7199)         # keeps the single worker busy while the batch queues
+    reqs = [W.heat2d_request(16, 16, seed=7100 + i) for i in range(5)]
+    with G.Server(workers=1, hbm_budget=32 << 30, prec=G.PREC_FP64, tol=0.0, max_iter=k, max_batch=8) as S:
+        tb = S.submit(blocker)
+        tickets = [S.submit(p) for p in reqs]
+        S.poll(tb, wait=True)
+        batched = [S.poll(t, wait=True) for t in tickets]
+    alone = []
+    with G.Server(workers=1, hbm_budget=32 << 30, prec=G.PREC_FP64, tol=0.0, max_iter=k, max_batch=1) as S:
+        for p in reqs:
+            alone.append(S.poll(S.submit(p), wait=True))
+    assert all(b[1]["batch"] == len(reqs) for b in batched), [b[1]["batch"] for b in batched]
+    assert all(a[1]["batch"] == 1 for a in alone)
+    for (_, rb, mb, vb), (_, ra, ma, va) in zip(batched, alone):
+        assert rb["rc"] == ra["rc"] == G.OK and rb["iters"] == ra["iters"] == k, (rb, ra)
+        assert abs(rb["rel_res"] - ra["rel_res"]) <= 1e-8 * ra["rel_res"], (rb["rel_res"], ra["rel_res"])
+        assert_close(mb, ma, 1e-6, what="batched vs alone mean")
+        assert_close(vb, va, 1e-6, what="batched vs alone var")
+    p = reqs[2]
+    o = O.Oracle(p)
+    S = SchurSystem(o)
+    X = o.grid_points(p.grid)
+    vp, D, eta, _ = O.itergp(S, k, passes=2)
+    m_ref, v_ref = two_stage_posterior(S, vp, X, D, eta)
+    assert_close(batched[2][2], m_ref, 1e-6, what="batched mean vs oracle")
+    assert_close(batched[2][3], v_ref, 1e-6, what="batched var vs oracle")
