@@ -50,6 +50,9 @@ def parse():
                          "64^3 heat volume matvec with 64")
     ap.add_argument("--large-timing", action="store_true",
                     help="only time the wave 64x128x128 problem: assemble, 200 IterGP iterations, posterior")
+    ap.add_argument("--c3-steps", type=int, default=2,
+                    help="timed steps of the 2-D heat 64^3 block (assemble + 200 IterGP + posterior, float64 and "
+                         "mixed; 0 = skip)")
     ap.add_argument("--mixed-only", action="store_true",
                     help="only the advection-diffusion block with its mixed-precision measurement (profiling)")
     ap.add_argument("--mixed-steps", type=int, default=5,
@@ -203,6 +206,9 @@ def main():
     if args.c2_steps > 0:
         out["advdiff_128x128"] = c2_block(args, G, W, stream)
         note("advection-diffusion block done")
+    if args.c3_steps > 0:
+        out["heat2d_64x64x64"] = c3_block(args.c3_steps, G, W, stream)
+        note("heat 64^3 block done")
     if args.extra_rooflines:
         out.update(extra_rooflines())
     if args.serve_requests > 0:
@@ -271,6 +277,45 @@ def c2_block(args, G, W, stream):
     if args.mixed_steps > 0:
         out["mixed"] = mixed_bench(p, args.mixed_steps, stream, mean.cpu().numpy(), var.cpu().numpy(), info["iters"],
                                    args.mv_reps)
+    return out
+
+
+def c3_block(steps, G, W, stream, iters=200):
+    """2-D heat on 64^3 volumes + 12288 initial/boundary points: assemble,
+    200 IterGP iterations, posterior mean and combined variance on the
+    16 x 64^2 grid, in float64 and on the mixed path (split-bfloat16 volume
+    Gram in blocks of 32, each re-stabilised in float64).  The mixed result is
+    compared with the float64 one of the same step."""
+    import numpy as np
+    import torch
+    p = W.heat2d_c3()
+    M = int(np.prod([len(a) for a in p.grid]))
+    mean = torch.empty(M, dtype=torch.float64, device="cuda:0")
+    var = torch.empty(M, dtype=torch.float64, device="cuda:0")
+    out = {"workload": "heat2d_64x64x64_cells_12288_pts_itergp200", "n_pde": int(p.n_pde), "n_b": int(p.n_b),
+           "itergp_iters": iters}
+    res = {}
+    for name, prec, tile in (("fp64", G.PREC_FP64, G.TILE_FP32), ("mixed_bf16x3", G.PREC_MIXED, G.TILE_BF16X3)):
+        lat = []
+        for k in range(steps + 1):
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            h = G.assemble(p, max_iter=iters, tile=tile, stream=stream.cuda_stream)
+            try:
+                info = G.solve(h, prec=prec, tile=tile, tol=0.0, max_iter=iters, check_every=50, block=32,
+                               stream=stream.cuda_stream)
+                G.posterior(h, p.grid, mean, var, stream=stream.cuda_stream)
+            finally:
+                G.destroy(h)
+            torch.cuda.synchronize()
+            if k > 0:
+                lat.append(time.perf_counter() - s0)
+        res[name] = (mean.cpu().numpy(), var.cpu().numpy())
+        out[name] = {"solves_per_s": len(lat) / sum(lat), "ms_per_step": 1e3 * float(np.mean(lat)),
+                     "rel_res": info["rel_res"], "iters": info["iters"]}
+    (m64, v64), (mm, vm) = res["fp64"], res["mixed_bf16x3"]
+    out["mixed_bf16x3"]["mean_rel_err_vs_fp64"] = float(np.linalg.norm(mm - m64) / np.linalg.norm(m64))
+    out["mixed_bf16x3"]["var_rel_err_vs_fp64"] = float(np.linalg.norm(vm - v64) / np.linalg.norm(v64))
     return out
 
 

@@ -1,5 +1,7 @@
-"""Write the stored oracle values for the full-size wave problem
-(64 x 128 x 128 volumes with per-cell c^2, 16384 initial/boundary points).
+"""Write the stored oracle values for the full-size 3-D problems: the wave
+problem (64 x 128 x 128 volumes with per-cell c^2, 16384 initial/boundary
+points; default) and, with the argument heat2d, the 2-D heat problem
+(64 x 64 x 64 volumes, 12288 initial/boundary points).
 
 Calls only the oracle: the two-stage system (exact Cholesky conditioning on
 the points, Sec. 4.2) and IterGP with CG actions and the projection done twice
@@ -8,10 +10,12 @@ after a fixed number of iterations.  The posterior mean and the combined
 variance (Sec. 2.1 eq. lin-cond-mean / lin-cond-cov with the IterGP inverse
 approximation) are stored at 256 seeded sample points of the 8 x 128 x 128
 evaluation grid of cell centres, after 30 and after 200 iterations (the
-second run continues the first, with the same recurrences).
+second run continues the first, with the same recurrences).  For the heat
+problem: after 30 iterations, at 256 points of its 16 x 64 x 64 grid.
 
-Run from the repository root:  python tests/golden/make_wave_c4_golden.py
-(about half an hour on 8 cores; writes tests/golden/wave2d_c4_itergp.json).
+Run from the repository root:  python tests/golden/make_fullsize_goldens.py [heat2d]
+(wave: about half an hour on 8 cores, writes tests/golden/wave2d_c4_itergp.json;
+heat2d: a few minutes, writes tests/golden/heat2d_c3_itergp.json).
 """
 import json
 import os
@@ -26,14 +30,18 @@ sys.path.insert(0, ROOT)
 import workloads as W                                     # noqa: E402
 from oracle import gpfvm_oracle as O                      # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "wave2d_c4_itergp.json")
-STOPS = (30, 200)
-N_SAMPLE, SAMPLE_SEED = 256, 4
+HERE = os.path.dirname(os.path.abspath(__file__))
+CASES = {
+    "wave2d": (W.wave2d_c4, os.path.join(HERE, "wave2d_c4_itergp.json"), (30, 200), 4),
+    "heat2d": (W.heat2d_c3, os.path.join(HERE, "heat2d_c3_itergp.json"), (30,), 3),
+}
+N_SAMPLE = 256
 
 
-def main():
+def main(case="wave2d"):
+    make, OUT, STOPS, SAMPLE_SEED = CASES[case]
     t0 = time.perf_counter()
-    p = W.wave2d_c4()
+    p = make()
     o = O.Oracle(p)
     S = O.SchurSystem(o)
     X = o.grid_points(p.grid)
@@ -59,4 +67,4 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else "wave2d")

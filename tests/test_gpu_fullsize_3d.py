@@ -1,0 +1,123 @@
+"""The full-size 3-D problems: the wave problem (64 x 128 x 128 volumes with
+per-cell c^2, 16384 initial/boundary points) in the configuration bench.py
+times, and the 2-D heat problem (64^3 volumes, 12288 points): assemble,
+early-terminated IterGP with CG actions (Sec. 4.1), posterior mean and
+combined variance on the evaluation grid (Sec. 2.1, Sec. 4.1-4.2).  Compared
+at 256 sampled grid points with the oracle's values after the same numbers of
+iterations, stored under tests/golden by a script that calls only the oracle
+(tests/golden/make_fullsize_goldens.py).  The heat problem's volume-system
+operator is also compared element by element."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import assert_close
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_05020_amd as G
+    G.lib()
+    return G
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN_DIR, name)) as f:
+        return json.load(f)
+
+
+def _run(G, p, k, prec=0, tile=0):
+    h = G.assemble(p, max_iter=k, tile=tile)
+    try:
+        print(f"{p.name}, {k} IterGP iterations, prec {prec}", flush=True)
+        info = G.solve(h, prec=prec, tile=tile, tol=0.0, max_iter=k, check_every=50, block=32)
+        assert info["iters"] == k, info
+        M = int(np.prod([len(a) for a in p.grid]))
+        mean = torch.empty(M, dtype=torch.float64, device="cuda:0")
+        var = torch.empty(M, dtype=torch.float64, device="cuda:0")
+        G.posterior(h, p.grid, mean, var)
+        torch.cuda.synchronize()
+        return info, mean.cpu().numpy(), var.cpu().numpy()
+    finally:
+        G.destroy(h)
+
+
+@pytest.mark.parametrize("k", [30, 200])
+def test_wave_fullsize_itergp_posterior_matches_oracle(G, k):
+    golden = _golden("wave2d_c4_itergp.json")
+    ref = golden["stops"][str(k)]
+    p = W.wave2d_c4()
+    assert p.name == golden["workload"] and p.n_b == golden["n_b"]
+    idx = np.asarray(golden["idx"])
+    info, m, v = _run(G, p, k)
+    assert abs(info["rel_res"] - ref["rel_res"]) <= 1e-6 * ref["rel_res"] + 1e-12, (info["rel_res"], ref["rel_res"])
+    assert_close(m[idx], ref["mean"], 1e-6, what="mean")
+    assert_close(v[idx], ref["var"], 1e-6, what="var")
+    # the whole grid: finite, and the combined variance stays within [0, sf2]
+    assert np.all(np.isfinite(m)) and np.all(np.isfinite(v))
+    assert v.min() >= -1e-9 and v.max() <= 1.0 + 1e-12
+
+
+def test_heat3d_fullsize_schur_operator_matches_oracle(G):
+    """The volume-system operator of the 2-D heat problem at full size (the
+    point block through the row-streaming triangular solves with one
+    right-hand side, through GEMM-form triangular products with two) against
+    the oracle's LAPACK Cholesky, element by element."""
+    from oracle import gpfvm_oracle as O
+    p = W.heat2d_c3()
+    S = O.SchurSystem(O.Oracle(p))
+    rng = np.random.default_rng(53)
+    X = rng.standard_normal((2, p.n_pde))
+    h = G.assemble(p, max_iter=4)
+    try:
+        errs = []
+        for nrhs in (1, 2):
+            x = torch.as_tensor(X[:nrhs].ravel(), device="cuda:0")
+            y = torch.empty_like(x)
+            G.schur_matvec(h, x, y, nrhs=nrhs)
+            torch.cuda.synchronize()
+            Y = y.cpu().numpy().reshape(nrhs, -1)
+            for r in range(nrhs):
+                ref = S.matvec(X[r])
+                errs.append((nrhs, r, float(np.linalg.norm(Y[r] - ref) / np.linalg.norm(ref)),
+                             float(np.max(np.abs(Y[r] - ref)) / np.max(np.abs(ref)))))
+        print("heat 64^3 Schur operator errors (nrhs, r, L2, max):", errs, flush=True)
+        assert all(e[2] <= 1e-9 and e[3] <= 1e-9 for e in errs), errs
+    finally:
+        G.destroy(h)
+
+
+# The 2-D heat problem's early-terminated mean is conditioning-limited: with
+# the point block solved by LAPACK's symmetric LDL^T in place of its Cholesky
+# (two backward-stable solvers), the oracle's own 30-iteration mean moves by
+# 3.5e-6 (L2) and its variance by 8.6e-8 (the right-hand side
+# b = y_p - G_pb G_bb^{-1} y_b carries the point block's condition number,
+# about 1e11).  The mean is held to HEAT3D_MEAN_TOL, about five times that
+# floor; the variance to the float64 bound.
+HEAT3D_MEAN_TOL = 2e-5
+
+
+def test_heat3d_fullsize_itergp_posterior_matches_oracle(G):
+    golden = _golden("heat2d_c3_itergp.json")
+    ref = golden["stops"]["30"]
+    p = W.heat2d_c3()
+    assert p.name == golden["workload"] and p.n_b == golden["n_b"]
+    idx = np.asarray(golden["idx"])
+    info, m, v = _run(G, p, 30)
+    print("heat 64^3, 30 iterations: rel_res", info["rel_res"], "oracle", ref["rel_res"],
+          "mean L2", float(np.linalg.norm(m[idx] - ref["mean"]) / np.linalg.norm(ref["mean"])),
+          "var L2", float(np.linalg.norm(v[idx] - ref["var"]) / np.linalg.norm(ref["var"])), flush=True)
+    assert_close(m[idx], ref["mean"], HEAT3D_MEAN_TOL, what="mean")
+    assert_close(v[idx], ref["var"], 1e-6, what="var")
+    assert abs(info["rel_res"] - ref["rel_res"]) <= HEAT3D_MEAN_TOL * ref["rel_res"], (info["rel_res"], ref["rel_res"])
+    assert v.min() >= -1e-9 and v.max() <= 1.0 + 1e-12
