@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests in the serving trace (0 = skip the serving measurement)")
     ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--serve-max-batch", type=int, default=16,
+                    help="most requests of one operator solved together (1 = no batching)")
     ap.add_argument("--serve-rates", default="0.8",
                     help="comma-separated arrival rates as fractions of the saturated throughput")
     ap.add_argument("--serving-only", action="store_true", help="only the serving measurement")
@@ -111,7 +113,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.serving_only:
         rates = tuple(float(r) for r in args.serve_rates.split(","))
-        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_workers, rates, args.serve_coarse)}), flush=True)
+        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_workers, rates, args.serve_coarse,
+                                                    args.serve_max_batch)}), flush=True)
         return
     if args.large_timing:
         print(json.dumps(large_timing()), flush=True)
@@ -213,7 +216,8 @@ def main():
         out.update(extra_rooflines())
     if args.serve_requests > 0:
         rates = tuple(float(r) for r in args.serve_rates.split(","))
-        out["serving"] = serving_bench(args.serve_requests, args.serve_workers, rates, args.serve_coarse)
+        out["serving"] = serving_bench(args.serve_requests, args.serve_workers, rates, args.serve_coarse,
+                                       args.serve_max_batch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_wave(p, iters, M)
     print(json.dumps(out), flush=True)
@@ -537,7 +541,7 @@ def _pctl(x, q):
     return float(np.percentile(np.asarray(x), q)) * 1e3
 
 
-def serving_bench(n_req, workers, rates=(0.8,), coarse_cells=0):
+def serving_bench(n_req, workers, rates=(0.8,), coarse_cells=0, max_batch=16):
     """Continuous batching vs the plain per-request float64 solve (FIFO, one at
     a time) on the same Poisson arrival trace of 2-D heat requests with grids
     drawn from {16,32,48,64}^2 x {16,24,32} cells and GP-drawn initial data.
@@ -558,7 +562,7 @@ def serving_bench(n_req, workers, rates=(0.8,), coarse_cells=0):
 
     probe = [W.heat2d_request(ns, nt, seed) for (_, ns, nt, seed) in W.serving_trace(n_req, 1.0, seed=5)]
     with G.Server(workers=workers, hbm_budget=96 << 30, prec=G.PREC_FP64, tol=SERVE_TOL,
-                  max_iter=SERVE_ITERS) as S:
+                  max_iter=SERVE_ITERS, max_batch=max_batch) as S:
         t0 = time.perf_counter()
         tk = [S.submit(q) for q in probe]
         for t in tk:
@@ -575,7 +579,7 @@ def serving_bench(n_req, workers, rates=(0.8,), coarse_cells=0):
         def served(coarse_cells):
             lat, conv, rres = [], [], []
             with G.Server(workers=workers, hbm_budget=96 << 30, prec=G.PREC_FP64, tol=SERVE_TOL,
-                          max_iter=SERVE_ITERS, coarse_cells=coarse_cells) as S:
+                          max_iter=SERVE_ITERS, coarse_cells=coarse_cells, max_batch=max_batch) as S:
                 start = time.perf_counter()
                 tickets = []
                 for arr, q in reqs:
@@ -634,7 +638,8 @@ def serving_bench(n_req, workers, rates=(0.8,), coarse_cells=0):
             "converged_fraction": float(np.mean(conv)), "rel_res_p50": float(np.median(rres)),
             "rel_res_max": float(np.max(rres)), **coarse,
         })
-    out = {"requests": n_req, "workers": workers, "saturated_solves_per_s": sat, **runs[0],
+    out = {"requests": n_req, "workers": workers, "max_batch": max_batch, "saturated_solves_per_s": sat,
+           **runs[0],
            "solve": f"fp64 IterGP-CG, tol {SERVE_TOL:g} or {SERVE_ITERS} iterations"}
     if len(runs) > 1:
         out["by_rate"] = runs

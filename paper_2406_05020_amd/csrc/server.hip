@@ -349,6 +349,13 @@ static void run_batch(gpfvm_server* S, std::vector<gpfvm_request*>& rs, hipStrea
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { r->rc = GPFVM_E_HIP; r->err = hipGetErrorString(e); }
     else r->rc = r->info.status == GPFVM_E_NOTPD ? GPFVM_E_NOTPD : r->info.status;
+    {                                  // this request's result is ready: release it now
+      std::lock_guard<std::mutex> lk(S->mu);
+      r->t_done = now_s();
+      r->done = true;
+      S->completed += 1;
+    }
+    S->cv.notify_all();
   }
   (void)hipStreamSynchronize(st);
   out.release();
@@ -416,10 +423,11 @@ static void worker_main(gpfvm_server* S, int w) {
       std::lock_guard<std::mutex> lk(S->mu);
       S->reserved -= batch_bytes;
       S->in_flight -= (int)batch.size();
-      S->completed += (long long)batch.size();
       for (auto* q : batch) {
+        if (q->done) continue;         // released by run_batch as its posterior finished
         q->t_done = t1;
         q->done = true;
+        S->completed += 1;
       }
     }
     S->cv.notify_all();
