@@ -1828,23 +1828,17 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
       hipLaunchKernelGGL(k_point_grid, dim3(nblk((i64)h->nb * nx)), dim3(256), 0, s, (const PGMeta*)dpg, h->nb, x0, nx,
                          h->sf2, KB);
       // T = L^{-1} KB, corrected once by iterative refinement: R = KB - L T in float64, then
-      // T += L^{-1} R with L^{-1} and R rounded to float32 (float32 MFMA).  R is the error of the
-      // float64 product times L, so the correction needs only a few correct digits: its
-      // float32 rounding leaves an error of about 1e-7 of the (already small) correction.
-      std::vector<Stage> st(2);
-      st[0].descs.push_back(desc1(TT, nx, h->Linv, h->nb, 1, KB, nx, 1, h->nb, (int)nx, h->nb, 1.0, 0.0, 1));
-      {
-        GemmDesc D = desc1(RR, nx, h->L, h->nb, 1, TT, nx, 1, h->nb, (int)nx, h->nb, -1.0, 0.0, 1);
-        D.X = KB; D.x_rs = nx; D.x_cs = 1; D.gamma = 1.0;
-        st[1].descs.push_back(D);
-      }
-      std::vector<Stage> st32(1);
-      st32[0].descs.push_back(desc1(C32, nx, h->Linv_f, h->nb, 1, R32, nx, 1, h->nb, (int)nx, h->nb, 1.0, 0.0, 1));
-      if (upload_stages(st, tmp, s) != hipSuccess || upload_stages(st32, tmp, s, F32) != hipSuccess)
-        return fail(GPFVM_E_HIP, "posterior: upload failed");
-      if (run_stages(st, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: gemm failed");
+      // T += L^{-1} R with L^{-1} and R rounded to float32.  R is the error of the float64
+      // product times L, so the correction needs only a few correct digits: its float32
+      // rounding leaves an error of about 1e-7 of the (already small) correction.  The three
+      // triangular products are library TRMMs.
       const i64 nbx = (i64)h->nb * nx;
-      if (launch_copy_f64_to_f32(RR, R32, nbx, s) != hipSuccess || launch_gemm_stage(F32, st32[0], s) != hipSuccess ||
+      if (trmm_lower_rows(h->nb, (int)nx, h->Linv, KB, TT, s) != hipSuccess ||
+          trmm_lower_rows(h->nb, (int)nx, h->L, TT, RR, s) != hipSuccess ||
+          launch_axpby(nbx, 1.0, KB, -1.0, RR, s) != hipSuccess)
+        return fail(GPFVM_E_HIP, "posterior: triangular product failed");
+      if (launch_copy_f64_to_f32(RR, R32, nbx, s) != hipSuccess ||
+          trmm_lower_rows_f32(h->nb, (int)nx, h->Linv_f, R32, C32, s) != hipSuccess ||
           launch_add_f32_to_f64(C32, TT, nbx, s) != hipSuccess)
         return fail(GPFVM_E_HIP, "posterior: correction failed");
       const int R = colsq_chunks(h->nb, nx);
