@@ -1,7 +1,7 @@
-// rocBLAS for the plain library products of the path: the posterior's
-// triangular products with many right-hand sides (TRMM), where the library
-// kernels run at 82% of the float64 MFMA peak on the wave problem's
-// 16384 x 2048 x 16384 shape (the grouped Kronecker GEMM reaches 60% there).
+// rocBLAS for a plain library product of the path: the posterior's triangular
+// product with many right-hand sides (TRMM), where the library kernels run at
+// 82% of the float64 MFMA peak on the wave problem's 16384 x 2048 x 16384
+// shape (the grouped Kronecker GEMM reaches 60% there).
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
@@ -44,15 +44,6 @@ hipError_t trmm_lower_rows(int n, int nx, const double* A, const double* B, doub
   if (!hd) return hipErrorNotInitialized;
   const double one = 1.0;
   const rocblas_status st = rocblas_dtrmm(hd, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                                          rocblas_diagonal_non_unit, nx, n, &one, A, n, B, nx, C, nx);
-  return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
-}
-
-hipError_t trmm_lower_rows_f32(int n, int nx, const float* A, const float* B, float* C, hipStream_t s) {
-  rocblas_handle hd = handle_for(s);
-  if (!hd) return hipErrorNotInitialized;
-  const float one = 1.0f;
-  const rocblas_status st = rocblas_strmm(hd, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
                                           rocblas_diagonal_non_unit, nx, n, &one, A, n, B, nx, C, nx);
   return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
 }

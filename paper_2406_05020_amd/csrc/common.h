@@ -249,7 +249,6 @@ hipError_t launch_scale(Elt elt, const void* src, i64 src_stride, const void* co
 hipError_t launch_axpby(i64 n, double a, const double* x, double b, double* y, hipStream_t s);
 hipError_t launch_copy_f64_to_f32(const double* x, float* y, i64 n, hipStream_t s);
 hipError_t launch_copy_f32_to_f64(const float* x, double* y, i64 n, hipStream_t s);
-hipError_t launch_add_f32_to_f64(const float* x, double* y, i64 n, hipStream_t s);   // y += x
 hipError_t launch_lincomb(int nmat, const double* const* mats, const double* coefs, i64 len,
                           double* out, hipStream_t s);
 hipError_t launch_fill(double* p, double v, i64 n, hipStream_t s);

@@ -62,9 +62,8 @@ int build_ops32(gpfvm_handle* h);
 std::vector<Stage> ginv_stages(const gpfvm_handle* h, int nrhs, const double* U, double* T, double* W, double* R);
 hipError_t run_stages(const std::vector<Stage>& st, hipStream_t s);
 hipError_t ginv_rows(const gpfvm_handle* h, const double* U, double* T, double* W, double* R, hipStream_t s);
-// rocBLAS products (blas.hip): C = A B, A row-major n x n lower-triangular, B and C row-major n x nx
+// rocBLAS product (blas.hip): C = A B, A row-major n x n lower-triangular, B and C row-major n x nx
 hipError_t trmm_lower_rows(int n, int nx, const double* A, const double* B, double* C, hipStream_t s);
-hipError_t trmm_lower_rows_f32(int n, int nx, const float* A, const float* B, float* C, hipStream_t s);
 
 // batched solve of problems sharing the handle's operator (solver.hip)
 struct BatchResult {

@@ -1091,18 +1091,6 @@ __global__ void k_f2d(const float* __restrict__ x, double* __restrict__ y, i64 n
   const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = (double)x[i];
 }
-// y += x (float32 addend widened to float64)
-__global__ void k_add_f2d(const float* __restrict__ x, double* __restrict__ y, i64 n) {
-  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] += (double)x[i];
-}
-
-hipError_t launch_add_f32_to_f64(const float* x, double* y, i64 n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  k_add_f2d<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, n);
-  return hipGetLastError();
-}
-
 hipError_t launch_copy_f64_to_f32(const double* x, float* y, i64 n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   k_d2f<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, n);
