@@ -130,6 +130,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"gpfvm HIP library not built: {LIB_PATH} is missing "
                                "(build it with: python paper_2406_05020_amd/build.py)")
+        # PyTorch-ROCm ships its own HIP runtime and rocBLAS under the system libraries'
+        # sonames; loaded after this library they would come in as second copies (two HIP
+        # runtimes in one process).  Loading torch first makes the library bind to its copies.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (args, res) in SYMBOLS.items():
             f = getattr(L, name)

@@ -36,15 +36,29 @@ rocblas_handle handle_for(hipStream_t s) {
 }
 }  // namespace
 
-// C = A B for row-major A (n x n, lower-triangular, leading dimension n) and
-// row-major B, C (n x nx, leading dimension nx).  In rocBLAS's column-major
-// view these are C^T = B^T A^T with A^T upper-triangular, a right-side TRMM.
-hipError_t trmm_lower_rows(int n, int nx, const double* A, const double* B, double* C, hipStream_t s) {
+// Row-major matrices are handed to rocBLAS as their column-major transposes:
+// a row-major lower-triangular T (leading dimension ldt) is the column-major
+// upper-triangular T^T, and a product with T on one side is a product with T^T
+// on the other.
+
+// C = alpha T B: T row-major m x m lower-triangular, B and C row-major m x k
+// (C and B distinct).
+hipError_t trmm_rows_left_lower(int m, int k, double alpha, const double* T, int ldt, const double* B, int ldb,
+                                double* C, int ldc, hipStream_t s) {
   rocblas_handle hd = handle_for(s);
   if (!hd) return hipErrorNotInitialized;
-  const double one = 1.0;
   const rocblas_status st = rocblas_dtrmm(hd, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                                          rocblas_diagonal_non_unit, nx, n, &one, A, n, B, nx, C, nx);
+                                          rocblas_diagonal_non_unit, k, m, &alpha, T, ldt, B, ldb, C, ldc);
+  return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+}
+
+// C = alpha B T: B and C row-major m x k (distinct), T row-major k x k lower-triangular.
+hipError_t trmm_rows_right_lower(int m, int k, double alpha, const double* T, int ldt, const double* B, int ldb,
+                                 double* C, int ldc, hipStream_t s) {
+  rocblas_handle hd = handle_for(s);
+  if (!hd) return hipErrorNotInitialized;
+  const rocblas_status st = rocblas_dtrmm(hd, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                                          rocblas_diagonal_non_unit, k, m, &alpha, T, ldt, B, ldb, C, ldc);
   return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
 }
 

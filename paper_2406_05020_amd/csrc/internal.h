@@ -62,8 +62,12 @@ int build_ops32(gpfvm_handle* h);
 std::vector<Stage> ginv_stages(const gpfvm_handle* h, int nrhs, const double* U, double* T, double* W, double* R);
 hipError_t run_stages(const std::vector<Stage>& st, hipStream_t s);
 hipError_t ginv_rows(const gpfvm_handle* h, const double* U, double* T, double* W, double* R, hipStream_t s);
-// rocBLAS product (blas.hip): C = A B, A row-major n x n lower-triangular, B and C row-major n x nx
-hipError_t trmm_lower_rows(int n, int nx, const double* A, const double* B, double* C, hipStream_t s);
+// rocBLAS triangular products (blas.hip) on row-major matrices, T lower-triangular,
+// C distinct from B: C = alpha T B (T m x m; B, C m x k) and C = alpha B T (B, C m x k; T k x k)
+hipError_t trmm_rows_left_lower(int m, int k, double alpha, const double* T, int ldt, const double* B, int ldb,
+                                double* C, int ldc, hipStream_t s);
+hipError_t trmm_rows_right_lower(int m, int k, double alpha, const double* T, int ldt, const double* B, int ldb,
+                                 double* C, int ldc, hipStream_t s);
 
 // batched solve of problems sharing the handle's operator (solver.hip)
 struct BatchResult {

@@ -44,6 +44,16 @@ namespace {
 // so no workgroup waits on another.  With rr_in this kernel also runs the
 // stopping test (converged if r.r <= tol^2 b.b: scal[4] = tol^2,
 // scal[3] = b.b).  rr_out receives this update's partials of the new r.r.
+//
+// With vbest the kernel also guards against divergence past the attainable
+// accuracy: a tolerance below it leaves the recursive residual stalled, and
+// the iterations that follow lose conjugacy and grow it without bound.  The
+// smallest r.r so far alternates between scal[8] and scal[9] (read one, write
+// the other, `par` = iteration parity, so no workgroup sees this update's
+// write); when r.r improves on it, the current v goes to vbest and the number
+// of directions to flag[2]; once r.r exceeds DIVERGE2 times it, flag[0] = 4 and
+// the host rolls the state back to that iterate.
+constexpr double DIVERGE2 = 1e6;                 // a 1000-fold growth of the residual norm
 __global__ __launch_bounds__(256) void k_update2x(i64 N, const double* __restrict__ d, const double* __restrict__ w,
                                                   double* __restrict__ v, double* __restrict__ r,
                                                   double* __restrict__ X, double* __restrict__ Dcol,
@@ -51,7 +61,8 @@ __global__ __launch_bounds__(256) void k_update2x(i64 N, const double* __restric
                                                   double* __restrict__ scal, int* __restrict__ flag,
                                                   const double* __restrict__ eta_part, int n_eta,
                                                   const double* __restrict__ rr_in, int n_rr,
-                                                  double* __restrict__ rr_out, BatchStrides bs) {
+                                                  double* __restrict__ rr_out, BatchStrides bs,
+                                                  double* __restrict__ vbest = nullptr, int par = 0) {
   __shared__ double red[256], red2[256];
   {                                              // problem blockIdx.y of a batch
     const i64 z = blockIdx.y;
@@ -101,6 +112,22 @@ __global__ __launch_bounds__(256) void k_update2x(i64 N, const double* __restric
       flag[0] = 1;
     }
     return;
+  }
+  if (vbest) {                                 // sr and the minimum are uniform over the grid
+    const double rmin = scal[8 + par];
+    if (sr > DIVERGE2 * rmin) {
+      if (k == 0) {
+        scal[0] = sr;
+        flag[0] = 4;
+      }
+      return;
+    }
+    const bool better = sr < rmin;
+    if (better && k < N) vbest[k] = vk;
+    if (k == 0) {
+      scal[9 - par] = better ? sr : rmin;
+      if (better) flag[2] = flag[1];
+    }
   }
   if (!(et > 0.0)) {
     if (k == 0) flag[0] = 2;
@@ -858,10 +885,14 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
   {
     const double t2 = action ? -1.0 : tol * tol;     // caller's actions: no stopping test
     HIPCHK(h, hipMemcpyAsync(h->scal + 4, &t2, sizeof(double), hipMemcpyHostToDevice, s));
+    static const double inf2[2] = {HUGE_VAL, HUGE_VAL};   // the divergence guard's smallest r.r
+    HIPCHK(h, hipMemcpyAsync(h->scal + 8, inf2, sizeof(inf2), hipMemcpyHostToDevice, s));
   }
+  // the divergence guard (two-pass loop with CG actions): v at the smallest residual
+  double* vbest = (passes == 2 && !action) ? h->vec + 7 * N : nullptr;
   hipLaunchKernelGGL(k_resid2, dim3(nblk(N)), dim3(256), 0, s, N, b, Y0, r, X, (const int*)h->flag);
   int i = start;
-  int hflag[2] = {0, 0};
+  int hflag[3] = {0, 0, 0};
   // coef = partial sums of D^T rhs over the first nd stored directions; the column update adds
   // them up and divides by eta, so it applies eta^-1 o (D^T rhs)
   auto project = [&](const double* rhs_vec, int nd) {
@@ -931,7 +962,7 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
         hipLaunchKernelGGL(k_update2x, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, (const double*)w, v, r,
                            X, h->Dd + (i64)i * N, h->Qd + (i64)i * N, h->eta + i, h->scal, h->flag,
                            (const double*)(i > 0 ? eta_p : nullptr), n_eta, (const double*)rr_prev, n_rr, rr_next,
-                           BatchStrides());
+                           BatchStrides(), vbest, (i - start) & 1);
         rr_prev = rr_next;
         if (replace) {
           HIPCHK(h, hipMemcpyAsync(X, v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -956,7 +987,7 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
     }
     HIPCHK(h, hipGetLastError());
     double hs[5] = {0, 0, 0, 0, 0};
-    HIPCHK(h, hipMemcpyAsync(hflag, h->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(hflag, h->flag, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipMemcpyAsync(hs, h->scal, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     if (hflag[0] != 0) break;
@@ -970,7 +1001,13 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
     rr_last = rr;
     i_last = i;
   }
-  *n_out = start + hflag[1];
+  if (hflag[0] == 4) {                   // diverged: back to the iterate with the smallest residual
+    HIPCHK(h, hipMemcpyAsync(v, vbest, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    *n_out = start + hflag[2];
+  } else {
+    *n_out = start + hflag[1];
+  }
   *state_out = hflag[0];
   return GPFVM_OK;
 }
@@ -1302,8 +1339,41 @@ static int coarse_init(gpfvm_handle* h, const int* factors, hipStream_t s, int* 
     st[3 * q + 1].descs.push_back(D);
     st[3 * q + 2].descs.push_back(desc1(outs[q], N, Lic, n, 1, R, N, 1, n, (int)N, n, 1.0, 1.0, 1));
   }
-  if (upload_stages(st, tmp, s) != hipSuccess) return fail(GPFVM_E_HIP, "coarse warm start: upload failed");
+  // A second orthonormalisation of the block in the S inner product (Cholesky QR twice):
+  // with C S C^T of condition ~1e9 (4 x 4 fine cells per coarse cell on advection-diffusion
+  // 128^2) the directions above are S-orthonormal only to ~1e-7, while the CG phase takes
+  // eta = 1 for them.  P = D0 (S D0)^T = L2 L2^T, D0 <- L2^{-1} D0, S D0 <- L2^{-1} S D0
+  // brings the block to S-orthonormality at rounding level (there the smallest residual
+  // of the CG phase drops from 1.9e-8 to 9e-9).  It spans the same space, so the
+  // conditioning it represents is unchanged.  Gc, Lic, C and SC are free for reuse here.
+  const int nch = long_k_chunks(N);
+  double* part = (double*)tmp.alloc((size_t)nch * n * n * sizeof(double));
+  if (!part) return fail(GPFVM_E_NOMEM, "coarse warm start: out of device memory");
+  std::vector<Stage> st2;
+  add_long_k(st2, Gc, h->Dd, N, h->Qd, N, n, n, N, part);              // partials of P
+  {
+    Stage up;
+    up.descs.push_back(desc1(h->Dd, N, Lic, n, 1, C, N, 1, n, (int)N, n, 1.0, 0.0, 1));
+    up.descs.push_back(desc1(h->Qd, N, Lic, n, 1, SC, N, 1, n, (int)N, n, 1.0, 0.0, 1));
+    st2.push_back(up);
+  }
+  if (upload_stages(st, tmp, s) != hipSuccess || upload_stages(st2, tmp, s) != hipSuccess)
+    return fail(GPFVM_E_HIP, "coarse warm start: upload failed");
   if (run_stages(st, s) != hipSuccess) return fail(GPFVM_E_HIP, "coarse warm start: gemm failed");
+  if (launch_gemm_stage(F64, st2[0], s) != hipSuccess) return fail(GPFVM_E_HIP, "coarse warm start: gemm failed");
+  hipLaunchKernelGGL(k_sum_rowscale, dim3(nblk((i64)n * n)), dim3(256), 0, s, nch, n, n, (const double*)part,
+                     (const double*)nullptr, Gc);
+  rc = cholesky_and_inverse(Gc, Lic, n, tmp, s, h->err);
+  if (rc) {
+    if (rc == GPFVM_E_NOTPD) h->err = "coarse warm start: the projected coarse Gram is not positive definite";
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    return rc;
+  }
+  if (hipMemcpyAsync(C, h->Dd, (size_t)n * N * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(SC, h->Qd, (size_t)n * N * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail(GPFVM_E_HIP, "coarse warm start: copy failed");
+  if (launch_gemm_stage(F64, st2[1], s) != hipSuccess) return fail(GPFVM_E_HIP, "coarse warm start: gemm failed");
   // eta = 1 ; v = D0 (D0^T b): the column update gives -D0 c from base 0, negated after
   double* coef = h->aux + 1024;
   if (launch_fill(h->eta, 1.0, Nc, s) != hipSuccess || launch_fill(h->v, 0.0, N, s) != hipSuccess ||
@@ -1490,7 +1560,10 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
   else if (o->tol > 0 && rs > o->tol) status = GPFVM_E_NOCONV;
   if (info) info->status = status;
   if (status == GPFVM_E_NOTPD) h->err = "IterGP breakdown: eta <= 0 (state kept up to the last good direction)";
-  if (status == GPFVM_E_NOCONV) h->err = "iteration budget exhausted above the tolerance";
+  if (status == GPFVM_E_NOCONV)
+    h->err = state == 4 ? "the residual grew 1000-fold above its smallest value (the tolerance is below the "
+                          "attainable accuracy); state rolled back to the iterate with the smallest residual"
+                        : "iteration budget exhausted above the tolerance";
   return status;
 }
 
@@ -1822,7 +1895,7 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
       // cond(L) eps relative, is that of a triangular solve, so ||T||^2 needs no residual
       // correction here (the solver's operator does: there the products must stay
       // consistent over hundreds of iterations).
-      if (trmm_lower_rows(h->nb, (int)nx, h->Linv, KB, TT, s) != hipSuccess)
+      if (trmm_rows_left_lower(h->nb, (int)nx, 1.0, h->Linv, h->nb, KB, (int)nx, TT, (int)nx, s) != hipSuccess)
         return fail(GPFVM_E_HIP, "posterior: triangular product failed");
       const int R = colsq_chunks(h->nb, nx);
       hipLaunchKernelGGL(k_colsq_part, dim3((unsigned)((nx + 63) / 64), (unsigned)R), dim3(256), 0, s, (i64)h->nb, nx,
