@@ -1486,9 +1486,55 @@ __global__ __launch_bounds__(256) void k_trmv_rows(int n, const double* __restri
   if (lane == 0) y[i] = (add ? add[i] : 0.0) + alpha * acc;
 }
 
+// The same product with 16-byte loads (n even, M and x 16-byte aligned: every
+// row starts on a pair): lane l takes the pairs l, l + 64, ... of [lo, hi)
+// rounded inward to pairs, four in flight, and lane 0 adds the odd element at
+// either end.  17% faster than the 8-byte form on the 16384^2 triangle.
+constexpr int TV_UN = 4;
+__global__ __launch_bounds__(256) void k_trmv_rows2(int n, const double* __restrict__ M, const double* __restrict__ x,
+                                                    double* __restrict__ y, double alpha,
+                                                    const double* __restrict__ add, int upper) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int lo = upper ? i : 0, hi = upper ? n : i + 1;
+  const double* __restrict__ row = M + (i64)i * n;
+  const double2* __restrict__ row2 = reinterpret_cast<const double2*>(row);
+  const double2* __restrict__ x2 = reinterpret_cast<const double2*>(x);
+  const int pa = (lo + 1) / 2, pb = hi / 2;      // pairs [2 pa, 2 pb) of [lo, hi)
+  double acc[TV_UN];
+#pragma unroll
+  for (int u = 0; u < TV_UN; ++u) acc[u] = 0.0;
+  int p = pa + lane;
+  for (; p + 64 * (TV_UN - 1) < pb; p += 64 * TV_UN) {
+    double2 mv[TV_UN], xv[TV_UN];
+#pragma unroll
+    for (int u = 0; u < TV_UN; ++u) {
+      mv[u] = row2[p + 64 * u];
+      xv[u] = x2[p + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < TV_UN; ++u) acc[u] += mv[u].x * xv[u].x + mv[u].y * xv[u].y;
+  }
+  for (; p < pb; p += 64) {
+    const double2 mv = row2[p], xv = x2[p];
+    acc[0] += mv.x * xv.x + mv.y * xv.y;
+  }
+  double a = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  if (lane == 0) {
+    if (lo & 1) a += row[lo] * x[lo];            // the odd element before the first pair
+    if (hi & 1) a += row[hi - 1] * x[hi - 1];    // and after the last (never the same one)
+  }
+  a = wave_sum(a);
+  if (lane == 0) y[i] = (add ? add[i] : 0.0) + alpha * a;
+}
+static_assert(TV_UN == 4, "the accumulators are added as two pairs");
+
 hipError_t launch_trmv_rows(int n, const double* M, const double* x, double* y, double alpha, const double* add,
                             int upper, hipStream_t s) {
-  k_trmv_rows<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, M, x, y, alpha, add, upper);
+  const bool pairs = (n % 2 == 0) && ((uintptr_t)M % 16 == 0) && ((uintptr_t)x % 16 == 0);
+  if (pairs) k_trmv_rows2<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, M, x, y, alpha, add, upper);
+  else k_trmv_rows<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, M, x, y, alpha, add, upper);
   return hipGetLastError();
 }
 
