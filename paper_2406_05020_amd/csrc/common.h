@@ -270,12 +270,13 @@ hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const 
 hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s);
 // Streaming products with a row-major nr x N matrix M:
 //   rows_dot:    part[j * nch + ch] = sum_{k in chunk ch} M[j][k] x[k], nch = rows_dot_chunks(nr, N)
-//                (part holds nr * nch <= nr + 527 values)
+//                (part holds nr * nch <= nr + ROWS_DOT_TARGET - 1 values)
 //   rows_dot_full: out[j] = sum_k M[j][k] x[k]
 //   cols_update: u_j = (sum_ch u[j * u_nch + ch]) / (eta ? eta[j] : 1);
 //                out[c] = base[c] - sum_j M[j][c] u_j (and out2[c] = out[c] if out2);
 //                with M2: out3[c] = base2[c] - sum_j M2[j][c] u_j.   base may alias out.
 //   (rows_dot with xm: the dots are taken with x - xm)
+constexpr int ROWS_DOT_TARGET = 2048;   // workgroups a row-dot launch aims at
 int rows_dot_chunks(int nr, i64 N);
 hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, double* part, hipStream_t s,
                            const double* xm = nullptr, int batch = 1, const BatchStrides& bs = BatchStrides());

@@ -1304,18 +1304,69 @@ constexpr int CU_MAXCH = 16;   // most partial sums per coefficient (rows_dot_ch
 // (k_cols_update) adds the nch partials of a row in order.
 constexpr int RP_THREADS = 256;
 
+// dot_range over pairs: q, x (and xm) 16-byte aligned, c_lo and c_hi even.
+// RD2_U 16-byte loads of each vector in flight per thread, then the same
+// fixed-order reduction.
+constexpr int RD2_U = 8;
+template <int NT>
+__device__ __forceinline__ double dot_range2(const double* __restrict__ q, const double* __restrict__ x, i64 c_lo,
+                                             i64 c_hi, double* red, const double* __restrict__ xm) {
+  const double2* __restrict__ q2 = reinterpret_cast<const double2*>(q);
+  const double2* __restrict__ x2 = reinterpret_cast<const double2*>(x);
+  const double2* __restrict__ m2 = reinterpret_cast<const double2*>(xm);
+  const i64 plo = c_lo / 2, phi = c_hi / 2;
+  double acc[RD2_U];
+#pragma unroll
+  for (int u = 0; u < RD2_U; ++u) acc[u] = 0.0;
+  for (i64 p0 = plo + threadIdx.x; p0 < phi; p0 += (i64)NT * RD2_U) {
+    double2 qv[RD2_U], xv[RD2_U];
+#pragma unroll
+    for (int u = 0; u < RD2_U; ++u) {
+      const i64 p = p0 + (i64)u * NT;
+      qv[u] = p < phi ? q2[p] : make_double2(0.0, 0.0);
+      xv[u] = p < phi ? x2[p] : make_double2(0.0, 0.0);
+    }
+    if (xm) {
+#pragma unroll
+      for (int u = 0; u < RD2_U; ++u) {
+        const i64 p = p0 + (i64)u * NT;
+        const double2 mv = p < phi ? m2[p] : make_double2(0.0, 0.0);
+        xv[u].x -= mv.x;
+        xv[u].y -= mv.y;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RD2_U; ++u) acc[u] = fma(qv[u].y, xv[u].y, fma(qv[u].x, xv[u].x, acc[u]));
+  }
+#pragma unroll
+  for (int w = RD2_U / 2; w > 0; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) acc[u] += acc[u + w];
+  double v = acc[0];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+  return s;
+}
+
+// pairs: every chunk starts and ends on a pair (N even, the vectors 16-byte aligned)
 __global__ __launch_bounds__(RP_THREADS) void k_rows_dot(i64 N, int nch, const double* __restrict__ M,
                                                          const double* __restrict__ x, const double* __restrict__ xm,
-                                                         double* __restrict__ part, BatchStrides bs) {
+                                                         double* __restrict__ part, BatchStrides bs, int pairs) {
   __shared__ double red[RP_THREADS / 64];
   M += blockIdx.y * bs.M;
   x += blockIdx.y * bs.v;
   if (xm) xm += blockIdx.y * bs.v;
   part += blockIdx.y * bs.u;
   const int row = (int)(blockIdx.x / nch), ch = (int)(blockIdx.x % nch);
-  const i64 L = (N + nch - 1) / nch;
-  const i64 lo = (i64)ch * L, hi = min(N, lo + L);
-  const double s = dot_range<RP_THREADS>(M + (i64)row * N, x, lo, hi, red, xm);
+  i64 L = (N + nch - 1) / nch;
+  if (pairs) L = (L + 1) & ~(i64)1;
+  const i64 lo = min(N, (i64)ch * L), hi = min(N, lo + L);
+  const double s = pairs ? dot_range2<RP_THREADS>(M + (i64)row * N, x, lo, hi, red, xm)
+                         : dot_range<RP_THREADS>(M + (i64)row * N, x, lo, hi, red, xm);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -1420,7 +1471,7 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
 
 int rows_dot_chunks(int nr, i64 N) {
   if (nr <= 0) return 1;
-  const i64 by_rows = (512 + nr - 1) / nr;           // aim at >= 512 workgroups
+  const i64 by_rows = (ROWS_DOT_TARGET + nr - 1) / nr;
   const i64 by_len = std::max<i64>(1, (N + 2047) / 2048);   // chunks of >= 2048 columns
   return (int)std::max<i64>(1, std::min<i64>(16, std::min(by_rows, by_len)));
 }
@@ -1429,13 +1480,16 @@ hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, doub
                            const double* xm, int batch, const BatchStrides& bs) {
   if (nr <= 0 || N <= 0) return hipSuccess;
   const int nch = rows_dot_chunks(nr, N);
-  k_rows_dot<<<dim3((unsigned)((i64)nr * nch), batch), dim3(RP_THREADS), 0, s>>>(N, nch, M, x, xm, part, bs);
+  const auto al = [](const void* p) { return (uintptr_t)p % 16 == 0; };
+  const bool odd_stride = (bs.M % 2) || (bs.v % 2);
+  const int pairs = (N % 2 == 0) && !odd_stride && al(M) && al(x) && (!xm || al(xm));
+  k_rows_dot<<<dim3((unsigned)((i64)nr * nch), batch), dim3(RP_THREADS), 0, s>>>(N, nch, M, x, xm, part, bs, pairs);
   return hipGetLastError();
 }
 
 hipError_t launch_rows_dot_full(int nr, i64 N, const double* M, const double* x, double* out, hipStream_t s) {
   if (nr <= 0 || N <= 0) return hipSuccess;
-  k_rows_dot<<<dim3((unsigned)nr), dim3(RP_THREADS), 0, s>>>(N, 1, M, x, nullptr, out, BatchStrides());
+  k_rows_dot<<<dim3((unsigned)nr), dim3(RP_THREADS), 0, s>>>(N, 1, M, x, nullptr, out, BatchStrides(), 0);
   return hipGetLastError();
 }
 

@@ -812,8 +812,8 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
   h->Dd = (double*)h->arena.alloc((size_t)N * h->max_iter * sizeof(double));
   h->eta = (double*)h->arena.alloc(h->max_iter * sizeof(double));
   h->vec = (double*)h->arena.alloc((size_t)8 * N * sizeof(double));
-  // 1024 dot partials, then the row-dot partials of the projections (<= max_iter + 527)
-  h->aux = (double*)h->arena.alloc((size_t)(2048 + h->max_iter) * sizeof(double));
+  // 1024 dot partials, then the row-dot partials of the projections (<= max_iter + ROWS_DOT_TARGET - 1)
+  h->aux = (double*)h->arena.alloc((size_t)(1024 + ROWS_DOT_TARGET + h->max_iter) * sizeof(double));
   h->scal = (double*)h->arena.alloc(64 * sizeof(double));
   h->flag = (int*)h->arena.alloc(16 * sizeof(int));
   h->part = (double*)h->arena.alloc((size_t)((N + 63) / 64 + 2 * nblk(N) + 1) * sizeof(double));
@@ -1978,7 +1978,7 @@ int gpfvm::batch_solve(gpfvm_handle* h, int R, const double* yobs_host, double t
   B = GpfvmBatch();
   B.R = R;
   const int n_eta = (int)((N + 63) / 64), n_rr = (int)nblk(N);
-  const i64 ucap = cap + 528, pstride = n_eta + 2 * (i64)n_rr;
+  const i64 ucap = cap + ROWS_DOT_TARGET, pstride = n_eta + 2 * (i64)n_rr;
   auto A = [&](size_t bytes) { return h->arena.alloc(bytes); };
   B.yobs = (double*)A((size_t)R * n * 8);
   B.bS = (double*)A((size_t)R * N * 8);
