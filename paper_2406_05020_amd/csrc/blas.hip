@@ -62,4 +62,16 @@ hipError_t trmm_rows_right_lower(int m, int k, double alpha, const double* T, in
   return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
 }
 
+// C -= A A^T on the lower triangle: C row-major n x n (leading dimension ldc),
+// A row-major n x k (leading dimension lda).  Column-major, C^T is upper and
+// the update is (A^T)^T (A^T): an upper SYRK with the transposed operand.
+hipError_t syrk_rows_lower_sub(int n, int k, const double* A, int lda, double* C, int ldc, hipStream_t s) {
+  rocblas_handle hd = handle_for(s);
+  if (!hd) return hipErrorNotInitialized;
+  const double minus_one = -1.0, one = 1.0;
+  const rocblas_status st = rocblas_dsyrk(hd, rocblas_fill_upper, rocblas_operation_transpose, n, k, &minus_one, A, lda,
+                                          &one, C, ldc);
+  return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+}
+
 }  // namespace gpfvm

@@ -87,61 +87,57 @@ hipError_t launch_gram_block(const GramMeta* meta, i64 r0, i64 nr, i64 c0, i64 n
 // ---------------------------------------------------------------------------
 // Diagonal block of the blocked Cholesky: factor the nb x nb block at (k0,k0)
 // in LDS, write L_kk back and the inverse of L_kk into dinv (NB x NB, row-major).
-// Sets *flag = 1 + k0 + j on the first non-positive pivot j.
+// Sets *flag = 1 + k0 if a pivot of the block is not positive.
 // ---------------------------------------------------------------------------
 constexpr int NB = 64;
 
-__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ A, i64 ld, int k0, int nb,
-                                                    double* __restrict__ dinv, int* __restrict__ flag) {
+// One wavefront: lane i owns row i while factoring, lane c owns column c of the
+// inverse.  Each element takes the same operations in the same order as the
+// textbook right-looking loop and the forward substitution.
+constexpr int PD_THREADS = 64;
+static_assert(PD_THREADS == NB, "one lane per row / column of the diagonal block");
+__global__ __launch_bounds__(PD_THREADS) void k_potrf_diag(double* __restrict__ A, i64 ld, int k0, int nb,
+                                                           double* __restrict__ dinv, int* __restrict__ flag) {
   __shared__ double L[NB][NB + 1];
   __shared__ double V[NB][NB + 1];
-  const int t = threadIdx.x, ty = t >> 4, tx = t & 15;     // 16 x 16 threads, 4 x 4 elements each
-  for (int e = t; e < NB * NB; e += blockDim.x) {
+  const int t = threadIdx.x;
+  for (int e = t; e < NB * NB; e += PD_THREADS) {
     const int i = e / NB, j = e % NB;
     L[i][j] = (i < nb && j < nb) ? A[(i64)(k0 + i) * ld + k0 + j] : (i == j ? 1.0 : 0.0);
-    V[i][j] = (i == j) ? 1.0 : 0.0;
+    V[i][j] = 0.0;
   }
   __syncthreads();
   if (*flag != 0) return;            // an earlier block already failed
-  // right-looking Cholesky: column j is scaled, then the trailing lower triangle
-  // takes the rank-1 update, each thread on its fixed 4 x 4 set of elements
+  // right-looking Cholesky: column j is scaled, then row t takes the rank-1 update
   int bad = 0;
   for (int j = 0; j < nb; ++j) {
-    const double p = L[j][j];          // the same value in every thread
+    const double p = L[j][j];          // the same value in every lane
     if (!(p > 0.0)) { bad = 1; break; }
     const double dj = sqrt(p);
-    __syncthreads();                   // every thread has read the pivot
-    for (int i = j + t; i < nb; i += blockDim.x) L[i][j] = (i == j) ? dj : L[i][j] / dj;
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int i = ty + 16 * a, c = tx + 16 * b;
-        if (i < nb && c > j && c <= i) L[i][c] -= L[i][j] * L[c][j];
-      }
+    double lij = 0.0;
+    if (t > j && t < nb) {
+      lij = L[t][j] / dj;
+      L[t][j] = lij;
+    }
+    __syncthreads();                   // every lane has read the pivot; column j is scaled
+    if (t == j) L[j][j] = dj;
+    if (t > j && t < nb)
+      for (int c = j + 1; c <= t; ++c) L[t][c] -= lij * L[c][j];
     __syncthreads();
   }
   if (bad) {
     if (t == 0) atomicCAS(flag, 0, 1 + k0);
     return;
   }
-  // inverse by forward elimination on [L | I]: row j of V is divided by L[j][j],
-  // then subtracted from the rows below with multipliers L[i][j]
-  for (int j = 0; j < nb; ++j) {
-    const double dj = L[j][j];
-    if (t <= j) V[j][t] /= dj;
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int i = ty + 16 * a, c = tx + 16 * b;
-        if (i > j && i < nb && c <= j) V[i][c] -= L[i][j] * V[j][c];
-      }
-    __syncthreads();
-  }
-  for (int e = t; e < NB * NB; e += blockDim.x) {
+  // column t of the inverse by forward substitution (no other lane's data)
+  if (t < nb)
+    for (int k = t; k < nb; ++k) {
+      double v = (k == t) ? 1.0 : 0.0;
+      for (int m = t; m < k; ++m) v -= L[k][m] * V[m][t];
+      V[k][t] = v / L[k][k];
+    }
+  __syncthreads();
+  for (int e = t; e < NB * NB; e += PD_THREADS) {
     const int i = e / NB, j = e % NB;
     if (i < nb && j < nb) A[(i64)(k0 + i) * ld + k0 + j] = (j <= i) ? L[i][j] : 0.0;
     dinv[e] = (i < nb && j < nb && j <= i) ? V[i][j] : 0.0;
@@ -281,38 +277,50 @@ hipError_t upload_stages(std::vector<Stage>& stages, Arena& arena, hipStream_t s
 
 // Blocked right-looking Cholesky of the n x n matrix A (row-major, lower),
 // then L^{-1} into Linv.  Returns GPFVM_OK / GPFVM_E_NOTPD / GPFVM_E_HIP.
+//
+// The columns go in panels of PANEL = 8 blocks of 64.  Inside a panel each
+// 64-column block is factored (diagonal block in LDS, explicit inverse of it),
+// its rows below are solved with that inverse, and only the rest of the panel
+// takes the block's rank-64 update; the trailing matrix takes the panel's
+// rank-512 update at once (a library SYRK).  Same arithmetic as updating the
+// whole trailing matrix after every block, with one eighth of its traffic.
+constexpr int PANEL = 8 * NB;
 int cholesky_and_inverse(double* A, double* Linv, int n, Arena& arena, hipStream_t s, std::string& err) {
   if (n == 0) return GPFVM_OK;
   const int nblk = (n + NB - 1) / NB;
   double* dinv = (double*)arena.alloc((size_t)nblk * NB * NB * sizeof(double));
   double* panel = (double*)arena.alloc((size_t)n * NB * sizeof(double));
-  double* tmp = (double*)arena.alloc((size_t)n * NB * sizeof(double));
   int* flag = (int*)arena.alloc(sizeof(int));
-  if (!dinv || !panel || !tmp || !flag) { err = "out of device memory (Cholesky workspace)"; return GPFVM_E_NOMEM; }
+  if (!dinv || !panel || !flag) { err = "out of device memory (Cholesky workspace)"; return GPFVM_E_NOMEM; }
   if (hipMemsetAsync(flag, 0, sizeof(int), s) != hipSuccess) return GPFVM_E_HIP;
 
-  // descriptors: per block k, a panel GEMM and a trailing update
+  // descriptors: per block k, the solve of the rows below it and the update of the rest of its panel
   std::vector<Stage> st(2 * nblk);
   for (int k = 0; k < nblk; ++k) {
     const int k0 = k * NB, nbk = std::min(NB, n - k0), r0 = k0 + nbk, mr = n - r0;
-    if (mr > 0) {
-      // L_panel = panel_copy * Dinv_k^T
+    const int pe = std::min(n, (k0 / PANEL + 1) * PANEL), pc = pe - r0;
+    if (mr > 0)       // L_rows = panel_copy * Dinv_k^T
       st[2 * k].descs.push_back(mk_desc(A + (i64)r0 * n + k0, n, panel, NB, 1, dinv + (i64)k * NB * NB, 1, NB,
                                         mr, nbk, nbk, 1.0, 0.0, 0, 0));
-      // A22 -= L_panel L_panel^T (lower tiles)
+    if (pc > 0)       // A[r0:, r0:pe] -= L_rows L_rows[0:pc]^T (lower tiles)
       st[2 * k + 1].descs.push_back(mk_desc(A + (i64)r0 * n + r0, n, A + (i64)r0 * n + k0, n, 1,
-                                            A + (i64)r0 * n + k0, 1, n, mr, mr, nbk, -1.0, 1.0, 1, 0));
-    }
+                                            A + (i64)r0 * n + k0, 1, n, mr, pc, nbk, -1.0, 1.0, 1, 0));
   }
   if (upload_stages(st, arena, s) != hipSuccess) { err = "descriptor upload failed"; return GPFVM_E_HIP; }
   for (int k = 0; k < nblk; ++k) {
     const int k0 = k * NB, nbk = std::min(NB, n - k0), r0 = k0 + nbk, mr = n - r0;
-    k_potrf_diag<<<1, 256, 0, s>>>(A, n, k0, nbk, dinv + (i64)k * NB * NB, flag);
+    const int p0 = (k0 / PANEL) * PANEL, pe = std::min(n, p0 + PANEL);
+    k_potrf_diag<<<1, PD_THREADS, 0, s>>>(A, n, k0, nbk, dinv + (i64)k * NB * NB, flag);
     if (mr > 0) {
       const i64 tot = (i64)mr * nbk;
       k_copy2d<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(A + (i64)r0 * n + k0, n, panel, NB, mr, nbk);
       if (launch_gemm_stage(F64, st[2 * k], s) != hipSuccess) return GPFVM_E_HIP;
-      if (launch_gemm_stage(F64, st[2 * k + 1], s) != hipSuccess) return GPFVM_E_HIP;
+      if (r0 < pe && launch_gemm_stage(F64, st[2 * k + 1], s) != hipSuccess) return GPFVM_E_HIP;
+    }
+    if (r0 == pe && pe < n &&          // the panel is done: the trailing matrix takes its update
+        syrk_rows_lower_sub(n - pe, pe - p0, A + (i64)pe * n + p0, n, A + (i64)pe * n + pe, n, s) != hipSuccess) {
+      err = "Cholesky trailing update failed";
+      return GPFVM_E_HIP;
     }
   }
   int hflag = 0;

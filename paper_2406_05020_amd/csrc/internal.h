@@ -68,6 +68,8 @@ hipError_t trmm_rows_left_lower(int m, int k, double alpha, const double* T, int
                                 double* C, int ldc, hipStream_t s);
 hipError_t trmm_rows_right_lower(int m, int k, double alpha, const double* T, int ldt, const double* B, int ldb,
                                  double* C, int ldc, hipStream_t s);
+// C -= A A^T on the lower triangle (C row-major n x n, A row-major n x k)
+hipError_t syrk_rows_lower_sub(int n, int k, const double* A, int lda, double* C, int ldc, hipStream_t s);
 
 // batched solve of problems sharing the handle's operator (solver.hip)
 struct BatchResult {
