@@ -42,24 +42,33 @@ rocblas_handle handle_for(hipStream_t s) {
 // on the other.
 
 // C = alpha T B: T row-major m x m lower-triangular, B and C row-major m x k
-// (C and B distinct).
+// (C and B distinct).  batch > 1: that many products, the operands st, sb, sc
+// elements apart.
 hipError_t trmm_rows_left_lower(int m, int k, double alpha, const double* T, int ldt, const double* B, int ldb,
-                                double* C, int ldc, hipStream_t s) {
+                                double* C, int ldc, hipStream_t s, int batch, i64 st, i64 sb, i64 sc) {
   rocblas_handle hd = handle_for(s);
   if (!hd) return hipErrorNotInitialized;
-  const rocblas_status st = rocblas_dtrmm(hd, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                                          rocblas_diagonal_non_unit, k, m, &alpha, T, ldt, B, ldb, C, ldc);
-  return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+  const rocblas_status r =
+      batch > 1 ? rocblas_dtrmm_strided_batched(hd, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                                                rocblas_diagonal_non_unit, k, m, &alpha, T, ldt, st, B, ldb, sb, C, ldc,
+                                                sc, batch)
+                : rocblas_dtrmm(hd, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                                rocblas_diagonal_non_unit, k, m, &alpha, T, ldt, B, ldb, C, ldc);
+  return r == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
 }
 
 // C = alpha B T: B and C row-major m x k (distinct), T row-major k x k lower-triangular.
 hipError_t trmm_rows_right_lower(int m, int k, double alpha, const double* T, int ldt, const double* B, int ldb,
-                                 double* C, int ldc, hipStream_t s) {
+                                 double* C, int ldc, hipStream_t s, int batch, i64 st, i64 sb, i64 sc) {
   rocblas_handle hd = handle_for(s);
   if (!hd) return hipErrorNotInitialized;
-  const rocblas_status st = rocblas_dtrmm(hd, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                                          rocblas_diagonal_non_unit, k, m, &alpha, T, ldt, B, ldb, C, ldc);
-  return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+  const rocblas_status r =
+      batch > 1 ? rocblas_dtrmm_strided_batched(hd, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                                                rocblas_diagonal_non_unit, k, m, &alpha, T, ldt, st, B, ldb, sb, C, ldc,
+                                                sc, batch)
+                : rocblas_dtrmm(hd, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                                rocblas_diagonal_non_unit, k, m, &alpha, T, ldt, B, ldb, C, ldc);
+  return r == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
 }
 
 // C -= A A^T on the lower triangle: C row-major n x n (leading dimension ldc),

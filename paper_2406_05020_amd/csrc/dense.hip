@@ -91,64 +91,71 @@ hipError_t launch_gram_block(const GramMeta* meta, i64 r0, i64 nr, i64 c0, i64 n
 // ---------------------------------------------------------------------------
 constexpr int NB = 64;
 
-// One wavefront: lane i owns row i while factoring, lane c owns column c of the
-// inverse.  Each element takes the same operations in the same order as the
-// textbook right-looking loop and the forward substitution.
-constexpr int PD_THREADS = 64;
-static_assert(PD_THREADS == NB, "one lane per row / column of the diagonal block");
-__global__ __launch_bounds__(PD_THREADS) void k_potrf_diag(double* __restrict__ A, i64 ld, int k0, int nb,
-                                                           double* __restrict__ dinv, int* __restrict__ flag) {
+__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ A, i64 ld, int k0, int nb,
+                                                    double* __restrict__ dinv, int* __restrict__ flag) {
   __shared__ double L[NB][NB + 1];
   __shared__ double V[NB][NB + 1];
-  const int t = threadIdx.x;
-  for (int e = t; e < NB * NB; e += PD_THREADS) {
+  const int t = threadIdx.x, ty = t >> 4, tx = t & 15;     // 16 x 16 threads, 4 x 4 elements each
+  for (int e = t; e < NB * NB; e += blockDim.x) {
     const int i = e / NB, j = e % NB;
     L[i][j] = (i < nb && j < nb) ? A[(i64)(k0 + i) * ld + k0 + j] : (i == j ? 1.0 : 0.0);
-    V[i][j] = 0.0;
+    V[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   if (*flag != 0) return;            // an earlier block already failed
-  // right-looking Cholesky: column j is scaled, then row t takes the rank-1 update
+  // right-looking Cholesky: column j is scaled, then the trailing lower triangle
+  // takes the rank-1 update, each thread on its fixed 4 x 4 set of elements
   int bad = 0;
   for (int j = 0; j < nb; ++j) {
-    const double p = L[j][j];          // the same value in every lane
+    const double p = L[j][j];          // the same value in every thread
     if (!(p > 0.0)) { bad = 1; break; }
     const double dj = sqrt(p);
-    double lij = 0.0;
-    if (t > j && t < nb) {
-      lij = L[t][j] / dj;
-      L[t][j] = lij;
-    }
-    __syncthreads();                   // every lane has read the pivot; column j is scaled
-    if (t == j) L[j][j] = dj;
-    if (t > j && t < nb)
-      for (int c = j + 1; c <= t; ++c) L[t][c] -= lij * L[c][j];
+    __syncthreads();                   // every thread has read the pivot
+    for (int i = j + t; i < nb; i += blockDim.x) L[i][j] = (i == j) ? dj : L[i][j] / dj;
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = ty + 16 * a, c = tx + 16 * b;
+        if (i < nb && c > j && c <= i) L[i][c] -= L[i][j] * L[c][j];
+      }
     __syncthreads();
   }
   if (bad) {
     if (t == 0) atomicCAS(flag, 0, 1 + k0);
     return;
   }
-  // column t of the inverse by forward substitution (no other lane's data)
-  if (t < nb)
-    for (int k = t; k < nb; ++k) {
-      double v = (k == t) ? 1.0 : 0.0;
-      for (int m = t; m < k; ++m) v -= L[k][m] * V[m][t];
-      V[k][t] = v / L[k][k];
-    }
-  __syncthreads();
-  for (int e = t; e < NB * NB; e += PD_THREADS) {
+  // inverse by forward elimination on [L | I]: row j of V is divided by L[j][j],
+  // then subtracted from the rows below with multipliers L[i][j]
+  for (int j = 0; j < nb; ++j) {
+    const double dj = L[j][j];
+    if (t <= j) V[j][t] /= dj;
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = ty + 16 * a, c = tx + 16 * b;
+        if (i > j && i < nb && c <= j) V[i][c] -= L[i][j] * V[j][c];
+      }
+    __syncthreads();
+  }
+  for (int e = t; e < NB * NB; e += blockDim.x) {
     const int i = e / NB, j = e % NB;
     if (i < nb && j < nb) A[(i64)(k0 + i) * ld + k0 + j] = (j <= i) ? L[i][j] : 0.0;
     dinv[e] = (i < nb && j < nb && j <= i) ? V[i][j] : 0.0;
   }
 }
 
-// dst[i][j] += alpha src[i][j] over an r x c block (row-major, leading dimensions sld, dld)
+// dst[i][j] += alpha src[i][j] over an r x c block (row-major, leading dimensions sld, dld),
+// for blockIdx.y blocks src_bs and dst_bs elements apart
 __global__ void k_axpy2d(const double* __restrict__ src, i64 sld, double* __restrict__ dst, i64 dld, i64 r, i64 c,
-                         double alpha) {
+                         double alpha, i64 src_bs = 0, i64 dst_bs = 0) {
   const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= r * c) return;
+  src += blockIdx.y * src_bs;
+  dst += blockIdx.y * dst_bs;
   const i64 i = t / c, j = t % c;
   dst[i * dld + j] += alpha * src[i * sld + j];
 }
@@ -310,7 +317,7 @@ int cholesky_and_inverse(double* A, double* Linv, int n, Arena& arena, hipStream
   for (int k = 0; k < nblk; ++k) {
     const int k0 = k * NB, nbk = std::min(NB, n - k0), r0 = k0 + nbk, mr = n - r0;
     const int p0 = (k0 / PANEL) * PANEL, pe = std::min(n, p0 + PANEL);
-    k_potrf_diag<<<1, PD_THREADS, 0, s>>>(A, n, k0, nbk, dinv + (i64)k * NB * NB, flag);
+    k_potrf_diag<<<1, 256, 0, s>>>(A, n, k0, nbk, dinv + (i64)k * NB * NB, flag);
     if (mr > 0) {
       const i64 tot = (i64)mr * nbk;
       k_copy2d<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(A + (i64)r0 * n + k0, n, panel, NB, mr, nbk);
@@ -383,7 +390,31 @@ int cholesky_and_inverse(double* A, double* Linv, int n, Arena& arena, hipStream
     k_axpy2d<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(W, n1, X21, n, n2, n1, -1.0);
     return hipGetLastError();
   };
-  const hipError_t ie = inv(0, nblk);
+  // With n = 64 * 2^l the tree is balanced: the nodes of one level have equal sizes and
+  // equal strides, and each level runs as six batched launches instead of six per node.
+  auto levels = [&]() -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (int sz = 2; sz <= nblk && e == hipSuccess; sz *= 2) {
+      const int count = nblk / sz, n1 = sz / 2 * NB, n2 = n1;
+      const i64 m = (i64)n2 * n1, nodes = (i64)sz * NB * (n + 1), ws = m;   // node stride on the diagonal
+      const double* X11 = Linv;
+      const double* X22 = Linv + (i64)n1 * (n + 1);
+      const double* L21 = A + (i64)n1 * n;
+      const double* L22 = A + (i64)n1 * (n + 1);
+      double* X21 = Linv + (i64)n1 * n;
+      if ((e = trmm_rows_right_lower(n2, n1, 1.0, X11, n, L21, n, W, n1, s, count, nodes, nodes, ws)) != hipSuccess ||
+          (e = trmm_rows_left_lower(n2, n1, -1.0, X22, n, W, n1, X21, n, s, count, nodes, ws, nodes)) != hipSuccess ||
+          (e = trmm_rows_left_lower(n2, n1, 1.0, L22, n, X21, n, R, n1, s, count, nodes, nodes, ws)) != hipSuccess ||
+          (e = launch_axpby(m * count, 1.0, W, 1.0, R, s)) != hipSuccess ||
+          (e = trmm_rows_left_lower(n2, n1, 1.0, X22, n, R, n1, W, n1, s, count, nodes, ws, ws)) != hipSuccess)
+        return e;
+      k_axpy2d<<<dim3((unsigned)((m + 255) / 256), (unsigned)count), 256, 0, s>>>(W, n1, X21, n, n2, n1, -1.0, ws, nodes);
+      e = hipGetLastError();
+    }
+    return e;
+  };
+  const bool balanced = (n % NB == 0) && ((nblk & (nblk - 1)) == 0);
+  const hipError_t ie = balanced ? levels() : inv(0, nblk);
   const hipError_t se = hipStreamSynchronize(s);
   work.release();
   if (ie != hipSuccess || se != hipSuccess) { err = "triangular inverse failed"; return GPFVM_E_HIP; }

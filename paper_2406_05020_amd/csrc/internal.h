@@ -64,10 +64,12 @@ hipError_t run_stages(const std::vector<Stage>& st, hipStream_t s);
 hipError_t ginv_rows(const gpfvm_handle* h, const double* U, double* T, double* W, double* R, hipStream_t s);
 // rocBLAS triangular products (blas.hip) on row-major matrices, T lower-triangular,
 // C distinct from B: C = alpha T B (T m x m; B, C m x k) and C = alpha B T (B, C m x k; T k x k)
+// (batch > 1: that many products, operands st, sb, sc elements apart)
 hipError_t trmm_rows_left_lower(int m, int k, double alpha, const double* T, int ldt, const double* B, int ldb,
-                                double* C, int ldc, hipStream_t s);
+                                double* C, int ldc, hipStream_t s, int batch = 1, i64 st = 0, i64 sb = 0, i64 sc = 0);
 hipError_t trmm_rows_right_lower(int m, int k, double alpha, const double* T, int ldt, const double* B, int ldb,
-                                 double* C, int ldc, hipStream_t s);
+                                 double* C, int ldc, hipStream_t s, int batch = 1, i64 st = 0, i64 sb = 0,
+                                 i64 sc = 0);
 // C -= A A^T on the lower triangle (C row-major n x n, A row-major n x k)
 hipError_t syrk_rows_lower_sub(int n, int k, const double* A, int lda, double* C, int ldc, hipStream_t s);
 
