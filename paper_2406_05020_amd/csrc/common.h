@@ -270,11 +270,14 @@ hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const 
 hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s);
 // Streaming products with a row-major nr x N matrix M:
 //   rows_dot:    part[j * nch + ch] = sum_{k in chunk ch} M[j][k] x[k], nch = rows_dot_chunks(nr, N)
-//                (part holds nr * nch <= nr + ROWS_DOT_TARGET - 1 values)
+//                (part holds nr * nch <= nr + ROWS_DOT_TARGET - 1 values; with the column update's
+//                finished coefficients after them, 2 nr + ROWS_DOT_TARGET - 1)
 //   rows_dot_full: out[j] = sum_k M[j][k] x[k]
 //   cols_update: u_j = (sum_ch u[j * u_nch + ch]) / (eta ? eta[j] : 1);
 //                out[c] = base[c] - sum_j M[j][c] u_j (and out2[c] = out[c] if out2);
 //                with M2: out3[c] = base2[c] - sum_j M2[j][c] u_j.   base may alias out.
+//                For N >= 2^18 with u_nch > 1 or eta, the nr finished u_j are first written to
+//                u + nr * u_nch: u then holds room for nr * (u_nch + 1) values.
 //   (rows_dot with xm: the dots are taken with x - xm)
 constexpr int ROWS_DOT_TARGET = 2048;   // workgroups a row-dot launch aims at
 int rows_dot_chunks(int nr, i64 N);
@@ -286,7 +289,7 @@ hipError_t launch_qf_v(const QFactor* F, int nunit, const double* x, double* vpa
 //   With M2 and dot_part: also dot_part[g] = workgroup g's share of sum_c out[c] * out3[c]
 //   (ceil(N/64) values; their fixed-order sum is the dot product).
 //   With base2m: out3[c] = (base2[c] - base2m[c]) - sum_j M2[j][c] u_j.
-hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, int u_nch, const double* eta,
+hipError_t launch_cols_update(int nr, i64 N, const double* M, double* u, int u_nch, const double* eta,
                               const double* base, double* out, double* out2, const double* M2, const double* base2,
                               double* out3, hipStream_t s, double* dot_part = nullptr,
                               const double* base2m = nullptr, int batch = 1,

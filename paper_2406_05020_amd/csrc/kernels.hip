@@ -1295,7 +1295,8 @@ hipError_t launch_ginv_small(int nb, const double* L, const double* Linv, const 
 constexpr int CU_WAVES = 16;
 static_assert(CU_WAVES == CS_PARTS, "the riding column sums follow the column update's order");
 constexpr int CU_BLK = 2048;
-constexpr int CU_PF = 8;        // rows per wavefront loaded before the coefficients are staged
+constexpr int CU_PF = 8;        // rows per wavefront loaded before the coefficients are staged (small N)
+constexpr i64 CU_FINISH_MIN_N = (i64)1 << 18;   // from here on the coefficients are finished beforehand
 constexpr int CU_MAXCH = 16;   // most partial sums per coefficient (rows_dot_chunks <= 16)
 
 // Row dots split over column chunks, so that a few long rows still occupy
@@ -1370,7 +1371,7 @@ __global__ __launch_bounds__(RP_THREADS) void k_rows_dot(i64 N, int nch, const d
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-template <bool TWO, bool DOT>
+template <bool TWO, bool DOT, int PF>
 __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, const double* __restrict__ M,
                                                                const double* __restrict__ u, int u_nch,
                                                                const double* __restrict__ eta, const double* base,
@@ -1403,11 +1404,11 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
   double acc = 0.0, acc2 = 0.0;
   for (int j0 = 0; j0 < nr; j0 += CU_BLK) {
     const int jn = min(CU_BLK, nr - j0);
-    // this wavefront's first CU_PF rows of the block, loaded before the
+    // this wavefront's first PF rows of the block, loaded before the
     // coefficients are staged (they do not depend on them)
-    double pm[CU_PF], pm2[CU_PF];
+    double pm[PF > 0 ? PF : 1], pm2[PF > 0 ? PF : 1];
 #pragma unroll
-    for (int k = 0; k < CU_PF; ++k) {
+    for (int k = 0; k < PF; ++k) {
       const int i = wave + k * CU_WAVES;
       const bool ok = c < N && i < jn;
       pm[k] = ok ? M[(i64)(j0 + i) * N + c] : 0.0;
@@ -1415,21 +1416,18 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
     }
     __syncthreads();
     for (int i = threadIdx.x; i < jn; i += 64 * CU_WAVES) {
-      // all partials of row j0 + i are loaded before they are added (in order)
+      // the partials of row j0 + i added in order (a register array of all of them
+      // doubled the kernel's registers and halved its occupancy)
       const double* pu = u + (i64)(j0 + i) * u_nch;
-      double pv[CU_MAXCH];
-#pragma unroll
-      for (int ch = 0; ch < CU_MAXCH; ++ch) pv[ch] = ch < u_nch ? pu[ch] : 0.0;
       const double ev = eta ? eta[j0 + i] : 1.0;
-      double v = pv[0];
-#pragma unroll
-      for (int ch = 1; ch < CU_MAXCH; ++ch) v += pv[ch];     // + 0.0 past u_nch: exact
+      double v = pu[0];
+      for (int ch = 1; ch < u_nch; ++ch) v += pu[ch];
       us[i] = eta ? v / ev : v;
     }
     __syncthreads();
     if (c < N) {
 #pragma unroll
-      for (int k = 0; k < CU_PF; ++k) {
+      for (int k = 0; k < PF; ++k) {
         const int i = wave + k * CU_WAVES;
         if (i < jn) {
           acc = fma(pm[k], us[i], acc);
@@ -1437,7 +1435,7 @@ __global__ __launch_bounds__(64 * CU_WAVES) void k_cols_update(int nr, i64 N, co
         }
       }
 #pragma unroll 4
-      for (int i = wave + CU_PF * CU_WAVES; i < jn; i += CU_WAVES) {
+      for (int i = wave + PF * CU_WAVES; i < jn; i += CU_WAVES) {
         const i64 off = (i64)(j0 + i) * N + c;
         acc = fma(M[off], us[i], acc);
         if (TWO) acc2 = fma(M2[off], us[i], acc2);
@@ -1493,22 +1491,60 @@ hipError_t launch_rows_dot_full(int nr, i64 N, const double* M, const double* x,
   return hipGetLastError();
 }
 
-hipError_t launch_cols_update(int nr, i64 N, const double* M, const double* u, int u_nch, const double* eta,
+// The coefficients of a column update, once: out[j] = (sum_ch u[j][ch]) / (eta ? eta[j] : 1),
+// the partials added in order (the same arithmetic as the staging inside k_cols_update).
+__global__ void k_coef_finish(int nr, int u_nch, const double* __restrict__ u, const double* __restrict__ eta,
+                              double* __restrict__ out, BatchStrides bs) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  u += blockIdx.y * bs.u;
+  out += blockIdx.y * bs.u;
+  if (eta) eta += blockIdx.y * bs.eta;
+  if (j >= nr) return;
+  const double* pu = u + (i64)j * u_nch;
+  double v = pu[0];
+  for (int ch = 1; ch < u_nch; ++ch) v += pu[ch];
+  out[j] = eta ? v / eta[j] : v;
+}
+
+template <int PF>
+static void cols_update_launch(dim3 grid, dim3 block, hipStream_t s, int nr, i64 N, const double* M, const double* u,
+                               int u_nch, const double* eta, const double* base, double* out, double* out2,
+                               const double* M2, const double* base2, double* out3, double* dot_part,
+                               const double* base2m, const BatchStrides& bs) {
+  if (M2 && dot_part)
+    k_cols_update<true, true, PF><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3,
+                                                         dot_part, base2m, bs);
+  else if (M2)
+    k_cols_update<true, false, PF><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3,
+                                                          nullptr, base2m, bs);
+  else
+    k_cols_update<false, false, PF><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, nullptr, nullptr,
+                                                           nullptr, nullptr, nullptr, bs);
+}
+
+hipError_t launch_cols_update(int nr, i64 N, const double* M, double* u, int u_nch, const double* eta,
                               const double* base, double* out, double* out2, const double* M2, const double* base2,
                               double* out3, hipStream_t s, double* dot_part, const double* base2m, int batch,
                               const BatchStrides& bs) {
   if (N <= 0) return hipSuccess;
   if (u_nch < 1 || u_nch > CU_MAXCH) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((N + 63) / 64), batch), block(64 * CU_WAVES);
-  if (M2 && dot_part)
-    k_cols_update<true, true><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3,
-                                                     dot_part, base2m, bs);
-  else if (M2)
-    k_cols_update<true, false><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3,
-                                                      nullptr, base2m, bs);
-  else
-    k_cols_update<false, false><<<grid, block, 0, s>>>(nr, N, M, u, u_nch, eta, base, out, out2, nullptr, nullptr,
-                                                       nullptr, nullptr, nullptr, bs);
+  if (N >= CU_FINISH_MIN_N) {
+    // Many workgroups per CU in turn: each would expose the latency of staging the
+    // coefficients from their partials, so they are finished once, after the partials.
+    if (nr > 0 && (u_nch > 1 || eta)) {
+      double* fin = u + (i64)nr * u_nch;
+      k_coef_finish<<<dim3((unsigned)((nr + 255) / 256), batch), 256, 0, s>>>(nr, u_nch, u, eta, fin, bs);
+      u = fin;
+      u_nch = 1;
+      eta = nullptr;
+    }
+    cols_update_launch<0>(grid, block, s, nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3, dot_part, base2m,
+                          bs);
+  } else {
+    cols_update_launch<CU_PF>(grid, block, s, nr, N, M, u, u_nch, eta, base, out, out2, M2, base2, out3, dot_part,
+                              base2m, bs);
+  }
   return hipGetLastError();
 }
 

@@ -741,7 +741,7 @@ static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
     if ((e = launch_copy_f64_to_f32((const double*)so->X, (float*)so->X32, NN, s)) != hipSuccess) return e;
     if ((e = run_plan(so->pp, s)) != hipSuccess) return e;
     if ((e = launch_copy_f32_to_f64((const float*)so->Y32, (double*)so->Y, NN, s)) != hipSuccess) return e;
-    return launch_cols_update(h->nb, h->N, h->Qc, (const double*)so->U, 1, nullptr, (const double*)so->Y,
+    return launch_cols_update(h->nb, h->N, h->Qc, (double*)so->U, 1, nullptr, (const double*)so->Y,
                               (double*)so->Y, nullptr, nullptr, nullptr, nullptr, s);
   }
   if (so->qform) {                                                  // G_pp X + s2 X - Q^T Q X
@@ -749,7 +749,7 @@ static hipError_t apply_sop(gpfvm_handle* h, gpfvm_sop* so, hipStream_t s) {
         (e = launch_rows_dot_full(h->nb, h->N, h->Qc, (const double*)so->X, (double*)so->U, s)) != hipSuccess)
       return e;
     if ((e = run_plan(so->pp, s)) != hipSuccess) return e;               // (with U = Q X riding along)
-    return launch_cols_update(h->nb, h->N, h->Qc, (const double*)so->U, 1, nullptr, (const double*)so->Y,
+    return launch_cols_update(h->nb, h->N, h->Qc, (double*)so->U, 1, nullptr, (const double*)so->Y,
                               (double*)so->Y, nullptr,
                               nullptr, nullptr, nullptr, s);
   }
@@ -812,8 +812,9 @@ static int ensure_state(gpfvm_handle* h, hipStream_t s) {
   h->Dd = (double*)h->arena.alloc((size_t)N * h->max_iter * sizeof(double));
   h->eta = (double*)h->arena.alloc(h->max_iter * sizeof(double));
   h->vec = (double*)h->arena.alloc((size_t)8 * N * sizeof(double));
-  // 1024 dot partials, then the row-dot partials of the projections (<= max_iter + ROWS_DOT_TARGET - 1)
-  h->aux = (double*)h->arena.alloc((size_t)(1024 + ROWS_DOT_TARGET + h->max_iter) * sizeof(double));
+  // 1024 dot partials, then the row-dot partials of the projections and the column update's
+  // finished coefficients after them (<= 2 max_iter + ROWS_DOT_TARGET - 1)
+  h->aux = (double*)h->arena.alloc((size_t)(1024 + ROWS_DOT_TARGET + 2 * h->max_iter) * sizeof(double));
   h->scal = (double*)h->arena.alloc(64 * sizeof(double));
   h->flag = (int*)h->arena.alloc(16 * sizeof(int));
   h->part = (double*)h->arena.alloc((size_t)((N + 63) / 64 + 2 * nblk(N) + 1) * sizeof(double));
@@ -1978,7 +1979,7 @@ int gpfvm::batch_solve(gpfvm_handle* h, int R, const double* yobs_host, double t
   B = GpfvmBatch();
   B.R = R;
   const int n_eta = (int)((N + 63) / 64), n_rr = (int)nblk(N);
-  const i64 ucap = cap + ROWS_DOT_TARGET, pstride = n_eta + 2 * (i64)n_rr;
+  const i64 ucap = 2 * cap + ROWS_DOT_TARGET, pstride = n_eta + 2 * (i64)n_rr;
   auto A = [&](size_t bytes) { return h->arena.alloc(bytes); };
   B.yobs = (double*)A((size_t)R * n * 8);
   B.bS = (double*)A((size_t)R * N * 8);
