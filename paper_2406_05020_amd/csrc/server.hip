@@ -213,8 +213,9 @@ static size_t estimate_bytes(const gpfvm_ibvp& p, int max_iter, long long M, int
   b += 4.0 * nb * nb * d8;             // L, L^{-1} (and transposes)
   if (qform_ok(N, nb)) b += 3.0 * nb * N * d8;             // point correction Q and its build buffers
   b += 2.0 * nb * 64 * d8 + 4.0 * (nb + 64) * 64 * d8;     // Cholesky workspace
-  const double chunk = std::max(32.0, std::min((double)M, (double)(32LL << 20) / std::max(1LL, nb)));
-  b += (3.0 * nb + 64.0) * chunk * d8;                     // posterior point-block chunks and column partials
+  b += 0.5 * nb * nb * d8;                                 // the triangular inverse's two workspaces
+  const double chunk = (double)posterior_chunk(nb, M);
+  b += (2.0 * nb + 64.0) * chunk * d8;                     // posterior point-block chunks and column partials
   {                                                        // posterior direction batches
     const double widest = std::max(std::max((double)M, (double)N), std::max(1.0, (double)nb));
     const double B = std::min((double)max_iter, std::max(64.0, std::floor((double)(512LL << 20) / (8.0 * widest))));

@@ -1882,8 +1882,7 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
     if (!dpg) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
     if (hipMemcpyAsync(dpg, &pg, sizeof(pg), hipMemcpyHostToDevice, s) != hipSuccess)
       return fail(GPFVM_E_HIP, "posterior: copy failed");
-    // chunk grid points so that n_b x chunk stays below ~256 MB per buffer
-    const i64 chunk = std::max<i64>(32, std::min<i64>(M, (i64)(32LL << 20) / h->nb));
+    const i64 chunk = posterior_chunk(h->nb, M);
     double* KB = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
     double* TT = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
     double* CP = (double*)tmp.alloc((size_t)COLSQ_MAX_CHUNKS * chunk * sizeof(double));
