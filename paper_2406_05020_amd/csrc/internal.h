@@ -72,6 +72,12 @@ inline i64 posterior_chunk(i64 nb, i64 M) {
   return std::max<i64>(32, std::min<i64>(M, (256LL << 20) / std::max<i64>(1, nb)));
 }
 
+// Directions per batch of the posterior's combined-variance term: each per-batch buffer
+// (widest of M, N, n_b by the batch) within 2 GiB, at least 64 directions.
+inline i64 posterior_dir_batch(i64 K, i64 widest) {
+  return std::min<i64>(K, std::max<i64>(64, (2048LL << 20) / (8 * std::max<i64>(1, widest))));
+}
+
 // rocBLAS triangular products (blas.hip) on row-major matrices, T lower-triangular,
 // C distinct from B: C = alpha T B (T m x m; B, C m x k) and C = alpha B T (B, C m x k; T k x k)
 // (batch > 1: that many products, operands st, sb, sc elements apart)

@@ -218,7 +218,7 @@ static size_t estimate_bytes(const gpfvm_ibvp& p, int max_iter, long long M, int
   b += (2.0 * nb + 64.0) * chunk * d8;                     // posterior point-block chunks and column partials
   {                                                        // posterior direction batches
     const double widest = std::max(std::max((double)M, (double)N), std::max(1.0, (double)nb));
-    const double B = std::min((double)max_iter, std::max(64.0, std::floor((double)(512LL << 20) / (8.0 * widest))));
+    const double B = (double)posterior_dir_batch(max_iter, (i64)widest);
     b += (2.0 * M * B + N * B + 4.0 * nb * B) * d8 + 8.0 * M * d8;
   }
   if (prec == GPFVM_PREC_MIXED) b += 12.0 * N * 4.0;       // float32 operator buffers

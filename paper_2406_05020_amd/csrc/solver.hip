@@ -1905,9 +1905,8 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
   }
   const int K = h->iters;
   if (K > 0) {
-    // direction batch: as many as keep each per-batch buffer within 512 MB (at least 64)
     const i64 widest = std::max<i64>(std::max<i64>(M, N), std::max(h->nb, 1));
-    const int B = (int)std::min<i64>(K, std::max<i64>(64, (512LL << 20) / (8 * widest)));
+    const int B = (int)posterior_dir_batch(K, widest);
     double* P1 = (double*)tmp.alloc((size_t)M * B * sizeof(double));
     double* P2 = h->nb > 0 ? (double*)tmp.alloc((size_t)M * B * sizeof(double)) : nullptr;
     double* Ub = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
