@@ -250,7 +250,12 @@ int gpfvm_volume_matvec_noalloc(gpfvm_handle* h, int nrhs, const double* x, doub
  * conditioning on the points, then IterGP with CG actions on the volume
  * observations (Sec. 4.1-4.2).  The state (weights, directions, eta) stays in
  * the handle for gpfvm_posterior and for resume.  Synchronises to fill info.
- * Returns GPFVM_OK, or NOCONV / NOTPD (info->status too), or INVALID / HIP. */
+ * Returns GPFVM_OK, or NOCONV / NOTPD (info->status too), or INVALID / HIP.
+ * A tolerance below the attainable accuracy: the float64 IterGP loop stops
+ * once its residual has grown 1000-fold above the smallest value it reached,
+ * rolls the weights and the stored directions back to that iterate, and
+ * returns NOCONV (gpfvm_last_error says so) with that iterate's state, which
+ * the posterior then uses. */
 int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* opts, gpfvm_solve_info* info,
                 void* stream);
 
