@@ -71,6 +71,19 @@ hipError_t trmm_rows_right_lower(int m, int k, double alpha, const double* T, in
   return r == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
 }
 
+// C = A B^T for row-major A (m x k, leading dimension lda), B (n x k, ldb) and
+// C (m x n, ldc).  In the column-major views (A^T, B^T, C^T) this is
+// C^T = (B^T)^T A^T: a GEMM with the first operand transposed.
+hipError_t gemm_rows_abt(int m, int n, int k, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                         hipStream_t s) {
+  rocblas_handle hd = handle_for(s);
+  if (!hd) return hipErrorNotInitialized;
+  const double one = 1.0, zero = 0.0;
+  const rocblas_status st = rocblas_dgemm(hd, rocblas_operation_transpose, rocblas_operation_none, n, m, k, &one, B,
+                                          ldb, A, lda, &zero, C, ldc);
+  return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+}
+
 // C -= A A^T on the lower triangle: C row-major n x n (leading dimension ldc),
 // A row-major n x k (leading dimension lda).  Column-major, C^T is upper and
 // the update is (A^T)^T (A^T): an upper SYRK with the transposed operand.

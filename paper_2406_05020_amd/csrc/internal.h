@@ -86,6 +86,9 @@ hipError_t trmm_rows_left_lower(int m, int k, double alpha, const double* T, int
 hipError_t trmm_rows_right_lower(int m, int k, double alpha, const double* T, int ldt, const double* B, int ldb,
                                  double* C, int ldc, hipStream_t s, int batch = 1, i64 st = 0, i64 sb = 0,
                                  i64 sc = 0);
+// C = A B^T, all row-major: A m x k, B n x k, C m x n
+hipError_t gemm_rows_abt(int m, int n, int k, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                         hipStream_t s);
 // C -= A A^T on the lower triangle (C row-major n x n, A row-major n x k)
 hipError_t syrk_rows_lower_sub(int n, int k, const double* A, int lda, double* C, int ldc, hipStream_t s);
 
