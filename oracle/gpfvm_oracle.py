@@ -35,6 +35,13 @@ Parity pins (tests under ``tests/test_oracle_*.py``):
   schur_cross ................ pinned: block elimination of the joint Gaussian
                                conditional (full posterior covariance and mean
                                from the dense Gram)
+  several outputs ............ pinned: decoupled equations reproduce separate
+                               single-output problems; equations on u0 +- u1 of
+                               two iid outputs are two problems with prior 2k;
+                               shallow-water Gram entries (per-cell H, Coriolis,
+                               drag, two-term radiation rows) against brute-force
+                               quadrature with autograd derivatives; a Poincare
+                               plane wave (exact solution) is recovered
 """
 from __future__ import annotations
 
@@ -156,15 +163,29 @@ def _mode_apply(mats: Sequence[np.ndarray], v: np.ndarray, shape_in: Sequence[in
 
 
 class Oracle:
-    """All oracle quantities of one IBVP (``workloads.IBVP``)."""
+    """All oracle quantities of one IBVP (``workloads.IBVP``).
+
+    Several outputs (Sec. 3.3): the prior is k = diag(k_11, ..., k_d'd')
+    (eq. multioutput-cov-def), here every k_ii the same tensor-product kernel
+    times its own outputscale sigma_i^2.  A volume observation of equation e
+    is sum over terms of e of c_t d^alpha_t u_out(t) integrated over the cell;
+    two observations covary only through terms on the same output, so every
+    Gram entry is a sum over term pairs with out(t1) = out(t2) of
+    sigma_out^2 c_t1 c_t2 prod_i F^{alpha_i alpha'_i}.  Volume observations
+    are ordered equation-major (all cells of equation 0 first).  A point
+    observation is a sum of terms coef * w(x) * d^beta u_out(x) (one term for
+    an initial or Dirichlet value, two for a radiation condition)."""
 
     def __init__(self, ibvp):
         self.p = ibvp
         self.d = ibvp.d
         self.ell = tuple(float(l) for l in ibvp.lengthscale)
         self.kq = tuple(kernel_q(c) for c in ibvp.kernel_codes())
-        self.sf2 = float(ibvp.outputscale)
+        self.sfo = ibvp.output_scales()
+        self.sf2 = float(self.sfo[0])
         self._cache: Dict[tuple, np.ndarray] = {}
+        self.neq = ibvp.neq
+        self.Nc = ibvp.n_cells
         self.N = ibvp.n_pde
         self.ncell = ibvp.ncell
         self.cc = None if ibvp.cell_coef is None else np.asarray(ibvp.cell_coef, float).ravel()
@@ -178,33 +199,41 @@ class Oracle:
         return self._cache[key]
 
     def term_coef(self, term) -> np.ndarray:
-        """c_alpha(V) for every volume V (Sec. 3.2; per-cell coefficients as
+        """c_alpha(V) for every cell V (Sec. 3.2; per-cell coefficients as
         in the appendix on variable bathymetry)."""
         if term.cellwise:
             return term.coef * self.cc
-        return np.full(self.N, term.coef)
+        return np.full(self.Nc, term.coef)
+
+    def _rows(self, eq: int) -> slice:
+        return slice(eq * self.Nc, (eq + 1) * self.Nc)
 
     # -- volume block (Sec. 3.2 eq. LkL, Sec. 4.1 eq. kronecker-structure) --
     def volume_gram(self) -> np.ndarray:
-        """Dense L_V k L_V' (N x N), summed over every (alpha, alpha') pair."""
+        """Dense L_V k L_V' (N x N), summed over every (alpha, alpha') pair
+        of terms on the same output."""
         G = np.zeros((self.N, self.N))
         for t1 in self.p.terms:
             c1 = self.term_coef(t1)
             for t2 in self.p.terms:
+                if t1.out != t2.out:
+                    continue
                 c2 = self.term_coef(t2)
                 K = _kron_all([self.F(i, t1.alpha[i], t2.alpha[i]) for i in range(self.d)])
-                G += c1[:, None] * K * c2[None, :]
-        return self.sf2 * G
+                G[self._rows(t1.eq), self._rows(t2.eq)] += self.sfo[t1.out] * (c1[:, None] * K * c2[None, :])
+        return G
 
     def volume_diag(self) -> np.ndarray:
         diag = np.zeros(self.N)
         for t1 in self.p.terms:
             c1 = self.term_coef(t1)
             for t2 in self.p.terms:
+                if t1.out != t2.out or t1.eq != t2.eq:
+                    continue
                 c2 = self.term_coef(t2)
                 dg = [np.diag(self.F(i, t1.alpha[i], t2.alpha[i])) for i in range(self.d)]
-                diag += c1 * c2 * _kron_all(dg)
-        return self.sf2 * diag
+                diag[self._rows(t1.eq)] += self.sfo[t1.out] * (c1 * c2 * _kron_all(dg))
+        return diag
 
     def noise_pde(self) -> float:
         """PDE-observation noise variance; relative mode scales by the mean of
@@ -219,10 +248,13 @@ class Oracle:
         for t1 in self.p.terms:
             c1 = self.term_coef(t1)
             for t2 in self.p.terms:
+                if t1.out != t2.out:
+                    continue
                 c2 = self.term_coef(t2)
                 mats = [self.F(i, t1.alpha[i], t2.alpha[i]) for i in range(self.d)]
-                y += c1 * _mode_apply(mats, c2 * v, self.ncell)
-        return self.sf2 * y
+                y[self._rows(t1.eq)] += self.sfo[t1.out] * (c1 * _mode_apply(mats, c2 * v[self._rows(t2.eq)],
+                                                                                   self.ncell))
+        return y
 
     # -- point observations (Sec. 2.2, IC/BC operator) -----------------------
     def point_gram(self) -> np.ndarray:
@@ -234,16 +266,23 @@ class Oracle:
         for g1 in gs:
             row = []
             for g2 in gs:
-                mats = [point_point(g1.deriv[i], g2.deriv[i], g1.axes[i], g2.axes[i], self.ell[i], self.kq[i])
-                        for i in range(self.d)]
-                row.append(self.sf2 * _kron_all(mats))
+                B = np.zeros((g1.size, g2.size))
+                for c1 in g1.components():
+                    for c2 in g2.components():
+                        if c1.out != c2.out:
+                            continue
+                        mats = [point_point(c1.deriv[i], c2.deriv[i], g1.axes[i], g2.axes[i], self.ell[i], self.kq[i])
+                                for i in range(self.d)]
+                        w = np.outer(c1.weight_grid(g1.shape), c2.weight_grid(g2.shape))
+                        B += (self.sfo[c1.out] * c1.coef * c2.coef) * (w * _kron_all(mats))
+                row.append(B)
             blocks.append(row)
         G = np.block(blocks)
         G[np.diag_indices_from(G)] += np.concatenate([np.full(g.size, g.noise_var) for g in gs])
         return G
 
-    def _group_cell_mats(self, g, alpha) -> List[np.ndarray]:
-        return [self.pc_cached(g, i, g.deriv[i], alpha[i]) for i in range(self.d)]
+    def _group_cell_mats(self, g, beta, alpha) -> List[np.ndarray]:
+        return [self.pc_cached(g, i, beta[i], alpha[i]) for i in range(self.d)]
 
     def pc_cached(self, g, dim, p, q):
         key = ("Q", id(g), dim, p, q)
@@ -251,14 +290,22 @@ class Oracle:
             self._cache[key] = point_cell(p, q, g.axes[dim], self.p.edges[dim], self.ell[dim], self.kq[dim])
         return self._cache[key]
 
+    def _pairs(self, g):
+        """(point term, PDE term, scale) for every pair on the same output."""
+        for c in g.components():
+            for t in self.p.terms:
+                if t.out == c.out:
+                    yield c, t, self.sfo[c.out] * c.coef
+
     def cross_gram(self) -> np.ndarray:
         """L_b k L_V' (n_b x N), dense."""
         rows = [np.zeros((0, self.N))]
         for g in self.p.groups:
             B = np.zeros((g.size, self.N))
-            for t in self.p.terms:
-                B += _kron_all(self._group_cell_mats(g, t.alpha)) * self.term_coef(t)[None, :]
-            rows.append(self.sf2 * B)
+            for c, t, a in self._pairs(g):
+                K = _kron_all(self._group_cell_mats(g, c.deriv, t.alpha))
+                B[:, self._rows(t.eq)] += a * (c.weight_grid(g.shape)[:, None] * K * self.term_coef(t)[None, :])
+            rows.append(B)
         return np.vstack(rows)
 
     def cross_matvec(self, v: np.ndarray) -> np.ndarray:
@@ -266,9 +313,10 @@ class Oracle:
         out = [np.zeros(0)]
         for g in self.p.groups:
             acc = np.zeros(g.size)
-            for t in self.p.terms:
-                acc += _mode_apply(self._group_cell_mats(g, t.alpha), self.term_coef(t) * v, self.ncell)
-            out.append(self.sf2 * acc)
+            for c, t, a in self._pairs(g):
+                acc += a * c.weight_grid(g.shape) * _mode_apply(self._group_cell_mats(g, c.deriv, t.alpha),
+                                                                self.term_coef(t) * v[self._rows(t.eq)], self.ncell)
+            out.append(acc)
         return np.concatenate(out)
 
     def cross_rmatvec(self, w: np.ndarray) -> np.ndarray:
@@ -277,10 +325,10 @@ class Oracle:
         off = 0
         for g in self.p.groups:
             wg = w[off:off + g.size]; off += g.size
-            for t in self.p.terms:
-                mats = [m.T for m in self._group_cell_mats(g, t.alpha)]
-                y += self.term_coef(t) * _mode_apply(mats, wg, g.shape)
-        return self.sf2 * y
+            for c, t, a in self._pairs(g):
+                mats = [m.T for m in self._group_cell_mats(g, c.deriv, t.alpha)]
+                y[self._rows(t.eq)] += a * self.term_coef(t) * _mode_apply(mats, c.weight_grid(g.shape) * wg, g.shape)
+        return y
 
     def gram(self) -> np.ndarray:
         """Full IBVP Gram G = L k L' + Sigma (Sec. 2.2)."""
@@ -295,42 +343,52 @@ class Oracle:
         mesh = np.meshgrid(*grid, indexing="ij")
         return np.stack([m.ravel() for m in mesh], axis=1)
 
-    def Lk_points(self, X: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
-        """(L_b k(x), L_V k(x)) for rows x of X: shapes (n_b, M) and (N, M)."""
+    def Lk_points(self, X: np.ndarray, out: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+        """(L_b k(x), L_V k(x)) for the value of output ``out`` at the rows x
+        of X: shapes (n_b, M) and (N, M)."""
         M = X.shape[0]
+        sf = self.sfo[out]
         kb = [np.zeros((0, M))]
         for g in self.p.groups:
-            mats = [point_point(g.deriv[i], 0, g.axes[i], X[:, i], self.ell[i], self.kq[i]) for i in range(self.d)]
-            # group tensor grid x each evaluation point: product over dims
-            blk = np.ones((g.size, M))
+            blk_g = np.zeros((g.size, M))
             idx = np.indices(g.shape).reshape(self.d, -1)
-            for i in range(self.d):
-                blk *= mats[i][idx[i], :]
-            kb.append(self.sf2 * blk)
+            for c in g.components():
+                if c.out != out:
+                    continue
+                mats = [point_point(c.deriv[i], 0, g.axes[i], X[:, i], self.ell[i], self.kq[i]) for i in range(self.d)]
+                # group tensor grid x each evaluation point: product over dims
+                blk = np.ones((g.size, M))
+                for i in range(self.d):
+                    blk *= mats[i][idx[i], :]
+                blk_g += (sf * c.coef) * (c.weight_grid(g.shape)[:, None] * blk)
+            kb.append(blk_g)
         kp = np.zeros((self.N, M))
         idx = np.indices(self.ncell).reshape(self.d, -1)
         for t in self.p.terms:
-            blk = np.ones((self.N, M))
+            if t.out != out:
+                continue
+            blk = np.ones((self.Nc, M))
             for i in range(self.d):
                 # L_[a,b];alpha applied to the first argument of k(., x)
                 q = point_cell(0, t.alpha[i], X[:, i], self.p.edges[i], self.ell[i], self.kq[i])  # M x N_i
                 blk *= q.T[idx[i], :]
-            kp += self.term_coef(t)[:, None] * blk
-        return np.vstack(kb), self.sf2 * kp
+            kp[self._rows(t.eq)] += sf * (self.term_coef(t)[:, None] * blk)
+        return np.vstack(kb), kp
 
 
-def dense_posterior(orc: Oracle, X: np.ndarray, y: Optional[np.ndarray] = None):
-    """Exact posterior mean/variance at rows of X (Sec. 2.1 eq. lin-cond-mean,
-    eq. lin-cond-cov; Sec. 4 representer weights via Cholesky)."""
+def dense_posterior(orc: Oracle, X: np.ndarray, y: Optional[np.ndarray] = None, out: int = 0):
+    """Exact posterior mean/variance of output ``out`` at rows of X (Sec. 2.1
+    eq. lin-cond-mean, eq. lin-cond-cov; Sec. 4 representer weights via
+    Cholesky)."""
     G = orc.gram()
     y = orc.p.y_obs() if y is None else y
     cf = sla.cho_factor(G, lower=True)
     alpha = sla.cho_solve(cf, y)
-    kb, kp = orc.Lk_points(X)
+    kb, kp = orc.Lk_points(X, out)
     Lk = np.vstack([kb, kp])
     mean = Lk.T @ alpha
     W = sla.solve_triangular(cf[0], Lk, lower=True)
-    var = orc.sf2 - np.einsum("ij,ij->j", W, W)
+    var = orc.sfo[out] - np.einsum("ij,ij->j", W, W)
     return mean, var, alpha
 
 
@@ -499,12 +557,12 @@ def cg_solve(S, tol: float, maxiter: int):
     return x, maxiter
 
 
-def schur_cross(S: "SchurSystem", X: np.ndarray) -> np.ndarray:
-    """Cross-covariance between the volume observations and the points X under
-    the IC/BC-conditioned prior (Sec. 4.2): K_S(X) = L_V k(X) - G_pb G_bb^{-1}
-    L_b k(X), shape (N, M)."""
+def schur_cross(S: "SchurSystem", X: np.ndarray, out: int = 0) -> np.ndarray:
+    """Cross-covariance between the volume observations and output ``out`` at
+    the points X under the IC/BC-conditioned prior (Sec. 4.2):
+    K_S(X) = L_V k(X) - G_pb G_bb^{-1} L_b k(X), shape (N, M)."""
     o = S.o
-    kb, kp = o.Lk_points(X)
+    kb, kp = o.Lk_points(X, out)
     if kb.size == 0:
         return kp
     return kp - np.stack([o.cross_rmatvec(c) for c in S.bb_solve(kb).T], axis=1)
@@ -551,18 +609,19 @@ def itergp_targeted(S, vp: np.ndarray, D: np.ndarray, eta: np.ndarray, KS: np.nd
 
 
 def two_stage_posterior(S: SchurSystem, vp: np.ndarray, X: np.ndarray,
-                        D: Optional[np.ndarray] = None, eta: Optional[np.ndarray] = None):
-    """Posterior mean, and (if D, eta given) IterGP combined variance, at the
-    rows of X from volume weights vp (Sec. 4.2; Wenger et al. 2022 combined
-    covariance k - k_x^T C k_x under the IC/BC-conditioned prior)."""
+                        D: Optional[np.ndarray] = None, eta: Optional[np.ndarray] = None, out: int = 0):
+    """Posterior mean, and (if D, eta given) IterGP combined variance, of
+    output ``out`` at the rows of X from volume weights vp (Sec. 4.2; Wenger
+    et al. 2022 combined covariance k - k_x^T C k_x under the IC/BC-conditioned
+    prior)."""
     o = S.o
-    kb, kp = o.Lk_points(X)
+    kb, kp = o.Lk_points(X, out)
     alpha = S.full_weights(vp)
     mean = kb.T @ alpha[:o.p.n_b] + kp.T @ alpha[o.p.n_b:]
     if D is None:
         return mean, None
     Wb = S.bb_lsolve(kb)
-    var_b = o.sf2 - np.einsum("ij,ij->j", Wb, Wb)
+    var_b = o.sfo[out] - np.einsum("ij,ij->j", Wb, Wb)
     # cross-covariance of the conditioned prior between volumes and x
     w = kp - np.stack([o.cross_rmatvec(c) for c in S.bb_solve(kb).T], axis=1)
     proj = D.T @ w                                   # k x M

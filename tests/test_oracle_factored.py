@@ -30,7 +30,7 @@ def _pieces(o, p):
         f = 1 - pdim
         for t in p.terms:
             assert not t.cellwise
-            mats = o._group_cell_mats(g, t.alpha)        # per dim: points x cells
+            mats = o._group_cell_mats(g, g.deriv, t.alpha)   # per dim: points x cells
             q = mats[pdim][0]
             gf = np.zeros((nb, p.ncell[f]))
             gf[off:off + g.size] = o.sf2 * t.coef * mats[f]

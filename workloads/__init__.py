@@ -26,19 +26,45 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 __all__ = [
-    "PointGroup", "PDETerm", "IBVP", "uniform_edges", "centres",
+    "PointTerm", "PointGroup", "PDETerm", "IBVP", "uniform_edges", "centres",
     "heat1d_c1", "advdiff_c2", "heat2d_c3", "wave2d_c4", "serving_trace",
     "heat2d_request", "scaled", "CONFIGS", "wave2d_benchmark", "wave2d_benchmark_solution",
+    "shallow_water", "sw_depth", "sw_terms",
 ]
 
 
 @dataclass
+class PointTerm:
+    """One summand ``coef * w(x) * d^beta u_out(x)`` of a point observation.
+    The per-point weight is separable: w(x) = prod_i weights[i][j_i] over the
+    group's grid indices (None: 1 in that dimension), e.g. the wave speed of a
+    radiation boundary condition along its edge."""
+    deriv: Tuple[int, ...]
+    coef: float = 1.0
+    out: int = 0
+    weights: Optional[List[Optional[np.ndarray]]] = None
+
+    def weight_grid(self, shape: Sequence[int]) -> np.ndarray:
+        """w over the group's points, row-major (prod(shape) values)."""
+        w = np.ones(tuple(shape))
+        for i, n in enumerate(shape):
+            if self.weights is not None and self.weights[i] is not None:
+                wi = np.asarray(self.weights[i], float)
+                assert wi.shape == (n,)
+                w = w * wi.reshape([n if k == i else 1 for k in range(len(shape))])
+        return w.ravel()
+
+
+@dataclass
 class PointGroup:
-    """A tensor grid of point observations ``d^beta u(x) = y + eps``."""
+    """A tensor grid of point observations ``d^beta u_out(x) = y + eps``, or,
+    with ``terms``, of a sum of such terms (e.g. h_t - c h_x = 0)."""
     axes: List[np.ndarray]            # one coordinate array per dim (len 1 pins it)
-    deriv: Tuple[int, ...]            # derivative multi-index beta
+    deriv: Tuple[int, ...]            # derivative multi-index beta (single-term form)
     y: np.ndarray                     # prod(len(axes[i])) values, row-major
     noise_var: float                  # variance of eps (absolute)
+    out: int = 0                      # observed output (single-term form)
+    terms: Optional[List[PointTerm]] = None   # multi-term form (replaces deriv/out)
 
     @property
     def shape(self) -> Tuple[int, ...]:
@@ -48,14 +74,23 @@ class PointGroup:
     def size(self) -> int:
         return int(np.prod(self.shape))
 
+    def components(self) -> List[PointTerm]:
+        if self.terms:
+            return list(self.terms)
+        return [PointTerm(tuple(self.deriv), 1.0, self.out, None)]
+
 
 @dataclass
 class PDETerm:
-    """One summand ``coef * d^alpha u`` of the operator D (optionally times a
-    per-cell coefficient, paper Appendix 'Variable bathymetry')."""
+    """One summand ``coef * d^alpha u_out`` of equation ``eq`` of the operator
+    (optionally times a per-cell coefficient, paper Appendix 'Variable
+    bathymetry').  Several equations over several outputs form a system such
+    as the linearised shallow-water equations (Sec. 3.3)."""
     alpha: Tuple[int, ...]
     coef: float
     cellwise: bool = False
+    out: int = 0
+    eq: int = 0
 
 
 @dataclass
@@ -67,25 +102,42 @@ class IBVP:
     outputscale: float                       # sigma_f^2
     terms: List[PDETerm]
     groups: List[PointGroup]
-    cell_coef: Optional[np.ndarray] = None   # N values (per-volume coefficient)
-    f_int: Optional[np.ndarray] = None       # N values of the integral of f over V; None = 0
+    cell_coef: Optional[np.ndarray] = None   # one value per cell (per-volume coefficient)
+    f_int: Optional[np.ndarray] = None       # neq x cells values of the integral of f over V; None = 0
     noise_pde: float = 1e-6                  # PDE-observation noise
     noise_pde_relative: bool = True          # True: variance = noise_pde * mean diag of the volume Gram
     grid: List[np.ndarray] = field(default_factory=list)   # posterior grid axes
     meta: dict = field(default_factory=dict)
     # per-dimension kernel: 0 = squared exponential, 1..4 = Matern nu = 1/2, 3/2, 5/2, 7/2
     kernel: Tuple[int, ...] = ()
+    # multi-output prior (Sec. 3.3 eq. multioutput-cov-def): nout independent
+    # outputs with the same tensor-product kernel and their own outputscales,
+    # neq equations observed on every cell (observation order: equation-major)
+    nout: int = 1
+    neq: int = 1
+    out_scale: Optional[Tuple[float, ...]] = None   # sigma_i^2 per output; None: outputscale
 
     def kernel_codes(self) -> Tuple[int, ...]:
         return tuple(self.kernel[i] if i < len(self.kernel) else 0 for i in range(self.d))
+
+    def output_scales(self) -> Tuple[float, ...]:
+        if self.out_scale is None:
+            return tuple(float(self.outputscale) for _ in range(self.nout))
+        assert len(self.out_scale) == self.nout
+        return tuple(float(v) for v in self.out_scale)
 
     @property
     def ncell(self) -> Tuple[int, ...]:
         return tuple(len(e) - 1 for e in self.edges)
 
     @property
-    def n_pde(self) -> int:
+    def n_cells(self) -> int:
         return int(np.prod(self.ncell))
+
+    @property
+    def n_pde(self) -> int:
+        """Volume observations: one per equation and cell."""
+        return self.neq * self.n_cells
 
     @property
     def n_b(self) -> int:
@@ -306,6 +358,86 @@ def heat2d_request(ns: int, nt: int, seed: int, kappa: float = 0.01, grid_t: int
     )
 
 
+def sw_depth(x, y, seed: int = 6) -> np.ndarray:
+    """Synthetic bathymetry H(x, y) (nondimensional, in [0.05, 1]): an ocean
+    of depth 1 rising over a shelf to depth 0.05 at a coast along x = 1; the
+    shelf edge x_s(y) and a mild depth modulation follow three seeded Fourier
+    modes.  Smooth, so it can be read at cell centres (the per-cell H) and at
+    boundary points (the radiation wave speed) alike."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1.0, 1.0, size=(3, 3))          # (amplitude, frequency, phase) of 3 modes
+    x = np.asarray(x, float); y = np.asarray(y, float)
+    xs = 0.72 + sum(0.04 * a[k, 0] * np.sin(2 * np.pi * (k + 1) * y + np.pi * a[k, 2]) for k in range(3))
+    shelf = 1.0 / (1.0 + np.exp(-(x - xs) / 0.06))
+    mod = 1.0 + sum(0.08 * a[k, 1] * np.cos(2 * np.pi * (k + 1) * (x + y) + np.pi * a[k, 2]) for k in range(3))
+    return 0.05 + 0.95 * (1.0 - shelf) * mod
+
+
+def sw_terms(g: float, f_cor: float, drag: float, H_cellwise: bool = True) -> List[PDETerm]:
+    """The three linearised shallow-water equations (eq. sw1 to sw3) as terms
+    on the outputs (h, u, v) = (0, 1, 2); H is the per-cell coefficient when
+    H_cellwise, else 1 (a constant depth folded into the data's scale)."""
+    return [PDETerm((1, 0, 0), 1.0, False, 0, 0), PDETerm((0, 1, 0), 1.0, H_cellwise, 1, 0),
+            PDETerm((0, 0, 1), 1.0, H_cellwise, 2, 0),
+            PDETerm((1, 0, 0), 1.0, False, 1, 1), PDETerm((0, 0, 0), -f_cor, False, 2, 1),
+            PDETerm((0, 1, 0), g, False, 0, 1), PDETerm((0, 0, 0), drag, False, 1, 1),
+            PDETerm((1, 0, 0), 1.0, False, 2, 2), PDETerm((0, 0, 0), f_cor, False, 1, 2),
+            PDETerm((0, 0, 1), g, False, 0, 2), PDETerm((0, 0, 0), drag, False, 2, 2)]
+
+
+def shallow_water(nt: int = 20, nx: int = 90, ny: int = 170, seed: int = 6, n_icx: int = 36, n_icy: int = 85,
+                  n_bt: int = 40, n_bx: int = 30, n_by: int = 85, g: float = 1.0, f_cor: float = 0.5,
+                  drag: float = 0.1, lengthscale=(0.25, 0.06, 0.1), out_scale=(1.0, 2.0, 2.0),
+                  grid_t: int = 4, kernel: int = 3) -> IBVP:
+    """Linearised 2-D shallow water (appendix "Tsunami propagation", eq. sw1 to
+    sw3) on [0,1]^3 in (t, x, y), nondimensional:
+
+        h_t + H (u_x + v_y)      = 0
+        u_t - f v + g h_x + k u  = 0
+        v_t + f u + g h_y + k v  = 0
+
+    Outputs (h, u, v), each with its own Matern-5/2 tensor-product prior
+    (same lengthscales, outputscales ``out_scale``; Sec. 3.3).  H is constant
+    per cell (appendix "Variable bathymetry"), the synthetic ``sw_depth`` at
+    the cell centre.  The default cell counts are the paper's 20 x 90 x 170
+    volumes (three observations each).  Initial condition: an anisotropic
+    Gaussian displacement of h (narrow along x), u = v = 0, on an
+    n_icx x n_icy grid.  Boundary: the radiation condition h_t = c dh/dn
+    pointing inward (h_t - c h_x = 0 at x = 0, h_t + c h_x = 0 at x = 1, the
+    same in y), c = sqrt(g H) at the boundary point, on n_bt times x n_by
+    (n_bx) points per edge."""
+    xc, yc = centres(nx), centres(ny)
+    H = sw_depth(xc[:, None], yc[None, :], seed)
+    cellH = np.broadcast_to(H[None, :, :], (nt, nx, ny)).ravel().copy()
+    xi, yi = centres(n_icx), centres(n_icy)
+    X, Y = np.meshgrid(xi, yi, indexing="ij")
+    h0 = np.exp(-0.5 * (((X - 0.35) / 0.05) ** 2 + ((Y - 0.5) / 0.15) ** 2))
+    zero, one = np.array([0.0]), np.array([1.0])
+    groups = [PointGroup([zero, xi, yi.copy()], (0, 0, 0), h0.ravel(), NOISE_EXACT, out=0),
+              PointGroup([zero, xi.copy(), yi.copy()], (0, 0, 0), np.zeros(h0.size), NOISE_EXACT, out=1),
+              PointGroup([zero, xi.copy(), yi.copy()], (0, 0, 0), np.zeros(h0.size), NOISE_EXACT, out=2)]
+    tb, xb, yb = centres(n_bt), centres(n_bx), centres(n_by)
+    for edge, sign in ((0.0, -1.0), (1.0, 1.0)):          # x = 0, x = 1: h_t -/+ c h_x = 0
+        c = np.sqrt(g * sw_depth(np.full(n_by, edge), yb, seed))
+        groups.append(PointGroup([tb.copy(), np.array([edge]), yb.copy()], (1, 0, 0), np.zeros(n_bt * n_by),
+                                 NOISE_EXACT, terms=[PointTerm((1, 0, 0), 1.0, 0),
+                                                     PointTerm((0, 1, 0), sign, 0, [None, None, c])]))
+    for edge, sign in ((0.0, -1.0), (1.0, 1.0)):          # y = 0, y = 1: h_t -/+ c h_y = 0
+        c = np.sqrt(g * sw_depth(xb, np.full(n_bx, edge), seed))
+        groups.append(PointGroup([tb.copy(), xb.copy(), np.array([edge])], (1, 0, 0), np.zeros(n_bt * n_bx),
+                                 NOISE_EXACT, terms=[PointTerm((1, 0, 0), 1.0, 0),
+                                                     PointTerm((0, 0, 1), sign, 0, [None, c, None])]))
+    terms = sw_terms(g, f_cor, drag)
+    return IBVP(
+        name=f"shallow_water_{nt}x{nx}x{ny}", d=3,
+        edges=[uniform_edges(0, 1, nt), uniform_edges(0, 1, nx), uniform_edges(0, 1, ny)],
+        lengthscale=tuple(lengthscale), outputscale=1.0, terms=terms, groups=groups, cell_coef=cellH,
+        noise_pde=TAU_PDE, grid=[centres(grid_t), xc.copy(), yc.copy()], kernel=(kernel,) * 3,
+        nout=3, neq=3, out_scale=tuple(out_scale),
+        meta={"g": g, "f": f_cor, "k": drag, "H_range": [0.05, 1.0], "outputs": ["h", "u", "v"]},
+    )
+
+
 SERVING_NS = (16, 32, 48, 64)
 SERVING_NT = (16, 24, 32)
 
@@ -330,4 +462,5 @@ CONFIGS = {
     "advdiff": advdiff_c2,
     "heat2d": heat2d_c3,
     "wave2d": wave2d_c4,
+    "shallow_water": shallow_water,
 }
