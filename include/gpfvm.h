@@ -48,9 +48,11 @@ extern "C" {
 #define GPFVM_E_STATE       -6   /* call out of order (e.g. posterior before solve)  */
 
 #define GPFVM_MAX_DIM        3
-#define GPFVM_MAX_TERMS      8
+#define GPFVM_MAX_TERMS     16
 #define GPFVM_MAX_GROUPS    16
 #define GPFVM_MAX_DERIV      4   /* highest derivative order per dim in any term    */
+#define GPFVM_MAX_OUTPUTS    8   /* outputs of a multi-output prior (Sec. 3.3)      */
+#define GPFVM_MAX_PTERMS     2   /* terms of one point observation (e.g. radiation) */
 
 #define GPFVM_PREC_FP64      0   /* every step in float64                            */
 #define GPFVM_PREC_MIXED     1   /* Gram matvec in low precision (tile format below)
@@ -92,20 +94,51 @@ extern "C" {
 
 typedef struct gpfvm_handle gpfvm_handle;
 
+/* One term  coef * w(x) * d^deriv u_output(x)  of a point observation.  The
+ * per-point weight is separable over the group's grid, w(x) = prod_i
+ * weight[i][j_i] (NULL: 1 in that dim); e.g. the wave speed c = sqrt(g H)
+ * along an edge in the radiation condition h_t = c dh/dn (appendix
+ * "Tsunami propagation", boundary condition). */
+typedef struct {
+  int deriv[GPFVM_MAX_DIM];            /* derivative multi-index                     */
+  double coef;                         /* finite                                     */
+  int output;                          /* 0 .. nout-1                                */
+  const double* weight[GPFVM_MAX_DIM]; /* host: n[i] values per dim, or NULL         */
+} gpfvm_pointterm;
+
 /* One tensor grid of point observations  d^deriv u(x) = y + eps,
- * eps ~ N(0, noise_var)  (Sec. 2.2: initial and boundary observations). */
+ * eps ~ N(0, noise_var)  (Sec. 2.2: initial and boundary observations), or,
+ * with nterm >= 1, of the sum of the point terms:  sum_c terms[c] = y + eps. */
 typedef struct {
   int n[GPFVM_MAX_DIM];              /* points per dim (1 pins a dim, e.g. t = 0)    */
   const double* axis[GPFVM_MAX_DIM]; /* host: n[i] coordinates per dim               */
-  int deriv[GPFVM_MAX_DIM];          /* derivative multi-index beta                  */
+  int deriv[GPFVM_MAX_DIM];          /* derivative multi-index beta (nterm = 0)      */
   const double* y;                   /* host: prod(n) values, row-major              */
   double noise_var;                  /* > 0                                          */
+  int output;                        /* observed output (nterm = 0)                  */
+  int nterm;                         /* 0: the single term (deriv, output);          */
+                                     /* 1..GPFVM_MAX_PTERMS: the sum of terms[]      */
+  const gpfvm_pointterm* terms;      /* host                                         */
 } gpfvm_pointgroup;
 
 /* An initial-boundary value problem (Sec. 1 eq. def-lin-pde with the IBVP
  * stacking of Sec. 2.2).  The operator is D = sum_t coef[t] * (cell_coef if
  * cellwise[t]) * d^alpha_t; per-cell coefficients are constant inside a cell
- * (appendix on variable bathymetry). */
+ * (appendix on variable bathymetry).
+ *
+ * Systems (Sec. 3.3): with nout > 1 outputs the prior is
+ * k = diag(s_0 k, ..., s_{nout-1} k) (eq. multioutput-cov-def; every output
+ * the same tensor-product kernel k, outputscale s_i = out_scale[i]), and
+ * with neq > 1 equations every cell carries neq volume observations,
+ * equation e being sum over the terms t with term_eq[t] = e of
+ * coef[t] (cell_coef) d^alpha_t u_{term_out[t]}.  Volume observations are
+ * ordered equation-major (all cells of equation 0 first), so f_int then
+ * holds neq * prod(ncell) values.  The linearised shallow-water equations
+ * (appendix "Tsunami propagation", eq. sw1 to sw3) are such a system: three
+ * outputs (h, u, v), three equations, cell_coef = H.  A system is solved in
+ * float64 (IterGP or CG) and its posterior gives every output; the mixed
+ * path, the coarse warm start, targeted reduction and the server take
+ * single-output problems only (GPFVM_E_INVALID otherwise). */
 typedef struct {
   int dim;                            /* 2 or 3 (time + 1 or 2 space dims)           */
   int ncell[GPFVM_MAX_DIM];           /* cells per dim, >= 1                          */
@@ -119,12 +152,18 @@ typedef struct {
   const int* cellwise;                /* host: nterm flags, or NULL (all 0)           */
   const double* cell_coef;            /* host: N per-volume values, needed if any     */
                                       /* cellwise flag is set, else ignored           */
-  const double* f_int;                /* host: N values of int_V f, or NULL (= 0)     */
+  const double* f_int;                /* host: neq*N values of int_V f, or NULL (= 0) */
   double noise_pde;                   /* PDE observation noise (see next field)       */
   int noise_pde_relative;             /* 1: variance = noise_pde * mean diagonal of   */
                                       /* L_V k L_V';  0: variance = noise_pde         */
   int ngroup;                         /* 0..GPFVM_MAX_GROUPS                          */
   const gpfvm_pointgroup* groups;     /* host                                         */
+  int nout;                           /* outputs, 0 or 1: one                         */
+  int neq;                            /* equations per cell, 0 or 1: one              */
+  const int* term_out;                /* host: nterm output indices, or NULL (all 0)  */
+  const int* term_eq;                 /* host: nterm equation indices, or NULL (0)    */
+  const double* out_scale;            /* host: nout outputscales > 0, or NULL (all    */
+                                      /* equal to outputscale)                        */
 } gpfvm_ibvp;
 
 typedef struct {
@@ -215,7 +254,7 @@ int gpfvm_matvec(gpfvm_handle* h, int nrhs, const void* x, void* y, int dtype, i
 /* y = S x with S = L_V k L_V' + Sigma_V - G_pb G_bb^{-1} G_bp, the Gram of the
  * volume observations under the prior already conditioned on the point
  * observations (Sec. 4.2): the operator the iterative solver applies.
- * x, y: device, N*nrhs doubles (N = number of volumes), no overlap.  prec
+ * x, y: device, N*nrhs doubles (N = volume observations, neq per cell), no overlap.  prec
  * GPFVM_PREC_MIXED evaluates the volume Kronecker block in the handle's
  * low-precision tile format and the point-block correction in float64.
  * Errors: INVALID, NOMEM, HIP. */
@@ -265,8 +304,10 @@ int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* opts, gpfvm_solve_info*
  * the reduction captured by the stored directions (it equals the mathematical
  * posterior variance once the directions span the volume system).
  * n: host, dim sizes; axis: host coordinate arrays; mean, var: device,
- * prod(n) doubles row-major (var may be NULL).  Errors: INVALID, STATE
- * (no solve yet), NOMEM, HIP. */
+ * prod(n) doubles row-major (var may be NULL); for a system with nout > 1
+ * outputs, nout * prod(n) doubles, output-major (output i at i * prod(n)),
+ * each output's variance taken against its own prior s_i k.  Errors:
+ * INVALID, STATE (no solve yet), NOMEM, HIP. */
 int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const double* const* axis,
                     double* mean, double* var, void* stream);
 

@@ -22,15 +22,20 @@ PREC_FP64, PREC_MIXED = 0, 1
 TILE_FP32, TILE_BF16X3 = 0, 1      # low-precision volume-Gram tile formats
 METHOD_ITERGP, METHOD_CG = 0, 1
 DTYPE_F64, DTYPE_F32 = 0, 1
-MAX_DIM, MAX_TERMS, MAX_GROUPS = 3, 8, 16
+MAX_DIM, MAX_TERMS, MAX_GROUPS, MAX_OUTPUTS, MAX_PTERMS = 3, 16, 16, 8, 2
 ERR_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOTPD", -5: "NOCONV", -6: "STATE"}
 
 _dp = C.POINTER(C.c_double)
 
 
+class PointTerm(C.Structure):
+    _fields_ = [("deriv", C.c_int * MAX_DIM), ("coef", C.c_double), ("output", C.c_int), ("weight", _dp * MAX_DIM)]
+
+
 class PointGroup(C.Structure):
     _fields_ = [("n", C.c_int * MAX_DIM), ("axis", _dp * MAX_DIM), ("deriv", C.c_int * MAX_DIM),
-                ("y", _dp), ("noise_var", C.c_double)]
+                ("y", _dp), ("noise_var", C.c_double), ("output", C.c_int), ("nterm", C.c_int),
+                ("terms", C.POINTER(PointTerm))]
 
 
 class IBVPStruct(C.Structure):
@@ -39,7 +44,9 @@ class IBVPStruct(C.Structure):
                 ("nterm", C.c_int),
                 ("alpha", C.POINTER(C.c_int)), ("coef", _dp), ("cellwise", C.POINTER(C.c_int)),
                 ("cell_coef", _dp), ("f_int", _dp), ("noise_pde", C.c_double), ("noise_pde_relative", C.c_int),
-                ("ngroup", C.c_int), ("groups", C.POINTER(PointGroup))]
+                ("ngroup", C.c_int), ("groups", C.POINTER(PointGroup)),
+                ("nout", C.c_int), ("neq", C.c_int), ("term_out", C.POINTER(C.c_int)),
+                ("term_eq", C.POINTER(C.c_int)), ("out_scale", _dp)]
 
 
 class AssembleOpts(C.Structure):
@@ -199,6 +206,15 @@ class _Marshal:
             s.f_int = self._keep(_arr(p.f_int).ravel()).ctypes.data_as(_dp)
         s.noise_pde = float(p.noise_pde)
         s.noise_pde_relative = 1 if p.noise_pde_relative else 0
+        nout, neq = int(getattr(p, "nout", 1)), int(getattr(p, "neq", 1))
+        s.nout, s.neq = nout, neq
+        if nout > 1 or neq > 1:
+            to = self._keep(np.array([int(getattr(t, "out", 0)) for t in terms], dtype=np.int32))
+            te = self._keep(np.array([int(getattr(t, "eq", 0)) for t in terms], dtype=np.int32))
+            s.term_out = to.ctypes.data_as(C.POINTER(C.c_int))
+            s.term_eq = te.ctypes.data_as(C.POINTER(C.c_int))
+        if getattr(p, "out_scale", None) is not None:
+            s.out_scale = self._keep(_arr(p.out_scale)).ctypes.data_as(_dp)
         groups = list(p.groups)
         s.ngroup = len(groups)
         ga = (PointGroup * max(1, len(groups)))()
@@ -210,6 +226,20 @@ class _Marshal:
                 ga[k].deriv[i] = int(g.deriv[i])
             ga[k].y = self._keep(_arr(g.y).ravel()).ctypes.data_as(_dp)
             ga[k].noise_var = float(g.noise_var)
+            ga[k].output = int(getattr(g, "out", 0))
+            pts = getattr(g, "terms", None)
+            if pts:
+                ta = (PointTerm * len(pts))()
+                for c, t in enumerate(pts):
+                    for i in range(min(d, len(t.deriv))):
+                        ta[c].deriv[i] = int(t.deriv[i])
+                        if t.weights is not None and t.weights[i] is not None:
+                            ta[c].weight[i] = self._keep(_arr(t.weights[i])).ctypes.data_as(_dp)
+                    ta[c].coef = float(t.coef)
+                    ta[c].output = int(t.out)
+                self.keep.append(ta)
+                ga[k].nterm = len(pts)
+                ga[k].terms = C.cast(ta, C.POINTER(PointTerm))
         self.keep.append(ga)
         s.groups = C.cast(ga, C.POINTER(PointGroup))
         self.s = s
@@ -296,6 +326,9 @@ def solve(h, prec: int = PREC_FP64, tol: float = 1e-8, max_iter: int = 512, resu
 
 
 def posterior(h, axes: Sequence[np.ndarray], mean, var=None, stream=None) -> None:
+    """Posterior mean (and combined variance) on the grid; for a system with
+    nout outputs, mean and var hold nout * prod(len(a) for a in axes) values,
+    output-major."""
     d = len(axes)
     ax = [_arr(a) for a in axes]
     n = (C.c_int * d)(*[len(a) for a in ax])

@@ -118,10 +118,23 @@ extern "C" int gpfvm_validate(const gpfvm_ibvp* p) {
   if (N > (1LL << 31) - 1) return fail_static(GPFVM_E_INVALID, "too many volumes");
   if (!(p->outputscale > 0) || !std::isfinite(p->outputscale))
     return fail_static(GPFVM_E_INVALID, "outputscale must be positive");
+  if (p->nout < 0 || p->nout > GPFVM_MAX_OUTPUTS) return fail_static(GPFVM_E_INVALID, "nout out of range");
+  if (p->neq < 0 || p->neq > GPFVM_MAX_TERMS) return fail_static(GPFVM_E_INVALID, "neq out of range");
+  const int nout = std::max(1, p->nout), neq = std::max(1, p->neq);
+  if (p->out_scale)
+    for (int o = 0; o < nout; ++o)
+      if (!(p->out_scale[o] > 0) || !std::isfinite(p->out_scale[o]))
+        return fail_static(GPFVM_E_INVALID, "out_scale must be positive");
   if (p->nterm < 1 || p->nterm > GPFVM_MAX_TERMS) return fail_static(GPFVM_E_INVALID, "nterm out of range");
   if (!p->alpha || !p->coef) return fail_static(GPFVM_E_INVALID, "alpha/coef is NULL");
   bool any_cw = false;
+  std::vector<int> eq_used(neq, 0), out_used(nout, 0);
   for (int t = 0; t < p->nterm; ++t) {
+    const int to = p->term_out ? p->term_out[t] : 0, te = p->term_eq ? p->term_eq[t] : 0;
+    if (to < 0 || to >= nout) return fail_static(GPFVM_E_INVALID, "term_out out of range");
+    if (te < 0 || te >= neq) return fail_static(GPFVM_E_INVALID, "term_eq out of range");
+    eq_used[te] = 1;
+    out_used[to] = 1;
     for (int i = 0; i < p->dim; ++i) {
       const int a = p->alpha[t * p->dim + i];
       if (a < 0 || a > GPFVM_MAX_DERIV)
@@ -133,11 +146,14 @@ extern "C" int gpfvm_validate(const gpfvm_ibvp* p) {
     if (!std::isfinite(p->coef[t])) return fail_static(GPFVM_E_INVALID, "coef not finite");
     if (p->cellwise && p->cellwise[t]) any_cw = true;
   }
+  for (int e = 0; e < neq; ++e)
+    if (!eq_used[e]) return fail_static(GPFVM_E_INVALID, "equation " + std::to_string(e) + " has no term");
   if (any_cw) {
     if (!p->cell_coef) return fail_static(GPFVM_E_INVALID, "cellwise term without cell_coef");
     if (!finite_arr(p->cell_coef, N)) return fail_static(GPFVM_E_INVALID, "cell_coef not finite");
   }
-  if (p->f_int && !finite_arr(p->f_int, N)) return fail_static(GPFVM_E_INVALID, "f_int not finite");
+  if ((long long)neq * N > (1LL << 31) - 1) return fail_static(GPFVM_E_INVALID, "too many volume observations");
+  if (p->f_int && !finite_arr(p->f_int, (long long)neq * N)) return fail_static(GPFVM_E_INVALID, "f_int not finite");
   if (!(p->noise_pde > 0) || !std::isfinite(p->noise_pde))
     return fail_static(GPFVM_E_INVALID, "noise_pde must be positive");
   if (p->ngroup < 0 || p->ngroup > GPFVM_MAX_GROUPS) return fail_static(GPFVM_E_INVALID, "ngroup out of range");
@@ -156,6 +172,29 @@ extern "C" int gpfvm_validate(const gpfvm_ibvp* p) {
         return fail_static(GPFVM_E_INVALID, "group derivative order above the smoothness of the Matern kernel in dim " +
                                                 std::to_string(i));
       sz *= G.n[i];
+    }
+    if (G.nterm < 0 || G.nterm > GPFVM_MAX_PTERMS)
+      return fail_static(GPFVM_E_INVALID, "group " + std::to_string(g) + ": nterm out of range");
+    if (G.nterm == 0) {
+      if (G.output < 0 || G.output >= nout)
+        return fail_static(GPFVM_E_INVALID, "group " + std::to_string(g) + ": output out of range");
+      if (!out_used[G.output])
+        return fail_static(GPFVM_E_INVALID, "group " + std::to_string(g) + ": its output appears in no equation");
+    } else {
+      if (!G.terms) return fail_static(GPFVM_E_INVALID, "group " + std::to_string(g) + ": terms is NULL");
+      for (int c = 0; c < G.nterm; ++c) {
+        const gpfvm_pointterm& T = G.terms[c];
+        if (T.output < 0 || T.output >= nout || !out_used[T.output])
+          return fail_static(GPFVM_E_INVALID, "group " + std::to_string(g) + ": a term's output is out of range or "
+                                              "appears in no equation");
+        if (!std::isfinite(T.coef)) return fail_static(GPFVM_E_INVALID, "group term coef not finite");
+        for (int i = 0; i < p->dim; ++i) {
+          if (T.deriv[i] < 0 || T.deriv[i] > GPFVM_MAX_DERIV || T.deriv[i] > order_cap(i))
+            return fail_static(GPFVM_E_INVALID, "group term derivative order out of range in dim " + std::to_string(i));
+          if (T.weight[i] && !finite_arr(T.weight[i], G.n[i]))
+            return fail_static(GPFVM_E_INVALID, "group term weight not finite");
+        }
+      }
     }
     if (!G.y) return fail_static(GPFVM_E_INVALID, "group " + std::to_string(g) + ": y is NULL");
     if (!finite_arr(G.y, sz)) return fail_static(GPFVM_E_INVALID, "group y not finite");
@@ -198,23 +237,28 @@ static int add_f32_copy(gpfvm_handle* h, Factor& f) {
 
 static void merge_terms(gpfvm_handle* h) {
   // (L_V k L_V')  =  sum_{a, a'} c_a c_a' prod_i F^{a_i a'_i}, F^{pq} = (-1)^q D(p+q)
-  // (Sec. 3.2 eq. LkL): merge pairs with the same orders and scaling flags.
+  // (Sec. 3.2 eq. LkL): merge pairs with the same orders, scaling flags and equation
+  // block.  Only terms on the same output pair up (k = diag(s_i k), Sec. 3.3), and each
+  // merged coefficient carries that output's outputscale.
   h->gterms.clear();
   for (auto& t1 : h->pterms)
     for (auto& t2 : h->pterms) {
+      if (t1.out != t2.out) continue;
       GramTerm g;
       int asum = 0;
       for (int i = 0; i < h->d; ++i) {
         g.m[i] = t1.alpha[i] + t2.alpha[i];
         asum += t2.alpha[i];
       }
-      g.coef = t1.coef * t2.coef * ((asum & 1) ? -1.0 : 1.0);
+      g.coef = h->sfo[t1.out] * t1.coef * t2.coef * ((asum & 1) ? -1.0 : 1.0);
       g.lflag = t1.cellwise;
       g.rflag = t2.cellwise;
+      g.e1 = t1.eq;
+      g.e2 = t2.eq;
       bool merged = false;
       for (auto& e : h->gterms)
-        if (e.lflag == g.lflag && e.rflag == g.rflag && e.m[0] == g.m[0] && e.m[1] == g.m[1] &&
-            e.m[2] == g.m[2]) {
+        if (e.lflag == g.lflag && e.rflag == g.rflag && e.e1 == g.e1 && e.e2 == g.e2 && e.m[0] == g.m[0] &&
+            e.m[1] == g.m[1] && e.m[2] == g.m[2]) {
           e.coef += g.coef;
           merged = true;
           break;
@@ -227,22 +271,28 @@ static void merge_terms(gpfvm_handle* h) {
 
 static int build_ops(gpfvm_handle* h) {
   const int d = h->d;
-  // ---- volume block ----
-  KronOp& op = h->op_pp;
-  op = KronOp();
-  op.d = d;
-  for (int i = 0; i < d; ++i) op.in_shape[i] = op.out_shape[i] = h->nc[i];
-  op.in_len = h->N;
+  const i64 Nc = h->Nc;
+  // ---- volume block: one operator per equation (its block row of the volume Gram) ----
+  h->op_pp.assign(h->neq, KronOp());
+  for (int e = 0; e < h->neq; ++e) {
+    KronOp& op = h->op_pp[e];
+    op.d = d;
+    for (int i = 0; i < d; ++i) op.in_shape[i] = op.out_shape[i] = h->nc[i];
+    op.in_len = h->N;
+    op.out_off = (i64)e * Nc;
+  }
   if (d == 2) {
-    // pre-sum the last-dimension matrices of terms sharing (m_0, L, R)
-    struct Key { int m0, l, r; };
+    // pre-sum the last-dimension matrices of terms sharing (m_0, L, R, block)
+    struct Key { int m0, l, r, e1, e2; };
     std::vector<Key> keys;
     std::vector<std::vector<const GramTerm*>> members;
     for (auto& g : h->gterms) {
       size_t k = 0;
       for (; k < keys.size(); ++k)
-        if (keys[k].m0 == g.m[0] && keys[k].l == g.lflag && keys[k].r == g.rflag) break;
-      if (k == keys.size()) { keys.push_back({g.m[0], g.lflag, g.rflag}); members.emplace_back(); }
+        if (keys[k].m0 == g.m[0] && keys[k].l == g.lflag && keys[k].r == g.rflag && keys[k].e1 == g.e1 &&
+            keys[k].e2 == g.e2)
+          break;
+      if (k == keys.size()) { keys.push_back({g.m[0], g.lflag, g.rflag, g.e1, g.e2}); members.emplace_back(); }
       members[k].push_back(&g);
     }
     h->combos.clear();
@@ -266,49 +316,65 @@ static int build_ops(gpfvm_handle* h) {
       KronTerm t{};
       t.M[0] = h->Dfac[{0, keys[k].m0}].d; t.ld[0] = h->nc[0];
       t.M[1] = h->combos.back().d; t.ld[1] = h->nc[1];
-      t.alpha = h->sf2;
+      t.alpha = 1.0;
       t.lscale = keys[k].l; t.rscale = keys[k].r;
-      op.terms.push_back(t);
+      t.in_off = (i64)keys[k].e2 * Nc;
+      h->op_pp[keys[k].e1].terms.push_back(t);
     }
   } else {
     for (auto& g : h->gterms) {
       KronTerm t{};
       for (int i = 0; i < d; ++i) { t.M[i] = h->Dfac[{i, g.m[i]}].d; t.ld[i] = h->nc[i]; }
-      t.alpha = h->sf2 * g.coef;
+      t.alpha = g.coef;
       t.lscale = g.lflag; t.rscale = g.rflag;
-      op.terms.push_back(t);
+      t.in_off = (i64)g.e2 * Nc;
+      h->op_pp[g.e1].terms.push_back(t);
     }
   }
-  // ---- cross blocks, one operator per point group ----
+  for (int e = 0; e < h->neq; ++e)
+    if (h->op_pp[e].terms.empty()) {
+      h->err = "the volume Gram's block row of equation " + std::to_string(e) + " is identically zero";
+      return GPFVM_E_INVALID;
+    }
+  // ---- cross blocks: per point group, every (point component, PDE term) pair on one output ----
   h->op_bp.clear();
   h->op_pb.clear();
+  const size_t T = h->pterms.size();
   for (size_t gi = 0; gi < h->groups.size(); ++gi) {
     const Group& G = h->groups[gi];
-    KronOp bp, pb;
-    bp.d = pb.d = d;
-    for (int i = 0; i < d; ++i) {
-      bp.in_shape[i] = h->nc[i]; bp.out_shape[i] = G.n[i];
-      pb.in_shape[i] = G.n[i]; pb.out_shape[i] = h->nc[i];
-    }
+    KronOp bp;
+    bp.d = d;
+    for (int i = 0; i < d; ++i) { bp.in_shape[i] = h->nc[i]; bp.out_shape[i] = G.n[i]; }
     bp.in_len = h->N; bp.out_off = G.offset;
-    pb.in_len = h->nb;
-    for (size_t ti = 0; ti < h->pterms.size(); ++ti) {
-      const PdeTerm& P = h->pterms[ti];
-      KronTerm a{}, b{};
-      for (int i = 0; i < d; ++i) {
-        a.M[i] = b.M[i] = h->Qfac[gi][ti][i].d;
-        a.ld[i] = b.ld[i] = h->nc[i];
-        b.trans[i] = 1;
-      }
-      a.alpha = b.alpha = h->sf2 * P.coef;
-      a.rscale = P.cellwise;
-      b.lscale = P.cellwise;
-      b.in_off = G.offset;
-      bp.terms.push_back(a);
-      pb.terms.push_back(b);
+    std::vector<KronOp> pb(h->neq);
+    for (int e = 0; e < h->neq; ++e) {
+      pb[e].d = d;
+      for (int i = 0; i < d; ++i) { pb[e].in_shape[i] = G.n[i]; pb[e].out_shape[i] = h->nc[i]; }
+      pb[e].in_len = h->nb;
+      pb[e].out_off = (i64)e * Nc;
     }
+    for (size_t c = 0; c < G.comps.size(); ++c)
+      for (size_t ti = 0; ti < T; ++ti) {
+        const PdeTerm& P = h->pterms[ti];
+        if (P.out != G.comps[c].out) continue;
+        KronTerm a{}, b{};
+        for (int i = 0; i < d; ++i) {
+          a.M[i] = b.M[i] = h->Qfac[gi][c * T + ti][i].d;
+          a.ld[i] = b.ld[i] = h->nc[i];
+          b.trans[i] = 1;
+        }
+        a.alpha = b.alpha = h->sfo[P.out] * G.comps[c].coef * P.coef;
+        a.rscale = P.cellwise;
+        a.in_off = (i64)P.eq * Nc;
+        b.lscale = P.cellwise;
+        b.in_off = G.offset;
+        bp.terms.push_back(a);
+        pb[P.eq].terms.push_back(b);
+      }
+    if (bp.terms.empty()) { h->err = "a point group shares no output with the equations"; return GPFVM_E_INVALID; }
     h->op_bp.push_back(bp);
-    h->op_pb.push_back(pb);
+    for (auto& o : pb)
+      if (!o.terms.empty()) h->op_pb.push_back(o);
   }
   return GPFVM_OK;
 }
@@ -332,7 +398,8 @@ int gpfvm::build_ops32(gpfvm_handle* h) {
       for (int i = 0; i < h->d; ++i) t.M[i] = to32(t.M[i]);
     return b;
   };
-  h->op_pp32 = conv(h->op_pp);
+  h->op_pp32.clear();
+  for (auto& o : h->op_pp) h->op_pp32.push_back(conv(o));
   h->op_bp32.clear(); h->op_pb32.clear();
   for (auto& o : h->op_bp) h->op_bp32.push_back(conv(o));
   for (auto& o : h->op_pb) h->op_pb32.push_back(conv(o));
@@ -350,19 +417,42 @@ int gpfvm::build_ops32(gpfvm_handle* h) {
 }
 
 
+// rows (columns) of a row-major n1 x n2 factor times per-point weights wr (wc); null: 1
+__global__ void k_scale_rows_cols(double* __restrict__ A, int n1, int n2, const double* __restrict__ wr,
+                                  const double* __restrict__ wc) {
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (i64)n1 * n2) return;
+  double v = A[i];
+  if (wr) v *= wr[i / n2];
+  if (wc) v *= wc[i % n2];
+  A[i] = v;
+}
+
+hipError_t gpfvm::scale_rows_cols(double* A, int n1, int n2, const double* wr, const double* wc, hipStream_t s) {
+  if (!wr && !wc) return hipSuccess;
+  const i64 n = (i64)n1 * n2;
+  hipLaunchKernelGGL(k_scale_rows_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, n1, n2, wr, wc);
+  return hipGetLastError();
+}
+
 static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, hipStream_t s, gpfvm_handle* h) {
   const int d = p->dim;
   h->d = d;
   h->stream = s;
-  h->N = 1;
+  h->Nc = 1;
   for (int i = 0; i < d; ++i) {
     h->nc[i] = p->ncell[i];
-    h->N *= p->ncell[i];
+    h->Nc *= p->ncell[i];
     h->ell[i] = p->lengthscale[i];
     h->kq[i] = p->kernel[i] == GPFVM_KERNEL_SE ? -1 : p->kernel[i] - 1;
     h->edges_h[i].assign(p->edges[i], p->edges[i] + p->ncell[i] + 1);
   }
-  h->sf2 = p->outputscale;
+  h->nout = std::max(1, p->nout);
+  h->neq = std::max(1, p->neq);
+  h->N = h->Nc * h->neq;
+  for (int o = 0; o < h->nout; ++o) h->sfo[o] = p->out_scale ? p->out_scale[o] : p->outputscale;
+  h->sf2 = h->sfo[0];
+  h->multi = h->nout > 1 || h->neq > 1;
   h->max_iter = opts ? std::max(1, opts->max_iter) : 512;
   h->tile = opts ? opts->tile : GPFVM_TILE_FP32;
   for (int t = 0; t < p->nterm; ++t) {
@@ -370,6 +460,8 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
     for (int i = 0; i < d; ++i) P.alpha[i] = p->alpha[t * d + i];
     P.coef = p->coef[t];
     P.cellwise = (p->cellwise && p->cellwise[t]) ? 1 : 0;
+    P.out = p->term_out ? p->term_out[t] : 0;
+    P.eq = p->term_eq ? p->term_eq[t] : 0;
     h->pterms.push_back(P);
   }
   h->has_cc = 0;
@@ -381,10 +473,28 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
     G.size = 1;
     for (int i = 0; i < d; ++i) {
       G.n[i] = S.n[i];
-      G.deriv[i] = S.deriv[i];
       G.axis[i].assign(S.axis[i], S.axis[i] + S.n[i]);
       G.size *= S.n[i];
     }
+    if (S.nterm == 0) {
+      PointComp c;
+      for (int i = 0; i < d; ++i) c.deriv[i] = S.deriv[i];
+      c.out = S.output;
+      G.comps.push_back(c);
+    } else {
+      h->multi = true;
+      for (int k = 0; k < S.nterm; ++k) {
+        PointComp c;
+        for (int i = 0; i < d; ++i) {
+          c.deriv[i] = S.terms[k].deriv[i];
+          if (S.terms[k].weight[i]) c.w[i].assign(S.terms[k].weight[i], S.terms[k].weight[i] + S.n[i]);
+        }
+        c.coef = S.terms[k].coef;
+        c.out = S.terms[k].output;
+        G.comps.push_back(c);
+      }
+    }
+    for (int i = 0; i < d; ++i) G.deriv[i] = G.comps[0].deriv[i];
     G.noise = S.noise_var;
     G.offset = off;
     off += G.size;
@@ -399,8 +509,13 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
   int rc;
   for (int i = 0; i < d; ++i)
     if ((rc = upload(h, h->edges_h[i].data(), h->edges_h[i].size(), &h->edges[i]))) return rc;
-  if (h->has_cc)
-    if ((rc = upload(h, p->cell_coef, (size_t)h->N, &h->cellc))) return rc;
+  if (h->has_cc) {
+    // the per-cell coefficient once per equation block, so every block of the volume vector
+    // finds its cell's value at the same offset
+    std::vector<double> cc((size_t)h->N);
+    for (int e = 0; e < h->neq; ++e) std::memcpy(&cc[(size_t)e * h->Nc], p->cell_coef, (size_t)h->Nc * sizeof(double));
+    if ((rc = upload(h, cc.data(), cc.size(), &h->cellc))) return rc;
+  }
   {
     std::vector<double> y((size_t)h->n, 0.0);
     for (int g = 0; g < p->ngroup; ++g)
@@ -419,32 +534,64 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
       h->Dfac[key] = f;
     }
   std::vector<std::array<double*, 3>> gaxis(h->groups.size());
-  for (size_t g = 0; g < h->groups.size(); ++g)
+  // per-point weights of the point components on the device: [group][comp][dim] (null: 1)
+  std::vector<std::vector<std::array<double*, 3>>> gw(h->groups.size());
+  for (size_t g = 0; g < h->groups.size(); ++g) {
     for (int i = 0; i < d; ++i)
       if ((rc = upload(h, h->groups[g].axis[i].data(), h->groups[g].axis[i].size(), &gaxis[g][i]))) return rc;
-  h->Qfac.assign(h->groups.size(), std::vector<std::array<Factor, 3>>(h->pterms.size()));
-  for (size_t g = 0; g < h->groups.size(); ++g)
-    for (size_t t = 0; t < h->pterms.size(); ++t)
-      for (int i = 0; i < d; ++i)
-        if ((rc = make_factor(h, 1, h->groups[g].deriv[i], h->pterms[t].alpha[i], h->groups[g].n[i], gaxis[g][i],
-                              h->nc[i], h->edges[i], i, h->Qfac[g][t][i])))
-          return rc;
-  std::vector<Factor> ppf;
-  GramMeta M;
+    gw[g].resize(h->groups[g].comps.size());
+    for (size_t c = 0; c < h->groups[g].comps.size(); ++c)
+      for (int i = 0; i < 3; ++i) {
+        gw[g][c][i] = nullptr;
+        const auto& w = h->groups[g].comps[c].w[i];
+        if (i < d && !w.empty())
+          if ((rc = upload(h, w.data(), w.size(), &gw[g][c][i]))) return rc;
+      }
+  }
+  const size_t T = h->pterms.size();
+  h->Qfac.assign(h->groups.size(), std::vector<std::array<Factor, 3>>());
+  for (size_t g = 0; g < h->groups.size(); ++g) {
+    const Group& G = h->groups[g];
+    h->Qfac[g].resize(G.comps.size() * T);
+    for (size_t c = 0; c < G.comps.size(); ++c)
+      for (size_t t = 0; t < T; ++t) {
+        if (h->pterms[t].out != G.comps[c].out) continue;
+        for (int i = 0; i < d; ++i) {
+          Factor& f = h->Qfac[g][c * T + t][i];
+          if ((rc = make_factor(h, 1, G.comps[c].deriv[i], h->pterms[t].alpha[i], G.n[i], gaxis[g][i], h->nc[i],
+                                h->edges[i], i, f)))
+            return rc;
+          HIPCHK(h, scale_rows_cols(f.d, f.n1, f.n2, gw[g][c][i], nullptr, s));
+        }
+      }
+  }
+  GramMeta* Mp = new (std::nothrow) GramMeta;
+  if (!Mp) { h->err = "host allocation failed"; return GPFVM_E_NOMEM; }
+  std::unique_ptr<GramMeta> Mown(Mp);
+  GramMeta& M = *Mp;
   std::memset(&M, 0, sizeof(M));
   for (size_t g1 = 0; g1 < h->groups.size(); ++g1)
-    for (size_t g2 = 0; g2 < h->groups.size(); ++g2)
-      for (int i = 0; i < d; ++i) {
-        Factor f;
-        if ((rc = make_factor(h, 2, h->groups[g1].deriv[i], h->groups[g2].deriv[i], h->groups[g1].n[i], gaxis[g1][i],
-                              h->groups[g2].n[i], gaxis[g2][i], i, f)))
-          return rc;
-        M.Pp[g1][g2][i] = f.d;
-      }
+    for (size_t g2 = 0; g2 < h->groups.size(); ++g2) {
+      const Group &A = h->groups[g1], &B = h->groups[g2];
+      for (size_t c1 = 0; c1 < A.comps.size(); ++c1)
+        for (size_t c2 = 0; c2 < B.comps.size(); ++c2) {
+          if (A.comps[c1].out != B.comps[c2].out) continue;
+          M.pcoef[g1][c1][g2][c2] = h->sfo[A.comps[c1].out] * A.comps[c1].coef * B.comps[c2].coef;
+          for (int i = 0; i < d; ++i) {
+            Factor f;
+            if ((rc = make_factor(h, 2, A.comps[c1].deriv[i], B.comps[c2].deriv[i], A.n[i], gaxis[g1][i], B.n[i],
+                                  gaxis[g2][i], i, f)))
+              return rc;
+            HIPCHK(h, scale_rows_cols(f.d, f.n1, f.n2, gw[g1][c1][i], gw[g2][c2][i], s));
+            M.Pp[g1][c1][g2][c2][i] = f.d;
+          }
+        }
+    }
 
   // ---- PDE noise ----
   if (p->noise_pde_relative) {
-    // mean over volumes of diag(L_V k L_V') = sf2 * sum_terms coef L R prod_i D_i(m_i)[j_i, j_i]
+    // mean over the volume observations of diag(L_V k L_V'): for equation e the merged
+    // terms of block (e, e), sum_terms coef L R prod_i D_i(m_i)[j_i, j_i] (coef with s_out)
     std::map<std::pair<int, int>, std::vector<double>> diag;
     for (auto& kv : h->Dfac) {
       const int n1 = kv.second.n1;
@@ -460,12 +607,13 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
       for (int i = 0; i < d; ++i) dp[t][i] = diag[{i, h->gterms[t].m[i]}].data();
     double acc = 0;
     int idx[3];
-    for (i64 v = 0; v < h->N; ++v) {
+    for (i64 v = 0; v < h->Nc; ++v) {
       i64 r = v;
       for (int i = d - 1; i >= 0; --i) { idx[i] = (int)(r % h->nc[i]); r /= h->nc[i]; }
       double sv = 0;
       for (size_t t = 0; t < h->gterms.size(); ++t) {
         const GramTerm& g = h->gterms[t];
+        if (g.e1 != g.e2) continue;
         double w = g.coef;
         if (g.lflag) w *= p->cell_coef[v];
         if (g.rflag) w *= p->cell_coef[v];
@@ -474,34 +622,42 @@ static int assemble_impl(const gpfvm_ibvp* p, const gpfvm_assemble_opts* opts, h
       }
       acc += sv;
     }
-    h->sig_pde = p->noise_pde * h->sf2 * acc / (double)h->N;
+    h->sig_pde = p->noise_pde * acc / (double)h->N;
   } else {
     h->sig_pde = p->noise_pde;
   }
 
   // ---- dense-entry metadata (point block, dense Gram tiles) ----
-  M.d = d; M.nb = h->nb; M.ngroup = (int)h->groups.size(); M.nterm = (int)h->pterms.size();
+  M.d = d; M.nb = h->nb; M.ngroup = (int)h->groups.size(); M.nterm = (int)T;
   M.ngterm = (int)h->gterms.size();
+  M.neq = h->neq;
+  M.Nc = h->Nc;
   if (M.ngterm > MAXGT) { h->err = "too many merged operator terms"; return GPFVM_E_INVALID; }
   for (int i = 0; i < d; ++i) M.nc[i] = h->nc[i];
   for (int i = d; i < 3; ++i) M.nc[i] = 1;
   for (size_t g = 0; g < h->groups.size(); ++g) {
-    for (int i = 0; i < 3; ++i) M.gn[g][i] = (i < d) ? h->groups[g].n[i] : 1;
-    M.goff[g] = h->groups[g].offset;
-    M.gnoise[g] = h->groups[g].noise;
-    for (size_t t = 0; t < h->pterms.size(); ++t)
-      for (int i = 0; i < d; ++i) M.Qp[g][t][i] = h->Qfac[g][t][i].d;
+    const Group& G = h->groups[g];
+    for (int i = 0; i < 3; ++i) M.gn[g][i] = (i < d) ? G.n[i] : 1;
+    M.goff[g] = G.offset;
+    M.gnoise[g] = G.noise;
+    M.gcomp[g] = (int)G.comps.size();
+    for (size_t c = 0; c < G.comps.size(); ++c)
+      for (size_t t = 0; t < T; ++t) {
+        if (h->pterms[t].out != G.comps[c].out) continue;
+        M.qcoef[g][c][t] = h->sfo[G.comps[c].out] * G.comps[c].coef * h->pterms[t].coef;
+        for (int i = 0; i < d; ++i) M.Qp[g][c][t][i] = h->Qfac[g][c * T + t][i].d;
+      }
   }
   M.goff[h->groups.size()] = h->nb;
-  for (size_t t = 0; t < h->pterms.size(); ++t) { M.tcoef[t] = h->pterms[t].coef; M.tcw[t] = h->pterms[t].cellwise; }
+  for (size_t t = 0; t < T; ++t) { M.tcw[t] = h->pterms[t].cellwise; M.teq[t] = h->pterms[t].eq; }
   for (size_t t = 0; t < h->gterms.size(); ++t) {
     for (int i = 0; i < 3; ++i) M.gm[t][i] = h->gterms[t].m[i];
     M.gcoef[t] = h->gterms[t].coef; M.gl[t] = h->gterms[t].lflag; M.gr[t] = h->gterms[t].rflag;
+    M.ge1[t] = h->gterms[t].e1; M.ge2[t] = h->gterms[t].e2;
   }
   for (auto& kv : h->Dfac) M.Dp[kv.first.first][kv.first.second] = kv.second.d;
   M.cellc = h->cellc;
   M.sig_pde = h->sig_pde;
-  M.sf2 = h->sf2;
   h->meta = (GramMeta*)h->arena.alloc(sizeof(GramMeta));
   if (!h->meta) { h->err = "out of device memory"; return GPFVM_E_NOMEM; }
   HIPCHK(h, hipMemcpyAsync(h->meta, &M, sizeof(M), hipMemcpyHostToDevice, s));
@@ -593,9 +749,8 @@ int gpfvm::get_full_ops(gpfvm_handle* h, int nrhs, gpfvm_opset** out) {
   os->TB = (double*)h->arena.alloc((size_t)std::max<i64>(nb, 1) * nrhs * sizeof(double));
   if (!os->XF || !os->YF || !os->TB) { h->err = "out of device memory"; return GPFVM_E_NOMEM; }
   // bind with explicit strides (vectors are [points; volumes] of length n)
-  std::vector<KronOp> pp{h->op_pp};
-  int rc = compile_kron_list(pp, F64, nrhs, os->XF + nb, n, os->YF + nb, n, h->cellc, h->cellc, 0.0, os->XF + nb,
-                         h->sig_pde, 1, h->arena, h->stream, os->pp, h->err);
+  int rc = compile_kron_list(h->op_pp, F64, nrhs, os->XF + nb, n, os->YF + nb, n, h->cellc, h->cellc, 0.0,
+                             os->XF + nb, h->sig_pde, pp_accumulate(h), h->arena, h->stream, os->pp, h->err);
   if (rc) return rc;
   if (nb > 0) {
     rc = compile_kron_list(h->op_bp, F64, nrhs, os->XF + nb, n, os->YF, n, h->cellc, h->cellc, 0.0, nullptr, 0, 0,
@@ -621,6 +776,7 @@ extern "C" int gpfvm_matvec(gpfvm_handle* h, int nrhs, const void* x, void* y, i
   if (!h) return fail_static(GPFVM_E_INVALID, "handle is NULL");
   if (nrhs < 1 || nrhs > 4096 || !x || !y) { h->err = "matvec: bad nrhs or NULL buffer"; return GPFVM_E_INVALID; }
   if (prec != GPFVM_PREC_FP64 && prec != GPFVM_PREC_MIXED) { h->err = "matvec: bad prec"; return GPFVM_E_INVALID; }
+  if (prec == GPFVM_PREC_MIXED && h->multi) { h->err = "matvec: the mixed path takes single-output problems"; return GPFVM_E_INVALID; }
   if (dtype != GPFVM_DTYPE_F64 && dtype != GPFVM_DTYPE_F32) { h->err = "matvec: bad dtype"; return GPFVM_E_INVALID; }
   const size_t esz = dtype == GPFVM_DTYPE_F64 ? sizeof(double) : sizeof(float);
   const size_t bytes = (size_t)h->n * nrhs * esz;
@@ -665,6 +821,7 @@ extern "C" int gpfvm_volume_matvec(gpfvm_handle* h, int nrhs, const double* x, d
   if (!h) return fail_static(GPFVM_E_INVALID, "handle is NULL");
   if (nrhs < 1 || nrhs > 4096 || !x || !y) { h->err = "volume_matvec: bad nrhs or NULL buffer"; return GPFVM_E_INVALID; }
   if (prec != GPFVM_PREC_FP64 && prec != GPFVM_PREC_MIXED) { h->err = "volume_matvec: bad prec"; return GPFVM_E_INVALID; }
+  if (prec == GPFVM_PREC_MIXED && h->multi) { h->err = "volume_matvec: the mixed path takes single-output problems"; return GPFVM_E_INVALID; }
   const size_t bytes = (size_t)h->N * nrhs * sizeof(double);
   if ((const char*)x < (const char*)y + bytes && (const char*)y < (const char*)x + bytes) {
     h->err = "volume_matvec: x and y overlap";
@@ -690,9 +847,8 @@ extern "C" int gpfvm_volume_matvec(gpfvm_handle* h, int nrhs, const double* x, d
     h->user_ranges.push_back(x);
     h->user_ranges.push_back(y);
     auto pl = std::make_unique<Plan>();
-    std::vector<KronOp> pp{h->op_pp};
-    int rc = compile_kron_list(pp, F64, nrhs, x, h->N, y, h->N, h->cellc, h->cellc, 0.0, x, h->sig_pde, 1, h->arena,
-                               s, *pl, h->err);
+    int rc = compile_kron_list(h->op_pp, F64, nrhs, x, h->N, y, h->N, h->cellc, h->cellc, 0.0, x, h->sig_pde,
+                               pp_accumulate(h), h->arena, s, *pl, h->err);
     if (rc) return rc;
     it = h->vplans.emplace(key, std::move(pl)).first;
   }

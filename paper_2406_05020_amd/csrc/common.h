@@ -210,24 +210,34 @@ struct Factor {            // (n1 x n2) matrix on the device, row-major
   int n1 = 0, n2 = 0;
 };
 
+struct PointComp {         // coef * w(x) * d^deriv u_out(x), w separable over the grid
+  int deriv[3] = {0, 0, 0};
+  double coef = 1;
+  int out = 0;
+  std::vector<double> w[3];   // per-dim weights (empty: 1)
+};
+
 struct Group {
   int n[3] = {1, 1, 1};
-  int deriv[3] = {0, 0, 0};
+  int deriv[3] = {0, 0, 0};   // the first component's derivative (single-term groups)
   double noise = 0;
   i64 size = 0, offset = 0;
   std::vector<double> axis[3];
+  std::vector<PointComp> comps;   // the observation is the sum of its components
 };
 
-struct PdeTerm {           // coef * (cell_coef if cellwise) * d^alpha
+struct PdeTerm {           // coef * (cell_coef if cellwise) * d^alpha u_out, in equation eq
   int alpha[3] = {0, 0, 0};
   double coef = 0;
   int cellwise = 0;
+  int out = 0, eq = 0;
 };
 
-struct GramTerm {          // merged volume-Gram term
+struct GramTerm {          // merged volume-Gram term (block eq1 x eq2, outputscale included)
   int m[3] = {0, 0, 0};
   double coef = 0;
   int lflag = 0, rflag = 0;
+  int e1 = 0, e2 = 0;
 };
 
 // Element offsets between the problems of a batch: problem z = blockIdx.y of a
@@ -355,11 +365,15 @@ struct GpfvmBatch {
 struct gpfvm_handle {
   int d = 0;
   int nc[3] = {1, 1, 1};
-  gpfvm::i64 N = 0, n = 0;
+  gpfvm::i64 N = 0, n = 0;         // N: volume observations (neq per cell), n = n_b + N
+  gpfvm::i64 Nc = 0;               // cells
   int nb = 0;
+  int nout = 1, neq = 1;           // outputs of the prior, equations per cell
+  bool multi = false;              // several outputs or equations, or multi-term point groups
+  double sfo[GPFVM_MAX_OUTPUTS] = {1, 1, 1, 1, 1, 1, 1, 1};   // outputscale per output
   double ell[3] = {1, 1, 1};
   int kq[3] = {-1, -1, -1};        // per dim: -1 squared exponential, q >= 0 Matern nu = q + 1/2
-  double sf2 = 1;
+  double sf2 = 1;                  // outputscale of output 0
   double sig_pde = 0;
   int has_cc = 0;
   int tile = GPFVM_TILE_FP32;
@@ -374,12 +388,12 @@ struct gpfvm_handle {
 
   gpfvm::Arena arena;
   double* edges[3] = {nullptr, nullptr, nullptr};
-  double* cellc = nullptr;         // N per-volume coefficient (or null)
+  double* cellc = nullptr;         // per-volume coefficient, repeated for each equation (N values), or null
   float* cellc_f = nullptr;
   double* yobs = nullptr;          // n: [y_b ; int_V f]
   std::map<std::pair<int, int>, gpfvm::Factor> Dfac;   // (dim, order) -> D_i(order)
   std::vector<gpfvm::Factor> combos;                  // pre-summed factor matrices
-  std::vector<std::vector<std::array<gpfvm::Factor, 3>>> Qfac;   // [group][term][dim]
+  std::vector<std::vector<std::array<gpfvm::Factor, 3>>> Qfac;   // [group][comp * nterm + term][dim]
   double* L = nullptr;             // n_b x n_b Cholesky factor of G_bb (lower)
   double* Linv = nullptr;          // n_b x n_b L^{-1} (lower)
   double* Lt = nullptr;            // row-major copies of L^T and L^{-T}
@@ -393,7 +407,7 @@ struct gpfvm_handle {
   bool process_cache = false;      // arena blocks come from the per-process cache
   float* Linv_f = nullptr;
   gpfvm::GramMeta* meta = nullptr;   // device
-  gpfvm::KronOp op_pp, op_pp32;
+  std::vector<gpfvm::KronOp> op_pp, op_pp32;   // one operator per equation (output block)
   std::vector<gpfvm::KronOp> op_bp, op_pb, op_bp32, op_pb32;
   std::map<int, std::unique_ptr<gpfvm_opset>> full_ops;  // by nrhs
   std::map<int, std::unique_ptr<gpfvm_sop>> sops;        // by nrhs (F64)

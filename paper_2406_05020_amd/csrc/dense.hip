@@ -39,38 +39,48 @@ __global__ void k_gram_block(const GramMeta* __restrict__ meta, i64 r0, i64 nr, 
   double v = 0;
   int ir[3] = {0, 0, 0}, ic[3] = {0, 0, 0};
   const bool rp = r < G.nb, cp = c < G.nb;
-  if (rp && cp) {                      // point - point
+  if (rp && cp) {                      // point - point: component pairs on the same output
     const int g1 = find_group(G, r), g2 = find_group(G, c);
     unflatten(r - G.goff[g1], d, G.gn[g1], ir);
     unflatten(c - G.goff[g2], d, G.gn[g2], ic);
-    double p = 1;
-    for (int i = 0; i < d; ++i) p *= G.Pp[g1][g2][i][(i64)ir[i] * G.gn[g2][i] + ic[i]];
-    v = G.sf2 * p;
+    for (int c1 = 0; c1 < G.gcomp[g1]; ++c1)
+      for (int c2 = 0; c2 < G.gcomp[g2]; ++c2) {
+        const double a = G.pcoef[g1][c1][g2][c2];
+        if (a == 0.0) continue;
+        double p = a;
+        for (int i = 0; i < d; ++i) p *= G.Pp[g1][c1][g2][c2][i][(i64)ir[i] * G.gn[g2][i] + ic[i]];
+        v += p;
+      }
     if (r == c) v += G.gnoise[g1];
-  } else if (rp != cp) {               // point - volume (symmetric)
-    const i64 pr = rp ? r : c, vc = rp ? c : r;
+  } else if (rp != cp) {               // point - volume (symmetric): the volume's equation
+    const i64 pr = rp ? r : c, vo = (rp ? c : r) - G.nb;
     const int g = find_group(G, pr);
+    const int e = (int)(vo / G.Nc);
+    const i64 vc = vo - (i64)e * G.Nc;
     unflatten(pr - G.goff[g], d, G.gn[g], ir);
-    unflatten(vc - G.nb, d, G.nc, ic);
-    for (int t = 0; t < G.nterm; ++t) {
-      double p = G.tcoef[t];
-      if (G.tcw[t]) p *= G.cellc[vc - G.nb];
-      for (int i = 0; i < d; ++i) p *= G.Qp[g][t][i][(i64)ir[i] * G.nc[i] + ic[i]];
-      v += p;
-    }
-    v *= G.sf2;
-  } else {                             // volume - volume
-    const i64 vr = r - G.nb, vc = c - G.nb;
+    unflatten(vc, d, G.nc, ic);
+    for (int k = 0; k < G.gcomp[g]; ++k)
+      for (int t = 0; t < G.nterm; ++t) {
+        if (G.teq[t] != e || G.qcoef[g][k][t] == 0.0) continue;
+        double p = G.qcoef[g][k][t];
+        if (G.tcw[t]) p *= G.cellc[vc];
+        for (int i = 0; i < d; ++i) p *= G.Qp[g][k][t][i][(i64)ir[i] * G.nc[i] + ic[i]];
+        v += p;
+      }
+  } else {                             // volume - volume: merged terms of the two equations
+    const i64 vr0 = r - G.nb, vc0 = c - G.nb;
+    const int er = (int)(vr0 / G.Nc), ec = (int)(vc0 / G.Nc);
+    const i64 vr = vr0 - (i64)er * G.Nc, vc = vc0 - (i64)ec * G.Nc;
     unflatten(vr, d, G.nc, ir);
     unflatten(vc, d, G.nc, ic);
     for (int t = 0; t < G.ngterm; ++t) {
+      if (G.ge1[t] != er || G.ge2[t] != ec) continue;
       double p = G.gcoef[t];
       if (G.gl[t]) p *= G.cellc[vr];
       if (G.gr[t]) p *= G.cellc[vc];
       for (int i = 0; i < d; ++i) p *= G.Dp[i][G.gm[t][i]][(i64)ir[i] * G.nc[i] + ic[i]];
       v += p;
     }
-    v *= G.sf2;
     if (r == c) v += G.sig_pde;
   }
   out[(idx / nc) * ld + (idx % nc)] = v;

@@ -11,25 +11,39 @@ constexpr int MAXG = GPFVM_MAX_GROUPS;
 constexpr int MAXT = GPFVM_MAX_TERMS;
 constexpr int MAXGT = 64;                  // merged volume-Gram terms
 constexpr int MAXM = 2 * GPFVM_MAX_DERIV + 1;
+constexpr int MAXC = GPFVM_MAX_PTERMS;     // components of one point observation
 
-// Everything the dense Gram-entry kernel needs, in one device struct.
+// Everything the dense Gram-entry kernel needs, in one device struct.  Every
+// coefficient carries its output's outputscale; a pair of terms on different
+// outputs has coefficient 0 (and no factor).  Point-group factors carry the
+// components' per-point weights on their group's side.
 struct GramMeta {
-  int d, nb, ngroup, nterm, ngterm, pad;
+  int d, nb, ngroup, nterm, ngterm, neq;
+  i64 Nc;                                  // cells (volume observations: neq * Nc)
   int nc[3];
   int gn[MAXG][3];
+  int gcomp[MAXG];
   i64 goff[MAXG + 1];
   double gnoise[MAXG];
-  double tcoef[MAXT];
-  int tcw[MAXT];
+  int tcw[MAXT], teq[MAXT];
+  double qcoef[MAXG][MAXC][MAXT];          // point comp x PDE term
   int gm[MAXGT][3];
   double gcoef[MAXGT];
-  int gl[MAXGT], gr[MAXGT];
+  int gl[MAXGT], gr[MAXGT], ge1[MAXGT], ge2[MAXGT];
+  double pcoef[MAXG][MAXC][MAXG][MAXC];    // point comp x point comp
   const double* Dp[3][MAXM];               // cell-cell factors D_i(m), ld = nc[i]
-  const double* Qp[MAXG][MAXT][3];         // point-cell, ld = nc[i]
-  const double* Pp[MAXG][MAXG][3];         // point-point, ld = gn[g2][i]
+  const double* Qp[MAXG][MAXC][MAXT][3];   // point-cell, ld = nc[i]
+  const double* Pp[MAXG][MAXC][MAXG][MAXC][3];   // point-point, ld = gn[g2][i]
   const double* cellc;
-  double sig_pde, sf2;
+  double sig_pde;
 };
+
+// The volume operators write disjoint blocks when there are several equations (each its
+// own output block, so each its own first write); one operator accumulates its chunks.
+inline int pp_accumulate(const gpfvm_handle* h) { return h->op_pp.size() == 1 ? 1 : 0; }
+
+// rows (columns) of a row-major n1 x n2 matrix times wr (wc); a null vector means 1
+hipError_t scale_rows_cols(double* A, int n1, int n2, const double* wr, const double* wc, hipStream_t s);
 
 hipError_t launch_gram_block(const GramMeta* meta, i64 r0, i64 nr, i64 c0, i64 nc, double* out, i64 ld,
                              hipStream_t s);

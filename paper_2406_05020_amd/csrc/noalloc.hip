@@ -61,10 +61,9 @@ extern "C" int gpfvm_volume_matvec_noalloc(gpfvm_handle* h, int nrhs, const doub
   a.fixed = base;
   a.fixed_cap = GPFVM_NOALLOC_SCRATCH_BYTES;
   Plan pl;
-  std::vector<KronOp> pp{h->op_pp};
   std::string err;
-  int rc = compile_kron_list(pp, F64, nrhs, x, h->N, y, h->N, h->cellc, h->cellc, 0.0, x, h->sig_pde, 1, a, s, pl,
-                             err);
+  int rc = compile_kron_list(h->op_pp, F64, nrhs, x, h->N, y, h->N, h->cellc, h->cellc, 0.0, x, h->sig_pde,
+                             pp_accumulate(h), a, s, pl, err);
   if (rc == GPFVM_E_NOMEM) {
     rc = GPFVM_E_INVALID;
     err = "volume_matvec_noalloc: the plan for this problem and nrhs needs more than the " +

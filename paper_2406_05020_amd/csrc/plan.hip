@@ -234,14 +234,15 @@ int compile_kron_list(const std::vector<KronOp>& ops, Elt elt, int nrhs, const v
   bool need_xs = false;
   for (auto& op : ops)
     for (auto& t : op.terms) need_xs |= (t.rscale != 0);
-  // Per-volume input scaling applies to volume-shaped inputs only: every op
-  // with a scaled term reads prod(in_shape) values at offset 0 of each rhs.
+  // Per-volume input scaling applies to volume inputs only: the whole input of
+  // every rhs (in_len values: one block of prod(in_shape) volumes per equation)
+  // is scaled once, and a scaled term reads its block at in_off.
   i64 xs_len = 0;
   for (auto& op : ops)
     for (auto& t : op.terms)
       if (t.rscale) {
-        const i64 len = prod(op.in_shape, 0, op.d);
-        if (t.in_off != 0 || (xs_len && xs_len != len) || len > x_rhs_stride) {
+        const i64 len = op.in_len;
+        if (t.in_off + prod(op.in_shape, 0, op.d) > len || (xs_len && xs_len != len) || len > x_rhs_stride) {
           err = "internal error: per-volume scaling of a non-volume input";
           return GPFVM_E_INVALID;
         }
@@ -385,7 +386,7 @@ int compile_kron_list(const std::vector<KronOp>& ops, Elt elt, int nrhs, const v
         }
         if (any_l) {
           if (!escale64) { err = "operator needs per-volume coefficients"; return GPFVM_E_INVALID; }
-          D.escale = escale64;
+          D.escale = escale64 + op.out_off;   // the coefficients of this output block
         }
         if (first_write && addx && (oi == 0 || !accumulate)) {
           D.X = (const char*)addx + (size_t)op.out_off * es + (batch_ok ? 0 : (size_t)r * y_rhs_stride * es);

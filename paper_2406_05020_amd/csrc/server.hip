@@ -31,6 +31,9 @@
 
 using namespace gpfvm;
 
+// PDE terms a request's memory estimate allows for (plan intermediates per term)
+constexpr int EST_TERMS = 8;
+
 namespace {
 
 double now_s() {
@@ -209,7 +212,7 @@ static size_t estimate_bytes(const gpfvm_ibvp& p, int max_iter, long long M, int
   const double d8 = 8.0;
   double b = 0;
   b += 2.0 * N * max_iter * d8;                            // directions and S D
-  b += (48.0 + 6.0 * GPFVM_MAX_TERMS) * N * d8;           // solver vectors, plan intermediates, full-Gram buffers
+  b += (48.0 + 6.0 * EST_TERMS) * N * d8;           // solver vectors, plan intermediates, full-Gram buffers
   b += 4.0 * nb * nb * d8;             // L, L^{-1} (and transposes)
   if (qform_ok(N, nb)) b += 3.0 * nb * N * d8;             // point correction Q and its build buffers
   b += 2.0 * nb * 64 * d8 + 4.0 * (nb + 64) * 64 * d8;     // Cholesky workspace
@@ -240,7 +243,7 @@ static size_t batch_extra_bytes(const gpfvm_ibvp& p, int max_iter) {
     for (int i = 0; i < p.dim; ++i) s *= p.groups[g].n[i];
     nb += s;
   }
-  const double b = (2.0 * max_iter + 24.0 + 2.0 * GPFVM_MAX_TERMS) * N * 8.0 + 8.0 * nb * 8.0 + 8.0 * max_iter;
+  const double b = (2.0 * max_iter + 24.0 + 2.0 * EST_TERMS) * N * 8.0 + 8.0 * nb * 8.0 + 8.0 * max_iter;
   return (size_t)(1.25 * b);
 }
 
@@ -482,6 +485,10 @@ extern "C" int gpfvm_server_submit(gpfvm_server* S, const gpfvm_ibvp* p, int dim
   int rc = gpfvm_validate(p);
   if (rc) return rc;
   if (dim != p->dim || !n || !axis) return GPFVM_E_INVALID;
+  // requests are single-output problems (the copy below keeps no system fields)
+  if (p->nout > 1 || p->neq > 1 || p->term_out || p->term_eq || p->out_scale) return GPFVM_E_INVALID;
+  for (int g = 0; g < p->ngroup; ++g)
+    if (p->groups[g].nterm != 0 || p->groups[g].output != 0) return GPFVM_E_INVALID;
   auto r = std::make_unique<gpfvm_request>();
   r->gdim = dim;
   r->M = 1;

@@ -256,15 +256,20 @@ __global__ void k_var_final(i64 M, double sf2, const double* __restrict__ red, d
 }
 
 // dense point-grid cross-covariance block: out[b][x - x0] = sf2 prod_i P_i[b_i][x_i]
+// Cross-covariances of the point observations with one output at the grid
+// points: row b of group g is sum_c pc[g][c] prod_i P[g][c][i][b_i][x_i] over the
+// group's components (pc = 0: a component on another output).
 struct PGMeta {
   int d, ngroup;
   int gn[GPFVM_MAX_GROUPS][3];
   i64 goff[GPFVM_MAX_GROUPS + 1];
   int gdim[3];
-  const double* P[GPFVM_MAX_GROUPS][3];    // n_{g,i} x G_i
+  int gcomp[GPFVM_MAX_GROUPS];
+  double pc[GPFVM_MAX_GROUPS][MAXC];               // outputscale x component coefficient
+  const double* P[GPFVM_MAX_GROUPS][MAXC][3];      // n_{g,i} x G_i, component weights folded in
 };
 
-__global__ void k_point_grid(const PGMeta* __restrict__ meta, int nb, i64 x0, i64 nx, double sf2,
+__global__ void k_point_grid(const PGMeta* __restrict__ meta, int nb, i64 x0, i64 nx,
                              double* __restrict__ out) {
   const PGMeta& G = *meta;
   const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -277,9 +282,14 @@ __global__ void k_point_grid(const PGMeta* __restrict__ meta, int nb, i64 x0, i6
   for (int i = G.d - 1; i >= 0; --i) { ib[i] = (int)(r % G.gn[g][i]); r /= G.gn[g][i]; }
   r = x;
   for (int i = G.d - 1; i >= 0; --i) { ix[i] = (int)(r % G.gdim[i]); r /= G.gdim[i]; }
-  double p = sf2;
-  for (int i = 0; i < G.d; ++i) p *= G.P[g][i][(i64)ib[i] * G.gdim[i] + ix[i]];
-  out[b * nx + xl] = p;
+  double v = 0.0;
+  for (int c = 0; c < G.gcomp[g]; ++c) {
+    if (G.pc[g][c] == 0.0) continue;
+    double p = G.pc[g][c];
+    for (int i = 0; i < G.d; ++i) p *= G.P[g][c][i][(i64)ib[i] * G.gdim[i] + ix[i]];
+    v += p;
+  }
+  out[b * nx + xl] = v;
 }
 
 
@@ -453,7 +463,7 @@ static int build_qc(gpfvm_handle* h, hipStream_t s) {
 // of the n_b N of a resident Q.
 // ---------------------------------------------------------------------------
 static bool qfact_ok(const gpfvm_handle* h, int* W_out, int* R_out) {
-  if (h->d != 2 || h->nb <= 0) return false;
+  if (h->d != 2 || h->nb <= 0 || h->multi) return false;
   for (const auto& t : h->pterms)
     if (t.cellwise) return false;
   int W = 0, R = 0;
@@ -574,7 +584,8 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
   auto& tab = (elt == F64) ? h->sops : h->sops32;
   auto it = tab.find(nrhs);
   if (it != tab.end()) { *out = it->second.get(); return GPFVM_OK; }
-  if (elt != F64 && h->op_pp32.terms.empty()) {
+  if (elt != F64 && h->multi) { h->err = "the mixed path takes single-output problems"; return GPFVM_E_INVALID; }
+  if (elt != F64 && h->op_pp32.empty()) {
     int rc = build_ops32(h);
     if (rc) return rc;
   }
@@ -596,15 +607,13 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
   }
   int rc;
   if (elt == F64) {
-    std::vector<KronOp> pp{h->op_pp};
-    rc = compile_kron_list(pp, F64, nrhs, so->X, N, so->Y, N, h->cellc, h->cellc, 0.0, so->X, h->sig_pde, 1,
-                           h->arena, h->stream, so->pp, h->err);
+    rc = compile_kron_list(h->op_pp, F64, nrhs, so->X, N, so->Y, N, h->cellc, h->cellc, 0.0, so->X, h->sig_pde,
+                           pp_accumulate(h), h->arena, h->stream, so->pp, h->err);
   } else {
     so->X32 = h->arena.alloc((size_t)N * nrhs * 4);
     so->Y32 = h->arena.alloc((size_t)N * nrhs * 4);
     if (!so->X32 || !so->Y32) { h->err = "out of device memory (S operator)"; return GPFVM_E_NOMEM; }
-    std::vector<KronOp> pp{h->op_pp32};
-    rc = compile_kron_list(pp, lowp, nrhs, so->X32, N, so->Y32, N, h->cellc_f, h->cellc, 0.0, so->X32, h->sig_pde,
+    rc = compile_kron_list(h->op_pp32, lowp, nrhs, so->X32, N, so->Y32, N, h->cellc_f, h->cellc, 0.0, so->X32, h->sig_pde,
                            1, h->arena, h->stream, so->pp, h->err);
   }
   if (rc) return rc;
@@ -1396,6 +1405,10 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
   if (!o) o = &def;
   if (o->prec != GPFVM_PREC_FP64 && o->prec != GPFVM_PREC_MIXED) { h->err = "solve: bad prec"; return GPFVM_E_INVALID; }
   if (o->method != GPFVM_METHOD_ITERGP && o->method != GPFVM_METHOD_CG) { h->err = "solve: bad method"; return GPFVM_E_INVALID; }
+  if (o->prec == GPFVM_PREC_MIXED && h->multi) {
+    h->err = "solve: the mixed path takes single-output problems";
+    return GPFVM_E_INVALID;
+  }
   if (o->prec == GPFVM_PREC_MIXED && o->tile != h->tile) {
     h->err = "solve: the mixed path's tile format must be the one given at assemble";
     return GPFVM_E_INVALID;
@@ -1422,6 +1435,10 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
     if (f < 1 || h->nc[k] % f != 0) { h->err = "solve: coarsening factors must divide the cell counts"; return GPFVM_E_INVALID; }
     n_coarse *= h->nc[k] / f;
     coarse |= (f > 1);
+  }
+  if (coarse && h->multi) {
+    h->err = "solve: the coarse warm start takes single-output problems";
+    return GPFVM_E_INVALID;
   }
   if (coarse) {
     if (o->resume || o->prec != GPFVM_PREC_FP64 || o->reorth_passes != 2 || o->method != GPFVM_METHOD_ITERGP) {
@@ -1582,6 +1599,7 @@ extern "C" int gpfvm_solve(gpfvm_handle* h, const gpfvm_solve_opts* o, gpfvm_sol
 extern "C" int gpfvm_refine_variance(gpfvm_handle* h, int dim, const int* n, const double* const* axis, int iters,
                                      const double* weights, gpfvm_solve_info* info, void* stream) {
   if (!h) return GPFVM_E_INVALID;
+  if (h->multi) { h->err = "refine_variance: targeted reduction takes single-output problems"; return GPFVM_E_INVALID; }
   if (dim != h->d || !n || !axis) { h->err = "refine_variance: bad target grid"; return GPFVM_E_INVALID; }
   i64 M = 1;
   for (int i = 0; i < dim; ++i) {
@@ -1774,7 +1792,7 @@ extern "C" int gpfvm_weights(gpfvm_handle* h, double* alpha, void* stream) {
 // On the wave problem this solves 36 864 columns instead of 131 072 and touches
 // only each group's rows of L^{-1}.
 // ---------------------------------------------------------------------------
-constexpr int GV_MAXG = 8;                   // groups handled by the grouped form
+constexpr int GV_MAXG = 12;                  // (group, component) pairs handled by the grouped form
 struct GVGroupDev {
   i64 off, C;                                // row offset, columns (free grid coordinates)
   i64 cs[3];                                 // column stride of each free grid coordinate (0 if pinned)
@@ -1794,8 +1812,8 @@ struct GVFactor {                            // one group's B_g^T (free grid coo
   const double* P[3];                        // n_{g,i} x gdim_i
 };
 
-// Bt[a][p] = sf2 prod_{i free} P_i[p_i][a_i]  (a over the free grid coordinates, p over the points)
-__global__ void k_gv_bt(GVFactor F, double sf2, i64 C, i64 np, double* __restrict__ Bt) {
+// Bt[a][p] = coef prod_{i free} P_i[p_i][a_i]  (a over the free grid coordinates, p over the points)
+__global__ void k_gv_bt(GVFactor F, double coef, i64 C, i64 np, double* __restrict__ Bt) {
   const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= C * np) return;
   const i64 a = idx / np, p = idx % np;
@@ -1805,7 +1823,7 @@ __global__ void k_gv_bt(GVFactor F, double sf2, i64 C, i64 np, double* __restric
   r = a;
   for (int i = F.d - 1; i >= 0; --i)
     if (F.isfree[i]) { ai[i] = (int)(r % F.ext[i]); r /= F.ext[i]; }
-  double v = sf2;
+  double v = coef;
   for (int i = 0; i < F.d; ++i)
     if (F.isfree[i]) v *= F.P[i][(i64)pi[i] * F.ext[i] + ai[i]];
   Bt[idx] = v;
@@ -1853,26 +1871,32 @@ __global__ __launch_bounds__(256) void k_gv_direct(const GVMeta* __restrict__ me
   red[x] += acc;
 }
 
-// The grouped point variance into red.  Returns 1 when it does not apply (more than
-// GV_MAXG groups, products not clearly cheaper than the chunked L^{-1} K_b, or buffers
-// beyond three of its chunk buffers); else a GPFVM code.
+// The grouped point variance into red.  Every (group, component) pair on the output is
+// one term of k_b(x) (two components of a group share its rows; their offsets tie, so
+// the first one's band of rows is empty and the second's covers both).  Returns 1 when
+// it does not apply (more than GV_MAXG pairs, products not clearly cheaper than the
+// chunked L^{-1} K_b, or buffers beyond three of its chunk buffers); else a GPFVM code.
 static int grouped_point_var(gpfvm_handle* h, const PGMeta& pg, const int* n, i64 M, double* red, Arena& tmp,
                              hipStream_t s) {
-  const int d = h->d, G = (int)h->groups.size();
+  const int d = h->d;
   const i64 nb = h->nb;
+  struct Grp { int g, c; double coef; i64 off, np, K, C; int isfree[3]; i64 cs[3]; double* Bt; double* U; };
+  std::vector<Grp> gr;
+  for (int g = 0; g < (int)h->groups.size(); ++g)
+    for (int c = 0; c < pg.gcomp[g]; ++c)
+      if (pg.pc[g][c] != 0.0) gr.push_back(Grp{g, c, pg.pc[g][c]});
+  const int G = (int)gr.size();
   if (G < 1 || G > GV_MAXG) return 1;
-  struct Grp { i64 off, np, K, C; int isfree[3]; i64 cs[3]; double* Bt; double* U; };
-  std::vector<Grp> gr(G);
   double work = 0, words = 0;
-  for (int g = 0; g < G; ++g) {
-    Grp& q = gr[g];
-    q.off = h->groups[g].offset;
+  for (Grp& q : gr) {
+    const Group& H = h->groups[q.g];
+    q.off = H.offset;
     q.np = 1;
     q.C = 1;
     for (int i = 0; i < 3; ++i) { q.isfree[i] = 0; q.cs[i] = 0; }
     for (int i = 0; i < d; ++i) {
-      q.np *= h->groups[g].n[i];
-      q.isfree[i] = h->groups[g].n[i] > 1;
+      q.np *= H.n[i];
+      q.isfree[i] = H.n[i] > 1;
     }
     for (int i = d - 1; i >= 0; --i) {
       q.cs[i] = q.isfree[i] ? q.C : 0;
@@ -1884,8 +1908,7 @@ static int grouped_point_var(gpfvm_handle* h, const PGMeta& pg, const int* n, i6
   }
   if (work > 0.25 * (double)nb * nb * M) return 1;
   if (words > 3.0 * nb * posterior_chunk(nb, M)) return 1;     // within the posterior's memory estimate
-  for (int g = 0; g < G; ++g) {
-    Grp& q = gr[g];
+  for (Grp& q : gr) {
     q.Bt = (double*)tmp.alloc((size_t)(q.C * q.np) * sizeof(double));
     q.U = (double*)tmp.alloc((size_t)(q.C * q.K) * sizeof(double));
     if (!q.Bt || !q.U) { h->err = "posterior: out of device memory"; return GPFVM_E_NOMEM; }
@@ -1893,12 +1916,12 @@ static int grouped_point_var(gpfvm_handle* h, const PGMeta& pg, const int* n, i6
     F.d = d;
     for (int i = 0; i < 3; ++i) { F.pn[i] = 1; F.ext[i] = 1; F.isfree[i] = 0; F.P[i] = nullptr; }
     for (int i = 0; i < d; ++i) {
-      F.pn[i] = h->groups[g].n[i];
+      F.pn[i] = h->groups[q.g].n[i];
       F.ext[i] = n[i];
       F.isfree[i] = q.isfree[i];
-      F.P[i] = pg.P[g][i];
+      F.P[i] = pg.P[q.g][q.c][i];
     }
-    hipLaunchKernelGGL(k_gv_bt, dim3(nblk(q.C * q.np)), dim3(256), 0, s, F, h->sf2, q.C, q.np, q.Bt);
+    hipLaunchKernelGGL(k_gv_bt, dim3(nblk(q.C * q.np)), dim3(256), 0, s, F, q.coef, q.C, q.np, q.Bt);
     // U (K x C) = X_sub (K x np) Bt^T, X_sub = L^{-1}[off:, off:off+np]
     if (gemm_rows_abt((int)q.K, (int)q.C, (int)q.np, h->Linv + q.off * nb + q.off, (int)nb, q.Bt, (int)q.np, q.U,
                       (int)q.C, s) != hipSuccess) {
@@ -1916,7 +1939,7 @@ static int grouped_point_var(gpfvm_handle* h, const PGMeta& pg, const int* n, i6
     meta.grp[g].C = gr[g].C;
     for (int i = 0; i < 3; ++i) meta.grp[g].cs[i] = gr[g].cs[i];
     meta.grp[g].U = gr[g].U;
-    for (int i = 0; i < d; ++i) meta.grp[g].W[i] = gr[g].isfree[i] ? nullptr : pg.P[g][i];
+    for (int i = 0; i < d; ++i) meta.grp[g].W[i] = gr[g].isfree[i] ? nullptr : pg.P[gr[g].g][gr[g].c][i];
   }
   GVMeta* dmeta = (GVMeta*)tmp.alloc(sizeof(GVMeta));
   if (!dmeta) { h->err = "posterior: out of device memory"; return GPFVM_E_NOMEM; }
@@ -1933,7 +1956,11 @@ static int grouped_point_var(gpfvm_handle* h, const PGMeta& pg, const int* n, i6
     case 5: hipLaunchKernelGGL(k_gv_direct<5>, grid, block, 0, s, (const GVMeta*)dmeta, M, nb, red); break;
     case 6: hipLaunchKernelGGL(k_gv_direct<6>, grid, block, 0, s, (const GVMeta*)dmeta, M, nb, red); break;
     case 7: hipLaunchKernelGGL(k_gv_direct<7>, grid, block, 0, s, (const GVMeta*)dmeta, M, nb, red); break;
-    default: hipLaunchKernelGGL(k_gv_direct<8>, grid, block, 0, s, (const GVMeta*)dmeta, M, nb, red); break;
+    case 8: hipLaunchKernelGGL(k_gv_direct<8>, grid, block, 0, s, (const GVMeta*)dmeta, M, nb, red); break;
+    case 9: hipLaunchKernelGGL(k_gv_direct<9>, grid, block, 0, s, (const GVMeta*)dmeta, M, nb, red); break;
+    case 10: hipLaunchKernelGGL(k_gv_direct<10>, grid, block, 0, s, (const GVMeta*)dmeta, M, nb, red); break;
+    case 11: hipLaunchKernelGGL(k_gv_direct<11>, grid, block, 0, s, (const GVMeta*)dmeta, M, nb, red); break;
+    default: hipLaunchKernelGGL(k_gv_direct<12>, grid, block, 0, s, (const GVMeta*)dmeta, M, nb, red); break;
   }
   if (hipGetLastError() != hipSuccess) { h->err = "posterior: launch failed"; return GPFVM_E_HIP; }
   return GPFVM_OK;
@@ -1958,7 +1985,8 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
   hipStream_t s = (hipStream_t)stream;
   h->stream = s;
   const int d = h->d;
-  const i64 N = h->N;
+  const i64 N = h->N, Nc = h->Nc;
+  const size_t T = h->pterms.size();
   Arena tmp;    // per-call allocations
   tmp.cache = h->arena.cache;
   auto fail = [&](int code, const std::string& m) { h->err = m; (void)hipStreamSynchronize(s); tmp.release(); return code; };
@@ -1970,9 +1998,10 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
     if (hipMemcpyAsync(gax[i], axis[i], n[i] * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
       return fail(GPFVM_E_HIP, "posterior: copy failed");
   }
-  // grid-cell factors per term and dim, grid-point factors per group and dim
-  std::vector<std::array<double*, 3>> Qg(h->pterms.size());
-  for (size_t t = 0; t < h->pterms.size(); ++t)
+  // grid-cell factors per term and dim, grid-point factors per point component and dim
+  // (the component's per-point weights folded into its rows)
+  std::vector<std::array<double*, 3>> Qg(T);
+  for (size_t t = 0; t < T; ++t)
     for (int i = 0; i < d; ++i) {
       Qg[t][i] = (double*)tmp.alloc((size_t)n[i] * h->nc[i] * sizeof(double));
       if (!Qg[t][i]) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
@@ -1985,157 +2014,198 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
   pg.d = d;
   pg.ngroup = (int)h->groups.size();
   for (int i = 0; i < d; ++i) pg.gdim[i] = n[i];
-  std::vector<std::array<double*, 3>> gaxis(h->groups.size());
   for (size_t g = 0; g < h->groups.size(); ++g) {
-    pg.goff[g] = h->groups[g].offset;
+    const Group& G = h->groups[g];
+    pg.goff[g] = G.offset;
+    pg.gcomp[g] = (int)G.comps.size();
+    for (int i = 0; i < d; ++i) pg.gn[g][i] = G.n[i];
+    double* ga[3] = {nullptr, nullptr, nullptr};
     for (int i = 0; i < d; ++i) {
-      const Group& G = h->groups[g];
-      pg.gn[g][i] = G.n[i];
-      gaxis[g][i] = (double*)tmp.alloc(G.n[i] * sizeof(double));
-      double* P = (double*)tmp.alloc((size_t)G.n[i] * n[i] * sizeof(double));
-      if (!gaxis[g][i] || !P) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
-      if (hipMemcpyAsync(gaxis[g][i], G.axis[i].data(), G.n[i] * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+      ga[i] = (double*)tmp.alloc(G.n[i] * sizeof(double));
+      if (!ga[i]) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+      if (hipMemcpyAsync(ga[i], G.axis[i].data(), G.n[i] * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(GPFVM_E_HIP, "posterior: copy failed");
-      // P[b][x] = d^beta_1 k(x_b, x)
-      if (launch_factor(2, h->kq[i], G.deriv[i], 0, G.n[i], gaxis[g][i], n[i], gax[i], h->ell[i], 1.0, P, n[i], s) !=
-          hipSuccess)
-        return fail(GPFVM_E_HIP, "posterior: factor launch failed");
-      pg.P[g][i] = P;
     }
+    for (size_t c = 0; c < G.comps.size(); ++c)
+      for (int i = 0; i < d; ++i) {
+        const PointComp& C = G.comps[c];
+        double* P = (double*)tmp.alloc((size_t)G.n[i] * n[i] * sizeof(double));
+        if (!P) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+        // P[b][x] = d^beta_1 k(x_b, x), times the component's weight of point b
+        if (launch_factor(2, h->kq[i], C.deriv[i], 0, G.n[i], ga[i], n[i], gax[i], h->ell[i], 1.0, P, n[i], s) !=
+            hipSuccess)
+          return fail(GPFVM_E_HIP, "posterior: factor launch failed");
+        if (!C.w[i].empty()) {
+          double* w = (double*)tmp.alloc(G.n[i] * sizeof(double));
+          if (!w) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+          if (hipMemcpyAsync(w, C.w[i].data(), G.n[i] * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+              scale_rows_cols(P, G.n[i], n[i], w, nullptr, s) != hipSuccess)
+            return fail(GPFVM_E_HIP, "posterior: weight scaling failed");
+        }
+        pg.P[g][c][i] = P;
+      }
   }
   pg.goff[h->groups.size()] = h->nb;
-  // operators: K_*p (cells -> grid), K_*b (points -> grid)
-  KronOp gp;
-  gp.d = d;
-  for (int i = 0; i < d; ++i) { gp.in_shape[i] = h->nc[i]; gp.out_shape[i] = n[i]; }
-  gp.in_len = N;
-  for (size_t t = 0; t < h->pterms.size(); ++t) {
-    KronTerm k{};
-    for (int i = 0; i < d; ++i) { k.M[i] = Qg[t][i]; k.ld[i] = h->nc[i]; }
-    k.alpha = h->sf2 * h->pterms[t].coef;
-    k.rscale = h->pterms[t].cellwise;
-    gp.terms.push_back(k);
-  }
-  std::vector<KronOp> gb;
-  for (size_t g = 0; g < h->groups.size(); ++g) {
-    KronOp o;
-    o.d = d;
-    for (int i = 0; i < d; ++i) { o.in_shape[i] = h->groups[g].n[i]; o.out_shape[i] = n[i]; }
-    o.in_len = h->nb;
-    KronTerm k{};
-    for (int i = 0; i < d; ++i) { k.M[i] = pg.P[g][i]; k.ld[i] = n[i]; k.trans[i] = 1; }
-    k.alpha = h->sf2;
-    k.in_off = h->groups[g].offset;
-    o.terms.push_back(k);
-    gb.push_back(o);
-  }
-  // ---- mean = K_*b alpha_b + K_*p alpha_p ----
   struct UserRange {
     const void* p;
     UserRange(const void* q, size_t n) : p(q) { register_range(q, n); }
     ~UserRange() { unregister_range(p); }
-  } user_mean(mean, (size_t)M * sizeof(double));
+  } user_mean(mean, (size_t)M * h->nout * sizeof(double));
   double* alpha = (double*)tmp.alloc((size_t)h->n * sizeof(double));
   if (!alpha) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
   int rc = gpfvm_weights(h, alpha, s);
   if (rc) { tmp.release(); return rc; }
-  {
-    Plan pm, pmb;
-    std::vector<KronOp> ops{gp};
-    rc = compile_kron_list(ops, F64, 1, alpha + h->nb, N, mean, M, h->cellc, h->cellc, 0.0, nullptr, 0, 1, tmp, s, pm,
-                           h->err);
-    if (rc) { tmp.release(); return rc; }
-    if (h->nb > 0) {
-      rc = compile_kron_list(gb, F64, 1, alpha, h->nb, mean, M, nullptr, nullptr, 1.0, nullptr, 0, 1, tmp, s, pmb,
-                             h->err);
-      if (rc) { tmp.release(); return rc; }
-    }
-    if (run_plan(pm, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: mean plan failed");
-    if (h->nb > 0 && run_plan(pmb, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: mean plan failed");
+  // ---- variance buffers and the output-independent part of the direction term ----
+  const int K = var ? h->iters : 0;
+  const i64 widest = std::max<i64>(std::max<i64>(M, N), std::max(h->nb, 1));
+  const int B = K > 0 ? (int)posterior_dir_batch(K, widest) : 0;
+  double *red = nullptr, *P1 = nullptr, *P2 = nullptr, *Ub = nullptr, *Tb = nullptr, *Wb = nullptr, *Rb = nullptr,
+         *Dbuf = nullptr;
+  Plan pbp;
+  std::vector<Stage> st;
+  if (var) {
+    red = (double*)tmp.alloc((size_t)M * sizeof(double));
+    if (!red) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
   }
-  if (!var) {
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: sync failed");
-    tmp.release();
-    return GPFVM_OK;
-  }
-  // ---- variance = sf2 - ||L^{-1} k_b(x)||^2 - sum_j (w_j(x))^2 / eta_j ----
-  double* red = (double*)tmp.alloc((size_t)M * sizeof(double));
-  if (!red) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
-  if (launch_fill(red, 0.0, M, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: fill failed");
-  if (h->nb > 0) {
-    PGMeta* dpg = (PGMeta*)tmp.alloc(sizeof(PGMeta));
-    if (!dpg) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
-    if (hipMemcpyAsync(dpg, &pg, sizeof(pg), hipMemcpyHostToDevice, s) != hipSuccess)
-      return fail(GPFVM_E_HIP, "posterior: copy failed");
-    const int grc = grouped_point_var(h, pg, n, M, red, tmp, s);
-    if (grc != 1 && grc != GPFVM_OK) return fail(grc, h->err);
-    if (grc == 1) {
-    const i64 chunk = posterior_chunk(h->nb, M);
-    double* KB = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
-    double* TT = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
-    double* CP = (double*)tmp.alloc((size_t)COLSQ_MAX_CHUNKS * chunk * sizeof(double));
-    if (!KB || !TT || !CP) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
-    for (i64 x0 = 0; x0 < M; x0 += chunk) {
-      const i64 nx = std::min(chunk, M - x0);
-      hipLaunchKernelGGL(k_point_grid, dim3(nblk((i64)h->nb * nx)), dim3(256), 0, s, (const PGMeta*)dpg, h->nb, x0, nx,
-                         h->sf2, KB);
-      // T = L^{-1} KB by the explicit inverse (a library TRMM).  Its forward error, about
-      // cond(L) eps relative, is that of a triangular solve, so ||T||^2 needs no residual
-      // correction here (the solver's operator does: there the products must stay
-      // consistent over hundreds of iterations).
-      if (trmm_rows_left_lower(h->nb, (int)nx, 1.0, h->Linv, h->nb, KB, (int)nx, TT, (int)nx, s) != hipSuccess)
-        return fail(GPFVM_E_HIP, "posterior: triangular product failed");
-      const int R = colsq_chunks(h->nb, nx);
-      hipLaunchKernelGGL(k_colsq_part, dim3((unsigned)((nx + 63) / 64), (unsigned)R), dim3(256), 0, s, (i64)h->nb, nx,
-                         (const double*)TT, CP);
-      hipLaunchKernelGGL(k_colsq_finish, dim3(nblk(nx)), dim3(256), 0, s, nx, R, (const double*)CP, red + x0);
-    }
-    }
-  }
-  const int K = h->iters;
   if (K > 0) {
-    const i64 widest = std::max<i64>(std::max<i64>(M, N), std::max(h->nb, 1));
-    const int B = (int)posterior_dir_batch(K, widest);
-    double* P1 = (double*)tmp.alloc((size_t)M * B * sizeof(double));
-    double* P2 = h->nb > 0 ? (double*)tmp.alloc((size_t)M * B * sizeof(double)) : nullptr;
-    double* Ub = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
-    double* Tb = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
-    double* Wb = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
-    double* Rb = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
-    double* Dbuf = (double*)tmp.alloc((size_t)N * B * sizeof(double));
+    P1 = (double*)tmp.alloc((size_t)M * B * sizeof(double));
+    P2 = h->nb > 0 ? (double*)tmp.alloc((size_t)M * B * sizeof(double)) : nullptr;
+    Ub = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
+    Tb = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
+    Wb = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
+    Rb = h->nb > 0 ? (double*)tmp.alloc((size_t)h->nb * B * sizeof(double)) : nullptr;
+    Dbuf = (double*)tmp.alloc((size_t)N * B * sizeof(double));
     if (!P1 || !Dbuf || (h->nb > 0 && (!P2 || !Ub || !Tb || !Wb || !Rb)))
       return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
-    Plan pgp, pbp, pgb;
-    std::vector<KronOp> ops{gp};
-    rc = compile_kron_list(ops, F64, B, Dbuf, N, P1, M, h->cellc, h->cellc, 0.0, nullptr, 0, 1, tmp, s, pgp, h->err);
-    if (rc) { tmp.release(); return rc; }
-    std::vector<Stage> st;
     if (h->nb > 0) {
       rc = compile_kron_list(h->op_bp, F64, B, Dbuf, N, Ub, h->nb, h->cellc, h->cellc, 0.0, nullptr, 0, 0, tmp, s, pbp,
                              h->err);
       if (rc) { tmp.release(); return rc; }
-      rc = compile_kron_list(gb, F64, B, Wb, h->nb, P2, M, nullptr, nullptr, 0.0, nullptr, 0, 1, tmp, s, pgb, h->err);
-      if (rc) { tmp.release(); return rc; }
       st = ginv_stages(h, B, Ub, Tb, Wb, Rb);
       if (upload_stages(st, tmp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: upload failed");
     }
-    for (int j0 = 0; j0 < K; j0 += B) {
-      const int nr = std::min(B, K - j0);
-      if (hipMemcpyAsync(Dbuf, h->Dd + (i64)j0 * N, (size_t)nr * N * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return fail(GPFVM_E_HIP, "posterior: copy failed");
-      if (nr < B && launch_fill(Dbuf + (i64)nr * N, 0.0, (i64)(B - nr) * N, s) != hipSuccess)
-        return fail(GPFVM_E_HIP, "posterior: fill failed");
-      if (run_plan(pgp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
-      if (h->nb > 0) {
-        if (run_plan(pbp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
-        if (run_stages(st, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: gemm failed");
-        if (run_plan(pgb, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
-      }
-      hipLaunchKernelGGL(k_sub_sq_acc, dim3(nblk(M)), dim3(256), 0, s, M, nr, (const double*)P1,
-                         (const double*)(h->nb > 0 ? P2 : nullptr), (const double*)(h->eta + j0), red);
-    }
   }
-  hipLaunchKernelGGL(k_var_final, dim3(nblk(M)), dim3(256), 0, s, M, h->sf2, (const double*)red, var);
+  std::vector<std::unique_ptr<PGMeta>> pg_keep;
+  for (int o = 0; o < h->nout; ++o) {
+    double* mean_o = mean + (i64)o * M;
+    double* var_o = var ? var + (i64)o * M : nullptr;
+    // operators for output o: K_*p (volumes -> grid), K_*b (points -> grid)
+    KronOp gp;
+    gp.d = d;
+    for (int i = 0; i < d; ++i) { gp.in_shape[i] = h->nc[i]; gp.out_shape[i] = n[i]; }
+    gp.in_len = N;
+    for (size_t t = 0; t < T; ++t) {
+      if (h->pterms[t].out != o) continue;
+      KronTerm k{};
+      for (int i = 0; i < d; ++i) { k.M[i] = Qg[t][i]; k.ld[i] = h->nc[i]; }
+      k.alpha = h->sfo[o] * h->pterms[t].coef;
+      k.rscale = h->pterms[t].cellwise;
+      k.in_off = (i64)h->pterms[t].eq * Nc;
+      gp.terms.push_back(k);
+    }
+    std::vector<KronOp> gb;
+    for (size_t g = 0; g < h->groups.size(); ++g) {
+      const Group& G = h->groups[g];
+      KronOp op;
+      op.d = d;
+      for (int i = 0; i < d; ++i) { op.in_shape[i] = G.n[i]; op.out_shape[i] = n[i]; }
+      op.in_len = h->nb;
+      for (size_t c = 0; c < G.comps.size(); ++c) {
+        pg.pc[g][c] = G.comps[c].out == o ? h->sfo[o] * G.comps[c].coef : 0.0;
+        if (G.comps[c].out != o) continue;
+        KronTerm k{};
+        for (int i = 0; i < d; ++i) { k.M[i] = pg.P[g][c][i]; k.ld[i] = n[i]; k.trans[i] = 1; }
+        k.alpha = h->sfo[o] * G.comps[c].coef;
+        k.in_off = G.offset;
+        op.terms.push_back(k);
+      }
+      if (!op.terms.empty()) gb.push_back(op);
+    }
+    // ---- mean = K_*b alpha_b + K_*p alpha_p ----
+    if (gp.terms.empty()) {
+      if (launch_fill(mean_o, 0.0, M, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: fill failed");
+    } else {
+      Plan pm;
+      std::vector<KronOp> ops{gp};
+      rc = compile_kron_list(ops, F64, 1, alpha + h->nb, N, mean_o, M, h->cellc, h->cellc, 0.0, nullptr, 0, 1, tmp, s,
+                             pm, h->err);
+      if (rc) { tmp.release(); return rc; }
+      if (run_plan(pm, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: mean plan failed");
+    }
+    if (!gb.empty()) {
+      Plan pmb;
+      rc = compile_kron_list(gb, F64, 1, alpha, h->nb, mean_o, M, nullptr, nullptr, 1.0, nullptr, 0, 1, tmp, s, pmb,
+                             h->err);
+      if (rc) { tmp.release(); return rc; }
+      if (run_plan(pmb, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: mean plan failed");
+    }
+    if (!var) continue;
+    // ---- variance = s_o - ||L^{-1} k_b(x)||^2 - sum_j (w_j(x))^2 / eta_j ----
+    if (launch_fill(red, 0.0, M, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: fill failed");
+    if (h->nb > 0 && !gb.empty()) {
+      // this output's coefficients, from a host copy that outlives the queued upload
+      pg_keep.push_back(std::make_unique<PGMeta>(pg));
+      PGMeta* dpg = (PGMeta*)tmp.alloc(sizeof(PGMeta));
+      if (!dpg) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+      if (hipMemcpyAsync(dpg, pg_keep.back().get(), sizeof(pg), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(GPFVM_E_HIP, "posterior: copy failed");
+      const int grc = grouped_point_var(h, pg, n, M, red, tmp, s);
+      if (grc != 1 && grc != GPFVM_OK) return fail(grc, h->err);
+      if (grc == 1) {
+        const i64 chunk = posterior_chunk(h->nb, M);
+        double* KB = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
+        double* TT = (double*)tmp.alloc((size_t)h->nb * chunk * sizeof(double));
+        double* CP = (double*)tmp.alloc((size_t)COLSQ_MAX_CHUNKS * chunk * sizeof(double));
+        if (!KB || !TT || !CP) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
+        for (i64 x0 = 0; x0 < M; x0 += chunk) {
+          const i64 nx = std::min(chunk, M - x0);
+          hipLaunchKernelGGL(k_point_grid, dim3(nblk((i64)h->nb * nx)), dim3(256), 0, s, (const PGMeta*)dpg, h->nb, x0,
+                             nx, KB);
+          // T = L^{-1} KB by the explicit inverse (a library TRMM).  Its forward error, about
+          // cond(L) eps relative, is that of a triangular solve, so ||T||^2 needs no residual
+          // correction here (the solver's operator does: there the products must stay
+          // consistent over hundreds of iterations).
+          if (trmm_rows_left_lower(h->nb, (int)nx, 1.0, h->Linv, h->nb, KB, (int)nx, TT, (int)nx, s) != hipSuccess)
+            return fail(GPFVM_E_HIP, "posterior: triangular product failed");
+          const int R = colsq_chunks(h->nb, nx);
+          hipLaunchKernelGGL(k_colsq_part, dim3((unsigned)((nx + 63) / 64), (unsigned)R), dim3(256), 0, s, (i64)h->nb,
+                             nx, (const double*)TT, CP);
+          hipLaunchKernelGGL(k_colsq_finish, dim3(nblk(nx)), dim3(256), 0, s, nx, R, (const double*)CP, red + x0);
+        }
+      }
+    }
+    if (K > 0) {
+      Plan pgp, pgb;
+      const bool have_gp = !gp.terms.empty(), have_gb = h->nb > 0 && !gb.empty();
+      if (have_gp) {
+        std::vector<KronOp> ops{gp};
+        rc = compile_kron_list(ops, F64, B, Dbuf, N, P1, M, h->cellc, h->cellc, 0.0, nullptr, 0, 1, tmp, s, pgp, h->err);
+        if (rc) { tmp.release(); return rc; }
+      }
+      if (have_gb) {
+        rc = compile_kron_list(gb, F64, B, Wb, h->nb, P2, M, nullptr, nullptr, 0.0, nullptr, 0, 1, tmp, s, pgb, h->err);
+        if (rc) { tmp.release(); return rc; }
+      }
+      if (!have_gp && launch_fill(P1, 0.0, M * B, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: fill failed");
+      for (int j0 = 0; j0 < K; j0 += B) {
+        const int nr = std::min(B, K - j0);
+        if (hipMemcpyAsync(Dbuf, h->Dd + (i64)j0 * N, (size_t)nr * N * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+            hipSuccess)
+          return fail(GPFVM_E_HIP, "posterior: copy failed");
+        if (nr < B && launch_fill(Dbuf + (i64)nr * N, 0.0, (i64)(B - nr) * N, s) != hipSuccess)
+          return fail(GPFVM_E_HIP, "posterior: fill failed");
+        if (have_gp && run_plan(pgp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
+        if (have_gb) {
+          if (run_plan(pbp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
+          if (run_stages(st, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: gemm failed");
+          if (run_plan(pgb, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
+        }
+        hipLaunchKernelGGL(k_sub_sq_acc, dim3(nblk(M)), dim3(256), 0, s, M, nr, (const double*)P1,
+                           (const double*)(have_gb ? P2 : nullptr), (const double*)(h->eta + j0), red);
+      }
+    }
+    hipLaunchKernelGGL(k_var_final, dim3(nblk(M)), dim3(256), 0, s, M, h->sfo[o], (const double*)red, var_o);
+  }
   if (hipStreamSynchronize(s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: kernel failed");
   tmp.release();
   return GPFVM_OK;
@@ -2157,6 +2227,7 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
 int gpfvm::batch_solve(gpfvm_handle* h, int R, const double* yobs_host, double tol, int max_iter, int check_every,
                        int replace_every, hipStream_t s, std::vector<BatchResult>& out) {
   if (R < 1 || max_iter < 1 || max_iter > h->max_iter) { h->err = "batch: bad size"; return GPFVM_E_INVALID; }
+  if (h->multi) { h->err = "batch: batched solves take single-output problems"; return GPFVM_E_INVALID; }
   h->stream = s;
   const i64 N = h->N, n = h->n, nb = h->nb, cap = h->max_iter;
   gpfvm_sop* so = nullptr;
