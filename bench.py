@@ -55,6 +55,11 @@ def parse():
     ap.add_argument("--c3-steps", type=int, default=2,
                     help="timed steps of the 2-D heat 64^3 block (assemble + 200 IterGP + posterior, float64 and "
                          "mixed; 0 = skip)")
+    ap.add_argument("--sw-steps", type=int, default=1,
+                    help="timed steps of the shallow-water system block (0: skip)")
+    ap.add_argument("--sw-iters", type=int, default=1250,
+                    help="IterGP iterations of the shallow-water block (the paper's CG budget)")
+    ap.add_argument("--sw-only", action="store_true", help="only the shallow-water block (for profiling)")
     ap.add_argument("--mixed-only", action="store_true",
                     help="only the advection-diffusion block with its mixed-precision measurement (profiling)")
     ap.add_argument("--mixed-steps", type=int, default=5,
@@ -131,6 +136,10 @@ def main():
 
     if args.mixed_only:
         print(json.dumps({"advdiff_128x128": c2_block(args, G, W, torch.cuda.current_stream())}), flush=True)
+        return
+    if args.sw_only:
+        print(json.dumps({"shallow_water": sw_block(max(1, args.sw_steps), G, W, torch.cuda.current_stream(),
+                                                    args.sw_iters)}), flush=True)
         return
 
     # ---- headline: wave 64x128x128 + 16384 points, assemble + 200 IterGP + posterior ----
@@ -212,6 +221,9 @@ def main():
     if args.c3_steps > 0:
         out["heat2d_64x64x64"] = c3_block(args.c3_steps, G, W, stream)
         note("heat 64^3 block done")
+    if args.sw_steps > 0:
+        out["shallow_water"] = sw_block(args.sw_steps, G, W, stream, args.sw_iters)
+        note("shallow-water block done")
     if args.extra_rooflines:
         out.update(extra_rooflines())
     if args.serve_requests > 0:
@@ -323,6 +335,54 @@ def c3_block(steps, G, W, stream, iters=200):
     return out
 
 
+def sw_block(steps, G, W, stream, iters=1250):
+    """The linearised shallow-water system at the paper's tsunami scale
+    (20 x 90 x 170 cells, three equations on three outputs: 918 000 volume
+    observations, 18 380 initial and radiation-boundary points): assemble,
+    `iters` IterGP iterations with CG actions (the paper's budget before its
+    targeted post-iterations), posterior mean and combined variance of h, u
+    and v on the 4 x 90 x 170 grid of cell centres.  One untimed step of 50
+    iterations first loads the kernels."""
+    import numpy as np
+    import torch
+    p = W.shallow_water()
+    M = int(np.prod([len(a) for a in p.grid]))
+    mean = torch.empty(p.nout * M, dtype=torch.float64, device="cuda:0")
+    var = torch.empty(p.nout * M, dtype=torch.float64, device="cuda:0")
+    out = {"workload": f"shallow_water_20x90x170_cells_3eq_{p.n_b}_pts_itergp{iters}", "n_pde": int(p.n_pde),
+           "n_b": int(p.n_b), "n_obs": int(p.n), "itergp_iters": iters, "grid": [len(a) for a in p.grid],
+           "outputs": p.nout,
+           "paper_context": "about 15 min for 1250 + 500 targeted iterations on one A100 (the paper's tsunami; "
+                            "GEBCO bathymetry, 936 672 observations)"}
+    phases = []
+    for k in range(steps + 1):
+        n_it = 50 if k == 0 else iters
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = G.assemble(p, max_iter=n_it, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        try:
+            info = G.solve(h, tol=0.0, max_iter=n_it, check_every=50, stream=stream.cuda_stream)
+            t2 = time.perf_counter()
+            G.posterior(h, p.grid, mean, var, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+        finally:
+            G.destroy(h)
+        if k > 0:
+            phases.append((t1 - t0, t2 - t1, t3 - t2))
+        note(f"shallow-water step {k}/{steps}: {n_it} iterations, {t3 - t0:.2f} s")
+    ph = np.median(np.asarray(phases), axis=0)
+    v = var.cpu().numpy().reshape(p.nout, M)
+    out.update({"s_per_step": float(np.sum(ph)), "phase_s": dict(zip(["assemble", "solve", "posterior"],
+                                                                       [float(x) for x in ph])),
+                "ms_per_iteration": 1e3 * float(ph[1]) / iters, "rel_res": info["rel_res"],
+                "iters": info["iters"],
+                "var_range": [[float(v[j].min()), float(v[j].max())] for j in range(p.nout)]})
+    return out
+
+
 def mixed_bench(p, steps, stream, mean64, var64, iters64, mv_reps):
     """The same step on the mixed-precision path: the volume Gram on the
     bfloat16 matrix cores (three bfloat16 slices per float32 operand) in
@@ -382,7 +442,7 @@ def mixed_bench(p, steps, stream, mean64, var64, iters64, mv_reps):
 # it is measured again.
 VOLUME_GEMM_TRAFFIC = {
     # (workload, rhs): (bytes per launch, source hash); profiles/k_gemm_lds_wave64x128x128_volume_gram_1rhs.md
-    ("wave2d_64x128x128", 1): (104.05e6, "42a0907f8199ca65"),
+    ("wave2d_64x128x128", 1): (101.7e6, "21cda3435c7404cf"),
 }
 TRAFFIC_SOURCES = ("kernels.hip", "plan.hip", "dense.hip", "common.h")
 

@@ -1,6 +1,8 @@
 """The full-size 3-D problems: the wave problem (64 x 128 x 128 volumes with
 per-cell c^2, 16384 initial/boundary points) in the configuration bench.py
-times, and the 2-D heat problem (64^3 volumes, 12288 points): assemble,
+times, the 2-D heat problem (64^3 volumes, 12288 points), and the linearised
+shallow-water system at the paper's tsunami scale (20 x 90 x 170 cells, three
+equations on three outputs, 18380 initial and radiation-boundary points): assemble,
 early-terminated IterGP with CG actions (Sec. 4.1), posterior mean and
 combined variance on the evaluation grid (Sec. 2.1, Sec. 4.1-4.2).  Compared
 at 256 sampled grid points with the oracle's values after the same numbers of
@@ -121,3 +123,31 @@ def test_heat3d_fullsize_itergp_posterior_matches_oracle(G):
     assert_close(v[idx], ref["var"], 1e-6, what="var")
     assert abs(info["rel_res"] - ref["rel_res"]) <= HEAT3D_MEAN_TOL * ref["rel_res"], (info["rel_res"], ref["rel_res"])
     assert v.min() >= -1e-9 and v.max() <= 1.0 + 1e-12
+
+
+def test_shallow_water_fullsize_itergp_posterior_matches_oracle(G):
+    """918 000 volume observations, 20 iterations; every output (h, u, v) at
+    128 sampled points of the 4 x 90 x 170 grid."""
+    golden = _golden("shallow_water_itergp.json")
+    ref = golden["stops"]["20"]
+    p = W.shallow_water()
+    assert p.name == golden["workload"] and p.n_b == golden["n_b"] and p.n_pde == golden["n_pde"]
+    idx = np.asarray(golden["idx"])
+    M = int(np.prod([len(a) for a in p.grid]))
+    h = G.assemble(p, max_iter=20)
+    try:
+        print(f"{p.name}, 20 IterGP iterations", flush=True)
+        info = G.solve(h, tol=0.0, max_iter=20, check_every=10)
+        assert info["iters"] == 20, info
+        mean = torch.empty(p.nout * M, dtype=torch.float64, device="cuda:0")
+        var = torch.empty(p.nout * M, dtype=torch.float64, device="cuda:0")
+        G.posterior(h, p.grid, mean, var)
+        torch.cuda.synchronize()
+        m, v = mean.cpu().numpy().reshape(p.nout, M), var.cpu().numpy().reshape(p.nout, M)
+    finally:
+        G.destroy(h)
+    assert abs(info["rel_res"] - ref["rel_res"]) <= 1e-6 * ref["rel_res"], (info["rel_res"], ref["rel_res"])
+    for j, sf in enumerate(p.output_scales()):
+        assert_close(m[j][idx], ref["mean"][j], 1e-6, sf2=sf, what=f"mean of output {j}")
+        assert_close(v[j][idx], ref["var"][j], 1e-6, sf2=sf, what=f"var of output {j}")
+        assert np.all(np.isfinite(m[j])) and np.all(v[j] <= sf * (1 + 1e-12))
