@@ -405,7 +405,8 @@ struct gpfvm_handle {
   double* qf_aq = nullptr;         // n0 x k0: q_r (pinned dim 0) as columns, each nunit times
   double* qf_bq = nullptr;         // k1 x n1: q_r (pinned dim 1) as rows, each nunit times
   bool process_cache = false;      // arena blocks come from the per-process cache
-  float* Linv_f = nullptr;
+  float* Linv_f = nullptr;         // float32 L^{-1} (mixed operator; corrections of the row-streaming solves)
+  float* Linvt_f = nullptr;        // float32 L^{-T} (row-major), corrections of the row-streaming solves
   gpfvm::GramMeta* meta = nullptr;   // device
   std::vector<gpfvm::KronOp> op_pp, op_pp32;   // one operator per equation (output block)
   std::vector<gpfvm::KronOp> op_bp, op_pb, op_bp32, op_pb32;

@@ -214,6 +214,7 @@ static size_t estimate_bytes(const gpfvm_ibvp& p, int max_iter, long long M, int
   b += 2.0 * N * max_iter * d8;                            // directions and S D
   b += (48.0 + 6.0 * EST_TERMS) * N * d8;           // solver vectors, plan intermediates, full-Gram buffers
   b += 4.0 * nb * nb * d8;             // L, L^{-1} (and transposes)
+  b += 1.0 * nb * nb * d8;             // float32 L^{-1} and L^{-T} of the row-streaming solves
   if (qform_ok(N, nb)) b += 3.0 * nb * N * d8;             // point correction Q and its build buffers
   b += 2.0 * nb * 64 * d8 + 4.0 * (nb + 64) * 64 * d8;     // Cholesky workspace
   b += 0.5 * nb * nb * d8;                                 // the triangular inverse's two workspaces

@@ -388,17 +388,92 @@ std::vector<Stage> gpfvm::ginv_stages(const gpfvm_handle* h, int nrhs, const dou
   return st;
 }
 
+// y[i] = add[i] + alpha * sum_k M[i][k] x[k] over k <= i (upper = 0) or k >= i (upper = 1) for a
+// float32 matrix: one wavefront per row, four matrix values per 16-byte load, products and sums in
+// float64.  Needs n % 4 == 0 and 16-byte aligned M and x; the up to three values before the first
+// aligned quad and after the last are taken one by one.
+__global__ __launch_bounds__(256) void k_trmv_rows_f32(int n, const float* __restrict__ M, const double* __restrict__ x,
+                                                       double* __restrict__ y, double alpha,
+                                                       const double* __restrict__ add, int upper) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int lo = upper ? i : 0, hi = upper ? n : i + 1;
+  const float* __restrict__ row = M + (i64)i * n;
+  const float4* __restrict__ row4 = reinterpret_cast<const float4*>(row);
+  const double2* __restrict__ x2 = reinterpret_cast<const double2*>(x);
+  const int qa = (lo + 3) / 4, qb = hi / 4;     // quads [4 qa, 4 qb) of [lo, hi)
+  double acc0 = 0.0, acc1 = 0.0;
+  int q = qa + lane;
+  for (; q + 64 < qb; q += 128) {
+    const float4 m0 = row4[q], m1 = row4[q + 64];
+    const double2 a0 = x2[2 * q], b0 = x2[2 * q + 1], a1 = x2[2 * (q + 64)], b1 = x2[2 * (q + 64) + 1];
+    acc0 += ((double)m0.x * a0.x + (double)m0.y * a0.y) + ((double)m0.z * b0.x + (double)m0.w * b0.y);
+    acc1 += ((double)m1.x * a1.x + (double)m1.y * a1.y) + ((double)m1.z * b1.x + (double)m1.w * b1.y);
+  }
+  for (; q < qb; q += 64) {
+    const float4 m0 = row4[q];
+    const double2 a0 = x2[2 * q], b0 = x2[2 * q + 1];
+    acc0 += ((double)m0.x * a0.x + (double)m0.y * a0.y) + ((double)m0.z * b0.x + (double)m0.w * b0.y);
+  }
+  double a = acc0 + acc1;
+  if (qa > qb) {                                 // no aligned quad: at most six values
+    const int e = lo + lane;
+    if (e < hi) a += (double)row[e] * x[e];
+  } else if (lane < 4 * qa - lo) {               // before the first quad (at most three)
+    const int e = lo + lane;
+    a += (double)row[e] * x[e];
+  } else if (lane >= 3 && lane - 3 < hi - 4 * qb) {   // after the last quad (at most three)
+    const int e = 4 * qb + lane - 3;
+    a += (double)row[e] * x[e];
+  }
+  a = wave_sum(a);
+  if (lane == 0) y[i] = (add ? add[i] : 0.0) + alpha * a;
+}
+
+// Float32 copies of L^{-1} and L^{-T} for the correction products of the row-streaming solves
+// (built once per handle; on allocation failure the corrections stay float64).
+static void ensure_inv_f32(gpfvm_handle* h, hipStream_t s) {
+  const i64 nn = (i64)h->nb * h->nb;
+  if (!h->Linv_f) {
+    float* p = (float*)h->arena.alloc((size_t)nn * sizeof(float));
+    if (!p || launch_copy_f64_to_f32(h->Linv, p, nn, s) != hipSuccess) return;
+    h->Linv_f = p;
+  }
+  if (!h->Linvt_f && h->Linvt) {
+    float* p = (float*)h->arena.alloc((size_t)nn * sizeof(float));
+    if (!p || launch_copy_f64_to_f32(h->Linvt, p, nn, s) != hipSuccess) return;
+    h->Linvt_f = p;
+  }
+}
+
+static hipError_t trmv_rows_f32(int n, const float* M, const double* x, double* y, double alpha, const double* add,
+                                int upper, hipStream_t s) {
+  hipLaunchKernelGGL(k_trmv_rows_f32, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, M, x, y, alpha, add, upper);
+  return hipGetLastError();
+}
+
 // Same six products for one right-hand side as row-streaming triangular
-// matrix-vector products (large point blocks).
+// matrix-vector products (large point blocks).  The two correction products
+// L^{-1} r and L^{-T} r read float32 copies of the inverse when the handle has
+// them: r is the residual of the first product, so the float32 rounding of
+// the matrix (2^-24 relative) perturbs t and w by far less than float64
+// rounding of the main products does, while the correction streams half the
+// bytes.  The main products and the residuals stay float64.
 hipError_t gpfvm::ginv_rows(const gpfvm_handle* h, const double* U, double* T, double* W, double* R, hipStream_t s) {
   const int nb = h->nb;
+  const bool f32 = h->Linv_f && h->Linvt_f && nb % 4 == 0 && (uintptr_t)R % 16 == 0 && (uintptr_t)h->Linv_f % 16 == 0 &&
+                   (uintptr_t)h->Linvt_f % 16 == 0;
   hipError_t e;
   if ((e = launch_trmv_rows(nb, h->Linv, U, T, 1.0, nullptr, 0, s)) != hipSuccess) return e;   // t = Li u
   if ((e = launch_trmv_rows(nb, h->L, T, R, -1.0, U, 0, s)) != hipSuccess) return e;           // r = u - L t
-  if ((e = launch_trmv_rows(nb, h->Linv, R, T, 1.0, T, 0, s)) != hipSuccess) return e;         // t += Li r
+  e = f32 ? trmv_rows_f32(nb, h->Linv_f, R, T, 1.0, T, 0, s)                                   // t += Li r
+          : launch_trmv_rows(nb, h->Linv, R, T, 1.0, T, 0, s);
+  if (e != hipSuccess) return e;
   if ((e = launch_trmv_rows(nb, h->Linvt, T, W, 1.0, nullptr, 1, s)) != hipSuccess) return e;  // w = Li^T t
   if ((e = launch_trmv_rows(nb, h->Lt, W, R, -1.0, T, 1, s)) != hipSuccess) return e;          // r = t - L^T w
-  return launch_trmv_rows(nb, h->Linvt, R, W, 1.0, W, 1, s);                                   // w += Li^T r
+  return f32 ? trmv_rows_f32(nb, h->Linvt_f, R, W, 1.0, W, 1, s)                               // w += Li^T r
+             : launch_trmv_rows(nb, h->Linvt, R, W, 1.0, W, 1, s);
 }
 
 hipError_t gpfvm::run_stages(const std::vector<Stage>& st, hipStream_t s) {
@@ -721,6 +796,8 @@ int gpfvm::get_sop(gpfvm_handle* h, int nrhs, Elt elt, gpfvm_sop** out) {
       }
     }
   }
+  // the one-rhs row-streaming point solve reads float32 copies of the inverse for its corrections
+  if (elt == F64 && nrhs == 1 && h->nb > 0 && !so->ginv_small && !so->qform && !so->qf) ensure_inv_f32(h, h->stream);
   if (elt == F64) {
     std::vector<const Plan*> parts{&so->pp};
     if (h->nb > 0) parts.push_back(&so->bp);
