@@ -200,10 +200,19 @@ class _Marshal:
         s.alpha = al.ctypes.data_as(C.POINTER(C.c_int))
         s.coef = cf.ctypes.data_as(_dp)
         s.cellwise = cw.ctypes.data_as(C.POINTER(C.c_int))
+        # the library reads cells values of cell_coef and neq x cells of f_int: check the lengths here
+        cells = int(np.prod([s.ncell[i] for i in range(d)]))
+        neq_ = max(1, int(getattr(p, "neq", 1)))
         if getattr(p, "cell_coef", None) is not None:
-            s.cell_coef = self._keep(_arr(p.cell_coef).ravel()).ctypes.data_as(_dp)
+            cc = self._keep(_arr(p.cell_coef).ravel())
+            if cc.size != cells:
+                raise ValueError(f"cell_coef holds {cc.size} values, the cells are {cells}")
+            s.cell_coef = cc.ctypes.data_as(_dp)
         if getattr(p, "f_int", None) is not None:
-            s.f_int = self._keep(_arr(p.f_int).ravel()).ctypes.data_as(_dp)
+            fi = self._keep(_arr(p.f_int).ravel())
+            if fi.size != neq_ * cells:
+                raise ValueError(f"f_int holds {fi.size} values, the volume observations are {neq_ * cells}")
+            s.f_int = fi.ctypes.data_as(_dp)
         s.noise_pde = float(p.noise_pde)
         s.noise_pde_relative = 1 if p.noise_pde_relative else 0
         nout, neq = int(getattr(p, "nout", 1)), int(getattr(p, "neq", 1))

@@ -1,6 +1,7 @@
 """CPU tests of the C-ABI boundary: the library loads, exports every entry
 point that include/gpfvm.h declares, and rejects malformed IBVPs before any
 HIP call (argument validation runs on the host)."""
+import dataclasses
 import os
 import re
 
@@ -113,3 +114,50 @@ def test_matern_orders_are_validated_on_the_host(G):
         with pytest.raises(G.GpfvmError) as e:
             G.validate(dataclasses.replace(p, kernel=bad))
         assert e.value.code == G.E_INVALID
+
+
+def _small_system():
+    return W.shallow_water(nt=2, nx=3, ny=4, n_icx=2, n_icy=3, n_bt=2, n_bx=2, n_by=2, grid_t=2)
+
+
+def test_systems_pass_validation(G):
+    G.validate(_small_system())
+    G.validate(W.shallow_water())
+
+
+def _set_term(p, k, **kw):
+    p.terms[k] = dataclasses.replace(p.terms[k], **kw)
+
+
+@pytest.mark.parametrize("mutate, msg", [
+    (lambda p: _set_term(p, 0, out=3), "term_out"),
+    (lambda p: _set_term(p, 0, eq=5), "term_eq"),
+    (lambda p: setattr(p, "out_scale", (1.0, -2.0, 2.0)), "out_scale"),
+    (lambda p: setattr(p, "terms", [t for t in p.terms if t.eq != 2]), "equation 2 has no term"),
+    (lambda p: setattr(p.groups[0], "out", 3), "output out of range"),
+    (lambda p: setattr(p, "terms", [t for t in p.terms if t.out != 2] + [W.PDETerm((1, 0, 0), 1.0, False, 0, 2)]),
+     "appears in no equation"),
+    (lambda p: p.groups[3].terms.append(W.PointTerm((0, 0, 0), 1.0, 0)), "nterm out of range"),
+    (lambda p: setattr(p.groups[3].terms[1], "weights", [None, None, np.array([np.nan, 1.0])]), "weight not finite"),
+    (lambda p: setattr(p.groups[3].terms[1], "deriv", (0, 3, 0)), "derivative order"),
+])
+def test_invalid_systems_rejected_on_host(G, mutate, msg):
+    p = _small_system()
+    mutate(p)
+    with pytest.raises(G.GpfvmError) as e:
+        G.validate(p)
+    assert e.value.code == G.E_INVALID
+    assert msg in str(e.value), str(e.value)
+
+
+def test_binding_checks_array_lengths(G):
+    """The library reads neq x cells values of f_int and one value per cell of
+    cell_coef through plain pointers; the binding refuses arrays of another length."""
+    p = _small_system()
+    p.f_int = np.zeros(p.n_cells)               # one equation's worth for three equations
+    with pytest.raises(ValueError):
+        G.validate(p)
+    p = _small_system()
+    p.cell_coef = np.ones(p.n_cells + 1)
+    with pytest.raises(ValueError):
+        G.validate(p)
