@@ -48,7 +48,33 @@ def _sw_se():
                            lengthscale=(0.3, 0.2, 0.25), f_cor=0.7, drag=0.3, out_scale=(1.0, 1.7, 0.6))
 
 
+def _sw1d(nt=6, nx=10):
+    """1-D linearised shallow water in (t, x): h_t + H u_x = 0, u_t + g h_x + k u = 0
+    with per-cell depth H (the 2-D pre-summed plan path with scaling at block
+    offsets) and radiation rows h_t -/+ c h_x = 0 at x = 0 and 1 whose wave
+    speed enters as a weight along t."""
+    xc = W.centres(nx)
+    H = 0.3 + 0.7 * np.exp(-((xc - 0.3) / 0.2) ** 2)
+    cellH = np.broadcast_to(H[None, :], (nt, nx)).ravel().copy()
+    xi, tb = W.centres(8), W.centres(5)
+    h0 = np.exp(-0.5 * ((xi - 0.5) / 0.1) ** 2)
+    groups = [W.PointGroup([np.array([0.0]), xi], (0, 0), h0, 1e-8, out=0),
+              W.PointGroup([np.array([0.0]), xi.copy()], (0, 0), np.zeros(8), 1e-8, out=1)]
+    for edge, sign, c in ((0.0, -1.0, np.sqrt(H[0])), (1.0, 1.0, np.sqrt(H[-1]))):
+        groups.append(W.PointGroup([tb.copy(), np.array([edge])], (1, 0), np.zeros(5), 1e-8,
+                                   terms=[W.PointTerm((1, 0), 1.0, 0),
+                                          W.PointTerm((0, 1), sign, 0, [np.full(5, c), None])]))
+    terms = [W.PDETerm((1, 0), 1.0, False, 0, 0), W.PDETerm((0, 1), 1.0, True, 1, 0),
+             W.PDETerm((1, 0), 1.0, False, 1, 1), W.PDETerm((0, 1), 1.0, False, 0, 1),
+             W.PDETerm((0, 0), 0.1, False, 1, 1)]
+    return W.IBVP(name="sw1d", d=2, edges=[W.uniform_edges(0, 1, nt), W.uniform_edges(0, 1, nx)],
+                  lengthscale=(0.3, 0.15), outputscale=1.0, terms=terms, groups=groups, cell_coef=cellH,
+                  noise_pde=1e-6, grid=[W.centres(3), W.centres(12)], kernel=(3, 3), nout=2, neq=2,
+                  out_scale=(1.0, 1.5))
+
+
 SYSTEMS = {
+    "sw1d_cellwise_2d": _sw1d,
     "sw_matern52": _sw_tiny,
     "sw_se": _sw_se,
     "decoupled_pair_2d": lambda: _pair_system()[2],
@@ -154,3 +180,43 @@ def test_system_is_refused_where_single_output_only(G):
         assert e.value.code == G.E_INVALID
     finally:
         G.destroy(h)
+
+
+def test_system_volume_matvecs_and_plain_cg(G):
+    """The volume-only matvec and its allocation-free variant against the
+    oracle's volume block; plain CG (mean only) against the dense posterior of
+    every output, at PDE noise 1e-2 of the mean diagonal where CG converges
+    without reorthogonalisation."""
+    p = _sw_tiny()
+    p.noise_pde = 1e-2
+    o = O.Oracle(p)
+    Gv = o.volume_gram() + o.noise_pde() * np.eye(p.n_pde)
+    x = np.random.default_rng(5).standard_normal(p.n_pde)
+    ref = Gv @ x
+    h = G.assemble(p, max_iter=8)
+    try:
+        for fn in (G.volume_matvec, G.volume_matvec_noalloc):
+            y = torch.empty(p.n_pde, dtype=torch.float64, device="cuda:0")
+            fn(h, dev(x), y)
+            assert np.linalg.norm(host(y) - ref) <= 1e-11 * np.linalg.norm(ref), fn.__name__
+        info = G.solve(h, tol=1e-10, max_iter=2000, method=G.METHOD_CG)
+        assert info["rc"] == G.OK, info
+        M = int(np.prod([len(a) for a in p.grid]))
+        mean = torch.empty(p.nout * M, dtype=torch.float64, device="cuda:0")
+        G.posterior(h, p.grid, mean)
+        m = host(mean).reshape(p.nout, M)
+    finally:
+        G.destroy(h)
+    X = o.grid_points(p.grid)
+    for j, sf in enumerate(p.output_scales()):
+        mr, _, _ = O.dense_posterior(o, X, out=j)
+        assert_close(m[j], mr, 1e-6, sf2=sf, what=f"CG mean of output {j}", converged=True)
+
+
+def test_system_without_point_observations(G):
+    """No initial or boundary points: the volume system is the whole Gram (with
+    a seeded source term, as zero data would give no directions at all)."""
+    p = _sw_tiny()
+    p.groups = []
+    p.f_int = np.random.default_rng(9).standard_normal(p.n_pde) * 1e-3
+    _compare(G, p, 12)
