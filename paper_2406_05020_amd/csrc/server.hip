@@ -219,8 +219,9 @@ static size_t estimate_bytes(const gpfvm_ibvp& p, int max_iter, long long M, int
   b += 2.0 * nb * 64 * d8 + 4.0 * (nb + 64) * 64 * d8;     // Cholesky workspace
   b += 0.5 * nb * nb * d8;                                 // the triangular inverse's two workspaces
   const double chunk = (double)posterior_chunk(nb, M);
-  b += (3.0 * nb + 64.0) * chunk * d8;                     // posterior point-block chunks (or the grouped form's
-                                                           // factors and solved columns) and column partials
+  b += (4.0 * nb + 64.0) * chunk * d8;                     // posterior point-block chunks (or the grouped form's
+                                                           // factors, mode-product intermediates and solved
+                                                           // columns) and column partials
   {                                                        // posterior direction batches
     const double widest = std::max(std::max((double)M, (double)N), std::max(1.0, (double)nb));
     const double B = (double)posterior_dir_batch(max_iter, (i64)widest);

@@ -1957,7 +1957,7 @@ static int grouped_point_var(gpfvm_handle* h, const PGMeta& pg, const int* n, i6
                              hipStream_t s) {
   const int d = h->d;
   const i64 nb = h->nb;
-  struct Grp { int g, c; double coef; i64 off, np, K, C; int isfree[3]; i64 cs[3]; double* Bt; double* U; };
+  struct Grp { int g, c; double coef; i64 off, np, K, C; int isfree[3]; i64 cs[3]; int nfree; double* Bt; double* U; };
   std::vector<Grp> gr;
   for (int g = 0; g < (int)h->groups.size(); ++g)
     for (int c = 0; c < pg.gcomp[g]; ++c)
@@ -1980,15 +1980,57 @@ static int grouped_point_var(gpfvm_handle* h, const PGMeta& pg, const int* n, i6
       if (q.isfree[i]) q.C *= n[i];
     }
     q.K = nb - q.off;
-    work += (double)q.K * q.np * q.C;
-    words += (double)q.C * q.K + (double)q.C * q.np;
+    q.nfree = 0;
+    int fd[3] = {0, 0, 0};
+    for (int i = 0; i < d; ++i)
+      if (q.isfree[i]) fd[q.nfree++] = i;
+    if (q.nfree == 2) {
+      // U = X_sub B_g^T as two mode products (B_g^T is the Kronecker product of the free
+      // dimensions' point factors): the cheaper order's flops and its intermediate
+      const double pa = H.n[fd[0]], pb = H.n[fd[1]], ga = n[fd[0]], gb = n[fd[1]];
+      const double w1 = pa * pb * gb + pa * gb * ga, w2 = pa * pb * ga + ga * pb * gb;
+      work += (double)q.K * std::min(w1, w2);
+      words += (double)q.C * q.K + (double)q.K * std::max(pa * gb, ga * pb);
+    } else {
+      work += (double)q.K * q.np * q.C;
+      words += (double)q.C * q.K + (double)q.C * q.np;
+    }
   }
   if (work > 0.25 * (double)nb * nb * M) return 1;
-  if (words > 3.0 * nb * posterior_chunk(nb, M)) return 1;     // within the posterior's memory estimate
+  if (words > 4.0 * nb * posterior_chunk(nb, M)) return 1;     // within the posterior's memory estimate
   for (Grp& q : gr) {
-    q.Bt = (double*)tmp.alloc((size_t)(q.C * q.np) * sizeof(double));
     q.U = (double*)tmp.alloc((size_t)(q.C * q.K) * sizeof(double));
-    if (!q.Bt || !q.U) { h->err = "posterior: out of device memory"; return GPFVM_E_NOMEM; }
+    if (!q.U) { h->err = "posterior: out of device memory"; return GPFVM_E_NOMEM; }
+    if (q.nfree == 2) {
+      // U (K x C) = X_sub (K x np) B_g^T by the Kronecker plan: the K rows of
+      // X_sub = L^{-1}[off:, off:off+np] are its right-hand sides (stride n_b), each a
+      // tensor over the group's two free dimensions mapped to the grid's
+      KronOp op;
+      op.d = 2;
+      KronTerm t{};
+      int k = 0;
+      for (int i = 0; i < d; ++i) {
+        if (!q.isfree[i]) continue;
+        op.in_shape[k] = h->groups[q.g].n[i];
+        op.out_shape[k] = n[i];
+        t.M[k] = pg.P[q.g][q.c][i];       // n_{g,i} x grid_i, used transposed
+        t.ld[k] = n[i];
+        t.trans[k] = 1;
+        ++k;
+      }
+      op.in_len = q.np;
+      t.alpha = q.coef;
+      op.terms.push_back(t);
+      std::vector<KronOp> ops{op};
+      Plan pl;
+      int rc = compile_kron_list(ops, F64, (int)q.K, h->Linv + q.off * nb + q.off, nb, q.U, q.C, nullptr, nullptr, 0.0,
+                                 nullptr, 0, 1, tmp, s, pl, h->err);
+      if (rc) return rc;
+      if (run_plan(pl, s) != hipSuccess) { h->err = "posterior: group product failed"; return GPFVM_E_HIP; }
+      continue;
+    }
+    q.Bt = (double*)tmp.alloc((size_t)(q.C * q.np) * sizeof(double));
+    if (!q.Bt) { h->err = "posterior: out of device memory"; return GPFVM_E_NOMEM; }
     GVFactor F{};
     F.d = d;
     for (int i = 0; i < 3; ++i) { F.pn[i] = 1; F.ext[i] = 1; F.isfree[i] = 0; F.P[i] = nullptr; }
