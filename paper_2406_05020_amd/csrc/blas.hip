@@ -71,6 +71,19 @@ hipError_t trmm_rows_right_lower(int m, int k, double alpha, const double* T, in
   return r == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
 }
 
+// Y[r] = A X[r] (trans = 0) or A^T X[r] (trans = 1) for nrhs vectors of length n stored one after
+// another (X[r] at X + r n), A row-major n x n lower-triangular.  Column-major, the vectors are the
+// columns of an n x nrhs matrix and A's storage is the upper-triangular A^T.
+hipError_t trmm_vecs_lower(int n, int nrhs, int trans, const double* A, const double* X, double* Y, hipStream_t s) {
+  rocblas_handle hd = handle_for(s);
+  if (!hd) return hipErrorNotInitialized;
+  const double one = 1.0;
+  const rocblas_status st = rocblas_dtrmm(hd, rocblas_side_left, rocblas_fill_upper,
+                                          trans ? rocblas_operation_none : rocblas_operation_transpose,
+                                          rocblas_diagonal_non_unit, n, nrhs, &one, A, n, X, n, Y, n);
+  return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+}
+
 // C = A B^T for row-major A (m x k, leading dimension lda), B (n x k, ldb) and
 // C (m x n, ldc).  In the column-major views (A^T, B^T, C^T) this is
 // C^T = (B^T)^T A^T: a GEMM with the first operand transposed.

@@ -114,6 +114,11 @@ struct Stage {
   int kind = 0;    // GEMM_SPLITK / GEMM_LDS16 / GEMM_LDS32 / GEMM_LDS64 (set when the stage is uploaded)
   int slot1 = 0;   // some segment accumulates into slot 1
   Rider rider;     // launched with the stage (kind RIDE_NONE: none)
+  // thin products (one output row or column, one segment, no epilogue): moved to the end
+  // of descs at upload and run by a one-thread-per-output kernel; tile_begin holds their
+  // output offsets
+  int nthin = 0;
+  i64 thin_outputs = 0;
 };
 enum GemmKind { GEMM_SPLITK = 0, GEMM_LDS32 = 1, GEMM_LDS64 = 2, GEMM_LDS16 = 3, GEMM_BF16S32 = 4, GEMM_BF16S64 = 5 };
 

@@ -270,6 +270,21 @@ hipError_t upload_stages(std::vector<Stage>& stages, Arena& arena, hipStream_t s
   std::vector<GemmDesc> host;
   host.reserve(total);
   for (auto& st : stages) {
+    // a mode product that contracts to a single output row or column uses 1/64 of a 64x64
+    // MFMA tile: such descriptors go to the end and run on the thin kernel
+    st.nthin = 0;
+    st.thin_outputs = 0;
+    if (elt != F32B) {
+      auto thin = [](const GemmDesc& D) {
+        return (D.M == 1 || D.N == 1) && D.nseg == 1 && !D.escale && !D.X && D.beta == 0.0 && D.seg[0].tri == 0 &&
+               D.seg[0].slot == 0 && D.seg[0].K <= 4096;
+      };
+      std::stable_partition(st.descs.begin(), st.descs.end(), [&](const GemmDesc& D) { return !thin(D); });
+      for (auto& D : st.descs)
+        if (thin(D)) ++st.nthin;
+    }
+    std::vector<GemmDesc> thin_descs(st.descs.end() - st.nthin, st.descs.end());
+    st.descs.resize(st.descs.size() - st.nthin);
     choose_kernel(st);
     if (elt == F32B) {               // split-bfloat16 GEMM: 64x64 tiles where there are enough, else 32x32
       i64 t64 = 0;
@@ -283,6 +298,11 @@ hipError_t upload_stages(std::vector<Stage>& stages, Arena& arena, hipStream_t s
       D.tiles_n = (D.N + t - 1) / t;
       D.tile_begin = st.tiles;
       st.tiles += (i64)D.tiles_m * D.tiles_n * D.batch;
+    }
+    for (auto& D : thin_descs) {
+      D.tile_begin = st.thin_outputs;
+      st.thin_outputs += (i64)D.M * D.N * D.batch;
+      st.descs.push_back(D);
     }
     st.d_descs = dev + host.size();
     host.insert(host.end(), st.descs.begin(), st.descs.end());

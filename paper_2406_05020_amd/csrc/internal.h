@@ -101,6 +101,7 @@ hipError_t trmm_rows_right_lower(int m, int k, double alpha, const double* T, in
                                  double* C, int ldc, hipStream_t s, int batch = 1, i64 st = 0, i64 sb = 0,
                                  i64 sc = 0);
 // C = A B^T, all row-major: A m x k, B n x k, C m x n
+hipError_t trmm_vecs_lower(int n, int nrhs, int trans, const double* A, const double* X, double* Y, hipStream_t s);
 hipError_t gemm_rows_abt(int m, int n, int k, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
                          hipStream_t s);
 // C -= A A^T on the lower triangle (C row-major n x n, A row-major n x k)

@@ -1009,8 +1009,44 @@ static void launch_lds(const Stage& st, int nd, hipStream_t s) {
     k_gemm_lds<T, BM, BM, KS, false, false><<<grid, block, 0, s>>>(st.d_descs, nd, st.tiles, st.rider);
 }
 
-hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
-  if (st.rider.kind != RIDE_NONE && (elt != F64 || st.kind == GEMM_SPLITK || st.tiles == 0 || st.descs.empty())) {
+// Thin products: C[b][m][n] = alpha sum_k A[b][m][k] B[b][k][n] for descriptors with M = 1 or
+// N = 1 (one segment, no epilogue), one thread per output element in (batch, m, n) order with n
+// fastest; the descriptors' tile_begin are their output offsets (ascending).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_thin(const GemmDesc* __restrict__ descs, int nd, i64 total) {
+  const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  int lo = 0, hi = nd - 1;                     // last descriptor with tile_begin <= idx
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= idx) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc& D = descs[lo];
+  i64 r = idx - D.tile_begin;
+  const i64 n = r % D.N;
+  r /= D.N;
+  const i64 m = r % D.M;
+  const i64 b = r / D.M;
+  const Seg& S = D.seg[0];
+  const T* __restrict__ A = (const T*)S.A + b * S.a_bs + m * S.a_rs;
+  const T* __restrict__ B = (const T*)S.B + b * S.b_bs + n * S.b_cs;
+  double acc = 0.0;
+  for (int k = 0; k < S.K; ++k) acc = fma((double)A[(i64)k * S.a_cs], (double)B[(i64)k * S.b_rs], acc);
+  ((T*)D.C)[b * D.c_bs + m * D.c_rs + n * D.c_cs] = (T)(S.alpha * acc);
+}
+
+static hipError_t launch_thin(Elt elt, const Stage& st, hipStream_t s) {
+  if (st.nthin == 0 || st.thin_outputs == 0) return hipSuccess;
+  const GemmDesc* d = st.d_descs + (st.descs.size() - st.nthin);
+  const unsigned g = (unsigned)((st.thin_outputs + 255) / 256);
+  if (elt == F64) k_gemm_thin<double><<<g, 256, 0, s>>>(d, st.nthin, st.thin_outputs);
+  else k_gemm_thin<float><<<g, 256, 0, s>>>(d, st.nthin, st.thin_outputs);
+  return hipGetLastError();
+}
+
+// The tiled products of a stage: its first nd descriptors (the thin ones follow them).
+static hipError_t launch_tiled(Elt elt, const Stage& st, int nd, hipStream_t s) {
+  if (st.rider.kind != RIDE_NONE && (elt != F64 || st.kind == GEMM_SPLITK || st.tiles == 0 || nd == 0)) {
     // the riding product runs on its own where the stage's kernel cannot carry it
     hipError_t e;
     if (st.rider.kind == RIDE_ROWS) {
@@ -1024,14 +1060,16 @@ hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
       e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
-    Stage plain = st;
-    plain.rider = Rider();
-    return launch_gemm_stage(elt, plain, s);
+    if (st.tiles == 0 || nd == 0) return hipSuccess;
+    Stage plain;
+    plain.d_descs = st.d_descs;
+    plain.tiles = st.tiles;
+    plain.kind = st.kind;
+    plain.slot1 = st.slot1;
+    return launch_tiled(elt, plain, nd, s);
   }
-  if (st.tiles == 0 || st.descs.empty()) return hipSuccess;
+  if (st.tiles == 0 || nd == 0) return hipSuccess;
   if (elt == F32B) return launch_gemm_bf16s(st, s);
-  const int nd = (int)st.descs.size();
   if (st.kind == GEMM_LDS64) {
     if (elt == F64) launch_lds<double, 64, 1>(st, nd, s); else launch_lds<float, 64, 1>(st, nd, s);
   } else if (st.kind == GEMM_LDS32) {
@@ -1044,6 +1082,13 @@ hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
     k_gemm_sk<float><<<dim3((unsigned)st.tiles), dim3(64 * SK_WAVES), 0, s>>>(st.d_descs, nd);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_gemm_stage(Elt elt, const Stage& st, hipStream_t s) {
+  // the thin products, then the stage's tiled products (disjoint outputs)
+  hipError_t e = launch_thin(elt, st, s);
+  if (e != hipSuccess) return e;
+  return launch_tiled(elt, st, (int)st.descs.size() - st.nthin, s);
 }
 
 // ============================================================================

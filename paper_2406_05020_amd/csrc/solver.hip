@@ -1840,7 +1840,7 @@ extern "C" int gpfvm_weights(gpfvm_handle* h, double* alpha, void* stream) {
     HIPCHK(h, hipMemcpyAsync(so->X, h->v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(h, run_plan(so->bp, s));
     HIPCHK(h, launch_axpby(h->nb, 1.0, h->yobs, -1.0, (double*)so->U, s));
-    HIPCHK(h, run_stages(so->ginv, s));
+    HIPCHK(h, apply_ginv(h, so, s));     // the one-vector form (one workgroup or row-streaming)
     HIPCHK(h, hipMemcpyAsync(alpha, so->W, h->nb * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   return GPFVM_OK;
@@ -2085,6 +2085,26 @@ static int grouped_point_var(gpfvm_handle* h, const PGMeta& pg, const int* n, i6
   return GPFVM_OK;
 }
 
+// W = G_bb^{-1} U for nrhs vectors (stored one after another) by library TRMMs: t = L^{-1} u,
+// r = u - L t, t += L^{-1} r, then w = L^{-T} t, r = t - L^T w, w += L^{-T} r (the triangular
+// solves with one residual correction each, as in the one-vector form).  U is overwritten.
+static hipError_t ginv_trmm(const gpfvm_handle* h, int nrhs, double* U, double* T, double* W, double* R,
+                            hipStream_t s) {
+  const int nb = h->nb;
+  const i64 len = (i64)nb * nrhs;
+  hipError_t e;
+  if ((e = trmm_vecs_lower(nb, nrhs, 0, h->Linv, U, T, s)) != hipSuccess) return e;     // t = Li u
+  if ((e = trmm_vecs_lower(nb, nrhs, 0, h->L, T, R, s)) != hipSuccess) return e;        // r = L t
+  if ((e = launch_axpby(len, 1.0, U, -1.0, R, s)) != hipSuccess) return e;             // r = u - r
+  if ((e = trmm_vecs_lower(nb, nrhs, 0, h->Linv, R, W, s)) != hipSuccess) return e;     // (Li r)
+  if ((e = launch_axpby(len, 1.0, W, 1.0, T, s)) != hipSuccess) return e;              // t += Li r
+  if ((e = trmm_vecs_lower(nb, nrhs, 1, h->Linv, T, W, s)) != hipSuccess) return e;     // w = Li^T t
+  if ((e = trmm_vecs_lower(nb, nrhs, 1, h->L, W, R, s)) != hipSuccess) return e;        // r = L^T w
+  if ((e = launch_axpby(len, 1.0, T, -1.0, R, s)) != hipSuccess) return e;             // r = t - r
+  if ((e = trmm_vecs_lower(nb, nrhs, 1, h->Linv, R, U, s)) != hipSuccess) return e;     // (Li^T r)
+  return launch_axpby(len, 1.0, U, 1.0, W, s);                                          // w += Li^T r
+}
+
 extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const double* const* axis, double* mean,
                                double* var, void* stream) {
   if (!h) return GPFVM_E_INVALID;
@@ -2181,7 +2201,6 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
   double *red = nullptr, *P1 = nullptr, *P2 = nullptr, *Ub = nullptr, *Tb = nullptr, *Wb = nullptr, *Rb = nullptr,
          *Dbuf = nullptr;
   Plan pbp;
-  std::vector<Stage> st;
   if (var) {
     red = (double*)tmp.alloc((size_t)M * sizeof(double));
     if (!red) return fail(GPFVM_E_NOMEM, "posterior: out of device memory");
@@ -2200,10 +2219,10 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
       rc = compile_kron_list(h->op_bp, F64, B, Dbuf, N, Ub, h->nb, h->cellc, h->cellc, 0.0, nullptr, 0, 0, tmp, s, pbp,
                              h->err);
       if (rc) { tmp.release(); return rc; }
-      st = ginv_stages(h, B, Ub, Tb, Wb, Rb);
-      if (upload_stages(st, tmp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: upload failed");
     }
   }
+  // with all directions in one batch, G_bb^{-1} G_bp D is shared by every output
+  bool wb_ready = false;
   std::vector<std::unique_ptr<PGMeta>> pg_keep;
   for (int o = 0; o < h->nout; ++o) {
     double* mean_o = mean + (i64)o * M;
@@ -2306,17 +2325,24 @@ extern "C" int gpfvm_posterior(gpfvm_handle* h, int dim, const int* n, const dou
         if (rc) { tmp.release(); return rc; }
       }
       if (!have_gp && launch_fill(P1, 0.0, M * B, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: fill failed");
+      const bool one_batch = K <= B;
       for (int j0 = 0; j0 < K; j0 += B) {
         const int nr = std::min(B, K - j0);
-        if (hipMemcpyAsync(Dbuf, h->Dd + (i64)j0 * N, (size_t)nr * N * sizeof(double), hipMemcpyDeviceToDevice, s) !=
-            hipSuccess)
-          return fail(GPFVM_E_HIP, "posterior: copy failed");
-        if (nr < B && launch_fill(Dbuf + (i64)nr * N, 0.0, (i64)(B - nr) * N, s) != hipSuccess)
-          return fail(GPFVM_E_HIP, "posterior: fill failed");
+        if (!(one_batch && wb_ready)) {
+          if (hipMemcpyAsync(Dbuf, h->Dd + (i64)j0 * N, (size_t)nr * N * sizeof(double), hipMemcpyDeviceToDevice,
+                             s) != hipSuccess)
+            return fail(GPFVM_E_HIP, "posterior: copy failed");
+          if (nr < B && launch_fill(Dbuf + (i64)nr * N, 0.0, (i64)(B - nr) * N, s) != hipSuccess)
+            return fail(GPFVM_E_HIP, "posterior: fill failed");
+        }
         if (have_gp && run_plan(pgp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
         if (have_gb) {
-          if (run_plan(pbp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
-          if (run_stages(st, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: gemm failed");
+          if (!(one_batch && wb_ready)) {
+            if (run_plan(pbp, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
+            if (ginv_trmm(h, B, Ub, Tb, Wb, Rb, s) != hipSuccess)
+              return fail(GPFVM_E_HIP, "posterior: triangular products failed");
+            wb_ready = one_batch;
+          }
           if (run_plan(pgb, s) != hipSuccess) return fail(GPFVM_E_HIP, "posterior: plan failed");
         }
         hipLaunchKernelGGL(k_sub_sq_acc, dim3(nblk(M)), dim3(256), 0, s, M, nr, (const double*)P1,
