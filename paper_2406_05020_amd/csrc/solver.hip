@@ -54,6 +54,42 @@ namespace {
 // of directions to flag[2]; once r.r exceeds DIVERGE2 times it, flag[0] = 4 and
 // the host rolls the state back to that iterate.
 constexpr double DIVERGE2 = 1e6;                 // a 1000-fold growth of the residual norm
+// The two partial-sum arrays of the update (r.r of the previous iteration, d.w for eta),
+// each summed in the fixed order of k_update2x's first version: thread t adds t, t + 256, ...
+// then a tree over the 256 threads.  One workgroup per problem writes the totals to
+// scal[12] and scal[13], which every workgroup of the update then reads.
+constexpr int SCAL_RR = 12, SCAL_ETA = 13;
+__global__ __launch_bounds__(256) void k_update_sums(const double* __restrict__ rr_in, int n_rr,
+                                                     const double* __restrict__ eta_part, int n_eta,
+                                                     double* __restrict__ scal, BatchStrides bs) {
+  __shared__ double red[256], red2[256];
+  {
+    const i64 z = blockIdx.y;
+    scal += z * bs.scal;
+    if (eta_part) eta_part += z * bs.part;
+    if (rr_in) rr_in += z * bs.part;
+  }
+  double pa = 0.0, pb = 0.0;
+  if (rr_in)
+    for (int i = threadIdx.x; i < n_rr; i += 256) pa += rr_in[i];
+  if (eta_part)
+    for (int i = threadIdx.x; i < n_eta; i += 256) pb += eta_part[i];
+  red[threadIdx.x] = pa;
+  red2[threadIdx.x] = pb;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if ((int)threadIdx.x < s2) {
+      red[threadIdx.x] += red[threadIdx.x + s2];
+      red2[threadIdx.x] += red2[threadIdx.x + s2];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    scal[SCAL_RR] = red[0];
+    scal[SCAL_ETA] = red2[0];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_update2x(i64 N, const double* __restrict__ d, const double* __restrict__ w,
                                                   double* __restrict__ v, double* __restrict__ r,
                                                   double* __restrict__ X, double* __restrict__ Dcol,
@@ -63,17 +99,15 @@ __global__ __launch_bounds__(256) void k_update2x(i64 N, const double* __restric
                                                   const double* __restrict__ rr_in, int n_rr,
                                                   double* __restrict__ rr_out, BatchStrides bs,
                                                   double* __restrict__ vbest = nullptr, int par = 0) {
-  __shared__ double red[256], red2[256];
+  __shared__ double red[4];
   {                                              // problem blockIdx.y of a batch
     const i64 z = blockIdx.y;
     d += z * bs.v; w += z * bs.v; v += z * bs.v; r += z * bs.v; X += z * bs.v;
     Dcol += z * bs.M; Qcol += z * bs.M; eta_slot += z * bs.eta;
     scal += z * bs.scal; flag += z * bs.flag;
-    if (eta_part) eta_part += z * bs.part;
-    if (rr_in) rr_in += z * bs.part;
     if (rr_out) rr_out += z * bs.part;
   }
-  // every load of the update is issued up front: the flag, both partial sums and the vectors
+  // every load of the update is issued up front: the flag, the totals and the vectors
   const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   const int fl = flag[0];
   double dk = 0.0, wk = 0.0, vk = 0.0, rk0 = 0.0;
@@ -83,29 +117,11 @@ __global__ __launch_bounds__(256) void k_update2x(i64 N, const double* __restric
     vk = v[k];
     rk0 = r[k];
   }
-  double pa = 0.0, pb = 0.0;                   // thread t adds t, t + 256, ... in order
-  if (rr_in)
-    for (int i = threadIdx.x; i < n_rr; i += 256) pa += rr_in[i];
-  if (eta_part)
-    for (int i = threadIdx.x; i < n_eta; i += 256) pb += eta_part[i];
-  double sr = scal[0], et = scal[1];
+  // the totals of the partial sums, formed once by k_update_sums just before
+  const double sr = rr_in ? scal[SCAL_RR] : scal[0];
+  const double et = eta_part ? scal[SCAL_ETA] : scal[1];
   const double stop2 = scal[4] * scal[3];
   if (fl != 0) return;                         // uniform: every thread read the same flag
-  if (rr_in || eta_part) {                     // both fixed trees at once
-    red[threadIdx.x] = pa;
-    red2[threadIdx.x] = pb;
-    __syncthreads();
-    for (int s2 = 128; s2 > 0; s2 >>= 1) {
-      if ((int)threadIdx.x < s2) {
-        red[threadIdx.x] += red[threadIdx.x + s2];
-        red2[threadIdx.x] += red2[threadIdx.x + s2];
-      }
-      __syncthreads();
-    }
-    if (rr_in) sr = red[0];
-    if (eta_part) et = red2[0];
-    __syncthreads();                           // red is reused for the r.r partials below
-  }
   if (rr_in && sr <= stop2) {
     if (k == 0) {
       scal[0] = sr;
@@ -1046,6 +1062,9 @@ static int itergp_run(gpfvm_handle* h, Elt elt, const double* b, double* v, int 
         double* rr_next = (replace || action) ? nullptr : (rr_prev == rr_a ? rr_b : rr_a);
         // with CG actions s = r, so the step numerator s^T r is r^T r; otherwise d^T r
         if (action) HIPCHK(h, launch_dot(N, d, r, dotp, h->scal, s));
+        if (i > 0 || rr_prev)
+          hipLaunchKernelGGL(k_update_sums, dim3(1), dim3(256), 0, s, (const double*)rr_prev, n_rr,
+                             (const double*)(i > 0 ? eta_p : nullptr), n_eta, h->scal, BatchStrides());
         hipLaunchKernelGGL(k_update2x, dim3(nblk(N)), dim3(256), 0, s, N, (const double*)d, (const double*)w, v, r,
                            X, h->Dd + (i64)i * N, h->Qd + (i64)i * N, h->eta + i, h->scal, h->flag,
                            (const double*)(i > 0 ? eta_p : nullptr), n_eta, (const double*)rr_prev, n_rr, rr_next,
@@ -2464,6 +2483,9 @@ int gpfvm::batch_solve(gpfvm_handle* h, int R, const double* yobs_host, double t
       }
       const bool replace = (i + 1) % std::max(1, replace_every) == 0;
       double* rr_next = replace ? nullptr : (rr_prev == rr_a ? rr_b : rr_a);
+      if (i > 0 || rr_prev)
+        hipLaunchKernelGGL(k_update_sums, dim3(1, R), dim3(256), 0, s, (const double*)rr_prev, n_rr,
+                           (const double*)(i > 0 ? eta_p : nullptr), n_eta, scal, bs);
       hipLaunchKernelGGL(k_update2x, dim3(nblk(N), R), dim3(256), 0, s, N, (const double*)d, (const double*)w, B.v,
                          r, X, B.Dd + (i64)i * N, B.Qd + (i64)i * N, B.eta + i, scal, flag,
                          (const double*)(i > 0 ? eta_p : nullptr), n_eta, (const double*)rr_prev, n_rr, rr_next, bs);
