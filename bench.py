@@ -34,7 +34,7 @@ def parse():
                     help="with --roofline-only: wave 64x128x128 with 1 rhs, advdiff 128^2 or heat 64^3 with 64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mv-reps", type=int, default=50)
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests in the serving trace (0 = skip the serving measurement)")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-max-batch", type=int, default=16,

@@ -404,47 +404,97 @@ std::vector<Stage> gpfvm::ginv_stages(const gpfvm_handle* h, int nrhs, const dou
   return st;
 }
 
-// y[i] = add[i] + alpha * sum_k M[i][k] x[k] over k <= i (upper = 0) or k >= i (upper = 1) for a
-// float32 matrix: one wavefront per row, four matrix values per 16-byte load, products and sums in
-// float64.  Needs n % 4 == 0 and 16-byte aligned M and x; the up to three values before the first
-// aligned quad and after the last are taken one by one.
-__global__ __launch_bounds__(256) void k_trmv_rows_f32(int n, const float* __restrict__ M, const double* __restrict__ x,
-                                                       double* __restrict__ y, double alpha,
-                                                       const double* __restrict__ add, int upper) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+// y[i] = add[i] + alpha * sum_k M[i][k] x[k] over k <= i (upper = 0) or k >= i (upper = 1), for a
+// row-major float64 or float32 matrix M, two adjacent rows per wavefront, so that each 16-byte load of x serves both
+// rows (the loads of x come from L2 and had outnumbered the matrix's own: twice its bytes for a
+// float32 matrix).  Matrix values in 16-byte loads (two float64 or four float32), UN of them per row
+// in flight, products and sums in float64.  Needs n even (n % 4 == 0 for float32) and 16-byte
+// aligned M and x.  The quads (pairs) inside both rows' ranges are shared; the up to 2V - 1 values
+// of a row before them and after them are taken one by one by lanes 8 seg .. 8 seg + 7.
+template <typename T, int UN>
+__global__ __launch_bounds__(256) void k_trmv_2rows(int n, const T* __restrict__ M, const double* __restrict__ x,
+                                                    double* __restrict__ y, double alpha,
+                                                    const double* __restrict__ add, int upper) {
+  constexpr int V = 16 / (int)sizeof(T);
+  typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type VT;
+  const int i0 = 2 * (blockIdx.x * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
-  if (i >= n) return;
-  const int lo = upper ? i : 0, hi = upper ? n : i + 1;
-  const float* __restrict__ row = M + (i64)i * n;
-  const float4* __restrict__ row4 = reinterpret_cast<const float4*>(row);
+  if (i0 >= n) return;                           // n is even: row i0 + 1 exists
+  const int i1 = i0 + 1;
+  const int lo0 = upper ? i0 : 0, hi0 = upper ? n : i0 + 1;
+  const int lo1 = upper ? i1 : 0, hi1 = upper ? n : i1 + 1;
+  const T* __restrict__ r0 = M + (i64)i0 * n;
+  const T* __restrict__ r1 = r0 + n;
+  const VT* __restrict__ v0 = reinterpret_cast<const VT*>(r0);
+  const VT* __restrict__ v1 = reinterpret_cast<const VT*>(r1);
   const double2* __restrict__ x2 = reinterpret_cast<const double2*>(x);
-  const int qa = (lo + 3) / 4, qb = hi / 4;     // quads [4 qa, 4 qb) of [lo, hi)
-  double acc0 = 0.0, acc1 = 0.0;
-  int q = qa + lane;
-  for (; q + 64 < qb; q += 128) {
-    const float4 m0 = row4[q], m1 = row4[q + 64];
-    const double2 a0 = x2[2 * q], b0 = x2[2 * q + 1], a1 = x2[2 * (q + 64)], b1 = x2[2 * (q + 64) + 1];
-    acc0 += ((double)m0.x * a0.x + (double)m0.y * a0.y) + ((double)m0.z * b0.x + (double)m0.w * b0.y);
-    acc1 += ((double)m1.x * a1.x + (double)m1.y * a1.y) + ((double)m1.z * b1.x + (double)m1.w * b1.y);
+  const int QA = max((lo0 + V - 1) / V, (lo1 + V - 1) / V), QB = min(hi0 / V, hi1 / V);
+  auto dotv = [](const VT& m, const double2* xv) -> double {
+    if constexpr (V == 2) return m.x * xv[0].x + m.y * xv[0].y;
+    else return ((double)m.x * xv[0].x + (double)m.y * xv[0].y) + ((double)m.z * xv[1].x + (double)m.w * xv[1].y);
+  };
+  double a0 = 0.0, a1 = 0.0;
+  if (QA < QB) {
+    double c0[UN], c1[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) c0[u] = c1[u] = 0.0;
+    int q = QA + lane;
+    for (; q + 64 * (UN - 1) < QB; q += 64 * UN) {
+      VT m0[UN], m1[UN];
+      double2 xv[UN][V / 2];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        m0[u] = v0[q + 64 * u];
+        m1[u] = v1[q + 64 * u];
+#pragma unroll
+        for (int hh = 0; hh < V / 2; ++hh) xv[u][hh] = x2[(q + 64 * u) * (V / 2) + hh];
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        c0[u] += dotv(m0[u], xv[u]);
+        c1[u] += dotv(m1[u], xv[u]);
+      }
+    }
+    for (; q < QB; q += 64) {
+      double2 xv[V / 2];
+#pragma unroll
+      for (int hh = 0; hh < V / 2; ++hh) xv[hh] = x2[q * (V / 2) + hh];
+      c0[0] += dotv(v0[q], xv);
+      c1[0] += dotv(v1[q], xv);
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      a0 += c0[u];
+      a1 += c1[u];
+    }
+    // segments: 0 row i0 before the shared quads, 1 after them, 2 and 3 the same for row i1
+    const int seg = lane >> 3, k = lane & 7;
+    if (seg == 0 && lo0 + k < V * QA) a0 += (double)r0[lo0 + k] * x[lo0 + k];
+    else if (seg == 1 && V * QB + k < hi0) a0 += (double)r0[V * QB + k] * x[V * QB + k];
+    else if (seg == 2 && lo1 + k < V * QA) a1 += (double)r1[lo1 + k] * x[lo1 + k];
+    else if (seg == 3 && V * QB + k < hi1) a1 += (double)r1[V * QB + k] * x[V * QB + k];
+  } else {                                       // short rows (at most V values each)
+    const int k = lane & 31;
+    if (lane < 32) {
+      if (lo0 + k < hi0) a0 = (double)r0[lo0 + k] * x[lo0 + k];
+    } else if (lo1 + k < hi1) {
+      a1 = (double)r1[lo1 + k] * x[lo1 + k];
+    }
   }
-  for (; q < qb; q += 64) {
-    const float4 m0 = row4[q];
-    const double2 a0 = x2[2 * q], b0 = x2[2 * q + 1];
-    acc0 += ((double)m0.x * a0.x + (double)m0.y * a0.y) + ((double)m0.z * b0.x + (double)m0.w * b0.y);
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  if (lane == 0) {
+    y[i0] = (add ? add[i0] : 0.0) + alpha * a0;
+    y[i1] = (add ? add[i1] : 0.0) + alpha * a1;
   }
-  double a = acc0 + acc1;
-  if (qa > qb) {                                 // no aligned quad: at most six values
-    const int e = lo + lane;
-    if (e < hi) a += (double)row[e] * x[e];
-  } else if (lane < 4 * qa - lo) {               // before the first quad (at most three)
-    const int e = lo + lane;
-    a += (double)row[e] * x[e];
-  } else if (lane >= 3 && lane - 3 < hi - 4 * qb) {   // after the last quad (at most three)
-    const int e = 4 * qb + lane - 3;
-    a += (double)row[e] * x[e];
-  }
-  a = wave_sum(a);
-  if (lane == 0) y[i] = (add ? add[i] : 0.0) + alpha * a;
+}
+
+template <typename T, int UN>
+static hipError_t trmv_2rows(int n, const T* M, const double* x, double* y, double alpha, const double* add, int upper,
+                             hipStream_t s) {
+  hipLaunchKernelGGL((k_trmv_2rows<T, UN>), dim3((unsigned)((n + 7) / 8)), dim3(256), 0, s, n, M, x, y, alpha, add,
+                     upper);
+  return hipGetLastError();
 }
 
 // Float32 copies of L^{-1} and L^{-T} for the correction products of the row-streaming solves
@@ -463,10 +513,21 @@ static void ensure_inv_f32(gpfvm_handle* h, hipStream_t s) {
   }
 }
 
+// float32 correction product (n % 4 == 0, M and x 16-byte aligned): two rows per wavefront, 100 us
+// per pass over the 16384^2 float32 triangle against 114 us one row per wavefront
 static hipError_t trmv_rows_f32(int n, const float* M, const double* x, double* y, double alpha, const double* add,
                                 int upper, hipStream_t s) {
-  hipLaunchKernelGGL(k_trmv_rows_f32, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, M, x, y, alpha, add, upper);
-  return hipGetLastError();
+  return trmv_2rows<float, 2>(n, M, x, y, alpha, add, upper, s);
+}
+
+// float64 row-streaming product: two rows per wavefront where n is even and M and x are 16-byte
+// aligned (188 us per pass over the 16384^2 float64 triangle, 5.7 TB/s, against 191 us one row per
+// wavefront: this pass is bound by HBM, not by the loads of x), else one row per wavefront
+static hipError_t trmv_rows_f64(int n, const double* M, const double* x, double* y, double alpha, const double* add,
+                                int upper, hipStream_t s) {
+  if (n % 2 == 0 && (uintptr_t)M % 16 == 0 && (uintptr_t)x % 16 == 0)
+    return trmv_2rows<double, 4>(n, M, x, y, alpha, add, upper, s);
+  return launch_trmv_rows(n, M, x, y, alpha, add, upper, s);
 }
 
 // Same six products for one right-hand side as row-streaming triangular
@@ -481,15 +542,15 @@ hipError_t gpfvm::ginv_rows(const gpfvm_handle* h, const double* U, double* T, d
   const bool f32 = h->Linv_f && h->Linvt_f && nb % 4 == 0 && (uintptr_t)R % 16 == 0 && (uintptr_t)h->Linv_f % 16 == 0 &&
                    (uintptr_t)h->Linvt_f % 16 == 0;
   hipError_t e;
-  if ((e = launch_trmv_rows(nb, h->Linv, U, T, 1.0, nullptr, 0, s)) != hipSuccess) return e;   // t = Li u
-  if ((e = launch_trmv_rows(nb, h->L, T, R, -1.0, U, 0, s)) != hipSuccess) return e;           // r = u - L t
-  e = f32 ? trmv_rows_f32(nb, h->Linv_f, R, T, 1.0, T, 0, s)                                   // t += Li r
-          : launch_trmv_rows(nb, h->Linv, R, T, 1.0, T, 0, s);
+  if ((e = trmv_rows_f64(nb, h->Linv, U, T, 1.0, nullptr, 0, s)) != hipSuccess) return e;   // t = Li u
+  if ((e = trmv_rows_f64(nb, h->L, T, R, -1.0, U, 0, s)) != hipSuccess) return e;           // r = u - L t
+  e = f32 ? trmv_rows_f32(nb, h->Linv_f, R, T, 1.0, T, 0, s)                                // t += Li r
+          : trmv_rows_f64(nb, h->Linv, R, T, 1.0, T, 0, s);
   if (e != hipSuccess) return e;
-  if ((e = launch_trmv_rows(nb, h->Linvt, T, W, 1.0, nullptr, 1, s)) != hipSuccess) return e;  // w = Li^T t
-  if ((e = launch_trmv_rows(nb, h->Lt, W, R, -1.0, T, 1, s)) != hipSuccess) return e;          // r = t - L^T w
-  return f32 ? trmv_rows_f32(nb, h->Linvt_f, R, W, 1.0, W, 1, s)                               // w += Li^T r
-             : launch_trmv_rows(nb, h->Linvt, R, W, 1.0, W, 1, s);
+  if ((e = trmv_rows_f64(nb, h->Linvt, T, W, 1.0, nullptr, 1, s)) != hipSuccess) return e;  // w = Li^T t
+  if ((e = trmv_rows_f64(nb, h->Lt, W, R, -1.0, T, 1, s)) != hipSuccess) return e;          // r = t - L^T w
+  return f32 ? trmv_rows_f32(nb, h->Linvt_f, R, W, 1.0, W, 1, s)                            // w += Li^T r
+             : trmv_rows_f64(nb, h->Linvt, R, W, 1.0, W, 1, s);
 }
 
 hipError_t gpfvm::run_stages(const std::vector<Stage>& st, hipStream_t s) {
