@@ -1349,6 +1349,7 @@ constexpr int CU_MAXCH = 16;   // most partial sums per coefficient (rows_dot_ch
 // chunks being consecutive ranges of ceil(N / nch) columns.  The consumer
 // (k_cols_update) adds the nch partials of a row in order.
 constexpr int RP_THREADS = 256;
+constexpr i64 ROWS_DOT_TWO_MIN_WG = 512;   // two rows per workgroup only where that leaves this many
 
 // dot_range over pairs: q, x (and xm) 16-byte aligned, c_lo and c_hi even.
 // RD2_U 16-byte loads of each vector in flight per thread, then the same
@@ -1396,6 +1397,99 @@ __device__ __forceinline__ double dot_range2(const double* __restrict__ q, const
   if (threadIdx.x == 0)
     for (int w = 0; w < NT / 64; ++w) s += red[w];
   return s;
+}
+
+// dot_range2 for two rows q0, q1 against the same x (and xm), whose loads then serve both rows.
+// Each row's sum takes exactly the steps of dot_range2 (the same accumulator per element, the same
+// reduction), so the results are the same bits.  Valid in thread 0; red holds 2 NT / 64 values.
+template <int NT>
+__device__ __forceinline__ void dot_range2_two(const double* __restrict__ q0, const double* __restrict__ q1,
+                                               const double* __restrict__ x, i64 c_lo, i64 c_hi, double* red,
+                                               const double* __restrict__ xm, double& s0, double& s1) {
+  const double2* __restrict__ a2 = reinterpret_cast<const double2*>(q0);
+  const double2* __restrict__ b2 = reinterpret_cast<const double2*>(q1);
+  const double2* __restrict__ x2 = reinterpret_cast<const double2*>(x);
+  const double2* __restrict__ m2 = reinterpret_cast<const double2*>(xm);
+  const i64 plo = c_lo / 2, phi = c_hi / 2;
+  double acc0[RD2_U], acc1[RD2_U];
+#pragma unroll
+  for (int u = 0; u < RD2_U; ++u) acc0[u] = acc1[u] = 0.0;
+  for (i64 p0 = plo + threadIdx.x; p0 < phi; p0 += (i64)NT * RD2_U) {
+    double2 av[RD2_U], bv[RD2_U], xv[RD2_U];
+#pragma unroll
+    for (int u = 0; u < RD2_U; ++u) {
+      const i64 p = p0 + (i64)u * NT;
+      av[u] = p < phi ? a2[p] : make_double2(0.0, 0.0);
+      bv[u] = p < phi ? b2[p] : make_double2(0.0, 0.0);
+      xv[u] = p < phi ? x2[p] : make_double2(0.0, 0.0);
+    }
+    if (xm) {
+#pragma unroll
+      for (int u = 0; u < RD2_U; ++u) {
+        const i64 p = p0 + (i64)u * NT;
+        const double2 mv = p < phi ? m2[p] : make_double2(0.0, 0.0);
+        xv[u].x -= mv.x;
+        xv[u].y -= mv.y;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RD2_U; ++u) {
+      acc0[u] = fma(av[u].y, xv[u].y, fma(av[u].x, xv[u].x, acc0[u]));
+      acc1[u] = fma(bv[u].y, xv[u].y, fma(bv[u].x, xv[u].x, acc1[u]));
+    }
+  }
+#pragma unroll
+  for (int w = RD2_U / 2; w > 0; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) {
+      acc0[u] += acc0[u + w];
+      acc1[u] += acc1[u + w];
+    }
+  double v0 = acc0[0], v1 = acc1[0];
+  for (int off = 32; off > 0; off >>= 1) {
+    v0 += __shfl_down(v0, off, 64);
+    v1 += __shfl_down(v1, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = v0;
+    red[NT / 64 + (threadIdx.x >> 6)] = v1;
+  }
+  __syncthreads();
+  s0 = s1 = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NT / 64; ++w) {
+      s0 += red[w];
+      s1 += red[NT / 64 + w];
+    }
+}
+
+// k_rows_dot with pairs, two rows per workgroup (rows 2 r and 2 r + 1 of chunk ch; an odd last row
+// is taken alone): the same partials, the same bits
+__global__ __launch_bounds__(RP_THREADS) void k_rows_dot_two(int nr, i64 N, int nch, const double* __restrict__ M,
+                                                             const double* __restrict__ x,
+                                                             const double* __restrict__ xm,
+                                                             double* __restrict__ part, BatchStrides bs) {
+  __shared__ double red[2 * RP_THREADS / 64];
+  M += blockIdx.y * bs.M;
+  x += blockIdx.y * bs.v;
+  if (xm) xm += blockIdx.y * bs.v;
+  part += blockIdx.y * bs.u;
+  const int r0 = 2 * (int)(blockIdx.x / nch), ch = (int)(blockIdx.x % nch);
+  const bool two = r0 + 1 < nr;
+  i64 L = (N + nch - 1) / nch;
+  L = (L + 1) & ~(i64)1;
+  const i64 lo = min(N, (i64)ch * L), hi = min(N, lo + L);
+  if (two) {
+    double s0, s1;
+    dot_range2_two<RP_THREADS>(M + (i64)r0 * N, M + (i64)(r0 + 1) * N, x, lo, hi, red, xm, s0, s1);
+    if (threadIdx.x == 0) {
+      part[(i64)r0 * nch + ch] = s0;
+      part[(i64)(r0 + 1) * nch + ch] = s1;
+    }
+  } else {
+    const double s0 = dot_range2<RP_THREADS>(M + (i64)r0 * N, x, lo, hi, red, xm);
+    if (threadIdx.x == 0) part[(i64)r0 * nch + ch] = s0;
+  }
 }
 
 // pairs: every chunk starts and ends on a pair (N even, the vectors 16-byte aligned)
@@ -1526,7 +1620,12 @@ hipError_t launch_rows_dot(int nr, i64 N, const double* M, const double* x, doub
   const auto al = [](const void* p) { return (uintptr_t)p % 16 == 0; };
   const bool odd_stride = (bs.M % 2) || (bs.v % 2);
   const int pairs = (N % 2 == 0) && !odd_stride && al(M) && al(x) && (!xm || al(xm));
-  k_rows_dot<<<dim3((unsigned)((i64)nr * nch), batch), dim3(RP_THREADS), 0, s>>>(N, nch, M, x, xm, part, bs, pairs);
+  const i64 pairs_of_rows = (nr + 1) / 2;
+  if (pairs && pairs_of_rows * nch >= ROWS_DOT_TWO_MIN_WG)   // enough workgroups with two rows each
+    k_rows_dot_two<<<dim3((unsigned)(pairs_of_rows * nch), batch), dim3(RP_THREADS), 0, s>>>(nr, N, nch, M, x, xm,
+                                                                                            part, bs);
+  else
+    k_rows_dot<<<dim3((unsigned)((i64)nr * nch), batch), dim3(RP_THREADS), 0, s>>>(N, nch, M, x, xm, part, bs, pairs);
   return hipGetLastError();
 }
 
