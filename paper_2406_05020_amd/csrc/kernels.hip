@@ -1772,16 +1772,31 @@ hipError_t launch_trmv_rows(int n, const double* M, const double* x, double* y, 
   return hipGetLastError();
 }
 
-__global__ void k_transpose(const double* __restrict__ A, double* __restrict__ B, int n) {
-  const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (i64)n * n) return;
-  const int r = (int)(idx / n), c = (int)(idx % n);
-  B[(i64)c * n + r] = A[idx];
+// B = A^T for n x n row-major matrices, in 64 x 64 tiles through LDS so that both the reads of A
+// and the writes of B run along rows (a row of the tile per wavefront pass, one element per lane);
+// the odd column of the padded LDS rows spreads a tile column over the banks.
+constexpr int TP_T = 64;
+__global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ A, double* __restrict__ B, int n) {
+  __shared__ double t[TP_T][TP_T + 1];
+  const int tiles = (n + TP_T - 1) / TP_T;
+  const int tr = (int)(blockIdx.x / tiles), tc = (int)(blockIdx.x % tiles);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = tr * TP_T, c0 = tc * TP_T;
+  for (int i = w; i < TP_T; i += 4) {            // tile row i of A: A[r0 + i][c0 + lane]
+    const int r = r0 + i, c = c0 + lane;
+    if (r < n && c < n) t[i][lane] = A[(i64)r * n + c];
+  }
+  __syncthreads();
+  for (int j = w; j < TP_T; j += 4) {            // row c0 + j of B: B[c0 + j][r0 + lane] = A[r0 + lane][c0 + j]
+    const int r = c0 + j, c = r0 + lane;
+    if (r < n && c < n) B[(i64)r * n + c] = t[lane][j];
+  }
 }
 
 hipError_t launch_transpose(const double* A, double* B, int n, hipStream_t s) {
-  const i64 tot = (i64)n * n;
-  k_transpose<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(A, B, n);
+  if (n <= 0) return hipSuccess;
+  const i64 tiles = (i64)((n + TP_T - 1) / TP_T);
+  k_transpose<<<(unsigned)(tiles * tiles), 256, 0, s>>>(A, B, n);
   return hipGetLastError();
 }
 
