@@ -1012,6 +1012,7 @@ static void launch_lds(const Stage& st, int nd, hipStream_t s) {
 // Thin products: C[b][m][n] = alpha sum_k A[b][m][k] B[b][k][n] for descriptors with M = 1 or
 // N = 1 (one segment, no epilogue), one thread per output element in (batch, m, n) order with n
 // fastest; the descriptors' tile_begin are their output offsets (ascending).
+constexpr int THIN_U = 8;
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_thin(const GemmDesc* __restrict__ descs, int nd, i64 total) {
   const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1030,8 +1031,23 @@ __global__ __launch_bounds__(256) void k_gemm_thin(const GemmDesc* __restrict__ 
   const Seg& S = D.seg[0];
   const T* __restrict__ A = (const T*)S.A + b * S.a_bs + m * S.a_rs;
   const T* __restrict__ B = (const T*)S.B + b * S.b_bs + n * S.b_cs;
+  // K in steps of THIN_U: the step's loads are issued together, then added in order (the same
+  // fmas in the same order as one at a time, with THIN_U loads in flight instead of one)
+  const int K = S.K;
+  const i64 a_cs = S.a_cs, b_rs = S.b_rs;
   double acc = 0.0;
-  for (int k = 0; k < S.K; ++k) acc = fma((double)A[(i64)k * S.a_cs], (double)B[(i64)k * S.b_rs], acc);
+  int k = 0;
+  for (; k + THIN_U <= K; k += THIN_U) {
+    double av[THIN_U], bv[THIN_U];
+#pragma unroll
+    for (int u = 0; u < THIN_U; ++u) {
+      av[u] = (double)A[(i64)(k + u) * a_cs];
+      bv[u] = (double)B[(i64)(k + u) * b_rs];
+    }
+#pragma unroll
+    for (int u = 0; u < THIN_U; ++u) acc = fma(av[u], bv[u], acc);
+  }
+  for (; k < K; ++k) acc = fma((double)A[(i64)k * a_cs], (double)B[(i64)k * b_rs], acc);
   ((T*)D.C)[b * D.c_bs + m * D.c_rs + n * D.c_cs] = (T)(S.alpha * acc);
 }
 
