@@ -15,7 +15,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgpfvm.so")
+# GPFVM_LIB names another build of the same library (the host-AddressSanitizer build of asan_check.py)
+LIB_PATH = os.environ.get("GPFVM_LIB") or os.path.join(HERE, "libgpfvm.so")
 
 OK, E_INVALID, E_NOMEM, E_HIP, E_NOTPD, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_MIXED = 0, 1
