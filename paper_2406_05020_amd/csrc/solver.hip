@@ -2021,6 +2021,7 @@ __global__ void k_gv_bt(GVFactor F, double coef, i64 C, i64 np, double* __restri
 // red[x] += sum_r (sum_{g: off_g <= r} w_g(x) U_g[r - off_g][a_g(x)])^2, one thread per grid
 // point, rows in order.  Neighbouring grid points differ in the last coordinate, so a
 // wavefront's loads of a row of U_g are contiguous or one address.
+constexpr int GV_U = 4;
 template <int NG>
 __global__ __launch_bounds__(256) void k_gv_direct(const GVMeta* __restrict__ meta, i64 M, i64 nb,
                                                    double* __restrict__ red) {
@@ -2050,7 +2051,23 @@ __global__ __launch_bounds__(256) void k_gv_direct(const GVMeta* __restrict__ me
 #pragma unroll
   for (int g1 = 0; g1 < NG; ++g1) {          // rows [off_g1, off_g1+1): groups 0..g1 contribute
     const i64 rlo = V.grp[g1].off, rhi = g1 + 1 < NG ? V.grp[g1 + 1].off : nb;
-    for (i64 r = rlo; r < rhi; ++r) {
+    i64 r = rlo;
+    // four rows at a time: their loads are issued together, then added in the same order
+    for (; r + GV_U <= rhi; r += GV_U) {
+      double v[GV_U][NG];
+#pragma unroll
+      for (int u = 0; u < GV_U; ++u)
+#pragma unroll
+        for (int g = 0; g <= g1; ++g) v[u][g] = p[g][(r + u - V.grp[g].off) * C[g]];
+#pragma unroll
+      for (int u = 0; u < GV_U; ++u) {
+        double t = 0.0;
+#pragma unroll
+        for (int g = 0; g <= g1; ++g) t = fma(w[g], v[u][g], t);
+        acc = fma(t, t, acc);
+      }
+    }
+    for (; r < rhi; ++r) {
       double t = 0.0;
 #pragma unroll
       for (int g = 0; g <= g1; ++g) t = fma(w[g], p[g][(r - V.grp[g].off) * C[g]], t);
